@@ -1,0 +1,352 @@
+// Oracle (test infrastructure only): nodal DG operators R(q) and L(q~)v.
+//
+// Equations (paper Section 3):
+//   Burgers, inviscid part:  u_t + (u^2/2)_x = 0, linear flux F_L = u~ u
+//     (Section 3.1 with kappa = 0).
+//   Euler 2D: q = (rho, rho u, rho v, rho E), F = (rho u, rho u (x) u + p I,
+//     rho u H), p = (gamma-1)(rho E - rho |u|^2 / 2) (Section 3.2), linear
+//     flux F_L = A(q~) q with the normal flux Jacobian A(n) printed there.
+//
+// Semi-discretization (eq. EXPO-SemiDiscretizedForm_ode): per element,
+//   (q_t, v)_K = -(div F, v)_K - <(F* - F) . n, v>_dK
+// with LGL collocation and a diagonal LGL mass matrix, i.e. the strong form
+//   R_i = -sum_dir (2/h_dir) (D_dir F_dir)_i
+//         - sum_faces (2/h_dir) (1/w_end) (F* . n - F . n)_i
+// on the face nodes.  Numerical flux: Lax-Friedrichs / Rusanov,
+//   F* . n^- = {{F}} . n^- + lambda/2 [[q]] . n^-
+//            = (F(q^-) + F(q^+))/2 . n^- + lambda/2 (q^- - q^+),
+// (Burgers LF flux, Section 3.1; Lax-Friedrichs for Euler, Section 5.2
+// opening) with lambda the larger of the two one-sided wave speeds at the
+// face node: |u| for Burgers, |u . n| + a for Euler.
+//
+// L(q~) v is the same operator with F replaced by F_L(v) = A(q~) v and the
+// dissipation lambda evaluated at q~ (the linear numerical flux (u~ u)* and
+// (A~ q)* of Sections 3.1 and 3.2).  Periodic boundaries everywhere.
+#include "oracle.h"
+
+#include <cmath>
+#include <complex>
+#include <vector>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+using cplx = std::complex<double>;
+
+struct Geo {
+    int eq, nx, ny, p, n1, Np, K, nvar, dim;
+    double hx, hy, gamma, x0, y0;
+    std::vector<double> xi, w, D;
+};
+
+bool make_geo(const orc_mesh *m, Geo *g) {
+    if (!m) return false;
+    if (m->equation != ORC_BURGERS1D && m->equation != ORC_EULER2D) return false;
+    if (m->p < 1 || m->p > 15 || m->nx < 1 || m->ny < 1) return false;
+    if (m->equation == ORC_BURGERS1D && m->ny != 1) return false;
+    if (!(m->x1 > m->x0)) return false;
+    if (m->equation == ORC_EULER2D && (!(m->y1 > m->y0) || !(m->gamma > 1.0))) return false;
+    g->eq = m->equation;
+    g->nx = m->nx;
+    g->ny = m->ny;
+    g->p = m->p;
+    g->n1 = m->p + 1;
+    g->dim = (m->equation == ORC_BURGERS1D) ? 1 : 2;
+    g->Np = (g->dim == 1) ? g->n1 : g->n1 * g->n1;
+    g->K = m->nx * m->ny;
+    g->nvar = (m->equation == ORC_BURGERS1D) ? 1 : 4;
+    g->hx = (m->x1 - m->x0) / m->nx;
+    g->hy = (g->dim == 2) ? (m->y1 - m->y0) / m->ny : 1.0;
+    g->x0 = m->x0;
+    g->y0 = m->y0;
+    g->gamma = m->gamma;
+    g->xi.resize(g->n1);
+    g->w.resize(g->n1);
+    g->D.resize(g->n1 * g->n1);
+    return orc_lgl(g->p, g->xi.data(), g->w.data(), g->D.data()) == 0;
+}
+
+// Periodic neighbour of element e across its face in direction dir
+// (0 = x, 1 = y) on side s (-1 = left/bottom, +1 = right/top).
+int neighbour(const Geo &g, int e, int dir, int s) {
+    int ex = e % g.nx, ey = e / g.nx;
+    if (dir == 0)
+        ex = (ex + s + g.nx) % g.nx;
+    else
+        ey = (ey + s + g.ny) % g.ny;
+    return ey * g.nx + ex;
+}
+
+// Node index of (i, j) and its mirror across a face.
+inline int node(const Geo &g, int i, int j) { return (g.dim == 1) ? i : j * g.n1 + i; }
+
+template <class T>
+void load(const Geo &g, const T *q, int e, int n, T *out) {
+    for (int c = 0; c < g.nvar; ++c) out[c] = q[((size_t)c * g.K + e) * g.Np + n];
+}
+
+// ---- physics -------------------------------------------------------------
+
+// Physical flux F_dir(q).
+template <class T>
+void flux(const Geo &g, const T *q, int dir, T *f) {
+    if (g.eq == ORC_BURGERS1D) {
+        f[0] = 0.5 * q[0] * q[0];
+        return;
+    }
+    const double gm = g.gamma;
+    T rho = q[0];
+    T u = q[1] / rho, v = q[2] / rho;
+    T p = (gm - 1.0) * (q[3] - 0.5 * (q[1] * u + q[2] * v));
+    T un = (dir == 0) ? u : v;
+    f[0] = rho * un;
+    f[1] = q[1] * un + ((dir == 0) ? p : T(0.0));
+    f[2] = q[2] * un + ((dir == 1) ? p : T(0.0));
+    f[3] = (q[3] + p) * un;
+}
+
+// Linear flux A_dir(qt) v: the paper's normal flux Jacobian with n = e_dir,
+//   A(n) = [ 0,                 n^T,                               0        ]
+//          [ phi n - u u_n,     u (x) n - (g-1) n (x) u + u_n I,   (g-1) n  ]
+//          [ (phi - H) u_n,     H n^T - (g-1) u^T u_n,             g u_n    ]
+// with phi = (g-1)/2 |u|^2 and u_n = n . u.  Burgers: A(u~) v = u~ v.
+template <class T>
+void lin_flux(const Geo &g, const double *qt, const T *v, int dir, T *f) {
+    if (g.eq == ORC_BURGERS1D) {
+        f[0] = qt[0] * v[0];
+        return;
+    }
+    const double gm = g.gamma, gt = g.gamma - 1.0;
+    const double rho = qt[0];
+    const double ux = qt[1] / rho, uy = qt[2] / rho;
+    const double p = gt * (qt[3] - 0.5 * rho * (ux * ux + uy * uy));
+    const double H = (qt[3] + p) / rho;
+    const double phi = 0.5 * gt * (ux * ux + uy * uy);
+    const double nx = (dir == 0) ? 1.0 : 0.0, ny = (dir == 1) ? 1.0 : 0.0;
+    const double un = nx * ux + ny * uy;
+    const double u[2] = {ux, uy}, n[2] = {nx, ny};
+    f[0] = nx * v[1] + ny * v[2];
+    for (int a = 0; a < 2; ++a) {
+        T acc = (phi * n[a] - u[a] * un) * v[0];
+        for (int b = 0; b < 2; ++b) {
+            double Mab = u[a] * n[b] - gt * n[a] * u[b] + ((a == b) ? un : 0.0);
+            acc += Mab * v[1 + b];
+        }
+        acc += gt * n[a] * v[3];
+        f[1 + a] = acc;
+    }
+    f[3] = (phi - H) * un * v[0] + (H * nx - gt * ux * un) * v[1] +
+           (H * ny - gt * uy * un) * v[2] + gm * un * v[3];
+}
+
+// One-sided wave speed for the Lax-Friedrichs dissipation.
+double wave_speed(const Geo &g, const double *q, int dir) {
+    if (g.eq == ORC_BURGERS1D) return std::fabs(q[0]);
+    const double rho = q[0];
+    const double ux = q[1] / rho, uy = q[2] / rho;
+    const double p = (g.gamma - 1.0) * (q[3] - 0.5 * rho * (ux * ux + uy * uy));
+    const double a = std::sqrt(g.gamma * p / rho);
+    return std::fabs(dir == 0 ? ux : uy) + a;
+}
+
+// ---- generic DG operator ------------------------------------------------
+//
+// out = DG operator applied to the field u with
+//   node_flux(e, n, dir, f): flux at a node (volume and face traces),
+//   lam_ref: real state whose traces give the LF wave speed lambda.
+template <class T, class FluxAt>
+void dg_apply(const Geo &g, const T *u, const double *lam_ref, FluxAt node_flux, T *out) {
+    const int n1 = g.n1, Np = g.Np, nv = g.nvar;
+    const double h[2] = {g.hx, g.hy};
+#pragma omp parallel for schedule(static)
+    for (int e = 0; e < g.K; ++e) {
+        // fluxes at all nodes of this element, per direction
+        std::vector<T> F((size_t)g.dim * Np * nv);
+        for (int dir = 0; dir < g.dim; ++dir)
+            for (int n = 0; n < Np; ++n) node_flux(e, n, dir, &F[((size_t)dir * Np + n) * nv]);
+        for (int jj = 0; jj < (g.dim == 2 ? n1 : 1); ++jj) {
+            for (int i = 0; i < n1; ++i) {
+                const int n = node(g, i, jj);
+                T res[4];
+                for (int c = 0; c < nv; ++c) res[c] = T(0.0);
+                // volume: -(2/h_dir) sum_l D_{il} F_dir at the nodes of the line
+                for (int dir = 0; dir < g.dim; ++dir) {
+                    const int a = (dir == 0) ? i : jj;  // coordinate index along dir
+                    for (int l = 0; l < n1; ++l) {
+                        const int nl = (dir == 0) ? node(g, l, jj) : node(g, i, l);
+                        const double Dal = g.D[a * n1 + l];
+                        for (int c = 0; c < nv; ++c)
+                            res[c] -= (2.0 / h[dir]) * Dal * F[((size_t)dir * Np + nl) * nv + c];
+                    }
+                }
+                // faces: -(2/h_dir)(1/w_end) (F* . n - F(u^-) . n)
+                for (int dir = 0; dir < g.dim; ++dir) {
+                    const int a = (dir == 0) ? i : jj;
+                    for (int s = -1; s <= 1; s += 2) {
+                        if ((s == -1 && a != 0) || (s == 1 && a != g.p)) continue;
+                        const int en = neighbour(g, e, dir, s);
+                        // mirror node on the neighbour: coordinate along dir flips end
+                        const int am = g.p - a;
+                        const int nn = (dir == 0) ? node(g, am, jj) : node(g, i, am);
+                        T fm[4], fp[4], um[4], up[4];
+                        for (int c = 0; c < nv; ++c) fm[c] = F[((size_t)dir * Np + n) * nv + c];
+                        node_flux(en, nn, dir, fp);
+                        load(g, u, e, n, um);
+                        load(g, u, en, nn, up);
+                        double qm[4], qp[4];
+                        load(g, lam_ref, e, n, qm);
+                        load(g, lam_ref, en, nn, qp);
+                        const double lam =
+                            std::fmax(wave_speed(g, qm, dir), wave_speed(g, qp, dir));
+                        const double sn = (double)s;  // n^- . e_dir
+                        for (int c = 0; c < nv; ++c) {
+                            T fstar_n = 0.5 * sn * (fm[c] + fp[c]) + 0.5 * lam * (um[c] - up[c]);
+                            T f_n = sn * fm[c];
+                            res[c] -= (2.0 / h[dir]) / g.w[a] * (fstar_n - f_n);
+                        }
+                    }
+                }
+                for (int c = 0; c < nv; ++c) out[((size_t)c * g.K + e) * Np + n] = res[c];
+            }
+        }
+    }
+}
+
+template <class T>
+void residual_frozen(const Geo &g, const T *q, const double *lam_ref, T *r) {
+    auto fl = [&](int e, int n, int dir, T *f) {
+        T qn[4];
+        load(g, q, e, n, qn);
+        flux(g, qn, dir, f);
+    };
+    dg_apply(g, q, lam_ref, fl, r);
+}
+
+void linear_op(const Geo &g, const double *qt, const double *v, double *w) {
+    auto fl = [&](int e, int n, int dir, double *f) {
+        double qn[4], vn[4];
+        load(g, qt, e, n, qn);
+        load(g, v, e, n, vn);
+        lin_flux(g, qn, vn, dir, f);
+    };
+    dg_apply(g, v, qt, fl, w);
+}
+
+}  // namespace
+
+extern "C" {
+
+int orc_ndof(const orc_mesh *m) {
+    Geo g;
+    if (!make_geo(m, &g)) return -1;
+    return g.nvar * g.K * g.Np;
+}
+
+int orc_nodes(const orc_mesh *m, double *x, double *y) {
+    Geo g;
+    if (!make_geo(m, &g) || !x) return -1;
+    for (int e = 0; e < g.K; ++e) {
+        const int ex = e % g.nx, ey = e / g.nx;
+        for (int jj = 0; jj < (g.dim == 2 ? g.n1 : 1); ++jj)
+            for (int i = 0; i < g.n1; ++i) {
+                const int n = node(g, i, jj);
+                x[(size_t)e * g.Np + n] = g.x0 + ex * g.hx + 0.5 * (g.xi[i] + 1.0) * g.hx;
+                if (y)
+                    y[(size_t)e * g.Np + n] =
+                        (g.dim == 2) ? g.y0 + ey * g.hy + 0.5 * (g.xi[jj] + 1.0) * g.hy : 0.0;
+            }
+    }
+    return 0;
+}
+
+int orc_mass(const orc_mesh *m, double *mass) {
+    Geo g;
+    if (!make_geo(m, &g) || !mass) return -1;
+    for (int e = 0; e < g.K; ++e)
+        for (int jj = 0; jj < (g.dim == 2 ? g.n1 : 1); ++jj)
+            for (int i = 0; i < g.n1; ++i) {
+                double v = 0.5 * g.hx * g.w[i];
+                if (g.dim == 2) v *= 0.5 * g.hy * g.w[jj];
+                mass[(size_t)e * g.Np + node(g, i, jj)] = v;
+            }
+    return 0;
+}
+
+int orc_rhs(const orc_mesh *m, const double *q, double *r) {
+    Geo g;
+    if (!make_geo(m, &g) || !q || !r) return -1;
+    residual_frozen<double>(g, q, q, r);
+    return 0;
+}
+
+int orc_jvp(const orc_mesh *m, const double *qref, const double *v, double *w) {
+    Geo g;
+    if (!make_geo(m, &g) || !qref || !v || !w) return -1;
+    linear_op(g, qref, v, w);
+    return 0;
+}
+
+int orc_jvp_complex_step(const orc_mesh *m, const double *qref, const double *v, double h,
+                         double *w) {
+    Geo g;
+    if (!make_geo(m, &g) || !qref || !v || !w || !(h > 0)) return -1;
+    const size_t n = (size_t)g.nvar * g.K * g.Np;
+    std::vector<cplx> qc(n), rc(n);
+    for (size_t i = 0; i < n; ++i) qc[i] = cplx(qref[i], h * v[i]);
+    residual_frozen<cplx>(g, qc.data(), qref, rc.data());
+    for (size_t i = 0; i < n; ++i) w[i] = rc[i].imag() / h;
+    return 0;
+}
+
+int orc_assemble_jvp(const orc_mesh *m, const double *qref, double *Lmat) {
+    Geo g;
+    if (!make_geo(m, &g) || !qref || !Lmat) return -1;
+    const size_t n = (size_t)g.nvar * g.K * g.Np;
+    std::vector<double> e(n, 0.0);
+    for (size_t j = 0; j < n; ++j) {
+        e[j] = 1.0;
+        linear_op(g, qref, e.data(), Lmat + j * n);
+        e[j] = 0.0;
+    }
+    return 0;
+}
+
+int orc_max_speed(const orc_mesh *m, const double *q, double *cmax, double *dxmin) {
+    Geo g;
+    if (!make_geo(m, &g) || !q) return -1;
+    double c = 0.0;
+    for (int e = 0; e < g.K; ++e)
+        for (int n = 0; n < g.Np; ++n) {
+            double qn[4];
+            load(g, q, e, n, qn);
+            for (int dir = 0; dir < g.dim; ++dir) c = std::fmax(c, wave_speed(g, qn, dir));
+        }
+    double dmin = 1e300;
+    for (int i = 0; i < g.p; ++i) dmin = std::fmin(dmin, g.xi[i + 1] - g.xi[i]);
+    double h = g.hx;
+    if (g.dim == 2) h = std::fmin(g.hx, g.hy);
+    if (cmax) *cmax = c;
+    if (dxmin) *dxmin = 0.5 * h * dmin;
+    return 0;
+}
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+}  // extern "C"

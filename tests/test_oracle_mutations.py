@@ -1,0 +1,64 @@
+"""The oracle's pins have teeth: plant a plausible mistake in a copy of the
+oracle sources (on the CPU), rebuild it, and check that a pin fails.
+
+Each mutation is a one-line edit of the kind a careful reading could miss: a
+flipped dissipation sign, min instead of max in the wave speed, a wrong
+Jacobian entry, a wrong lifting factor, a dropped pressure term, a wrong Pade
+coefficient, a broken augmented shift or scaling, a wrong stepper
+coefficient, a wrong quadrature weight.
+"""
+import os
+import shutil
+
+import pytest
+
+import oracle
+from tests import test_oracle_dg as dg
+from tests import test_oracle_phi as phi
+from tests import test_oracle_refelem as refelem
+from tests import test_oracle_steppers as steppers
+
+MUTATIONS = {
+    "dissipation_sign": ("dg.cpp", "0.5 * lam * (um[c] - up[c])", "0.5 * lam * (up[c] - um[c])",
+                         lambda: dg.test_burgers_upwind_energy(0.9, 1)),
+    "lambda_min": ("dg.cpp", "std::fmax(wave_speed(g, qm, dir), wave_speed(g, qp, dir))",
+                   "std::fmin(wave_speed(g, qm, dir), wave_speed(g, qp, dir))",
+                   lambda: dg.test_piecewise_constant_rusanov(1)),
+    "jacobian_entry": ("dg.cpp", "acc += gt * n[a] * v[3];", "acc += gm * n[a] * v[3];",
+                       lambda: dg.test_jvp_equals_complex_step(2)),
+    "lift_factor": ("dg.cpp", "res[c] -= (2.0 / h[dir]) / g.w[a] * (fstar_n - f_n);",
+                    "res[c] -= (2.0 / h[dir]) * g.w[a] * (fstar_n - f_n);",
+                    lambda: dg.test_piecewise_constant_rusanov(3)),
+    "energy_flux": ("dg.cpp", "f[3] = (q[3] + p) * un;", "f[3] = q[3] * un;",
+                    lambda: steppers.test_vortex_spatial_order(2)),
+    "pade_coeff": ("expm.cpp", "(k * (2 * q - k + 1))", "(k * (2 * q - k))",
+                   lambda: phi.test_expm_vs_scipy(12, 1.0)),
+    "augmented_shift": ("krylov.cpp", "y[n + k] = x[n + k + 1];", "y[n + k + 1] = x[n + k];",
+                        lambda: phi.test_krylov_dense_random(3)),
+    "eta_scaling": ("krylov.cpp", "z[n + p - 1] = 1.0 / eta;", "z[n + p - 1] = eta;",
+                    lambda: phi.test_krylov_dense_random(2)),
+    "epi3_coeff": ("steppers.cpp", "(2.0 / 3.0) * (Rp[i]", "0.5 * (Rp[i]",
+                   lambda: steppers.test_temporal_order_burgers("epi3", 3.0)),
+    "exprb32_coeff": ("steppers.cpp", "b3[i] = 2.0 * (R2[i]", "b3[i] = 1.0 * (R2[i]",
+                      lambda: steppers.test_temporal_order_burgers("exprb32", 3.0)),
+    "lgl_weight": ("refelem.cpp", "w[i] = 2.0 / (p * (p + 1.0) * P * P);",
+                   "w[i] = 2.0 / ((p + 1.0) * (p + 1.0) * P * P);",
+                   lambda: refelem.test_quadrature_exactness(3)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_pin_catches_mutation(name, tmp_path):
+    fname, old, new, pin = MUTATIONS[name]
+    src = tmp_path / "src"
+    src.mkdir()
+    for f in oracle.SOURCES + ["oracle.h"]:
+        shutil.copy(os.path.join(oracle.HERE, f), src / f)
+    text = (src / fname).read_text()
+    assert text.count(old) == 1, f"mutation anchor not unique in {fname}: {old}"
+    (src / fname).write_text(text.replace(old, new))
+    lib = oracle.build_at(str(src), str(tmp_path / "libmut.so"))
+    pin()  # the unmutated oracle passes the pin
+    with oracle.use_library(lib):
+        with pytest.raises(AssertionError):
+            pin()
