@@ -1,0 +1,199 @@
+/*
+ * expdg.h -- C ABI of the MI355X (gfx950) exponential-DG library.
+ *
+ * The library evaluates the hot path of the exponential DG method of Kang &
+ * Bui-Thanh ("A scalable exponential-DG approach for nonlinear conservation
+ * laws: with application to Burger and Euler equations"):
+ *
+ *   q_t + div F(q) = 0 on a uniform periodic mesh (Section 2.2, eq. pde),
+ *   DG semi-discretization dq/dt = R(q) = L q + N(q) with LGL collocation and
+ *   Lax-Friedrichs / Rusanov numerical fluxes (Section 2.2,
+ *   eq. EXPO-SemiDiscretizedForm_ode; Sections 3.1 and 3.2),
+ *   phi-function combinations sum_k tau^k phi_k(tau L) b_k by Krylov
+ *   projection of the augmented matrix (Section 2.3,
+ *   eq. linear_combination_of_phifunctions), and
+ *   the exponential steppers EPI2 and EXPRB32 (footnotes of Section 5.1) and
+ *   Tokman's EPI3 (cited in Section 1).
+ *
+ * Every compute step runs in HIP kernels on the device.  All entry points are
+ * plain C: pointers and sizes, no C++ or framework types.
+ *
+ * Nodal layout of every state vector (device memory):
+ *     idx = (c * K + e) * Np + n,   c = variable, e = ey * nx + ex,
+ *     n = j * (p + 1) + i  (i along x; 1D: n = i),
+ * Burgers: one variable u.  Euler: (rho, rho u, rho v, rho E).
+ * Np = p + 1 (1D) or (p + 1)^2 (2D); K = nx * ny; ndof = nvar * K * Np.
+ *
+ * Precision: in EXPDG_FP64 every buffer is double.  In EXPDG_FP32_BULK the
+ * operator buffers of expdg_rhs / expdg_jvp / expdg_phi_krylov are float and
+ * the Krylov basis is stored in float, while inner products, norms, the
+ * Hessenberg matrix, its exponential and the controller stay in double, and
+ * expdg_step keeps its state q in double.
+ *
+ * Ownership: the caller owns every state, input and output buffer; the mesh
+ * owns its geometry tables and the Krylov workspace, allocated once by
+ * expdg_mesh_create (sized by m_max) and released by expdg_mesh_destroy.  No
+ * entry point allocates device memory after creation.
+ *
+ * Streams: hip_stream is a hipStream_t passed as void* (NULL = the null
+ * stream).  expdg_rhs and expdg_jvp are asynchronous on that stream.
+ * expdg_phi_krylov and expdg_step return after the work has completed, so
+ * their statistics are valid on return.
+ *
+ * Errors: every entry point returns EXPDG_OK (0) or a negative status and
+ * never throws.  Arguments are validated before anything is launched; on
+ * EXPDG_EINVAL outputs are untouched.  On EXPDG_ENOCONV / EXPDG_ENONFINITE
+ * the output is undefined and the mesh stays usable.  expdg_last_error()
+ * returns a thread-local description of the last failure.  A mesh handle may
+ * be used by one host thread at a time.
+ */
+#ifndef EXPDG_H
+#define EXPDG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { EXPDG_BURGERS1D = 1, EXPDG_EULER2D = 2 };
+enum { EXPDG_FP64 = 0, EXPDG_FP32_BULK = 1 };
+enum { EXPDG_EPI2 = 2, EXPDG_EPI3 = 3, EXPDG_EXPRB32 = 32 };
+enum {
+    EXPDG_OK = 0,
+    EXPDG_EINVAL = -1,     /* invalid argument */
+    EXPDG_ENOMEM = -2,     /* device allocation failed */
+    EXPDG_EDEVICE = -3,    /* HIP runtime error */
+    EXPDG_ENOCONV = -4,    /* Krylov substep fell below its floor */
+    EXPDG_ENONFINITE = -5  /* non-finite norm, Hessenberg entry or state */
+};
+
+/* Mesh description.  Uniform periodic mesh: nx intervals on [x0, x1]
+ * (Burgers, ny = 1) or nx x ny quadrilaterals on [x0, x1] x [y0, y1]
+ * (Euler).  p is the LGL degree (1..6).  m_max bounds the Krylov basis
+ * (1..64).  gamma is used by Euler only. */
+typedef struct {
+    int equation;   /* EXPDG_BURGERS1D or EXPDG_EULER2D */
+    int nx, ny;
+    int p;
+    int precision;  /* EXPDG_FP64 or EXPDG_FP32_BULK */
+    int device;     /* HIP device ordinal */
+    double x0, x1, y0, y1;
+    double gamma;
+    int m_max;
+} expdg_mesh_desc;
+
+typedef struct expdg_mesh expdg_mesh; /* opaque, library-owned */
+
+/* Sizes of a created mesh. */
+typedef struct {
+    size_t ndof;       /* nvar * K * Np */
+    int nvar, K, Np;
+    int elem_bytes;    /* 8 (FP64) or 4 (FP32_BULK) for operator buffers */
+    double hx, hy;     /* element sizes */
+    double dx_min;     /* smallest LGL node spacing in physical units */
+} expdg_mesh_info;
+
+/* One accepted Krylov substep: basis size m, substep length dtau, last != 0
+ * when it completes its phi evaluation. */
+typedef struct {
+    int m;
+    int last;
+    double dtau;
+} expdg_substep;
+
+/* Krylov controller options (Section 2.3; the paper runs an adaptive Krylov
+ * method with unreported parameters, so the controller is fixed here):
+ * error checked at m_min and every check_every iterations after it; tol is
+ * relative to nu = ||b_0|| + sum_k tau^k ||b_k|| / k!.  If n_forced > 0 the
+ * substeps in forced[] are replayed with no error checks (m_max is then
+ * ignored except as the workspace bound). */
+typedef struct {
+    double tol;
+    int m_min, m_max, check_every;
+    const expdg_substep *forced;
+    int n_forced;
+} expdg_krylov_opts;
+
+/* Statistics, accumulated over the call (zero them before the call).  If
+ * log != NULL accepted substeps are appended while log_len < log_cap
+ * (log_len counts all of them). */
+typedef struct {
+    int substeps, rejects, krylov_iters, jvps, breakdown, phi_calls, rhs_calls;
+    double err_est;
+    expdg_substep *log;
+    int log_cap, log_len;
+} expdg_krylov_stats;
+
+/* ---- mesh -------------------------------------------------------------- */
+
+/* Create a mesh on desc->device: builds the LGL tables (Section 4 opening:
+ * LGL quadrature), allocates the Krylov workspace.  *out receives the
+ * handle.  EXPDG_EINVAL for an invalid description, EXPDG_ENOMEM if the
+ * workspace does not fit. */
+int expdg_mesh_create(const expdg_mesh_desc *desc, expdg_mesh **out);
+int expdg_mesh_destroy(expdg_mesh *m);
+/* Device bytes expdg_mesh_create would allocate for desc (0 if invalid). */
+size_t expdg_workspace_bytes(const expdg_mesh_desc *desc);
+int expdg_mesh_get_info(const expdg_mesh *m, expdg_mesh_info *info);
+/* Physical node coordinates, host arrays of K*Np doubles (y may be NULL). */
+int expdg_mesh_nodes(const expdg_mesh *m, double *x, double *y);
+/* The library's LGL reference element: nodes, weights, and the
+ * differentiation matrix D[i*(p+1)+j] = l_j'(xi_i); host arrays. */
+int expdg_lgl(int p, double *xi, double *w, double *D);
+
+/* ---- operators (Section 2.2; Sections 3.1 and 3.2) ---------------------- */
+
+/* r = R(q): full DG residual with Lax-Friedrichs / Rusanov flux, lambda =
+ * max(|u^-|, |u^+|) (Burgers) or max(|u.n| + a) over the two traces
+ * (Euler).  q, r: device buffers of ndof bulk-type elements. */
+int expdg_rhs(expdg_mesh *m, const void *q, void *r, void *hip_stream);
+
+/* w = L(qref) v: the DG operator of the linear flux F_L = A(qref) v (eq.
+ * linearflux; Burgers F_L = u~ v, Euler the flux Jacobian of Section 3.2),
+ * with the numerical flux dissipation frozen at qref.  Device buffers of
+ * ndof bulk-type elements; v and w must not alias. */
+int expdg_jvp(expdg_mesh *m, const void *qref, const void *v, void *w, void *hip_stream);
+
+/* Largest wave speed max(|u|) or max(|u.n| + a) over the nodes of q
+ * (device, FP64 state) into *cmax (host); synchronous.  Used for the CFL
+ * time step dt = Cr dx_min / c (Courant number of Section 5). */
+int expdg_max_speed(expdg_mesh *m, const double *q, double *cmax, void *hip_stream);
+
+/* ---- phi combinations (Section 2.3) ------------------------------------- */
+
+/* w = sum_{k=0}^{p} tau^k phi_k(tau L(qref)) b_k, 0 <= p <= 3, by adaptive
+ * Arnoldi (classical Gram-Schmidt, two passes, FP64 inner products) on the
+ * augmented matrix [[L, W], [0, J]].  b is a host array of p+1 device
+ * pointers (NULL entries are zero vectors); qref, b[k] and w are bulk-type
+ * device buffers of ndof elements.  Returns after completion. */
+int expdg_phi_krylov(expdg_mesh *m, const void *qref, double tau, int p,
+                     const void *const *b, void *w, const expdg_krylov_opts *o,
+                     expdg_krylov_stats *s, void *hip_stream);
+
+/* ---- time step (footnotes of Section 5.1; EPI3 after Tokman) ------------ */
+
+/* One step of size dt of scheme EXPDG_EPI2, EXPDG_EPI3 or EXPDG_EXPRB32 on
+ * the FP64 device state q (in/out).  EPI3 uses q_prev: when have_prev != 0
+ * it holds q^{n-1} on entry; when have_prev == 0 the step is an EPI2 step.
+ * If q_prev != NULL it receives q^n on return (for every scheme).  Returns
+ * after completion. */
+int expdg_step(expdg_mesh *m, int scheme, double dt, double *q, double *q_prev, int have_prev,
+               const expdg_krylov_opts *o, expdg_krylov_stats *s, void *hip_stream);
+
+/* Exponential of a small dense matrix on the device with the same kernel the
+ * Krylov controller uses for the projected Hessenberg matrix (diagonal Pade
+ * (6,6) with scaling and squaring, Section 2.3).  A and E are row-major
+ * n x n FP64 device buffers, 1 <= n <= 65; asynchronous on hip_stream.  E
+ * is NaN if the Pade denominator is singular. */
+int expdg_small_expm(int n, const double *A, double *E, void *hip_stream);
+
+/* Thread-local description of the last error (never NULL). */
+const char *expdg_last_error(void);
+/* ABI version: major * 10000 + minor * 100 + patch. */
+int expdg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EXPDG_H */

@@ -1,0 +1,265 @@
+"""Thin ctypes binding of ``libexpdg.so`` (C ABI in ``include/expdg.h``).
+
+Argument marshalling only: every entry point forwards device pointers (torch
+tensors' ``data_ptr()``), sizes and the current HIP stream to the library,
+where all the work runs in HIP kernels.  The module-level functions carry the
+C names (``expdg_mesh_create``, ``expdg_rhs``, ``expdg_jvp``,
+``expdg_phi_krylov``, ``expdg_step``, ...); :class:`Mesh` wraps a handle for
+convenience.  Loading fails loudly if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libexpdg.so")
+
+BURGERS1D, EULER2D = 1, 2
+FP64, FP32_BULK = 0, 1
+EPI2, EPI3, EXPRB32 = 2, 3, 32
+OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ENONFINITE = 0, -1, -2, -3, -4, -5
+
+
+class ExpdgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"expdg error {code}: {msg}")
+        self.code = code
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("equation", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("p", C.c_int),
+                ("precision", C.c_int), ("device", C.c_int), ("x0", C.c_double),
+                ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
+                ("gamma", C.c_double), ("m_max", C.c_int)]
+
+
+class MeshInfo(C.Structure):
+    _fields_ = [("ndof", C.c_size_t), ("nvar", C.c_int), ("K", C.c_int), ("Np", C.c_int),
+                ("elem_bytes", C.c_int), ("hx", C.c_double), ("hy", C.c_double),
+                ("dx_min", C.c_double)]
+
+
+class Substep(C.Structure):
+    _fields_ = [("m", C.c_int), ("last", C.c_int), ("dtau", C.c_double)]
+
+
+class KrylovOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("m_min", C.c_int), ("m_max", C.c_int),
+                ("check_every", C.c_int), ("forced", C.POINTER(Substep)), ("n_forced", C.c_int)]
+
+
+class KrylovStats(C.Structure):
+    _fields_ = [("substeps", C.c_int), ("rejects", C.c_int), ("krylov_iters", C.c_int),
+                ("jvps", C.c_int), ("breakdown", C.c_int), ("phi_calls", C.c_int),
+                ("rhs_calls", C.c_int), ("err_est", C.c_double),
+                ("log", C.POINTER(Substep)), ("log_cap", C.c_int), ("log_len", C.c_int)]
+
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "expdg_mesh_create": (C.c_int, [C.POINTER(MeshDesc), C.POINTER(C.c_void_p)]),
+    "expdg_mesh_destroy": (C.c_int, [C.c_void_p]),
+    "expdg_workspace_bytes": (C.c_size_t, [C.POINTER(MeshDesc)]),
+    "expdg_mesh_get_info": (C.c_int, [C.c_void_p, C.POINTER(MeshInfo)]),
+    "expdg_mesh_nodes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "expdg_lgl": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "expdg_rhs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "expdg_jvp": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "expdg_max_speed": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.c_void_p]),
+    "expdg_phi_krylov": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_int,
+                                   C.POINTER(C.c_void_p), C.c_void_p, C.POINTER(KrylovOpts),
+                                   C.POINTER(KrylovStats), C.c_void_p]),
+    "expdg_step": (C.c_int, [C.c_void_p, C.c_int, C.c_double, C.c_void_p, C.c_void_p, C.c_int,
+                             C.POINTER(KrylovOpts), C.POINTER(KrylovStats), C.c_void_p]),
+    "expdg_small_expm": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "expdg_last_error": (C.c_char_p, []),
+    "expdg_version": (C.c_int, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libexpdg.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ExpdgError(EDEVICE, f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise ExpdgError(rc, lib().expdg_last_error().decode(errors="replace"))
+
+
+def _ptr(x):
+    """Device pointer of a tensor, an int address, or None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return stream if isinstance(stream, int) else stream.cuda_stream
+
+
+# ---- C names ---------------------------------------------------------------
+def expdg_mesh_create(desc: MeshDesc) -> int:
+    h = C.c_void_p()
+    _check(lib().expdg_mesh_create(C.byref(desc), C.byref(h)))
+    return h.value
+
+
+def expdg_mesh_destroy(handle: int) -> None:
+    _check(lib().expdg_mesh_destroy(handle))
+
+
+def expdg_workspace_bytes(desc: MeshDesc) -> int:
+    return lib().expdg_workspace_bytes(C.byref(desc))
+
+
+def expdg_rhs(handle, q, r, stream=None):
+    _check(lib().expdg_rhs(handle, _ptr(q), _ptr(r), _stream(stream)))
+
+
+def expdg_jvp(handle, qref, v, w, stream=None):
+    _check(lib().expdg_jvp(handle, _ptr(qref), _ptr(v), _ptr(w), _stream(stream)))
+
+
+def expdg_max_speed(handle, q, stream=None) -> float:
+    c = C.c_double()
+    _check(lib().expdg_max_speed(handle, _ptr(q), C.byref(c), _stream(stream)))
+    return c.value
+
+
+def make_opts(tol=1e-10, m_min=10, m_max=64, check_every=1, forced=None):
+    """Krylov options; forced is a list of (m, dtau, last)."""
+    keep = None
+    if forced:
+        keep = (Substep * len(forced))(*[Substep(int(m), int(last), float(dt))
+                                         for (m, dt, last) in forced])
+        o = KrylovOpts(tol, m_min, m_max, check_every, keep, len(forced))
+    else:
+        o = KrylovOpts(tol, m_min, m_max, check_every, None, 0)
+    o._keep = keep
+    return o
+
+
+def make_stats(log_cap=4096):
+    log = (Substep * log_cap)()
+    s = KrylovStats(0, 0, 0, 0, 0, 0, 0, 0.0, log, log_cap, 0)
+    s._keep = log
+    return s
+
+
+def stats_dict(s: KrylovStats):
+    n = min(s.log_len, s.log_cap)
+    return {"substeps": s.substeps, "rejects": s.rejects, "krylov_iters": s.krylov_iters,
+            "jvps": s.jvps, "breakdown": s.breakdown, "phi_calls": s.phi_calls,
+            "rhs_calls": s.rhs_calls, "err_est": s.err_est,
+            "log": [(s.log[i].m, s.log[i].dtau, s.log[i].last) for i in range(n)]}
+
+
+def expdg_phi_krylov(handle, qref, tau, bs, w, opts, stats=None, stream=None):
+    arr = (C.c_void_p * len(bs))(*[_ptr(b) for b in bs])
+    _check(lib().expdg_phi_krylov(handle, _ptr(qref), tau, len(bs) - 1, arr, _ptr(w),
+                                  C.byref(opts), C.byref(stats) if stats is not None else None,
+                                  _stream(stream)))
+
+
+def expdg_step(handle, scheme, dt, q, q_prev, have_prev, opts, stats=None, stream=None):
+    _check(lib().expdg_step(handle, scheme, dt, _ptr(q), _ptr(q_prev), int(have_prev),
+                            C.byref(opts), C.byref(stats) if stats is not None else None,
+                            _stream(stream)))
+
+
+def expdg_small_expm(n, A, E, stream=None):
+    _check(lib().expdg_small_expm(n, _ptr(A), _ptr(E), _stream(stream)))
+
+
+def expdg_lgl(p):
+    import numpy as np
+    xi, w, D = np.zeros(p + 1), np.zeros(p + 1), np.zeros((p + 1) * (p + 1))
+    _check(lib().expdg_lgl(p, xi.ctypes.data, w.ctypes.data, D.ctypes.data))
+    return xi, w, D.reshape(p + 1, p + 1)
+
+
+# ---- convenience wrapper ------------------------------------------------------
+class Mesh:
+    """Owns an expdg mesh handle; methods forward to the C entry points."""
+
+    def __init__(self, equation, nx, p, ny=1, precision=FP64, device=0, x0=0.0, x1=1.0,
+                 y0=0.0, y1=1.0, gamma=1.4, m_max=64):
+        self.desc = MeshDesc(equation, nx, ny, p, precision, device, x0, x1, y0, y1, gamma,
+                             m_max)
+        self.handle = expdg_mesh_create(self.desc)
+        info = MeshInfo()
+        _check(lib().expdg_mesh_get_info(self.handle, C.byref(info)))
+        self.n, self.nvar, self.K, self.Np = info.ndof, info.nvar, info.K, info.Np
+        self.hx, self.hy, self.dx_min = info.hx, info.hy, info.dx_min
+        self.elem_bytes = info.elem_bytes
+        self.p, self.equation, self.precision = p, equation, precision
+
+    def close(self):
+        if self.handle:
+            expdg_mesh_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def dtype(self):
+        import torch
+        return torch.float64 if self.precision == FP64 else torch.float32
+
+    def nodes(self):
+        import numpy as np
+        x = np.zeros(self.K * self.Np)
+        y = np.zeros(self.K * self.Np)
+        _check(lib().expdg_mesh_nodes(self.handle, x.ctypes.data, y.ctypes.data))
+        return x, y
+
+    def rhs(self, q, r, stream=None):
+        expdg_rhs(self.handle, q, r, stream)
+
+    def jvp(self, qref, v, w, stream=None):
+        expdg_jvp(self.handle, qref, v, w, stream)
+
+    def max_speed(self, q, stream=None):
+        return expdg_max_speed(self.handle, q, stream)
+
+    def phi_krylov(self, qref, tau, bs, w, opts, stats=None, stream=None):
+        expdg_phi_krylov(self.handle, qref, tau, bs, w, opts, stats, stream)
+
+    def step(self, scheme, dt, q, q_prev=None, have_prev=False, opts=None, stats=None,
+             stream=None):
+        expdg_step(self.handle, scheme, dt, q, q_prev, have_prev, opts or make_opts(), stats,
+                   stream)

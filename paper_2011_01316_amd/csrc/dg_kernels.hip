@@ -1,0 +1,488 @@
+// Fused nodal DG operator kernels for gfx950: residual R(q) and the linear
+// operator L(q~) v of the flux-Jacobian split, plus elementwise helpers.
+//
+// Operator (Section 2.2, eq. EXPO-SemiDiscretizedForm_ode, in strong form on
+// LGL nodes with the diagonal LGL mass matrix):
+//   out_i = -sum_dir (2/h_dir) sum_l D_il F_dir,l
+//           - sum_faces (2/h_dir)(1/w_0) [ s (F^+ - F^-)/2 + lambda (u^- - u^+)/2 ]
+// on face nodes, s = +-1 the outward normal along dir.  The residual uses the
+// physical flux F(q) and the Lax-Friedrichs / Rusanov speed lambda(q); the
+// linear operator uses F_L = A(q~) v with lambda(q~) (Sections 3.1-3.2).
+//
+// Work mapping: one thread per LGL node, floor(256/Np) whole elements per
+// 256-thread block, so a block reads each variable plane as one contiguous
+// run.  The per-node fluxes go through LDS for the tensor-product derivative
+// (a (p+1)-point contraction per direction: too small for MFMA tiles, it is
+// bandwidth-bound).  Face traces of the neighbour are gathered from global
+// memory; the block -> tile map gives each XCD a contiguous range of
+// elements so y-neighbours (nx elements away) are usually resident in that
+// XCD's L2.
+#include "internal.h"
+
+namespace expdg {
+namespace {
+
+// Hardware dispatches block b to XCD b % 8.  Give XCD x the contiguous tile
+// range it would own under a block partition of the tiles.
+__device__ __forceinline__ int xcd_tile(int b, int G) {
+    const int q = G >> 3, r = G & 7;
+    const int x = b & 7, k = b >> 3;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+}
+
+// ---- Euler physics --------------------------------------------------------
+// Physical fluxes F_x, F_y of q = (rho, m, n, E), m = rho u, n = rho v.
+template <typename T>
+__device__ __forceinline__ void euler_flux(const T *q, T gm1, T *fx, T *fy) {
+    const T ir = T(1) / q[0];
+    const T u = q[1] * ir, v = q[2] * ir;
+    const T p = gm1 * (q[3] - T(0.5) * (q[1] * u + q[2] * v));
+    fx[0] = q[1];
+    fx[1] = q[1] * u + p;
+    fx[2] = q[2] * u;
+    fx[3] = (q[3] + p) * u;
+    fy[0] = q[2];
+    fy[1] = q[1] * v;
+    fy[2] = q[2] * v + p;
+    fy[3] = (q[3] + p) * v;
+}
+
+// Directional derivatives dF_x(q)[d], dF_y(q)[d], written through the
+// pressure perturbation dp = (g-1)(|u|^2/2 drho - u dm - v dn + dE); equal to
+// the flux Jacobian of Section 3.2 applied to d.
+template <typename T>
+__device__ __forceinline__ void euler_jac(const T *q, const T *d, T gm1, T *fx, T *fy) {
+    const T ir = T(1) / q[0];
+    const T u = q[1] * ir, v = q[2] * ir;
+    const T p = gm1 * (q[3] - T(0.5) * (q[1] * u + q[2] * v));
+    const T H = (q[3] + p) * ir;
+    const T dp = gm1 * (T(0.5) * (u * u + v * v) * d[0] - u * d[1] - v * d[2] + d[3]);
+    fx[0] = d[1];
+    fx[1] = T(2) * u * d[1] - u * u * d[0] + dp;
+    fx[2] = u * d[2] + v * d[1] - u * v * d[0];
+    fx[3] = u * (d[3] + dp) + H * (d[1] - u * d[0]);
+    fy[0] = d[2];
+    fy[1] = v * d[1] + u * d[2] - u * v * d[0];
+    fy[2] = T(2) * v * d[2] - v * v * d[0] + dp;
+    fy[3] = v * (d[3] + dp) + H * (d[2] - v * d[0]);
+}
+
+// One direction only (for the neighbour trace).
+template <typename T, int DIR>
+__device__ __forceinline__ void euler_flux_dir(const T *q, T gm1, T *f) {
+    const T ir = T(1) / q[0];
+    const T u = q[1] * ir, v = q[2] * ir;
+    const T p = gm1 * (q[3] - T(0.5) * (q[1] * u + q[2] * v));
+    const T un = DIR == 0 ? u : v;
+    f[0] = q[1 + DIR];
+    f[1] = q[1] * un + (DIR == 0 ? p : T(0));
+    f[2] = q[2] * un + (DIR == 1 ? p : T(0));
+    f[3] = (q[3] + p) * un;
+}
+
+template <typename T, int DIR>
+__device__ __forceinline__ void euler_jac_dir(const T *q, const T *d, T gm1, T *f) {
+    const T ir = T(1) / q[0];
+    const T u = q[1] * ir, v = q[2] * ir;
+    const T p = gm1 * (q[3] - T(0.5) * (q[1] * u + q[2] * v));
+    const T H = (q[3] + p) * ir;
+    const T dp = gm1 * (T(0.5) * (u * u + v * v) * d[0] - u * d[1] - v * d[2] + d[3]);
+    if (DIR == 0) {
+        f[0] = d[1];
+        f[1] = T(2) * u * d[1] - u * u * d[0] + dp;
+        f[2] = u * d[2] + v * d[1] - u * v * d[0];
+        f[3] = u * (d[3] + dp) + H * (d[1] - u * d[0]);
+    } else {
+        f[0] = d[2];
+        f[1] = v * d[1] + u * d[2] - u * v * d[0];
+        f[2] = T(2) * v * d[2] - v * v * d[0] + dp;
+        f[3] = v * (d[3] + dp) + H * (d[2] - v * d[0]);
+    }
+}
+
+// |u . e_dir| + a, a = sqrt(gamma p / rho).
+template <typename T, int DIR>
+__device__ __forceinline__ T euler_speed(const T *q, T gamma) {
+    const T ir = T(1) / q[0];
+    const T u = q[1] * ir, v = q[2] * ir;
+    const T p = (gamma - T(1)) * (q[3] - T(0.5) * (q[1] * u + q[2] * v));
+    return fabs(DIR == 0 ? u : v) + sqrt(gamma * p * ir);
+}
+
+// ---- Euler 2D operator ------------------------------------------------------
+template <int P, typename T, bool JVP>
+__global__ __launch_bounds__(256) void euler_op(OpArgs<T> a) {
+    constexpr int N1 = P + 1, NP = N1 * N1, EPB = 256 / NP, NT = EPB * NP;
+    __shared__ T sF[8][NT];
+    const int tid = threadIdx.x;
+    const int le = tid / NP;
+    const int n = tid - le * NP;
+    const int i = n % N1, j = n / N1;
+    const int e = xcd_tile(blockIdx.x, gridDim.x) * EPB + le;
+    const bool active = (tid < NT) && (e < a.K);
+    const size_t plane = (size_t)a.K * NP;
+    const size_t idx = (size_t)e * NP + n;
+    const T gm1 = a.gamma - T(1);
+
+    T sc = T(1);
+    if (a.vscale) sc = (T)(*a.vscale);
+    // augmented entries of the output: (y_2, ..., y_p, 0), scaled
+    if (a.naug > 0 && blockIdx.x == 0 && tid == 0) {
+        for (int k = 0; k < a.naug; ++k)
+            a.otail[k] = (k + 1 < a.naug) ? sc * a.vtail[k + 1] : T(0);
+    }
+
+    T q[4], u[4], fx[4], fy[4];
+    if (active) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) q[c] = a.q[c * plane + idx];
+        if (JVP) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) u[c] = a.v[c * plane + idx];
+            euler_jac(q, u, gm1, fx, fy);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) u[c] = q[c];
+            euler_flux(q, gm1, fx, fy);
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) q[c] = u[c] = fx[c] = fy[c] = T(0);
+    }
+    if (tid < NT) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            sF[c][tid] = fx[c];
+            sF[4 + c][tid] = fy[c];
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+
+    T res[4] = {T(0), T(0), T(0), T(0)};
+    const int base = le * NP;
+#pragma unroll
+    for (int l = 0; l < N1; ++l) {
+        const T dx = a.rhx * a.D[i * N1 + l];
+        const T dy = a.rhy * a.D[j * N1 + l];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            res[c] -= dx * sF[c][base + j * N1 + l] + dy * sF[4 + c][base + l * N1 + i];
+    }
+
+    const int ex = e % a.nx, ey = e / a.nx;
+    if (i == 0 || i == P) {
+        const int s = (i == P) ? 1 : -1;
+        int exn = ex + s;
+        exn = exn < 0 ? a.nx - 1 : (exn >= a.nx ? 0 : exn);
+        const size_t nidx = (size_t)(ey * a.nx + exn) * NP + j * N1 + (P - i);
+        T qn[4], un[4], fn[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) qn[c] = a.q[c * plane + nidx];
+        if (JVP) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) un[c] = a.v[c * plane + nidx];
+            euler_jac_dir<T, 0>(qn, un, gm1, fn);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) un[c] = qn[c];
+            euler_flux_dir<T, 0>(qn, gm1, fn);
+        }
+        const T lam = fmax(euler_speed<T, 0>(q, a.gamma), euler_speed<T, 0>(qn, a.gamma));
+        const T cf = a.rhx * a.lift;
+        const T hs = T(0.5) * T(s);
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            res[c] -= cf * (hs * (fn[c] - fx[c]) + T(0.5) * lam * (u[c] - un[c]));
+    }
+    if (j == 0 || j == P) {
+        const int s = (j == P) ? 1 : -1;
+        int eyn = ey + s;
+        eyn = eyn < 0 ? a.ny - 1 : (eyn >= a.ny ? 0 : eyn);
+        const size_t nidx = (size_t)(eyn * a.nx + ex) * NP + (P - j) * N1 + i;
+        T qn[4], un[4], fn[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) qn[c] = a.q[c * plane + nidx];
+        if (JVP) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) un[c] = a.v[c * plane + nidx];
+            euler_jac_dir<T, 1>(qn, un, gm1, fn);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) un[c] = qn[c];
+            euler_flux_dir<T, 1>(qn, gm1, fn);
+        }
+        const T lam = fmax(euler_speed<T, 1>(q, a.gamma), euler_speed<T, 1>(qn, a.gamma));
+        const T cf = a.rhy * a.lift;
+        const T hs = T(0.5) * T(s);
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            res[c] -= cf * (hs * (fn[c] - fy[c]) + T(0.5) * lam * (u[c] - un[c]));
+    }
+
+    // augmented block: + eta sum_k y_k b_{p+1-k}
+    for (int k = 0; k < a.naug; ++k) {
+        const T *b = a.aug[k];
+        if (!b) continue;
+        const T yk = (T)a.eta * a.vtail[k];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) res[c] += yk * b[c * plane + idx];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a.out[c * plane + idx] = sc * res[c];
+}
+
+// ---- Burgers 1D operator ----------------------------------------------------
+template <int P, typename T, bool JVP>
+__global__ __launch_bounds__(256) void burgers_op(OpArgs<T> a) {
+    constexpr int N1 = P + 1, EPB = 256 / N1, NT = EPB * N1;
+    __shared__ T sF[NT];
+    const int tid = threadIdx.x;
+    const int le = tid / N1;
+    const int i = tid - le * N1;
+    const int e = xcd_tile(blockIdx.x, gridDim.x) * EPB + le;
+    const bool active = (tid < NT) && (e < a.K);
+    const size_t idx = (size_t)e * N1 + i;
+
+    T sc = T(1);
+    if (a.vscale) sc = (T)(*a.vscale);
+    if (a.naug > 0 && blockIdx.x == 0 && tid == 0) {
+        for (int k = 0; k < a.naug; ++k)
+            a.otail[k] = (k + 1 < a.naug) ? sc * a.vtail[k + 1] : T(0);
+    }
+
+    T qv = T(0), uv = T(0), f = T(0);
+    if (active) {
+        qv = a.q[idx];
+        uv = JVP ? a.v[idx] : qv;
+        f = JVP ? qv * uv : T(0.5) * qv * qv;
+    }
+    if (tid < NT) sF[tid] = f;
+    __syncthreads();
+    if (!active) return;
+
+    T res = T(0);
+    const int base = le * N1;
+#pragma unroll
+    for (int l = 0; l < N1; ++l) res -= a.rhx * a.D[i * N1 + l] * sF[base + l];
+    if (i == 0 || i == P) {
+        const int s = (i == P) ? 1 : -1;
+        int en = e + s;
+        en = en < 0 ? a.K - 1 : (en >= a.K ? 0 : en);
+        const size_t nidx = (size_t)en * N1 + (P - i);
+        const T qn = a.q[nidx];
+        const T un = JVP ? a.v[nidx] : qn;
+        const T fn = JVP ? qn * un : T(0.5) * qn * qn;
+        const T lam = fmax(fabs(qv), fabs(qn));
+        res -= a.rhx * a.lift * (T(0.5) * T(s) * (fn - f) + T(0.5) * lam * (uv - un));
+    }
+    for (int k = 0; k < a.naug; ++k) {
+        const T *b = a.aug[k];
+        if (!b) continue;
+        res += (T)a.eta * a.vtail[k] * b[idx];
+    }
+    a.out[idx] = sc * res;
+}
+
+template <int P, typename T>
+hipError_t launch_p(int equation, bool jvp, const OpArgs<T> &a, hipStream_t s) {
+    if (equation == EXPDG_EULER2D) {
+        constexpr int EPB = 256 / ((P + 1) * (P + 1));
+        const int grid = (a.K + EPB - 1) / EPB;
+        if (jvp)
+            euler_op<P, T, true><<<grid, 256, 0, s>>>(a);
+        else
+            euler_op<P, T, false><<<grid, 256, 0, s>>>(a);
+    } else {
+        constexpr int EPB = 256 / (P + 1);
+        const int grid = (a.K + EPB - 1) / EPB;
+        if (jvp)
+            burgers_op<P, T, true><<<grid, 256, 0, s>>>(a);
+        else
+            burgers_op<P, T, false><<<grid, 256, 0, s>>>(a);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_any(int equation, int p, bool jvp, const OpArgs<T> &a, hipStream_t s) {
+    switch (p) {
+        case 1: return launch_p<1, T>(equation, jvp, a, s);
+        case 2: return launch_p<2, T>(equation, jvp, a, s);
+        case 3: return launch_p<3, T>(equation, jvp, a, s);
+        case 4: return launch_p<4, T>(equation, jvp, a, s);
+        case 5: return launch_p<5, T>(equation, jvp, a, s);
+        case 6: return launch_p<6, T>(equation, jvp, a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// ---- wave speed -------------------------------------------------------------
+__global__ __launch_bounds__(256) void max_speed_kernel(int equation, const double *q,
+                                                        size_t npts, double gamma,
+                                                        double *part) {
+    __shared__ double sm[256];
+    double mx = 0.0;
+    for (size_t r = (size_t)blockIdx.x * 256 + threadIdx.x; r < npts;
+         r += (size_t)gridDim.x * 256) {
+        if (equation == EXPDG_BURGERS1D) {
+            mx = fmax(mx, fabs(q[r]));
+        } else {
+            const double qq[4] = {q[r], q[npts + r], q[2 * npts + r], q[3 * npts + r]};
+            mx = fmax(mx, fmax(euler_speed<double, 0>(qq, gamma), euler_speed<double, 1>(qq, gamma)));
+        }
+    }
+    sm[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+}
+
+// ---- elementwise ------------------------------------------------------------
+template <typename TO, typename TI>
+__global__ __launch_bounds__(256) void convert_kernel(const TI *x, TO *y, size_t n) {
+    for (size_t r = (size_t)blockIdx.x * 256 + threadIdx.x; r < n; r += (size_t)gridDim.x * 256)
+        y[r] = (TO)x[r];
+}
+
+template <typename TO, typename TX>
+__global__ __launch_bounds__(256) void lincomb_kernel(TO *out, double a, const TX *x, double b,
+                                                      const TX *y, double c, const TX *z,
+                                                      size_t n) {
+    for (size_t r = (size_t)blockIdx.x * 256 + threadIdx.x; r < n;
+         r += (size_t)gridDim.x * 256) {
+        double acc = a * (double)x[r];
+        if (y) acc += b * (double)y[r];
+        if (z) acc += c * (double)z[r];
+        out[r] = (TO)acc;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void add_to_kernel(double *q, const T *w, size_t n) {
+    for (size_t r = (size_t)blockIdx.x * 256 + threadIdx.x; r < n; r += (size_t)gridDim.x * 256)
+        q[r] += (double)w[r];
+}
+
+// out = x + y (FP64 out and x, y of the bulk type)
+template <typename T>
+__global__ __launch_bounds__(256) void add_mixed_kernel(double *out, const double *x, const T *y,
+                                                        size_t n) {
+    for (size_t r = (size_t)blockIdx.x * 256 + threadIdx.x; r < n; r += (size_t)gridDim.x * 256)
+        out[r] = x[r] + (double)y[r];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void fill_kernel(T *x, T val, size_t n) {
+    for (size_t r = (size_t)blockIdx.x * 256 + threadIdx.x; r < n; r += (size_t)gridDim.x * 256)
+        x[r] = val;
+}
+
+// x[0..p) = (0, ..., 0, last)
+template <typename T>
+__global__ void set_tail_kernel(T *x, int p, double last) {
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        for (int k = 0; k < p; ++k) x[k] = (k == p - 1) ? (T)last : T(0);
+}
+
+int grid_for(size_t n) {
+    size_t g = (n + 255) / 256;
+    if (g > 8192) g = 8192;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_dg_op(int equation, int p, bool jvp, const OpArgs<double> &a, hipStream_t s) {
+    return launch_any<double>(equation, p, jvp, a, s);
+}
+hipError_t launch_dg_op(int equation, int p, bool jvp, const OpArgs<float> &a, hipStream_t s) {
+    return launch_any<float>(equation, p, jvp, a, s);
+}
+
+int max_speed_blocks(size_t npts) {
+    size_t g = (npts + 255) / 256;
+    if (g > 1024) g = 1024;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+hipError_t launch_max_speed(int equation, const double *q, size_t npts, double gamma, double *part,
+                            int nblk, hipStream_t s) {
+    max_speed_kernel<<<nblk, 256, 0, s>>>(equation, q, npts, gamma, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert(const double *x, float *y, size_t n, hipStream_t s) {
+    convert_kernel<float, double><<<grid_for(n), 256, 0, s>>>(x, y, n);
+    return hipGetLastError();
+}
+hipError_t launch_convert(const float *x, double *y, size_t n, hipStream_t s) {
+    convert_kernel<double, float><<<grid_for(n), 256, 0, s>>>(x, y, n);
+    return hipGetLastError();
+}
+hipError_t launch_copy(const double *x, double *y, size_t n, hipStream_t s) {
+    convert_kernel<double, double><<<grid_for(n), 256, 0, s>>>(x, y, n);
+    return hipGetLastError();
+}
+hipError_t launch_copy(const float *x, float *y, size_t n, hipStream_t s) {
+    convert_kernel<float, float><<<grid_for(n), 256, 0, s>>>(x, y, n);
+    return hipGetLastError();
+}
+
+template <typename TO, typename TX>
+hipError_t launch_lincomb(TO *out, double a, const TX *x, double b, const TX *y, double c,
+                          const TX *z, size_t n, hipStream_t s) {
+    lincomb_kernel<TO, TX><<<grid_for(n), 256, 0, s>>>(out, a, x, b, y, c, z, n);
+    return hipGetLastError();
+}
+template hipError_t launch_lincomb<double, double>(double *, double, const double *, double,
+                                                   const double *, double, const double *,
+                                                   size_t, hipStream_t);
+template hipError_t launch_lincomb<float, float>(float *, double, const float *, double,
+                                                 const float *, double, const float *, size_t,
+                                                 hipStream_t);
+template hipError_t launch_lincomb<float, double>(float *, double, const double *, double,
+                                                  const double *, double, const double *,
+                                                  size_t, hipStream_t);
+
+template <typename T>
+hipError_t launch_add_to(double *q, const T *w, size_t n, hipStream_t s) {
+    add_to_kernel<T><<<grid_for(n), 256, 0, s>>>(q, w, n);
+    return hipGetLastError();
+}
+template hipError_t launch_add_to<double>(double *, const double *, size_t, hipStream_t);
+template hipError_t launch_add_to<float>(double *, const float *, size_t, hipStream_t);
+
+template <typename T>
+hipError_t launch_add_mixed(double *out, const double *x, const T *y, size_t n, hipStream_t s) {
+    add_mixed_kernel<T><<<grid_for(n), 256, 0, s>>>(out, x, y, n);
+    return hipGetLastError();
+}
+template hipError_t launch_add_mixed<double>(double *, const double *, const double *, size_t,
+                                             hipStream_t);
+template hipError_t launch_add_mixed<float>(double *, const double *, const float *, size_t,
+                                            hipStream_t);
+
+template <typename T>
+hipError_t launch_fill(T *x, double val, size_t n, hipStream_t s) {
+    fill_kernel<T><<<grid_for(n), 256, 0, s>>>(x, (T)val, n);
+    return hipGetLastError();
+}
+template hipError_t launch_fill<double>(double *, double, size_t, hipStream_t);
+template hipError_t launch_fill<float>(float *, double, size_t, hipStream_t);
+template hipError_t launch_fill<int>(int *, double, size_t, hipStream_t);
+
+template <typename T>
+hipError_t launch_set_tail(T *x, int p, double last, hipStream_t s) {
+    set_tail_kernel<T><<<1, 64, 0, s>>>(x, p, last);
+    return hipGetLastError();
+}
+template hipError_t launch_set_tail<double>(double *, int, double, hipStream_t);
+template hipError_t launch_set_tail<float>(float *, int, double, hipStream_t);
+
+}  // namespace expdg

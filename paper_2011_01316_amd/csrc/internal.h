@@ -1,0 +1,127 @@
+// Internal declarations of the MI355X exponential-DG library (not part of the
+// C ABI).  Kernels live in dg_kernels.hip and krylov_kernels.hip; the host
+// drivers in api.cpp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/expdg.h"
+
+namespace expdg {
+
+constexpr int kMaxP = 6;       // largest LGL degree compiled
+constexpr int kMaxM = 64;      // largest Krylov basis (Hessenberg exponential in LDS)
+constexpr int kMaxAug = 3;     // largest number of phi terms beyond phi_0
+constexpr int kRedBlocks = 1024;  // blocks of the row-partitioned reduction kernels
+constexpr int kRedThreads = 256;
+
+// Arguments of the fused DG operator kernels (residual or linear operator).
+template <typename T>
+struct OpArgs {
+    const T *q;        // state (residual) or reference state (linear operator)
+    const T *v;        // direction of the linear operator (nullptr for the residual)
+    T *out;
+    const T *aug[kMaxAug];  // aug[k-1] multiplies y_k: b_{p+1-k} (nullptr = zero)
+    const T *vtail;    // the p augmented entries y of the input (nullptr if p = 0)
+    T *otail;          // the p augmented entries of the output
+    const double *vscale;  // device scalar multiplying the whole result (nullptr = 1)
+    double eta;        // scaling of the augmented block
+    int naug;          // p
+    int K, nx, ny;
+    T rhx, rhy;        // 2/hx, 2/hy
+    T lift;            // 1/w_0 (= 1/w_p)
+    T gamma;
+    T D[(kMaxP + 1) * (kMaxP + 1)];  // D[i*(p+1)+l] = l_l'(xi_i)
+};
+
+// Host-side LGL tables of degree p (library's own construction).
+int lgl_tables(int p, double *xi, double *w, double *D);
+
+// ---- kernel launchers (dg_kernels.hip) ----
+hipError_t launch_dg_op(int equation, int p, bool jvp, const OpArgs<double> &a, hipStream_t s);
+hipError_t launch_dg_op(int equation, int p, bool jvp, const OpArgs<float> &a, hipStream_t s);
+// Per-block maxima of the wave speed (FP64 state) into part[0..nblk).
+hipError_t launch_max_speed(int equation, const double *q, size_t npts, double gamma,
+                            double *part, int nblk, hipStream_t s);
+int max_speed_blocks(size_t npts);
+
+// Elementwise kernels (dg_kernels.hip).  All lengths in elements.
+// y = (To)x
+hipError_t launch_convert(const double *x, float *y, size_t n, hipStream_t s);
+hipError_t launch_convert(const float *x, double *y, size_t n, hipStream_t s);
+hipError_t launch_copy(const double *x, double *y, size_t n, hipStream_t s);
+hipError_t launch_copy(const float *x, float *y, size_t n, hipStream_t s);
+// out = a*x + b*y + c*z (z may be nullptr)
+template <typename TO, typename TX>
+hipError_t launch_lincomb(TO *out, double a, const TX *x, double b, const TX *y, double c,
+                          const TX *z, size_t n, hipStream_t s);
+// q (double) += w (T)
+template <typename T>
+hipError_t launch_add_to(double *q, const T *w, size_t n, hipStream_t s);
+// out (double) = x (double) + y (T)
+template <typename T>
+hipError_t launch_add_mixed(double *out, const double *x, const T *y, size_t n, hipStream_t s);
+// x[0..n) = val
+template <typename T>
+hipError_t launch_fill(T *x, double val, size_t n, hipStream_t s);
+// x[0..p) = (0, ..., 0, last)
+template <typename T>
+hipError_t launch_set_tail(T *x, int p, double last, hipStream_t s);
+
+// ---- Krylov kernels (krylov_kernels.hip) ----
+struct KrylovDev {
+    double *H;       // (kMaxM+1) x kMaxM Hessenberg, row-major, ld = kMaxM
+    double *S;       // kMaxM+1 basis scales (v_i = S[i] * u_i)
+    double *coef;    // kMaxM+1 update coefficients
+    double *part;    // kRedBlocks x (kMaxM+1) partial sums
+    double *res;     // result slots (see krylov_kernels.hip)
+    int *flags;      // device flags: [0] breakdown iteration (0 = none)
+};
+
+// Block partials of V_i^T w (i < nv) after w -= sum coef_i V_i (if coef).
+// mode 0: dots with V_0..V_{nv-1}; mode 1: squared norm of w (nv vectors
+// still subtracted when coef != nullptr).
+template <typename T>
+hipError_t launch_cgs_pass(const T *V, size_t stride, int nv, const double *coef, T *w,
+                           size_t L, double *part, int mode, hipStream_t s);
+// Number of blocks (and partials per output) of the row-partitioned kernels
+// for vectors of length L.
+int red_blocks(size_t L);
+// Finish a dot pass: h_i = S[i] * sum_b part; H[i][col] (+)= h_i; coef_i = h_i S[i].
+hipError_t launch_dot_finish(const double *part, int nblk, int nv, const double *S, double *H,
+                             int col, int accumulate, double *coef, hipStream_t s);
+// Finish a norm pass for column col: hn = sqrt(sum); H[col+1][col] = hn;
+// breakdown test against ||H||_F; S[col+1] = 1/hn (0 on breakdown, and
+// flags[0] = col+1 the first time); flags[1] = 1 if non-finite.
+hipError_t launch_norm_finish(const double *part, int nblk, double *H, double *S, int col,
+                              int *flags, hipStream_t s);
+// Norm of the start vector: res[0] = beta = sqrt(sum), S[0] = 1/beta,
+// flags[0] = 0.
+hipError_t launch_beta_finish(const double *part, int nblk, double *S, double *res, int *flags,
+                              hipStream_t s);
+// Norms of up to 4 vectors of length n (block partials, then finish):
+// out[k] = ||x_k||_2 (device doubles).
+template <typename T>
+hipError_t launch_norms(const T *const *x, int nx, size_t n, double *part, double *out,
+                        hipStream_t s);
+// Small exponential: F = expm(dtau * Hhat_j) (size j+1), err = beta |F[j][0]|,
+// combine coefficients ccoef[i] = beta F[i][0] S[i] (i < j), into slot.
+hipError_t launch_hess_expm(const double *H, int j, double dtau, const double *S,
+                            const double *res_beta, double *slot, hipStream_t s);
+// z = sum_{i<m} ccoef[i] * V_i (row-local; z may alias V_0).
+template <typename T>
+hipError_t launch_combine(const T *V, size_t stride, int m, const double *ccoef, T *z, size_t L,
+                          hipStream_t s);
+// Dense expm on the device for testing the small-exponential kernel: A and E
+// are n x n row-major device buffers (n <= kMaxM + 1).
+hipError_t launch_dense_expm(const double *A, int n, double *E, hipStream_t s);
+
+// Slot layout written by launch_hess_expm (doubles).
+constexpr int kSlotErr = 0;
+constexpr int kSlotCoef = 8;                 // kMaxM + 1 combine coefficients
+constexpr int kSlotSize = kSlotCoef + kMaxM + 8;
+
+}  // namespace expdg

@@ -1,0 +1,75 @@
+"""Host-side checks of the HIP library that need no GPU.
+
+  * libexpdg.so loads and exports every entry point include/expdg.h declares;
+  * the library's own LGL tables (a different construction from the
+    oracle's) agree with the oracle's to rounding;
+  * host-side validation: invalid mesh descriptions size to 0 bytes;
+  * workspace sizing grows with m_max as the Krylov block does.
+No compute call is made here.
+"""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2011_01316_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    text = open(os.path.join(ROOT, "include", "expdg.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(expdg_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = B.lib()
+    syms = header_symbols()
+    assert "expdg_step" in syms and "expdg_phi_krylov" in syms
+    for s in syms:
+        assert hasattr(L, s), s
+    assert set(syms) == set(B.exported_symbols())
+    assert L.expdg_version() >= 100
+
+
+@pytest.mark.parametrize("p", range(1, 7))
+def test_library_lgl_matches_oracle(p):
+    xi, w, D = B.expdg_lgl(p)
+    oxi, ow, oD = oracle.lgl(p)
+    np.testing.assert_allclose(xi, oxi, atol=2e-16 * 4)
+    np.testing.assert_allclose(w, ow, rtol=4e-15)
+    np.testing.assert_allclose(D, oD, atol=1e-13 * p * p)
+
+
+def test_lgl_rejects_bad_degree():
+    xi = np.zeros(20)
+    rc = B.lib().expdg_lgl(0, xi.ctypes.data, xi.ctypes.data, xi.ctypes.data)
+    assert rc == B.EINVAL
+    rc = B.lib().expdg_lgl(7, xi.ctypes.data, xi.ctypes.data, xi.ctypes.data)
+    assert rc == B.EINVAL
+    assert b"p must be" in B.lib().expdg_last_error()
+
+
+def desc(**kw):
+    d = dict(equation=B.EULER2D, nx=64, ny=64, p=4, precision=B.FP64, device=0, x0=0.0,
+             x1=10.0, y0=0.0, y1=10.0, gamma=1.4, m_max=64)
+    d.update(kw)
+    return B.MeshDesc(*[d[f] for f, _ in B.MeshDesc._fields_])
+
+
+def test_workspace_bytes_and_validation():
+    ok = B.expdg_workspace_bytes(desc())
+    ndof = 4 * 64 * 64 * 25
+    assert ok > 65 * ndof * 8  # the Krylov block alone
+    assert B.expdg_workspace_bytes(desc(m_max=32)) < ok
+    assert B.expdg_workspace_bytes(desc(precision=B.FP32_BULK)) < ok
+    for bad in [dict(p=0), dict(p=7), dict(nx=0), dict(m_max=0), dict(m_max=65),
+                dict(equation=3), dict(precision=2), dict(x1=-1.0), dict(gamma=1.0),
+                dict(equation=B.BURGERS1D, ny=2)]:
+        assert B.expdg_workspace_bytes(desc(**bad)) == 0, bad
+    h = C.c_void_p()
+    assert B.lib().expdg_mesh_create(C.byref(desc(p=9)), C.byref(h)) == B.EINVAL
