@@ -188,6 +188,35 @@ int expdg_step(expdg_mesh *m, int scheme, double dt, double *q, double *q_prev, 
  * is NaN if the Pade denominator is singular. */
 int expdg_small_expm(int n, const double *A, double *E, void *hip_stream);
 
+/* ---- live kernel timing ------------------------------------------------ */
+
+/* Kernel classes that can be timed with HIP events recorded around each
+ * launch on the launching stream. */
+enum {
+    EXPDG_K_RESIDUAL = 0,  /* DG residual R(q) */
+    EXPDG_K_LINEAR = 1,    /* DG linear operator L(q~) v (+ augmented block) */
+    EXPDG_K_GRAMSCHMIDT = 2, /* Gram-Schmidt dot / update / norm passes */
+    EXPDG_K_SMALLEXPM = 3, /* exponential of the projected Hessenberg matrix */
+    EXPDG_K_COMBINE = 4,   /* Krylov combine z = beta V F e_1 */
+    EXPDG_K_NCLASSES = 5
+};
+
+/* Accumulated timing of one kernel class: launches, summed event-measured
+ * duration, and summed algorithmic bytes (each input vector element read
+ * once, each output element written once). */
+typedef struct {
+    long long launches;
+    double total_ms;
+    double bytes;
+} expdg_kernel_profile;
+
+/* Enable (enable != 0) or disable timing of kernel_class on mesh m; either
+ * call resets its counters.  Timing adds two event records per launch of that
+ * class only. */
+int expdg_profile_enable(expdg_mesh *m, int kernel_class, int enable);
+/* Read the counters of kernel_class (waits for the recorded events). */
+int expdg_profile_read(expdg_mesh *m, int kernel_class, expdg_kernel_profile *out);
+
 /* Thread-local description of the last error (never NULL). */
 const char *expdg_last_error(void);
 /* ABI version: major * 10000 + minor * 100 + patch. */

@@ -56,6 +56,14 @@ class KrylovStats(C.Structure):
                 ("log", C.POINTER(Substep)), ("log_cap", C.c_int), ("log_len", C.c_int)]
 
 
+class KernelProfile(C.Structure):
+    _fields_ = [("launches", C.c_longlong), ("total_ms", C.c_double), ("bytes", C.c_double)]
+
+
+K_RESIDUAL, K_LINEAR, K_GRAMSCHMIDT, K_SMALLEXPM, K_COMBINE = 0, 1, 2, 3, 4
+KERNEL_CLASSES = {K_RESIDUAL: "residual", K_LINEAR: "linear_operator",
+                  K_GRAMSCHMIDT: "gram_schmidt", K_SMALLEXPM: "small_expm", K_COMBINE: "combine"}
+
 # name -> (restype, argtypes)
 _SIGS = {
     "expdg_mesh_create": (C.c_int, [C.POINTER(MeshDesc), C.POINTER(C.c_void_p)]),
@@ -73,6 +81,8 @@ _SIGS = {
     "expdg_step": (C.c_int, [C.c_void_p, C.c_int, C.c_double, C.c_void_p, C.c_void_p, C.c_int,
                              C.POINTER(KrylovOpts), C.POINTER(KrylovStats), C.c_void_p]),
     "expdg_small_expm": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "expdg_profile_enable": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
+    "expdg_profile_read": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(KernelProfile)]),
     "expdg_last_error": (C.c_char_p, []),
     "expdg_version": (C.c_int, []),
 }
@@ -192,6 +202,16 @@ def expdg_step(handle, scheme, dt, q, q_prev, have_prev, opts, stats=None, strea
 
 def expdg_small_expm(n, A, E, stream=None):
     _check(lib().expdg_small_expm(n, _ptr(A), _ptr(E), _stream(stream)))
+
+
+def expdg_profile_enable(handle, kernel_class, enable=True):
+    _check(lib().expdg_profile_enable(handle, kernel_class, int(enable)))
+
+
+def expdg_profile_read(handle, kernel_class):
+    out = KernelProfile()
+    _check(lib().expdg_profile_read(handle, kernel_class, C.byref(out)))
+    return {"launches": out.launches, "total_ms": out.total_ms, "bytes": out.bytes}
 
 
 def expdg_lgl(p):

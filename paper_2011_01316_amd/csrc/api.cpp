@@ -172,6 +172,16 @@ struct expdg_mesh {
     hipEvent_t ev[2] = {nullptr, nullptr};
     size_t bytes = 0;
     std::vector<void *> allocs;
+
+    // live timing of one or more kernel classes
+    struct Prof {
+        bool on = false;
+        std::vector<hipEvent_t> ev;  // start/stop pairs
+        std::vector<double> bytes;   // algorithmic bytes per recorded launch
+        int used = 0;
+        long long launches = 0;
+        double ms = 0.0, total_bytes = 0.0;
+    } prof[EXPDG_K_NCLASSES];
 };
 
 namespace {
@@ -247,6 +257,42 @@ void release(expdg_mesh *m) {
     if (m->pin) (void)hipHostFree(m->pin);
     for (auto &e : m->ev)
         if (e) (void)hipEventDestroy(e);
+    for (auto &P : m->prof)
+        for (auto &e : P.ev) (void)hipEventDestroy(e);
+}
+
+constexpr int kProfPairs = 1024;
+
+// Fold the recorded launches of class c into its counters.
+int prof_flush(expdg_mesh *m, int c) {
+    auto &P = m->prof[c];
+    for (int k = 0; k < P.used; ++k) {
+        HIPTRY(hipEventSynchronize(P.ev[2 * k + 1]));
+        float ms = 0.0f;
+        HIPTRY(hipEventElapsedTime(&ms, P.ev[2 * k], P.ev[2 * k + 1]));
+        P.ms += ms;
+        P.launches += 1;
+        P.total_bytes += P.bytes[k];
+    }
+    P.used = 0;
+    return EXPDG_OK;
+}
+
+int prof_begin(expdg_mesh *m, int c, hipStream_t s) {
+    auto &P = m->prof[c];
+    if (!P.on) return EXPDG_OK;
+    if (P.used == kProfPairs) TRY(prof_flush(m, c));
+    HIPTRY(hipEventRecord(P.ev[2 * P.used], s));
+    return EXPDG_OK;
+}
+
+int prof_end(expdg_mesh *m, int c, hipStream_t s, double bytes) {
+    auto &P = m->prof[c];
+    if (!P.on) return EXPDG_OK;
+    HIPTRY(hipEventRecord(P.ev[2 * P.used + 1], s));
+    P.bytes[P.used] = bytes;
+    P.used += 1;
+    return EXPDG_OK;
 }
 
 template <typename T>
@@ -398,7 +444,10 @@ int apply_op(expdg_mesh *m, bool jvp, const T *q, const T *v, T *out, hipStream_
     a.q = q;
     a.v = v;
     a.out = out;
+    const int cls = jvp ? EXPDG_K_LINEAR : EXPDG_K_RESIDUAL;
+    TRY(prof_begin(m, cls, s));
     HIPTRY(launch_dg_op(m->d.equation, m->d.p, jvp, a, s));
+    TRY(prof_end(m, cls, s, (double)(jvp ? 3 : 2) * m->n * m->ebytes));
     return EXPDG_OK;
 }
 
@@ -530,7 +579,12 @@ int phi_impl(expdg_mesh *m, const T *qref, double tau, int p, const T *const *b,
     a.q = qref;
     a.eta = eta;
     a.naug = p;
-    for (int k = 1; k <= p; ++k) a.aug[k - 1] = bx[p + 1 - k];
+    int naug_nz = 0;
+    for (int k = 1; k <= p; ++k) {
+        a.aug[k - 1] = bx[p + 1 - k];
+        naug_nz += bx[p + 1 - k] ? 1 : 0;
+    }
+    const double eb = (double)sizeof(T);
 
     int nchecks = 0;
     // enqueue the small exponential for dimension j and substep dtau
@@ -538,7 +592,9 @@ int phi_impl(expdg_mesh *m, const T *qref, double tau, int p, const T *const *b,
         c->j = j;
         c->slot = (nchecks++) & 1;
         double *slot = m->slots + c->slot * kSlotSize;
+        TRY(prof_begin(m, EXPDG_K_SMALLEXPM, s));
         HIPTRY(launch_hess_expm(kd.H, j, dtau, kd.S, kd.res, slot, s));
+        TRY(prof_end(m, EXPDG_K_SMALLEXPM, s, 0.0));
         HIPTRY(hipMemcpyAsync(m->pin + kPinSlots + c->slot * 8, slot, 4 * 8,
                               hipMemcpyDeviceToHost, s));
         HIPTRY(hipMemcpyAsync((char *)(m->pin + kPinSlots + c->slot * 8 + 4), kd.flags, 2 * 4,
@@ -575,7 +631,9 @@ int phi_impl(expdg_mesh *m, const T *qref, double tau, int p, const T *const *b,
             sub_last = o->forced[*fpos].last != 0;
         }
         // beta = ||z||, S[0] = 1/beta
+        TRY(prof_begin(m, EXPDG_K_GRAMSCHMIDT, s));
         HIPTRY(launch_cgs_pass<T>(V, stride, 0, nullptr, V, L, kd.part, 1, s));
+        TRY(prof_end(m, EXPDG_K_GRAMSCHMIDT, s, (double)L * eb));
         HIPTRY(launch_beta_finish(kd.part, nblkL, kd.S, kd.res, kd.flags, s));
         HIPTRY(launch_fill<double>(kd.H, 0.0, (size_t)(kMaxM + 1) * kMaxM, s));
 
@@ -593,13 +651,21 @@ int phi_impl(expdg_mesh *m, const T *qref, double tau, int p, const T *const *b,
             a.vtail = vin + n;
             a.otail = w + n;
             a.vscale = kd.S + (j - 1);
+            TRY(prof_begin(m, EXPDG_K_LINEAR, s));
             HIPTRY(launch_dg_op(m->d.equation, m->d.p, true, a, s));
+            TRY(prof_end(m, EXPDG_K_LINEAR, s, (double)(3 + naug_nz) * n * eb));
             // classical Gram-Schmidt, two passes, then the norm
+            TRY(prof_begin(m, EXPDG_K_GRAMSCHMIDT, s));
             HIPTRY(launch_cgs_pass<T>(V, stride, j, nullptr, w, L, kd.part, 0, s));
+            TRY(prof_end(m, EXPDG_K_GRAMSCHMIDT, s, (double)(j + 1) * L * eb));
             HIPTRY(launch_dot_finish(kd.part, nblkL, j, kd.S, kd.H, col, 0, kd.coef, s));
+            TRY(prof_begin(m, EXPDG_K_GRAMSCHMIDT, s));
             HIPTRY(launch_cgs_pass<T>(V, stride, j, kd.coef, w, L, kd.part, 0, s));
+            TRY(prof_end(m, EXPDG_K_GRAMSCHMIDT, s, (double)(j + 2) * L * eb));
             HIPTRY(launch_dot_finish(kd.part, nblkL, j, kd.S, kd.H, col, 1, kd.coef, s));
+            TRY(prof_begin(m, EXPDG_K_GRAMSCHMIDT, s));
             HIPTRY(launch_cgs_pass<T>(V, stride, j, kd.coef, w, L, kd.part, 1, s));
+            TRY(prof_end(m, EXPDG_K_GRAMSCHMIDT, s, (double)(j + 2) * L * eb));
             HIPTRY(launch_norm_finish(kd.part, nblkL, kd.H, kd.S, col, kd.flags, s));
             if (st) {
                 st->krylov_iters += 1;
@@ -694,8 +760,10 @@ int phi_impl(expdg_mesh *m, const T *qref, double tau, int p, const T *const *b,
         if (j_acc == 0) return fail(EXPDG_ENOCONV, "Krylov controller made no decision");
 
         // accept: z <- beta V_j F_{1:j,1}
+        TRY(prof_begin(m, EXPDG_K_COMBINE, s));
         HIPTRY(launch_combine<T>(V, stride, j_acc, m->slots + acc_check.slot * kSlotSize + kSlotCoef,
                                  V, L, s));
+        TRY(prof_end(m, EXPDG_K_COMBINE, s, (double)(j_acc + 1) * L * eb));
         t_done += dt_sub;
         log_sub(st, j_acc, sub_last ? 1 : 0, dt_sub);
         if (st) st->err_est = err;
@@ -848,6 +916,33 @@ extern "C" int expdg_step(expdg_mesh *m, int scheme, double dt, double *q, doubl
 extern "C" int expdg_small_expm(int n, const double *A, double *E, void *stream) {
     if (!A || !E || n < 1 || n > kMaxM + 1) return fail(EXPDG_EINVAL, "need 1 <= n <= 65");
     HIPTRY(launch_dense_expm(A, n, E, (hipStream_t)stream));
+    return EXPDG_OK;
+}
+
+extern "C" int expdg_profile_enable(expdg_mesh *m, int c, int enable) {
+    if (!m || c < 0 || c >= EXPDG_K_NCLASSES) return fail(EXPDG_EINVAL, "bad kernel class");
+    DeviceGuard g(m->d.device);
+    auto &P = m->prof[c];
+    if (P.used) TRY(prof_flush(m, c));
+    if (enable && P.ev.empty()) {
+        P.ev.resize(2 * kProfPairs, nullptr);
+        P.bytes.resize(kProfPairs, 0.0);
+        for (auto &e : P.ev) HIPTRY(hipEventCreate(&e));
+    }
+    P.on = enable != 0;
+    P.launches = 0;
+    P.ms = 0.0;
+    P.total_bytes = 0.0;
+    return EXPDG_OK;
+}
+
+extern "C" int expdg_profile_read(expdg_mesh *m, int c, expdg_kernel_profile *out) {
+    if (!m || !out || c < 0 || c >= EXPDG_K_NCLASSES) return fail(EXPDG_EINVAL, "bad argument");
+    DeviceGuard g(m->d.device);
+    TRY(prof_flush(m, c));
+    out->launches = m->prof[c].launches;
+    out->total_ms = m->prof[c].ms;
+    out->bytes = m->prof[c].total_bytes;
     return EXPDG_OK;
 }
 
