@@ -193,12 +193,15 @@ int expdg_small_expm(int n, const double *A, double *E, void *hip_stream);
 /* Kernel classes that can be timed with HIP events recorded around each
  * launch on the launching stream. */
 enum {
-    EXPDG_K_RESIDUAL = 0,  /* DG residual R(q) */
-    EXPDG_K_LINEAR = 1,    /* DG linear operator L(q~) v (+ augmented block) */
-    EXPDG_K_GRAMSCHMIDT = 2, /* Gram-Schmidt dot / update / norm passes */
-    EXPDG_K_SMALLEXPM = 3, /* exponential of the projected Hessenberg matrix */
-    EXPDG_K_COMBINE = 4,   /* Krylov combine z = beta V F e_1 */
-    EXPDG_K_NCLASSES = 5
+    EXPDG_K_RESIDUAL = 0,       /* DG residual R(q) */
+    EXPDG_K_LINEAR = 1,         /* DG linear operator L(q~) v (+ augmented block) */
+    EXPDG_K_GS_DOTS = 2,        /* Gram-Schmidt first pass: block partials of V^T w */
+    EXPDG_K_SMALLEXPM = 3,      /* exponential of the projected Hessenberg matrix */
+    EXPDG_K_COMBINE = 4,        /* Krylov combine z = beta V F e_1 */
+    EXPDG_K_GS_UPDATE_DOTS = 5, /* second pass: w -= V h, partials of V^T w */
+    EXPDG_K_GS_UPDATE_NORM = 6, /* w -= V h, partials of ||w||^2 */
+    EXPDG_K_GS_FINISH = 7,      /* fixed-order sums of the block partials */
+    EXPDG_K_NCLASSES = 8
 };
 
 /* Accumulated timing of one kernel class: launches, summed event-measured

@@ -60,9 +60,18 @@ class KernelProfile(C.Structure):
     _fields_ = [("launches", C.c_longlong), ("total_ms", C.c_double), ("bytes", C.c_double)]
 
 
-K_RESIDUAL, K_LINEAR, K_GRAMSCHMIDT, K_SMALLEXPM, K_COMBINE = 0, 1, 2, 3, 4
-KERNEL_CLASSES = {K_RESIDUAL: "residual", K_LINEAR: "linear_operator",
-                  K_GRAMSCHMIDT: "gram_schmidt", K_SMALLEXPM: "small_expm", K_COMBINE: "combine"}
+K_RESIDUAL, K_LINEAR, K_GS_DOTS, K_SMALLEXPM, K_COMBINE = 0, 1, 2, 3, 4
+K_GS_UPDATE_DOTS, K_GS_UPDATE_NORM, K_GS_FINISH = 5, 6, 7
+KERNEL_CLASSES = {K_RESIDUAL: "residual", K_LINEAR: "linear_operator", K_GS_DOTS: "gs_dots",
+                  K_SMALLEXPM: "small_expm", K_COMBINE: "combine",
+                  K_GS_UPDATE_DOTS: "gs_update_dots", K_GS_UPDATE_NORM: "gs_update_norm",
+                  K_GS_FINISH: "gs_finish"}
+# kernel symbol of each class, as rocprofv3 names it
+KERNEL_SYMBOLS = {"residual": "euler_op<4, double, false>", "linear_operator": "euler_op<4, double, true>",
+                  "gs_dots": "gs_dots_kernel<double>", "small_expm": "hess_expm_kernel",
+                  "combine": "combine_kernel<double>", "gs_update_dots": "gs_update_dots_kernel<double>",
+                  "gs_update_norm": "gs_update_norm_kernel<double>",
+                  "gs_finish": "finish_dots_kernel / finish_norm_kernel"}
 
 # name -> (restype, argtypes)
 _SIGS = {

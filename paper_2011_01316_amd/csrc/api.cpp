@@ -158,7 +158,6 @@ struct expdg_mesh {
     int ebytes;     // bytes per bulk element
     double hx, hy, dxmin;
     double xi[kMaxP + 1], w[kMaxP + 1], D[(kMaxP + 1) * (kMaxP + 1)];
-    int nblk_vec;   // reduction blocks for vectors of length ~n
 
     void *V = nullptr;           // (m_max+1) x stride bulk
     void *vec[6] = {};           // bulk work vectors (stride each)
@@ -169,7 +168,9 @@ struct expdg_mesh {
     double *dnorm = nullptr;     // 8
     double *spart = nullptr;     // 1024 (wave-speed partials)
     double *pin = nullptr;       // pinned host mirror
-    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr};   // check results ready (side stream)
+    hipEvent_t evH[2] = {nullptr, nullptr};  // Hessenberg column ready (main stream)
+    hipStream_t side = nullptr;              // small exponentials run here
     size_t bytes = 0;
     std::vector<void *> allocs;
 
@@ -231,7 +232,7 @@ Sizes sizes_of(const expdg_mesh_desc *d) {
     t += 6 * s.stride * s.ebytes;                                          // work vectors
     if (d->precision == EXPDG_FP32_BULK) t += 3 * s.stride * s.ebytes;     // bulk state copies
     t += s.stride * 8;                                                     // q2
-    t += (size_t)(kMaxM + 1) * kMaxM * 8 + 3 * (kMaxM + 1) * 8;            // H, S, coef
+    t += (size_t)(kMaxM + 1) * kMaxM * 8 + 3 * (kMaxM + 1) * 8 + 64;       // H, S, coefs
     t += (size_t)kRedBlocks * (kMaxM + 1) * 8 + 64 * 8 + 16;               // part, res, flags
     t += 2 * kSlotSize * 8 + 8 * 8 + 1024 * 8;                             // slots, norms, speed
     s.total = t;
@@ -257,6 +258,9 @@ void release(expdg_mesh *m) {
     if (m->pin) (void)hipHostFree(m->pin);
     for (auto &e : m->ev)
         if (e) (void)hipEventDestroy(e);
+    for (auto &e : m->evH)
+        if (e) (void)hipEventDestroy(e);
+    if (m->side) (void)hipStreamDestroy(m->side);
     for (auto &P : m->prof)
         for (auto &e : P.ev) (void)hipEventDestroy(e);
 }
@@ -347,7 +351,6 @@ extern "C" int expdg_mesh_create(const expdg_mesh_desc *d, expdg_mesh **out) {
     double dmin = 2.0;
     for (int i = 0; i < d->p; ++i) dmin = std::min(dmin, m->xi[i + 1] - m->xi[i]);
     m->dxmin = 0.5 * ((m->dim == 2) ? std::min(m->hx, m->hy) : m->hx) * dmin;
-    m->nblk_vec = red_blocks(m->n + kMaxAug);
 
     int rc = EXPDG_OK;
     const size_t vb = m->stride * m->ebytes;
@@ -361,7 +364,8 @@ extern "C" int expdg_mesh_create(const expdg_mesh_desc *d, expdg_mesh **out) {
     chk(dalloc(m, &m->q2, m->stride * 8));
     chk(dalloc(m, &m->kd.H, (size_t)(kMaxM + 1) * kMaxM * 8));
     chk(dalloc(m, &m->kd.S, (size_t)(kMaxM + 1) * 8));
-    chk(dalloc(m, &m->kd.coef, (size_t)(kMaxM + 1) * 8));
+    chk(dalloc(m, &m->kd.coefA, (size_t)(kMaxM + 1) * 8));
+    chk(dalloc(m, &m->kd.coefB, (size_t)(kMaxM + 1) * 8));
     chk(dalloc(m, &m->kd.part, (size_t)kRedBlocks * (kMaxM + 1) * 8));
     chk(dalloc(m, &m->kd.res, 64 * 8));
     chk(dalloc(m, &m->kd.flags, 16));
@@ -375,6 +379,12 @@ extern "C" int expdg_mesh_create(const expdg_mesh_desc *d, expdg_mesh **out) {
     for (auto &e : m->ev)
         if (rc == EXPDG_OK && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
             rc = fail(EXPDG_EDEVICE, "hipEventCreate failed");
+    for (auto &e : m->evH)
+        if (rc == EXPDG_OK && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+            rc = fail(EXPDG_EDEVICE, "hipEventCreate failed");
+    // default-priority side stream for the small exponentials
+    if (rc == EXPDG_OK && hipStreamCreateWithFlags(&m->side, hipStreamNonBlocking) != hipSuccess)
+        rc = fail(EXPDG_EDEVICE, "hipStreamCreate failed");
     if (rc == EXPDG_OK) {
         // zero the whole Krylov block once (padding stays zero)
         if (hipMemset(m->V, 0, (size_t)(d->m_max + 1) * vb) != hipSuccess ||
@@ -536,7 +546,7 @@ int phi_impl(expdg_mesh *m, const T *qref, double tau, int p, const T *const *b,
     T *V = (T *)m->V;
     KrylovDev &kd = m->kd;
     const bool forced = o->n_forced > 0;
-    const int nblkL = red_blocks(L);
+    const RowPartition rp = row_partition(L);
     if (st) st->phi_calls += 1;
 
     // 1. scaling and 2. tolerance: norms of b_0..b_p
@@ -588,18 +598,24 @@ int phi_impl(expdg_mesh *m, const T *qref, double tau, int p, const T *const *b,
 
     int nchecks = 0;
     // enqueue the small exponential for dimension j and substep dtau
+    // The small exponential of check j runs on the side stream once the
+    // Hessenberg column j-1 is complete on the main stream, overlapping the
+    // next Arnoldi iteration; its result is read back one iteration later.
+    hipStream_t side = m->side;
     auto enqueue_check = [&](int j, double dtau, Check *c) -> int {
         c->j = j;
         c->slot = (nchecks++) & 1;
         double *slot = m->slots + c->slot * kSlotSize;
-        TRY(prof_begin(m, EXPDG_K_SMALLEXPM, s));
-        HIPTRY(launch_hess_expm(kd.H, j, dtau, kd.S, kd.res, slot, s));
-        TRY(prof_end(m, EXPDG_K_SMALLEXPM, s, 0.0));
+        HIPTRY(hipEventRecord(m->evH[c->slot], s));
+        HIPTRY(hipStreamWaitEvent(side, m->evH[c->slot], 0));
+        TRY(prof_begin(m, EXPDG_K_SMALLEXPM, side));
+        HIPTRY(launch_hess_expm(kd.H, j, dtau, kd.S, kd.res, slot, side));
+        TRY(prof_end(m, EXPDG_K_SMALLEXPM, side, 0.0));
         HIPTRY(hipMemcpyAsync(m->pin + kPinSlots + c->slot * 8, slot, 4 * 8,
-                              hipMemcpyDeviceToHost, s));
+                              hipMemcpyDeviceToHost, side));
         HIPTRY(hipMemcpyAsync((char *)(m->pin + kPinSlots + c->slot * 8 + 4), kd.flags, 2 * 4,
-                              hipMemcpyDeviceToHost, s));
-        HIPTRY(hipEventRecord(m->ev[c->slot], s));
+                              hipMemcpyDeviceToHost, side));
+        HIPTRY(hipEventRecord(m->ev[c->slot], side));
         return EXPDG_OK;
     };
     struct CheckResult {
@@ -631,10 +647,13 @@ int phi_impl(expdg_mesh *m, const T *qref, double tau, int p, const T *const *b,
             sub_last = o->forced[*fpos].last != 0;
         }
         // beta = ||z||, S[0] = 1/beta
-        TRY(prof_begin(m, EXPDG_K_GRAMSCHMIDT, s));
-        HIPTRY(launch_cgs_pass<T>(V, stride, 0, nullptr, V, L, kd.part, 1, s));
-        TRY(prof_end(m, EXPDG_K_GRAMSCHMIDT, s, (double)L * eb));
-        HIPTRY(launch_beta_finish(kd.part, nblkL, kd.S, kd.res, kd.flags, s));
+        TRY(prof_begin(m, EXPDG_K_GS_UPDATE_NORM, s));
+        HIPTRY(launch_gs_update_norm<T>(V, stride, 0, nullptr, V, L, rp, kd.part, kd.H, kd.S, -1,
+                                        kd.flags, kd.res, s));
+        TRY(prof_end(m, EXPDG_K_GS_UPDATE_NORM, s, (double)L * eb));
+        TRY(prof_begin(m, EXPDG_K_GS_FINISH, s));
+        HIPTRY(launch_gs_finish_norm(kd.part, rp, kd.H, kd.S, -1, kd.flags, kd.res, s));
+        TRY(prof_end(m, EXPDG_K_GS_FINISH, s, 8.0 * rp.nrb));
         HIPTRY(launch_fill<double>(kd.H, 0.0, (size_t)(kMaxM + 1) * kMaxM, s));
 
         int j_acc = 0;
@@ -655,18 +674,30 @@ int phi_impl(expdg_mesh *m, const T *qref, double tau, int p, const T *const *b,
             HIPTRY(launch_dg_op(m->d.equation, m->d.p, true, a, s));
             TRY(prof_end(m, EXPDG_K_LINEAR, s, (double)(3 + naug_nz) * n * eb));
             // classical Gram-Schmidt, two passes, then the norm
-            TRY(prof_begin(m, EXPDG_K_GRAMSCHMIDT, s));
-            HIPTRY(launch_cgs_pass<T>(V, stride, j, nullptr, w, L, kd.part, 0, s));
-            TRY(prof_end(m, EXPDG_K_GRAMSCHMIDT, s, (double)(j + 1) * L * eb));
-            HIPTRY(launch_dot_finish(kd.part, nblkL, j, kd.S, kd.H, col, 0, kd.coef, s));
-            TRY(prof_begin(m, EXPDG_K_GRAMSCHMIDT, s));
-            HIPTRY(launch_cgs_pass<T>(V, stride, j, kd.coef, w, L, kd.part, 0, s));
-            TRY(prof_end(m, EXPDG_K_GRAMSCHMIDT, s, (double)(j + 2) * L * eb));
-            HIPTRY(launch_dot_finish(kd.part, nblkL, j, kd.S, kd.H, col, 1, kd.coef, s));
-            TRY(prof_begin(m, EXPDG_K_GRAMSCHMIDT, s));
-            HIPTRY(launch_cgs_pass<T>(V, stride, j, kd.coef, w, L, kd.part, 1, s));
-            TRY(prof_end(m, EXPDG_K_GRAMSCHMIDT, s, (double)(j + 2) * L * eb));
-            HIPTRY(launch_norm_finish(kd.part, nblkL, kd.H, kd.S, col, kd.flags, s));
+            const double fin_bytes = 8.0 * rp.nrb * j;
+            TRY(prof_begin(m, EXPDG_K_GS_DOTS, s));
+            HIPTRY(launch_gs_dots<T>(V, stride, j, w, L, rp, kd.part, kd.S, kd.H, col, 0, kd.coefA,
+                                     s));
+            TRY(prof_end(m, EXPDG_K_GS_DOTS, s, (double)(j + 1) * L * eb));
+            TRY(prof_begin(m, EXPDG_K_GS_FINISH, s));
+            HIPTRY(launch_gs_finish_dots(kd.part, j, rp, kd.S, kd.H, col, 0, kd.coefA, s));
+            TRY(prof_end(m, EXPDG_K_GS_FINISH, s, fin_bytes));
+            // (j > 32: a plain update then a dot pass, 2j + 3 vectors of traffic)
+            TRY(prof_begin(m, EXPDG_K_GS_UPDATE_DOTS, s));
+            HIPTRY(launch_gs_update_dots<T>(V, stride, j, kd.coefA, w, L, rp, kd.part, kd.S, kd.H,
+                                            col, kd.coefB, s));
+            TRY(prof_end(m, EXPDG_K_GS_UPDATE_DOTS, s,
+                         (double)(j <= 32 ? j + 2 : 2 * j + 3) * L * eb));
+            TRY(prof_begin(m, EXPDG_K_GS_FINISH, s));
+            HIPTRY(launch_gs_finish_dots(kd.part, j, rp, kd.S, kd.H, col, 1, kd.coefB, s));
+            TRY(prof_end(m, EXPDG_K_GS_FINISH, s, fin_bytes));
+            TRY(prof_begin(m, EXPDG_K_GS_UPDATE_NORM, s));
+            HIPTRY(launch_gs_update_norm<T>(V, stride, j, kd.coefB, w, L, rp, kd.part, kd.H, kd.S,
+                                            col, kd.flags, kd.res, s));
+            TRY(prof_end(m, EXPDG_K_GS_UPDATE_NORM, s, (double)(j + 2) * L * eb));
+            TRY(prof_begin(m, EXPDG_K_GS_FINISH, s));
+            HIPTRY(launch_gs_finish_norm(kd.part, rp, kd.H, kd.S, col, kd.flags, kd.res, s));
+            TRY(prof_end(m, EXPDG_K_GS_FINISH, s, 8.0 * rp.nrb));
             if (st) {
                 st->krylov_iters += 1;
                 st->jvps += 1;
@@ -759,7 +790,8 @@ int phi_impl(expdg_mesh *m, const T *qref, double tau, int p, const T *const *b,
         }
         if (j_acc == 0) return fail(EXPDG_ENOCONV, "Krylov controller made no decision");
 
-        // accept: z <- beta V_j F_{1:j,1}
+        // accept: z <- beta V_j F_{1:j,1} (after the check's side-stream work)
+        HIPTRY(hipStreamWaitEvent(s, m->ev[acc_check.slot], 0));
         TRY(prof_begin(m, EXPDG_K_COMBINE, s));
         HIPTRY(launch_combine<T>(V, stride, j_acc, m->slots + acc_check.slot * kSlotSize + kSlotCoef,
                                  V, L, s));
@@ -786,6 +818,7 @@ int phi_impl(expdg_mesh *m, const T *qref, double tau, int p, const T *const *b,
         }
     }
     HIPTRY(launch_copy(V, out, n, s));
+    HIPTRY(hipStreamSynchronize(side));  // no speculative check left running
     if (forced) {
         // a forced run reads nothing back: surface non-finite values here
         HIPTRY(hipMemcpyAsync(m->pin + kPinSlots, kd.flags, 8, hipMemcpyDeviceToHost, s));

@@ -75,33 +75,49 @@ hipError_t launch_set_tail(T *x, int p, double last, hipStream_t s);
 struct KrylovDev {
     double *H;       // (kMaxM+1) x kMaxM Hessenberg, row-major, ld = kMaxM
     double *S;       // kMaxM+1 basis scales (v_i = S[i] * u_i)
-    double *coef;    // kMaxM+1 update coefficients
-    double *part;    // kRedBlocks x (kMaxM+1) partial sums
-    double *res;     // result slots (see krylov_kernels.hip)
-    int *flags;      // device flags: [0] breakdown iteration (0 = none)
+    double *coefA;   // kMaxM+1 first-pass Gram-Schmidt coefficients h1_i S[i]
+    double *coefB;   // kMaxM+1 second-pass coefficients h2_i S[i]
+    double *part;    // kRedBlocks x (kMaxM+1) block partial sums
+    double *res;     // res[0] = beta
+    int *flags;      // [0] first breakdown iteration (0 = none), [1] non-finite
 };
 
-// Block partials of V_i^T w (i < nv) after w -= sum coef_i V_i (if coef).
-// mode 0: dots with V_0..V_{nv-1}; mode 1: squared norm of w (nv vectors
-// still subtracted when coef != nullptr).
+// Fixed row partition of a length-L vector: nrb blocks of rpb rows (rpb a
+// multiple of 256, nrb <= kRedBlocks).
+struct RowPartition {
+    size_t rpb;
+    int nrb;
+};
+RowPartition row_partition(size_t L);
+
+// Block partials of V_i^T w (i < nv) into part (the finish is a separate
+// launch: launch_gs_finish_dots).
 template <typename T>
-hipError_t launch_cgs_pass(const T *V, size_t stride, int nv, const double *coef, T *w,
-                           size_t L, double *part, int mode, hipStream_t s);
-// Number of blocks (and partials per output) of the row-partitioned kernels
-// for vectors of length L.
-int red_blocks(size_t L);
-// Finish a dot pass: h_i = S[i] * sum_b part; H[i][col] (+)= h_i; coef_i = h_i S[i].
-hipError_t launch_dot_finish(const double *part, int nblk, int nv, const double *S, double *H,
-                             int col, int accumulate, double *coef, hipStream_t s);
-// Finish a norm pass for column col: hn = sqrt(sum); H[col+1][col] = hn;
-// breakdown test against ||H||_F; S[col+1] = 1/hn (0 on breakdown, and
-// flags[0] = col+1 the first time); flags[1] = 1 if non-finite.
-hipError_t launch_norm_finish(const double *part, int nblk, double *H, double *S, int col,
-                              int *flags, hipStream_t s);
-// Norm of the start vector: res[0] = beta = sqrt(sum), S[0] = 1/beta,
-// flags[0] = 0.
-hipError_t launch_beta_finish(const double *part, int nblk, double *S, double *res, int *flags,
-                              hipStream_t s);
+hipError_t launch_gs_dots(const T *V, size_t stride, int nv, const T *w, size_t L,
+                          const RowPartition &rp, double *part, const double *S, double *H,
+                          int col, int accumulate, double *coef_out, hipStream_t s);
+// w -= sum_i coef_in[i] V_i, then block partials of V_i^T w into part.
+template <typename T>
+hipError_t launch_gs_update_dots(const T *V, size_t stride, int nv, const double *coef_in, T *w,
+                                 size_t L, const RowPartition &rp, double *part, const double *S,
+                                 double *H, int col, double *coef_out, hipStream_t s);
+// w -= sum_i coef[i] V_i (if coef), then block partials of ||w||^2.
+template <typename T>
+hipError_t launch_gs_update_norm(const T *V, size_t stride, int nv, const double *coef, T *w,
+                                 size_t L, const RowPartition &rp, double *part, double *H,
+                                 double *S, int col, int *flags, double *res, hipStream_t s);
+// Fixed-order finish of a dot pass: h_i = S[i] sum_b part[i][b]; H[i][col] set
+// (accumulate = 0) or incremented; coef_out[i] = h_i S[i].
+hipError_t launch_gs_finish_dots(const double *part, int nv, const RowPartition &rp,
+                                 const double *S, double *H, int col, int accumulate,
+                                 double *coef_out, hipStream_t s);
+// Fixed-order finish of a norm pass: hn = sqrt(sum_b part[b]).  col >= 0:
+// H[col+1][col] = hn, breakdown test against ||H||_F (flags[0] = col+1 the
+// first time, S[col+1] = 0), else S[col+1] = 1/hn.  col < 0 (start vector):
+// res[0] = beta = hn, S[0] = 1/beta, flags[0] = 0.  flags[1] = 1 on a
+// non-finite norm.
+hipError_t launch_gs_finish_norm(const double *part, const RowPartition &rp, double *H, double *S,
+                                 int col, int *flags, double *res, hipStream_t s);
 // Norms of up to 4 vectors of length n (block partials, then finish):
 // out[k] = ||x_k||_2 (device doubles).
 template <typename T>

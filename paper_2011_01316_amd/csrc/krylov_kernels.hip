@@ -4,20 +4,41 @@
 // Basis storage: V holds unnormalised vectors u_i (bulk type, float or
 // double) with FP64 scales S[i] so that v_i = S[i] u_i; no separate
 // normalisation pass is needed.  Inner products and norms are accumulated in
-// FP64 with a fixed two-stage reduction (per-block partials over a fixed row
-// partition, then a fixed-order tree), so results do not depend on timing and
-// are identical run to run.
+// FP64 over a fixed row partition; the block partials are summed in a fixed
+// order by a small finishing kernel, so results are identical run to run.
+// (Two alternatives measured slower on MI355X: letting the last block of each
+// launch finish needs a device-scope release fence in every block, which
+// writes back the XCD's L2 each time; letting every block of the consuming
+// kernel re-derive the sums makes each block wait on partials that other XCDs
+// wrote.)
+// (Letting the last block of each launch finish instead needs a device-scope
+// release fence in every block, which writes back the XCD's L2 each time:
+// measured 3x slower on MI355X.)
 //
-// The small (j+1) x (j+1) exponential of the projected Hessenberg matrix
-// runs in one 256-thread workgroup with four FP64 matrices resident in LDS
-// (gfx950 gives a workgroup up to 160 KB): diagonal Pade (6,6) with scaling
-// and squaring and Gaussian elimination with partial pivoting.
+// Per Arnoldi step j (nv = j basis vectors, w = the new vector):
+//   gs_dots         h1 = V^T w                     (2D grid: row blocks x 16-vector chunks)
+//   gs_update_dots  w -= V h1 ; h2 = V^T w         (32 accumulators in registers, j <= 32)
+//   (gs_update + gs_dots for j > 32)
+//   gs_update_norm  w -= V h2 ; ||w|| partials
+//   finish_*        fixed-order sums of the block partials; H, coefficients,
+//                   ||w||, breakdown test, S[j] = 1/||w||
+// Block sums use a transpose reduction: 16 (or 32) accumulators of a wave are
+// summed with 17 (or 32) cross-lane exchanges instead of 6 per accumulator.
+//
+// The small (j+1) x (j+1) exponential of the projected Hessenberg matrix runs
+// in one 256-thread workgroup with four FP64 matrices in LDS (gfx950 gives a
+// workgroup up to 160 KB): diagonal Pade (6,6), scaling and squaring, and
+// Gaussian elimination with partial pivoting.  For a Hessenberg argument the
+// Pade denominator has lower bandwidth 6, so elimination only visits the six
+// rows below the pivot: the rows further down hold exact zeros, so the result
+// is the same as a full elimination.
 #include "internal.h"
 
 namespace expdg {
 namespace {
 
 constexpr int LDH = kMaxM;  // leading dimension of H
+constexpr int CH = 16;      // basis vectors per chunk of the dot kernel
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -25,133 +46,245 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Row partition shared by every row-partitioned kernel: block b owns rows
-// [b*rpb, min(L, (b+1)*rpb)); rpb is a multiple of 256.
-__host__ __device__ inline size_t rows_per_block(size_t L) {
-    size_t rpb = (L + kRedBlocks - 1) / kRedBlocks;
-    rpb = (rpb + 255) / 256 * 256;
-    return rpb;
-}
-
-// mode 0: part[i*nblk + b] = sum_r V_i[r] w'[r] (i < nv)
-// mode 1: part[b]          = sum_r w'[r]^2
-// where w' = w - sum_i coef[i] V_i (coef may be nullptr: w' = w); if coef is
-// given, w' is stored back.
-template <typename T, int NVMAX, int MODE>
-__global__ __launch_bounds__(256) void cgs_kernel(const T *__restrict__ V, size_t stride, int nv,
-                                                  const double *__restrict__ coef,
-                                                  T *__restrict__ w, size_t L, size_t rpb,
-                                                  double *__restrict__ part) {
-    __shared__ double scoef[NVMAX];
-    __shared__ double sred[NVMAX > 0 ? NVMAX : 1][4];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (coef && tid < nv) scoef[tid] = coef[tid];
-    __syncthreads();
-    const size_t r0 = (size_t)blockIdx.x * rpb;
-    const size_t r1 = (r0 + rpb < L) ? r0 + rpb : L;
-    double acc[MODE == 0 ? NVMAX : 1];
+// One halving step of the transpose reduction: lanes with bit m set keep the
+// upper half of a[0..2*HALF), the others the lower half; each adds the
+// partner's copy of the half it keeps.
+template <int HALF>
+__device__ __forceinline__ void tr_step(double *a, int lane, int m) {
+    const bool up = (lane & m) != 0;
 #pragma unroll
-    for (int i = 0; i < (MODE == 0 ? NVMAX : 1); ++i) acc[i] = 0.0;
-    for (size_t r = r0 + tid; r < r1; r += 256) {
-        double x = (double)w[r];
-        if (coef) {
-#pragma unroll
-            for (int i = 0; i < NVMAX; ++i)
-                if (i < nv) x -= scoef[i] * (double)V[(size_t)i * stride + r];
-            w[r] = (T)x;
-            x = (double)(T)x;
-        }
-        if (MODE == 0) {
-#pragma unroll
-            for (int i = 0; i < NVMAX; ++i)
-                if (i < nv) acc[i] += (double)V[(size_t)i * stride + r] * x;
-        } else {
-            acc[0] += x * x;
-        }
-    }
-    const int nout = (MODE == 0) ? nv : 1;
-#pragma unroll
-    for (int i = 0; i < (MODE == 0 ? NVMAX : 1); ++i) {
-        if (i < nout) {
-            const double s = wave_sum(acc[i]);
-            if (lane == 0) sred[i][wave] = s;
-        }
-    }
-    __syncthreads();
-    if (tid < nout) {
-        const double s = (sred[tid][0] + sred[tid][1]) + (sred[tid][2] + sred[tid][3]);
-        part[(size_t)tid * gridDim.x + blockIdx.x] = s;
+    for (int k = 0; k < HALF; ++k) {
+        const double keep = up ? a[HALF + k] : a[k];
+        const double send = up ? a[k] : a[HALF + k];
+        a[k] = keep + __shfl_xor(send, m, 64);
     }
 }
 
-// Fixed-order sum of nblk partials by one block; returns the total to all.
-__device__ double block_sum_partials(const double *p, int nblk) {
+// Wave sums of a[0..16): lane l returns the sum of a[l >> 2].
+__device__ __forceinline__ double transpose_reduce16(double *a) {
+    const int lane = threadIdx.x & 63;
+    tr_step<8>(a, lane, 32);
+    tr_step<4>(a, lane, 16);
+    tr_step<2>(a, lane, 8);
+    tr_step<1>(a, lane, 4);
+    double v = a[0];
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 1, 64);
+    return v;
+}
+
+// Wave sums of a[0..32): lane l returns the sum of a[l >> 1].
+__device__ __forceinline__ double transpose_reduce32(double *a) {
+    const int lane = threadIdx.x & 63;
+    tr_step<16>(a, lane, 32);
+    tr_step<8>(a, lane, 16);
+    tr_step<4>(a, lane, 8);
+    tr_step<2>(a, lane, 4);
+    tr_step<1>(a, lane, 2);
+    double v = a[0];
+    v += __shfl_xor(v, 1, 64);
+    return v;
+}
+
+// The previous pass whose coefficients a kernel applies.
+struct PrevPass {
+    const double *coef;  // nullptr: no previous pass (no update)
+};
+
+struct DotFinish {
+    const double *S;
+    double *H;
+    int col;
+    int accumulate;
+    double *coef_out;
+};
+
+// h_i = S[i] sum_b part[i][b]; H[i][col] (+)= h_i; coef_out[i] = h_i S[i].
+// One wave per output (four per block), partials summed in a fixed order.
+__global__ __launch_bounds__(256) void finish_dots_kernel(const double *part, int nv, int nrb,
+                                                          DotFinish f) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = blockIdx.x * 4 + wave;
+    if (i >= nv) return;
+    double a = 0.0;
+    for (int b = lane; b < nrb; b += 64) a += part[(size_t)i * nrb + b];
+    a = wave_sum(a);
+    if (lane == 0) {
+        const double h = f.S[i] * a;
+        double *hij = &f.H[(size_t)i * LDH + f.col];
+        *hij = f.accumulate ? *hij + h : h;
+        f.coef_out[i] = h * f.S[i];
+    }
+}
+
+struct NormFinish {
+    double *H;
+    double *S;
+    int col;        // column of the new subdiagonal entry; -1: start vector
+    int *flags;     // [0] first breakdown iteration, [1] non-finite
+    double *res;    // res[0] = beta (start vector)
+};
+
+__global__ __launch_bounds__(256) void finish_norm_kernel(const double *part, int nrb,
+                                                          NormFinish f) {
     __shared__ double sw[4];
     const int tid = threadIdx.x;
-    double acc = 0.0;
-    for (int b = tid; b < nblk; b += 256) acc += p[b];
-    acc = wave_sum(acc);
-    if ((tid & 63) == 0) sw[tid >> 6] = acc;
+    double a = 0.0;
+    for (int b = tid; b < nrb; b += 256) a += part[b];
+    a = wave_sum(a);
+    if ((tid & 63) == 0) sw[tid >> 6] = a;
     __syncthreads();
-    const double t = (sw[0] + sw[1]) + (sw[2] + sw[3]);
+    const double hn = sqrt((sw[0] + sw[1]) + (sw[2] + sw[3]));
     __syncthreads();
-    return t;
-}
-
-__global__ __launch_bounds__(256) void dot_finish_kernel(const double *part, int nblk,
-                                                         const double *S, double *H, int col,
-                                                         int accumulate, double *coef) {
-    const int i = blockIdx.x;
-    const double t = block_sum_partials(part + (size_t)i * nblk, nblk);
-    if (threadIdx.x == 0) {
-        const double h = S[i] * t;
-        double *hij = &H[(size_t)i * LDH + col];
-        *hij = accumulate ? *hij + h : h;
-        coef[i] = h * S[i];
+    if (f.col < 0) {
+        if (tid == 0) {
+            f.res[0] = hn;
+            f.S[0] = (hn > 0.0) ? 1.0 / hn : 0.0;
+            f.flags[0] = 0;
+            if (!isfinite(hn)) f.flags[1] = 1;
+        }
+        return;
     }
-}
-
-__global__ __launch_bounds__(256) void norm_finish_kernel(const double *part, int nblk, double *H,
-                                                          double *S, int col, int *flags) {
-    __shared__ double sw[4];
-    const double t = block_sum_partials(part, nblk);
-    const double hn = sqrt(t);
     // ||H_{0:col+2, 0:col+1}||_F including the new subdiagonal entry
+    const int col = f.col, rows = col + 2, cols = col + 1;
     double acc = 0.0;
-    const int rows = col + 2, cols = col + 1;
-    for (int e = threadIdx.x; e < rows * cols; e += 256) {
+    for (int e = tid; e < rows * cols; e += 256) {
         const int r = e / cols, c = e % cols;
-        const double h = (r == col + 1) ? ((c == col) ? hn : 0.0) : H[(size_t)r * LDH + c];
+        const double h = (r == col + 1) ? ((c == col) ? hn : 0.0) : f.H[(size_t)r * LDH + c];
         acc += h * h;
     }
     acc = wave_sum(acc);
-    if ((threadIdx.x & 63) == 0) sw[threadIdx.x >> 6] = acc;
+    if ((tid & 63) == 0) sw[tid >> 6] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         const double hf = sqrt((sw[0] + sw[1]) + (sw[2] + sw[3]));
-        if (!isfinite(hn) || !isfinite(hf)) flags[1] = 1;
+        if (!isfinite(hn) || !isfinite(hf)) f.flags[1] = 1;
         const bool brk = hn <= 1e-12 * hf;
         if (brk) {
-            H[(size_t)(col + 1) * LDH + col] = 0.0;
-            S[col + 1] = 0.0;
-            if (flags[0] == 0) flags[0] = col + 1;
+            f.H[(size_t)(col + 1) * LDH + col] = 0.0;
+            f.S[col + 1] = 0.0;
+            if (f.flags[0] == 0) f.flags[0] = col + 1;
         } else {
-            H[(size_t)(col + 1) * LDH + col] = hn;
-            S[col + 1] = 1.0 / hn;
+            f.H[(size_t)(col + 1) * LDH + col] = hn;
+            f.S[col + 1] = 1.0 / hn;
         }
     }
 }
 
-__global__ __launch_bounds__(256) void beta_finish_kernel(const double *part, int nblk, double *S,
-                                                          double *res, int *flags) {
-    const double t = block_sum_partials(part, nblk);
-    if (threadIdx.x == 0) {
-        const double beta = sqrt(t);
-        res[0] = beta;
-        S[0] = (beta > 0.0) ? 1.0 / beta : 0.0;
-        flags[0] = 0;
-        if (!isfinite(beta)) flags[1] = 1;
+// part[i][rb] = sum over the block's rows of V_i[r] w[r], i in the block's
+// 16-vector chunk.
+template <typename T>
+__global__ __launch_bounds__(256) void gs_dots_kernel(const T *__restrict__ V, size_t stride,
+                                                      int nv, const T *__restrict__ w, size_t L,
+                                                      size_t rpb, int nrb,
+                                                      double *__restrict__ part) {
+    __shared__ double sw[4][CH];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int rb = blockIdx.x, i0 = blockIdx.y * CH;
+    const int nloc = min(CH, nv - i0);
+    const size_t r0 = (size_t)rb * rpb;
+    const size_t r1 = (r0 + rpb < L) ? r0 + rpb : L;
+    double acc[CH];
+#pragma unroll
+    for (int i = 0; i < CH; ++i) acc[i] = 0.0;
+    const T *Vc = V + (size_t)i0 * stride;
+    for (size_t r = r0 + tid; r < r1; r += 256) {
+        const double x = (double)w[r];
+#pragma unroll
+        for (int i = 0; i < CH; ++i)
+            if (i < nloc) acc[i] += (double)Vc[(size_t)i * stride + r] * x;
     }
+    const double v = transpose_reduce16(acc);
+    if ((lane & 3) == 0) sw[wave][lane >> 2] = v;
+    __syncthreads();
+    if (tid < nloc)
+        part[(size_t)(i0 + tid) * nrb + rb] = (sw[0][tid] + sw[1][tid]) + (sw[2][tid] + sw[3][tid]);
+}
+
+// w -= sum_i c_i V_i with c from the previous pass, then
+// part[i][rb] = sum_r V_i[r] w[r] (nv <= 32).
+template <typename T>
+__global__ __launch_bounds__(256) void gs_update_dots_kernel(
+    const T *__restrict__ V, size_t stride, int nv, PrevPass prev, T *__restrict__ w, size_t L,
+    size_t rpb, int nrb, double *__restrict__ part) {
+    __shared__ double scoef[32];
+    __shared__ double sw[4][32];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid < nv) scoef[tid] = prev.coef[tid];
+    __syncthreads();
+    const int rb = blockIdx.x;
+    const size_t r0 = (size_t)rb * rpb;
+    const size_t r1 = (r0 + rpb < L) ? r0 + rpb : L;
+    double acc[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) acc[i] = 0.0;
+    for (size_t r = r0 + tid; r < r1; r += 256) {
+        double x = (double)w[r];
+        for (int i = 0; i < nv; ++i) x -= scoef[i] * (double)V[(size_t)i * stride + r];
+        const T xs = (T)x;
+        w[r] = xs;
+        x = (double)xs;
+        // the basis rows were just read by this thread: the second read is
+        // served by the caches, not HBM
+#pragma unroll
+        for (int i = 0; i < 32; ++i)
+            if (i < nv) acc[i] += (double)V[(size_t)i * stride + r] * x;
+    }
+    const double v = transpose_reduce32(acc);
+    if ((lane & 1) == 0) sw[wave][lane >> 1] = v;
+    __syncthreads();
+    if (tid < nv) part[(size_t)tid * nrb + rb] = (sw[0][tid] + sw[1][tid]) + (sw[2][tid] + sw[3][tid]);
+}
+
+// w -= sum_i c_i V_i with c from the previous pass (any nv <= kMaxM + 1).
+template <typename T>
+__global__ __launch_bounds__(256) void gs_update_kernel(const T *__restrict__ V, size_t stride,
+                                                        int nv, PrevPass prev,
+                                                        T *__restrict__ w, size_t L, size_t rpb,
+                                                        int nrb) {
+    __shared__ double scoef[kMaxM + 1];
+    const int tid = threadIdx.x;
+    if (tid < nv) scoef[tid] = prev.coef[tid];
+    __syncthreads();
+    const size_t r0 = (size_t)blockIdx.x * rpb;
+    const size_t r1 = (r0 + rpb < L) ? r0 + rpb : L;
+    for (size_t r = r0 + tid; r < r1; r += 256) {
+        double x = (double)w[r];
+        for (int i = 0; i < nv; ++i) x -= scoef[i] * (double)V[(size_t)i * stride + r];
+        w[r] = (T)x;
+    }
+}
+
+// w -= sum_i c_i V_i with c from the previous pass (if any), then the
+// ||w||^2 partials.
+template <typename T>
+__global__ __launch_bounds__(256) void gs_update_norm_kernel(
+    const T *__restrict__ V, size_t stride, int nv, PrevPass prev, T *__restrict__ w, size_t L,
+    size_t rpb, int nrb, double *__restrict__ part) {
+    __shared__ double scoef[kMaxM + 1];
+    __shared__ double sw[4];
+    const int tid = threadIdx.x;
+    const bool upd = prev.coef != nullptr;
+    if (upd && tid < nv) scoef[tid] = prev.coef[tid];
+    __syncthreads();
+    const int rb = blockIdx.x;
+    const size_t r0 = (size_t)rb * rpb;
+    const size_t r1 = (r0 + rpb < L) ? r0 + rpb : L;
+    double acc = 0.0;
+    for (size_t r = r0 + tid; r < r1; r += 256) {
+        double x = (double)w[r];
+        if (upd) {
+            for (int i = 0; i < nv; ++i) x -= scoef[i] * (double)V[(size_t)i * stride + r];
+            const T xs = (T)x;
+            w[r] = xs;
+            x = (double)xs;
+        }
+        acc += x * x;
+    }
+    acc = wave_sum(acc);
+    if ((tid & 63) == 0) sw[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) part[rb] = (sw[0] + sw[1]) + (sw[2] + sw[3]);
 }
 
 template <typename T>
@@ -181,67 +314,104 @@ __global__ __launch_bounds__(256) void norms_kernel(NormArgs<T> a, int nx, size_
         if ((tid & 63) == 0) sred[k][tid >> 6] = s;
     }
     __syncthreads();
-    if (tid < 4) part[(size_t)tid * gridDim.x + blockIdx.x] =
-        (sred[tid][0] + sred[tid][1]) + (sred[tid][2] + sred[tid][3]);
+    if (tid < 4)
+        part[(size_t)tid * gridDim.x + blockIdx.x] =
+            (sred[tid][0] + sred[tid][1]) + (sred[tid][2] + sred[tid][3]);
 }
 
 __global__ __launch_bounds__(256) void norms_finish_kernel(const double *part, int nblk,
                                                            double *out) {
-    const double t = block_sum_partials(part + (size_t)blockIdx.x * nblk, nblk);
-    if (threadIdx.x == 0) out[blockIdx.x] = sqrt(t);
+    __shared__ double sw[4];
+    const int tid = threadIdx.x;
+    double a = 0.0;
+    for (int b = tid; b < nblk; b += 256) a += part[(size_t)blockIdx.x * nblk + b];
+    a = wave_sum(a);
+    if ((tid & 63) == 0) sw[tid >> 6] = a;
+    __syncthreads();
+    if (tid == 0) out[blockIdx.x] = sqrt((sw[0] + sw[1]) + (sw[2] + sw[3]));
 }
 
 // ---- small dense exponential in LDS -----------------------------------------
 constexpr int NMAX = kMaxM + 1;
 constexpr int LDA = NMAX;  // LDS row stride (doubles)
 
-// C = A * B for n x n matrices in LDS (C may alias A or B): results are held
-// in registers until every thread has read its operands.
-__device__ void lds_matmul(const double *A, const double *B, double *C, int n) {
-    constexpr int PER = (NMAX * NMAX + 255) / 256;
-    double t[PER];
-    const int tot = n * n;
+// Orders LDS traffic within one wavefront (no workgroup barrier).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// C = A * B (n x n in LDS, C may alias A or B).  The 256 threads form a
+// 16 x 16 grid; thread (ty, tx) owns rows ty + 16 a and columns tx + 16 b
+// (a, b < TILE), so a wave reads 16 consecutive B columns (no bank conflicts)
+// and broadcasts A; TILE^2 products per 2 TILE LDS loads.  Each entry is
+// summed over q in ascending order.
+template <int TILE>
+__device__ void mm_tile(const double *A, const double *B, double *C, int n) {
+    const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+    double acc[TILE][TILE];
+    int ra[TILE], cb[TILE];
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int e = threadIdx.x + k * 256;
-        double acc = 0.0;
-        if (e < tot) {
-            const int r = e / n, c = e - (e / n) * n;
-            for (int q = 0; q < n; ++q) acc += A[r * LDA + q] * B[q * LDA + c];
-        }
-        t[k] = acc;
+    for (int a = 0; a < TILE; ++a) {
+        ra[a] = min(ty + 16 * a, n - 1) * LDA;
+        cb[a] = min(tx + 16 * a, n - 1);
+#pragma unroll
+        for (int b = 0; b < TILE; ++b) acc[a][b] = 0.0;
+    }
+    for (int q = 0; q < n; ++q) {
+        double av[TILE], bv[TILE];
+#pragma unroll
+        for (int a = 0; a < TILE; ++a) av[a] = A[ra[a] + q];
+#pragma unroll
+        for (int b = 0; b < TILE; ++b) bv[b] = B[q * LDA + cb[b]];
+#pragma unroll
+        for (int a = 0; a < TILE; ++a)
+#pragma unroll
+            for (int b = 0; b < TILE; ++b) acc[a][b] += av[a] * bv[b];
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int e = threadIdx.x + k * 256;
-        if (e < tot) {
-            const int r = e / n, c = e - (e / n) * n;
-            C[r * LDA + c] = t[k];
+    for (int a = 0; a < TILE; ++a)
+#pragma unroll
+        for (int b = 0; b < TILE; ++b) {
+            const int r = ty + 16 * a, c = tx + 16 * b;
+            if (r < n && c < n) C[r * LDA + c] = acc[a][b];
         }
-    }
     __syncthreads();
 }
 
-// E = expm(X) for X (n x n) already in sX; result left in sN.  Returns the
-// number of squarings; sets *singular if the Pade denominator is singular.
-__device__ int lds_expm(double *sX, double *sP, double *sN, double *sD, int n, int *singular) {
-    __shared__ double sred[256];
-    __shared__ int spiv;
+__device__ void matmul(const double *A, const double *B, double *C, int n) {
+    if (n <= 16)
+        mm_tile<1>(A, B, C, n);
+    else if (n <= 32)
+        mm_tile<2>(A, B, C, n);
+    else if (n <= 48)
+        mm_tile<3>(A, B, C, n);
+    else if (n <= 64)
+        mm_tile<4>(A, B, C, n);
+    else
+        mm_tile<5>(A, B, C, n);
+}
+
+// E = expm(X) for X (n x n) in sX; result left in sN.  band = lower bandwidth
+// of the Pade denominator (6 for a Hessenberg X, n - 1 in general).  Returns
+// the number of squarings; sets *singular if the denominator is singular.
+__device__ int lds_expm(double *sX, double *sP, double *sN, double *sD, int n, int band,
+                        int *singular) {
+    __shared__ double swm[4];
     __shared__ double sf[NMAX];
-    const int tid = threadIdx.x;
+    __shared__ int sbad;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // infinity norm
     double rs = 0.0;
     if (tid < n)
         for (int c = 0; c < n; ++c) rs += fabs(sX[tid * LDA + c]);
-    sred[tid] = rs;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) rs = fmax(rs, __shfl_xor(rs, off, 64));
+    if (lane == 0) swm[wave] = rs;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (tid < w) sred[tid] = fmax(sred[tid], sred[tid + w]);
-        __syncthreads();
-    }
-    const double nrm = sred[0];
-    __syncthreads();
+    const double nrm = fmax(fmax(swm[0], swm[1]), fmax(swm[2], swm[3]));
     int s = 0;
     if (nrm > 0.5) s = max(0, (int)ceil(log2(nrm / 0.5)));
     const double scale = ldexp(1.0, -s);
@@ -258,7 +428,7 @@ __device__ int lds_expm(double *sX, double *sP, double *sN, double *sD, int n, i
     const int q = 6;
     for (int k = 1; k <= q; ++k) {
         cf = cf * (q - k + 1) / (double)(k * (2 * q - k + 1));
-        lds_matmul(sX, sP, sP, n);
+        matmul(sX, sP, sP, n);
         const double sg = (k % 2 == 0) ? 1.0 : -1.0;
         for (int e = tid; e < n * n; e += 256) {
             const int r = e / n, c = e % n;
@@ -268,18 +438,22 @@ __device__ int lds_expm(double *sX, double *sP, double *sN, double *sD, int n, i
         }
         __syncthreads();
     }
-    // solve D F = N (partial pivoting, first maximal row on ties)
-    for (int k = 0; k < n; ++k) {
-        if (tid < 64) {
+    // Gaussian elimination with partial pivoting (first maximal row on ties)
+    // in wave 0: rows below the band are exact zeros and are left alone.
+    if (wave == 0) {
+        int bad = 0;
+        for (int k = 0; k < n; ++k) {
+            const int hi = min(n - 1, k + band);
             double best = -1.0;
             int bi = n;
-            for (int r = k + tid; r < n; r += 64) {
+            for (int r = k + lane; r <= hi; r += 64) {
                 const double v = fabs(sD[r * LDA + k]);
                 if (v > best) {
                     best = v;
                     bi = r;
                 }
             }
+#pragma unroll
             for (int off = 32; off > 0; off >>= 1) {
                 const double ob = __shfl_xor(best, off, 64);
                 const int oi = __shfl_xor(bi, off, 64);
@@ -288,45 +462,57 @@ __device__ int lds_expm(double *sX, double *sP, double *sN, double *sD, int n, i
                     bi = oi;
                 }
             }
-            if (tid == 0) spiv = bi;
-        }
-        __syncthreads();
-        const int piv = spiv;
-        if (sD[piv * LDA + k] == 0.0) {
-            if (tid == 0) *singular = 1;
-            return s;
-        }
-        if (piv != k) {
-            for (int c = tid; c < n; c += 256) {
-                double t = sD[k * LDA + c];
-                sD[k * LDA + c] = sD[piv * LDA + c];
-                sD[piv * LDA + c] = t;
-                t = sN[k * LDA + c];
-                sN[k * LDA + c] = sN[piv * LDA + c];
-                sN[piv * LDA + c] = t;
+            const int piv = bi;
+            if (!(sD[piv * LDA + k] != 0.0)) {
+                bad = 1;
+                break;
             }
-            __syncthreads();
+            if (piv != k) {
+                for (int c = lane; c < n; c += 64) {
+                    double t = sD[k * LDA + c];
+                    sD[k * LDA + c] = sD[piv * LDA + c];
+                    sD[piv * LDA + c] = t;
+                    t = sN[k * LDA + c];
+                    sN[k * LDA + c] = sN[piv * LDA + c];
+                    sN[piv * LDA + c] = t;
+                }
+                wave_sync();
+            }
+            // multipliers of every band row first, then one update pass
+            const double dkk = sD[k * LDA + k];
+            for (int r = k + 1 + lane; r <= hi; r += 64) sf[r] = sD[r * LDA + k] / dkk;
+            wave_sync();
+            const int nr = hi - k;
+            for (int e = lane; e < nr * n; e += 64) {
+                const int r = k + 1 + e / n, c = e % n;
+                const double f = sf[r];
+                if (f != 0.0) {
+                    if (c >= k) sD[r * LDA + c] -= f * sD[k * LDA + c];
+                    sN[r * LDA + c] -= f * sN[k * LDA + c];
+                }
+            }
+            wave_sync();
         }
-        for (int r = k + 1 + tid; r < n; r += 256) sf[r] = sD[r * LDA + k] / sD[k * LDA + k];
-        __syncthreads();
-        const int rows = n - k - 1;
-        for (int e = tid; e < rows * n; e += 256) {
-            const int r = k + 1 + e / n, c = e % n;
-            const double f = sf[r];
-            if (c >= k) sD[r * LDA + c] -= f * sD[k * LDA + c];
-            sN[r * LDA + c] -= f * sN[k * LDA + c];
-        }
-        __syncthreads();
+        if (lane == 0) sbad = bad;
     }
+    __syncthreads();
+    if (sbad) {
+        if (tid == 0) *singular = 1;
+        return s;
+    }
+    // back substitution, right-looking: row k is final once divided by its
+    // pivot, then removed from the rows above it
     for (int k = n - 1; k >= 0; --k) {
-        for (int c = tid; c < n; c += 256) {
-            double acc = sN[k * LDA + c];
-            for (int r = k + 1; r < n; ++r) acc -= sD[k * LDA + r] * sN[r * LDA + c];
-            sN[k * LDA + c] = acc / sD[k * LDA + k];
+        const double dkk = sD[k * LDA + k];
+        for (int c = tid; c < n; c += 256) sN[k * LDA + c] /= dkk;
+        __syncthreads();
+        for (int e = tid; e < k * n; e += 256) {
+            const int r = e / n, c = e % n;
+            sN[r * LDA + c] -= sD[r * LDA + k] * sN[k * LDA + c];
         }
         __syncthreads();
     }
-    for (int k = 0; k < s; ++k) lds_matmul(sN, sN, sN, n);
+    for (int k = 0; k < s; ++k) matmul(sN, sN, sN, n);
     return s;
 }
 
@@ -343,7 +529,7 @@ __global__ __launch_bounds__(256) void hess_expm_kernel(const double *H, int j, 
         sX[r * LDA + c] = (c < j) ? dtau * H[(size_t)r * LDH + c] : 0.0;
     }
     __syncthreads();
-    const int s = lds_expm(sX, sP, sN, sD, n, &singular);
+    const int s = lds_expm(sX, sP, sN, sD, n, 6, &singular);
     __syncthreads();
     const double beta = res[0];
     if (threadIdx.x == 0) {
@@ -361,7 +547,7 @@ __global__ __launch_bounds__(256) void dense_expm_kernel(const double *A, int n,
     if (threadIdx.x == 0) singular = 0;
     for (int e = threadIdx.x; e < n * n; e += 256) sX[(e / n) * LDA + e % n] = A[e];
     __syncthreads();
-    lds_expm(sX, sP, sN, sD, n, &singular);
+    lds_expm(sX, sP, sN, sD, n, n - 1, &singular);
     __syncthreads();
     for (int e = threadIdx.x; e < n * n; e += 256)
         E[e] = singular ? __builtin_nan("") : sN[(e / n) * LDA + e % n];
@@ -382,59 +568,100 @@ __global__ __launch_bounds__(256) void combine_kernel(const T *V, size_t stride,
 
 constexpr size_t kExpmLds = (size_t)4 * NMAX * LDA * sizeof(double);
 
-template <typename T, int NVMAX, int MODE>
-hipError_t cgs_launch(const T *V, size_t stride, int nv, const double *coef, T *w, size_t L,
-                      double *part, hipStream_t s) {
-    const size_t rpb = rows_per_block(L);
-    const int nblk = (int)((L + rpb - 1) / rpb);
-    cgs_kernel<T, NVMAX, MODE><<<nblk, 256, 0, s>>>(V, stride, nv, coef, w, L, rpb, part);
-    return hipGetLastError();
+// Allow the dynamic LDS of the exponential kernels (above the 64 KB default
+// of older targets); the attribute call is harmless where it is not needed.
+void allow_expm_lds() {
+    (void)hipFuncSetAttribute((const void *)hess_expm_kernel,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kExpmLds);
+    (void)hipFuncSetAttribute((const void *)dense_expm_kernel,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kExpmLds);
+    (void)hipGetLastError();
 }
 
 }  // namespace
 
-int red_blocks(size_t L) {
-    const size_t rpb = rows_per_block(L);
-    return (int)((L + rpb - 1) / rpb);
+RowPartition row_partition(size_t L) {
+    RowPartition p;
+    size_t nrb = (L + 255) / 256;
+    if (nrb > (size_t)kRedBlocks) nrb = kRedBlocks;
+    if (nrb < 1) nrb = 1;
+    size_t rpb = (L + nrb - 1) / nrb;
+    rpb = (rpb + 255) / 256 * 256;
+    p.rpb = rpb;
+    p.nrb = (int)((L + rpb - 1) / rpb);
+    if (p.nrb < 1) p.nrb = 1;
+    return p;
 }
 
 template <typename T>
-hipError_t launch_cgs_pass(const T *V, size_t stride, int nv, const double *coef, T *w, size_t L,
-                           double *part, int mode, hipStream_t s) {
-    if (nv < 0 || nv > kMaxM + 1) return hipErrorInvalidValue;
-    if (mode == 1) {
-        if (nv <= 8) return cgs_launch<T, 8, 1>(V, stride, nv, coef, w, L, part, s);
-        if (nv <= 16) return cgs_launch<T, 16, 1>(V, stride, nv, coef, w, L, part, s);
-        if (nv <= 32) return cgs_launch<T, 32, 1>(V, stride, nv, coef, w, L, part, s);
-        return cgs_launch<T, kMaxM + 1, 1>(V, stride, nv, coef, w, L, part, s);
+hipError_t launch_gs_dots(const T *V, size_t stride, int nv, const T *w, size_t L,
+                          const RowPartition &rp, double *part, const double *S, double *H,
+                          int col, int accumulate, double *coef_out, hipStream_t s) {
+    if (nv < 1 || nv > kMaxM + 1) return hipErrorInvalidValue;
+    dim3 grid(rp.nrb, (nv + CH - 1) / CH);
+    gs_dots_kernel<T><<<grid, 256, 0, s>>>(V, stride, nv, w, L, rp.rpb, rp.nrb, part);
+    (void)S, (void)H, (void)col, (void)accumulate, (void)coef_out;
+    return hipGetLastError();
+}
+
+hipError_t launch_gs_finish_dots(const double *part, int nv, const RowPartition &rp,
+                                 const double *S, double *H, int col, int accumulate,
+                                 double *coef_out, hipStream_t s) {
+    finish_dots_kernel<<<(nv + 3) / 4, 256, 0, s>>>(part, nv, rp.nrb,
+                                                    DotFinish{S, H, col, accumulate, coef_out});
+    return hipGetLastError();
+}
+
+hipError_t launch_gs_finish_norm(const double *part, const RowPartition &rp, double *H, double *S,
+                                 int col, int *flags, double *res, hipStream_t s) {
+    finish_norm_kernel<<<1, 256, 0, s>>>(part, rp.nrb, NormFinish{H, S, col, flags, res});
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gs_update_dots(const T *V, size_t stride, int nv, const double *coef_in, T *w,
+                                 size_t L, const RowPartition &rp, double *part, const double *S,
+                                 double *H, int col, double *coef_out, hipStream_t s) {
+    if (nv < 1 || nv > kMaxM + 1) return hipErrorInvalidValue;
+    PrevPass prev{coef_in};
+    if (nv <= 32) {
+        gs_update_dots_kernel<T><<<rp.nrb, 256, 0, s>>>(V, stride, nv, prev, w, L, rp.rpb, rp.nrb,
+                                                         part);
+        return hipGetLastError();
     }
-    if (nv <= 8) return cgs_launch<T, 8, 0>(V, stride, nv, coef, w, L, part, s);
-    if (nv <= 16) return cgs_launch<T, 16, 0>(V, stride, nv, coef, w, L, part, s);
-    if (nv <= 32) return cgs_launch<T, 32, 0>(V, stride, nv, coef, w, L, part, s);
-    return cgs_launch<T, kMaxM + 1, 0>(V, stride, nv, coef, w, L, part, s);
+    gs_update_kernel<T><<<rp.nrb, 256, 0, s>>>(V, stride, nv, prev, w, L, rp.rpb, rp.nrb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_gs_dots<T>(V, stride, nv, w, L, rp, part, S, H, col, 1, coef_out, s);
 }
-template hipError_t launch_cgs_pass<double>(const double *, size_t, int, const double *, double *,
-                                            size_t, double *, int, hipStream_t);
-template hipError_t launch_cgs_pass<float>(const float *, size_t, int, const double *, float *,
-                                           size_t, double *, int, hipStream_t);
 
-hipError_t launch_dot_finish(const double *part, int nblk, int nv, const double *S, double *H,
-                             int col, int accumulate, double *coef, hipStream_t s) {
-    dot_finish_kernel<<<nv, 256, 0, s>>>(part, nblk, S, H, col, accumulate, coef);
+template <typename T>
+hipError_t launch_gs_update_norm(const T *V, size_t stride, int nv, const double *coef, T *w,
+                                 size_t L, const RowPartition &rp, double *part, double *H,
+                                 double *S, int col, int *flags, double *res, hipStream_t s) {
+    if (nv < 0 || nv > kMaxM + 1) return hipErrorInvalidValue;
+    PrevPass prev{coef};
+    gs_update_norm_kernel<T><<<rp.nrb, 256, 0, s>>>(V, stride, nv, prev, w, L, rp.rpb, rp.nrb,
+                                                     part);
+    (void)H, (void)S, (void)col, (void)flags, (void)res;
     return hipGetLastError();
 }
 
-hipError_t launch_norm_finish(const double *part, int nblk, double *H, double *S, int col,
-                              int *flags, hipStream_t s) {
-    norm_finish_kernel<<<1, 256, 0, s>>>(part, nblk, H, S, col, flags);
-    return hipGetLastError();
-}
-
-hipError_t launch_beta_finish(const double *part, int nblk, double *S, double *res, int *flags,
-                              hipStream_t s) {
-    beta_finish_kernel<<<1, 256, 0, s>>>(part, nblk, S, res, flags);
-    return hipGetLastError();
-}
+#define EXPDG_INST(T)                                                                         \
+    template hipError_t launch_gs_dots<T>(const T *, size_t, int, const T *, size_t,           \
+                                          const RowPartition &, double *, const double *,       \
+                                          double *, int, int, double *, hipStream_t);           \
+    template hipError_t launch_gs_update_dots<T>(const T *, size_t, int, const double *, T *,  \
+                                                 size_t, const RowPartition &, double *,        \
+                                                 const double *, double *, int, double *,       \
+                                                 hipStream_t);                                  \
+    template hipError_t launch_gs_update_norm<T>(const T *, size_t, int, const double *, T *,  \
+                                                 size_t, const RowPartition &, double *,        \
+                                                 double *, double *, int, int *, double *,      \
+                                                 hipStream_t);
+EXPDG_INST(double)
+EXPDG_INST(float)
+#undef EXPDG_INST
 
 template <typename T>
 hipError_t launch_norms(const T *const *x, int nx, size_t n, double *part, double *out,
@@ -442,28 +669,17 @@ hipError_t launch_norms(const T *const *x, int nx, size_t n, double *part, doubl
     if (nx < 1 || nx > 4) return hipErrorInvalidValue;
     NormArgs<T> a;
     for (int k = 0; k < 4; ++k) a.x[k] = (k < nx) ? x[k] : nullptr;
-    const size_t rpb = rows_per_block(n);
-    const int nblk = (int)((n + rpb - 1) / rpb);
-    norms_kernel<T><<<nblk, 256, 0, s>>>(a, nx, n, rpb, part);
+    const RowPartition rp = row_partition(n);
+    norms_kernel<T><<<rp.nrb, 256, 0, s>>>(a, nx, n, rp.rpb, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    norms_finish_kernel<<<nx, 256, 0, s>>>(part, nblk, out);
+    norms_finish_kernel<<<nx, 256, 0, s>>>(part, rp.nrb, out);
     return hipGetLastError();
 }
 template hipError_t launch_norms<double>(const double *const *, int, size_t, double *, double *,
                                          hipStream_t);
 template hipError_t launch_norms<float>(const float *const *, int, size_t, double *, double *,
                                         hipStream_t);
-
-// Allow the dynamic LDS of the exponential kernels (above the 64 KB default
-// of older targets); the attribute call is harmless where it is not needed.
-static void allow_expm_lds() {
-    (void)hipFuncSetAttribute((const void *)hess_expm_kernel,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kExpmLds);
-    (void)hipFuncSetAttribute((const void *)dense_expm_kernel,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kExpmLds);
-    (void)hipGetLastError();
-}
 
 hipError_t launch_hess_expm(const double *H, int j, double dtau, const double *S,
                             const double *res_beta, double *slot, hipStream_t s) {
