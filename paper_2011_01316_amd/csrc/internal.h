@@ -83,7 +83,7 @@ struct KrylovDev {
 };
 
 // Fixed row partition of a length-L vector: nrb blocks of rpb rows (rpb a
-// multiple of 256, nrb <= kRedBlocks).
+// multiple of 1024, nrb <= kRedBlocks).
 struct RowPartition {
     size_t rpb;
     int nrb;

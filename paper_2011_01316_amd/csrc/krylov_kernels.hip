@@ -40,6 +40,43 @@ namespace {
 constexpr int LDH = kMaxM;  // leading dimension of H
 constexpr int CH = 16;      // basis vectors per chunk of the dot kernel
 
+// 16-byte vector access: 2 doubles or 4 floats per lane per load.
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<double> {
+    static constexpr int N = 2;
+    using type = double2;
+};
+template <>
+struct Vec16<float> {
+    static constexpr int N = 4;
+    using type = float4;
+};
+
+template <typename T>
+__device__ __forceinline__ void ld16(const T *p, double *out) {
+    using VT = typename Vec16<T>::type;
+    const VT v = *reinterpret_cast<const VT *>(p);
+    const T *e = reinterpret_cast<const T *>(&v);
+#pragma unroll
+    for (int k = 0; k < Vec16<T>::N; ++k) out[k] = (double)e[k];
+}
+
+// Stores the values rounded to T and returns the rounded values in x.
+template <typename T>
+__device__ __forceinline__ void st16(T *p, double *x) {
+    using VT = typename Vec16<T>::type;
+    VT v;
+    T *e = reinterpret_cast<T *>(&v);
+#pragma unroll
+    for (int k = 0; k < Vec16<T>::N; ++k) {
+        e[k] = (T)x[k];
+        x[k] = (double)e[k];
+    }
+    *reinterpret_cast<VT *>(p) = v;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -188,7 +225,23 @@ __global__ __launch_bounds__(256) void gs_dots_kernel(const T *__restrict__ V, s
 #pragma unroll
     for (int i = 0; i < CH; ++i) acc[i] = 0.0;
     const T *Vc = V + (size_t)i0 * stride;
-    for (size_t r = r0 + tid; r < r1; r += 256) {
+    constexpr int N = Vec16<T>::N;
+    // full 16-byte sweeps, then the ragged tail one row at a time
+    const size_t nsw = (r1 - r0) / (256 * N);
+    for (size_t k = 0; k < nsw; ++k) {
+        const size_t r = r0 + (k * 256 + tid) * N;
+        double x[N];
+        ld16(w + r, x);
+#pragma unroll
+        for (int i = 0; i < CH; ++i)
+            if (i < nloc) {
+                double vv[N];
+                ld16(Vc + (size_t)i * stride + r, vv);
+#pragma unroll
+                for (int e = 0; e < N; ++e) acc[i] += vv[e] * x[e];
+            }
+    }
+    for (size_t r = r0 + nsw * 256 * N + tid; r < r1; r += 256) {
         const double x = (double)w[r];
 #pragma unroll
         for (int i = 0; i < CH; ++i)
@@ -218,14 +271,36 @@ __global__ __launch_bounds__(256) void gs_update_dots_kernel(
     double acc[32];
 #pragma unroll
     for (int i = 0; i < 32; ++i) acc[i] = 0.0;
-    for (size_t r = r0 + tid; r < r1; r += 256) {
+    constexpr int N = Vec16<T>::N;
+    const size_t nsw = (r1 - r0) / (256 * N);
+    for (size_t k = 0; k < nsw; ++k) {
+        const size_t r = r0 + (k * 256 + tid) * N;
+        double x[N];
+        ld16(w + r, x);
+        for (int i = 0; i < nv; ++i) {
+            double vv[N];
+            ld16(V + (size_t)i * stride + r, vv);
+#pragma unroll
+            for (int e = 0; e < N; ++e) x[e] -= scoef[i] * vv[e];
+        }
+        st16(w + r, x);
+        // the basis rows were just read by this thread: the second read is
+        // served by the caches, not HBM
+#pragma unroll
+        for (int i = 0; i < 32; ++i)
+            if (i < nv) {
+                double vv[N];
+                ld16(V + (size_t)i * stride + r, vv);
+#pragma unroll
+                for (int e = 0; e < N; ++e) acc[i] += vv[e] * x[e];
+            }
+    }
+    for (size_t r = r0 + nsw * 256 * N + tid; r < r1; r += 256) {
         double x = (double)w[r];
         for (int i = 0; i < nv; ++i) x -= scoef[i] * (double)V[(size_t)i * stride + r];
         const T xs = (T)x;
         w[r] = xs;
         x = (double)xs;
-        // the basis rows were just read by this thread: the second read is
-        // served by the caches, not HBM
 #pragma unroll
         for (int i = 0; i < 32; ++i)
             if (i < nv) acc[i] += (double)V[(size_t)i * stride + r] * x;
@@ -248,7 +323,21 @@ __global__ __launch_bounds__(256) void gs_update_kernel(const T *__restrict__ V,
     __syncthreads();
     const size_t r0 = (size_t)blockIdx.x * rpb;
     const size_t r1 = (r0 + rpb < L) ? r0 + rpb : L;
-    for (size_t r = r0 + tid; r < r1; r += 256) {
+    constexpr int N = Vec16<T>::N;
+    const size_t nsw = (r1 - r0) / (256 * N);
+    for (size_t k = 0; k < nsw; ++k) {
+        const size_t r = r0 + (k * 256 + tid) * N;
+        double x[N];
+        ld16(w + r, x);
+        for (int i = 0; i < nv; ++i) {
+            double vv[N];
+            ld16(V + (size_t)i * stride + r, vv);
+#pragma unroll
+            for (int e = 0; e < N; ++e) x[e] -= scoef[i] * vv[e];
+        }
+        st16(w + r, x);
+    }
+    for (size_t r = r0 + nsw * 256 * N + tid; r < r1; r += 256) {
         double x = (double)w[r];
         for (int i = 0; i < nv; ++i) x -= scoef[i] * (double)V[(size_t)i * stride + r];
         w[r] = (T)x;
@@ -271,7 +360,25 @@ __global__ __launch_bounds__(256) void gs_update_norm_kernel(
     const size_t r0 = (size_t)rb * rpb;
     const size_t r1 = (r0 + rpb < L) ? r0 + rpb : L;
     double acc = 0.0;
-    for (size_t r = r0 + tid; r < r1; r += 256) {
+    constexpr int N = Vec16<T>::N;
+    const size_t nsw = (r1 - r0) / (256 * N);
+    for (size_t k = 0; k < nsw; ++k) {
+        const size_t r = r0 + (k * 256 + tid) * N;
+        double x[N];
+        ld16(w + r, x);
+        if (upd) {
+            for (int i = 0; i < nv; ++i) {
+                double vv[N];
+                ld16(V + (size_t)i * stride + r, vv);
+#pragma unroll
+                for (int e = 0; e < N; ++e) x[e] -= scoef[i] * vv[e];
+            }
+            st16(w + r, x);
+        }
+#pragma unroll
+        for (int e = 0; e < N; ++e) acc += x[e] * x[e];
+    }
+    for (size_t r = r0 + nsw * 256 * N + tid; r < r1; r += 256) {
         double x = (double)w[r];
         if (upd) {
             for (int i = 0; i < nv; ++i) x -= scoef[i] * (double)V[(size_t)i * stride + r];
@@ -559,11 +666,27 @@ __global__ __launch_bounds__(256) void combine_kernel(const T *V, size_t stride,
     __shared__ double sc[kMaxM];
     if ((int)threadIdx.x < m) sc[threadIdx.x] = ccoef[threadIdx.x];
     __syncthreads();
-    for (size_t r = (size_t)blockIdx.x * 256 + threadIdx.x; r < L; r += (size_t)gridDim.x * 256) {
-        double acc = 0.0;
-        for (int i = 0; i < m; ++i) acc += sc[i] * (double)V[(size_t)i * stride + r];
-        z[r] = (T)acc;
+    constexpr int N = Vec16<T>::N;
+    const size_t Lv = L / N * N;  // rows covered by full 16-byte vectors
+    for (size_t r = ((size_t)blockIdx.x * 256 + threadIdx.x) * N; r < Lv;
+         r += (size_t)gridDim.x * 256 * N) {
+        double acc[N];
+#pragma unroll
+        for (int e = 0; e < N; ++e) acc[e] = 0.0;
+        for (int i = 0; i < m; ++i) {
+            double vv[N];
+            ld16(V + (size_t)i * stride + r, vv);
+#pragma unroll
+            for (int e = 0; e < N; ++e) acc[e] += sc[i] * vv[e];
+        }
+        st16(z + r, acc);
     }
+    if (blockIdx.x == 0)
+        for (size_t r = Lv + threadIdx.x; r < L; r += 256) {
+            double acc = 0.0;
+            for (int i = 0; i < m; ++i) acc += sc[i] * (double)V[(size_t)i * stride + r];
+            z[r] = (T)acc;
+        }
 }
 
 constexpr size_t kExpmLds = (size_t)4 * NMAX * LDA * sizeof(double);
@@ -586,7 +709,7 @@ RowPartition row_partition(size_t L) {
     if (nrb > (size_t)kRedBlocks) nrb = kRedBlocks;
     if (nrb < 1) nrb = 1;
     size_t rpb = (L + nrb - 1) / nrb;
-    rpb = (rpb + 255) / 256 * 256;
+    rpb = (rpb + 1023) / 1024 * 1024;  // whole 16-byte sweeps for double and float
     p.rpb = rpb;
     p.nrb = (int)((L + rpb - 1) / rpb);
     if (p.nrb < 1) p.nrb = 1;

@@ -11,7 +11,7 @@
     least p + 1/2 (the paper observes k + 1/2, Table
     expo-euler-isentropic-sconv-uni);
   * a replayed Krylov schedule reproduces a step bit for bit;
-  * Krylov iterations per step grow with the Courant number (Section 5.4).
+  * Krylov iterations per step grow with the Courant number (Section 5.2.5).
 """
 import math
 
