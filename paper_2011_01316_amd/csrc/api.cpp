@@ -72,6 +72,13 @@ double round2(double x) {
 
 }  // namespace
 
+namespace expdg {
+LaunchEvents &next_launch_events() {
+    thread_local LaunchEvents e;
+    return e;
+}
+}  // namespace expdg
+
 // ---------------------------------------------------------------------------
 // LGL reference element (library construction).
 //
@@ -282,18 +289,22 @@ int prof_flush(expdg_mesh *m, int c) {
     return EXPDG_OK;
 }
 
+// The next kernel launch records the event pair as part of its own dispatch
+// (hipExtLaunchKernelGGL), so the interval is the kernel's execution.
 int prof_begin(expdg_mesh *m, int c, hipStream_t s) {
+    (void)s;
     auto &P = m->prof[c];
     if (!P.on) return EXPDG_OK;
     if (P.used == kProfPairs) TRY(prof_flush(m, c));
-    HIPTRY(hipEventRecord(P.ev[2 * P.used], s));
+    next_launch_events() = LaunchEvents{P.ev[2 * P.used], P.ev[2 * P.used + 1]};
     return EXPDG_OK;
 }
 
 int prof_end(expdg_mesh *m, int c, hipStream_t s, double bytes) {
+    (void)s;
     auto &P = m->prof[c];
     if (!P.on) return EXPDG_OK;
-    HIPTRY(hipEventRecord(P.ev[2 * P.used + 1], s));
+    next_launch_events() = LaunchEvents{};
     P.bytes[P.used] = bytes;
     P.used += 1;
     return EXPDG_OK;

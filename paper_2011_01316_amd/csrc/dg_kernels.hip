@@ -289,19 +289,13 @@ hipError_t launch_p(int equation, bool jvp, const OpArgs<T> &a, hipStream_t s) {
     if (equation == EXPDG_EULER2D) {
         constexpr int EPB = 256 / ((P + 1) * (P + 1));
         const int grid = (a.K + EPB - 1) / EPB;
-        if (jvp)
-            euler_op<P, T, true><<<grid, 256, 0, s>>>(a);
-        else
-            euler_op<P, T, false><<<grid, 256, 0, s>>>(a);
-    } else {
-        constexpr int EPB = 256 / (P + 1);
-        const int grid = (a.K + EPB - 1) / EPB;
-        if (jvp)
-            burgers_op<P, T, true><<<grid, 256, 0, s>>>(a);
-        else
-            burgers_op<P, T, false><<<grid, 256, 0, s>>>(a);
+        if (jvp) return launch_kernel(euler_op<P, T, true>, dim3(grid), dim3(256), 0, s, a);
+        return launch_kernel(euler_op<P, T, false>, dim3(grid), dim3(256), 0, s, a);
     }
-    return hipGetLastError();
+    constexpr int EPB = 256 / (P + 1);
+    const int grid = (a.K + EPB - 1) / EPB;
+    if (jvp) return launch_kernel(burgers_op<P, T, true>, dim3(grid), dim3(256), 0, s, a);
+    return launch_kernel(burgers_op<P, T, false>, dim3(grid), dim3(256), 0, s, a);
 }
 
 template <typename T>

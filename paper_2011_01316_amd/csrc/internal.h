@@ -3,6 +3,7 @@
 // drivers in api.cpp.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -36,6 +37,26 @@ struct OpArgs {
     T gamma;
     T D[(kMaxP + 1) * (kMaxP + 1)];  // D[i*(p+1)+l] = l_l'(xi_i)
 };
+
+// Start/stop events that the next kernel launch of this host thread records as
+// part of its own dispatch (live kernel timing); the launch consumes them.
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+LaunchEvents &next_launch_events();
+
+template <typename K, typename... Args>
+hipError_t launch_kernel(K kernel, dim3 grid, dim3 block, unsigned shmem, hipStream_t s,
+                         Args... args) {
+    LaunchEvents &e = next_launch_events();
+    if (e.start) {
+        hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, e.start, e.stop, 0, args...);
+        e = LaunchEvents{};
+    } else {
+        kernel<<<grid, block, shmem, s>>>(args...);
+    }
+    return hipGetLastError();
+}
 
 // Host-side LGL tables of degree p (library's own construction).
 int lgl_tables(int p, double *xi, double *w, double *D);

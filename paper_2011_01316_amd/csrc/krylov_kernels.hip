@@ -277,17 +277,35 @@ __global__ __launch_bounds__(256) void gs_update_dots_kernel(
         const size_t r = r0 + (k * 256 + tid) * N;
         double x[N];
         ld16(w + r, x);
-        for (int i = 0; i < nv; ++i) {
+        // the first KEEP basis rows (32 values per lane) stay in registers for
+        // the second product; the others are read again (the same thread just
+        // read them, so mostly from cache)
+        constexpr int KEEP = 32 / N;
+        double keep[KEEP][N];
+#pragma unroll
+        for (int i = 0; i < KEEP; ++i) {
+            if (i < nv) {
+                ld16(V + (size_t)i * stride + r, keep[i]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < N; ++e) keep[i][e] = 0.0;
+            }
+#pragma unroll
+            for (int e = 0; e < N; ++e) x[e] -= scoef[i < nv ? i : 0] * keep[i][e];
+        }
+        for (int i = KEEP; i < nv; ++i) {
             double vv[N];
             ld16(V + (size_t)i * stride + r, vv);
 #pragma unroll
             for (int e = 0; e < N; ++e) x[e] -= scoef[i] * vv[e];
         }
         st16(w + r, x);
-        // the basis rows were just read by this thread: the second read is
-        // served by the caches, not HBM
 #pragma unroll
-        for (int i = 0; i < 32; ++i)
+        for (int i = 0; i < KEEP; ++i)
+#pragma unroll
+            for (int e = 0; e < N; ++e) acc[i] += keep[i][e] * x[e];
+#pragma unroll
+        for (int i = KEEP; i < 32; ++i)
             if (i < nv) {
                 double vv[N];
                 ld16(V + (size_t)i * stride + r, vv);
@@ -722,23 +740,22 @@ hipError_t launch_gs_dots(const T *V, size_t stride, int nv, const T *w, size_t 
                           int col, int accumulate, double *coef_out, hipStream_t s) {
     if (nv < 1 || nv > kMaxM + 1) return hipErrorInvalidValue;
     dim3 grid(rp.nrb, (nv + CH - 1) / CH);
-    gs_dots_kernel<T><<<grid, 256, 0, s>>>(V, stride, nv, w, L, rp.rpb, rp.nrb, part);
     (void)S, (void)H, (void)col, (void)accumulate, (void)coef_out;
-    return hipGetLastError();
+    return launch_kernel(gs_dots_kernel<T>, grid, dim3(256), 0, s, V, stride, nv, w, L, rp.rpb,
+                         rp.nrb, part);
 }
 
 hipError_t launch_gs_finish_dots(const double *part, int nv, const RowPartition &rp,
                                  const double *S, double *H, int col, int accumulate,
                                  double *coef_out, hipStream_t s) {
-    finish_dots_kernel<<<(nv + 3) / 4, 256, 0, s>>>(part, nv, rp.nrb,
-                                                    DotFinish{S, H, col, accumulate, coef_out});
-    return hipGetLastError();
+    return launch_kernel(finish_dots_kernel, dim3((nv + 3) / 4), dim3(256), 0, s, part, nv,
+                         rp.nrb, DotFinish{S, H, col, accumulate, coef_out});
 }
 
 hipError_t launch_gs_finish_norm(const double *part, const RowPartition &rp, double *H, double *S,
                                  int col, int *flags, double *res, hipStream_t s) {
-    finish_norm_kernel<<<1, 256, 0, s>>>(part, rp.nrb, NormFinish{H, S, col, flags, res});
-    return hipGetLastError();
+    return launch_kernel(finish_norm_kernel, dim3(1), dim3(256), 0, s, part, rp.nrb,
+                         NormFinish{H, S, col, flags, res});
 }
 
 template <typename T>
@@ -748,12 +765,11 @@ hipError_t launch_gs_update_dots(const T *V, size_t stride, int nv, const double
     if (nv < 1 || nv > kMaxM + 1) return hipErrorInvalidValue;
     PrevPass prev{coef_in};
     if (nv <= 32) {
-        gs_update_dots_kernel<T><<<rp.nrb, 256, 0, s>>>(V, stride, nv, prev, w, L, rp.rpb, rp.nrb,
-                                                         part);
-        return hipGetLastError();
+        return launch_kernel(gs_update_dots_kernel<T>, dim3(rp.nrb), dim3(256), 0, s, V, stride,
+                             nv, prev, w, L, rp.rpb, rp.nrb, part);
     }
-    gs_update_kernel<T><<<rp.nrb, 256, 0, s>>>(V, stride, nv, prev, w, L, rp.rpb, rp.nrb);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_kernel(gs_update_kernel<T>, dim3(rp.nrb), dim3(256), 0, s, V, stride,
+                                 nv, prev, w, L, rp.rpb, rp.nrb);
     if (e != hipSuccess) return e;
     return launch_gs_dots<T>(V, stride, nv, w, L, rp, part, S, H, col, 1, coef_out, s);
 }
@@ -764,10 +780,9 @@ hipError_t launch_gs_update_norm(const T *V, size_t stride, int nv, const double
                                  double *S, int col, int *flags, double *res, hipStream_t s) {
     if (nv < 0 || nv > kMaxM + 1) return hipErrorInvalidValue;
     PrevPass prev{coef};
-    gs_update_norm_kernel<T><<<rp.nrb, 256, 0, s>>>(V, stride, nv, prev, w, L, rp.rpb, rp.nrb,
-                                                     part);
     (void)H, (void)S, (void)col, (void)flags, (void)res;
-    return hipGetLastError();
+    return launch_kernel(gs_update_norm_kernel<T>, dim3(rp.nrb), dim3(256), 0, s, V, stride, nv,
+                         prev, w, L, rp.rpb, rp.nrb, part);
 }
 
 #define EXPDG_INST(T)                                                                         \
@@ -809,8 +824,8 @@ hipError_t launch_hess_expm(const double *H, int j, double dtau, const double *S
     if (j < 1 || j > kMaxM) return hipErrorInvalidValue;
     static bool once = (allow_expm_lds(), true);
     (void)once;
-    hess_expm_kernel<<<1, 256, kExpmLds, s>>>(H, j, dtau, S, res_beta, slot);
-    return hipGetLastError();
+    return launch_kernel(hess_expm_kernel, dim3(1), dim3(256), (unsigned)kExpmLds, s, H, j, dtau,
+                         S, res_beta, slot);
 }
 
 hipError_t launch_dense_expm(const double *A, int n, double *E, hipStream_t s) {
@@ -827,8 +842,8 @@ hipError_t launch_combine(const T *V, size_t stride, int m, const double *ccoef,
     if (m < 1 || m > kMaxM) return hipErrorInvalidValue;
     size_t g = (L + 255) / 256;
     if (g > 4096) g = 4096;
-    combine_kernel<T><<<(int)g, 256, 0, s>>>(V, stride, m, ccoef, z, L);
-    return hipGetLastError();
+    return launch_kernel(combine_kernel<T>, dim3((unsigned)g), dim3(256), 0, s, V, stride, m,
+                         ccoef, z, L);
 }
 template hipError_t launch_combine<double>(const double *, size_t, int, const double *, double *,
                                            size_t, hipStream_t);
