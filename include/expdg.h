@@ -220,6 +220,101 @@ int expdg_profile_enable(expdg_mesh *m, int kernel_class, int enable);
 /* Read the counters of kernel_class (waits for the recorded events). */
 int expdg_profile_read(expdg_mesh *m, int kernel_class, expdg_kernel_profile *out);
 
+/* ------------------------------------------------------------------------
+ * Solve server: many independent solves share the device.
+ *
+ * A pattern on top of the method (the paper runs one solve at a time).  Each
+ * submitted request is a whole time integration: nsteps steps of EPI2 or EPI3
+ * (FP64) from the initial state q0 on its own mesh, with the adaptive Krylov
+ * controller of expdg_step.  Requests are admitted in arrival order while
+ * their device memory (expdg_request_bytes) fits the HBM budget given at
+ * creation and fewer than max_active solves run; an admitted solve keeps its
+ * state and Krylov workspace resident until it ends.  The server advances all
+ * running solves together in ticks (expdg_server_tick): in one tick every
+ * solve that is ready takes one Arnoldi step, and the same step of all of
+ * them runs as grouped launches -- one linear-operator launch per (equation,
+ * degree) and one launch per Gram-Schmidt pass over all solves -- while the
+ * small Hessenberg exponentials of all solves that check their Krylov error in
+ * that tick run as one batched launch on a second stream.  A solve gives the
+ * same bits as expdg_step on its own mesh with the same options, whatever
+ * else runs beside it.
+ *
+ * Threading: a server handle is used by one host thread at a time.  All host
+ * buffers passed in are copied before the call returns.
+ * ------------------------------------------------------------------------ */
+typedef struct expdg_server expdg_server; /* opaque, library-owned */
+
+typedef struct {
+    expdg_mesh_desc mesh; /* precision must be EXPDG_FP64; device is ignored
+                             (the server's device is used) */
+    int scheme;           /* EXPDG_EPI2 or EXPDG_EPI3 (first step EPI2) */
+    int nsteps;           /* >= 1 */
+    double dt;            /* > 0: the step; <= 0: cfl * dx_min / max wave speed of q0 */
+    double cfl;           /* used when dt <= 0 (must then be > 0) */
+    double tol;           /* Krylov options as in expdg_krylov_opts (no forced schedule) */
+    int m_min, m_max, check_every;
+} expdg_request;
+
+enum {
+    EXPDG_REQ_QUEUED = 0,    /* waiting for admission */
+    EXPDG_REQ_ACTIVE = 1,    /* admitted, running */
+    EXPDG_REQ_DONE = 2,      /* finished; the state can be fetched */
+    EXPDG_REQ_FAILED = 3     /* stopped with an error (info.error) */
+};
+
+typedef struct {
+    int state;               /* EXPDG_REQ_* */
+    int error;               /* status of a failed solve, else EXPDG_OK */
+    int steps_done;
+    double dt;               /* the step used (after the cfl rule) */
+    expdg_krylov_stats stats; /* accumulated over all steps; log is NULL */
+    double t_submit, t_admit, t_done; /* seconds on the server clock (-1: not yet) */
+    size_t bytes;            /* device memory the solve holds while running */
+} expdg_request_info;
+
+typedef struct {
+    long long ticks;             /* ticks that launched work */
+    long long grouped_launches;  /* grouped operator + Gram-Schmidt launches */
+    long long batched_checks;    /* batched small-exponential launches */
+    long long arnoldi_items;     /* Arnoldi steps run inside grouped launches */
+    long long check_items;       /* checks run inside batched launches */
+    int active, queued, done;
+    size_t arena_bytes, arena_used, arena_peak;
+} expdg_server_stats;
+
+/* Device memory one request holds while running (workspace + states);
+ * 0 if the request is invalid. */
+size_t expdg_request_bytes(const expdg_request *r);
+/* hbm_budget: bytes of device memory the server reserves at creation and
+ * admits solves into; max_active: most solves running at once (1..4096). */
+int expdg_server_create(int device, size_t hbm_budget, int max_active, expdg_server **out);
+/* Waits for the device, releases everything (running solves are dropped). */
+int expdg_server_destroy(expdg_server *s);
+/* Queues a request with its initial state q0 (host, ndof doubles, copied).
+ * EINVAL if it is invalid or can never fit the budget; *id identifies it. */
+int expdg_server_submit(expdg_server *s, const expdg_request *r, const double *q0, long long *id);
+/* Admits what fits, advances every ready solve and launches the tick's grouped
+ * work.  block != 0: if no solve is ready, first wait until one is.  Returns
+ * the number of solves that finished in this call in *finished (may be NULL). */
+int expdg_server_tick(expdg_server *s, int block, int *finished);
+/* Ids of solves finished (DONE or FAILED) since the last call, at most cap;
+ * returns the count written (or a negative status). */
+int expdg_server_finished(expdg_server *s, long long *ids, int cap);
+int expdg_server_poll(expdg_server *s, long long id, expdg_request_info *info);
+/* Copies the final state of a DONE solve to q_out (host, ndof doubles) and
+ * releases the solve. */
+int expdg_server_fetch(expdg_server *s, long long id, double *q_out);
+/* Drops a request in any state (a running solve stops; its memory returns
+ * to the budget once the device is done with it). */
+int expdg_server_cancel(expdg_server *s, long long id);
+/* Counters; memory of ended solves the device is done with is reclaimed first. */
+int expdg_server_get_stats(expdg_server *s, expdg_server_stats *out);
+/* Waits until the device has finished everything launched so far and
+ * reclaims the memory of ended solves. */
+int expdg_server_sync(expdg_server *s);
+/* Seconds since the server was created (the clock of the info timestamps). */
+double expdg_server_clock(const expdg_server *s);
+
 /* Thread-local description of the last error (never NULL). */
 const char *expdg_last_error(void);
 /* ABI version: major * 10000 + minor * 100 + patch. */

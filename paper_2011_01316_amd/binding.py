@@ -60,6 +60,28 @@ class KernelProfile(C.Structure):
     _fields_ = [("launches", C.c_longlong), ("total_ms", C.c_double), ("bytes", C.c_double)]
 
 
+class Request(C.Structure):
+    _fields_ = [("mesh", MeshDesc), ("scheme", C.c_int), ("nsteps", C.c_int),
+                ("dt", C.c_double), ("cfl", C.c_double), ("tol", C.c_double),
+                ("m_min", C.c_int), ("m_max", C.c_int), ("check_every", C.c_int)]
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("state", C.c_int), ("error", C.c_int), ("steps_done", C.c_int),
+                ("dt", C.c_double), ("stats", KrylovStats), ("t_submit", C.c_double),
+                ("t_admit", C.c_double), ("t_done", C.c_double), ("bytes", C.c_size_t)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("ticks", C.c_longlong), ("grouped_launches", C.c_longlong),
+                ("batched_checks", C.c_longlong), ("arnoldi_items", C.c_longlong),
+                ("check_items", C.c_longlong), ("active", C.c_int), ("queued", C.c_int),
+                ("done", C.c_int), ("arena_bytes", C.c_size_t), ("arena_used", C.c_size_t),
+                ("arena_peak", C.c_size_t)]
+
+
+REQ_QUEUED, REQ_ACTIVE, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
+
 K_RESIDUAL, K_LINEAR, K_GS_DOTS, K_SMALLEXPM, K_COMBINE = 0, 1, 2, 3, 4
 K_GS_UPDATE_DOTS, K_GS_UPDATE_NORM, K_GS_FINISH = 5, 6, 7
 KERNEL_CLASSES = {K_RESIDUAL: "residual", K_LINEAR: "linear_operator", K_GS_DOTS: "gs_dots",
@@ -92,6 +114,19 @@ _SIGS = {
     "expdg_small_expm": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "expdg_profile_enable": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     "expdg_profile_read": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(KernelProfile)]),
+    "expdg_request_bytes": (C.c_size_t, [C.POINTER(Request)]),
+    "expdg_server_create": (C.c_int, [C.c_int, C.c_size_t, C.c_int, C.POINTER(C.c_void_p)]),
+    "expdg_server_destroy": (C.c_int, [C.c_void_p]),
+    "expdg_server_submit": (C.c_int, [C.c_void_p, C.POINTER(Request), C.c_void_p,
+                                      C.POINTER(C.c_longlong)]),
+    "expdg_server_tick": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int)]),
+    "expdg_server_finished": (C.c_int, [C.c_void_p, C.POINTER(C.c_longlong), C.c_int]),
+    "expdg_server_poll": (C.c_int, [C.c_void_p, C.c_longlong, C.POINTER(RequestInfo)]),
+    "expdg_server_fetch": (C.c_int, [C.c_void_p, C.c_longlong, C.c_void_p]),
+    "expdg_server_cancel": (C.c_int, [C.c_void_p, C.c_longlong]),
+    "expdg_server_get_stats": (C.c_int, [C.c_void_p, C.POINTER(ServerStats)]),
+    "expdg_server_sync": (C.c_int, [C.c_void_p]),
+    "expdg_server_clock": (C.c_double, [C.c_void_p]),
     "expdg_last_error": (C.c_char_p, []),
     "expdg_version": (C.c_int, []),
 }
@@ -292,3 +327,144 @@ class Mesh:
              stream=None):
         expdg_step(self.handle, scheme, dt, q, q_prev, have_prev, opts or make_opts(), stats,
                    stream)
+
+
+# ---- solve server -------------------------------------------------------------
+def make_request(equation, nx, p, ny=1, scheme=EPI3, nsteps=20, dt=0.0, cfl=0.0, tol=1e-10,
+                 m_min=10, m_max=64, check_every=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0,
+                 gamma=1.4, mesh_m_max=64):
+    return Request(MeshDesc(equation, nx, ny, p, FP64, 0, x0, x1, y0, y1, gamma, mesh_m_max),
+                   scheme, nsteps, dt, cfl, tol, m_min, m_max, check_every)
+
+
+def expdg_request_bytes(req: Request) -> int:
+    return lib().expdg_request_bytes(C.byref(req))
+
+
+def expdg_server_create(device: int, hbm_budget: int, max_active: int) -> int:
+    h = C.c_void_p()
+    _check(lib().expdg_server_create(device, hbm_budget, max_active, C.byref(h)))
+    return h.value
+
+
+def expdg_server_destroy(handle: int) -> None:
+    _check(lib().expdg_server_destroy(handle))
+
+
+def expdg_server_submit(handle, req: Request, q0) -> int:
+    """q0: contiguous float64 numpy array on the host (copied)."""
+    import numpy as np
+    q0 = np.ascontiguousarray(q0, dtype=np.float64)
+    rid = C.c_longlong()
+    _check(lib().expdg_server_submit(handle, C.byref(req), q0.ctypes.data, C.byref(rid)))
+    return rid.value
+
+
+def expdg_server_tick(handle, block=True) -> int:
+    n = C.c_int()
+    _check(lib().expdg_server_tick(handle, int(block), C.byref(n)))
+    return n.value
+
+
+def expdg_server_finished(handle, cap=4096):
+    ids = (C.c_longlong * cap)()
+    k = lib().expdg_server_finished(handle, ids, cap)
+    if k < 0:
+        _check(k)
+    return [ids[i] for i in range(k)]
+
+
+def expdg_server_poll(handle, rid):
+    info = RequestInfo()
+    _check(lib().expdg_server_poll(handle, rid, C.byref(info)))
+    st = info.stats
+    return {"state": info.state, "error": info.error, "steps_done": info.steps_done,
+            "dt": info.dt, "t_submit": info.t_submit, "t_admit": info.t_admit,
+            "t_done": info.t_done, "bytes": info.bytes,
+            "stats": {"substeps": st.substeps, "rejects": st.rejects,
+                      "krylov_iters": st.krylov_iters, "jvps": st.jvps,
+                      "breakdown": st.breakdown, "phi_calls": st.phi_calls,
+                      "rhs_calls": st.rhs_calls, "err_est": st.err_est}}
+
+
+def expdg_server_fetch(handle, rid, n):
+    import numpy as np
+    out = np.empty(n, dtype=np.float64)
+    _check(lib().expdg_server_fetch(handle, rid, out.ctypes.data))
+    return out
+
+
+def expdg_server_cancel(handle, rid):
+    _check(lib().expdg_server_cancel(handle, rid))
+
+
+def expdg_server_get_stats(handle):
+    s = ServerStats()
+    _check(lib().expdg_server_get_stats(handle, C.byref(s)))
+    return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+
+def expdg_server_sync(handle):
+    _check(lib().expdg_server_sync(handle))
+
+
+def expdg_server_clock(handle) -> float:
+    return lib().expdg_server_clock(handle)
+
+
+class Server:
+    """Owns an expdg solve server; methods forward to the C entry points."""
+
+    def __init__(self, hbm_budget=64 << 30, max_active=256, device=0):
+        self.handle = expdg_server_create(device, hbm_budget, max_active)
+        self._ndof = {}
+
+    def close(self):
+        if self.handle:
+            expdg_server_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, req: Request, q0) -> int:
+        rid = expdg_server_submit(self.handle, req, q0)
+        self._ndof[rid] = len(q0)
+        return rid
+
+    def tick(self, block=True) -> int:
+        return expdg_server_tick(self.handle, block)
+
+    def finished(self):
+        return expdg_server_finished(self.handle)
+
+    def poll(self, rid):
+        return expdg_server_poll(self.handle, rid)
+
+    def fetch(self, rid):
+        out = expdg_server_fetch(self.handle, rid, self._ndof[rid])
+        self._ndof.pop(rid, None)
+        return out
+
+    def cancel(self, rid):
+        expdg_server_cancel(self.handle, rid)
+        self._ndof.pop(rid, None)
+
+    def stats(self):
+        return expdg_server_get_stats(self.handle)
+
+    def sync(self):
+        expdg_server_sync(self.handle)
+
+    def clock(self) -> float:
+        return expdg_server_clock(self.handle)

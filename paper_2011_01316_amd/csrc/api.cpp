@@ -1,11 +1,8 @@
 // C ABI of the MI355X exponential-DG library: validation, mesh and workspace,
-// the adaptive Krylov controller, and the exponential steppers.  Every
-// arithmetic step on state-sized data runs in the HIP kernels of
+// the stand-alone operator, phi and step entry points, and live kernel timing.
+// Every arithmetic step on state-sized data runs in the HIP kernels of
 // dg_kernels.hip and krylov_kernels.hip; the host only makes the scalar
-// controller decisions (Section 2.3: adaptive Krylov evaluation of the phi
-// combination; the paper leaves the controller parameters unreported, so the
-// controller below is a fixed written specification shared with the test
-// oracle).
+// controller decisions (controller.h).  The solve server is in serve.cpp.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -18,15 +15,18 @@
 #include <type_traits>
 #include <vector>
 
-#include "internal.h"
+#include "controller.h"
+#include "runtime.h"
 
 using namespace expdg;
 
 // ---------------------------------------------------------------------------
-// errors
-namespace {
+// errors, shared helpers
+namespace expdg {
 
+namespace {
 thread_local char g_err[512] = "no error";
+}
 
 int fail(int code, const char *fmt, ...) {
     va_list ap;
@@ -36,47 +36,17 @@ int fail(int code, const char *fmt, ...) {
     return code;
 }
 
-#define HIPTRY(call)                                                                          \
-    do {                                                                                      \
-        hipError_t e_ = (call);                                                               \
-        if (e_ != hipSuccess)                                                                 \
-            return fail(EXPDG_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));        \
-    } while (0)
-
-#define TRY(call)                    \
-    do {                             \
-        int rc_ = (call);            \
-        if (rc_ != EXPDG_OK) return rc_; \
-    } while (0)
-
-// Restores the caller's current device on scope exit.
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = false;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        ok = hipSetDevice(dev) == hipSuccess;
-    }
-    ~DeviceGuard() {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
-
-// Two significant decimal digits, rounded up (step-size quantisation of the
-// controller, so that oracle and device take the same decisions).
 double round2(double x) {
     if (!(x > 0.0)) return x;
     const double s = std::pow(10.0, std::floor(std::log10(x)) - 1.0);
     return std::ceil(x / s) * s;
 }
 
-}  // namespace
-
-namespace expdg {
 LaunchEvents &next_launch_events() {
     thread_local LaunchEvents e;
     return e;
 }
+
 }  // namespace expdg
 
 // ---------------------------------------------------------------------------
@@ -157,49 +127,9 @@ int lgl_tables(int p, double *xi, double *w, double *D) {
 // ---------------------------------------------------------------------------
 // mesh
 
-struct expdg_mesh {
-    expdg_mesh_desc d;
-    int nvar, n1, Np, K, dim;
-    size_t n;       // ndof
-    size_t stride;  // elements between Krylov vectors (>= n + kMaxAug)
-    int ebytes;     // bytes per bulk element
-    double hx, hy, dxmin;
-    double xi[kMaxP + 1], w[kMaxP + 1], D[(kMaxP + 1) * (kMaxP + 1)];
+namespace expdg {
 
-    void *V = nullptr;           // (m_max+1) x stride bulk
-    void *vec[6] = {};           // bulk work vectors (stride each)
-    void *bq[3] = {};            // bulk copies of FP64 states (FP32_BULK only)
-    double *q2 = nullptr;        // FP64 stage state (EXPRB32)
-    KrylovDev kd{};
-    double *slots = nullptr;     // 2 x kSlotSize
-    double *dnorm = nullptr;     // 8
-    double *spart = nullptr;     // 1024 (wave-speed partials)
-    double *pin = nullptr;       // pinned host mirror
-    hipEvent_t ev[2] = {nullptr, nullptr};   // check results ready (side stream)
-    hipEvent_t evH[2] = {nullptr, nullptr};  // Hessenberg column ready (main stream)
-    hipStream_t side = nullptr;              // small exponentials run here
-    size_t bytes = 0;
-    std::vector<void *> allocs;
-
-    // live timing of one or more kernel classes
-    struct Prof {
-        bool on = false;
-        std::vector<hipEvent_t> ev;  // start/stop pairs
-        std::vector<double> bytes;   // algorithmic bytes per recorded launch
-        int used = 0;
-        long long launches = 0;
-        double ms = 0.0, total_bytes = 0.0;
-    } prof[EXPDG_K_NCLASSES];
-};
-
-namespace {
-
-constexpr int kPinSlots = 0;    // 2 x 8 doubles: err, s, singular, flags...
-constexpr int kPinNorms = 16;   // 8 doubles
-constexpr int kPinSpeed = 32;   // 1024 doubles
-constexpr int kPinSize = 32 + 1024;
-
-bool desc_ok(const expdg_mesh_desc *d, std::string *why) {
+bool desc_ok(const expdg_mesh_desc *d, const char **why) {
     if (!d) return *why = "desc is NULL", false;
     if (d->equation != EXPDG_BURGERS1D && d->equation != EXPDG_EULER2D)
         return *why = "equation must be EXPDG_BURGERS1D or EXPDG_EULER2D", false;
@@ -221,10 +151,38 @@ bool desc_ok(const expdg_mesh_desc *d, std::string *why) {
     return true;
 }
 
-struct Sizes {
-    size_t n, stride, total;
-    int ebytes;
-};
+namespace {
+
+// Lays the device buffers of a mesh out in one block (256-byte aligned);
+// assigns the pointers if base is given and returns the block size.
+size_t layout(expdg_mesh *m, const expdg_mesh_desc *d, size_t stride, int eb, char *base) {
+    size_t off = 0;
+    auto take = [&](auto *&ptr, size_t bytes) {
+        using P = std::remove_reference_t<decltype(ptr)>;
+        off = (off + 255) / 256 * 256;
+        if (base) ptr = (P)(base + off);
+        off += bytes;
+    };
+    const size_t vb = stride * eb;
+    take(m->V, (size_t)(d->m_max + 1) * vb);
+    for (auto &v : m->vec) take(v, vb);
+    if (d->precision == EXPDG_FP32_BULK)
+        for (auto &v : m->bq) take(v, vb);
+    take(m->q2, stride * 8);
+    take(m->kd.H, (size_t)(kMaxM + 1) * kMaxM * 8);
+    take(m->kd.S, (size_t)(kMaxM + 1) * 8);
+    take(m->kd.coefA, (size_t)(kMaxM + 1) * 8);
+    take(m->kd.coefB, (size_t)(kMaxM + 1) * 8);
+    take(m->kd.part, (size_t)kRedBlocks * (kMaxM + 1) * 8);
+    take(m->kd.res, 64 * 8);
+    take(m->kd.flags, 16);
+    take(m->slots, 2 * kSlotSize * 8);
+    take(m->dnorm, 8 * 8);
+    take(m->spart, 1024 * 8);
+    return (off + 255) / 256 * 256;
+}
+
+}  // namespace
 
 Sizes sizes_of(const expdg_mesh_desc *d) {
     Sizes s{};
@@ -234,43 +192,39 @@ Sizes sizes_of(const expdg_mesh_desc *d) {
     s.n = (size_t)nvar * d->nx * d->ny * Np;
     s.stride = (s.n + kMaxAug + 63) / 64 * 64;
     s.ebytes = (d->precision == EXPDG_FP64) ? 8 : 4;
-    size_t t = 0;
-    t += (size_t)(d->m_max + 1) * s.stride * s.ebytes;                      // V
-    t += 6 * s.stride * s.ebytes;                                          // work vectors
-    if (d->precision == EXPDG_FP32_BULK) t += 3 * s.stride * s.ebytes;     // bulk state copies
-    t += s.stride * 8;                                                     // q2
-    t += (size_t)(kMaxM + 1) * kMaxM * 8 + 3 * (kMaxM + 1) * 8 + 64;       // H, S, coefs
-    t += (size_t)kRedBlocks * (kMaxM + 1) * 8 + 64 * 8 + 16;               // part, res, flags
-    t += 2 * kSlotSize * 8 + 8 * 8 + 1024 * 8;                             // slots, norms, speed
-    s.total = t;
+    expdg_mesh probe;
+    s.total = layout(&probe, d, s.stride, s.ebytes, nullptr);
     return s;
 }
 
-template <typename P>
-int dalloc(expdg_mesh *m, P **ptr, size_t bytes) {
-    void *p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(EXPDG_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
-    }
-    m->allocs.push_back(p);
-    m->bytes += bytes;
-    *ptr = (P *)p;
-    return EXPDG_OK;
+void mesh_setup(expdg_mesh *m, const expdg_mesh_desc *d) {
+    m->d = *d;
+    m->dim = (d->equation == EXPDG_BURGERS1D) ? 1 : 2;
+    m->n1 = d->p + 1;
+    m->Np = (m->dim == 1) ? m->n1 : m->n1 * m->n1;
+    m->K = d->nx * d->ny;
+    m->nvar = (m->dim == 1) ? 1 : 4;
+    const Sizes sz = sizes_of(d);
+    m->n = sz.n;
+    m->stride = sz.stride;
+    m->ebytes = sz.ebytes;
+    m->bytes = sz.total;
+    m->hx = (d->x1 - d->x0) / d->nx;
+    m->hy = (m->dim == 2) ? (d->y1 - d->y0) / d->ny : 1.0;
+    lgl_tables(d->p, m->xi, m->w, m->D);
+    double dmin = 2.0;
+    for (int i = 0; i < d->p; ++i) dmin = std::min(dmin, m->xi[i + 1] - m->xi[i]);
+    m->dxmin = 0.5 * ((m->dim == 2) ? std::min(m->hx, m->hy) : m->hx) * dmin;
 }
 
-void release(expdg_mesh *m) {
-    for (void *p : m->allocs) (void)hipFree(p);
-    m->allocs.clear();
-    if (m->pin) (void)hipHostFree(m->pin);
-    for (auto &e : m->ev)
-        if (e) (void)hipEventDestroy(e);
-    for (auto &e : m->evH)
-        if (e) (void)hipEventDestroy(e);
-    if (m->side) (void)hipStreamDestroy(m->side);
-    for (auto &P : m->prof)
-        for (auto &e : P.ev) (void)hipEventDestroy(e);
+void mesh_carve(expdg_mesh *m, void *block) {
+    m->block = block;
+    layout(m, &m->d, m->stride, m->ebytes, (char *)block);
 }
+
+// ---- live timing ----
+
+namespace {
 
 constexpr int kProfPairs = 1024;
 
@@ -289,10 +243,11 @@ int prof_flush(expdg_mesh *m, int c) {
     return EXPDG_OK;
 }
 
+}  // namespace
+
 // The next kernel launch records the event pair as part of its own dispatch
 // (hipExtLaunchKernelGGL), so the interval is the kernel's execution.
-int prof_begin(expdg_mesh *m, int c, hipStream_t s) {
-    (void)s;
+int prof_begin(expdg_mesh *m, int c) {
     auto &P = m->prof[c];
     if (!P.on) return EXPDG_OK;
     if (P.used == kProfPairs) TRY(prof_flush(m, c));
@@ -300,8 +255,7 @@ int prof_begin(expdg_mesh *m, int c, hipStream_t s) {
     return EXPDG_OK;
 }
 
-int prof_end(expdg_mesh *m, int c, hipStream_t s, double bytes) {
-    (void)s;
+int prof_end(expdg_mesh *m, int c, double bytes) {
     auto &P = m->prof[c];
     if (!P.on) return EXPDG_OK;
     next_launch_events() = LaunchEvents{};
@@ -310,33 +264,36 @@ int prof_end(expdg_mesh *m, int c, hipStream_t s, double bytes) {
     return EXPDG_OK;
 }
 
-template <typename T>
-OpArgs<T> op_args(const expdg_mesh *m) {
-    OpArgs<T> a{};
-    a.K = m->K;
-    a.nx = m->d.nx;
-    a.ny = m->d.ny;
-    a.rhx = (T)(2.0 / m->hx);
-    a.rhy = (T)(2.0 / m->hy);
-    a.lift = (T)(1.0 / m->w[0]);
-    a.gamma = (T)m->d.gamma;
-    for (int k = 0; k < m->n1 * m->n1; ++k) a.D[k] = (T)m->D[k];
-    a.eta = 1.0;
-    return a;
+}  // namespace expdg
+
+namespace {
+
+void release(expdg_mesh *m) {
+    if (m->owns_block && m->block) (void)hipFree(m->block);
+    m->block = nullptr;
+    if (m->owns_pin && m->pin) (void)hipHostFree(m->pin);
+    m->pin = nullptr;
+    for (auto &e : m->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto &e : m->evH)
+        if (e) (void)hipEventDestroy(e);
+    if (m->side) (void)hipStreamDestroy(m->side);
+    for (auto &P : m->prof)
+        for (auto &e : P.ev) (void)hipEventDestroy(e);
 }
 
 }  // namespace
 
 extern "C" size_t expdg_workspace_bytes(const expdg_mesh_desc *d) {
-    std::string why;
+    const char *why = "";
     if (!desc_ok(d, &why)) return 0;
     return sizes_of(d).total;
 }
 
 extern "C" int expdg_mesh_create(const expdg_mesh_desc *d, expdg_mesh **out) {
-    std::string why;
+    const char *why = "";
     if (!out) return fail(EXPDG_EINVAL, "out is NULL");
-    if (!desc_ok(d, &why)) return fail(EXPDG_EINVAL, "invalid mesh description: %s", why.c_str());
+    if (!desc_ok(d, &why)) return fail(EXPDG_EINVAL, "invalid mesh description: %s", why);
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
         return fail(EXPDG_EDEVICE, "no HIP device available");
@@ -346,46 +303,28 @@ extern "C" int expdg_mesh_create(const expdg_mesh_desc *d, expdg_mesh **out) {
 
     expdg_mesh *m = new (std::nothrow) expdg_mesh();
     if (!m) return fail(EXPDG_ENOMEM, "host allocation failed");
-    m->d = *d;
-    m->dim = (d->equation == EXPDG_BURGERS1D) ? 1 : 2;
-    m->n1 = d->p + 1;
-    m->Np = (m->dim == 1) ? m->n1 : m->n1 * m->n1;
-    m->K = d->nx * d->ny;
-    m->nvar = (m->dim == 1) ? 1 : 4;
-    const Sizes sz = sizes_of(d);
-    m->n = sz.n;
-    m->stride = sz.stride;
-    m->ebytes = sz.ebytes;
-    m->hx = (d->x1 - d->x0) / d->nx;
-    m->hy = (m->dim == 2) ? (d->y1 - d->y0) / d->ny : 1.0;
-    lgl_tables(d->p, m->xi, m->w, m->D);
-    double dmin = 2.0;
-    for (int i = 0; i < d->p; ++i) dmin = std::min(dmin, m->xi[i + 1] - m->xi[i]);
-    m->dxmin = 0.5 * ((m->dim == 2) ? std::min(m->hx, m->hy) : m->hx) * dmin;
+    mesh_setup(m, d);
 
     int rc = EXPDG_OK;
-    const size_t vb = m->stride * m->ebytes;
-    auto chk = [&](int r) {
-        if (rc == EXPDG_OK && r != EXPDG_OK) rc = r;
-    };
-    chk(dalloc(m, &m->V, (size_t)(d->m_max + 1) * vb));
-    for (auto &v : m->vec) chk(dalloc(m, &v, vb));
-    if (d->precision == EXPDG_FP32_BULK)
-        for (auto &v : m->bq) chk(dalloc(m, &v, vb));
-    chk(dalloc(m, &m->q2, m->stride * 8));
-    chk(dalloc(m, &m->kd.H, (size_t)(kMaxM + 1) * kMaxM * 8));
-    chk(dalloc(m, &m->kd.S, (size_t)(kMaxM + 1) * 8));
-    chk(dalloc(m, &m->kd.coefA, (size_t)(kMaxM + 1) * 8));
-    chk(dalloc(m, &m->kd.coefB, (size_t)(kMaxM + 1) * 8));
-    chk(dalloc(m, &m->kd.part, (size_t)kRedBlocks * (kMaxM + 1) * 8));
-    chk(dalloc(m, &m->kd.res, 64 * 8));
-    chk(dalloc(m, &m->kd.flags, 16));
-    chk(dalloc(m, &m->slots, 2 * kSlotSize * 8));
-    chk(dalloc(m, &m->dnorm, 8 * 8));
-    chk(dalloc(m, &m->spart, 1024 * 8));
-    if (rc == EXPDG_OK && hipHostMalloc((void **)&m->pin, kPinSize * 8) != hipSuccess) {
-        m->pin = nullptr;
-        rc = fail(EXPDG_ENOMEM, "pinned host allocation failed");
+    void *block = nullptr;
+    if (hipMalloc(&block, m->bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        rc = fail(EXPDG_ENOMEM, "hipMalloc of %zu bytes failed", m->bytes);
+    } else {
+        m->owns_block = true;
+        mesh_carve(m, block);
+    }
+    // pinned mirror, also written by the check kernels through its device address
+    if (rc == EXPDG_OK) {
+        if (hipHostMalloc((void **)&m->pin, kPinSize * 8,
+                          hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+            m->pin = nullptr;
+            rc = fail(EXPDG_ENOMEM, "pinned host allocation failed");
+        } else {
+            m->owns_pin = true;
+            if (hipHostGetDevicePointer((void **)&m->pin_dev, m->pin, 0) != hipSuccess)
+                rc = fail(EXPDG_EDEVICE, "hipHostGetDevicePointer failed");
+        }
     }
     for (auto &e : m->ev)
         if (rc == EXPDG_OK && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
@@ -397,9 +336,8 @@ extern "C" int expdg_mesh_create(const expdg_mesh_desc *d, expdg_mesh **out) {
     if (rc == EXPDG_OK && hipStreamCreateWithFlags(&m->side, hipStreamNonBlocking) != hipSuccess)
         rc = fail(EXPDG_EDEVICE, "hipStreamCreate failed");
     if (rc == EXPDG_OK) {
-        // zero the whole Krylov block once (padding stays zero)
-        if (hipMemset(m->V, 0, (size_t)(d->m_max + 1) * vb) != hipSuccess ||
-            hipMemset(m->kd.flags, 0, 16) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+        // zero the whole workspace once (vector padding stays zero)
+        if (hipMemset(m->block, 0, m->bytes) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
             rc = fail(EXPDG_EDEVICE, "workspace initialisation failed");
     }
     if (rc != EXPDG_OK) {
@@ -457,23 +395,6 @@ extern "C" int expdg_lgl(int p, double *xi, double *w, double *D) {
 // ---------------------------------------------------------------------------
 // operators
 
-namespace {
-
-template <typename T>
-int apply_op(expdg_mesh *m, bool jvp, const T *q, const T *v, T *out, hipStream_t s) {
-    OpArgs<T> a = op_args<T>(m);
-    a.q = q;
-    a.v = v;
-    a.out = out;
-    const int cls = jvp ? EXPDG_K_LINEAR : EXPDG_K_RESIDUAL;
-    TRY(prof_begin(m, cls, s));
-    HIPTRY(launch_dg_op(m->d.equation, m->d.p, jvp, a, s));
-    TRY(prof_end(m, cls, s, (double)(jvp ? 3 : 2) * m->n * m->ebytes));
-    return EXPDG_OK;
-}
-
-}  // namespace
-
 extern "C" int expdg_rhs(expdg_mesh *m, const void *q, void *r, void *stream) {
     if (!m || !q || !r) return fail(EXPDG_EINVAL, "NULL argument");
     if (q == r) return fail(EXPDG_EINVAL, "q and r must not alias");
@@ -511,9 +432,9 @@ extern "C" int expdg_max_speed(expdg_mesh *m, const double *q, double *cmax, voi
 }
 
 // ---------------------------------------------------------------------------
-// phi combinations
+// phi combinations and steps: the controller driven by the immediate executor
 
-namespace {
+namespace expdg {
 
 int check_opts(const expdg_mesh *m, const expdg_krylov_opts *o) {
     if (!o) return fail(EXPDG_EINVAL, "options are NULL");
@@ -543,304 +464,113 @@ void log_sub(expdg_krylov_stats *st, int mm, int last, double dtau) {
     st->log_len += 1;
 }
 
-// A check (small exponential + error) enqueued but not yet read.
-struct Check {
-    int j = 0;       // Krylov dimension
-    int slot = 0;    // device / pinned slot
+}  // namespace expdg
+
+namespace {
+
+// Launches everything at once on stream s; a check's small exponential runs on
+// the mesh's side stream behind the Hessenberg column it needs, overlapping
+// the next Arnoldi step, and is read back one step later.
+template <typename T>
+struct DirectExec {
+    hipStream_t s;
+
+    hipStream_t stream() const { return s; }
+
+    int enqueue_check(expdg_mesh *m, const CheckReq &r, Check *c) {
+        c->j = r.j;
+        c->slot = r.slot;
+        HIPTRY(hipEventRecord(m->evH[c->slot], s));
+        HIPTRY(hipStreamWaitEvent(m->side, m->evH[c->slot], 0));
+        const KrylovDev &kd = m->kd;
+        ExpmItem it{kd.H,
+                    kd.S,
+                    kd.res,
+                    kd.flags,
+                    m->slots + c->slot * kSlotSize,
+                    m->pin_dev + kPinSlots + c->slot * 8,
+                    r.dtau,
+                    r.j};
+        TRY(prof_begin(m, EXPDG_K_SMALLEXPM));
+        HIPTRY(launch_hess_expm(it, m->side));
+        TRY(prof_end(m, EXPDG_K_SMALLEXPM, 0.0));
+        HIPTRY(hipEventRecord(m->ev[c->slot], m->side));
+        return EXPDG_OK;
+    }
+
+    int iterate_now(expdg_mesh *m, const OpArgs<T> &a, int j, int naug_nz, const CheckReq *cr,
+                    Check *c) {
+        const size_t n = m->n, L = n + (size_t)a.naug, stride = m->stride;
+        const RowPartition rp = row_partition(L);
+        const KrylovDev &kd = m->kd;
+        const T *V = (const T *)m->V;
+        T *w = a.out;
+        const int col = j - 1;
+        const double eb = (double)sizeof(T);
+        TRY(prof_begin(m, EXPDG_K_LINEAR));
+        HIPTRY(launch_dg_op(m->d.equation, m->d.p, true, a, s));
+        TRY(prof_end(m, EXPDG_K_LINEAR, (double)(3 + naug_nz) * n * eb));
+        // classical Gram-Schmidt, two passes, then the norm
+        const double fin_bytes = 8.0 * rp.nrb * j;
+        TRY(prof_begin(m, EXPDG_K_GS_DOTS));
+        HIPTRY(launch_gs_dots<T>(V, stride, j, w, L, rp, kd.part, kd.S, kd.H, col, 0, kd.coefA, s));
+        TRY(prof_end(m, EXPDG_K_GS_DOTS, (double)(j + 1) * L * eb));
+        TRY(prof_begin(m, EXPDG_K_GS_FINISH));
+        HIPTRY(launch_gs_finish_dots(kd.part, j, rp, kd.S, kd.H, col, 0, kd.coefA, s));
+        TRY(prof_end(m, EXPDG_K_GS_FINISH, fin_bytes));
+        // (j > 32: a plain update then a dot pass, 2j + 3 vectors of traffic)
+        TRY(prof_begin(m, EXPDG_K_GS_UPDATE_DOTS));
+        HIPTRY(launch_gs_update_dots<T>(V, stride, j, kd.coefA, w, L, rp, kd.part, kd.S, kd.H, col,
+                                        kd.coefB, s));
+        TRY(prof_end(m, EXPDG_K_GS_UPDATE_DOTS, (double)(j <= 32 ? j + 2 : 2 * j + 3) * L * eb));
+        TRY(prof_begin(m, EXPDG_K_GS_FINISH));
+        HIPTRY(launch_gs_finish_dots(kd.part, j, rp, kd.S, kd.H, col, 1, kd.coefB, s));
+        TRY(prof_end(m, EXPDG_K_GS_FINISH, fin_bytes));
+        TRY(prof_begin(m, EXPDG_K_GS_UPDATE_NORM));
+        HIPTRY(launch_gs_update_norm<T>(V, stride, j, kd.coefB, w, L, rp, kd.part, kd.H, kd.S, col,
+                                        kd.flags, kd.res, s));
+        TRY(prof_end(m, EXPDG_K_GS_UPDATE_NORM, (double)(j + 2) * L * eb));
+        TRY(prof_begin(m, EXPDG_K_GS_FINISH));
+        HIPTRY(launch_gs_finish_norm(kd.part, rp, kd.H, kd.S, col, kd.flags, kd.res, s));
+        TRY(prof_end(m, EXPDG_K_GS_FINISH, 8.0 * rp.nrb));
+        if (cr) TRY(enqueue_check(m, *cr, c));
+        return EXPDG_OK;
+    }
+
+    Ready iterate(expdg_mesh *m, const OpArgs<T> &a, int j, int naug_nz, const CheckReq *cr,
+                  Check *c) {
+        return Ready{iterate_now(m, a, j, naug_nz, cr, c)};
+    }
+    Ready check(expdg_mesh *m, const CheckReq &r, Check *c) { return Ready{enqueue_check(m, r, c)}; }
+    Ready wait_check(expdg_mesh *m, const Check &c) { return Ready{sync_event(m->ev[c.slot])}; }
+    int after_check(expdg_mesh *m, const Check &c) {
+        HIPTRY(hipStreamWaitEvent(s, m->ev[c.slot], 0));
+        return EXPDG_OK;
+    }
+    Ready readback(expdg_mesh *) { return Ready{sync_stream(s)}; }
+    Ready finish(expdg_mesh *m) {
+        // no speculative check left running on the side stream
+        int rc = sync_stream(m->side);
+        if (rc == EXPDG_OK) rc = sync_stream(s);
+        return Ready{rc};
+    }
+
+    static int sync_event(hipEvent_t e) {
+        HIPTRY(hipEventSynchronize(e));
+        return EXPDG_OK;
+    }
+    static int sync_stream(hipStream_t st) {
+        HIPTRY(hipStreamSynchronize(st));
+        return EXPDG_OK;
+    }
 };
 
-template <typename T>
-int phi_impl(expdg_mesh *m, const T *qref, double tau, int p, const T *const *b, T *out,
-             const expdg_krylov_opts *o, expdg_krylov_stats *st, int *fpos, hipStream_t s) {
-    const size_t n = m->n, L = n + (size_t)p;
-    const size_t stride = m->stride;
-    T *V = (T *)m->V;
-    KrylovDev &kd = m->kd;
-    const bool forced = o->n_forced > 0;
-    const RowPartition rp = row_partition(L);
-    if (st) st->phi_calls += 1;
-
-    // 1. scaling and 2. tolerance: norms of b_0..b_p
-    const T *bx[4] = {nullptr, nullptr, nullptr, nullptr};
-    for (int k = 0; k <= p; ++k) bx[k] = b ? b[k] : nullptr;
-    HIPTRY(launch_norms<T>(bx, p + 1, n, kd.part, m->dnorm, s));
-    HIPTRY(hipMemcpyAsync(m->pin + kPinNorms, m->dnorm, (p + 1) * 8, hipMemcpyDeviceToHost, s));
-    HIPTRY(hipStreamSynchronize(s));
-    double bn[4] = {0, 0, 0, 0};
-    for (int k = 0; k <= p; ++k) bn[k] = bx[k] ? m->pin[kPinNorms + k] : 0.0;
-    double bmax = 0.0;
-    for (int k = 1; k <= p; ++k) bmax = std::max(bmax, bn[k]);
-    const double eta = (bmax > 0.0) ? std::ldexp(1.0, -(int)std::lround(std::log2(bmax))) : 1.0;
-    double nu = bn[0], tk = 1.0, fact = 1.0;
-    for (int k = 1; k <= p; ++k) {
-        tk *= tau;
-        fact *= k;
-        nu += tk * bn[k] / fact;
-    }
-    if (!std::isfinite(nu)) return fail(EXPDG_ENONFINITE, "non-finite input norm");
-    if (nu == 0.0 || tau == 0.0) {
-        if (bx[0])
-            HIPTRY(launch_copy(bx[0], out, n, s));
-        else
-            HIPTRY(launch_fill<T>(out, 0.0, n, s));
-        HIPTRY(hipStreamSynchronize(s));
-        return EXPDG_OK;
-    }
-    const double tol_abs = o->tol * nu;
-
-    // z = [b_0; 0, ..., 0, 1/eta] lives in V_0
-    if (bx[0])
-        HIPTRY(launch_copy(bx[0], V, n, s));
-    else
-        HIPTRY(launch_fill<T>(V, 0.0, n, s));
-    if (p > 0) HIPTRY(launch_set_tail<T>(V + n, p, 1.0 / eta, s));
-    HIPTRY(launch_fill<int>(kd.flags, 0.0, 4, s));
-
-    OpArgs<T> a = op_args<T>(m);
-    a.q = qref;
-    a.eta = eta;
-    a.naug = p;
-    int naug_nz = 0;
-    for (int k = 1; k <= p; ++k) {
-        a.aug[k - 1] = bx[p + 1 - k];
-        naug_nz += bx[p + 1 - k] ? 1 : 0;
-    }
-    const double eb = (double)sizeof(T);
-
-    int nchecks = 0;
-    // enqueue the small exponential for dimension j and substep dtau
-    // The small exponential of check j runs on the side stream once the
-    // Hessenberg column j-1 is complete on the main stream, overlapping the
-    // next Arnoldi iteration; its result is read back one iteration later.
-    hipStream_t side = m->side;
-    auto enqueue_check = [&](int j, double dtau, Check *c) -> int {
-        c->j = j;
-        c->slot = (nchecks++) & 1;
-        double *slot = m->slots + c->slot * kSlotSize;
-        HIPTRY(hipEventRecord(m->evH[c->slot], s));
-        HIPTRY(hipStreamWaitEvent(side, m->evH[c->slot], 0));
-        TRY(prof_begin(m, EXPDG_K_SMALLEXPM, side));
-        HIPTRY(launch_hess_expm(kd.H, j, dtau, kd.S, kd.res, slot, side));
-        TRY(prof_end(m, EXPDG_K_SMALLEXPM, side, 0.0));
-        HIPTRY(hipMemcpyAsync(m->pin + kPinSlots + c->slot * 8, slot, 4 * 8,
-                              hipMemcpyDeviceToHost, side));
-        HIPTRY(hipMemcpyAsync((char *)(m->pin + kPinSlots + c->slot * 8 + 4), kd.flags, 2 * 4,
-                              hipMemcpyDeviceToHost, side));
-        HIPTRY(hipEventRecord(m->ev[c->slot], side));
-        return EXPDG_OK;
-    };
-    struct CheckResult {
-        double err;
-        int singular, brk, nonfinite;
-    };
-    auto read_check = [&](const Check &c, CheckResult *r) -> int {
-        HIPTRY(hipEventSynchronize(m->ev[c.slot]));
-        const double *pv = m->pin + kPinSlots + c.slot * 8;
-        r->err = pv[kSlotErr];
-        r->singular = pv[2] != 0.0;
-        int fl[2];
-        std::memcpy(fl, pv + 4, 8);
-        r->brk = fl[0];
-        r->nonfinite = fl[1];
-        return EXPDG_OK;
-    };
-
-    double t_done = 0.0, dtau = tau;
-    bool reaches_end = true;
-    while (true) {
-        int m_target = o->m_max;
-        double dt_sub = dtau;
-        bool sub_last = reaches_end;
-        if (forced) {
-            if (*fpos >= o->n_forced) return fail(EXPDG_EINVAL, "forced schedule exhausted");
-            m_target = o->forced[*fpos].m;
-            dt_sub = o->forced[*fpos].dtau;
-            sub_last = o->forced[*fpos].last != 0;
-        }
-        // beta = ||z||, S[0] = 1/beta
-        TRY(prof_begin(m, EXPDG_K_GS_UPDATE_NORM, s));
-        HIPTRY(launch_gs_update_norm<T>(V, stride, 0, nullptr, V, L, rp, kd.part, kd.H, kd.S, -1,
-                                        kd.flags, kd.res, s));
-        TRY(prof_end(m, EXPDG_K_GS_UPDATE_NORM, s, (double)L * eb));
-        TRY(prof_begin(m, EXPDG_K_GS_FINISH, s));
-        HIPTRY(launch_gs_finish_norm(kd.part, rp, kd.H, kd.S, -1, kd.flags, kd.res, s));
-        TRY(prof_end(m, EXPDG_K_GS_FINISH, s, 8.0 * rp.nrb));
-        HIPTRY(launch_fill<double>(kd.H, 0.0, (size_t)(kMaxM + 1) * kMaxM, s));
-
-        int j_acc = 0;
-        double err = 0.0;
-        Check pending, acc_check;
-        bool have_pending = false;
-        for (int j = 1; j <= m_target; ++j) {
-            const int col = j - 1;
-            T *vin = V + (size_t)(j - 1) * stride;
-            T *w = V + (size_t)j * stride;
-            // w = S[j-1] * Aug(u_{j-1})
-            a.v = vin;
-            a.out = w;
-            a.vtail = vin + n;
-            a.otail = w + n;
-            a.vscale = kd.S + (j - 1);
-            TRY(prof_begin(m, EXPDG_K_LINEAR, s));
-            HIPTRY(launch_dg_op(m->d.equation, m->d.p, true, a, s));
-            TRY(prof_end(m, EXPDG_K_LINEAR, s, (double)(3 + naug_nz) * n * eb));
-            // classical Gram-Schmidt, two passes, then the norm
-            const double fin_bytes = 8.0 * rp.nrb * j;
-            TRY(prof_begin(m, EXPDG_K_GS_DOTS, s));
-            HIPTRY(launch_gs_dots<T>(V, stride, j, w, L, rp, kd.part, kd.S, kd.H, col, 0, kd.coefA,
-                                     s));
-            TRY(prof_end(m, EXPDG_K_GS_DOTS, s, (double)(j + 1) * L * eb));
-            TRY(prof_begin(m, EXPDG_K_GS_FINISH, s));
-            HIPTRY(launch_gs_finish_dots(kd.part, j, rp, kd.S, kd.H, col, 0, kd.coefA, s));
-            TRY(prof_end(m, EXPDG_K_GS_FINISH, s, fin_bytes));
-            // (j > 32: a plain update then a dot pass, 2j + 3 vectors of traffic)
-            TRY(prof_begin(m, EXPDG_K_GS_UPDATE_DOTS, s));
-            HIPTRY(launch_gs_update_dots<T>(V, stride, j, kd.coefA, w, L, rp, kd.part, kd.S, kd.H,
-                                            col, kd.coefB, s));
-            TRY(prof_end(m, EXPDG_K_GS_UPDATE_DOTS, s,
-                         (double)(j <= 32 ? j + 2 : 2 * j + 3) * L * eb));
-            TRY(prof_begin(m, EXPDG_K_GS_FINISH, s));
-            HIPTRY(launch_gs_finish_dots(kd.part, j, rp, kd.S, kd.H, col, 1, kd.coefB, s));
-            TRY(prof_end(m, EXPDG_K_GS_FINISH, s, fin_bytes));
-            TRY(prof_begin(m, EXPDG_K_GS_UPDATE_NORM, s));
-            HIPTRY(launch_gs_update_norm<T>(V, stride, j, kd.coefB, w, L, rp, kd.part, kd.H, kd.S,
-                                            col, kd.flags, kd.res, s));
-            TRY(prof_end(m, EXPDG_K_GS_UPDATE_NORM, s, (double)(j + 2) * L * eb));
-            TRY(prof_begin(m, EXPDG_K_GS_FINISH, s));
-            HIPTRY(launch_gs_finish_norm(kd.part, rp, kd.H, kd.S, col, kd.flags, kd.res, s));
-            TRY(prof_end(m, EXPDG_K_GS_FINISH, s, 8.0 * rp.nrb));
-            if (st) {
-                st->krylov_iters += 1;
-                st->jvps += 1;
-            }
-            if (forced) continue;
-
-            const bool is_check =
-                j == o->m_max || (j >= o->m_min && (j - o->m_min) % o->check_every == 0);
-            Check cur;
-            if (is_check) TRY(enqueue_check(j, dt_sub, &cur));
-            // look one check behind: the device works on iteration j meanwhile
-            auto decide = [&](const Check &c, bool *done) -> int {
-                CheckResult r;
-                TRY(read_check(c, &r));
-                *done = false;
-                if (r.nonfinite) return fail(EXPDG_ENONFINITE, "non-finite Krylov norm");
-                if (r.brk > 0) {
-                    // happy breakdown: exact, take the whole remaining interval
-                    dt_sub = tau - t_done;
-                    sub_last = true;
-                    Check bc;
-                    TRY(enqueue_check(r.brk, dt_sub, &bc));
-                    CheckResult br;
-                    TRY(read_check(bc, &br));
-                    if (br.singular) return fail(EXPDG_ENONFINITE, "singular Pade denominator");
-                    if (st) st->breakdown += 1;
-                    err = 0.0;
-                    j_acc = r.brk;
-                    acc_check = bc;
-                    *done = true;
-                    return EXPDG_OK;
-                }
-                if (r.singular) return fail(EXPDG_ENONFINITE, "singular Pade denominator");
-                if (!std::isfinite(r.err)) return fail(EXPDG_ENONFINITE, "non-finite error estimate");
-                if (r.err <= tol_abs * dt_sub / tau) {
-                    err = r.err;
-                    j_acc = c.j;
-                    acc_check = c;
-                    *done = true;
-                    return EXPDG_OK;
-                }
-                if (c.j == o->m_max) {
-                    // shrink on the same basis until it passes
-                    double e = r.err;
-                    Check sc = c;
-                    while (e > tol_abs * dt_sub / tau) {
-                        const double ratio = tol_abs * dt_sub / tau / e;
-                        const double fac = std::max(0.2, 0.9 * std::pow(ratio, 1.0 / o->m_max));
-                        dt_sub = round2(dt_sub * fac);
-                        sub_last = false;
-                        if (st) st->rejects += 1;
-                        if (!(dt_sub > 1e-12 * tau))
-                            return fail(EXPDG_ENOCONV, "Krylov substep below its floor");
-                        TRY(enqueue_check(c.j, dt_sub, &sc));
-                        CheckResult sr;
-                        TRY(read_check(sc, &sr));
-                        if (sr.singular || !std::isfinite(sr.err))
-                            return fail(EXPDG_ENONFINITE, "non-finite error estimate");
-                        e = sr.err;
-                    }
-                    err = e;
-                    j_acc = c.j;
-                    acc_check = sc;
-                    *done = true;
-                }
-                return EXPDG_OK;
-            };
-            bool done = false;
-            if (have_pending) {
-                TRY(decide(pending, &done));
-                have_pending = false;
-                if (done) break;
-            }
-            if (is_check) {
-                pending = cur;
-                have_pending = true;
-            }
-            if (j == m_target && have_pending) {
-                TRY(decide(pending, &done));
-                have_pending = false;
-                if (done) break;
-            }
-        }
-        if (forced) {
-            Check fc;
-            TRY(enqueue_check(m_target, dt_sub, &fc));
-            acc_check = fc;
-            j_acc = m_target;
-            err = 0.0;
-        }
-        if (j_acc == 0) return fail(EXPDG_ENOCONV, "Krylov controller made no decision");
-
-        // accept: z <- beta V_j F_{1:j,1} (after the check's side-stream work)
-        HIPTRY(hipStreamWaitEvent(s, m->ev[acc_check.slot], 0));
-        TRY(prof_begin(m, EXPDG_K_COMBINE, s));
-        HIPTRY(launch_combine<T>(V, stride, j_acc, m->slots + acc_check.slot * kSlotSize + kSlotCoef,
-                                 V, L, s));
-        TRY(prof_end(m, EXPDG_K_COMBINE, s, (double)(j_acc + 1) * L * eb));
-        t_done += dt_sub;
-        log_sub(st, j_acc, sub_last ? 1 : 0, dt_sub);
-        if (st) st->err_est = err;
-        if (forced) *fpos += 1;
-        if (sub_last) break;
-        if (forced) continue;
-
-        const double ratio = (err > 0.0) ? tol_abs * dt_sub / tau / err : 0.0;
-        double fac = (err > 0.0) ? 0.9 * std::pow(ratio, 1.0 / j_acc) : 5.0;
-        fac = std::min(5.0, std::max(1.0, fac));
-        const double cand = round2(dt_sub * fac);
-        const double rem = tau - t_done;
-        if (!(rem > 1e-15 * tau)) break;
-        if (cand >= rem) {
-            dtau = rem;
-            reaches_end = true;
-        } else {
-            dtau = cand;
-            reaches_end = false;
-        }
-    }
-    HIPTRY(launch_copy(V, out, n, s));
-    HIPTRY(hipStreamSynchronize(side));  // no speculative check left running
-    if (forced) {
-        // a forced run reads nothing back: surface non-finite values here
-        HIPTRY(hipMemcpyAsync(m->pin + kPinSlots, kd.flags, 8, hipMemcpyDeviceToHost, s));
-    }
-    HIPTRY(hipStreamSynchronize(s));
-    if (forced) {
-        int fl[2];
-        std::memcpy(fl, m->pin + kPinSlots, 8);
-        if (fl[1]) return fail(EXPDG_ENONFINITE, "non-finite Krylov norm");
-    }
-    return EXPDG_OK;
+// Runs a controller task to completion (the immediate executor never suspends).
+int run_now(Task<int> t) {
+    if (!t.valid()) return fail(EXPDG_ENOMEM, "coroutine frame allocation failed");
+    t.start();
+    if (!t.done()) return fail(EXPDG_EDEVICE, "controller suspended under the immediate executor");
+    return t.result();
 }
 
 }  // namespace
@@ -858,84 +588,15 @@ extern "C" int expdg_phi_krylov(expdg_mesh *m, const void *qref, double tau, int
     DeviceGuard g(m->d.device);
     int fpos = 0;
     hipStream_t st = (hipStream_t)stream;
-    if (m->d.precision == EXPDG_FP64)
-        return phi_impl<double>(m, (const double *)qref, tau, p, (const double *const *)b,
-                                (double *)w, o, s, &fpos, st);
-    return phi_impl<float>(m, (const float *)qref, tau, p, (const float *const *)b, (float *)w, o,
-                           s, &fpos, st);
-}
-
-// ---------------------------------------------------------------------------
-// steppers (EPI2, EXPRB32: footnotes of Section 5.1; EPI3 after Tokman)
-
-namespace {
-
-template <typename T>
-int step_impl(expdg_mesh *m, int scheme, double dt, double *q, double *q_prev, int have_prev,
-              const expdg_krylov_opts *o, expdg_krylov_stats *st, hipStream_t s) {
-    const size_t n = m->n;
-    const bool bulk = !std::is_same<T, double>::value;
-    T *Rn = (T *)m->vec[0], *Rp = (T *)m->vec[1], *d = (T *)m->vec[2], *Ld = (T *)m->vec[3],
-      *w = (T *)m->vec[4], *w2 = (T *)m->vec[5];
-    // operator views of the FP64 states
-    auto view = [&](double *x, int k) -> T * {
-        if (!bulk) return (T *)x;
-        T *y = (T *)m->bq[k];
-        (void)launch_convert(x, (float *)y, n, s);  // errors surface via hipGetLastError
-        return y;
-    };
-    int fpos = 0;
-    T *qb = view(q, 0);
-    HIPTRY(hipGetLastError());
-    TRY(apply_op<T>(m, false, qb, nullptr, Rn, s));
-    if (st) st->rhs_calls += 1;
-
-    if (scheme == EXPDG_EPI2 || (scheme == EXPDG_EPI3 && !(q_prev && have_prev))) {
-        const T *b[2] = {nullptr, Rn};
-        TRY(phi_impl<T>(m, qb, dt, 1, b, w, o, st, &fpos, s));
-        if (q_prev) HIPTRY(launch_copy(q, q_prev, n, s));
-        HIPTRY(launch_add_to<T>(q, w, n, s));
-    } else if (scheme == EXPDG_EPI3) {
-        T *qpb = view(q_prev, 1);
-        HIPTRY(hipGetLastError());
-        TRY(apply_op<T>(m, false, qpb, nullptr, Rp, s));
-        HIPTRY((launch_lincomb<T, T>(d, 1.0, qpb, -1.0, qb, 0.0, nullptr, n, s)));
-        TRY(apply_op<T>(m, true, qb, d, Ld, s));
-        if (st) {
-            st->rhs_calls += 1;
-            st->jvps += 1;
-        }
-        const double c = 2.0 / (3.0 * dt);
-        HIPTRY((launch_lincomb<T, T>(d, c, Rp, -c, Rn, -c, Ld, n, s)));  // b_2 into d
-        const T *b[3] = {nullptr, Rn, d};
-        TRY(phi_impl<T>(m, qb, dt, 2, b, w, o, st, &fpos, s));
-        HIPTRY(launch_copy(q, q_prev, n, s));
-        HIPTRY(launch_add_to<T>(q, w, n, s));
-    } else {  // EXPRB32
-        const T *b1[2] = {nullptr, Rn};
-        TRY(phi_impl<T>(m, qb, dt, 1, b1, w, o, st, &fpos, s));
-        HIPTRY(launch_add_mixed<T>(m->q2, q, w, n, s));  // q2 = q^n + w1
-        T *q2b = view(m->q2, 2);
-        HIPTRY(hipGetLastError());
-        TRY(apply_op<T>(m, false, q2b, nullptr, Rp, s));  // R(q2)
-        HIPTRY((launch_lincomb<T, T>(d, 1.0, q2b, -1.0, qb, 0.0, nullptr, n, s)));
-        TRY(apply_op<T>(m, true, qb, d, Ld, s));
-        if (st) {
-            st->rhs_calls += 1;
-            st->jvps += 1;
-        }
-        const double c = 2.0 / (dt * dt);
-        HIPTRY((launch_lincomb<T, T>(d, c, Rp, -c, Rn, -c, Ld, n, s)));  // b_3 into d
-        const T *b[4] = {nullptr, nullptr, nullptr, d};
-        TRY(phi_impl<T>(m, qb, dt, 3, b, w2, o, st, &fpos, s));
-        if (q_prev) HIPTRY(launch_copy(q, q_prev, n, s));
-        HIPTRY(launch_add_mixed<T>(q, m->q2, w2, n, s));
+    if (m->d.precision == EXPDG_FP64) {
+        DirectExec<double> x{st};
+        return run_now(phi_co<double>(x, m, (const double *)qref, tau, p, (const double *const *)b,
+                                      (double *)w, o, s, &fpos));
     }
-    HIPTRY(hipStreamSynchronize(s));
-    return EXPDG_OK;
+    DirectExec<float> x{st};
+    return run_now(phi_co<float>(x, m, (const float *)qref, tau, p, (const float *const *)b,
+                                 (float *)w, o, s, &fpos));
 }
-
-}  // namespace
 
 extern "C" int expdg_step(expdg_mesh *m, int scheme, double dt, double *q, double *q_prev,
                           int have_prev, const expdg_krylov_opts *o, expdg_krylov_stats *s,
@@ -950,9 +611,12 @@ extern "C" int expdg_step(expdg_mesh *m, int scheme, double dt, double *q, doubl
     TRY(check_opts(m, o));
     DeviceGuard g(m->d.device);
     hipStream_t st = (hipStream_t)stream;
-    if (m->d.precision == EXPDG_FP64)
-        return step_impl<double>(m, scheme, dt, q, q_prev, have_prev, o, s, st);
-    return step_impl<float>(m, scheme, dt, q, q_prev, have_prev, o, s, st);
+    if (m->d.precision == EXPDG_FP64) {
+        DirectExec<double> x{st};
+        return run_now(step_co<double>(x, m, scheme, dt, q, q_prev, have_prev, o, s));
+    }
+    DirectExec<float> x{st};
+    return run_now(step_co<float>(x, m, scheme, dt, q, q_prev, have_prev, o, s));
 }
 
 // ---------------------------------------------------------------------------
@@ -992,4 +656,4 @@ extern "C" int expdg_profile_read(expdg_mesh *m, int c, expdg_kernel_profile *ou
 
 extern "C" const char *expdg_last_error(void) { return g_err; }
 
-extern "C" int expdg_version(void) { return 100; }
+extern "C" int expdg_version(void) { return 200; }

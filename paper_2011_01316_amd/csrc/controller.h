@@ -1,0 +1,411 @@
+// The adaptive Krylov controller and the exponential steppers, written once as
+// coroutines over an executor.
+//
+// The controller (Section 2.3: Krylov projection of the augmented matrix whose
+// exponential yields the phi combination; the paper leaves the adaptivity
+// parameters unreported, so the rules below are a fixed written specification
+// that the test oracle follows too) makes every decision on the host from a
+// few scalars per check; all state-sized arithmetic is launched on the
+// executor's stream.  The executor decides when the Arnoldi steps and the
+// small exponentials run:
+//   * the stand-alone entry points launch each operation at once and wait in
+//     place (no coroutine ever suspends);
+//   * the solve server collects the same Arnoldi step of many solves into
+//     grouped launches and all pending checks into one batched launch per
+//     tick, suspending each solve until its results are there.
+// Both make the same decisions from the same numbers, so a solve gives the
+// same bits alone, in the server, or among other solves.
+//
+// An executor X provides
+//   hipStream_t stream();
+//   awaitable<int> iterate(m, a, j, naug_nz, const CheckReq *chk, Check *c):
+//       the Arnoldi step j (linear operator on u_{j-1}, two Gram-Schmidt
+//       passes, norm) and, if chk, the check of dimension j behind it;
+//   awaitable<int> check(m, req, Check *c): a check on the current basis;
+//   awaitable<int> wait_check(m, c): the check's header is in the pinned mirror;
+//   int after_check(m, c): the stream waits for the check's coefficients;
+//   awaitable<int> readback(m): device-to-host copies enqueued so far are done;
+//   awaitable<int> finish(m): the end of one library call.
+#pragma once
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <type_traits>
+
+#include "runtime.h"
+#include "task.h"
+
+namespace expdg {
+
+// A check asked for: dimension j, substep dtau, result slot (0 or 1).
+struct CheckReq {
+    int j;
+    double dtau;
+    int slot;
+};
+
+// A check enqueued (tick: the server's batch that runs it).
+struct Check {
+    int j = 0;
+    int slot = 0;
+    long long tick = 0;
+};
+
+struct CheckResult {
+    double err;
+    int singular, brk, nonfinite;
+};
+
+// The header of a check as the small-exponential kernel wrote it into the
+// pinned mirror.  The Krylov flags are read while the next (speculative)
+// Arnoldi step may already run, so a breakdown or a non-finite norm counts for
+// this check only if it happened at a dimension <= j.
+inline CheckResult read_check(const expdg_mesh *m, const Check &c) {
+    const volatile double *pv = m->pin + kPinSlots + c.slot * 8;
+    CheckResult r;
+    r.err = pv[kSlotErr];
+    r.singular = pv[kSlotSingular] != 0.0;
+    const int brk = (int)pv[kSlotBreak];
+    const int nf = (int)pv[kSlotNonfinite];
+    r.brk = (brk > 0 && brk <= c.j) ? brk : 0;
+    r.nonfinite = (nf > 0 && nf <= c.j) ? 1 : 0;
+    return r;
+}
+
+// Scalars of one phi evaluation shared by its loop and its decisions.
+template <typename T, typename X>
+struct PhiRun {
+    X &x;
+    expdg_mesh *m;
+    const expdg_krylov_opts *o;
+    expdg_krylov_stats *st;
+    double tau = 0.0, tol_abs = 0.0;
+    double t_done = 0.0, dt_sub = 0.0, err = 0.0;
+    bool sub_last = true;
+    int j_acc = 0, nchecks = 0;
+    Check acc;
+
+    PhiRun(X &x_, expdg_mesh *m_, const expdg_krylov_opts *o_, expdg_krylov_stats *st_)
+        : x(x_), m(m_), o(o_), st(st_) {}
+
+    CheckReq req(int j, double dtau) { return CheckReq{j, dtau, (nchecks++) & 1}; }
+
+    // Decision on check c: accept (possibly after shrinking the substep on the
+    // same basis at m_max), take a happy breakdown, or go on (done = false).
+    Task<int> decide(Check c, bool *done) {
+        *done = false;
+        CO_TRY(co_await x.wait_check(m, c));
+        const CheckResult r = read_check(m, c);
+        if (r.nonfinite) co_return fail(EXPDG_ENONFINITE, "non-finite Krylov norm");
+        if (r.brk > 0) {
+            // happy breakdown: the space is invariant, take the whole remaining interval
+            dt_sub = tau - t_done;
+            sub_last = true;
+            Check bc;
+            CO_TRY(co_await x.check(m, req(r.brk, dt_sub), &bc));
+            CO_TRY(co_await x.wait_check(m, bc));
+            const CheckResult br = read_check(m, bc);
+            if (br.singular) co_return fail(EXPDG_ENONFINITE, "singular Pade denominator");
+            if (st) st->breakdown += 1;
+            err = 0.0;
+            j_acc = r.brk;
+            acc = bc;
+            *done = true;
+            co_return EXPDG_OK;
+        }
+        if (r.singular) co_return fail(EXPDG_ENONFINITE, "singular Pade denominator");
+        if (!std::isfinite(r.err)) co_return fail(EXPDG_ENONFINITE, "non-finite error estimate");
+        if (r.err <= tol_abs * dt_sub / tau) {
+            err = r.err;
+            j_acc = c.j;
+            acc = c;
+            *done = true;
+            co_return EXPDG_OK;
+        }
+        if (c.j == o->m_max) {
+            // shrink on the same basis until it passes
+            double e = r.err;
+            Check sc = c;
+            while (e > tol_abs * dt_sub / tau) {
+                const double ratio = tol_abs * dt_sub / tau / e;
+                const double fac = std::max(0.2, 0.9 * std::pow(ratio, 1.0 / o->m_max));
+                dt_sub = round2(dt_sub * fac);
+                sub_last = false;
+                if (st) st->rejects += 1;
+                if (!(dt_sub > 1e-12 * tau))
+                    co_return fail(EXPDG_ENOCONV, "Krylov substep below its floor");
+                CO_TRY(co_await x.check(m, req(c.j, dt_sub), &sc));
+                CO_TRY(co_await x.wait_check(m, sc));
+                const CheckResult sr = read_check(m, sc);
+                if (sr.singular || !std::isfinite(sr.err))
+                    co_return fail(EXPDG_ENONFINITE, "non-finite error estimate");
+                e = sr.err;
+            }
+            err = e;
+            j_acc = c.j;
+            acc = sc;
+            *done = true;
+        }
+        co_return EXPDG_OK;
+    }
+};
+
+// Awaits a sub-task, reporting a frame allocation failure as ENOMEM.
+#define CO_AWAIT_TASK(task_expr)                                                   \
+    do {                                                                           \
+        auto t_ = (task_expr);                                                     \
+        if (!t_.valid()) co_return ::expdg::fail(EXPDG_ENOMEM, "coroutine frame"); \
+        CO_TRY(co_await t_);                                                       \
+    } while (0)
+
+// w = sum_{k=0}^{p} tau^k phi_k(tau L~) b_k by the augmented Krylov method
+// (Section 2.3), with L~ the linear operator frozen at qref.  b[k] == nullptr
+// is a zero vector.  *fpos walks a forced substep schedule.
+template <typename T, typename X>
+Task<int> phi_co(X &x, expdg_mesh *m, const T *qref, double tau, int p, const T *const *b, T *out,
+                 const expdg_krylov_opts *o, expdg_krylov_stats *st, int *fpos) {
+    hipStream_t s = x.stream();
+    const size_t n = m->n, L = n + (size_t)p;
+    const size_t stride = m->stride;
+    T *V = (T *)m->V;
+    KrylovDev &kd = m->kd;
+    const bool forced = o->n_forced > 0;
+    const RowPartition rp = row_partition(L);
+    if (st) st->phi_calls += 1;
+
+    // 1. scaling and 2. tolerance: norms of b_0..b_p
+    const T *bx[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (int k = 0; k <= p; ++k) bx[k] = b ? b[k] : nullptr;
+    CO_HIPTRY(launch_norms<T>(bx, p + 1, n, kd.part, m->dnorm, s));
+    CO_HIPTRY(hipMemcpyAsync(m->pin + kPinNorms, m->dnorm, (p + 1) * 8, hipMemcpyDeviceToHost, s));
+    CO_TRY(co_await x.readback(m));
+    double bn[4] = {0, 0, 0, 0};
+    for (int k = 0; k <= p; ++k) bn[k] = bx[k] ? m->pin[kPinNorms + k] : 0.0;
+    double bmax = 0.0;
+    for (int k = 1; k <= p; ++k) bmax = std::max(bmax, bn[k]);
+    const double eta = (bmax > 0.0) ? std::ldexp(1.0, -(int)std::lround(std::log2(bmax))) : 1.0;
+    double nu = bn[0], tk = 1.0, fact = 1.0;
+    for (int k = 1; k <= p; ++k) {
+        tk *= tau;
+        fact *= k;
+        nu += tk * bn[k] / fact;
+    }
+    if (!std::isfinite(nu)) co_return fail(EXPDG_ENONFINITE, "non-finite input norm");
+    if (nu == 0.0 || tau == 0.0) {
+        if (bx[0])
+            CO_HIPTRY(launch_copy(bx[0], out, n, s));
+        else
+            CO_HIPTRY(launch_fill<T>(out, 0.0, n, s));
+        CO_TRY(co_await x.finish(m));
+        co_return EXPDG_OK;
+    }
+    PhiRun<T, X> R(x, m, o, st);
+    R.tau = tau;
+    R.tol_abs = o->tol * nu;
+
+    // z = [b_0; 0, ..., 0, 1/eta] lives in V_0
+    if (bx[0])
+        CO_HIPTRY(launch_copy(bx[0], V, n, s));
+    else
+        CO_HIPTRY(launch_fill<T>(V, 0.0, n, s));
+    if (p > 0) CO_HIPTRY(launch_set_tail<T>(V + n, p, 1.0 / eta, s));
+    CO_HIPTRY(launch_fill<int>(kd.flags, 0.0, 4, s));
+
+    OpArgs<T> a = op_args<T>(m);
+    a.q = qref;
+    a.eta = eta;
+    a.naug = p;
+    int naug_nz = 0;
+    for (int k = 1; k <= p; ++k) {
+        a.aug[k - 1] = bx[p + 1 - k];
+        naug_nz += bx[p + 1 - k] ? 1 : 0;
+    }
+    const double eb = (double)sizeof(T);
+
+    double dtau = tau;
+    bool reaches_end = true;
+    while (true) {
+        int m_target = o->m_max;
+        R.dt_sub = dtau;
+        R.sub_last = reaches_end;
+        if (forced) {
+            if (*fpos >= o->n_forced) co_return fail(EXPDG_EINVAL, "forced schedule exhausted");
+            m_target = o->forced[*fpos].m;
+            R.dt_sub = o->forced[*fpos].dtau;
+            R.sub_last = o->forced[*fpos].last != 0;
+        }
+        // beta = ||z||, S[0] = 1/beta, flags cleared
+        CO_TRY(prof_begin(m, EXPDG_K_GS_UPDATE_NORM));
+        CO_HIPTRY(launch_gs_update_norm<T>(V, stride, 0, nullptr, V, L, rp, kd.part, kd.H, kd.S,
+                                           -1, kd.flags, kd.res, s));
+        CO_TRY(prof_end(m, EXPDG_K_GS_UPDATE_NORM, (double)L * eb));
+        CO_TRY(prof_begin(m, EXPDG_K_GS_FINISH));
+        CO_HIPTRY(launch_gs_finish_norm(kd.part, rp, kd.H, kd.S, -1, kd.flags, kd.res, s));
+        CO_TRY(prof_end(m, EXPDG_K_GS_FINISH, 8.0 * rp.nrb));
+        CO_HIPTRY(launch_fill<double>(kd.H, 0.0, (size_t)(kMaxM + 1) * kMaxM, s));
+
+        R.j_acc = 0;
+        R.err = 0.0;
+        Check pending;
+        bool have_pending = false;
+        for (int j = 1; j <= m_target; ++j) {
+            T *vin = V + (size_t)(j - 1) * stride;
+            T *w = V + (size_t)j * stride;
+            // w = S[j-1] * Aug(u_{j-1})
+            a.v = vin;
+            a.out = w;
+            a.vtail = vin + n;
+            a.otail = w + n;
+            a.vscale = kd.S + (j - 1);
+            const bool is_check =
+                !forced && (j == o->m_max || (j >= o->m_min && (j - o->m_min) % o->check_every == 0));
+            CheckReq cr{};
+            if (is_check) cr = R.req(j, R.dt_sub);
+            Check cur;
+            CO_TRY(co_await x.iterate(m, a, j, naug_nz, is_check ? &cr : nullptr, &cur));
+            if (st) {
+                st->krylov_iters += 1;
+                st->jvps += 1;
+            }
+            if (forced) continue;
+            // look one check behind: the device works on step j meanwhile
+            bool done = false;
+            if (have_pending) {
+                have_pending = false;
+                CO_AWAIT_TASK(R.decide(pending, &done));
+                if (done) break;
+            }
+            if (is_check) {
+                pending = cur;
+                have_pending = true;
+            }
+            if (j == m_target && have_pending) {
+                have_pending = false;
+                CO_AWAIT_TASK(R.decide(pending, &done));
+                if (done) break;
+            }
+        }
+        if (forced) {
+            Check fc;
+            CO_TRY(co_await x.check(m, R.req(m_target, R.dt_sub), &fc));
+            R.acc = fc;
+            R.j_acc = m_target;
+            R.err = 0.0;
+        }
+        if (R.j_acc == 0) co_return fail(EXPDG_ENOCONV, "Krylov controller made no decision");
+
+        // accept: z <- beta V_j F_{1:j,1} (once the check's coefficients are written)
+        CO_TRY(x.after_check(m, R.acc));
+        CO_TRY(prof_begin(m, EXPDG_K_COMBINE));
+        CO_HIPTRY(launch_combine<T>(V, stride, R.j_acc,
+                                    m->slots + R.acc.slot * kSlotSize + kSlotCoef, V, L, s));
+        CO_TRY(prof_end(m, EXPDG_K_COMBINE, (double)(R.j_acc + 1) * L * eb));
+        R.t_done += R.dt_sub;
+        log_sub(st, R.j_acc, R.sub_last ? 1 : 0, R.dt_sub);
+        if (st) st->err_est = R.err;
+        if (forced) *fpos += 1;
+        if (R.sub_last) break;
+        if (forced) continue;
+
+        const double ratio = (R.err > 0.0) ? R.tol_abs * R.dt_sub / tau / R.err : 0.0;
+        double fac = (R.err > 0.0) ? 0.9 * std::pow(ratio, 1.0 / R.j_acc) : 5.0;
+        fac = std::min(5.0, std::max(1.0, fac));
+        const double cand = round2(R.dt_sub * fac);
+        const double rem = tau - R.t_done;
+        if (!(rem > 1e-15 * tau)) break;
+        if (cand >= rem) {
+            dtau = rem;
+            reaches_end = true;
+        } else {
+            dtau = cand;
+            reaches_end = false;
+        }
+    }
+    CO_HIPTRY(launch_copy(V, out, n, s));
+    if (forced) {
+        // a forced run reads no check back: surface non-finite values here
+        CO_HIPTRY(hipMemcpyAsync(m->pin + kPinNorms, kd.flags, 8, hipMemcpyDeviceToHost, s));
+        CO_TRY(co_await x.readback(m));
+        int fl[2];
+        std::memcpy(fl, m->pin + kPinNorms, 8);
+        if (fl[1]) co_return fail(EXPDG_ENONFINITE, "non-finite Krylov norm");
+    }
+    CO_TRY(co_await x.finish(m));
+    co_return EXPDG_OK;
+}
+
+// One step of EPI2, EPI3 (Tokman's three-stage form; the first step, without
+// history, is EPI2) or EXPRB32 (the schemes of Section 5.1), on the FP64 state
+// q (and its history q_prev for EPI3).  The operator views are bulk copies in
+// FP32_BULK.
+template <typename T, typename X>
+Task<int> step_co(X &x, expdg_mesh *m, int scheme, double dt, double *q, double *q_prev,
+                  int have_prev, const expdg_krylov_opts *o, expdg_krylov_stats *st) {
+    hipStream_t s = x.stream();
+    const size_t n = m->n;
+    constexpr bool bulk = !std::is_same<T, double>::value;
+    T *Rn = (T *)m->vec[0], *Rp = (T *)m->vec[1], *d = (T *)m->vec[2], *Ld = (T *)m->vec[3],
+      *w = (T *)m->vec[4], *w2 = (T *)m->vec[5];
+    // operator views of the FP64 states
+    auto view = [&](double *src, int k, T **dst) -> hipError_t {
+        if constexpr (!bulk) {
+            *dst = (T *)src;
+            return hipSuccess;
+        } else {
+            *dst = (T *)m->bq[k];
+            return launch_convert(src, (float *)*dst, n, s);
+        }
+    };
+    int fpos = 0;
+    T *qb = nullptr;
+    CO_HIPTRY(view(q, 0, &qb));
+    CO_TRY(apply_op<T>(m, false, qb, nullptr, Rn, s));
+    if (st) st->rhs_calls += 1;
+
+    if (scheme == EXPDG_EPI2 || (scheme == EXPDG_EPI3 && !(q_prev && have_prev))) {
+        const T *b[2] = {nullptr, Rn};
+        CO_AWAIT_TASK((phi_co<T, X>(x, m, qb, dt, 1, b, w, o, st, &fpos)));
+        if (q_prev) CO_HIPTRY(launch_copy(q, q_prev, n, s));
+        CO_HIPTRY(launch_add_to<T>(q, w, n, s));
+    } else if (scheme == EXPDG_EPI3) {
+        T *qpb = nullptr;
+        CO_HIPTRY(view(q_prev, 1, &qpb));
+        CO_TRY(apply_op<T>(m, false, qpb, nullptr, Rp, s));
+        CO_HIPTRY((launch_lincomb<T, T>(d, 1.0, qpb, -1.0, qb, 0.0, nullptr, n, s)));
+        CO_TRY(apply_op<T>(m, true, qb, d, Ld, s));
+        if (st) {
+            st->rhs_calls += 1;
+            st->jvps += 1;
+        }
+        const double c = 2.0 / (3.0 * dt);
+        CO_HIPTRY((launch_lincomb<T, T>(d, c, Rp, -c, Rn, -c, Ld, n, s)));  // b_2 into d
+        const T *b[3] = {nullptr, Rn, d};
+        CO_AWAIT_TASK((phi_co<T, X>(x, m, qb, dt, 2, b, w, o, st, &fpos)));
+        CO_HIPTRY(launch_copy(q, q_prev, n, s));
+        CO_HIPTRY(launch_add_to<T>(q, w, n, s));
+    } else {  // EXPRB32
+        const T *b1[2] = {nullptr, Rn};
+        CO_AWAIT_TASK((phi_co<T, X>(x, m, qb, dt, 1, b1, w, o, st, &fpos)));
+        CO_HIPTRY(launch_add_mixed<T>(m->q2, q, w, n, s));  // q2 = q^n + w1
+        T *q2b = nullptr;
+        CO_HIPTRY(view(m->q2, 2, &q2b));
+        CO_TRY(apply_op<T>(m, false, q2b, nullptr, Rp, s));  // R(q2)
+        CO_HIPTRY((launch_lincomb<T, T>(d, 1.0, q2b, -1.0, qb, 0.0, nullptr, n, s)));
+        CO_TRY(apply_op<T>(m, true, qb, d, Ld, s));
+        if (st) {
+            st->rhs_calls += 1;
+            st->jvps += 1;
+        }
+        const double c = 2.0 / (dt * dt);
+        CO_HIPTRY((launch_lincomb<T, T>(d, c, Rp, -c, Rn, -c, Ld, n, s)));  // b_3 into d
+        const T *b[4] = {nullptr, nullptr, nullptr, d};
+        CO_AWAIT_TASK((phi_co<T, X>(x, m, qb, dt, 3, b, w2, o, st, &fpos)));
+        if (q_prev) CO_HIPTRY(launch_copy(q, q_prev, n, s));
+        CO_HIPTRY(launch_add_mixed<T>(q, m->q2, w2, n, s));
+    }
+    CO_TRY(co_await x.finish(m));
+    co_return EXPDG_OK;
+}
+
+}  // namespace expdg

@@ -110,15 +110,17 @@ __device__ __forceinline__ T euler_speed(const T *q, T gamma) {
 }
 
 // ---- Euler 2D operator ------------------------------------------------------
+// One tile (floor(256/Np) elements) of the operator; first marks the item's
+// first block, which also writes the augmented entries of the output.
 template <int P, typename T, bool JVP>
-__global__ __launch_bounds__(256) void euler_op(OpArgs<T> a) {
+__device__ __forceinline__ void euler_op_body(const OpArgs<T> &a, int tile, bool first) {
     constexpr int N1 = P + 1, NP = N1 * N1, EPB = 256 / NP, NT = EPB * NP;
     __shared__ T sF[8][NT];
     const int tid = threadIdx.x;
     const int le = tid / NP;
     const int n = tid - le * NP;
     const int i = n % N1, j = n / N1;
-    const int e = xcd_tile(blockIdx.x, gridDim.x) * EPB + le;
+    const int e = tile * EPB + le;
     const bool active = (tid < NT) && (e < a.K);
     const size_t plane = (size_t)a.K * NP;
     const size_t idx = (size_t)e * NP + n;
@@ -127,7 +129,7 @@ __global__ __launch_bounds__(256) void euler_op(OpArgs<T> a) {
     T sc = T(1);
     if (a.vscale) sc = (T)(*a.vscale);
     // augmented entries of the output: (y_2, ..., y_p, 0), scaled
-    if (a.naug > 0 && blockIdx.x == 0 && tid == 0) {
+    if (a.naug > 0 && first && tid == 0) {
         for (int k = 0; k < a.naug; ++k)
             a.otail[k] = (k + 1 < a.naug) ? sc * a.vtail[k + 1] : T(0);
     }
@@ -234,19 +236,19 @@ __global__ __launch_bounds__(256) void euler_op(OpArgs<T> a) {
 
 // ---- Burgers 1D operator ----------------------------------------------------
 template <int P, typename T, bool JVP>
-__global__ __launch_bounds__(256) void burgers_op(OpArgs<T> a) {
+__device__ __forceinline__ void burgers_op_body(const OpArgs<T> &a, int tile, bool first) {
     constexpr int N1 = P + 1, EPB = 256 / N1, NT = EPB * N1;
     __shared__ T sF[NT];
     const int tid = threadIdx.x;
     const int le = tid / N1;
     const int i = tid - le * N1;
-    const int e = xcd_tile(blockIdx.x, gridDim.x) * EPB + le;
+    const int e = tile * EPB + le;
     const bool active = (tid < NT) && (e < a.K);
     const size_t idx = (size_t)e * N1 + i;
 
     T sc = T(1);
     if (a.vscale) sc = (T)(*a.vscale);
-    if (a.naug > 0 && blockIdx.x == 0 && tid == 0) {
+    if (a.naug > 0 && first && tid == 0) {
         for (int k = 0; k < a.naug; ++k)
             a.otail[k] = (k + 1 < a.naug) ? sc * a.vtail[k + 1] : T(0);
     }
@@ -282,6 +284,49 @@ __global__ __launch_bounds__(256) void burgers_op(OpArgs<T> a) {
         res += (T)a.eta * a.vtail[k] * b[idx];
     }
     a.out[idx] = sc * res;
+}
+
+template <int P, typename T, bool JVP>
+__global__ __launch_bounds__(256) void euler_op(OpArgs<T> a) {
+    euler_op_body<P, T, JVP>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.x == 0);
+}
+
+template <int P, typename T, bool JVP>
+__global__ __launch_bounds__(256) void burgers_op(OpArgs<T> a) {
+    burgers_op_body<P, T, JVP>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.x == 0);
+}
+
+template <int P, typename T, bool JVP>
+__global__ __launch_bounds__(256) void euler_op_group(const OpArgs<T> *items, const int *bstart,
+                                                      int n) {
+    const int it = group_item(bstart, n, blockIdx.x);
+    const int local = blockIdx.x - bstart[it], G = bstart[it + 1] - bstart[it];
+    euler_op_body<P, T, JVP>(items[it], xcd_tile(local, G), local == 0);
+}
+
+template <int P, typename T, bool JVP>
+__global__ __launch_bounds__(256) void burgers_op_group(const OpArgs<T> *items, const int *bstart,
+                                                        int n) {
+    const int it = group_item(bstart, n, blockIdx.x);
+    const int local = blockIdx.x - bstart[it], G = bstart[it + 1] - bstart[it];
+    burgers_op_body<P, T, JVP>(items[it], xcd_tile(local, G), local == 0);
+}
+
+template <int P, typename T>
+hipError_t launch_group_p(int equation, bool jvp, const OpArgs<T> *items, const int *bstart,
+                          int n, int total, hipStream_t s) {
+    if (equation == EXPDG_EULER2D) {
+        if (jvp)
+            return launch_kernel(euler_op_group<P, T, true>, dim3(total), dim3(256), 0, s, items,
+                                 bstart, n);
+        return launch_kernel(euler_op_group<P, T, false>, dim3(total), dim3(256), 0, s, items,
+                             bstart, n);
+    }
+    if (jvp)
+        return launch_kernel(burgers_op_group<P, T, true>, dim3(total), dim3(256), 0, s, items,
+                             bstart, n);
+    return launch_kernel(burgers_op_group<P, T, false>, dim3(total), dim3(256), 0, s, items,
+                         bstart, n);
 }
 
 template <int P, typename T>
@@ -390,6 +435,25 @@ int grid_for(size_t n) {
 }
 
 }  // namespace
+
+int dg_blocks(int equation, int p, int K) {
+    const int np = (equation == EXPDG_EULER2D) ? (p + 1) * (p + 1) : (p + 1);
+    const int epb = 256 / np;
+    return (K + epb - 1) / epb;
+}
+
+hipError_t launch_dg_op_group(int equation, int p, bool jvp, const OpArgs<double> *items,
+                              const int *bstart, int n, int total, hipStream_t s) {
+    switch (p) {
+        case 1: return launch_group_p<1, double>(equation, jvp, items, bstart, n, total, s);
+        case 2: return launch_group_p<2, double>(equation, jvp, items, bstart, n, total, s);
+        case 3: return launch_group_p<3, double>(equation, jvp, items, bstart, n, total, s);
+        case 4: return launch_group_p<4, double>(equation, jvp, items, bstart, n, total, s);
+        case 5: return launch_group_p<5, double>(equation, jvp, items, bstart, n, total, s);
+        case 6: return launch_group_p<6, double>(equation, jvp, items, bstart, n, total, s);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_dg_op(int equation, int p, bool jvp, const OpArgs<double> &a, hipStream_t s) {
     return launch_any<double>(equation, p, jvp, a, s);

@@ -64,6 +64,12 @@ int lgl_tables(int p, double *xi, double *w, double *D);
 // ---- kernel launchers (dg_kernels.hip) ----
 hipError_t launch_dg_op(int equation, int p, bool jvp, const OpArgs<double> &a, hipStream_t s);
 hipError_t launch_dg_op(int equation, int p, bool jvp, const OpArgs<float> &a, hipStream_t s);
+// Blocks one operator launch uses for K elements.
+int dg_blocks(int equation, int p, int K);
+// Grouped FP64 launch over n meshes of the same equation and degree: item it
+// owns blocks [bstart[it], bstart[it+1]) (device arrays), total = bstart[n].
+hipError_t launch_dg_op_group(int equation, int p, bool jvp, const OpArgs<double> *items,
+                              const int *bstart, int n, int total, hipStream_t s);
 // Per-block maxima of the wave speed (FP64 state) into part[0..nblk).
 hipError_t launch_max_speed(int equation, const double *q, size_t npts, double gamma,
                             double *part, int nblk, hipStream_t s);
@@ -134,9 +140,9 @@ hipError_t launch_gs_finish_dots(const double *part, int nv, const RowPartition 
                                  double *coef_out, hipStream_t s);
 // Fixed-order finish of a norm pass: hn = sqrt(sum_b part[b]).  col >= 0:
 // H[col+1][col] = hn, breakdown test against ||H||_F (flags[0] = col+1 the
-// first time, S[col+1] = 0), else S[col+1] = 1/hn.  col < 0 (start vector):
-// res[0] = beta = hn, S[0] = 1/beta, flags[0] = 0.  flags[1] = 1 on a
-// non-finite norm.
+// first time, S[col+1] = 0), else S[col+1] = 1/hn; flags[1] = col+1 the first
+// time a norm is non-finite.  col < 0 (start vector): res[0] = beta = hn,
+// S[0] = 1/beta, flags[0] = 0, flags[1] = 1 if beta is non-finite, else 0.
 hipError_t launch_gs_finish_norm(const double *part, const RowPartition &rp, double *H, double *S,
                                  int col, int *flags, double *res, hipStream_t s);
 // Norms of up to 4 vectors of length n (block partials, then finish):
@@ -144,10 +150,41 @@ hipError_t launch_gs_finish_norm(const double *part, const RowPartition &rp, dou
 template <typename T>
 hipError_t launch_norms(const T *const *x, int nx, size_t n, double *part, double *out,
                         hipStream_t s);
-// Small exponential: F = expm(dtau * Hhat_j) (size j+1), err = beta |F[j][0]|,
-// combine coefficients ccoef[i] = beta F[i][0] S[i] (i < j), into slot.
-hipError_t launch_hess_expm(const double *H, int j, double dtau, const double *S,
-                            const double *res_beta, double *slot, hipStream_t s);
+// One small-exponential check: F = expm(dtau * Hhat_j) (size j+1) of the
+// Hessenberg matrix H (j columns), err = beta |F[j][0]|, combine coefficients
+// ccoef[i] = beta F[i][0] S[i] (i < j).  Results go to slot (layout below).
+struct ExpmItem {
+    const double *H;
+    const double *S;
+    const double *res;   // res[0] = beta
+    const int *flags;    // Krylov flags, copied into the slot header
+    double *slot;
+    double *report;      // host-mapped copy of the first kSummary header values (or nullptr)
+    double dtau;
+    int j;
+};
+hipError_t launch_hess_expm(const ExpmItem &c, hipStream_t s);
+// n checks (device array), one workgroup each.
+hipError_t launch_hess_expm_group(const ExpmItem *items, int n, hipStream_t s);
+
+// One Arnoldi step (FP64) of one solve inside a grouped launch: the CGS2
+// passes and the norm of w = u_nv against the basis u_0..u_{nv-1}.
+struct GsItem {
+    const double *V;
+    double *w;
+    size_t stride, L, rpb;
+    int nrb, nv, col;    // col = nv - 1
+    double *part, *S, *H, *coefA, *coefB, *res;
+    int *flags;
+};
+// Launches of a grouped Arnoldi step: first dots, finish, fused update+dots
+// (nv <= 32), plain update (nv > 32), dots after it (nv > 32), update+norm.
+constexpr int kGroupLaunches = 6;
+// Host: block ranges bstart[k*(n+1) + it] of launch k and the totals.
+void arnoldi_group_layout(const GsItem *items, int n, int *bstart, int *totals);
+// Device copies of items and bstart; totals from arnoldi_group_layout.
+hipError_t launch_arnoldi_group(const GsItem *items, const int *bstart, const int *totals, int n,
+                                hipStream_t s);
 // z = sum_{i<m} ccoef[i] * V_i (row-local; z may alias V_0).
 template <typename T>
 hipError_t launch_combine(const T *V, size_t stride, int m, const double *ccoef, T *z, size_t L,
@@ -156,9 +193,29 @@ hipError_t launch_combine(const T *V, size_t stride, int m, const double *ccoef,
 // are n x n row-major device buffers (n <= kMaxM + 1).
 hipError_t launch_dense_expm(const double *A, int n, double *E, hipStream_t s);
 
-// Slot layout written by launch_hess_expm (doubles).
-constexpr int kSlotErr = 0;
-constexpr int kSlotCoef = 8;                 // kMaxM + 1 combine coefficients
+// Slot layout written by the small-exponential kernels (doubles).
+constexpr int kSlotErr = 0;        // beta |F[j][0]|
+constexpr int kSlotSingular = 1;   // 1: singular Pade denominator
+constexpr int kSlotBreak = 2;      // Krylov flags[0]: first breakdown iteration (0 = none)
+constexpr int kSlotNonfinite = 3;  // Krylov flags[1]: a non-finite norm was seen
+constexpr int kSlotSquarings = 4;
+constexpr int kSlotHeader = 5;
+constexpr int kSummary = 4;        // header values a check reports to the host
+constexpr int kSlotCoef = 8;       // kMaxM combine coefficients
 constexpr int kSlotSize = kSlotCoef + kMaxM + 8;
+
+// Grouped launches: block b belongs to the largest item it with
+// bstart[it] <= b (items with no blocks are skipped).
+__device__ __forceinline__ int group_item(const int *bstart, int n, int b) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (bstart[mid] <= b)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
 
 }  // namespace expdg

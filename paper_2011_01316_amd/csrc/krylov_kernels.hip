@@ -138,10 +138,10 @@ struct DotFinish {
 
 // h_i = S[i] sum_b part[i][b]; H[i][col] (+)= h_i; coef_out[i] = h_i S[i].
 // One wave per output (four per block), partials summed in a fixed order.
-__global__ __launch_bounds__(256) void finish_dots_kernel(const double *part, int nv, int nrb,
-                                                          DotFinish f) {
+__device__ __forceinline__ void finish_dots_body(const double *part, int nv, int nrb,
+                                                 const DotFinish &f, int blk) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int i = blockIdx.x * 4 + wave;
+    const int i = blk * 4 + wave;
     if (i >= nv) return;
     double a = 0.0;
     for (int b = lane; b < nrb; b += 64) a += part[(size_t)i * nrb + b];
@@ -154,6 +154,11 @@ __global__ __launch_bounds__(256) void finish_dots_kernel(const double *part, in
     }
 }
 
+__global__ __launch_bounds__(256) void finish_dots_kernel(const double *part, int nv, int nrb,
+                                                          DotFinish f) {
+    finish_dots_body(part, nv, nrb, f, blockIdx.x);
+}
+
 struct NormFinish {
     double *H;
     double *S;
@@ -162,8 +167,7 @@ struct NormFinish {
     double *res;    // res[0] = beta (start vector)
 };
 
-__global__ __launch_bounds__(256) void finish_norm_kernel(const double *part, int nrb,
-                                                          NormFinish f) {
+__device__ __forceinline__ void finish_norm_body(const double *part, int nrb, const NormFinish &f) {
     __shared__ double sw[4];
     const int tid = threadIdx.x;
     double a = 0.0;
@@ -178,7 +182,7 @@ __global__ __launch_bounds__(256) void finish_norm_kernel(const double *part, in
             f.res[0] = hn;
             f.S[0] = (hn > 0.0) ? 1.0 / hn : 0.0;
             f.flags[0] = 0;
-            if (!isfinite(hn)) f.flags[1] = 1;
+            f.flags[1] = isfinite(hn) ? 0 : 1;
         }
         return;
     }
@@ -195,7 +199,7 @@ __global__ __launch_bounds__(256) void finish_norm_kernel(const double *part, in
     __syncthreads();
     if (tid == 0) {
         const double hf = sqrt((sw[0] + sw[1]) + (sw[2] + sw[3]));
-        if (!isfinite(hn) || !isfinite(hf)) f.flags[1] = 1;
+        if ((!isfinite(hn) || !isfinite(hf)) && f.flags[1] == 0) f.flags[1] = col + 1;
         const bool brk = hn <= 1e-12 * hf;
         if (brk) {
             f.H[(size_t)(col + 1) * LDH + col] = 0.0;
@@ -208,16 +212,21 @@ __global__ __launch_bounds__(256) void finish_norm_kernel(const double *part, in
     }
 }
 
+__global__ __launch_bounds__(256) void finish_norm_kernel(const double *part, int nrb,
+                                                          NormFinish f) {
+    finish_norm_body(part, nrb, f);
+}
+
 // part[i][rb] = sum over the block's rows of V_i[r] w[r], i in the block's
 // 16-vector chunk.
 template <typename T>
-__global__ __launch_bounds__(256) void gs_dots_kernel(const T *__restrict__ V, size_t stride,
-                                                      int nv, const T *__restrict__ w, size_t L,
-                                                      size_t rpb, int nrb,
-                                                      double *__restrict__ part) {
+__device__ __forceinline__ void gs_dots_body(const T *__restrict__ V, size_t stride, int nv,
+                                             const T *__restrict__ w, size_t L, size_t rpb,
+                                             int nrb, double *__restrict__ part, int rb,
+                                             int chunk) {
     __shared__ double sw[4][CH];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int rb = blockIdx.x, i0 = blockIdx.y * CH;
+    const int i0 = chunk * CH;
     const int nloc = min(CH, nv - i0);
     const size_t r0 = (size_t)rb * rpb;
     const size_t r1 = (r0 + rpb < L) ? r0 + rpb : L;
@@ -254,18 +263,26 @@ __global__ __launch_bounds__(256) void gs_dots_kernel(const T *__restrict__ V, s
         part[(size_t)(i0 + tid) * nrb + rb] = (sw[0][tid] + sw[1][tid]) + (sw[2][tid] + sw[3][tid]);
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void gs_dots_kernel(const T *__restrict__ V, size_t stride,
+                                                      int nv, const T *__restrict__ w, size_t L,
+                                                      size_t rpb, int nrb,
+                                                      double *__restrict__ part) {
+    gs_dots_body<T>(V, stride, nv, w, L, rpb, nrb, part, blockIdx.x, blockIdx.y);
+}
+
 // w -= sum_i c_i V_i with c from the previous pass, then
 // part[i][rb] = sum_r V_i[r] w[r] (nv <= 32).
 template <typename T>
-__global__ __launch_bounds__(256) void gs_update_dots_kernel(
-    const T *__restrict__ V, size_t stride, int nv, PrevPass prev, T *__restrict__ w, size_t L,
-    size_t rpb, int nrb, double *__restrict__ part) {
+__device__ __forceinline__ void gs_update_dots_body(const T *__restrict__ V, size_t stride, int nv,
+                                                    const double *coef, T *__restrict__ w,
+                                                    size_t L, size_t rpb, int nrb,
+                                                    double *__restrict__ part, int rb) {
     __shared__ double scoef[32];
     __shared__ double sw[4][32];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (tid < nv) scoef[tid] = prev.coef[tid];
+    if (tid < nv) scoef[tid] = coef[tid];
     __syncthreads();
-    const int rb = blockIdx.x;
     const size_t r0 = (size_t)rb * rpb;
     const size_t r1 = (r0 + rpb < L) ? r0 + rpb : L;
     double acc[32];
@@ -329,17 +346,23 @@ __global__ __launch_bounds__(256) void gs_update_dots_kernel(
     if (tid < nv) part[(size_t)tid * nrb + rb] = (sw[0][tid] + sw[1][tid]) + (sw[2][tid] + sw[3][tid]);
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void gs_update_dots_kernel(
+    const T *__restrict__ V, size_t stride, int nv, PrevPass prev, T *__restrict__ w, size_t L,
+    size_t rpb, int nrb, double *__restrict__ part) {
+    gs_update_dots_body<T>(V, stride, nv, prev.coef, w, L, rpb, nrb, part, blockIdx.x);
+}
+
 // w -= sum_i c_i V_i with c from the previous pass (any nv <= kMaxM + 1).
 template <typename T>
-__global__ __launch_bounds__(256) void gs_update_kernel(const T *__restrict__ V, size_t stride,
-                                                        int nv, PrevPass prev,
-                                                        T *__restrict__ w, size_t L, size_t rpb,
-                                                        int nrb) {
+__device__ __forceinline__ void gs_update_body(const T *__restrict__ V, size_t stride, int nv,
+                                               const double *coef, T *__restrict__ w, size_t L,
+                                               size_t rpb, int rb) {
     __shared__ double scoef[kMaxM + 1];
     const int tid = threadIdx.x;
-    if (tid < nv) scoef[tid] = prev.coef[tid];
+    if (tid < nv) scoef[tid] = coef[tid];
     __syncthreads();
-    const size_t r0 = (size_t)blockIdx.x * rpb;
+    const size_t r0 = (size_t)rb * rpb;
     const size_t r1 = (r0 + rpb < L) ? r0 + rpb : L;
     constexpr int N = Vec16<T>::N;
     const size_t nsw = (r1 - r0) / (256 * N);
@@ -362,19 +385,28 @@ __global__ __launch_bounds__(256) void gs_update_kernel(const T *__restrict__ V,
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void gs_update_kernel(const T *__restrict__ V, size_t stride,
+                                                        int nv, PrevPass prev,
+                                                        T *__restrict__ w, size_t L, size_t rpb,
+                                                        int nrb) {
+    (void)nrb;
+    gs_update_body<T>(V, stride, nv, prev.coef, w, L, rpb, blockIdx.x);
+}
+
 // w -= sum_i c_i V_i with c from the previous pass (if any), then the
 // ||w||^2 partials.
 template <typename T>
-__global__ __launch_bounds__(256) void gs_update_norm_kernel(
-    const T *__restrict__ V, size_t stride, int nv, PrevPass prev, T *__restrict__ w, size_t L,
-    size_t rpb, int nrb, double *__restrict__ part) {
+__device__ __forceinline__ void gs_update_norm_body(const T *__restrict__ V, size_t stride, int nv,
+                                                    const double *coef, T *__restrict__ w,
+                                                    size_t L, size_t rpb,
+                                                    double *__restrict__ part, int rb) {
     __shared__ double scoef[kMaxM + 1];
     __shared__ double sw[4];
     const int tid = threadIdx.x;
-    const bool upd = prev.coef != nullptr;
-    if (upd && tid < nv) scoef[tid] = prev.coef[tid];
+    const bool upd = coef != nullptr;
+    if (upd && tid < nv) scoef[tid] = coef[tid];
     __syncthreads();
-    const int rb = blockIdx.x;
     const size_t r0 = (size_t)rb * rpb;
     const size_t r1 = (r0 + rpb < L) ? r0 + rpb : L;
     double acc = 0.0;
@@ -410,6 +442,14 @@ __global__ __launch_bounds__(256) void gs_update_norm_kernel(
     if ((tid & 63) == 0) sw[tid >> 6] = acc;
     __syncthreads();
     if (tid == 0) part[rb] = (sw[0] + sw[1]) + (sw[2] + sw[3]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void gs_update_norm_kernel(
+    const T *__restrict__ V, size_t stride, int nv, PrevPass prev, T *__restrict__ w, size_t L,
+    size_t rpb, int nrb, double *__restrict__ part) {
+    (void)nrb;
+    gs_update_norm_body<T>(V, stride, nv, prev.coef, w, L, rpb, part, blockIdx.x);
 }
 
 template <typename T>
@@ -641,12 +681,17 @@ __device__ int lds_expm(double *sX, double *sP, double *sN, double *sD, int n, i
     return s;
 }
 
-__global__ __launch_bounds__(256) void hess_expm_kernel(const double *H, int j, double dtau,
-                                                        const double *S, const double *res,
-                                                        double *slot) {
+// Small exponential of one check; writes the slot (error, singular flag, the
+// Krylov flags as of this launch, squarings, combine coefficients) and the
+// first kSummary header values to the item's host-mapped report, if any.
+__device__ __forceinline__ void hess_expm_body(const ExpmItem &c) {
     extern __shared__ double smem[];
     double *sX = smem, *sP = sX + NMAX * LDA, *sN = sP + NMAX * LDA, *sD = sN + NMAX * LDA;
     __shared__ int singular;
+    const int j = c.j;
+    const double dtau = c.dtau;
+    const double *H = c.H;
+    double *slot = c.slot;
     const int n = j + 1;
     if (threadIdx.x == 0) singular = 0;
     for (int e = threadIdx.x; e < n * n; e += 256) {
@@ -656,13 +701,22 @@ __global__ __launch_bounds__(256) void hess_expm_kernel(const double *H, int j, 
     __syncthreads();
     const int s = lds_expm(sX, sP, sN, sD, n, 6, &singular);
     __syncthreads();
-    const double beta = res[0];
+    const double beta = c.res[0];
     if (threadIdx.x == 0) {
-        slot[kSlotErr] = beta * fabs(sN[j * LDA + 0]);
-        slot[1] = (double)s;
-        slot[2] = (double)singular;
+        const double hdr[kSlotHeader] = {beta * fabs(sN[j * LDA + 0]), (double)singular,
+                                         (double)c.flags[0], (double)c.flags[1], (double)s};
+        for (int k = 0; k < kSlotHeader; ++k) slot[k] = hdr[k];
+        if (c.report)
+            for (int k = 0; k < kSummary; ++k) c.report[k] = hdr[k];
     }
-    for (int i = threadIdx.x; i < j; i += 256) slot[kSlotCoef + i] = beta * sN[i * LDA + 0] * S[i];
+    for (int i = threadIdx.x; i < j; i += 256) slot[kSlotCoef + i] = beta * sN[i * LDA + 0] * c.S[i];
+}
+
+__global__ __launch_bounds__(256) void hess_expm_kernel(ExpmItem c) { hess_expm_body(c); }
+
+// One workgroup per check.
+__global__ __launch_bounds__(256) void hess_expm_group(const ExpmItem *items) {
+    hess_expm_body(items[blockIdx.x]);
 }
 
 __global__ __launch_bounds__(256) void dense_expm_kernel(const double *A, int n, double *E) {
@@ -707,12 +761,65 @@ __global__ __launch_bounds__(256) void combine_kernel(const T *V, size_t stride,
         }
 }
 
+// ---- grouped launches: one launch serves the same Arnoldi step of many
+// independent solves.  Item it owns blocks [bstart[it], bstart[it+1]); an item
+// with no blocks in a launch is skipped.  Each item computes exactly what its
+// own single launch computes (same row partition, same block partials).
+__global__ __launch_bounds__(256) void gs_dots_group(const GsItem *items, const int *bstart,
+                                                     int n) {
+    const int it = group_item(bstart, n, blockIdx.x);
+    const GsItem &g = items[it];
+    const int local = blockIdx.x - bstart[it];
+    gs_dots_body<double>(g.V, g.stride, g.nv, g.w, g.L, g.rpb, g.nrb, g.part, local % g.nrb,
+                         local / g.nrb);
+}
+
+__global__ __launch_bounds__(256) void finish_dots_group(const GsItem *items, const int *bstart,
+                                                         int n, int pass) {
+    const int it = group_item(bstart, n, blockIdx.x);
+    const GsItem &g = items[it];
+    const DotFinish f{g.S, g.H, g.col, pass, pass ? g.coefB : g.coefA};
+    finish_dots_body(g.part, g.nv, g.nrb, f, blockIdx.x - bstart[it]);
+}
+
+__global__ __launch_bounds__(256) void gs_update_dots_group(const GsItem *items,
+                                                            const int *bstart, int n) {
+    const int it = group_item(bstart, n, blockIdx.x);
+    const GsItem &g = items[it];
+    gs_update_dots_body<double>(g.V, g.stride, g.nv, g.coefA, g.w, g.L, g.rpb, g.nrb, g.part,
+                                blockIdx.x - bstart[it]);
+}
+
+__global__ __launch_bounds__(256) void gs_update_group(const GsItem *items, const int *bstart,
+                                                       int n) {
+    const int it = group_item(bstart, n, blockIdx.x);
+    const GsItem &g = items[it];
+    gs_update_body<double>(g.V, g.stride, g.nv, g.coefA, g.w, g.L, g.rpb,
+                           blockIdx.x - bstart[it]);
+}
+
+__global__ __launch_bounds__(256) void gs_update_norm_group(const GsItem *items,
+                                                            const int *bstart, int n) {
+    const int it = group_item(bstart, n, blockIdx.x);
+    const GsItem &g = items[it];
+    gs_update_norm_body<double>(g.V, g.stride, g.nv, g.coefB, g.w, g.L, g.rpb, g.part,
+                                blockIdx.x - bstart[it]);
+}
+
+// One workgroup per item.
+__global__ __launch_bounds__(256) void finish_norm_group(const GsItem *items) {
+    const GsItem &g = items[blockIdx.x];
+    finish_norm_body(g.part, g.nrb, NormFinish{g.H, g.S, g.col, g.flags, g.res});
+}
+
 constexpr size_t kExpmLds = (size_t)4 * NMAX * LDA * sizeof(double);
 
 // Allow the dynamic LDS of the exponential kernels (above the 64 KB default
 // of older targets); the attribute call is harmless where it is not needed.
 void allow_expm_lds() {
     (void)hipFuncSetAttribute((const void *)hess_expm_kernel,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kExpmLds);
+    (void)hipFuncSetAttribute((const void *)hess_expm_group,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kExpmLds);
     (void)hipFuncSetAttribute((const void *)dense_expm_kernel,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kExpmLds);
@@ -819,13 +926,67 @@ template hipError_t launch_norms<double>(const double *const *, int, size_t, dou
 template hipError_t launch_norms<float>(const float *const *, int, size_t, double *, double *,
                                         hipStream_t);
 
-hipError_t launch_hess_expm(const double *H, int j, double dtau, const double *S,
-                            const double *res_beta, double *slot, hipStream_t s) {
-    if (j < 1 || j > kMaxM) return hipErrorInvalidValue;
+hipError_t launch_hess_expm(const ExpmItem &c, hipStream_t s) {
+    if (c.j < 1 || c.j > kMaxM) return hipErrorInvalidValue;
     static bool once = (allow_expm_lds(), true);
     (void)once;
-    return launch_kernel(hess_expm_kernel, dim3(1), dim3(256), (unsigned)kExpmLds, s, H, j, dtau,
-                         S, res_beta, slot);
+    return launch_kernel(hess_expm_kernel, dim3(1), dim3(256), (unsigned)kExpmLds, s, c);
+}
+
+hipError_t launch_hess_expm_group(const ExpmItem *items, int n, hipStream_t s) {
+    if (n < 1) return hipErrorInvalidValue;
+    static bool once = (allow_expm_lds(), true);
+    (void)once;
+    return launch_kernel(hess_expm_group, dim3(n), dim3(256), (unsigned)kExpmLds, s, items);
+}
+
+void arnoldi_group_layout(const GsItem *items, int n, int *bstart, int *totals) {
+    int t[kGroupLaunches] = {};
+    for (int it = 0; it < n; ++it) {
+        const GsItem &g = items[it];
+        const int chunks = (g.nv + CH - 1) / CH;
+        const bool small = g.nv <= 32;
+        const int blocks[kGroupLaunches] = {g.nrb * chunks, (g.nv + 3) / 4, small ? g.nrb : 0,
+                                            small ? 0 : g.nrb, small ? 0 : g.nrb * chunks, g.nrb};
+        for (int k = 0; k < kGroupLaunches; ++k) {
+            bstart[k * (n + 1) + it] = t[k];
+            t[k] += blocks[k];
+        }
+    }
+    for (int k = 0; k < kGroupLaunches; ++k) {
+        bstart[k * (n + 1) + n] = t[k];
+        totals[k] = t[k];
+    }
+}
+
+hipError_t launch_arnoldi_group(const GsItem *items, const int *bstart, const int *totals, int n,
+                                hipStream_t s) {
+    if (n < 1) return hipErrorInvalidValue;
+    const int *b[kGroupLaunches];
+    for (int k = 0; k < kGroupLaunches; ++k) b[k] = bstart + (size_t)k * (n + 1);
+    hipError_t e;
+    // first pass: h1 = V^T w
+    e = launch_kernel(gs_dots_group, dim3(totals[0]), dim3(256), 0, s, items, b[0], n);
+    if (e != hipSuccess) return e;
+    e = launch_kernel(finish_dots_group, dim3(totals[1]), dim3(256), 0, s, items, b[1], n, 0);
+    if (e != hipSuccess) return e;
+    // second pass: w -= V h1 ; h2 = V^T w (fused for j <= 32)
+    if (totals[2] > 0) {
+        e = launch_kernel(gs_update_dots_group, dim3(totals[2]), dim3(256), 0, s, items, b[2], n);
+        if (e != hipSuccess) return e;
+    }
+    if (totals[3] > 0) {
+        e = launch_kernel(gs_update_group, dim3(totals[3]), dim3(256), 0, s, items, b[3], n);
+        if (e != hipSuccess) return e;
+        e = launch_kernel(gs_dots_group, dim3(totals[4]), dim3(256), 0, s, items, b[4], n);
+        if (e != hipSuccess) return e;
+    }
+    e = launch_kernel(finish_dots_group, dim3(totals[1]), dim3(256), 0, s, items, b[1], n, 1);
+    if (e != hipSuccess) return e;
+    // w -= V h2 ; ||w||, H[j][j-1], S[j], breakdown test
+    e = launch_kernel(gs_update_norm_group, dim3(totals[5]), dim3(256), 0, s, items, b[5], n);
+    if (e != hipSuccess) return e;
+    return launch_kernel(finish_norm_group, dim3(n), dim3(256), 0, s, items);
 }
 
 hipError_t launch_dense_expm(const double *A, int n, double *E, hipStream_t s) {

@@ -1,0 +1,160 @@
+// Host runtime of the library (not part of the C ABI): the mesh / workspace
+// object, error reporting, live kernel timing, and the small helpers shared by
+// the stand-alone entry points and the solve server.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <vector>
+
+#include "internal.h"
+
+// Mesh, reference element, and the Krylov workspace of one solve.  All device
+// buffers are carved out of one contiguous block (owned by the mesh for the
+// stand-alone entry points, by the server's HBM arena for served solves).
+struct expdg_mesh {
+    expdg_mesh_desc d;
+    int nvar, n1, Np, K, dim;
+    size_t n;       // ndof
+    size_t stride;  // elements between Krylov vectors (>= n + kMaxAug)
+    int ebytes;     // bytes per bulk element
+    double hx, hy, dxmin;
+    double xi[expdg::kMaxP + 1], w[expdg::kMaxP + 1];
+    double D[(expdg::kMaxP + 1) * (expdg::kMaxP + 1)];
+
+    void *block = nullptr;       // the device block (owned iff owns_block)
+    bool owns_block = false;
+    void *V = nullptr;           // (m_max+1) x stride bulk
+    void *vec[6] = {};           // bulk work vectors (stride each)
+    void *bq[3] = {};            // bulk copies of FP64 states (FP32_BULK only)
+    double *q2 = nullptr;        // FP64 stage state (EXPRB32)
+    expdg::KrylovDev kd{};
+    double *slots = nullptr;     // 2 x kSlotSize
+    double *dnorm = nullptr;     // 8
+    double *spart = nullptr;     // 1024 (wave-speed partials)
+    double *pin = nullptr;       // pinned, device-mapped host mirror (kPinSize doubles)
+    double *pin_dev = nullptr;   // the device's address of pin
+    bool owns_pin = false;
+    hipEvent_t ev[2] = {nullptr, nullptr};   // check results ready (side stream)
+    hipEvent_t evH[2] = {nullptr, nullptr};  // Hessenberg column ready (main stream)
+    hipStream_t side = nullptr;              // small exponentials run here
+    size_t bytes = 0;
+
+    // live timing of one or more kernel classes
+    struct Prof {
+        bool on = false;
+        std::vector<hipEvent_t> ev;  // start/stop pairs
+        std::vector<double> bytes;   // algorithmic bytes per recorded launch
+        int used = 0;
+        long long launches = 0;
+        double ms = 0.0, total_bytes = 0.0;
+    } prof[EXPDG_K_NCLASSES];
+};
+
+namespace expdg {
+
+// pinned mirror layout (doubles)
+constexpr int kPinSlots = 0;    // 2 x 8: the header of each check slot
+constexpr int kPinNorms = 16;   // 8 input norms
+constexpr int kPinSpeed = 32;   // 1024 wave-speed partials (stand-alone only)
+constexpr int kPinServed = 32;  // doubles a served solve needs
+constexpr int kPinSize = 32 + 1024;
+
+// Records the message (thread-local, read by expdg_last_error) and returns code.
+int fail(int code, const char *fmt, ...);
+
+#define HIPTRY(call)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return ::expdg::fail(EXPDG_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+#define TRY(call)                        \
+    do {                                 \
+        int rc_ = (call);                \
+        if (rc_ != EXPDG_OK) return rc_; \
+    } while (0)
+
+#define CO_HIPTRY(call)                                                                        \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            co_return ::expdg::fail(EXPDG_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+#define CO_TRY(expr)                        \
+    do {                                    \
+        int rc_ = (expr);                   \
+        if (rc_ != EXPDG_OK) co_return rc_; \
+    } while (0)
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+// Two significant decimal digits, rounded up (step-size quantisation of the
+// controller, so that oracle and device take the same decisions).
+double round2(double x);
+
+// Description checks and workspace size of a mesh.
+bool desc_ok(const expdg_mesh_desc *d, const char **why);
+struct Sizes {
+    size_t n, stride, total;
+    int ebytes;
+};
+Sizes sizes_of(const expdg_mesh_desc *d);
+// Host tables and sizes of a mesh (no device work).
+void mesh_setup(expdg_mesh *m, const expdg_mesh_desc *d);
+// Points every device buffer into block (sizes_of(d).total bytes, 256-aligned).
+void mesh_carve(expdg_mesh *m, void *block);
+
+// Live timing of kernel class c around the next launch.
+int prof_begin(expdg_mesh *m, int c);
+int prof_end(expdg_mesh *m, int c, double bytes);
+
+template <typename T>
+OpArgs<T> op_args(const expdg_mesh *m) {
+    OpArgs<T> a{};
+    a.K = m->K;
+    a.nx = m->d.nx;
+    a.ny = m->d.ny;
+    a.rhx = (T)(2.0 / m->hx);
+    a.rhy = (T)(2.0 / m->hy);
+    a.lift = (T)(1.0 / m->w[0]);
+    a.gamma = (T)m->d.gamma;
+    for (int k = 0; k < m->n1 * m->n1; ++k) a.D[k] = (T)m->D[k];
+    a.eta = 1.0;
+    return a;
+}
+
+// Residual (jvp = false) or linear operator of the mesh on stream s.
+template <typename T>
+int apply_op(expdg_mesh *m, bool jvp, const T *q, const T *v, T *out, hipStream_t s) {
+    OpArgs<T> a = op_args<T>(m);
+    a.q = q;
+    a.v = v;
+    a.out = out;
+    const int cls = jvp ? EXPDG_K_LINEAR : EXPDG_K_RESIDUAL;
+    TRY(prof_begin(m, cls));
+    HIPTRY(launch_dg_op(m->d.equation, m->d.p, jvp, a, s));
+    TRY(prof_end(m, cls, (double)(jvp ? 3 : 2) * m->n * m->ebytes));
+    return EXPDG_OK;
+}
+
+// Validation of Krylov options against a mesh.
+int check_opts(const expdg_mesh *m, const expdg_krylov_opts *o);
+// Appends one accepted substep to the statistics.
+void log_sub(expdg_krylov_stats *st, int mm, int last, double dtau);
+
+}  // namespace expdg

@@ -1,0 +1,203 @@
+"""Solve server on the GPU, through the C ABI.
+
+A served solve runs the same controller and kernel bodies as expdg_step, so
+its final state must be bit-identical to the stand-alone step loop on its own
+mesh with the same options -- alone in the server, among other solves of
+other equations, sizes and degrees, under a small HBM budget that forces
+queueing, and next to solves that are cancelled.  One served solve is also
+compared with the oracle directly (FP64 tolerance as for expdg_step).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2011_01316_amd import binding as B
+from paper_2011_01316_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL, MMIN, MMAX = 1e-10, 6, 40
+
+
+def lgl_nodes(nx, ny, p, x0, x1, y0, y1, dim):
+    xi, _, _ = B.expdg_lgl(p)
+    hx = (x1 - x0) / nx
+    if dim == 1:
+        return (x0 + np.arange(nx)[:, None] * hx + 0.5 * (xi[None, :] + 1.0) * hx).ravel(), None
+    hy = (y1 - y0) / ny
+    ex = np.arange(nx * ny) % nx
+    ey = np.arange(nx * ny) // nx
+    i = np.arange((p + 1) ** 2) % (p + 1)
+    j = np.arange((p + 1) ** 2) // (p + 1)
+    x = x0 + ex[:, None] * hx + 0.5 * (xi[i][None, :] + 1.0) * hx
+    y = y0 + ey[:, None] * hy + 0.5 * (xi[j][None, :] + 1.0) * hy
+    return x.ravel(), y.ravel()
+
+
+def burgers_case(K, p, theta, nsteps=6, scheme=B.EPI3, dt=1e-2):
+    x, _ = lgl_nodes(K, 1, p, 0.0, 2 * math.pi, 0, 1, 1)
+    q0 = inputs.burgers_ic(x, theta)
+    req = B.make_request(B.BURGERS1D, K, p, scheme=scheme, nsteps=nsteps, dt=dt, tol=TOL,
+                         m_min=MMIN, m_max=MMAX, x0=0.0, x1=2 * math.pi)
+    return req, q0
+
+
+def euler_case(n, p, xc, yc, beta, nsteps=3, scheme=B.EPI3, dt=0.0, cfl=5.0):
+    x, y = lgl_nodes(n, n, p, 0.0, 10.0, 0.0, 10.0, 2)
+    q0 = inputs.vortex(x, y, beta=beta, xc=xc, yc=yc).ravel()
+    req = B.make_request(B.EULER2D, n, p, ny=n, scheme=scheme, nsteps=nsteps, dt=dt, cfl=cfl,
+                         tol=TOL, m_min=MMIN, m_max=MMAX, x0=0.0, x1=10.0, y0=0.0, y1=10.0)
+    return req, q0
+
+
+def standalone(req, q0):
+    """The same solve with expdg_step on its own mesh."""
+    d = req.mesh
+    m = B.Mesh(d.equation, d.nx, d.p, ny=d.ny, x0=d.x0, x1=d.x1, y0=d.y0, y1=d.y1,
+               gamma=d.gamma, m_max=d.m_max)
+    q = torch.tensor(q0, dtype=torch.float64, device="cuda")
+    qp = torch.zeros_like(q)
+    dt = req.dt if req.dt > 0 else req.cfl * m.dx_min / m.max_speed(q)
+    o = B.make_opts(req.tol, req.m_min, req.m_max, req.check_every)
+    for k in range(req.nsteps):
+        m.step(req.scheme, dt, q, qp if req.scheme == B.EPI3 else None, k > 0, o)
+    torch.cuda.synchronize()
+    out = q.cpu().numpy()
+    m.close()
+    return out, dt
+
+
+def serve_all(srv, cases):
+    """Submits every case, ticks until all finish, fetching each state as soon
+    as its solve is done (a finished state holds its memory until fetched)."""
+    ids = [srv.submit(r, q0) for r, q0 in cases]
+    done, guard = {}, 0
+    while len(done) < len(ids):
+        srv.tick(block=True)
+        for rid in srv.finished():
+            info = srv.poll(rid)
+            assert info["state"] == B.REQ_DONE, (rid, info)
+            done[rid] = (srv.fetch(rid), info)
+        guard += 1
+        assert guard < 200000, "server made no progress"
+    return {k: done[rid] for k, rid in enumerate(ids)}
+
+
+def test_single_served_solve_is_bitwise_the_stepper():
+    req, q0 = burgers_case(48, 3, 0.3)
+    want, dt = standalone(req, q0)
+    with B.Server(hbm_budget=1 << 30, max_active=8) as srv:
+        got = serve_all(srv, [(req, q0)])
+        q, info = got[0]
+        assert info["steps_done"] == req.nsteps and info["dt"] == dt
+        np.testing.assert_array_equal(q, want)
+        srv.sync()
+        assert srv.stats()["arena_used"] == 0
+
+
+def test_served_solve_matches_oracle():
+    req, q0 = burgers_case(32, 2, 0.0, nsteps=4, scheme=B.EPI3)
+    with B.Server(hbm_budget=1 << 30, max_active=4) as srv:
+        q, info = serve_all(srv, [(req, q0)])[0]
+    om = oracle.Mesh(oracle.BURGERS1D, 32, 2, x1=2 * math.pi)
+    o = dict(tol=TOL, m_min=MMIN, m_max=MMAX, check_every=1)
+    qo, qp = om.step(oracle.EPI3, 1e-2, q0, None, **o)
+    for _ in range(3):
+        qo, qp = om.step(oracle.EPI3, 1e-2, qo, qp, **o)
+    assert np.linalg.norm(q - qo) <= 1e-12 * np.linalg.norm(qo)
+
+
+def mixed_cases():
+    return [
+        burgers_case(40, 1, 0.1),
+        euler_case(10, 2, 4.0, 6.0, 3.0),
+        burgers_case(200, 4, 2.0, scheme=B.EPI2),
+        euler_case(12, 3, 5.0, 5.0, 5.0),
+        burgers_case(64, 2, 1.0),
+        euler_case(9, 4, 2.5, 7.5, 1.5, scheme=B.EPI2),
+        burgers_case(33, 3, 4.0, nsteps=9),
+        euler_case(14, 2, 7.0, 3.0, 4.0, nsteps=2),
+    ]
+
+
+def test_mixed_batch_is_bitwise_each_stepper():
+    cases = mixed_cases()
+    want = [standalone(r, q0)[0] for r, q0 in cases]
+    with B.Server(hbm_budget=4 << 30, max_active=64) as srv:
+        got = serve_all(srv, cases)
+        srv.sync()
+        st = srv.stats()
+        assert st["arena_used"] == 0 and st["active"] == 0 and st["queued"] == 0
+        # the solves really shared launches
+        assert st["arnoldi_items"] > st["ticks"]
+        assert st["check_items"] >= st["batched_checks"]
+    for k, w in enumerate(want):
+        np.testing.assert_array_equal(got[k][0], w, err_msg=f"case {k}")
+
+
+def test_small_budget_queues_and_stays_exact():
+    cases = mixed_cases()[:5]
+    need = [B.expdg_request_bytes(r) for r, _ in cases]
+    budget = max(need) + min(need) + (1 << 20)  # at most two solves fit at once
+    want = [standalone(r, q0)[0] for r, q0 in cases]
+    with B.Server(hbm_budget=budget, max_active=64) as srv:
+        got = serve_all(srv, cases)
+        srv.sync()
+        st = srv.stats()
+        assert st["arena_peak"] <= budget
+        assert st["arena_used"] == 0
+    for k, w in enumerate(want):
+        np.testing.assert_array_equal(got[k][0], w, err_msg=f"case {k}")
+
+
+def test_cancel_queued_and_running():
+    cases = mixed_cases()[:6]
+    want = {k: standalone(r, q0)[0] for k, (r, q0) in enumerate(cases)}
+    with B.Server(hbm_budget=4 << 30, max_active=3) as srv:
+        ids = [srv.submit(r, q0) for r, q0 in cases]
+        srv.cancel(ids[5])  # still queued (only 3 run at once)
+        for _ in range(5):
+            srv.tick(block=True)
+        srv.cancel(ids[1])  # running
+        done = {}
+        while len(done) < 4:
+            srv.tick(block=True)
+            for rid in srv.finished():
+                done[rid] = srv.poll(rid)
+        for k in (0, 2, 3, 4):
+            assert done[ids[k]]["state"] == B.REQ_DONE
+            np.testing.assert_array_equal(srv.fetch(ids[k]), want[k])
+        for k in (1, 5):
+            with pytest.raises(B.ExpdgError):
+                srv.poll(ids[k])
+        # memory of the cancelled running solve returns once the device is done
+        srv.sync()
+        assert srv.stats()["arena_used"] == 0
+
+
+def test_cfl_step_uses_the_wave_speed_of_q0():
+    req, q0 = euler_case(8, 3, 5.0, 5.0, 5.0, nsteps=1, dt=0.0, cfl=2.5)
+    want, dt = standalone(req, q0)
+    with B.Server(hbm_budget=1 << 30, max_active=4) as srv:
+        q, info = serve_all(srv, [(req, q0)])[0]
+    assert info["dt"] == dt
+    np.testing.assert_array_equal(q, want)
+
+
+def test_server_rejects_bad_requests():
+    with B.Server(hbm_budget=64 << 20, max_active=4) as srv:
+        req, q0 = burgers_case(32, 2, 0.0)
+        bad = B.make_request(B.BURGERS1D, 32, 2, scheme=B.EXPRB32, dt=1e-2)
+        with pytest.raises(B.ExpdgError):
+            srv.submit(bad, q0)
+        big, qb = euler_case(128, 4, 5, 5, 5)
+        with pytest.raises(B.ExpdgError):  # can never fit 64 MiB
+            srv.submit(big, qb)
+        req.mesh.precision = B.FP32_BULK
+        with pytest.raises(B.ExpdgError):
+            srv.submit(req, q0)
+        with pytest.raises(B.ExpdgError):
+            srv.poll(12345)

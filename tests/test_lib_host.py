@@ -73,3 +73,33 @@ def test_workspace_bytes_and_validation():
         assert B.expdg_workspace_bytes(desc(**bad)) == 0, bad
     h = C.c_void_p()
     assert B.lib().expdg_mesh_create(C.byref(desc(p=9)), C.byref(h)) == B.EINVAL
+
+
+def test_request_bytes_is_workspace_plus_two_states():
+    req = B.make_request(B.EULER2D, 20, 3, ny=20, nsteps=5, dt=1e-2, x1=10.0, y1=10.0)
+    ws = B.expdg_workspace_bytes(req.mesh)
+    ndof = 4 * 20 * 20 * 16
+    stride = (ndof + 3 + 63) // 64 * 64
+    st = 2 * ((stride * 8 + 255) // 256 * 256)
+    assert B.expdg_request_bytes(req) == (ws + 255) // 256 * 256 + st
+
+
+@pytest.mark.parametrize("field,value", [("scheme", B.EXPRB32), ("nsteps", 0), ("tol", 0.0),
+                                         ("m_min", 0), ("check_every", 0)])
+def test_invalid_requests_size_to_zero(field, value):
+    req = B.make_request(B.BURGERS1D, 64, 2, dt=1e-2)
+    assert B.expdg_request_bytes(req) > 0
+    setattr(req, field, value)
+    assert B.expdg_request_bytes(req) == 0
+
+
+def test_request_needs_fp64_a_step_and_krylov_room():
+    req = B.make_request(B.BURGERS1D, 64, 2, dt=1e-2)
+    req.mesh.precision = B.FP32_BULK
+    assert B.expdg_request_bytes(req) == 0
+    req = B.make_request(B.BURGERS1D, 64, 2, dt=0.0, cfl=0.0)
+    assert B.expdg_request_bytes(req) == 0
+    req = B.make_request(B.BURGERS1D, 64, 2, dt=0.0, cfl=2.0)
+    assert B.expdg_request_bytes(req) > 0
+    req = B.make_request(B.BURGERS1D, 64, 2, dt=1e-2, m_max=40, mesh_m_max=30)
+    assert B.expdg_request_bytes(req) == 0
