@@ -16,7 +16,11 @@ in the timed steps) / wall time of the timed steps.
 Then: the same steps again with live HIP-event timing of every kernel class
 (roofline of the dominant main-stream kernel and of the linear operator), the
 FP32-bulk variant of the same workload, the FP64 / FP32-bulk comparison on the
-256 x 256, p = 3 vortex (4,194,304 DOF), and the FP64 oracle on the host cores
+256 x 256, p = 3 vortex (4,194,304 DOF), the served workload (2000 solves of
+20 EPI3 steps arriving as a Poisson stream at 200/s, 50/50 Burgers / Euler,
+sizes log-uniform; p50 / p99 arrival-to-completion latency and solves/s
+through the solve server, and the same first requests run one after another
+through expdg_step for comparison), and the FP64 oracle on the host cores
 over a bounded sample.  Prints one JSON line.
 """
 import argparse
@@ -193,6 +197,97 @@ def run_gpu(args):
     return out
 
 
+SERVED = dict(n_requests=2000, rate=200.0, seed=0, steps=20, tol=1e-10, m_min=10, m_max=64,
+              name="served mix: 2000 solves, Poisson arrivals 200/s (seed 0), 50/50 Burgers "
+                   "(K log-uniform 32..4096, p 1..4, dt 1e-2) / Euler vortex (n x n log-uniform "
+                   "16..128, p 2..4, Courant 5), 20 EPI3 steps each, FP64, tol 1e-10")
+
+
+def run_served(args):
+    import numpy as np
+    import torch
+
+    from paper_2011_01316_amd import binding as B
+    from paper_2011_01316_amd import inputs, serving
+
+    w = SERVED
+    t = time.time()
+    mix = inputs.served_mix(n_requests=args.serve_requests, rate=w["rate"], seed=w["seed"],
+                            steps=w["steps"])
+    items = serving.prepare(mix, tol=w["tol"], m_min=w["m_min"], m_max=w["m_max"])
+    log(f"served: {len(items)} requests prepared in {time.time() - t:.1f}s")
+    torch.zeros(1, device="cuda")
+    srv = B.Server(hbm_budget=int(args.serve_budget_gib * (1 << 30)),
+                   max_active=args.serve_max_active)
+    marks = [time.time()]
+
+    def progress(done, n):
+        if time.time() - marks[0] > 5.0:
+            marks[0] = time.time()
+            log(f"served: {done}/{n} done at {srv.clock():.1f}s")
+
+    res = serving.run(srv, items, progress=progress)
+    srv.sync()
+    st = srv.stats()
+    srv.close()
+    log(f"served: {res['completed']} solves, {res['solves_per_s']:.1f}/s, "
+        f"p50 {res['latency_p50_s']:.2f}s p99 {res['latency_p99_s']:.2f}s")
+    out = dict(
+        workload=w["name"], requests=res["requests"], completed=res["completed"],
+        failed=[dict(request=k, status=e, **{x: mix[k][x] for x in ("equation", "nx", "p")})
+                for k, e in res["failed"]],
+        latency_p50_s=round(res["latency_p50_s"], 4), latency_p99_s=round(res["latency_p99_s"], 4),
+        latency_max_s=round(res["latency_max_s"], 4),
+        admission_wait_p50_s=round(res["admission_wait_p50_s"], 4),
+        admission_wait_p99_s=round(res["admission_wait_p99_s"], 4),
+        solves_per_s=round(res["solves_per_s"], 2), makespan_s=round(res["makespan_s"], 3),
+        dof_stage_updates_per_s=round(res["dof_stage_updates_per_s"], 1),
+        hbm_budget_gib=args.serve_budget_gib, max_active=args.serve_max_active,
+        arena_peak_gib=round(st["arena_peak"] / (1 << 30), 3),
+        ticks=st["ticks"], arnoldi_steps_per_tick=round(st["arnoldi_items"] / max(1, st["ticks"]), 2),
+        checks_per_batched_launch=round(st["check_items"] / max(1, st["batched_checks"]), 2),
+        grouped_launches=st["grouped_launches"])
+
+    # the first requests one after another through expdg_step
+    K = min(args.serve_seq, len(items))
+    t = time.time()
+    work = 0.0
+    for it in items[:K]:
+        r = it["req"]
+        d = r.mesh
+        m = B.Mesh(d.equation, d.nx, d.p, ny=d.ny, x0=d.x0, x1=d.x1, y0=d.y0, y1=d.y1,
+                   m_max=d.m_max)
+        q = torch.tensor(it["q0"], dtype=torch.float64, device="cuda")
+        qp = torch.zeros_like(q)
+        dt = r.dt if r.dt > 0 else r.cfl * m.dx_min / m.max_speed(q)
+        o = B.make_opts(r.tol, r.m_min, r.m_max, r.check_every)
+        st = B.make_stats(1)
+        try:
+            for k in range(r.nsteps):
+                m.step(r.scheme, dt, q, qp, k > 0, o, st)
+        except B.ExpdgError:
+            pass
+        work += it["ndof"] * (st.rhs_calls + st.jvps)
+        m.close()
+    torch.cuda.synchronize()
+    el = time.time() - t
+    seq = dict(requests=K, seconds=round(el, 3), solves_per_s=round(K / el, 2),
+               dof_stage_updates_per_s=round(work / el, 1))
+    # the same first requests through the server, arriving all at once
+    srv = B.Server(hbm_budget=int(args.serve_budget_gib * (1 << 30)),
+                   max_active=args.serve_max_active)
+    batch = [dict(it, arrival=0.0) for it in items[:K]]
+    rb = serving.run(srv, batch)
+    srv.close()
+    seq["served_all_at_once"] = dict(seconds=round(rb["makespan_s"], 3),
+                                     solves_per_s=round(rb["solves_per_s"], 2),
+                                     dof_stage_updates_per_s=round(rb["dof_stage_updates_per_s"], 1))
+    out["first_requests_compared"] = seq
+    log(f"served: first {K} sequential {seq['solves_per_s']}/s vs server "
+        f"{seq['served_all_at_once']['solves_per_s']}/s")
+    return out
+
+
 def run_cpu_baseline(args):
     import oracle
     from paper_2011_01316_amd import inputs
@@ -252,6 +347,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=200)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=SERVED["n_requests"])
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--serve-max-active", type=int, default=256)
+    ap.add_argument("--serve-seq", type=int, default=40,
+                    help="first requests also run one after another for comparison")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only time a plain 1 GiB device copy and print it")
     args = ap.parse_args()
@@ -341,6 +442,8 @@ def main():
             gs_update_dots_roofline=roof(pb["gs_update_dots"], "gs_update_dots",
                                          B.KERNEL_SYMBOLS["gs_update_dots"]),
             gs_dots_roofline=roof(pb["gs_dots"], "gs_dots", B.KERNEL_SYMBOLS["gs_dots"]))
+    if not args.no_serve:
+        line["served"] = run_served(args)
     line["cpu_baseline"] = None if args.no_cpu_baseline else run_cpu_baseline(args)
     print(json.dumps(line), flush=True)
 
