@@ -198,8 +198,8 @@ enum {
     EXPDG_K_GS_DOTS = 2,        /* Gram-Schmidt first pass: block partials of V^T w */
     EXPDG_K_SMALLEXPM = 3,      /* exponential of the projected Hessenberg matrix */
     EXPDG_K_COMBINE = 4,        /* Krylov combine z = beta V F e_1 */
-    EXPDG_K_GS_UPDATE_DOTS = 5, /* second pass: w -= V h, partials of V^T w */
-    EXPDG_K_GS_UPDATE_NORM = 6, /* w -= V h, partials of ||w||^2 */
+    EXPDG_K_GS_UPDATE_DOTS = 5, /* second pass: w -= V h1, partials of V^T w and ||w||^2 */
+    EXPDG_K_GS_UPDATE_NORM = 6, /* final update w -= V h2 (at a substep start: ||z||^2) */
     EXPDG_K_GS_FINISH = 7,      /* fixed-order sums of the block partials */
     EXPDG_K_NCLASSES = 8
 };

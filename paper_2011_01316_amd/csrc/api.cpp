@@ -137,6 +137,12 @@ bool desc_ok(const expdg_mesh_desc *d, const char **why) {
     if (d->nx < 1 || d->ny < 1) return *why = "nx and ny must be >= 1", false;
     if (d->equation == EXPDG_BURGERS1D && d->ny != 1) return *why = "Burgers needs ny == 1", false;
     if ((long long)d->nx * d->ny > (1LL << 26)) return *why = "too many elements", false;
+    {
+        // the kernels address one variable plane with 32-bit byte offsets
+        const long long np = (d->equation == EXPDG_BURGERS1D) ? (d->p + 1) : (d->p + 1) * (d->p + 1);
+        if ((long long)d->nx * d->ny * np > (1LL << 29) - 1)
+            return *why = "too many nodes (at most 2^29 - 1 per variable)", false;
+    }
     if (d->precision != EXPDG_FP64 && d->precision != EXPDG_FP32_BULK)
         return *why = "precision must be EXPDG_FP64 or EXPDG_FP32_BULK", false;
     if (!(d->x1 > d->x0) || !std::isfinite(d->x0) || !std::isfinite(d->x1))
@@ -169,6 +175,8 @@ size_t layout(expdg_mesh *m, const expdg_mesh_desc *d, size_t stride, int eb, ch
     if (d->precision == EXPDG_FP32_BULK)
         for (auto &v : m->bq) take(v, vb);
     take(m->q2, stride * 8);
+    const size_t nlin = lin_elems(d->equation, d->p, d->nx * d->ny);
+    if (nlin) take(m->lin, nlin * eb);
     take(m->kd.H, (size_t)(kMaxM + 1) * kMaxM * 8);
     take(m->kd.S, (size_t)(kMaxM + 1) * 8);
     take(m->kd.coefA, (size_t)(kMaxM + 1) * 8);
@@ -410,8 +418,11 @@ extern "C" int expdg_jvp(expdg_mesh *m, const void *qref, const void *v, void *w
     if (v == w || qref == w) return fail(EXPDG_EINVAL, "output must not alias an input");
     DeviceGuard g(m->d.device);
     hipStream_t s = (hipStream_t)stream;
-    if (m->d.precision == EXPDG_FP64)
+    if (m->d.precision == EXPDG_FP64) {
+        HIPTRY(prepare_lin<double>(m, (const double *)qref, s));
         return apply_op<double>(m, true, (const double *)qref, (const double *)v, (double *)w, s);
+    }
+    HIPTRY(prepare_lin<float>(m, (const float *)qref, s));
     return apply_op<float>(m, true, (const float *)qref, (const float *)v, (float *)w, s);
 }
 
@@ -518,21 +529,20 @@ struct DirectExec {
         TRY(prof_begin(m, EXPDG_K_GS_FINISH));
         HIPTRY(launch_gs_finish_dots(kd.part, j, rp, kd.S, kd.H, col, 0, kd.coefA, s));
         TRY(prof_end(m, EXPDG_K_GS_FINISH, fin_bytes));
-        // (j > 32: a plain update then a dot pass, 2j + 3 vectors of traffic)
+        // second pass with ||w||^2 (j > 32: a plain update then a dot pass,
+        // 2j + 4 vectors of traffic)
         TRY(prof_begin(m, EXPDG_K_GS_UPDATE_DOTS));
         HIPTRY(launch_gs_update_dots<T>(V, stride, j, kd.coefA, w, L, rp, kd.part, kd.S, kd.H, col,
                                         kd.coefB, s));
-        TRY(prof_end(m, EXPDG_K_GS_UPDATE_DOTS, (double)(j <= 32 ? j + 2 : 2 * j + 3) * L * eb));
+        TRY(prof_end(m, EXPDG_K_GS_UPDATE_DOTS, (double)(j <= 32 ? j + 2 : 2 * j + 4) * L * eb));
+        // h2, the norm of the orthogonalised vector (Pythagoras), S[j], breakdown test
         TRY(prof_begin(m, EXPDG_K_GS_FINISH));
-        HIPTRY(launch_gs_finish_dots(kd.part, j, rp, kd.S, kd.H, col, 1, kd.coefB, s));
-        TRY(prof_end(m, EXPDG_K_GS_FINISH, fin_bytes));
+        HIPTRY(launch_gs_finish_pass2(kd.part, j, rp, kd.S, kd.H, col, kd.coefB, kd.flags, s));
+        TRY(prof_end(m, EXPDG_K_GS_FINISH, fin_bytes + 8.0 * rp.nrb));
+        // w -= V h2
         TRY(prof_begin(m, EXPDG_K_GS_UPDATE_NORM));
-        HIPTRY(launch_gs_update_norm<T>(V, stride, j, kd.coefB, w, L, rp, kd.part, kd.H, kd.S, col,
-                                        kd.flags, kd.res, s));
+        HIPTRY(launch_gs_update<T>(V, stride, j, kd.coefB, w, L, rp, s));
         TRY(prof_end(m, EXPDG_K_GS_UPDATE_NORM, (double)(j + 2) * L * eb));
-        TRY(prof_begin(m, EXPDG_K_GS_FINISH));
-        HIPTRY(launch_gs_finish_norm(kd.part, rp, kd.H, kd.S, col, kd.flags, kd.res, s));
-        TRY(prof_end(m, EXPDG_K_GS_FINISH, 8.0 * rp.nrb));
         if (cr) TRY(enqueue_check(m, *cr, c));
         return EXPDG_OK;
     }
@@ -591,11 +601,11 @@ extern "C" int expdg_phi_krylov(expdg_mesh *m, const void *qref, double tau, int
     if (m->d.precision == EXPDG_FP64) {
         DirectExec<double> x{st};
         return run_now(phi_co<double>(x, m, (const double *)qref, tau, p, (const double *const *)b,
-                                      (double *)w, o, s, &fpos));
+                                      (double *)w, o, s, &fpos, false));
     }
     DirectExec<float> x{st};
     return run_now(phi_co<float>(x, m, (const float *)qref, tau, p, (const float *const *)b,
-                                 (float *)w, o, s, &fpos));
+                                 (float *)w, o, s, &fpos, false));
 }
 
 extern "C" int expdg_step(expdg_mesh *m, int scheme, double dt, double *q, double *q_prev,

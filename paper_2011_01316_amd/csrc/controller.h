@@ -161,10 +161,11 @@ struct PhiRun {
 
 // w = sum_{k=0}^{p} tau^k phi_k(tau L~) b_k by the augmented Krylov method
 // (Section 2.3), with L~ the linear operator frozen at qref.  b[k] == nullptr
-// is a zero vector.  *fpos walks a forced substep schedule.
+// is a zero vector.  *fpos walks a forced substep schedule.  lin_ready: the
+// frozen fields of qref are already in the workspace.
 template <typename T, typename X>
 Task<int> phi_co(X &x, expdg_mesh *m, const T *qref, double tau, int p, const T *const *b, T *out,
-                 const expdg_krylov_opts *o, expdg_krylov_stats *st, int *fpos) {
+                 const expdg_krylov_opts *o, expdg_krylov_stats *st, int *fpos, bool lin_ready) {
     hipStream_t s = x.stream();
     const size_t n = m->n, L = n + (size_t)p;
     const size_t stride = m->stride;
@@ -212,8 +213,10 @@ Task<int> phi_co(X &x, expdg_mesh *m, const T *qref, double tau, int p, const T 
     if (p > 0) CO_HIPTRY(launch_set_tail<T>(V + n, p, 1.0 / eta, s));
     CO_HIPTRY(launch_fill<int>(kd.flags, 0.0, 4, s));
 
+    if (!lin_ready) CO_HIPTRY(prepare_lin<T>(m, qref, s));
     OpArgs<T> a = op_args<T>(m);
     a.q = qref;
+    a.lin = (const T *)m->lin;
     a.eta = eta;
     a.naug = p;
     int naug_nz = 0;
@@ -360,12 +363,14 @@ Task<int> step_co(X &x, expdg_mesh *m, int scheme, double dt, double *q, double 
     int fpos = 0;
     T *qb = nullptr;
     CO_HIPTRY(view(q, 0, &qb));
+    // every linear operator of the step is frozen at q^n
+    CO_HIPTRY(prepare_lin<T>(m, qb, s));
     CO_TRY(apply_op<T>(m, false, qb, nullptr, Rn, s));
     if (st) st->rhs_calls += 1;
 
     if (scheme == EXPDG_EPI2 || (scheme == EXPDG_EPI3 && !(q_prev && have_prev))) {
         const T *b[2] = {nullptr, Rn};
-        CO_AWAIT_TASK((phi_co<T, X>(x, m, qb, dt, 1, b, w, o, st, &fpos)));
+        CO_AWAIT_TASK((phi_co<T, X>(x, m, qb, dt, 1, b, w, o, st, &fpos, true)));
         if (q_prev) CO_HIPTRY(launch_copy(q, q_prev, n, s));
         CO_HIPTRY(launch_add_to<T>(q, w, n, s));
     } else if (scheme == EXPDG_EPI3) {
@@ -381,12 +386,12 @@ Task<int> step_co(X &x, expdg_mesh *m, int scheme, double dt, double *q, double 
         const double c = 2.0 / (3.0 * dt);
         CO_HIPTRY((launch_lincomb<T, T>(d, c, Rp, -c, Rn, -c, Ld, n, s)));  // b_2 into d
         const T *b[3] = {nullptr, Rn, d};
-        CO_AWAIT_TASK((phi_co<T, X>(x, m, qb, dt, 2, b, w, o, st, &fpos)));
+        CO_AWAIT_TASK((phi_co<T, X>(x, m, qb, dt, 2, b, w, o, st, &fpos, true)));
         CO_HIPTRY(launch_copy(q, q_prev, n, s));
         CO_HIPTRY(launch_add_to<T>(q, w, n, s));
     } else {  // EXPRB32
         const T *b1[2] = {nullptr, Rn};
-        CO_AWAIT_TASK((phi_co<T, X>(x, m, qb, dt, 1, b1, w, o, st, &fpos)));
+        CO_AWAIT_TASK((phi_co<T, X>(x, m, qb, dt, 1, b1, w, o, st, &fpos, true)));
         CO_HIPTRY(launch_add_mixed<T>(m->q2, q, w, n, s));  // q2 = q^n + w1
         T *q2b = nullptr;
         CO_HIPTRY(view(m->q2, 2, &q2b));
@@ -400,7 +405,7 @@ Task<int> step_co(X &x, expdg_mesh *m, int scheme, double dt, double *q, double 
         const double c = 2.0 / (dt * dt);
         CO_HIPTRY((launch_lincomb<T, T>(d, c, Rp, -c, Rn, -c, Ld, n, s)));  // b_3 into d
         const T *b[4] = {nullptr, nullptr, nullptr, d};
-        CO_AWAIT_TASK((phi_co<T, X>(x, m, qb, dt, 3, b, w2, o, st, &fpos)));
+        CO_AWAIT_TASK((phi_co<T, X>(x, m, qb, dt, 3, b, w2, o, st, &fpos, true)));
         if (q_prev) CO_HIPTRY(launch_copy(q, q_prev, n, s));
         CO_HIPTRY(launch_add_mixed<T>(q, m->q2, w2, n, s));
     }

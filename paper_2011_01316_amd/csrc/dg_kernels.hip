@@ -109,13 +109,106 @@ __device__ __forceinline__ T euler_speed(const T *q, T gamma) {
     return fabs(DIR == 0 ? u : v) + sqrt(gamma * p * ir);
 }
 
+// The same directional derivatives from the frozen fields w = (u, v, H) of
+// the reference state (linear operator; no division or square root), with
+// alpha = dm - u drho, beta = dn - v drho:
+//   dp = (g-1)(dE - u alpha - v beta - |u|^2/2 drho),
+//   dF_x = (dm, u (dm + alpha) + dp, u dn + v alpha, u (dE + dp) + H alpha),
+//   dF_y = (dn, u dn + v alpha, v (dn + beta) + dp, v (dE + dp) + H beta).
+template <typename T>
+__device__ __forceinline__ void euler_jac_lin(const T *w, const T *d, T gm1, T *fx, T *fy) {
+    const T u = w[0], v = w[1], H = w[2];
+    const T al = fma(-u, d[0], d[1]), be = fma(-v, d[0], d[2]);
+    const T k = T(0.5) * fma(u, u, v * v);
+    const T dp = gm1 * fma(-k, d[0], fma(-v, be, fma(-u, al, d[3])));
+    const T ep = d[3] + dp;
+    const T cross = fma(u, d[2], v * al);
+    fx[0] = d[1];
+    fx[1] = fma(u, d[1] + al, dp);
+    fx[2] = cross;
+    fx[3] = fma(u, ep, H * al);
+    fy[0] = d[2];
+    fy[1] = cross;
+    fy[2] = fma(v, d[2] + be, dp);
+    fy[3] = fma(v, ep, H * be);
+}
+
+template <typename T, int DIR>
+__device__ __forceinline__ void euler_jac_lin_dir(const T *w, const T *d, T gm1, T *f) {
+    T fx[4], fy[4];
+    euler_jac_lin(w, d, gm1, fx, fy);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) f[c] = DIR == 0 ? fx[c] : fy[c];
+}
+
+// Load of base[off] through a 32-bit byte offset from a block-uniform base
+// (one addressing instruction instead of 64-bit index arithmetic); callers
+// keep every plane below 2^32 bytes.
+template <typename T>
+__device__ __forceinline__ T ld32(const T *base, unsigned off) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) +
+                                        (unsigned)(off * (unsigned)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ void st32(T *base, unsigned off, T v) {
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + (unsigned)(off * (unsigned)sizeof(T))) =
+        v;
+}
+
+// Frozen fields of the linear operator at the reference state q~ (computed
+// once per reference state): planes u, v, H, then the Rusanov speed of every
+// x face, lamx[e (p+1) + j] = max(|u|+a) over the face between element e and
+// its x+ neighbour at node row j, and of every y face, lamy[e (p+1) + i].
+template <int P, typename T>
+__global__ __launch_bounds__(256) void euler_lin_prepare(const T *q, T *lin, int K, int nx, int ny,
+                                                         T gamma) {
+    constexpr int N1 = P + 1, NP = N1 * N1;
+    const size_t plane = (size_t)K * NP;
+    const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= plane) return;
+    const int e = (int)(t / NP), n = (int)(t - (size_t)e * NP);
+    const int i = n % N1, j = n / N1;
+    T qq[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) qq[c] = q[c * plane + t];
+    const T ir = T(1) / qq[0];
+    const T u = qq[1] * ir, v = qq[2] * ir;
+    const T p = (gamma - T(1)) * (qq[3] - T(0.5) * (qq[1] * u + qq[2] * v));
+    lin[t] = u;
+    lin[plane + t] = v;
+    lin[2 * plane + t] = (qq[3] + p) * ir;
+    T *lamx = lin + 3 * plane, *lamy = lamx + (size_t)K * N1;
+    const int ex = e % nx, ey = e / nx;
+    if (i == P) {
+        const int en = ey * nx + (ex + 1 == nx ? 0 : ex + 1);
+        const size_t nidx = (size_t)en * NP + j * N1;
+        T qn[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) qn[c] = q[c * plane + nidx];
+        lamx[(size_t)e * N1 + j] = fmax(euler_speed<T, 0>(qq, gamma), euler_speed<T, 0>(qn, gamma));
+    }
+    if (j == P) {
+        const int en = (ey + 1 == ny ? 0 : ey + 1) * nx + ex;
+        const size_t nidx = (size_t)en * NP + i;
+        T qn[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) qn[c] = q[c * plane + nidx];
+        lamy[(size_t)e * N1 + i] = fmax(euler_speed<T, 1>(qq, gamma), euler_speed<T, 1>(qn, gamma));
+    }
+}
+
 // ---- Euler 2D operator ------------------------------------------------------
 // One tile (floor(256/Np) elements) of the operator; first marks the item's
-// first block, which also writes the augmented entries of the output.
+// first block, which also writes the augmented entries of the output.  The
+// linear operator reads the frozen fields of euler_lin_prepare (a.lin), the
+// residual the state itself.  Face and augmented terms need no LDS and are
+// added before the barrier; -(2/h) D is staged in LDS for the derivative.
+// Node offsets are 32-bit within one variable plane.
 template <int P, typename T, bool JVP>
 __device__ __forceinline__ void euler_op_body(const OpArgs<T> &a, int tile, bool first) {
     constexpr int N1 = P + 1, NP = N1 * N1, EPB = 256 / NP, NT = EPB * NP;
     __shared__ T sF[8][NT];
+    __shared__ T sDx[N1 * N1], sDy[N1 * N1];
     const int tid = threadIdx.x;
     const int le = tid / NP;
     const int n = tid - le * NP;
@@ -123,8 +216,19 @@ __device__ __forceinline__ void euler_op_body(const OpArgs<T> &a, int tile, bool
     const int e = tile * EPB + le;
     const bool active = (tid < NT) && (e < a.K);
     const size_t plane = (size_t)a.K * NP;
-    const size_t idx = (size_t)e * NP + n;
+    const unsigned idx = (unsigned)e * NP + n;
     const T gm1 = a.gamma - T(1);
+    if (tid < N1 * N1) {
+        sDx[tid] = -a.rhx * a.D[tid];
+        sDy[tid] = -a.rhy * a.D[tid];
+    }
+    // block-uniform plane pointers
+    const T *src[4], *vin[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        src[c] = (JVP ? a.lin : a.q) + c * plane;  // lin: u, v, H planes (the fourth unused)
+        vin[c] = JVP ? a.v + c * plane : src[c];
+    }
 
     T sc = T(1);
     if (a.vscale) sc = (T)(*a.vscale);
@@ -134,17 +238,19 @@ __device__ __forceinline__ void euler_op_body(const OpArgs<T> &a, int tile, bool
             a.otail[k] = (k + 1 < a.naug) ? sc * a.vtail[k + 1] : T(0);
     }
 
+    const int ex = e % a.nx, ey = e / a.nx;
+    const T *lamx = a.lin + 3 * plane, *lamy = lamx + (size_t)a.K * N1;
     T q[4], u[4], fx[4], fy[4];
     if (active) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) q[c] = a.q[c * plane + idx];
         if (JVP) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) u[c] = a.v[c * plane + idx];
-            euler_jac(q, u, gm1, fx, fy);
+            for (int c = 0; c < 3; ++c) q[c] = ld32(src[c], idx);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) u[c] = ld32(vin[c], idx);
+            euler_jac_lin(q, u, gm1, fx, fy);
         } else {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) u[c] = q[c];
+            for (int c = 0; c < 4; ++c) q[c] = u[c] = ld32(src[c], idx);
             euler_flux(q, gm1, fx, fy);
         }
     } else {
@@ -158,80 +264,86 @@ __device__ __forceinline__ void euler_op_body(const OpArgs<T> &a, int tile, bool
             sF[4 + c][tid] = fy[c];
         }
     }
-    __syncthreads();
-    if (!active) return;
 
     T res[4] = {T(0), T(0), T(0), T(0)};
-    const int base = le * NP;
-#pragma unroll
-    for (int l = 0; l < N1; ++l) {
-        const T dx = a.rhx * a.D[i * N1 + l];
-        const T dy = a.rhy * a.D[j * N1 + l];
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-            res[c] -= dx * sF[c][base + j * N1 + l] + dy * sF[4 + c][base + l * N1 + i];
-    }
-
-    const int ex = e % a.nx, ey = e / a.nx;
-    if (i == 0 || i == P) {
+    if (active && (i == 0 || i == P)) {
         const int s = (i == P) ? 1 : -1;
         int exn = ex + s;
         exn = exn < 0 ? a.nx - 1 : (exn >= a.nx ? 0 : exn);
-        const size_t nidx = (size_t)(ey * a.nx + exn) * NP + j * N1 + (P - i);
-        T qn[4], un[4], fn[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) qn[c] = a.q[c * plane + nidx];
+        const int en = ey * a.nx + exn;
+        const unsigned nidx = (unsigned)en * NP + j * N1 + (P - i);
+        T qn[4], un[4], fn[4], lam;
         if (JVP) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) un[c] = a.v[c * plane + nidx];
-            euler_jac_dir<T, 0>(qn, un, gm1, fn);
+            for (int c = 0; c < 3; ++c) qn[c] = ld32(src[c], nidx);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) un[c] = ld32(vin[c], nidx);
+            euler_jac_lin_dir<T, 0>(qn, un, gm1, fn);
+            lam = ld32(lamx, (unsigned)(s > 0 ? e : en) * N1 + j);
         } else {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) un[c] = qn[c];
+            for (int c = 0; c < 4; ++c) qn[c] = un[c] = ld32(src[c], nidx);
             euler_flux_dir<T, 0>(qn, gm1, fn);
+            lam = fmax(euler_speed<T, 0>(q, a.gamma), euler_speed<T, 0>(qn, a.gamma));
         }
-        const T lam = fmax(euler_speed<T, 0>(q, a.gamma), euler_speed<T, 0>(qn, a.gamma));
+        // res -= (2/h)(1/w_0) [ s (F_n - F)/2 + lam (u - u_n)/2 ]
         const T cf = a.rhx * a.lift;
-        const T hs = T(0.5) * T(s);
+        const T ca = cf * T(0.5) * T(s), cb = cf * T(0.5) * lam;
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-            res[c] -= cf * (hs * (fn[c] - fx[c]) + T(0.5) * lam * (u[c] - un[c]));
+        for (int c = 0; c < 4; ++c) res[c] = fma(-cb, u[c] - un[c], fma(-ca, fn[c] - fx[c], res[c]));
     }
-    if (j == 0 || j == P) {
+    if (active && (j == 0 || j == P)) {
         const int s = (j == P) ? 1 : -1;
         int eyn = ey + s;
         eyn = eyn < 0 ? a.ny - 1 : (eyn >= a.ny ? 0 : eyn);
-        const size_t nidx = (size_t)(eyn * a.nx + ex) * NP + (P - j) * N1 + i;
-        T qn[4], un[4], fn[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) qn[c] = a.q[c * plane + nidx];
+        const int en = eyn * a.nx + ex;
+        const unsigned nidx = (unsigned)en * NP + (P - j) * N1 + i;
+        T qn[4], un[4], fn[4], lam;
         if (JVP) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) un[c] = a.v[c * plane + nidx];
-            euler_jac_dir<T, 1>(qn, un, gm1, fn);
+            for (int c = 0; c < 3; ++c) qn[c] = ld32(src[c], nidx);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) un[c] = ld32(vin[c], nidx);
+            euler_jac_lin_dir<T, 1>(qn, un, gm1, fn);
+            lam = ld32(lamy, (unsigned)(s > 0 ? e : en) * N1 + i);
         } else {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) un[c] = qn[c];
+            for (int c = 0; c < 4; ++c) qn[c] = un[c] = ld32(src[c], nidx);
             euler_flux_dir<T, 1>(qn, gm1, fn);
+            lam = fmax(euler_speed<T, 1>(q, a.gamma), euler_speed<T, 1>(qn, a.gamma));
         }
-        const T lam = fmax(euler_speed<T, 1>(q, a.gamma), euler_speed<T, 1>(qn, a.gamma));
         const T cf = a.rhy * a.lift;
-        const T hs = T(0.5) * T(s);
+        const T ca = cf * T(0.5) * T(s), cb = cf * T(0.5) * lam;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) res[c] = fma(-cb, u[c] - un[c], fma(-ca, fn[c] - fy[c], res[c]));
+    }
+    // augmented block: + eta sum_k y_k b_{p+1-k}
+    if (active) {
+        for (int k = 0; k < a.naug; ++k) {
+            const T *b = a.aug[k];
+            if (!b) continue;
+            const T yk = (T)a.eta * a.vtail[k];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) res[c] = fma(yk, ld32(b + c * plane, idx), res[c]);
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+
+    const int base = le * NP;
+#pragma unroll
+    for (int l = 0; l < N1; ++l) {
+        const T dx = sDx[i * N1 + l];
+        const T dy = sDy[j * N1 + l];
 #pragma unroll
         for (int c = 0; c < 4; ++c)
-            res[c] -= cf * (hs * (fn[c] - fy[c]) + T(0.5) * lam * (u[c] - un[c]));
+            res[c] = fma(dy, sF[4 + c][base + l * N1 + i], fma(dx, sF[c][base + j * N1 + l], res[c]));
     }
-
-    // augmented block: + eta sum_k y_k b_{p+1-k}
-    for (int k = 0; k < a.naug; ++k) {
-        const T *b = a.aug[k];
-        if (!b) continue;
-        const T yk = (T)a.eta * a.vtail[k];
+    T *out[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) res[c] += yk * b[c * plane + idx];
-    }
+    for (int c = 0; c < 4; ++c) out[c] = a.out + c * plane;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) a.out[c * plane + idx] = sc * res[c];
+    for (int c = 0; c < 4; ++c) st32(out[c], idx, sc * res[c]);
 }
 
 // ---- Burgers 1D operator ----------------------------------------------------
@@ -435,6 +547,32 @@ int grid_for(size_t n) {
 }
 
 }  // namespace
+
+template <typename T>
+hipError_t launch_lin_prepare(int equation, int p, const T *q, T *lin, int K, int nx, int ny,
+                              double gamma, hipStream_t s) {
+    if (equation != EXPDG_EULER2D) return hipSuccess;  // Burgers reads the state itself
+    const size_t npts = (size_t)K * (p + 1) * (p + 1);
+    const dim3 grid((unsigned)((npts + 255) / 256));
+    switch (p) {
+        case 1: return launch_kernel(euler_lin_prepare<1, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, (T)gamma);
+        case 2: return launch_kernel(euler_lin_prepare<2, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, (T)gamma);
+        case 3: return launch_kernel(euler_lin_prepare<3, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, (T)gamma);
+        case 4: return launch_kernel(euler_lin_prepare<4, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, (T)gamma);
+        case 5: return launch_kernel(euler_lin_prepare<5, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, (T)gamma);
+        case 6: return launch_kernel(euler_lin_prepare<6, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, (T)gamma);
+        default: return hipErrorInvalidValue;
+    }
+}
+template hipError_t launch_lin_prepare<double>(int, int, const double *, double *, int, int, int,
+                                               double, hipStream_t);
+template hipError_t launch_lin_prepare<float>(int, int, const float *, float *, int, int, int,
+                                              double, hipStream_t);
+
+size_t lin_elems(int equation, int p, int K) {
+    if (equation != EXPDG_EULER2D) return 0;
+    return (size_t)K * (3 * (p + 1) * (p + 1) + 2 * (p + 1));
+}
 
 int dg_blocks(int equation, int p, int K) {
     const int np = (equation == EXPDG_EULER2D) ? (p + 1) * (p + 1) : (p + 1);

@@ -29,6 +29,7 @@ struct OpArgs {
     const T *vtail;    // the p augmented entries y of the input (nullptr if p = 0)
     T *otail;          // the p augmented entries of the output
     const double *vscale;  // device scalar multiplying the whole result (nullptr = 1)
+    const T *lin;      // frozen fields of q~ for the 2D linear operator (launch_lin_prepare)
     double eta;        // scaling of the augmented block
     int naug;          // p
     int K, nx, ny;
@@ -64,6 +65,13 @@ int lgl_tables(int p, double *xi, double *w, double *D);
 // ---- kernel launchers (dg_kernels.hip) ----
 hipError_t launch_dg_op(int equation, int p, bool jvp, const OpArgs<double> &a, hipStream_t s);
 hipError_t launch_dg_op(int equation, int p, bool jvp, const OpArgs<float> &a, hipStream_t s);
+// Frozen fields of the 2D linear operator at the reference state q (planes u,
+// v, H, then the Rusanov speed of every x face and every y face; lin_elems
+// elements).  Burgers needs none (no-op, lin_elems = 0).
+template <typename T>
+hipError_t launch_lin_prepare(int equation, int p, const T *q, T *lin, int K, int nx, int ny,
+                              double gamma, hipStream_t s);
+size_t lin_elems(int equation, int p, int K);
 // Blocks one operator launch uses for K elements.
 int dg_blocks(int equation, int p, int K);
 // Grouped FP64 launch over n meshes of the same equation and degree: item it
@@ -123,7 +131,9 @@ template <typename T>
 hipError_t launch_gs_dots(const T *V, size_t stride, int nv, const T *w, size_t L,
                           const RowPartition &rp, double *part, const double *S, double *H,
                           int col, int accumulate, double *coef_out, hipStream_t s);
-// w -= sum_i coef_in[i] V_i, then block partials of V_i^T w into part.
+// w -= sum_i coef_in[i] V_i, then block partials of V_i^T w (rows i < nv) and
+// of ||w||^2 (row nv; w must be V_nv).  nv <= 32: one fused pass; else a plain
+// update then a dot pass over the nv + 1 vectors V_0..V_nv.
 template <typename T>
 hipError_t launch_gs_update_dots(const T *V, size_t stride, int nv, const double *coef_in, T *w,
                                  size_t L, const RowPartition &rp, double *part, const double *S,
@@ -138,6 +148,17 @@ hipError_t launch_gs_update_norm(const T *V, size_t stride, int nv, const double
 hipError_t launch_gs_finish_dots(const double *part, int nv, const RowPartition &rp,
                                  const double *S, double *H, int col, int accumulate,
                                  double *coef_out, hipStream_t s);
+// w -= sum_i coef[i] V_i, no reduction.
+template <typename T>
+hipError_t launch_gs_update(const T *V, size_t stride, int nv, const double *coef, T *w, size_t L,
+                            const RowPartition &rp, hipStream_t s);
+// Fixed-order finish of the second pass with the norm (one block): h2_i from
+// rows i < nv, H[i][col] += h2_i, coef_out[i] = h2_i S[i]; hn^2 = row nv -
+// sum h2_i^2 (Pythagoras: the norm of w - V h2 for an orthonormal basis), then
+// H[col+1][col], S[col+1] and the flags as in launch_gs_finish_norm.
+hipError_t launch_gs_finish_pass2(const double *part, int nv, const RowPartition &rp, double *S,
+                                  double *H, int col, double *coef_out, int *flags,
+                                  hipStream_t s);
 // Fixed-order finish of a norm pass: hn = sqrt(sum_b part[b]).  col >= 0:
 // H[col+1][col] = hn, breakdown test against ||H||_F (flags[0] = col+1 the
 // first time, S[col+1] = 0), else S[col+1] = 1/hn; flags[1] = col+1 the first
@@ -177,8 +198,10 @@ struct GsItem {
     double *part, *S, *H, *coefA, *coefB, *res;
     int *flags;
 };
-// Launches of a grouped Arnoldi step: first dots, finish, fused update+dots
-// (nv <= 32), plain update (nv > 32), dots after it (nv > 32), update+norm.
+// Block ranges of a grouped Arnoldi step: first dots, first finish, fused
+// update+dots+norm (nv <= 32), plain update (nv > 32), dots with w itself
+// after it (nv > 32), final update.  (The second finish runs one block per
+// item.)
 constexpr int kGroupLaunches = 6;
 // Host: block ranges bstart[k*(n+1) + it] of launch k and the totals.
 void arnoldi_group_layout(const GsItem *items, int n, int *bstart, int *totals);

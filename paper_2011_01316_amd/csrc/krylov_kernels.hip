@@ -217,6 +217,85 @@ __global__ __launch_bounds__(256) void finish_norm_kernel(const double *part, in
     finish_norm_body(part, nrb, f);
 }
 
+// Finish of the second Gram-Schmidt pass together with the norm (one block of
+// kFin2Threads threads).  d_i = sum_b part[i][b] in a fixed order for i <= nv,
+// where row nv holds ||w'||^2 of the stored vector w'; h2_i = S[i] d_i,
+// H[i][col] += h2_i, coef_out[i] = h2_i S[i].  The vector after the update,
+// w'' = w' - sum_i h2_i v_i, has ||w''||^2 = ||w'||^2 - sum_i h2_i^2 because the
+// v_i are orthonormal (Pythagoras), so no further reduction is needed; the
+// breakdown test and S[col+1] then follow as in finish_norm.
+constexpr int kFin2Threads = 1024;
+
+struct Pass2Finish {
+    double *S;
+    double *H;
+    int col;
+    double *coef_out;
+    int *flags;
+};
+
+__device__ __forceinline__ void finish_pass2_body(const double *part, int nv, int nrb,
+                                                  const Pass2Finish &f) {
+    int *flags = f.flags;
+    constexpr int NW = kFin2Threads / 64;
+    __shared__ double sv[kMaxM + 2];
+    __shared__ double sw[NW];
+    __shared__ double shh;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int i = wave; i <= nv; i += NW) {
+        double a = 0.0;
+        for (int b = lane; b < nrb; b += 64) a += part[(size_t)i * nrb + b];
+        a = wave_sum(a);
+        if (lane == 0) sv[i] = a;
+    }
+    __syncthreads();
+    const int col = f.col;
+    double h = 0.0;
+    if (tid < nv) {
+        h = f.S[tid] * sv[tid];
+        double *hij = &f.H[(size_t)tid * LDH + col];
+        *hij = *hij + h;
+        f.coef_out[tid] = h * f.S[tid];
+    }
+    // nv <= kMaxM = 64: every h2_i lives in wave 0
+    const double hh = wave_sum(h * h);
+    if (tid == 0) shh = hh;
+    __syncthreads();
+    const double hn2 = sv[nv] - shh;
+    const double hn = (hn2 < 0.0) ? 0.0 : sqrt(hn2);  // NaN stays NaN
+    // ||H_{0:col+2, 0:col+1}||_F including the new subdiagonal entry
+    const int rows = col + 2, cols = col + 1;
+    double acc = 0.0;
+    for (int e = tid; e < rows * cols; e += kFin2Threads) {
+        const int r = e / cols, c = e % cols;
+        const double hv = (r == col + 1) ? ((c == col) ? hn : 0.0) : f.H[(size_t)r * LDH + c];
+        acc += hv * hv;
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) sw[wave] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        double s = 0.0;
+        for (int k = 0; k < NW; ++k) s += sw[k];
+        const double hf = sqrt(s);
+        if ((!isfinite(hn) || !isfinite(hf)) && flags[1] == 0) flags[1] = col + 1;
+        const bool brk = hn <= 1e-12 * hf;
+        if (brk) {
+            f.H[(size_t)(col + 1) * LDH + col] = 0.0;
+            f.S[col + 1] = 0.0;
+            if (flags[0] == 0) flags[0] = col + 1;
+        } else {
+            f.H[(size_t)(col + 1) * LDH + col] = hn;
+            f.S[col + 1] = 1.0 / hn;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kFin2Threads) void finish_pass2_kernel(const double *part, int nv,
+                                                                    int nrb, Pass2Finish f) {
+    finish_pass2_body(part, nv, nrb, f);
+}
+
 // part[i][rb] = sum over the block's rows of V_i[r] w[r], i in the block's
 // 16-vector chunk.
 template <typename T>
@@ -272,7 +351,8 @@ __global__ __launch_bounds__(256) void gs_dots_kernel(const T *__restrict__ V, s
 }
 
 // w -= sum_i c_i V_i with c from the previous pass, then
-// part[i][rb] = sum_r V_i[r] w[r] (nv <= 32).
+// part[i][rb] = sum_r V_i[r] w[r] (nv <= 32) and part[nv][rb] = sum_r w[r]^2
+// (the stored, rounded w).
 template <typename T>
 __device__ __forceinline__ void gs_update_dots_body(const T *__restrict__ V, size_t stride, int nv,
                                                     const double *coef, T *__restrict__ w,
@@ -280,12 +360,14 @@ __device__ __forceinline__ void gs_update_dots_body(const T *__restrict__ V, siz
                                                     double *__restrict__ part, int rb) {
     __shared__ double scoef[32];
     __shared__ double sw[4][32];
+    __shared__ double sn[4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (tid < nv) scoef[tid] = coef[tid];
     __syncthreads();
     const size_t r0 = (size_t)rb * rpb;
     const size_t r1 = (r0 + rpb < L) ? r0 + rpb : L;
     double acc[32];
+    double nrm = 0.0;
 #pragma unroll
     for (int i = 0; i < 32; ++i) acc[i] = 0.0;
     constexpr int N = Vec16<T>::N;
@@ -318,6 +400,8 @@ __device__ __forceinline__ void gs_update_dots_body(const T *__restrict__ V, siz
         }
         st16(w + r, x);
 #pragma unroll
+        for (int e = 0; e < N; ++e) nrm += x[e] * x[e];
+#pragma unroll
         for (int i = 0; i < KEEP; ++i)
 #pragma unroll
             for (int e = 0; e < N; ++e) acc[i] += keep[i][e] * x[e];
@@ -336,14 +420,18 @@ __device__ __forceinline__ void gs_update_dots_body(const T *__restrict__ V, siz
         const T xs = (T)x;
         w[r] = xs;
         x = (double)xs;
+        nrm += x * x;
 #pragma unroll
         for (int i = 0; i < 32; ++i)
             if (i < nv) acc[i] += (double)V[(size_t)i * stride + r] * x;
     }
     const double v = transpose_reduce32(acc);
     if ((lane & 1) == 0) sw[wave][lane >> 1] = v;
+    nrm = wave_sum(nrm);
+    if (lane == 0) sn[wave] = nrm;
     __syncthreads();
     if (tid < nv) part[(size_t)tid * nrb + rb] = (sw[0][tid] + sw[1][tid]) + (sw[2][tid] + sw[3][tid]);
+    if (tid == 0) part[(size_t)nv * nrb + rb] = (sn[0] + sn[1]) + (sn[2] + sn[3]);
 }
 
 template <typename T>
@@ -765,13 +853,14 @@ __global__ __launch_bounds__(256) void combine_kernel(const T *V, size_t stride,
 // independent solves.  Item it owns blocks [bstart[it], bstart[it+1]); an item
 // with no blocks in a launch is skipped.  Each item computes exactly what its
 // own single launch computes (same row partition, same block partials).
+// extra = 1: the dots also take w itself (V_nv is w), giving ||w||^2 in row nv.
 __global__ __launch_bounds__(256) void gs_dots_group(const GsItem *items, const int *bstart,
-                                                     int n) {
+                                                     int n, int extra) {
     const int it = group_item(bstart, n, blockIdx.x);
     const GsItem &g = items[it];
     const int local = blockIdx.x - bstart[it];
-    gs_dots_body<double>(g.V, g.stride, g.nv, g.w, g.L, g.rpb, g.nrb, g.part, local % g.nrb,
-                         local / g.nrb);
+    gs_dots_body<double>(g.V, g.stride, g.nv + extra, g.w, g.L, g.rpb, g.nrb, g.part,
+                         local % g.nrb, local / g.nrb);
 }
 
 __global__ __launch_bounds__(256) void finish_dots_group(const GsItem *items, const int *bstart,
@@ -790,26 +879,19 @@ __global__ __launch_bounds__(256) void gs_update_dots_group(const GsItem *items,
                                 blockIdx.x - bstart[it]);
 }
 
+// pass 0: w -= V coefA (first-pass coefficients); pass 1: w -= V coefB.
 __global__ __launch_bounds__(256) void gs_update_group(const GsItem *items, const int *bstart,
-                                                       int n) {
+                                                       int n, int pass) {
     const int it = group_item(bstart, n, blockIdx.x);
     const GsItem &g = items[it];
-    gs_update_body<double>(g.V, g.stride, g.nv, g.coefA, g.w, g.L, g.rpb,
+    gs_update_body<double>(g.V, g.stride, g.nv, pass ? g.coefB : g.coefA, g.w, g.L, g.rpb,
                            blockIdx.x - bstart[it]);
 }
 
-__global__ __launch_bounds__(256) void gs_update_norm_group(const GsItem *items,
-                                                            const int *bstart, int n) {
-    const int it = group_item(bstart, n, blockIdx.x);
-    const GsItem &g = items[it];
-    gs_update_norm_body<double>(g.V, g.stride, g.nv, g.coefB, g.w, g.L, g.rpb, g.part,
-                                blockIdx.x - bstart[it]);
-}
-
 // One workgroup per item.
-__global__ __launch_bounds__(256) void finish_norm_group(const GsItem *items) {
+__global__ __launch_bounds__(kFin2Threads) void finish_pass2_group(const GsItem *items) {
     const GsItem &g = items[blockIdx.x];
-    finish_norm_body(g.part, g.nrb, NormFinish{g.H, g.S, g.col, g.flags, g.res});
+    finish_pass2_body(g.part, g.nv, g.nrb, Pass2Finish{g.S, g.H, g.col, g.coefB, g.flags});
 }
 
 constexpr size_t kExpmLds = (size_t)4 * NMAX * LDA * sizeof(double);
@@ -878,7 +960,25 @@ hipError_t launch_gs_update_dots(const T *V, size_t stride, int nv, const double
     hipError_t e = launch_kernel(gs_update_kernel<T>, dim3(rp.nrb), dim3(256), 0, s, V, stride,
                                  nv, prev, w, L, rp.rpb, rp.nrb);
     if (e != hipSuccess) return e;
-    return launch_gs_dots<T>(V, stride, nv, w, L, rp, part, S, H, col, 1, coef_out, s);
+    // the dots also take w itself (it is V_nv): ||w||^2 in row nv
+    return launch_gs_dots<T>(V, stride, nv + 1, w, L, rp, part, S, H, col, 1, coef_out, s);
+}
+
+template <typename T>
+hipError_t launch_gs_update(const T *V, size_t stride, int nv, const double *coef, T *w, size_t L,
+                            const RowPartition &rp, hipStream_t s) {
+    if (nv < 1 || nv > kMaxM + 1) return hipErrorInvalidValue;
+    PrevPass prev{coef};
+    return launch_kernel(gs_update_kernel<T>, dim3(rp.nrb), dim3(256), 0, s, V, stride, nv, prev,
+                         w, L, rp.rpb, rp.nrb);
+}
+
+hipError_t launch_gs_finish_pass2(const double *part, int nv, const RowPartition &rp, double *S,
+                                  double *H, int col, double *coef_out, int *flags,
+                                  hipStream_t s) {
+    if (nv < 1 || nv > kMaxM) return hipErrorInvalidValue;
+    return launch_kernel(finish_pass2_kernel, dim3(1), dim3(kFin2Threads), 0, s, part, nv, rp.nrb,
+                         Pass2Finish{S, H, col, coef_out, flags});
 }
 
 template <typename T>
@@ -903,7 +1003,9 @@ hipError_t launch_gs_update_norm(const T *V, size_t stride, int nv, const double
     template hipError_t launch_gs_update_norm<T>(const T *, size_t, int, const double *, T *,  \
                                                  size_t, const RowPartition &, double *,        \
                                                  double *, double *, int, int *, double *,      \
-                                                 hipStream_t);
+                                                 hipStream_t);                                  \
+    template hipError_t launch_gs_update<T>(const T *, size_t, int, const double *, T *, size_t, \
+                                            const RowPartition &, hipStream_t);
 EXPDG_INST(double)
 EXPDG_INST(float)
 #undef EXPDG_INST
@@ -945,9 +1047,11 @@ void arnoldi_group_layout(const GsItem *items, int n, int *bstart, int *totals) 
     for (int it = 0; it < n; ++it) {
         const GsItem &g = items[it];
         const int chunks = (g.nv + CH - 1) / CH;
+        const int chunks2 = (g.nv + 1 + CH - 1) / CH;  // with w itself
         const bool small = g.nv <= 32;
-        const int blocks[kGroupLaunches] = {g.nrb * chunks, (g.nv + 3) / 4, small ? g.nrb : 0,
-                                            small ? 0 : g.nrb, small ? 0 : g.nrb * chunks, g.nrb};
+        const int blocks[kGroupLaunches] = {g.nrb * chunks, (g.nv + 3) / 4,
+                                            small ? g.nrb : 0,     small ? 0 : g.nrb,
+                                            small ? 0 : g.nrb * chunks2, g.nrb};
         for (int k = 0; k < kGroupLaunches; ++k) {
             bstart[k * (n + 1) + it] = t[k];
             t[k] += blocks[k];
@@ -966,27 +1070,26 @@ hipError_t launch_arnoldi_group(const GsItem *items, const int *bstart, const in
     for (int k = 0; k < kGroupLaunches; ++k) b[k] = bstart + (size_t)k * (n + 1);
     hipError_t e;
     // first pass: h1 = V^T w
-    e = launch_kernel(gs_dots_group, dim3(totals[0]), dim3(256), 0, s, items, b[0], n);
+    e = launch_kernel(gs_dots_group, dim3(totals[0]), dim3(256), 0, s, items, b[0], n, 0);
     if (e != hipSuccess) return e;
     e = launch_kernel(finish_dots_group, dim3(totals[1]), dim3(256), 0, s, items, b[1], n, 0);
     if (e != hipSuccess) return e;
-    // second pass: w -= V h1 ; h2 = V^T w (fused for j <= 32)
+    // second pass: w -= V h1 ; h2 = V^T w and ||w||^2 (fused for j <= 32)
     if (totals[2] > 0) {
         e = launch_kernel(gs_update_dots_group, dim3(totals[2]), dim3(256), 0, s, items, b[2], n);
         if (e != hipSuccess) return e;
     }
     if (totals[3] > 0) {
-        e = launch_kernel(gs_update_group, dim3(totals[3]), dim3(256), 0, s, items, b[3], n);
+        e = launch_kernel(gs_update_group, dim3(totals[3]), dim3(256), 0, s, items, b[3], n, 0);
         if (e != hipSuccess) return e;
-        e = launch_kernel(gs_dots_group, dim3(totals[4]), dim3(256), 0, s, items, b[4], n);
+        e = launch_kernel(gs_dots_group, dim3(totals[4]), dim3(256), 0, s, items, b[4], n, 1);
         if (e != hipSuccess) return e;
     }
-    e = launch_kernel(finish_dots_group, dim3(totals[1]), dim3(256), 0, s, items, b[1], n, 1);
+    // h2, ||w''|| by Pythagoras, H[j][j-1], S[j], breakdown test
+    e = launch_kernel(finish_pass2_group, dim3(n), dim3(kFin2Threads), 0, s, items);
     if (e != hipSuccess) return e;
-    // w -= V h2 ; ||w||, H[j][j-1], S[j], breakdown test
-    e = launch_kernel(gs_update_norm_group, dim3(totals[5]), dim3(256), 0, s, items, b[5], n);
-    if (e != hipSuccess) return e;
-    return launch_kernel(finish_norm_group, dim3(n), dim3(256), 0, s, items);
+    // w -= V h2
+    return launch_kernel(gs_update_group, dim3(totals[5]), dim3(256), 0, s, items, b[5], n, 1);
 }
 
 hipError_t launch_dense_expm(const double *A, int n, double *E, hipStream_t s) {

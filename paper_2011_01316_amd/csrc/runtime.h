@@ -29,6 +29,7 @@ struct expdg_mesh {
     void *vec[6] = {};           // bulk work vectors (stride each)
     void *bq[3] = {};            // bulk copies of FP64 states (FP32_BULK only)
     double *q2 = nullptr;        // FP64 stage state (EXPRB32)
+    void *lin = nullptr;         // frozen fields of the 2D linear operator (bulk type)
     expdg::KrylovDev kd{};
     double *slots = nullptr;     // 2 x kSlotSize
     double *dnorm = nullptr;     // 8
@@ -138,13 +139,22 @@ OpArgs<T> op_args(const expdg_mesh *m) {
     return a;
 }
 
-// Residual (jvp = false) or linear operator of the mesh on stream s.
+// Frozen fields of the linear operator at the reference state q (into m->lin).
+template <typename T>
+hipError_t prepare_lin(expdg_mesh *m, const T *q, hipStream_t s) {
+    return launch_lin_prepare<T>(m->d.equation, m->d.p, q, (T *)m->lin, m->K, m->d.nx, m->d.ny,
+                                 m->d.gamma, s);
+}
+
+// Residual (jvp = false) or linear operator of the mesh on stream s; the
+// linear operator needs the frozen fields of q prepared (prepare_lin).
 template <typename T>
 int apply_op(expdg_mesh *m, bool jvp, const T *q, const T *v, T *out, hipStream_t s) {
     OpArgs<T> a = op_args<T>(m);
     a.q = q;
     a.v = v;
     a.out = out;
+    a.lin = (const T *)m->lin;
     const int cls = jvp ? EXPDG_K_LINEAR : EXPDG_K_RESIDUAL;
     TRY(prof_begin(m, cls));
     HIPTRY(launch_dg_op(m->d.equation, m->d.p, jvp, a, s));
