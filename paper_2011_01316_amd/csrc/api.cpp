@@ -181,7 +181,10 @@ size_t layout(expdg_mesh *m, const expdg_mesh_desc *d, size_t stride, int eb, ch
     take(m->kd.S, (size_t)(kMaxM + 1) * 8);
     take(m->kd.coefA, (size_t)(kMaxM + 1) * 8);
     take(m->kd.coefB, (size_t)(kMaxM + 1) * 8);
-    take(m->kd.part, (size_t)kRedBlocks * (kMaxM + 1) * 8);
+    // block partials: row-partitioned passes (<= kRedBlocks) and the first
+    // pass fused into the linear operator (one partial per operator block)
+    const size_t npart = std::max<size_t>(kRedBlocks, dg_blocks(d->equation, d->p, d->nx * d->ny));
+    take(m->kd.part, npart * (kMaxM + 1) * 8);
     take(m->kd.res, 64 * 8);
     take(m->kd.flags, 16);
     take(m->slots, 2 * kSlotSize * 8);
@@ -518,17 +521,15 @@ struct DirectExec {
         T *w = a.out;
         const int col = j - 1;
         const double eb = (double)sizeof(T);
+        // linear operator with the first Gram-Schmidt pass (V^T w block partials)
         TRY(prof_begin(m, EXPDG_K_LINEAR));
         HIPTRY(launch_dg_op(m->d.equation, m->d.p, true, a, s));
-        TRY(prof_end(m, EXPDG_K_LINEAR, (double)(3 + naug_nz) * n * eb));
-        // classical Gram-Schmidt, two passes, then the norm
-        const double fin_bytes = 8.0 * rp.nrb * j;
-        TRY(prof_begin(m, EXPDG_K_GS_DOTS));
-        HIPTRY(launch_gs_dots<T>(V, stride, j, w, L, rp, kd.part, kd.S, kd.H, col, 0, kd.coefA, s));
-        TRY(prof_end(m, EXPDG_K_GS_DOTS, (double)(j + 1) * L * eb));
+        TRY(prof_end(m, EXPDG_K_LINEAR, (double)(3 + naug_nz + j) * n * eb));
+        const RowPartition rp1{0, a.dnb};  // partials of the fused pass
         TRY(prof_begin(m, EXPDG_K_GS_FINISH));
-        HIPTRY(launch_gs_finish_dots(kd.part, j, rp, kd.S, kd.H, col, 0, kd.coefA, s));
-        TRY(prof_end(m, EXPDG_K_GS_FINISH, fin_bytes));
+        HIPTRY(launch_gs_finish_dots(kd.part, j, rp1, kd.S, kd.H, col, 0, kd.coefA, s));
+        TRY(prof_end(m, EXPDG_K_GS_FINISH, 8.0 * rp1.nrb * j));
+        const double fin_bytes = 8.0 * rp.nrb * j;
         // second pass with ||w||^2 (j > 32: a plain update then a dot pass,
         // 2j + 4 vectors of traffic)
         TRY(prof_begin(m, EXPDG_K_GS_UPDATE_DOTS));

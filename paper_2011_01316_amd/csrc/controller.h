@@ -218,6 +218,11 @@ Task<int> phi_co(X &x, expdg_mesh *m, const T *qref, double tau, int p, const T 
     a.q = qref;
     a.lin = (const T *)m->lin;
     a.eta = eta;
+    // the first Gram-Schmidt pass runs inside the linear operator
+    a.basis = V;
+    a.bstride = stride;
+    a.dpart = kd.part;
+    a.dnb = dg_blocks(m->d.equation, m->d.p, m->K);
     a.naug = p;
     int naug_nz = 0;
     for (int k = 1; k <= p; ++k) {
@@ -261,6 +266,7 @@ Task<int> phi_co(X &x, expdg_mesh *m, const T *qref, double tau, int p, const T 
             a.vtail = vin + n;
             a.otail = w + n;
             a.vscale = kd.S + (j - 1);
+            a.nv = j;
             const bool is_check =
                 !forced && (j == o->m_max || (j >= o->m_min && (j - o->m_min) % o->check_every == 0));
             CheckReq cr{};

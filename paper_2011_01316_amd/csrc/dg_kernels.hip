@@ -18,6 +18,7 @@
 // elements so y-neighbours (nx elements away) are usually resident in that
 // XCD's L2.
 #include "internal.h"
+#include "reduce.h"
 
 namespace expdg {
 namespace {
@@ -197,6 +198,52 @@ __global__ __launch_bounds__(256) void euler_lin_prepare(const T *q, T *lin, int
     }
 }
 
+// First Gram-Schmidt pass fused into the linear operator: the block's partial
+// sums of V_i^T w over its own outputs wv (NV values per thread, one per
+// variable plane, node offset idx), i < a.nv, in chunks of 16 vectors with a
+// transpose reduction; the first tile adds the augmented entries.  Every
+// thread of the block takes part (inactive ones contribute zero).
+template <typename T, int NV>
+__device__ __forceinline__ void op_dots(const OpArgs<T> &a, bool active, unsigned idx,
+                                        size_t plane, const T *wv, int tile, bool first) {
+    __shared__ double sw[4][16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const size_t ntot = NV * plane;
+    for (int i0 = 0; i0 < a.nv; i0 += 16) {
+        double acc[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) acc[k] = 0.0;
+        if (active) {
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+                if (i0 + k < a.nv) {
+                    const T *Vi = a.basis + (size_t)(i0 + k) * a.bstride;
+                    double s = 0.0;
+#pragma unroll
+                    for (int c = 0; c < NV; ++c) s += (double)ld32(Vi + c * plane, idx) * (double)wv[c];
+                    acc[k] = s;
+                }
+        }
+        if (first && tid == 0 && a.naug > 0) {
+            const T sc = a.vscale ? (T)(*a.vscale) : T(1);
+            for (int t = 0; t < a.naug; ++t) {
+                const T wt = (t + 1 < a.naug) ? sc * a.vtail[t + 1] : T(0);
+#pragma unroll
+                for (int k = 0; k < 16; ++k)
+                    if (i0 + k < a.nv)
+                        acc[k] += (double)a.basis[(size_t)(i0 + k) * a.bstride + ntot + t] * (double)wt;
+            }
+        }
+        const double v = transpose_reduce16(acc);
+        if ((lane & 3) == 0) sw[wave][lane >> 2] = v;
+        __syncthreads();
+        if (tid < 16 && i0 + tid < a.nv)
+            a.dpart[(size_t)(i0 + tid) * a.dnb + tile] =
+                (sw[0][tid] + sw[1][tid]) + (sw[2][tid] + sw[3][tid]);
+        __syncthreads();
+    }
+}
+
 // ---- Euler 2D operator ------------------------------------------------------
 // One tile (floor(256/Np) elements) of the operator; first marks the item's
 // first block, which also writes the augmented entries of the output.  The
@@ -328,22 +375,31 @@ __device__ __forceinline__ void euler_op_body(const OpArgs<T> &a, int tile, bool
         }
     }
     __syncthreads();
-    if (!active) return;
 
-    const int base = le * NP;
+    T wv[4];
+    if (active) {
+        const int base = le * NP;
 #pragma unroll
-    for (int l = 0; l < N1; ++l) {
-        const T dx = sDx[i * N1 + l];
-        const T dy = sDy[j * N1 + l];
+        for (int l = 0; l < N1; ++l) {
+            const T dx = sDx[i * N1 + l];
+            const T dy = sDy[j * N1 + l];
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-            res[c] = fma(dy, sF[4 + c][base + l * N1 + i], fma(dx, sF[c][base + j * N1 + l], res[c]));
+            for (int c = 0; c < 4; ++c)
+                res[c] = fma(dy, sF[4 + c][base + l * N1 + i], fma(dx, sF[c][base + j * N1 + l], res[c]));
+        }
+        T *out[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) out[c] = a.out + c * plane;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            wv[c] = sc * res[c];
+            st32(out[c], idx, wv[c]);
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) wv[c] = T(0);
     }
-    T *out[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) out[c] = a.out + c * plane;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) st32(out[c], idx, sc * res[c]);
+    if (JVP && a.nv > 0) op_dots<T, 4>(a, active, idx, plane, wv, tile, first);
 }
 
 // ---- Burgers 1D operator ----------------------------------------------------
@@ -373,13 +429,14 @@ __device__ __forceinline__ void burgers_op_body(const OpArgs<T> &a, int tile, bo
     }
     if (tid < NT) sF[tid] = f;
     __syncthreads();
-    if (!active) return;
 
     T res = T(0);
     const int base = le * N1;
+    if (active) {
 #pragma unroll
-    for (int l = 0; l < N1; ++l) res -= a.rhx * a.D[i * N1 + l] * sF[base + l];
-    if (i == 0 || i == P) {
+        for (int l = 0; l < N1; ++l) res -= a.rhx * a.D[i * N1 + l] * sF[base + l];
+    }
+    if (active && (i == 0 || i == P)) {
         const int s = (i == P) ? 1 : -1;
         int en = e + s;
         en = en < 0 ? a.K - 1 : (en >= a.K ? 0 : en);
@@ -390,12 +447,17 @@ __device__ __forceinline__ void burgers_op_body(const OpArgs<T> &a, int tile, bo
         const T lam = fmax(fabs(qv), fabs(qn));
         res -= a.rhx * a.lift * (T(0.5) * T(s) * (fn - f) + T(0.5) * lam * (uv - un));
     }
-    for (int k = 0; k < a.naug; ++k) {
-        const T *b = a.aug[k];
-        if (!b) continue;
-        res += (T)a.eta * a.vtail[k] * b[idx];
+    T wv = T(0);
+    if (active) {
+        for (int k = 0; k < a.naug; ++k) {
+            const T *b = a.aug[k];
+            if (!b) continue;
+            res += (T)a.eta * a.vtail[k] * b[idx];
+        }
+        wv = sc * res;
+        a.out[idx] = wv;
     }
-    a.out[idx] = sc * res;
+    if (JVP && a.nv > 0) op_dots<T, 1>(a, active, (unsigned)idx, (size_t)a.K * N1, &wv, tile, first);
 }
 
 template <int P, typename T, bool JVP>

@@ -30,6 +30,14 @@ struct OpArgs {
     T *otail;          // the p augmented entries of the output
     const double *vscale;  // device scalar multiplying the whole result (nullptr = 1)
     const T *lin;      // frozen fields of q~ for the 2D linear operator (launch_lin_prepare)
+    // First Gram-Schmidt pass fused into the linear operator (nv > 0): block
+    // partials dpart[i * dnb + tile] of V_i^T out over the tile's nodes (and,
+    // in tile 0, the augmented entries), i < nv, V_i = basis + i * bstride.
+    const T *basis;
+    size_t bstride;
+    int nv;
+    int dnb;           // blocks of the launch (partials per vector)
+    double *dpart;
     double eta;        // scaling of the augmented block
     int naug;          // p
     int K, nx, ny;
@@ -195,13 +203,14 @@ struct GsItem {
     double *w;
     size_t stride, L, rpb;
     int nrb, nv, col;    // col = nv - 1
+    int nrb1;            // partials per vector of the first pass (linear operator blocks)
     double *part, *S, *H, *coefA, *coefB, *res;
     int *flags;
 };
-// Block ranges of a grouped Arnoldi step: first dots, first finish, fused
-// update+dots+norm (nv <= 32), plain update (nv > 32), dots with w itself
-// after it (nv > 32), final update.  (The second finish runs one block per
-// item.)
+// Block ranges of a grouped Arnoldi step: (unused: the first dots run inside
+// the linear operator), first finish, fused update+dots+norm (nv <= 32),
+// plain update (nv > 32), dots with w itself after it (nv > 32), final
+// update.  (The second finish runs one block per item.)
 constexpr int kGroupLaunches = 6;
 // Host: block ranges bstart[k*(n+1) + it] of launch k and the totals.
 void arnoldi_group_layout(const GsItem *items, int n, int *bstart, int *totals);

@@ -33,6 +33,7 @@
 // rows below the pivot: the rows further down hold exact zeros, so the result
 // is the same as a full elimination.
 #include "internal.h"
+#include "reduce.h"
 
 namespace expdg {
 namespace {
@@ -75,52 +76,6 @@ __device__ __forceinline__ void st16(T *p, double *x) {
         x[k] = (double)e[k];
     }
     *reinterpret_cast<VT *>(p) = v;
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// One halving step of the transpose reduction: lanes with bit m set keep the
-// upper half of a[0..2*HALF), the others the lower half; each adds the
-// partner's copy of the half it keeps.
-template <int HALF>
-__device__ __forceinline__ void tr_step(double *a, int lane, int m) {
-    const bool up = (lane & m) != 0;
-#pragma unroll
-    for (int k = 0; k < HALF; ++k) {
-        const double keep = up ? a[HALF + k] : a[k];
-        const double send = up ? a[k] : a[HALF + k];
-        a[k] = keep + __shfl_xor(send, m, 64);
-    }
-}
-
-// Wave sums of a[0..16): lane l returns the sum of a[l >> 2].
-__device__ __forceinline__ double transpose_reduce16(double *a) {
-    const int lane = threadIdx.x & 63;
-    tr_step<8>(a, lane, 32);
-    tr_step<4>(a, lane, 16);
-    tr_step<2>(a, lane, 8);
-    tr_step<1>(a, lane, 4);
-    double v = a[0];
-    v += __shfl_xor(v, 2, 64);
-    v += __shfl_xor(v, 1, 64);
-    return v;
-}
-
-// Wave sums of a[0..32): lane l returns the sum of a[l >> 1].
-__device__ __forceinline__ double transpose_reduce32(double *a) {
-    const int lane = threadIdx.x & 63;
-    tr_step<16>(a, lane, 32);
-    tr_step<8>(a, lane, 16);
-    tr_step<4>(a, lane, 8);
-    tr_step<2>(a, lane, 4);
-    tr_step<1>(a, lane, 2);
-    double v = a[0];
-    v += __shfl_xor(v, 1, 64);
-    return v;
 }
 
 // The previous pass whose coefficients a kernel applies.
@@ -863,12 +818,14 @@ __global__ __launch_bounds__(256) void gs_dots_group(const GsItem *items, const 
                          local % g.nrb, local / g.nrb);
 }
 
+// Finish of the first pass (its partials come from the linear operator's
+// blocks: nrb1 per vector).
 __global__ __launch_bounds__(256) void finish_dots_group(const GsItem *items, const int *bstart,
-                                                         int n, int pass) {
+                                                         int n) {
     const int it = group_item(bstart, n, blockIdx.x);
     const GsItem &g = items[it];
-    const DotFinish f{g.S, g.H, g.col, pass, pass ? g.coefB : g.coefA};
-    finish_dots_body(g.part, g.nv, g.nrb, f, blockIdx.x - bstart[it]);
+    const DotFinish f{g.S, g.H, g.col, 0, g.coefA};
+    finish_dots_body(g.part, g.nv, g.nrb1, f, blockIdx.x - bstart[it]);
 }
 
 __global__ __launch_bounds__(256) void gs_update_dots_group(const GsItem *items,
@@ -1049,7 +1006,8 @@ void arnoldi_group_layout(const GsItem *items, int n, int *bstart, int *totals) 
         const int chunks = (g.nv + CH - 1) / CH;
         const int chunks2 = (g.nv + 1 + CH - 1) / CH;  // with w itself
         const bool small = g.nv <= 32;
-        const int blocks[kGroupLaunches] = {g.nrb * chunks, (g.nv + 3) / 4,
+        (void)chunks;
+        const int blocks[kGroupLaunches] = {0, (g.nv + 3) / 4,
                                             small ? g.nrb : 0,     small ? 0 : g.nrb,
                                             small ? 0 : g.nrb * chunks2, g.nrb};
         for (int k = 0; k < kGroupLaunches; ++k) {
@@ -1069,10 +1027,8 @@ hipError_t launch_arnoldi_group(const GsItem *items, const int *bstart, const in
     const int *b[kGroupLaunches];
     for (int k = 0; k < kGroupLaunches; ++k) b[k] = bstart + (size_t)k * (n + 1);
     hipError_t e;
-    // first pass: h1 = V^T w
-    e = launch_kernel(gs_dots_group, dim3(totals[0]), dim3(256), 0, s, items, b[0], n, 0);
-    if (e != hipSuccess) return e;
-    e = launch_kernel(finish_dots_group, dim3(totals[1]), dim3(256), 0, s, items, b[1], n, 0);
+    // first pass: h1 = V^T w from the linear operator's block partials
+    e = launch_kernel(finish_dots_group, dim3(totals[1]), dim3(256), 0, s, items, b[1], n);
     if (e != hipSuccess) return e;
     // second pass: w -= V h1 ; h2 = V^T w and ||w||^2 (fused for j <= 32)
     if (totals[2] > 0) {
