@@ -521,11 +521,19 @@ struct DirectExec {
         T *w = a.out;
         const int col = j - 1;
         const double eb = (double)sizeof(T);
-        // linear operator with the first Gram-Schmidt pass (V^T w block partials)
+        // linear operator, with the first Gram-Schmidt pass (V^T w block
+        // partials) when a.nv > 0, else a separate dot pass
+        const bool fused = a.nv > 0;
         TRY(prof_begin(m, EXPDG_K_LINEAR));
         HIPTRY(launch_dg_op(m->d.equation, m->d.p, true, a, s));
-        TRY(prof_end(m, EXPDG_K_LINEAR, (double)(3 + naug_nz + j) * n * eb));
-        const RowPartition rp1{0, a.dnb};  // partials of the fused pass
+        TRY(prof_end(m, EXPDG_K_LINEAR, (double)(3 + naug_nz + (fused ? j : 0)) * n * eb));
+        if (!fused) {
+            TRY(prof_begin(m, EXPDG_K_GS_DOTS));
+            HIPTRY(launch_gs_dots<T>(V, stride, j, w, L, rp, kd.part, kd.S, kd.H, col, 0, kd.coefA,
+                                     s));
+            TRY(prof_end(m, EXPDG_K_GS_DOTS, (double)(j + 1) * L * eb));
+        }
+        const RowPartition rp1 = fused ? RowPartition{0, a.dnb} : rp;
         TRY(prof_begin(m, EXPDG_K_GS_FINISH));
         HIPTRY(launch_gs_finish_dots(kd.part, j, rp1, kd.S, kd.H, col, 0, kd.coefA, s));
         TRY(prof_end(m, EXPDG_K_GS_FINISH, 8.0 * rp1.nrb * j));

@@ -178,8 +178,8 @@ Task<int> phi_co(X &x, expdg_mesh *m, const T *qref, double tau, int p, const T 
     // 1. scaling and 2. tolerance: norms of b_0..b_p
     const T *bx[4] = {nullptr, nullptr, nullptr, nullptr};
     for (int k = 0; k <= p; ++k) bx[k] = b ? b[k] : nullptr;
-    CO_HIPTRY(launch_norms<T>(bx, p + 1, n, kd.part, m->dnorm, s));
-    CO_HIPTRY(hipMemcpyAsync(m->pin + kPinNorms, m->dnorm, (p + 1) * 8, hipMemcpyDeviceToHost, s));
+    // (written straight into the mapped pinned mirror)
+    CO_HIPTRY(launch_norms<T>(bx, p + 1, n, kd.part, m->pin_dev + kPinNorms, s));
     CO_TRY(co_await x.readback(m));
     double bn[4] = {0, 0, 0, 0};
     for (int k = 0; k <= p; ++k) bn[k] = bx[k] ? m->pin[kPinNorms + k] : 0.0;
@@ -205,20 +205,17 @@ Task<int> phi_co(X &x, expdg_mesh *m, const T *qref, double tau, int p, const T 
     R.tau = tau;
     R.tol_abs = o->tol * nu;
 
-    // z = [b_0; 0, ..., 0, 1/eta] lives in V_0
-    if (bx[0])
-        CO_HIPTRY(launch_copy(bx[0], V, n, s));
-    else
-        CO_HIPTRY(launch_fill<T>(V, 0.0, n, s));
-    if (p > 0) CO_HIPTRY(launch_set_tail<T>(V + n, p, 1.0 / eta, s));
-    CO_HIPTRY(launch_fill<int>(kd.flags, 0.0, 4, s));
+    // z = [b_0; 0, ..., 0, 1/eta] lives in V_0; flags cleared
+    CO_HIPTRY(launch_phi_init<T>(V, bx[0], n, p, 1.0 / eta, kd.flags, s));
 
     if (!lin_ready) CO_HIPTRY(prepare_lin<T>(m, qref, s));
     OpArgs<T> a = op_args<T>(m);
     a.q = qref;
     a.lin = (const T *)m->lin;
     a.eta = eta;
-    // the first Gram-Schmidt pass runs inside the linear operator
+    // the first Gram-Schmidt pass runs inside the 2D linear operator (a
+    // Burgers tile has too little work to carry it: separate pass there)
+    const bool fuse_dots = m->d.equation == EXPDG_EULER2D;
     a.basis = V;
     a.bstride = stride;
     a.dpart = kd.part;
@@ -251,7 +248,6 @@ Task<int> phi_co(X &x, expdg_mesh *m, const T *qref, double tau, int p, const T 
         CO_TRY(prof_begin(m, EXPDG_K_GS_FINISH));
         CO_HIPTRY(launch_gs_finish_norm(kd.part, rp, kd.H, kd.S, -1, kd.flags, kd.res, s));
         CO_TRY(prof_end(m, EXPDG_K_GS_FINISH, 8.0 * rp.nrb));
-        CO_HIPTRY(launch_fill<double>(kd.H, 0.0, (size_t)(kMaxM + 1) * kMaxM, s));
 
         R.j_acc = 0;
         R.err = 0.0;
@@ -266,7 +262,7 @@ Task<int> phi_co(X &x, expdg_mesh *m, const T *qref, double tau, int p, const T 
             a.vtail = vin + n;
             a.otail = w + n;
             a.vscale = kd.S + (j - 1);
-            a.nv = j;
+            a.nv = fuse_dots ? j : 0;
             const bool is_check =
                 !forced && (j == o->m_max || (j >= o->m_min && (j - o->m_min) % o->check_every == 0));
             CheckReq cr{};
@@ -377,8 +373,7 @@ Task<int> step_co(X &x, expdg_mesh *m, int scheme, double dt, double *q, double 
     if (scheme == EXPDG_EPI2 || (scheme == EXPDG_EPI3 && !(q_prev && have_prev))) {
         const T *b[2] = {nullptr, Rn};
         CO_AWAIT_TASK((phi_co<T, X>(x, m, qb, dt, 1, b, w, o, st, &fpos, true)));
-        if (q_prev) CO_HIPTRY(launch_copy(q, q_prev, n, s));
-        CO_HIPTRY(launch_add_to<T>(q, w, n, s));
+        CO_HIPTRY(launch_step_update<T>(q, q_prev, w, n, s));
     } else if (scheme == EXPDG_EPI3) {
         T *qpb = nullptr;
         CO_HIPTRY(view(q_prev, 1, &qpb));
@@ -393,8 +388,7 @@ Task<int> step_co(X &x, expdg_mesh *m, int scheme, double dt, double *q, double 
         CO_HIPTRY((launch_lincomb<T, T>(d, c, Rp, -c, Rn, -c, Ld, n, s)));  // b_2 into d
         const T *b[3] = {nullptr, Rn, d};
         CO_AWAIT_TASK((phi_co<T, X>(x, m, qb, dt, 2, b, w, o, st, &fpos, true)));
-        CO_HIPTRY(launch_copy(q, q_prev, n, s));
-        CO_HIPTRY(launch_add_to<T>(q, w, n, s));
+        CO_HIPTRY(launch_step_update<T>(q, q_prev, w, n, s));
     } else {  // EXPRB32
         const T *b1[2] = {nullptr, Rn};
         CO_AWAIT_TASK((phi_co<T, X>(x, m, qb, dt, 1, b1, w, o, st, &fpos, true)));

@@ -601,6 +601,30 @@ __global__ void set_tail_kernel(T *x, int p, double last) {
         for (int k = 0; k < p; ++k) x[k] = (k == p - 1) ? (T)last : T(0);
 }
 
+// Start vector of a phi evaluation: z[0..n) = b0 (or 0), z[n..n+p) =
+// (0, ..., 0, last); the Krylov flags (4 ints) cleared.
+template <typename T>
+__global__ __launch_bounds__(256) void phi_init_kernel(T *z, const T *b0, size_t n, int p,
+                                                       double last, int *flags) {
+    for (size_t r = (size_t)blockIdx.x * 256 + threadIdx.x; r < n; r += (size_t)gridDim.x * 256)
+        z[r] = b0 ? b0[r] : T(0);
+    if (blockIdx.x == 0 && threadIdx.x < 4) flags[threadIdx.x] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        for (int k = 0; k < p; ++k) z[n + k] = (k == p - 1) ? (T)last : T(0);
+}
+
+// End of a step: q_prev = q (if given), then q += w.
+template <typename T>
+__global__ __launch_bounds__(256) void step_update_kernel(double *q, double *q_prev, const T *w,
+                                                          size_t n) {
+    for (size_t r = (size_t)blockIdx.x * 256 + threadIdx.x; r < n;
+         r += (size_t)gridDim.x * 256) {
+        const double x = q[r];
+        if (q_prev) q_prev[r] = x;
+        q[r] = x + (double)w[r];
+    }
+}
+
 int grid_for(size_t n) {
     size_t g = (n + 255) / 256;
     if (g > 8192) g = 8192;
@@ -742,5 +766,26 @@ hipError_t launch_set_tail(T *x, int p, double last, hipStream_t s) {
 }
 template hipError_t launch_set_tail<double>(double *, int, double, hipStream_t);
 template hipError_t launch_set_tail<float>(float *, int, double, hipStream_t);
+
+template <typename T>
+hipError_t launch_phi_init(T *z, const T *b0, size_t n, int p, double last, int *flags,
+                           hipStream_t s) {
+    phi_init_kernel<T><<<grid_for(n), 256, 0, s>>>(z, b0, n, p, last, flags);
+    return hipGetLastError();
+}
+template hipError_t launch_phi_init<double>(double *, const double *, size_t, int, double, int *,
+                                            hipStream_t);
+template hipError_t launch_phi_init<float>(float *, const float *, size_t, int, double, int *,
+                                           hipStream_t);
+
+template <typename T>
+hipError_t launch_step_update(double *q, double *q_prev, const T *w, size_t n, hipStream_t s) {
+    step_update_kernel<T><<<grid_for(n), 256, 0, s>>>(q, q_prev, w, n);
+    return hipGetLastError();
+}
+template hipError_t launch_step_update<double>(double *, double *, const double *, size_t,
+                                               hipStream_t);
+template hipError_t launch_step_update<float>(double *, double *, const float *, size_t,
+                                              hipStream_t);
 
 }  // namespace expdg

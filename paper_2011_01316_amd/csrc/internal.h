@@ -113,6 +113,14 @@ hipError_t launch_fill(T *x, double val, size_t n, hipStream_t s);
 // x[0..p) = (0, ..., 0, last)
 template <typename T>
 hipError_t launch_set_tail(T *x, int p, double last, hipStream_t s);
+// Start vector of a phi evaluation: z[0..n) = b0 (nullptr: 0), z[n..n+p) =
+// (0, ..., 0, last), flags[0..4) = 0.
+template <typename T>
+hipError_t launch_phi_init(T *z, const T *b0, size_t n, int p, double last, int *flags,
+                           hipStream_t s);
+// End of a step: q_prev = q (if q_prev), then q += w.
+template <typename T>
+hipError_t launch_step_update(double *q, double *q_prev, const T *w, size_t n, hipStream_t s);
 
 // ---- Krylov kernels (krylov_kernels.hip) ----
 struct KrylovDev {
@@ -170,8 +178,9 @@ hipError_t launch_gs_finish_pass2(const double *part, int nv, const RowPartition
 // Fixed-order finish of a norm pass: hn = sqrt(sum_b part[b]).  col >= 0:
 // H[col+1][col] = hn, breakdown test against ||H||_F (flags[0] = col+1 the
 // first time, S[col+1] = 0), else S[col+1] = 1/hn; flags[1] = col+1 the first
-// time a norm is non-finite.  col < 0 (start vector): res[0] = beta = hn,
-// S[0] = 1/beta, flags[0] = 0, flags[1] = 1 if beta is non-finite, else 0.
+// time a norm is non-finite.  col < 0 (start vector of a substep): res[0] =
+// beta = hn, S[0] = 1/beta, flags[0] = 0, flags[1] = 1 if beta is
+// non-finite, else 0, and the Hessenberg matrix is cleared.
 hipError_t launch_gs_finish_norm(const double *part, const RowPartition &rp, double *H, double *S,
                                  int col, int *flags, double *res, hipStream_t s);
 // Norms of up to 4 vectors of length n (block partials, then finish):
@@ -203,14 +212,15 @@ struct GsItem {
     double *w;
     size_t stride, L, rpb;
     int nrb, nv, col;    // col = nv - 1
-    int nrb1;            // partials per vector of the first pass (linear operator blocks)
+    int nrb1;            // partials per vector of a first pass fused into the linear
+                         // operator (its blocks), or 0: a separate dot pass
     double *part, *S, *H, *coefA, *coefB, *res;
     int *flags;
 };
-// Block ranges of a grouped Arnoldi step: (unused: the first dots run inside
-// the linear operator), first finish, fused update+dots+norm (nv <= 32),
-// plain update (nv > 32), dots with w itself after it (nv > 32), final
-// update.  (The second finish runs one block per item.)
+// Block ranges of a grouped Arnoldi step: first dots (items whose linear
+// operator does not carry them), first finish, fused update+dots+norm
+// (nv <= 32), plain update (nv > 32), dots with w itself after it (nv > 32),
+// final update.  (The second finish runs one block per item.)
 constexpr int kGroupLaunches = 6;
 // Host: block ranges bstart[k*(n+1) + it] of launch k and the totals.
 void arnoldi_group_layout(const GsItem *items, int n, int *bstart, int *totals);

@@ -139,6 +139,8 @@ __device__ __forceinline__ void finish_norm_body(const double *part, int nrb, co
             f.flags[0] = 0;
             f.flags[1] = isfinite(hn) ? 0 : 1;
         }
+        // a new substep: the Hessenberg matrix starts from zero
+        for (int e = tid; e < (kMaxM + 1) * LDH; e += 256) f.H[e] = 0.0;
         return;
     }
     // ||H_{0:col+2, 0:col+1}||_F including the new subdiagonal entry
@@ -818,14 +820,14 @@ __global__ __launch_bounds__(256) void gs_dots_group(const GsItem *items, const 
                          local % g.nrb, local / g.nrb);
 }
 
-// Finish of the first pass (its partials come from the linear operator's
-// blocks: nrb1 per vector).
+// Finish of the first pass: nrb1 partials per vector from the linear
+// operator's blocks, or (nrb1 = 0) nrb from the separate dot pass.
 __global__ __launch_bounds__(256) void finish_dots_group(const GsItem *items, const int *bstart,
                                                          int n) {
     const int it = group_item(bstart, n, blockIdx.x);
     const GsItem &g = items[it];
     const DotFinish f{g.S, g.H, g.col, 0, g.coefA};
-    finish_dots_body(g.part, g.nv, g.nrb1, f, blockIdx.x - bstart[it]);
+    finish_dots_body(g.part, g.nv, g.nrb1 > 0 ? g.nrb1 : g.nrb, f, blockIdx.x - bstart[it]);
 }
 
 __global__ __launch_bounds__(256) void gs_update_dots_group(const GsItem *items,
@@ -1006,8 +1008,7 @@ void arnoldi_group_layout(const GsItem *items, int n, int *bstart, int *totals) 
         const int chunks = (g.nv + CH - 1) / CH;
         const int chunks2 = (g.nv + 1 + CH - 1) / CH;  // with w itself
         const bool small = g.nv <= 32;
-        (void)chunks;
-        const int blocks[kGroupLaunches] = {0, (g.nv + 3) / 4,
+        const int blocks[kGroupLaunches] = {g.nrb1 > 0 ? 0 : g.nrb * chunks, (g.nv + 3) / 4,
                                             small ? g.nrb : 0,     small ? 0 : g.nrb,
                                             small ? 0 : g.nrb * chunks2, g.nrb};
         for (int k = 0; k < kGroupLaunches; ++k) {
@@ -1027,7 +1028,11 @@ hipError_t launch_arnoldi_group(const GsItem *items, const int *bstart, const in
     const int *b[kGroupLaunches];
     for (int k = 0; k < kGroupLaunches; ++k) b[k] = bstart + (size_t)k * (n + 1);
     hipError_t e;
-    // first pass: h1 = V^T w from the linear operator's block partials
+    // first pass: h1 = V^T w (partials from the linear operator, or a dot pass)
+    if (totals[0] > 0) {
+        e = launch_kernel(gs_dots_group, dim3(totals[0]), dim3(256), 0, s, items, b[0], n, 0);
+        if (e != hipSuccess) return e;
+    }
     e = launch_kernel(finish_dots_group, dim3(totals[1]), dim3(256), 0, s, items, b[1], n);
     if (e != hipSuccess) return e;
     // second pass: w -= V h1 ; h2 = V^T w and ||w||^2 (fused for j <= 32)

@@ -260,7 +260,7 @@ ServeExec::Await ServeExec::iterate(expdg_mesh *m, const OpArgs<double> &a, int 
     g.L = L;
     g.rpb = rp.rpb;
     g.nrb = rp.nrb;
-    g.nrb1 = a.dnb;
+    g.nrb1 = (a.nv > 0) ? a.dnb : 0;  // 0: a separate first dot pass
     g.nv = j;
     g.col = j - 1;
     g.part = kd.part;
