@@ -250,6 +250,8 @@ def run_served(args):
 
     # the first requests one after another through expdg_step
     K = min(args.serve_seq, len(items))
+    if K < 1:
+        return out
     t = time.time()
     work = 0.0
     for it in items[:K]:
@@ -353,11 +355,16 @@ def main():
     ap.add_argument("--serve-max-active", type=int, default=256)
     ap.add_argument("--serve-seq", type=int, default=40,
                     help="first requests also run one after another for comparison")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="only run the served workload and print its figures")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only time a plain 1 GiB device copy and print it")
     args = ap.parse_args()
     if args.copy_probe:
         print(json.dumps(copy_probe()), flush=True)
+        return
+    if args.serve_only:
+        print(json.dumps(run_served(args)), flush=True)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

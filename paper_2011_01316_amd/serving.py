@@ -88,6 +88,8 @@ def run(server, items, keep_states=False, progress=None, time_limit=None):
     with their status and their work still counts in the DOF-stage rate.
     """
     n = len(items)
+    if n == 0:
+        raise ValueError("no requests to serve")
     order = sorted(range(n), key=lambda k: items[k]["arrival"])
     t0 = server.clock()
     nxt = 0
