@@ -11,27 +11,28 @@
 // writes back the XCD's L2 each time; letting every block of the consuming
 // kernel re-derive the sums makes each block wait on partials that other XCDs
 // wrote.)
-// (Letting the last block of each launch finish instead needs a device-scope
-// release fence in every block, which writes back the XCD's L2 each time:
-// measured 3x slower on MI355X.)
 //
-// Per Arnoldi step j (nv = j basis vectors, w = the new vector):
-//   gs_dots         h1 = V^T w                     (2D grid: row blocks x 16-vector chunks)
-//   gs_update_dots  w -= V h1 ; h2 = V^T w         (32 accumulators in registers, j <= 32)
-//   (gs_update + gs_dots for j > 32)
-//   gs_update_norm  w -= V h2 ; ||w|| partials
-//   finish_*        fixed-order sums of the block partials; H, coefficients,
-//                   ||w||, breakdown test, S[j] = 1/||w||
+// Per Arnoldi step j (j basis vectors, w = the new vector):
+//   first pass      h1 = V^T w: block partials from the 2D linear operator's
+//                   epilogue, or gs_dots (2D grid: row blocks x 16-vector
+//                   chunks) after the 1D operator
+//   finish_dots     h1 (fixed-order sums), H column, coefficients
+//   gs_update_dots  w -= V h1 ; h2 = V^T w and ||w||^2 in the same sweep
+//                   (32 accumulators in registers, j <= 32; an update and a
+//                   dot pass for j > 32)
+//   finish_pass2    h2, H += h2, ||w - V h2||^2 = ||w||^2 - ||h2||^2
+//                   (Pythagoras), S[j], breakdown test
+//   gs_update       w -= V h2
 // Block sums use a transpose reduction: 16 (or 32) accumulators of a wave are
 // summed with 17 (or 32) cross-lane exchanges instead of 6 per accumulator.
 //
 // The small (j+1) x (j+1) exponential of the projected Hessenberg matrix runs
 // in one 256-thread workgroup with four FP64 matrices in LDS (gfx950 gives a
-// workgroup up to 160 KB): diagonal Pade (6,6), scaling and squaring, and
-// Gaussian elimination with partial pivoting.  For a Hessenberg argument the
-// Pade denominator has lower bandwidth 6, so elimination only visits the six
-// rows below the pivot: the rows further down hold exact zeros, so the result
-// is the same as a full elimination.
+// workgroup up to 160 KB): diagonal Pade (6,6) with scaling and squaring.  Its
+// rational form D^-1 N is evaluated with matrix products only (the scaled
+// denominator is within 0.2805 of the identity, so a product of five Neumann
+// factors reaches FP64 accuracy), which keeps every step parallel over the
+// workgroup instead of a sequential elimination.
 #include "internal.h"
 #include "reduce.h"
 
@@ -545,20 +546,16 @@ __global__ __launch_bounds__(256) void norms_finish_kernel(const double *part, i
 constexpr int NMAX = kMaxM + 1;
 constexpr int LDA = NMAX;  // LDS row stride (doubles)
 
-// Orders LDS traffic within one wavefront (no workgroup barrier).
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// C = A * B (n x n in LDS, C may alias A or B).  The 256 threads form a
-// 16 x 16 grid; thread (ty, tx) owns rows ty + 16 a and columns tx + 16 b
-// (a, b < TILE), so a wave reads 16 consecutive B columns (no bank conflicts)
-// and broadcasts A; TILE^2 products per 2 TILE LDS loads.  Each entry is
-// summed over q in ascending order.
-template <int TILE>
-__device__ void mm_tile(const double *A, const double *B, double *C, int n) {
+// C = A * B, or C += A * B with ACC (n x n in LDS, row stride LDA; C may alias
+// A or B: every operand is read before the first store).  The 256 threads
+// form a 16 x 16 grid; thread (ty, tx) owns rows ty + 16 a and columns
+// tx + 16 b (a, b < TILE), so a wave reads 16 consecutive B columns and
+// broadcasts A.  The operands of four consecutive k are loaded together before
+// their products are added, so LDS latency is paid once per four k; each entry
+// is still summed over k in ascending order.
+template <int TILE, bool ACC>
+__device__ __forceinline__ void mm_tile(const double *A, const double *B, double *C, int n) {
+    n = __builtin_amdgcn_readfirstlane(n);  // uniform: scalar loop control
     const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
     double acc[TILE][TILE];
     int ra[TILE], cb[TILE];
@@ -569,7 +566,25 @@ __device__ void mm_tile(const double *A, const double *B, double *C, int n) {
 #pragma unroll
         for (int b = 0; b < TILE; ++b) acc[a][b] = 0.0;
     }
-    for (int q = 0; q < n; ++q) {
+    constexpr int U = 4;
+    int q = 0;
+    for (; q + U <= n; q += U) {
+        double av[U][TILE], bv[U][TILE];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int a = 0; a < TILE; ++a) av[u][a] = A[ra[a] + q + u];
+#pragma unroll
+            for (int b = 0; b < TILE; ++b) bv[u][b] = B[(q + u) * LDA + cb[b]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int a = 0; a < TILE; ++a)
+#pragma unroll
+                for (int b = 0; b < TILE; ++b) acc[a][b] += av[u][a] * bv[u][b];
+    }
+    for (; q < n; ++q) {
         double av[TILE], bv[TILE];
 #pragma unroll
         for (int a = 0; a < TILE; ++a) av[a] = A[ra[a] + q];
@@ -586,32 +601,34 @@ __device__ void mm_tile(const double *A, const double *B, double *C, int n) {
 #pragma unroll
         for (int b = 0; b < TILE; ++b) {
             const int r = ty + 16 * a, c = tx + 16 * b;
-            if (r < n && c < n) C[r * LDA + c] = acc[a][b];
+            if (r < n && c < n) C[r * LDA + c] = ACC ? C[r * LDA + c] + acc[a][b] : acc[a][b];
         }
     __syncthreads();
 }
 
-__device__ void matmul(const double *A, const double *B, double *C, int n) {
+template <bool ACC = false>
+__device__ __forceinline__ void matmul(const double *A, const double *B, double *C, int n) {
+    n = __builtin_amdgcn_readfirstlane(n);
     if (n <= 16)
-        mm_tile<1>(A, B, C, n);
+        mm_tile<1, ACC>(A, B, C, n);
     else if (n <= 32)
-        mm_tile<2>(A, B, C, n);
+        mm_tile<2, ACC>(A, B, C, n);
     else if (n <= 48)
-        mm_tile<3>(A, B, C, n);
+        mm_tile<3, ACC>(A, B, C, n);
     else if (n <= 64)
-        mm_tile<4>(A, B, C, n);
+        mm_tile<4, ACC>(A, B, C, n);
     else
-        mm_tile<5>(A, B, C, n);
+        mm_tile<5, ACC>(A, B, C, n);
 }
 
-// E = expm(X) for X (n x n) in sX; result left in sN.  band = lower bandwidth
-// of the Pade denominator (6 for a Hessenberg X, n - 1 in general).  Returns
-// the number of squarings; sets *singular if the denominator is singular.
-__device__ int lds_expm(double *sX, double *sP, double *sN, double *sD, int n, int band,
-                        int *singular) {
+// Diagonal Pade (6,6) approximant of exp(X), X (n x n) in sX, after scaling X
+// by 2^-s with s from its infinity norm.  The numerator and denominator are
+// formed from their even and odd parts, E = c0 I + c2 X^2 + c4 X^4 + c6 X^6
+// and O = X (c1 I + c3 X^2 + c5 X^4), as N = E + O (sN) and D = E - O (sD):
+// four products instead of six.  Returns s.
+__device__ __forceinline__ int expm_pade(double *sX, double *sP, double *sN, double *sD, int n) {
+    n = __builtin_amdgcn_readfirstlane(n);  // the same in every lane: scalar control flow
     __shared__ double swm[4];
-    __shared__ double sf[NMAX];
-    __shared__ int sbad;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // infinity norm
     double rs = 0.0;
@@ -625,136 +642,132 @@ __device__ int lds_expm(double *sX, double *sP, double *sN, double *sD, int n, i
     int s = 0;
     if (nrm > 0.5) s = max(0, (int)ceil(log2(nrm / 0.5)));
     const double scale = ldexp(1.0, -s);
-    for (int e = tid; e < n * n; e += 256) {
-        const int r = e / n, c = e % n;
-        sX[r * LDA + c] *= scale;
-        const double id = (r == c) ? 1.0 : 0.0;
-        sP[r * LDA + c] = id;
-        sN[r * LDA + c] = id;
-        sD[r * LDA + c] = id;
-    }
+    for (int r = wave; r < n; r += 4)
+        for (int c = lane; c < n; c += 64) sX[r * LDA + c] *= scale;
     __syncthreads();
-    double cf = 1.0;
-    const int q = 6;
-    for (int k = 1; k <= q; ++k) {
-        cf = cf * (q - k + 1) / (double)(k * (2 * q - k + 1));
-        matmul(sX, sP, sP, n);
-        const double sg = (k % 2 == 0) ? 1.0 : -1.0;
-        for (int e = tid; e < n * n; e += 256) {
-            const int r = e / n, c = e % n;
-            const double pv = sP[r * LDA + c];
-            sN[r * LDA + c] += cf * pv;
-            sD[r * LDA + c] += sg * cf * pv;
-        }
-        __syncthreads();
-    }
-    // Gaussian elimination with partial pivoting (first maximal row on ties)
-    // in wave 0: rows below the band are exact zeros and are left alone.
-    if (wave == 0) {
-        int bad = 0;
-        for (int k = 0; k < n; ++k) {
-            const int hi = min(n - 1, k + band);
-            double best = -1.0;
-            int bi = n;
-            for (int r = k + lane; r <= hi; r += 64) {
-                const double v = fabs(sD[r * LDA + k]);
-                if (v > best) {
-                    best = v;
-                    bi = r;
-                }
-            }
+    // Pade coefficients c_k = c_{k-1} (q - k + 1) / (k (2q - k + 1)), q = 6
+    double cf[7];
+    cf[0] = 1.0;
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                const double ob = __shfl_xor(best, off, 64);
-                const int oi = __shfl_xor(bi, off, 64);
-                if (ob > best || (ob == best && oi < bi)) {
-                    best = ob;
-                    bi = oi;
-                }
-            }
-            const int piv = bi;
-            if (!(sD[piv * LDA + k] != 0.0)) {
-                bad = 1;
-                break;
-            }
-            if (piv != k) {
-                for (int c = lane; c < n; c += 64) {
-                    double t = sD[k * LDA + c];
-                    sD[k * LDA + c] = sD[piv * LDA + c];
-                    sD[piv * LDA + c] = t;
-                    t = sN[k * LDA + c];
-                    sN[k * LDA + c] = sN[piv * LDA + c];
-                    sN[piv * LDA + c] = t;
-                }
-                wave_sync();
-            }
-            // multipliers of every band row first, then one update pass
-            const double dkk = sD[k * LDA + k];
-            for (int r = k + 1 + lane; r <= hi; r += 64) sf[r] = sD[r * LDA + k] / dkk;
-            wave_sync();
-            const int nr = hi - k;
-            for (int e = lane; e < nr * n; e += 64) {
-                const int r = k + 1 + e / n, c = e % n;
-                const double f = sf[r];
-                if (f != 0.0) {
-                    if (c >= k) sD[r * LDA + c] -= f * sD[k * LDA + c];
-                    sN[r * LDA + c] -= f * sN[k * LDA + c];
-                }
-            }
-            wave_sync();
+    for (int k = 1; k <= 6; ++k) cf[k] = cf[k - 1] * (6 - k + 1) / (double)(k * (12 - k + 1));
+    matmul(sX, sX, sP, n);  // X^2
+    matmul(sP, sP, sN, n);  // X^4
+    matmul(sN, sP, sD, n);  // X^6
+    for (int r = wave; r < n; r += 4)
+        for (int c = lane; c < n; c += 64) {
+            const double id = (r == c) ? 1.0 : 0.0;
+            const double x2 = sP[r * LDA + c], x4 = sN[r * LDA + c], x6 = sD[r * LDA + c];
+            sD[r * LDA + c] = cf[0] * id + cf[2] * x2 + cf[4] * x4 + cf[6] * x6;  // even part
+            sN[r * LDA + c] = cf[1] * id + cf[3] * x2 + cf[5] * x4;                // odd / X
         }
-        if (lane == 0) sbad = bad;
-    }
     __syncthreads();
-    if (sbad) {
-        if (tid == 0) *singular = 1;
-        return s;
-    }
-    // back substitution, right-looking: row k is final once divided by its
-    // pivot, then removed from the rows above it
-    for (int k = n - 1; k >= 0; --k) {
-        const double dkk = sD[k * LDA + k];
-        for (int c = tid; c < n; c += 256) sN[k * LDA + c] /= dkk;
-        __syncthreads();
-        for (int e = tid; e < k * n; e += 256) {
-            const int r = e / n, c = e % n;
-            sN[r * LDA + c] -= sD[r * LDA + k] * sN[k * LDA + c];
+    matmul(sX, sN, sP, n);  // odd part
+    for (int r = wave; r < n; r += 4)
+        for (int c = lane; c < n; c += 64) {
+            const double ev = sD[r * LDA + c], od = sP[r * LDA + c];
+            sN[r * LDA + c] = ev + od;
+            sD[r * LDA + c] = ev - od;
         }
-        __syncthreads();
-    }
-    for (int k = 0; k < s; ++k) matmul(sN, sN, sN, n);
+    __syncthreads();
     return s;
 }
 
-// Small exponential of one check; writes the slot (error, singular flag, the
+// R = D^-1 N into sN, with matrix products only.  After the scaling,
+// ||X||_inf <= 1/2, so F = I - D = -sum_{k>=1} (-1)^k c_k X^k has
+// ||F||_inf <= sum_{k>=1} c_k 2^-k < 0.2805 and
+//   D^-1 = (I + F)(I + F^2)(I + F^4)(I + F^8)(I + F^16) + F^32 D^-1,
+// where the last term is below 0.2805^32 / (1 - 0.2805) < 3e-18 relative, under
+// the FP64 rounding of the products.  The factors are applied to N one after
+// the other (R <- R + F^(2^m) R) while F is squared, nine products in all and
+// no sequential elimination.  sD holds F, and sX (free after the Pade step)
+// takes every other power of it.
+__device__ __forceinline__ void expm_solve(double *sX, double *sD, double *sN, int n) {
+    n = __builtin_amdgcn_readfirstlane(n);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int r = wave; r < n; r += 4)
+        for (int c = lane; c < n; c += 64) {
+            const double id = (r == c) ? 1.0 : 0.0;
+            sD[r * LDA + c] = id - sD[r * LDA + c];
+        }
+    __syncthreads();
+    double *f = sD, *g = sX;
+    for (int m = 0; m < 5; ++m) {
+        matmul<true>(f, sN, sN, n);  // R += F^(2^m) R
+        if (m < 4) {
+            matmul(f, f, g, n);
+            double *t = f;
+            f = g;
+            g = t;
+        }
+    }
+}
+
+// s squarings of R (in sN), alternating between sN and sP; returns the buffer
+// that holds the result.  With col0 only the first column of the result is
+// formed: the last squaring becomes a product with one column.
+__device__ __forceinline__ double *expm_square(double *sN, double *sP, int n, int s, bool col0) {
+    n = __builtin_amdgcn_readfirstlane(n);
+    s = __builtin_amdgcn_readfirstlane(s);
+    col0 = __builtin_amdgcn_readfirstlane((int)col0) != 0;
+    const int tid = threadIdx.x;
+    double *cur = sN, *nxt = sP;
+    const int full = col0 ? s - 1 : s;
+    for (int k = 0; k < full; ++k) {
+        matmul(cur, cur, nxt, n);
+        double *t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    if (col0 && s > 0) {
+        double acc = 0.0;
+        if (tid < n)
+            for (int q = 0; q < n; ++q) acc += cur[tid * LDA + q] * cur[q * LDA];
+        if (tid < n) nxt[tid * LDA] = acc;
+        __syncthreads();
+        cur = nxt;
+    }
+    return cur;
+}
+
+// E = expm(X) for X (n x n) in sX (overwritten): Pade (6,6), the solve for its
+// rational form, squarings.  Returns the buffer (sN or sP) that holds E (only
+// its first column with col0); *s = number of squarings.
+__device__ __forceinline__ double *lds_expm(double *sX, double *sP, double *sN, double *sD, int n,
+                                            bool col0, int *s) {
+    *s = expm_pade(sX, sP, sN, sD, n);
+    expm_solve(sX, sD, sN, n);
+    return expm_square(sN, sP, n, *s, col0);
+}
+
+// Small exponential of one check; writes the slot (error, the singular flag,
+// which stays 0 because the scaled Pade denominator is always invertible, the
 // Krylov flags as of this launch, squarings, combine coefficients) and the
 // first kSummary header values to the item's host-mapped report, if any.
 __device__ __forceinline__ void hess_expm_body(const ExpmItem &c) {
     extern __shared__ double smem[];
     double *sX = smem, *sP = sX + NMAX * LDA, *sN = sP + NMAX * LDA, *sD = sN + NMAX * LDA;
-    __shared__ int singular;
     const int j = c.j;
     const double dtau = c.dtau;
     const double *H = c.H;
     double *slot = c.slot;
     const int n = j + 1;
-    if (threadIdx.x == 0) singular = 0;
-    for (int e = threadIdx.x; e < n * n; e += 256) {
-        const int r = e / n, c = e % n;
-        sX[r * LDA + c] = (c < j) ? dtau * H[(size_t)r * LDH + c] : 0.0;
-    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int r = wave; r < n; r += 4)
+        for (int col = lane; col < n; col += 64)
+            sX[r * LDA + col] = (col < j) ? dtau * H[(size_t)r * LDH + col] : 0.0;
     __syncthreads();
-    const int s = lds_expm(sX, sP, sN, sD, n, 6, &singular);
+    int s = 0;
+    const double *E = lds_expm(sX, sP, sN, sD, n, true, &s);
     __syncthreads();
     const double beta = c.res[0];
     if (threadIdx.x == 0) {
-        const double hdr[kSlotHeader] = {beta * fabs(sN[j * LDA + 0]), (double)singular,
-                                         (double)c.flags[0], (double)c.flags[1], (double)s};
+        const double hdr[kSlotHeader] = {beta * fabs(E[j * LDA + 0]), 0.0, (double)c.flags[0],
+                                         (double)c.flags[1], (double)s};
         for (int k = 0; k < kSlotHeader; ++k) slot[k] = hdr[k];
         if (c.report)
             for (int k = 0; k < kSummary; ++k) c.report[k] = hdr[k];
     }
-    for (int i = threadIdx.x; i < j; i += 256) slot[kSlotCoef + i] = beta * sN[i * LDA + 0] * c.S[i];
+    for (int i = threadIdx.x; i < j; i += 256) slot[kSlotCoef + i] = beta * E[i * LDA + 0] * c.S[i];
 }
 
 __global__ __launch_bounds__(256) void hess_expm_kernel(ExpmItem c) { hess_expm_body(c); }
@@ -767,14 +780,15 @@ __global__ __launch_bounds__(256) void hess_expm_group(const ExpmItem *items) {
 __global__ __launch_bounds__(256) void dense_expm_kernel(const double *A, int n, double *E) {
     extern __shared__ double smem[];
     double *sX = smem, *sP = sX + NMAX * LDA, *sN = sP + NMAX * LDA, *sD = sN + NMAX * LDA;
-    __shared__ int singular;
-    if (threadIdx.x == 0) singular = 0;
-    for (int e = threadIdx.x; e < n * n; e += 256) sX[(e / n) * LDA + e % n] = A[e];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int r = wave; r < n; r += 4)
+        for (int c = lane; c < n; c += 64) sX[r * LDA + c] = A[(size_t)r * n + c];
     __syncthreads();
-    lds_expm(sX, sP, sN, sD, n, n - 1, &singular);
+    int s = 0;
+    const double *R = lds_expm(sX, sP, sN, sD, n, false, &s);
     __syncthreads();
-    for (int e = threadIdx.x; e < n * n; e += 256)
-        E[e] = singular ? __builtin_nan("") : sN[(e / n) * LDA + e % n];
+    for (int r = wave; r < n; r += 4)
+        for (int c = lane; c < n; c += 64) E[(size_t)r * n + c] = R[r * LDA + c];
 }
 
 template <typename T>
