@@ -187,7 +187,7 @@ size_t layout(expdg_mesh *m, const expdg_mesh_desc *d, size_t stride, int eb, ch
     take(m->kd.part, npart * (kMaxM + 1) * 8);
     take(m->kd.res, 64 * 8);
     take(m->kd.flags, 16);
-    take(m->slots, 2 * kSlotSize * 8);
+    take(m->slots, (size_t)kCheckSlots * kSlotSize * 8);
     take(m->dnorm, 8 * 8);
     take(m->spart, 1024 * 8);
     return (off + 255) / 256 * 256;
@@ -487,6 +487,9 @@ namespace {
 // the next Arnoldi step, and is read back one step later.
 template <typename T>
 struct DirectExec {
+    // a check is decided one Arnoldi step after the one that launched it (a
+    // deeper lookahead measured slower: the host, not the check, sets the pace)
+    static constexpr int kLookahead = 1;
     hipStream_t s;
 
     hipStream_t stream() const { return s; }
@@ -526,7 +529,8 @@ struct DirectExec {
         const bool fused = a.nv > 0;
         TRY(prof_begin(m, EXPDG_K_LINEAR));
         HIPTRY(launch_dg_op(m->d.equation, m->d.p, true, a, s));
-        TRY(prof_end(m, EXPDG_K_LINEAR, (double)(3 + naug_nz + (fused ? j : 0)) * n * eb));
+        TRY(prof_end(m, EXPDG_K_LINEAR,
+                     op_bytes(m, true) + (double)(naug_nz + (fused ? j : 0)) * n * eb));
         if (!fused) {
             TRY(prof_begin(m, EXPDG_K_GS_DOTS));
             HIPTRY(launch_gs_dots<T>(V, stride, j, w, L, rp, kd.part, kd.S, kd.H, col, 0, kd.coefA,
@@ -610,11 +614,11 @@ extern "C" int expdg_phi_krylov(expdg_mesh *m, const void *qref, double tau, int
     if (m->d.precision == EXPDG_FP64) {
         DirectExec<double> x{st};
         return run_now(phi_co<double>(x, m, (const double *)qref, tau, p, (const double *const *)b,
-                                      (double *)w, o, s, &fpos, false));
+                                      (double *)w, o, s, &fpos, false, false));
     }
     DirectExec<float> x{st};
     return run_now(phi_co<float>(x, m, (const float *)qref, tau, p, (const float *const *)b,
-                                 (float *)w, o, s, &fpos, false));
+                                 (float *)w, o, s, &fpos, false, false));
 }
 
 extern "C" int expdg_step(expdg_mesh *m, int scheme, double dt, double *q, double *q_prev,

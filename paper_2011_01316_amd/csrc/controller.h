@@ -25,7 +25,9 @@
 //   awaitable<int> wait_check(m, c): the check's header is in the pinned mirror;
 //   int after_check(m, c): the stream waits for the check's coefficients;
 //   awaitable<int> readback(m): device-to-host copies enqueued so far are done;
-//   awaitable<int> finish(m): the end of one library call.
+//   awaitable<int> finish(m): the end of one library call;
+//   static constexpr int kLookahead: how many Arnoldi steps a check's decision
+//       may lag behind the step that launched it (1 .. kCheckSlots - 2).
 #pragma once
 
 #include <algorithm>
@@ -89,7 +91,7 @@ struct PhiRun {
     PhiRun(X &x_, expdg_mesh *m_, const expdg_krylov_opts *o_, expdg_krylov_stats *st_)
         : x(x_), m(m_), o(o_), st(st_) {}
 
-    CheckReq req(int j, double dtau) { return CheckReq{j, dtau, (nchecks++) & 1}; }
+    CheckReq req(int j, double dtau) { return CheckReq{j, dtau, (nchecks++) % kCheckSlots}; }
 
     // Decision on check c: accept (possibly after shrinking the substep on the
     // same basis at m_max), take a happy breakdown, or go on (done = false).
@@ -162,10 +164,14 @@ struct PhiRun {
 // w = sum_{k=0}^{p} tau^k phi_k(tau L~) b_k by the augmented Krylov method
 // (Section 2.3), with L~ the linear operator frozen at qref.  b[k] == nullptr
 // is a zero vector.  *fpos walks a forced substep schedule.  lin_ready: the
-// frozen fields of qref are already in the workspace.
+// frozen fields of qref are already in the workspace.  nested: called inside a
+// step, whose own end waits for the device, so this evaluation ends without
+// waiting (a speculative check may still run on the side stream; it only
+// writes its own result slot, and later checks queue behind it).
 template <typename T, typename X>
 Task<int> phi_co(X &x, expdg_mesh *m, const T *qref, double tau, int p, const T *const *b, T *out,
-                 const expdg_krylov_opts *o, expdg_krylov_stats *st, int *fpos, bool lin_ready) {
+                 const expdg_krylov_opts *o, expdg_krylov_stats *st, int *fpos, bool lin_ready,
+                 bool nested) {
     hipStream_t s = x.stream();
     const size_t n = m->n, L = n + (size_t)p;
     const size_t stride = m->stride;
@@ -198,7 +204,7 @@ Task<int> phi_co(X &x, expdg_mesh *m, const T *qref, double tau, int p, const T 
             CO_HIPTRY(launch_copy(bx[0], out, n, s));
         else
             CO_HIPTRY(launch_fill<T>(out, 0.0, n, s));
-        CO_TRY(co_await x.finish(m));
+        if (!nested) CO_TRY(co_await x.finish(m));
         co_return EXPDG_OK;
     }
     PhiRun<T, X> R(x, m, o, st);
@@ -251,8 +257,8 @@ Task<int> phi_co(X &x, expdg_mesh *m, const T *qref, double tau, int p, const T 
 
         R.j_acc = 0;
         R.err = 0.0;
-        Check pending;
-        bool have_pending = false;
+        Check pend[kCheckSlots];  // checks launched and not yet decided, oldest first
+        int np = 0;
         for (int j = 1; j <= m_target; ++j) {
             T *vin = V + (size_t)(j - 1) * stride;
             T *w = V + (size_t)j * stride;
@@ -274,22 +280,18 @@ Task<int> phi_co(X &x, expdg_mesh *m, const T *qref, double tau, int p, const T 
                 st->jvps += 1;
             }
             if (forced) continue;
-            // look one check behind: the device works on step j meanwhile
+            // decide the checks at least kLookahead steps old (all of them at
+            // the last step): the device works on the newer steps meanwhile
+            if (is_check) pend[np++] = cur;
             bool done = false;
-            if (have_pending) {
-                have_pending = false;
-                CO_AWAIT_TASK(R.decide(pending, &done));
+            while (np > 0 && (j == m_target || pend[0].j <= j - X::kLookahead)) {
+                const Check c = pend[0];
+                for (int k = 1; k < np; ++k) pend[k - 1] = pend[k];
+                --np;
+                CO_AWAIT_TASK(R.decide(c, &done));
                 if (done) break;
             }
-            if (is_check) {
-                pending = cur;
-                have_pending = true;
-            }
-            if (j == m_target && have_pending) {
-                have_pending = false;
-                CO_AWAIT_TASK(R.decide(pending, &done));
-                if (done) break;
-            }
+            if (done) break;
         }
         if (forced) {
             Check fc;
@@ -336,7 +338,7 @@ Task<int> phi_co(X &x, expdg_mesh *m, const T *qref, double tau, int p, const T 
         std::memcpy(fl, m->pin + kPinNorms, 8);
         if (fl[1]) co_return fail(EXPDG_ENONFINITE, "non-finite Krylov norm");
     }
-    CO_TRY(co_await x.finish(m));
+    if (!nested) CO_TRY(co_await x.finish(m));
     co_return EXPDG_OK;
 }
 
@@ -372,7 +374,7 @@ Task<int> step_co(X &x, expdg_mesh *m, int scheme, double dt, double *q, double 
 
     if (scheme == EXPDG_EPI2 || (scheme == EXPDG_EPI3 && !(q_prev && have_prev))) {
         const T *b[2] = {nullptr, Rn};
-        CO_AWAIT_TASK((phi_co<T, X>(x, m, qb, dt, 1, b, w, o, st, &fpos, true)));
+        CO_AWAIT_TASK((phi_co<T, X>(x, m, qb, dt, 1, b, w, o, st, &fpos, true, true)));
         CO_HIPTRY(launch_step_update<T>(q, q_prev, w, n, s));
     } else if (scheme == EXPDG_EPI3) {
         T *qpb = nullptr;
@@ -387,11 +389,11 @@ Task<int> step_co(X &x, expdg_mesh *m, int scheme, double dt, double *q, double 
         const double c = 2.0 / (3.0 * dt);
         CO_HIPTRY((launch_lincomb<T, T>(d, c, Rp, -c, Rn, -c, Ld, n, s)));  // b_2 into d
         const T *b[3] = {nullptr, Rn, d};
-        CO_AWAIT_TASK((phi_co<T, X>(x, m, qb, dt, 2, b, w, o, st, &fpos, true)));
+        CO_AWAIT_TASK((phi_co<T, X>(x, m, qb, dt, 2, b, w, o, st, &fpos, true, true)));
         CO_HIPTRY(launch_step_update<T>(q, q_prev, w, n, s));
     } else {  // EXPRB32
         const T *b1[2] = {nullptr, Rn};
-        CO_AWAIT_TASK((phi_co<T, X>(x, m, qb, dt, 1, b1, w, o, st, &fpos, true)));
+        CO_AWAIT_TASK((phi_co<T, X>(x, m, qb, dt, 1, b1, w, o, st, &fpos, true, true)));
         CO_HIPTRY(launch_add_mixed<T>(m->q2, q, w, n, s));  // q2 = q^n + w1
         T *q2b = nullptr;
         CO_HIPTRY(view(m->q2, 2, &q2b));
@@ -405,7 +407,7 @@ Task<int> step_co(X &x, expdg_mesh *m, int scheme, double dt, double *q, double 
         const double c = 2.0 / (dt * dt);
         CO_HIPTRY((launch_lincomb<T, T>(d, c, Rp, -c, Rn, -c, Ld, n, s)));  // b_3 into d
         const T *b[4] = {nullptr, nullptr, nullptr, d};
-        CO_AWAIT_TASK((phi_co<T, X>(x, m, qb, dt, 3, b, w2, o, st, &fpos, true)));
+        CO_AWAIT_TASK((phi_co<T, X>(x, m, qb, dt, 3, b, w2, o, st, &fpos, true, true)));
         if (q_prev) CO_HIPTRY(launch_copy(q, q_prev, n, s));
         CO_HIPTRY(launch_add_mixed<T>(q, m->q2, w2, n, s));
     }

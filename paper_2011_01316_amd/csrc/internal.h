@@ -245,6 +245,7 @@ constexpr int kSlotHeader = 5;
 constexpr int kSummary = 4;        // header values a check reports to the host
 constexpr int kSlotCoef = 8;       // kMaxM combine coefficients
 constexpr int kSlotSize = kSlotCoef + kMaxM + 8;
+constexpr int kCheckSlots = 4;     // result slots of the checks in flight (one solve)
 
 // Grouped launches: block b belongs to the largest item it with
 // bstart[it] <= b (items with no blocks are skipped).

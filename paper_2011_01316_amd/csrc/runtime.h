@@ -31,14 +31,14 @@ struct expdg_mesh {
     double *q2 = nullptr;        // FP64 stage state (EXPRB32)
     void *lin = nullptr;         // frozen fields of the 2D linear operator (bulk type)
     expdg::KrylovDev kd{};
-    double *slots = nullptr;     // 2 x kSlotSize
+    double *slots = nullptr;     // kCheckSlots x kSlotSize
     double *dnorm = nullptr;     // 8
     double *spart = nullptr;     // 1024 (wave-speed partials)
     double *pin = nullptr;       // pinned, device-mapped host mirror (kPinSize doubles)
     double *pin_dev = nullptr;   // the device's address of pin
     bool owns_pin = false;
-    hipEvent_t ev[2] = {nullptr, nullptr};   // check results ready (side stream)
-    hipEvent_t evH[2] = {nullptr, nullptr};  // Hessenberg column ready (main stream)
+    hipEvent_t ev[expdg::kCheckSlots] = {};   // check results ready (side stream)
+    hipEvent_t evH[expdg::kCheckSlots] = {};  // Hessenberg column ready (main stream)
     hipStream_t side = nullptr;              // small exponentials run here
     size_t bytes = 0;
 
@@ -56,11 +56,11 @@ struct expdg_mesh {
 namespace expdg {
 
 // pinned mirror layout (doubles)
-constexpr int kPinSlots = 0;    // 2 x 8: the header of each check slot
-constexpr int kPinNorms = 16;   // 8 input norms
-constexpr int kPinSpeed = 32;   // 1024 wave-speed partials (stand-alone only)
-constexpr int kPinServed = 32;  // doubles a served solve needs
-constexpr int kPinSize = 32 + 1024;
+constexpr int kPinSlots = 0;                      // kCheckSlots x 8: check slot headers
+constexpr int kPinNorms = kPinSlots + kCheckSlots * 8;  // 8 input norms
+constexpr int kPinSpeed = kPinNorms + 8;             // 1024 wave-speed partials (stand-alone only)
+constexpr int kPinServed = kPinSpeed;                // doubles a served solve needs
+constexpr int kPinSize = kPinSpeed + 1024;
 
 // Records the message (thread-local, read by expdg_last_error) and returns code.
 int fail(int code, const char *fmt, ...);
@@ -146,6 +146,17 @@ hipError_t prepare_lin(expdg_mesh *m, const T *q, hipStream_t s) {
                                  m->d.gamma, s);
 }
 
+// Algorithmic bytes of one residual (jvp = false) or linear-operator
+// application: the input state and the output (residual); the input vector,
+// the output and either the frozen fields (2D) or the reference state (1D)
+// (linear operator).  Augmented blocks and fused dots are added by the caller.
+inline double op_bytes(const expdg_mesh *m, bool jvp) {
+    const double n = (double)m->n, eb = (double)m->ebytes;
+    if (!jvp) return 2.0 * n * eb;
+    const double lin = (double)lin_elems(m->d.equation, m->d.p, m->K);
+    return (lin > 0.0 ? 2.0 * n + lin : 3.0 * n) * eb;
+}
+
 // Residual (jvp = false) or linear operator of the mesh on stream s; the
 // linear operator needs the frozen fields of q prepared (prepare_lin).
 template <typename T>
@@ -158,7 +169,7 @@ int apply_op(expdg_mesh *m, bool jvp, const T *q, const T *v, T *out, hipStream_
     const int cls = jvp ? EXPDG_K_LINEAR : EXPDG_K_RESIDUAL;
     TRY(prof_begin(m, cls));
     HIPTRY(launch_dg_op(m->d.equation, m->d.p, jvp, a, s));
-    TRY(prof_end(m, cls, (double)(jvp ? 3 : 2) * m->n * m->ebytes));
+    TRY(prof_end(m, cls, op_bytes(m, jvp)));
     return EXPDG_OK;
 }
 

@@ -128,6 +128,8 @@ namespace {
 
 // The executor of one served solve.
 struct ServeExec {
+    // a solve decides a check one Arnoldi step after the one that launched it
+    static constexpr int kLookahead = 1;
     expdg_server *sv = nullptr;
     Req *r = nullptr;
 
