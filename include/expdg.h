@@ -195,12 +195,13 @@ int expdg_small_expm(int n, const double *A, double *E, void *hip_stream);
 enum {
     EXPDG_K_RESIDUAL = 0,       /* DG residual R(q) */
     EXPDG_K_LINEAR = 1,         /* DG linear operator L(q~) v (+ augmented block) */
-    EXPDG_K_GS_DOTS = 2,        /* Gram-Schmidt first pass: block partials of V^T w */
+    EXPDG_K_GS_DOTS = 2,        /* Arnoldi dot pass after the 1D operator (the 2D operator carries it) */
     EXPDG_K_SMALLEXPM = 3,      /* exponential of the projected Hessenberg matrix */
     EXPDG_K_COMBINE = 4,        /* Krylov combine z = beta V F e_1 */
-    EXPDG_K_GS_UPDATE_DOTS = 5, /* second pass: w -= V h1, partials of V^T w and ||w||^2 */
-    EXPDG_K_GS_UPDATE_NORM = 6, /* final update w -= V h2 (at a substep start: ||z||^2) */
-    EXPDG_K_GS_FINISH = 7,      /* fixed-order sums of the block partials */
+    EXPDG_K_GS_UPDATE = 5,      /* Arnoldi update sweep: second pass of the previous vector,
+                                   first pass of the new one */
+    EXPDG_K_GS_NORM = 6,        /* norm of a substep's start vector */
+    EXPDG_K_GS_FINISH = 7,      /* fixed-order sums of the block partials (step finish) */
     EXPDG_K_NCLASSES = 8
 };
 

@@ -170,21 +170,22 @@ size_t layout(expdg_mesh *m, const expdg_mesh_desc *d, size_t stride, int eb, ch
         off += bytes;
     };
     const size_t vb = stride * eb;
-    take(m->V, (size_t)(d->m_max + 1) * vb);
+    // m_max + 2 vectors: the step that finishes dimension m_max also writes the next one
+    take(m->V, (size_t)(d->m_max + 2) * vb);
     for (auto &v : m->vec) take(v, vb);
     if (d->precision == EXPDG_FP32_BULK)
         for (auto &v : m->bq) take(v, vb);
     take(m->q2, stride * 8);
     const size_t nlin = lin_elems(d->equation, d->p, d->nx * d->ny);
     if (nlin) take(m->lin, nlin * eb);
-    take(m->kd.H, (size_t)(kMaxM + 1) * kMaxM * 8);
+    take(m->kd.H, (size_t)(kMaxM + 1) * kLDH * 8);
     take(m->kd.S, (size_t)(kMaxM + 1) * 8);
     take(m->kd.coefA, (size_t)(kMaxM + 1) * 8);
-    take(m->kd.coefB, (size_t)(kMaxM + 1) * 8);
-    // block partials: row-partitioned passes (<= kRedBlocks) and the first
-    // pass fused into the linear operator (one partial per operator block)
+    take(m->kd.coefB, (size_t)(kMaxM + 3) * 8);
+    // block partials: row-partitioned passes (<= kRedBlocks) and the dot pass
+    // fused into the linear operator (one partial per operator block)
     const size_t npart = std::max<size_t>(kRedBlocks, dg_blocks(d->equation, d->p, d->nx * d->ny));
-    take(m->kd.part, npart * (kMaxM + 1) * 8);
+    take(m->kd.part, npart * kPartRows * 8);
     take(m->kd.res, 64 * 8);
     take(m->kd.flags, 16);
     take(m->slots, (size_t)kCheckSlots * kSlotSize * 8);
@@ -515,54 +516,42 @@ struct DirectExec {
         return EXPDG_OK;
     }
 
-    int iterate_now(expdg_mesh *m, const OpArgs<T> &a, int j, int naug_nz, const CheckReq *cr,
+    // Arnoldi step k: the operator on x = u_{k-1} (and, in 2D, the dot pass
+    // in its epilogue), the dot pass (1D), the finish, the update sweep.
+    int iterate_now(expdg_mesh *m, const OpArgs<T> &a, int k, int naug_nz, const CheckReq *cr,
                     Check *c) {
         const size_t n = m->n, L = n + (size_t)a.naug, stride = m->stride;
         const RowPartition rp = row_partition(L);
         const KrylovDev &kd = m->kd;
-        const T *V = (const T *)m->V;
-        T *w = a.out;
-        const int col = j - 1;
+        T *V = (T *)m->V;
+        T *x = V + (size_t)(k - 1) * stride, *w = a.out;
+        const int nv = k - 1;
         const double eb = (double)sizeof(T);
-        // linear operator, with the first Gram-Schmidt pass (V^T w block
-        // partials) when a.nv > 0, else a separate dot pass
-        const bool fused = a.nv > 0;
+        const bool fused = a.dots != 0;
         TRY(prof_begin(m, EXPDG_K_LINEAR));
         HIPTRY(launch_dg_op(m->d.equation, m->d.p, true, a, s));
         TRY(prof_end(m, EXPDG_K_LINEAR,
-                     op_bytes(m, true) + (double)(naug_nz + (fused ? j : 0)) * n * eb));
+                     op_bytes(m, true) + (double)(naug_nz + (fused ? nv : 0)) * n * eb));
         if (!fused) {
             TRY(prof_begin(m, EXPDG_K_GS_DOTS));
-            HIPTRY(launch_gs_dots<T>(V, stride, j, w, L, rp, kd.part, kd.S, kd.H, col, 0, kd.coefA,
-                                     s));
-            TRY(prof_end(m, EXPDG_K_GS_DOTS, (double)(j + 1) * L * eb));
+            HIPTRY(launch_gs_dots2<T>(V, stride, nv, x, w, L, rp, kd.part, s));
+            TRY(prof_end(m, EXPDG_K_GS_DOTS, (double)(nv + 2) * L * eb));
         }
-        const RowPartition rp1 = fused ? RowPartition{0, a.dnb} : rp;
+        const int nrb = fused ? a.dnb : rp.nrb;
         TRY(prof_begin(m, EXPDG_K_GS_FINISH));
-        HIPTRY(launch_gs_finish_dots(kd.part, j, rp1, kd.S, kd.H, col, 0, kd.coefA, s));
-        TRY(prof_end(m, EXPDG_K_GS_FINISH, 8.0 * rp1.nrb * j));
-        const double fin_bytes = 8.0 * rp.nrb * j;
-        // second pass with ||w||^2 (j > 32: a plain update then a dot pass,
-        // 2j + 4 vectors of traffic)
-        TRY(prof_begin(m, EXPDG_K_GS_UPDATE_DOTS));
-        HIPTRY(launch_gs_update_dots<T>(V, stride, j, kd.coefA, w, L, rp, kd.part, kd.S, kd.H, col,
-                                        kd.coefB, s));
-        TRY(prof_end(m, EXPDG_K_GS_UPDATE_DOTS, (double)(j <= 32 ? j + 2 : 2 * j + 4) * L * eb));
-        // h2, the norm of the orthogonalised vector (Pythagoras), S[j], breakdown test
-        TRY(prof_begin(m, EXPDG_K_GS_FINISH));
-        HIPTRY(launch_gs_finish_pass2(kd.part, j, rp, kd.S, kd.H, col, kd.coefB, kd.flags, s));
-        TRY(prof_end(m, EXPDG_K_GS_FINISH, fin_bytes + 8.0 * rp.nrb));
-        // w -= V h2
-        TRY(prof_begin(m, EXPDG_K_GS_UPDATE_NORM));
-        HIPTRY(launch_gs_update<T>(V, stride, j, kd.coefB, w, L, rp, s));
-        TRY(prof_end(m, EXPDG_K_GS_UPDATE_NORM, (double)(j + 2) * L * eb));
+        HIPTRY(launch_dcgs_finish(kd.part, nrb, k, kd.S, kd.H, kd.coefA, kd.coefB, kd.flags, s));
+        TRY(prof_end(m, EXPDG_K_GS_FINISH, 8.0 * nrb * (2 * nv + 2)));
+        // the check needs H and S only: it starts while the update sweep runs
         if (cr) TRY(enqueue_check(m, *cr, c));
+        TRY(prof_begin(m, EXPDG_K_GS_UPDATE));
+        HIPTRY(launch_dcgs_update<T>(V, stride, nv, kd.coefA, kd.coefB, x, w, L, rp, s));
+        TRY(prof_end(m, EXPDG_K_GS_UPDATE, (double)(nv + (nv > 0 ? 4 : 3)) * L * eb));
         return EXPDG_OK;
     }
 
-    Ready iterate(expdg_mesh *m, const OpArgs<T> &a, int j, int naug_nz, const CheckReq *cr,
+    Ready iterate(expdg_mesh *m, const OpArgs<T> &a, int k, int naug_nz, const CheckReq *cr,
                   Check *c) {
-        return Ready{iterate_now(m, a, j, naug_nz, cr, c)};
+        return Ready{iterate_now(m, a, k, naug_nz, cr, c)};
     }
     Ready check(expdg_mesh *m, const CheckReq &r, Check *c) { return Ready{enqueue_check(m, r, c)}; }
     Ready wait_check(expdg_mesh *m, const Check &c) { return Ready{sync_event(m->ev[c.slot])}; }

@@ -18,9 +18,10 @@
 //
 // An executor X provides
 //   hipStream_t stream();
-//   awaitable<int> iterate(m, a, j, naug_nz, const CheckReq *chk, Check *c):
-//       the Arnoldi step j (linear operator on u_{j-1}, two Gram-Schmidt
-//       passes, norm) and, if chk, the check of dimension j behind it;
+//   awaitable<int> iterate(m, a, k, naug_nz, const CheckReq *chk, Check *c):
+//       the Arnoldi step k (linear operator on u_{k-1}, dot pass, finish,
+//       update sweep; it finishes dimension k - 1) and, if chk, the check of
+//       dimension k - 1 behind it;
 //   awaitable<int> check(m, req, Check *c): a check on the current basis;
 //   awaitable<int> wait_check(m, c): the check's header is in the pinned mirror;
 //   int after_check(m, c): the stream waits for the check's coefficients;
@@ -219,13 +220,15 @@ Task<int> phi_co(X &x, expdg_mesh *m, const T *qref, double tau, int p, const T 
     a.q = qref;
     a.lin = (const T *)m->lin;
     a.eta = eta;
-    // the first Gram-Schmidt pass runs inside the 2D linear operator (a
+    // the dot pass of each Arnoldi step runs inside the 2D linear operator (a
     // Burgers tile has too little work to carry it: separate pass there)
     const bool fuse_dots = m->d.equation == EXPDG_EULER2D;
     a.basis = V;
     a.bstride = stride;
     a.dpart = kd.part;
     a.dnb = dg_blocks(m->d.equation, m->d.p, m->K);
+    a.dots = fuse_dots ? 1 : 0;
+    a.vscale = nullptr;  // the operator acts on the stored, unscaled vector
     a.naug = p;
     int naug_nz = 0;
     for (int k = 1; k <= p; ++k) {
@@ -247,34 +250,35 @@ Task<int> phi_co(X &x, expdg_mesh *m, const T *qref, double tau, int p, const T 
             R.sub_last = o->forced[*fpos].last != 0;
         }
         // beta = ||z||, S[0] = 1/beta, flags cleared
-        CO_TRY(prof_begin(m, EXPDG_K_GS_UPDATE_NORM));
-        CO_HIPTRY(launch_gs_update_norm<T>(V, stride, 0, nullptr, V, L, rp, kd.part, kd.H, kd.S,
-                                           -1, kd.flags, kd.res, s));
-        CO_TRY(prof_end(m, EXPDG_K_GS_UPDATE_NORM, (double)L * eb));
+        CO_TRY(prof_begin(m, EXPDG_K_GS_NORM));
+        CO_HIPTRY(launch_gs_norm<T>(V, L, rp, kd.part, s));
+        CO_TRY(prof_end(m, EXPDG_K_GS_NORM, (double)L * eb));
         CO_TRY(prof_begin(m, EXPDG_K_GS_FINISH));
-        CO_HIPTRY(launch_gs_finish_norm(kd.part, rp, kd.H, kd.S, -1, kd.flags, kd.res, s));
+        CO_HIPTRY(launch_gs_finish_norm(kd.part, rp, kd.H, kd.S, kd.flags, kd.res, s));
         CO_TRY(prof_end(m, EXPDG_K_GS_FINISH, 8.0 * rp.nrb));
 
         R.j_acc = 0;
         R.err = 0.0;
         Check pend[kCheckSlots];  // checks launched and not yet decided, oldest first
         int np = 0;
-        for (int j = 1; j <= m_target; ++j) {
-            T *vin = V + (size_t)(j - 1) * stride;
-            T *w = V + (size_t)j * stride;
-            // w = S[j-1] * Aug(u_{j-1})
+        // Arnoldi step k finishes dimension D = k - 1 (its basis vectors and
+        // Hessenberg columns), so dimension m_target needs step m_target + 1.
+        for (int k = 1; k <= m_target + 1; ++k) {
+            const int D = k - 1;
+            T *vin = V + (size_t)(k - 1) * stride;
+            T *w = V + (size_t)k * stride;
             a.v = vin;
             a.out = w;
             a.vtail = vin + n;
             a.otail = w + n;
-            a.vscale = kd.S + (j - 1);
-            a.nv = fuse_dots ? j : 0;
-            const bool is_check =
-                !forced && (j == o->m_max || (j >= o->m_min && (j - o->m_min) % o->check_every == 0));
+            a.nv = k - 1;
+            const bool is_check = !forced && D >= 1 &&
+                                  (D == o->m_max ||
+                                   (D >= o->m_min && (D - o->m_min) % o->check_every == 0));
             CheckReq cr{};
-            if (is_check) cr = R.req(j, R.dt_sub);
+            if (is_check) cr = R.req(D, R.dt_sub);
             Check cur;
-            CO_TRY(co_await x.iterate(m, a, j, naug_nz, is_check ? &cr : nullptr, &cur));
+            CO_TRY(co_await x.iterate(m, a, k, naug_nz, is_check ? &cr : nullptr, &cur));
             if (st) {
                 st->krylov_iters += 1;
                 st->jvps += 1;
@@ -284,9 +288,9 @@ Task<int> phi_co(X &x, expdg_mesh *m, const T *qref, double tau, int p, const T 
             // the last step): the device works on the newer steps meanwhile
             if (is_check) pend[np++] = cur;
             bool done = false;
-            while (np > 0 && (j == m_target || pend[0].j <= j - X::kLookahead)) {
+            while (np > 0 && (D == m_target || pend[0].j <= D - X::kLookahead)) {
                 const Check c = pend[0];
-                for (int k = 1; k < np; ++k) pend[k - 1] = pend[k];
+                for (int q = 1; q < np; ++q) pend[q - 1] = pend[q];
                 --np;
                 CO_AWAIT_TASK(R.decide(c, &done));
                 if (done) break;

@@ -198,50 +198,89 @@ __global__ __launch_bounds__(256) void euler_lin_prepare(const T *q, T *lin, int
     }
 }
 
-// First Gram-Schmidt pass fused into the linear operator: the block's partial
-// sums of V_i^T w over its own outputs wv (NV values per thread, one per
-// variable plane, node offset idx), i < a.nv, in chunks of 16 vectors with a
-// transpose reduction; the first tile adds the augmented entries.  Every
-// thread of the block takes part (inactive ones contribute zero).
+// Dot pass of an Arnoldi step from the tile just produced: over the tile's
+// nodes, u_i^T w and u_i^T x for i < nv (x = the input, w = the output, both as
+// stored), then x^T x and x^T w; tile 0 adds the augmented entries.  Row r of
+// the partials goes to dpart[r * dnb + tile], rows as in launch_gs_dots2.
 template <typename T, int NV>
-__device__ __forceinline__ void op_dots(const OpArgs<T> &a, bool active, unsigned idx,
-                                        size_t plane, const T *wv, int tile, bool first) {
-    __shared__ double sw[4][16];
+__device__ __forceinline__ void op_dots2(const OpArgs<T> &a, bool active, unsigned idx,
+                                         size_t plane, const T *xv, const T *wv, int tile,
+                                         bool first) {
+    __shared__ double sw[4][32];
+    __shared__ double s2[4][2];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const size_t ntot = NV * plane;
-    for (int i0 = 0; i0 < a.nv; i0 += 16) {
-        double acc[16];
+    const int nv = a.nv;
+    const bool tail = first && tid == 0 && a.naug > 0;
+    const T sc = a.vscale ? (T)(*a.vscale) : T(1);
+    for (int i0 = 0; i0 < nv; i0 += 16) {
+        double acc[32];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) acc[k] = 0.0;
+        for (int k = 0; k < 32; ++k) acc[k] = 0.0;
         if (active) {
 #pragma unroll
             for (int k = 0; k < 16; ++k)
-                if (i0 + k < a.nv) {
+                if (i0 + k < nv) {
                     const T *Vi = a.basis + (size_t)(i0 + k) * a.bstride;
-                    double s = 0.0;
+                    double sw_ = 0.0, sx_ = 0.0;
 #pragma unroll
-                    for (int c = 0; c < NV; ++c) s += (double)ld32(Vi + c * plane, idx) * (double)wv[c];
-                    acc[k] = s;
+                    for (int c = 0; c < NV; ++c) {
+                        const double u = (double)ld32(Vi + c * plane, idx);
+                        sw_ += u * (double)wv[c];
+                        sx_ += u * (double)xv[c];
+                    }
+                    acc[k] = sw_;
+                    acc[16 + k] = sx_;
                 }
         }
-        if (first && tid == 0 && a.naug > 0) {
-            const T sc = a.vscale ? (T)(*a.vscale) : T(1);
+        if (tail) {
             for (int t = 0; t < a.naug; ++t) {
                 const T wt = (t + 1 < a.naug) ? sc * a.vtail[t + 1] : T(0);
+                const T xt = a.vtail[t];
 #pragma unroll
                 for (int k = 0; k < 16; ++k)
-                    if (i0 + k < a.nv)
-                        acc[k] += (double)a.basis[(size_t)(i0 + k) * a.bstride + ntot + t] * (double)wt;
+                    if (i0 + k < nv) {
+                        const double u = (double)a.basis[(size_t)(i0 + k) * a.bstride + ntot + t];
+                        acc[k] += u * (double)wt;
+                        acc[16 + k] += u * (double)xt;
+                    }
             }
         }
-        const double v = transpose_reduce16(acc);
-        if ((lane & 3) == 0) sw[wave][lane >> 2] = v;
+        const double v = transpose_reduce32(acc);
+        if ((lane & 1) == 0) sw[wave][lane >> 1] = v;
         __syncthreads();
-        if (tid < 16 && i0 + tid < a.nv)
-            a.dpart[(size_t)(i0 + tid) * a.dnb + tile] =
-                (sw[0][tid] + sw[1][tid]) + (sw[2][tid] + sw[3][tid]);
+        if (tid < 32 && i0 + (tid & 15) < nv) {
+            const int row = (tid < 16) ? i0 + tid : nv + i0 + (tid - 16);
+            a.dpart[(size_t)row * a.dnb + tile] = (sw[0][tid] + sw[1][tid]) + (sw[2][tid] + sw[3][tid]);
+        }
         __syncthreads();
     }
+    double xx = 0.0, xw = 0.0;
+    if (active) {
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+            xx += (double)xv[c] * (double)xv[c];
+            xw += (double)xv[c] * (double)wv[c];
+        }
+    }
+    if (tail) {
+        for (int t = 0; t < a.naug; ++t) {
+            const T wt = (t + 1 < a.naug) ? sc * a.vtail[t + 1] : T(0);
+            const T xt = a.vtail[t];
+            xx += (double)xt * (double)xt;
+            xw += (double)xt * (double)wt;
+        }
+    }
+    xx = wave_sum(xx);
+    xw = wave_sum(xw);
+    if (lane == 0) {
+        s2[wave][0] = xx;
+        s2[wave][1] = xw;
+    }
+    __syncthreads();
+    if (tid < 2)
+        a.dpart[(size_t)(2 * nv + tid) * a.dnb + tile] =
+            (s2[0][tid] + s2[1][tid]) + (s2[2][tid] + s2[3][tid]);
 }
 
 // ---- Euler 2D operator ------------------------------------------------------
@@ -399,7 +438,7 @@ __device__ __forceinline__ void euler_op_body(const OpArgs<T> &a, int tile, bool
 #pragma unroll
         for (int c = 0; c < 4; ++c) wv[c] = T(0);
     }
-    if (JVP && a.nv > 0) op_dots<T, 4>(a, active, idx, plane, wv, tile, first);
+    if (JVP && a.dots) op_dots2<T, 4>(a, active, idx, plane, u, wv, tile, first);
 }
 
 // ---- Burgers 1D operator ----------------------------------------------------
@@ -457,7 +496,8 @@ __device__ __forceinline__ void burgers_op_body(const OpArgs<T> &a, int tile, bo
         wv = sc * res;
         a.out[idx] = wv;
     }
-    if (JVP && a.nv > 0) op_dots<T, 1>(a, active, (unsigned)idx, (size_t)a.K * N1, &wv, tile, first);
+    if (JVP && a.dots)
+        op_dots2<T, 1>(a, active, (unsigned)idx, (size_t)a.K * N1, &uv, &wv, tile, first);
 }
 
 template <int P, typename T, bool JVP>

@@ -30,13 +30,15 @@ struct OpArgs {
     T *otail;          // the p augmented entries of the output
     const double *vscale;  // device scalar multiplying the whole result (nullptr = 1)
     const T *lin;      // frozen fields of q~ for the 2D linear operator (launch_lin_prepare)
-    // First Gram-Schmidt pass fused into the linear operator (nv > 0): block
-    // partials dpart[i * dnb + tile] of V_i^T out over the tile's nodes (and,
-    // in tile 0, the augmented entries), i < nv, V_i = basis + i * bstride.
+    // Dot pass of an Arnoldi step fused into the linear operator (dots != 0):
+    // block partials dpart[r * dnb + tile] over the tile's nodes (and, in
+    // tile 0, the augmented entries) of the rows of launch_gs_dots2 with
+    // x = v, w = out and u_i = basis + i * bstride, i < nv.
     const T *basis;
     size_t bstride;
     int nv;
-    int dnb;           // blocks of the launch (partials per vector)
+    int dots;
+    int dnb;           // blocks of the launch (partials per row)
     double *dpart;
     double eta;        // scaling of the augmented block
     int naug;          // p
@@ -123,14 +125,27 @@ template <typename T>
 hipError_t launch_step_update(double *q, double *q_prev, const T *w, size_t n, hipStream_t s);
 
 // ---- Krylov kernels (krylov_kernels.hip) ----
+// Arnoldi by classical Gram-Schmidt applied twice, with the second pass of
+// each vector delayed into the next step (one dot pass and one update sweep
+// per step).  Step k applies the operator to x = u_{k-1}, a vector that has
+// had its first pass only, giving w = A x; one pass of block partials gives
+// u_i^T w and u_i^T x (i < k-1), x^T x and x^T w; the finish completes x
+// (second pass, norm by Pythagoras: column k-2 of H and H[k-1][k-2] become
+// final), rescales w to A v_{k-1} through the Arnoldi relation, and takes
+// the first pass of w (column k-1 of H); one sweep then stores the finished
+// x and the once-orthogonalised new vector.
+constexpr int kLDH = kMaxM + 1;          // row stride of H
+constexpr int kPartRows = 2 * kMaxM + 2;  // partial rows of one step: V^T w, V^T x, x^T x, x^T w
+constexpr int kScalW = kMaxM + 1;        // coefB[kScalW] = 1 / beta (scale of w)
+constexpr int kScalX = kMaxM + 2;        // coefB[kScalX] = e_{k-1} / beta (multiple of x)
 struct KrylovDev {
-    double *H;       // (kMaxM+1) x kMaxM Hessenberg, row-major, ld = kMaxM
+    double *H;       // (kMaxM+1) x kLDH Hessenberg, row-major
     double *S;       // kMaxM+1 basis scales (v_i = S[i] * u_i)
-    double *coefA;   // kMaxM+1 first-pass Gram-Schmidt coefficients h1_i S[i]
-    double *coefB;   // kMaxM+1 second-pass coefficients h2_i S[i]
-    double *part;    // kRedBlocks x (kMaxM+1) block partial sums
+    double *coefA;   // kMaxM+1: x -= sum_i coefA[i] u_i
+    double *coefB;   // kMaxM+3: w <- coefB[kScalW] w - coefB[kScalX] x - sum_i coefB[i] u_i
+    double *part;    // partials: kPartRows rows of max(kRedBlocks, operator blocks)
     double *res;     // res[0] = beta
-    int *flags;      // [0] first breakdown iteration (0 = none), [1] non-finite
+    int *flags;      // [0] first breakdown dimension (0 = none), [1] first non-finite one
 };
 
 // Fixed row partition of a length-L vector: nrb blocks of rpb rows (rpb a
@@ -141,48 +156,39 @@ struct RowPartition {
 };
 RowPartition row_partition(size_t L);
 
-// Block partials of V_i^T w (i < nv) into part (the finish is a separate
-// launch: launch_gs_finish_dots).
+// Block partials of step k (nv = k - 1 finished vectors u_0..u_{nv-1}):
+// row i < nv: u_i^T w; row nv + i: u_i^T x; row 2 nv: x^T x; row 2 nv + 1:
+// x^T w (the 1D path; the 2D linear operator writes the same rows itself).
 template <typename T>
-hipError_t launch_gs_dots(const T *V, size_t stride, int nv, const T *w, size_t L,
-                          const RowPartition &rp, double *part, const double *S, double *H,
-                          int col, int accumulate, double *coef_out, hipStream_t s);
-// w -= sum_i coef_in[i] V_i, then block partials of V_i^T w (rows i < nv) and
-// of ||w||^2 (row nv; w must be V_nv).  nv <= 32: one fused pass; else a plain
-// update then a dot pass over the nv + 1 vectors V_0..V_nv.
+hipError_t launch_gs_dots2(const T *V, size_t stride, int nv, const T *x, const T *w, size_t L,
+                           const RowPartition &rp, double *part, hipStream_t s);
+// Fixed-order finish of step k from nrb partials per row (one block): with
+// a_i = S[i] (u_i^T x), b_i = S[i] (u_i^T w): beta = sqrt(x^T x - |a|^2)
+// (k = 1: beta = 1 / S[0], x = u_0 is already finished); H[i][k-2] += a_i,
+// H[k-1][k-2] = beta, breakdown test against ||H||_F (flags[0] = k-1 the
+// first time, S[k-1] = 0) else S[k-1] = 1/beta; flags[1] = k-1 the first time
+// beta or ||H||_F is non-finite.  t = H_{0:k,0:k-1} a; first pass of
+// A v_{k-1} = (w - V_k t) / beta: g_i = (b_i - t_i) / beta (i < k-1),
+// g_{k-1} = ((x^T w - a.b) / beta - t_{k-1}) / beta, H[i][k-1] = g_i; with
+// e = t / beta + g: coefA[i] = S[i] a_i, coefB[i] = S[i] (e_i - a_i e_{k-1} /
+// beta), coefB[kScalW] = 1 / beta, coefB[kScalX] = e_{k-1} / beta.
+hipError_t launch_dcgs_finish(const double *part, int nrb, int k, double *S, double *H,
+                              double *coefA, double *coefB, int *flags, hipStream_t s);
+// One sweep of step k: x -= sum_{i<nv} coefA[i] u_i (skipped for nv = 0) and
+// w <- coefB[kScalW] w - coefB[kScalX] x_old - sum_{i<nv} coefB[i] u_i.
 template <typename T>
-hipError_t launch_gs_update_dots(const T *V, size_t stride, int nv, const double *coef_in, T *w,
-                                 size_t L, const RowPartition &rp, double *part, const double *S,
-                                 double *H, int col, double *coef_out, hipStream_t s);
-// w -= sum_i coef[i] V_i (if coef), then block partials of ||w||^2.
+hipError_t launch_dcgs_update(const T *V, size_t stride, int nv, const double *coefA,
+                              const double *coefB, T *x, T *w, size_t L, const RowPartition &rp,
+                              hipStream_t s);
+// Start vector of a substep: block partials of ||z||^2 (z = V_0) ...
 template <typename T>
-hipError_t launch_gs_update_norm(const T *V, size_t stride, int nv, const double *coef, T *w,
-                                 size_t L, const RowPartition &rp, double *part, double *H,
-                                 double *S, int col, int *flags, double *res, hipStream_t s);
-// Fixed-order finish of a dot pass: h_i = S[i] sum_b part[i][b]; H[i][col] set
-// (accumulate = 0) or incremented; coef_out[i] = h_i S[i].
-hipError_t launch_gs_finish_dots(const double *part, int nv, const RowPartition &rp,
-                                 const double *S, double *H, int col, int accumulate,
-                                 double *coef_out, hipStream_t s);
-// w -= sum_i coef[i] V_i, no reduction.
-template <typename T>
-hipError_t launch_gs_update(const T *V, size_t stride, int nv, const double *coef, T *w, size_t L,
-                            const RowPartition &rp, hipStream_t s);
-// Fixed-order finish of the second pass with the norm (one block): h2_i from
-// rows i < nv, H[i][col] += h2_i, coef_out[i] = h2_i S[i]; hn^2 = row nv -
-// sum h2_i^2 (Pythagoras: the norm of w - V h2 for an orthonormal basis), then
-// H[col+1][col], S[col+1] and the flags as in launch_gs_finish_norm.
-hipError_t launch_gs_finish_pass2(const double *part, int nv, const RowPartition &rp, double *S,
-                                  double *H, int col, double *coef_out, int *flags,
-                                  hipStream_t s);
-// Fixed-order finish of a norm pass: hn = sqrt(sum_b part[b]).  col >= 0:
-// H[col+1][col] = hn, breakdown test against ||H||_F (flags[0] = col+1 the
-// first time, S[col+1] = 0), else S[col+1] = 1/hn; flags[1] = col+1 the first
-// time a norm is non-finite.  col < 0 (start vector of a substep): res[0] =
-// beta = hn, S[0] = 1/beta, flags[0] = 0, flags[1] = 1 if beta is
-// non-finite, else 0, and the Hessenberg matrix is cleared.
+hipError_t launch_gs_norm(const T *z, size_t L, const RowPartition &rp, double *part,
+                          hipStream_t s);
+// ... and their fixed-order finish: res[0] = beta = ||z||, S[0] = 1/beta,
+// flags[0] = 0, flags[1] = 1 if beta is non-finite, else 0, and the Hessenberg
+// matrix is cleared.
 hipError_t launch_gs_finish_norm(const double *part, const RowPartition &rp, double *H, double *S,
-                                 int col, int *flags, double *res, hipStream_t s);
+                                 int *flags, double *res, hipStream_t s);
 // Norms of up to 4 vectors of length n (block partials, then finish):
 // out[k] = ||x_k||_2 (device doubles).
 template <typename T>
@@ -205,23 +211,21 @@ hipError_t launch_hess_expm(const ExpmItem &c, hipStream_t s);
 // n checks (device array), one workgroup each.
 hipError_t launch_hess_expm_group(const ExpmItem *items, int n, hipStream_t s);
 
-// One Arnoldi step (FP64) of one solve inside a grouped launch: the CGS2
-// passes and the norm of w = u_nv against the basis u_0..u_{nv-1}.
+// One Arnoldi step k (FP64) of one solve inside a grouped launch.
 struct GsItem {
-    const double *V;
-    double *w;
+    const double *V;     // u_0, u_1, ...: x = u_{k-1}, w = u_k
+    double *x, *w;
     size_t stride, L, rpb;
-    int nrb, nv, col;    // col = nv - 1
-    int nrb1;            // partials per vector of a first pass fused into the linear
-                         // operator (its blocks), or 0: a separate dot pass
-    double *part, *S, *H, *coefA, *coefB, *res;
+    int nrb, k;
+    int nrb1;            // partials per row written by the linear operator (its blocks),
+                         // or 0: a separate dot pass
+    double *part, *S, *H, *coefA, *coefB;
     int *flags;
 };
-// Block ranges of a grouped Arnoldi step: first dots (items whose linear
-// operator does not carry them), first finish, fused update+dots+norm
-// (nv <= 32), plain update (nv > 32), dots with w itself after it (nv > 32),
-// final update.  (The second finish runs one block per item.)
-constexpr int kGroupLaunches = 6;
+// Block ranges of a grouped Arnoldi step: the dot pass (items whose linear
+// operator does not carry it) and the update sweep.  (The finish runs one
+// block per item.)
+constexpr int kGroupLaunches = 2;
 // Host: block ranges bstart[k*(n+1) + it] of launch k and the totals.
 void arnoldi_group_layout(const GsItem *items, int n, int *bstart, int *totals);
 // Device copies of items and bstart; totals from arnoldi_group_layout.

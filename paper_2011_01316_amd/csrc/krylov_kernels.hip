@@ -1,5 +1,7 @@
 // Arnoldi / Krylov kernels for gfx950 (Section 2.3: Krylov projection of the
-// augmented matrix; classical Gram-Schmidt applied twice).
+// augmented matrix).  The orthogonalisation is classical Gram-Schmidt applied
+// twice, with the second pass of each vector delayed into the next Arnoldi
+// step so that one dot pass and one update sweep serve both passes.
 //
 // Basis storage: V holds unnormalised vectors u_i (bulk type, float or
 // double) with FP64 scales S[i] so that v_i = S[i] u_i; no separate
@@ -12,19 +14,19 @@
 // kernel re-derive the sums makes each block wait on partials that other XCDs
 // wrote.)
 //
-// Per Arnoldi step j (j basis vectors, w = the new vector):
-//   first pass      h1 = V^T w: block partials from the 2D linear operator's
-//                   epilogue, or gs_dots (2D grid: row blocks x 16-vector
-//                   chunks) after the 1D operator
-//   finish_dots     h1 (fixed-order sums), H column, coefficients
-//   gs_update_dots  w -= V h1 ; h2 = V^T w and ||w||^2 in the same sweep
-//                   (32 accumulators in registers, j <= 32; an update and a
-//                   dot pass for j > 32)
-//   finish_pass2    h2, H += h2, ||w - V h2||^2 = ||w||^2 - ||h2||^2
-//                   (Pythagoras), S[j], breakdown test
-//   gs_update       w -= V h2
-// Block sums use a transpose reduction: 16 (or 32) accumulators of a wave are
-// summed with 17 (or 32) cross-lane exchanges instead of 6 per accumulator.
+// Arnoldi step k (the operator was applied to x = u_{k-1}, which has had its
+// first pass only; w = A x):
+//   dot pass     u_i^T w, u_i^T x (i < k-1), x^T x, x^T w: block partials
+//                from the 2D linear operator's epilogue, or gs_dots2 (2D grid:
+//                row blocks x 16-vector chunks) after the 1D operator
+//   dcgs_finish  second pass of x (a = V^T x, beta = sqrt(x^T x - |a|^2) by
+//                Pythagoras): column k-2 of H and H[k-1][k-2] final; the
+//                Arnoldi relation A V = V H turns w = A x into
+//                A v_{k-1} = (w - V_k t) / beta, t = H a, whose first pass g
+//                (column k-1 of H) follows from the same dots; breakdown test
+//   dcgs_update  x -= V a and w <- (w - V_k t) / beta - V_k g in one sweep
+// Block sums use a transpose reduction: 32 accumulators of a wave are summed
+// with 32 cross-lane exchanges instead of 6 per accumulator.
 //
 // The small (j+1) x (j+1) exponential of the projected Hessenberg matrix runs
 // in one 256-thread workgroup with four FP64 matrices in LDS (gfx950 gives a
@@ -39,7 +41,7 @@
 namespace expdg {
 namespace {
 
-constexpr int LDH = kMaxM;  // leading dimension of H
+constexpr int LDH = kLDH;   // leading dimension of H
 constexpr int CH = 16;      // basis vectors per chunk of the dot kernel
 
 // 16-byte vector access: 2 doubles or 4 floats per lane per load.
@@ -79,380 +81,13 @@ __device__ __forceinline__ void st16(T *p, double *x) {
     *reinterpret_cast<VT *>(p) = v;
 }
 
-// The previous pass whose coefficients a kernel applies.
-struct PrevPass {
-    const double *coef;  // nullptr: no previous pass (no update)
-};
-
-struct DotFinish {
-    const double *S;
-    double *H;
-    int col;
-    int accumulate;
-    double *coef_out;
-};
-
-// h_i = S[i] sum_b part[i][b]; H[i][col] (+)= h_i; coef_out[i] = h_i S[i].
-// One wave per output (four per block), partials summed in a fixed order.
-__device__ __forceinline__ void finish_dots_body(const double *part, int nv, int nrb,
-                                                 const DotFinish &f, int blk) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int i = blk * 4 + wave;
-    if (i >= nv) return;
-    double a = 0.0;
-    for (int b = lane; b < nrb; b += 64) a += part[(size_t)i * nrb + b];
-    a = wave_sum(a);
-    if (lane == 0) {
-        const double h = f.S[i] * a;
-        double *hij = &f.H[(size_t)i * LDH + f.col];
-        *hij = f.accumulate ? *hij + h : h;
-        f.coef_out[i] = h * f.S[i];
-    }
-}
-
-__global__ __launch_bounds__(256) void finish_dots_kernel(const double *part, int nv, int nrb,
-                                                          DotFinish f) {
-    finish_dots_body(part, nv, nrb, f, blockIdx.x);
-}
-
-struct NormFinish {
-    double *H;
-    double *S;
-    int col;        // column of the new subdiagonal entry; -1: start vector
-    int *flags;     // [0] first breakdown iteration, [1] non-finite
-    double *res;    // res[0] = beta (start vector)
-};
-
-__device__ __forceinline__ void finish_norm_body(const double *part, int nrb, const NormFinish &f) {
+// ---- start vector of a substep ----------------------------------------------
+// Block partials of ||z||^2.
+template <typename T>
+__device__ __forceinline__ void gs_norm_body(const T *__restrict__ z, size_t L, size_t rpb,
+                                             double *__restrict__ part, int rb) {
     __shared__ double sw[4];
     const int tid = threadIdx.x;
-    double a = 0.0;
-    for (int b = tid; b < nrb; b += 256) a += part[b];
-    a = wave_sum(a);
-    if ((tid & 63) == 0) sw[tid >> 6] = a;
-    __syncthreads();
-    const double hn = sqrt((sw[0] + sw[1]) + (sw[2] + sw[3]));
-    __syncthreads();
-    if (f.col < 0) {
-        if (tid == 0) {
-            f.res[0] = hn;
-            f.S[0] = (hn > 0.0) ? 1.0 / hn : 0.0;
-            f.flags[0] = 0;
-            f.flags[1] = isfinite(hn) ? 0 : 1;
-        }
-        // a new substep: the Hessenberg matrix starts from zero
-        for (int e = tid; e < (kMaxM + 1) * LDH; e += 256) f.H[e] = 0.0;
-        return;
-    }
-    // ||H_{0:col+2, 0:col+1}||_F including the new subdiagonal entry
-    const int col = f.col, rows = col + 2, cols = col + 1;
-    double acc = 0.0;
-    for (int e = tid; e < rows * cols; e += 256) {
-        const int r = e / cols, c = e % cols;
-        const double h = (r == col + 1) ? ((c == col) ? hn : 0.0) : f.H[(size_t)r * LDH + c];
-        acc += h * h;
-    }
-    acc = wave_sum(acc);
-    if ((tid & 63) == 0) sw[tid >> 6] = acc;
-    __syncthreads();
-    if (tid == 0) {
-        const double hf = sqrt((sw[0] + sw[1]) + (sw[2] + sw[3]));
-        if ((!isfinite(hn) || !isfinite(hf)) && f.flags[1] == 0) f.flags[1] = col + 1;
-        const bool brk = hn <= 1e-12 * hf;
-        if (brk) {
-            f.H[(size_t)(col + 1) * LDH + col] = 0.0;
-            f.S[col + 1] = 0.0;
-            if (f.flags[0] == 0) f.flags[0] = col + 1;
-        } else {
-            f.H[(size_t)(col + 1) * LDH + col] = hn;
-            f.S[col + 1] = 1.0 / hn;
-        }
-    }
-}
-
-__global__ __launch_bounds__(256) void finish_norm_kernel(const double *part, int nrb,
-                                                          NormFinish f) {
-    finish_norm_body(part, nrb, f);
-}
-
-// Finish of the second Gram-Schmidt pass together with the norm (one block of
-// kFin2Threads threads).  d_i = sum_b part[i][b] in a fixed order for i <= nv,
-// where row nv holds ||w'||^2 of the stored vector w'; h2_i = S[i] d_i,
-// H[i][col] += h2_i, coef_out[i] = h2_i S[i].  The vector after the update,
-// w'' = w' - sum_i h2_i v_i, has ||w''||^2 = ||w'||^2 - sum_i h2_i^2 because the
-// v_i are orthonormal (Pythagoras), so no further reduction is needed; the
-// breakdown test and S[col+1] then follow as in finish_norm.
-constexpr int kFin2Threads = 1024;
-
-struct Pass2Finish {
-    double *S;
-    double *H;
-    int col;
-    double *coef_out;
-    int *flags;
-};
-
-__device__ __forceinline__ void finish_pass2_body(const double *part, int nv, int nrb,
-                                                  const Pass2Finish &f) {
-    int *flags = f.flags;
-    constexpr int NW = kFin2Threads / 64;
-    __shared__ double sv[kMaxM + 2];
-    __shared__ double sw[NW];
-    __shared__ double shh;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int i = wave; i <= nv; i += NW) {
-        double a = 0.0;
-        for (int b = lane; b < nrb; b += 64) a += part[(size_t)i * nrb + b];
-        a = wave_sum(a);
-        if (lane == 0) sv[i] = a;
-    }
-    __syncthreads();
-    const int col = f.col;
-    double h = 0.0;
-    if (tid < nv) {
-        h = f.S[tid] * sv[tid];
-        double *hij = &f.H[(size_t)tid * LDH + col];
-        *hij = *hij + h;
-        f.coef_out[tid] = h * f.S[tid];
-    }
-    // nv <= kMaxM = 64: every h2_i lives in wave 0
-    const double hh = wave_sum(h * h);
-    if (tid == 0) shh = hh;
-    __syncthreads();
-    const double hn2 = sv[nv] - shh;
-    const double hn = (hn2 < 0.0) ? 0.0 : sqrt(hn2);  // NaN stays NaN
-    // ||H_{0:col+2, 0:col+1}||_F including the new subdiagonal entry
-    const int rows = col + 2, cols = col + 1;
-    double acc = 0.0;
-    for (int e = tid; e < rows * cols; e += kFin2Threads) {
-        const int r = e / cols, c = e % cols;
-        const double hv = (r == col + 1) ? ((c == col) ? hn : 0.0) : f.H[(size_t)r * LDH + c];
-        acc += hv * hv;
-    }
-    acc = wave_sum(acc);
-    if (lane == 0) sw[wave] = acc;
-    __syncthreads();
-    if (tid == 0) {
-        double s = 0.0;
-        for (int k = 0; k < NW; ++k) s += sw[k];
-        const double hf = sqrt(s);
-        if ((!isfinite(hn) || !isfinite(hf)) && flags[1] == 0) flags[1] = col + 1;
-        const bool brk = hn <= 1e-12 * hf;
-        if (brk) {
-            f.H[(size_t)(col + 1) * LDH + col] = 0.0;
-            f.S[col + 1] = 0.0;
-            if (flags[0] == 0) flags[0] = col + 1;
-        } else {
-            f.H[(size_t)(col + 1) * LDH + col] = hn;
-            f.S[col + 1] = 1.0 / hn;
-        }
-    }
-}
-
-__global__ __launch_bounds__(kFin2Threads) void finish_pass2_kernel(const double *part, int nv,
-                                                                    int nrb, Pass2Finish f) {
-    finish_pass2_body(part, nv, nrb, f);
-}
-
-// part[i][rb] = sum over the block's rows of V_i[r] w[r], i in the block's
-// 16-vector chunk.
-template <typename T>
-__device__ __forceinline__ void gs_dots_body(const T *__restrict__ V, size_t stride, int nv,
-                                             const T *__restrict__ w, size_t L, size_t rpb,
-                                             int nrb, double *__restrict__ part, int rb,
-                                             int chunk) {
-    __shared__ double sw[4][CH];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int i0 = chunk * CH;
-    const int nloc = min(CH, nv - i0);
-    const size_t r0 = (size_t)rb * rpb;
-    const size_t r1 = (r0 + rpb < L) ? r0 + rpb : L;
-    double acc[CH];
-#pragma unroll
-    for (int i = 0; i < CH; ++i) acc[i] = 0.0;
-    const T *Vc = V + (size_t)i0 * stride;
-    constexpr int N = Vec16<T>::N;
-    // full 16-byte sweeps, then the ragged tail one row at a time
-    const size_t nsw = (r1 - r0) / (256 * N);
-    for (size_t k = 0; k < nsw; ++k) {
-        const size_t r = r0 + (k * 256 + tid) * N;
-        double x[N];
-        ld16(w + r, x);
-#pragma unroll
-        for (int i = 0; i < CH; ++i)
-            if (i < nloc) {
-                double vv[N];
-                ld16(Vc + (size_t)i * stride + r, vv);
-#pragma unroll
-                for (int e = 0; e < N; ++e) acc[i] += vv[e] * x[e];
-            }
-    }
-    for (size_t r = r0 + nsw * 256 * N + tid; r < r1; r += 256) {
-        const double x = (double)w[r];
-#pragma unroll
-        for (int i = 0; i < CH; ++i)
-            if (i < nloc) acc[i] += (double)Vc[(size_t)i * stride + r] * x;
-    }
-    const double v = transpose_reduce16(acc);
-    if ((lane & 3) == 0) sw[wave][lane >> 2] = v;
-    __syncthreads();
-    if (tid < nloc)
-        part[(size_t)(i0 + tid) * nrb + rb] = (sw[0][tid] + sw[1][tid]) + (sw[2][tid] + sw[3][tid]);
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void gs_dots_kernel(const T *__restrict__ V, size_t stride,
-                                                      int nv, const T *__restrict__ w, size_t L,
-                                                      size_t rpb, int nrb,
-                                                      double *__restrict__ part) {
-    gs_dots_body<T>(V, stride, nv, w, L, rpb, nrb, part, blockIdx.x, blockIdx.y);
-}
-
-// w -= sum_i c_i V_i with c from the previous pass, then
-// part[i][rb] = sum_r V_i[r] w[r] (nv <= 32) and part[nv][rb] = sum_r w[r]^2
-// (the stored, rounded w).
-template <typename T>
-__device__ __forceinline__ void gs_update_dots_body(const T *__restrict__ V, size_t stride, int nv,
-                                                    const double *coef, T *__restrict__ w,
-                                                    size_t L, size_t rpb, int nrb,
-                                                    double *__restrict__ part, int rb) {
-    __shared__ double scoef[32];
-    __shared__ double sw[4][32];
-    __shared__ double sn[4];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (tid < nv) scoef[tid] = coef[tid];
-    __syncthreads();
-    const size_t r0 = (size_t)rb * rpb;
-    const size_t r1 = (r0 + rpb < L) ? r0 + rpb : L;
-    double acc[32];
-    double nrm = 0.0;
-#pragma unroll
-    for (int i = 0; i < 32; ++i) acc[i] = 0.0;
-    constexpr int N = Vec16<T>::N;
-    const size_t nsw = (r1 - r0) / (256 * N);
-    for (size_t k = 0; k < nsw; ++k) {
-        const size_t r = r0 + (k * 256 + tid) * N;
-        double x[N];
-        ld16(w + r, x);
-        // the first KEEP basis rows (32 values per lane) stay in registers for
-        // the second product; the others are read again (the same thread just
-        // read them, so mostly from cache)
-        constexpr int KEEP = 32 / N;
-        double keep[KEEP][N];
-#pragma unroll
-        for (int i = 0; i < KEEP; ++i) {
-            if (i < nv) {
-                ld16(V + (size_t)i * stride + r, keep[i]);
-            } else {
-#pragma unroll
-                for (int e = 0; e < N; ++e) keep[i][e] = 0.0;
-            }
-#pragma unroll
-            for (int e = 0; e < N; ++e) x[e] -= scoef[i < nv ? i : 0] * keep[i][e];
-        }
-        for (int i = KEEP; i < nv; ++i) {
-            double vv[N];
-            ld16(V + (size_t)i * stride + r, vv);
-#pragma unroll
-            for (int e = 0; e < N; ++e) x[e] -= scoef[i] * vv[e];
-        }
-        st16(w + r, x);
-#pragma unroll
-        for (int e = 0; e < N; ++e) nrm += x[e] * x[e];
-#pragma unroll
-        for (int i = 0; i < KEEP; ++i)
-#pragma unroll
-            for (int e = 0; e < N; ++e) acc[i] += keep[i][e] * x[e];
-#pragma unroll
-        for (int i = KEEP; i < 32; ++i)
-            if (i < nv) {
-                double vv[N];
-                ld16(V + (size_t)i * stride + r, vv);
-#pragma unroll
-                for (int e = 0; e < N; ++e) acc[i] += vv[e] * x[e];
-            }
-    }
-    for (size_t r = r0 + nsw * 256 * N + tid; r < r1; r += 256) {
-        double x = (double)w[r];
-        for (int i = 0; i < nv; ++i) x -= scoef[i] * (double)V[(size_t)i * stride + r];
-        const T xs = (T)x;
-        w[r] = xs;
-        x = (double)xs;
-        nrm += x * x;
-#pragma unroll
-        for (int i = 0; i < 32; ++i)
-            if (i < nv) acc[i] += (double)V[(size_t)i * stride + r] * x;
-    }
-    const double v = transpose_reduce32(acc);
-    if ((lane & 1) == 0) sw[wave][lane >> 1] = v;
-    nrm = wave_sum(nrm);
-    if (lane == 0) sn[wave] = nrm;
-    __syncthreads();
-    if (tid < nv) part[(size_t)tid * nrb + rb] = (sw[0][tid] + sw[1][tid]) + (sw[2][tid] + sw[3][tid]);
-    if (tid == 0) part[(size_t)nv * nrb + rb] = (sn[0] + sn[1]) + (sn[2] + sn[3]);
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void gs_update_dots_kernel(
-    const T *__restrict__ V, size_t stride, int nv, PrevPass prev, T *__restrict__ w, size_t L,
-    size_t rpb, int nrb, double *__restrict__ part) {
-    gs_update_dots_body<T>(V, stride, nv, prev.coef, w, L, rpb, nrb, part, blockIdx.x);
-}
-
-// w -= sum_i c_i V_i with c from the previous pass (any nv <= kMaxM + 1).
-template <typename T>
-__device__ __forceinline__ void gs_update_body(const T *__restrict__ V, size_t stride, int nv,
-                                               const double *coef, T *__restrict__ w, size_t L,
-                                               size_t rpb, int rb) {
-    __shared__ double scoef[kMaxM + 1];
-    const int tid = threadIdx.x;
-    if (tid < nv) scoef[tid] = coef[tid];
-    __syncthreads();
-    const size_t r0 = (size_t)rb * rpb;
-    const size_t r1 = (r0 + rpb < L) ? r0 + rpb : L;
-    constexpr int N = Vec16<T>::N;
-    const size_t nsw = (r1 - r0) / (256 * N);
-    for (size_t k = 0; k < nsw; ++k) {
-        const size_t r = r0 + (k * 256 + tid) * N;
-        double x[N];
-        ld16(w + r, x);
-        for (int i = 0; i < nv; ++i) {
-            double vv[N];
-            ld16(V + (size_t)i * stride + r, vv);
-#pragma unroll
-            for (int e = 0; e < N; ++e) x[e] -= scoef[i] * vv[e];
-        }
-        st16(w + r, x);
-    }
-    for (size_t r = r0 + nsw * 256 * N + tid; r < r1; r += 256) {
-        double x = (double)w[r];
-        for (int i = 0; i < nv; ++i) x -= scoef[i] * (double)V[(size_t)i * stride + r];
-        w[r] = (T)x;
-    }
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void gs_update_kernel(const T *__restrict__ V, size_t stride,
-                                                        int nv, PrevPass prev,
-                                                        T *__restrict__ w, size_t L, size_t rpb,
-                                                        int nrb) {
-    (void)nrb;
-    gs_update_body<T>(V, stride, nv, prev.coef, w, L, rpb, blockIdx.x);
-}
-
-// w -= sum_i c_i V_i with c from the previous pass (if any), then the
-// ||w||^2 partials.
-template <typename T>
-__device__ __forceinline__ void gs_update_norm_body(const T *__restrict__ V, size_t stride, int nv,
-                                                    const double *coef, T *__restrict__ w,
-                                                    size_t L, size_t rpb,
-                                                    double *__restrict__ part, int rb) {
-    __shared__ double scoef[kMaxM + 1];
-    __shared__ double sw[4];
-    const int tid = threadIdx.x;
-    const bool upd = coef != nullptr;
-    if (upd && tid < nv) scoef[tid] = coef[tid];
-    __syncthreads();
     const size_t r0 = (size_t)rb * rpb;
     const size_t r1 = (r0 + rpb < L) ? r0 + rpb : L;
     double acc = 0.0;
@@ -461,27 +96,12 @@ __device__ __forceinline__ void gs_update_norm_body(const T *__restrict__ V, siz
     for (size_t k = 0; k < nsw; ++k) {
         const size_t r = r0 + (k * 256 + tid) * N;
         double x[N];
-        ld16(w + r, x);
-        if (upd) {
-            for (int i = 0; i < nv; ++i) {
-                double vv[N];
-                ld16(V + (size_t)i * stride + r, vv);
-#pragma unroll
-                for (int e = 0; e < N; ++e) x[e] -= scoef[i] * vv[e];
-            }
-            st16(w + r, x);
-        }
+        ld16(z + r, x);
 #pragma unroll
         for (int e = 0; e < N; ++e) acc += x[e] * x[e];
     }
     for (size_t r = r0 + nsw * 256 * N + tid; r < r1; r += 256) {
-        double x = (double)w[r];
-        if (upd) {
-            for (int i = 0; i < nv; ++i) x -= scoef[i] * (double)V[(size_t)i * stride + r];
-            const T xs = (T)x;
-            w[r] = xs;
-            x = (double)xs;
-        }
+        const double x = (double)z[r];
         acc += x * x;
     }
     acc = wave_sum(acc);
@@ -491,11 +111,348 @@ __device__ __forceinline__ void gs_update_norm_body(const T *__restrict__ V, siz
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void gs_update_norm_kernel(
-    const T *__restrict__ V, size_t stride, int nv, PrevPass prev, T *__restrict__ w, size_t L,
-    size_t rpb, int nrb, double *__restrict__ part) {
-    (void)nrb;
-    gs_update_norm_body<T>(V, stride, nv, prev.coef, w, L, rpb, part, blockIdx.x);
+__global__ __launch_bounds__(256) void gs_norm_kernel(const T *__restrict__ z, size_t L,
+                                                      size_t rpb, double *__restrict__ part) {
+    gs_norm_body<T>(z, L, rpb, part, blockIdx.x);
+}
+
+struct NormFinish {
+    double *H;
+    double *S;
+    int *flags;     // [0] first breakdown dimension, [1] first non-finite one
+    double *res;    // res[0] = beta
+};
+
+// beta = ||z|| from the partials in a fixed order; S[0] = 1/beta, the flags
+// reset, and the Hessenberg matrix cleared for the new substep.
+__device__ __forceinline__ void finish_norm_body(const double *part, int nrb, const NormFinish &f) {
+    __shared__ double sw[4];
+    const int tid = threadIdx.x;
+    double a = 0.0;
+    for (int b = tid; b < nrb; b += 256) a += part[b];
+    a = wave_sum(a);
+    if ((tid & 63) == 0) sw[tid >> 6] = a;
+    __syncthreads();
+    const double hn = sqrt((sw[0] + sw[1]) + (sw[2] + sw[3]));
+    if (tid == 0) {
+        f.res[0] = hn;
+        f.S[0] = (hn > 0.0) ? 1.0 / hn : 0.0;
+        f.flags[0] = 0;
+        f.flags[1] = isfinite(hn) ? 0 : 1;
+    }
+    for (int e = tid; e < (kMaxM + 1) * LDH; e += 256) f.H[e] = 0.0;
+}
+
+__global__ __launch_bounds__(256) void finish_norm_kernel(const double *part, int nrb,
+                                                          NormFinish f) {
+    finish_norm_body(part, nrb, f);
+}
+
+// ---- one Arnoldi step: dot pass, finish, update sweep -----------------------
+// Block partials of step k (nv = k - 1 finished vectors), for the block's rows
+// and the chunk of CH basis vectors i0 = chunk * CH: rows i0 + i (u^T w) and
+// nv + i0 + i (u^T x); chunk 0 also gives rows 2 nv (x^T x) and 2 nv + 1 (x^T w).
+template <typename T>
+__device__ __forceinline__ void gs_dots2_body(const T *__restrict__ V, size_t stride, int nv,
+                                              const T *__restrict__ x, const T *__restrict__ w,
+                                              size_t L, size_t rpb, int nrb,
+                                              double *__restrict__ part, int rb, int chunk) {
+    __shared__ double sw[4][2 * CH];
+    __shared__ double s2[4][2];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int i0 = chunk * CH;
+    const int nloc = max(0, min(CH, nv - i0));
+    const bool own = chunk == 0;  // this block also sums x^T x and x^T w
+    const size_t r0 = (size_t)rb * rpb;
+    const size_t r1 = (r0 + rpb < L) ? r0 + rpb : L;
+    double acc[2 * CH];
+#pragma unroll
+    for (int i = 0; i < 2 * CH; ++i) acc[i] = 0.0;
+    double axx = 0.0, axw = 0.0;
+    const T *Vc = V + (size_t)i0 * stride;
+    constexpr int N = Vec16<T>::N;
+    const size_t nsw = (r1 - r0) / (256 * N);
+    for (size_t k = 0; k < nsw; ++k) {
+        const size_t r = r0 + (k * 256 + tid) * N;
+        double xv[N], wv[N];
+        ld16(x + r, xv);
+        ld16(w + r, wv);
+#pragma unroll
+        for (int i = 0; i < CH; ++i)
+            if (i < nloc) {
+                double vv[N];
+                ld16(Vc + (size_t)i * stride + r, vv);
+#pragma unroll
+                for (int e = 0; e < N; ++e) {
+                    acc[i] += vv[e] * wv[e];
+                    acc[CH + i] += vv[e] * xv[e];
+                }
+            }
+        if (own) {
+#pragma unroll
+            for (int e = 0; e < N; ++e) {
+                axx += xv[e] * xv[e];
+                axw += xv[e] * wv[e];
+            }
+        }
+    }
+    for (size_t r = r0 + nsw * 256 * N + tid; r < r1; r += 256) {
+        const double xs = (double)x[r], ws = (double)w[r];
+#pragma unroll
+        for (int i = 0; i < CH; ++i)
+            if (i < nloc) {
+                const double u = (double)Vc[(size_t)i * stride + r];
+                acc[i] += u * ws;
+                acc[CH + i] += u * xs;
+            }
+        if (own) {
+            axx += xs * xs;
+            axw += xs * ws;
+        }
+    }
+    const double v = transpose_reduce32(acc);
+    if ((lane & 1) == 0) sw[wave][lane >> 1] = v;
+    axx = wave_sum(axx);
+    axw = wave_sum(axw);
+    if (lane == 0) {
+        s2[wave][0] = axx;
+        s2[wave][1] = axw;
+    }
+    __syncthreads();
+    if (tid < 2 * CH && (tid % CH) < nloc) {
+        const int row = (tid < CH) ? i0 + tid : nv + i0 + (tid - CH);
+        part[(size_t)row * nrb + rb] = (sw[0][tid] + sw[1][tid]) + (sw[2][tid] + sw[3][tid]);
+    }
+    if (own && tid < 2)
+        part[(size_t)(2 * nv + tid) * nrb + rb] = (s2[0][tid] + s2[1][tid]) + (s2[2][tid] + s2[3][tid]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void gs_dots2_kernel(const T *__restrict__ V, size_t stride,
+                                                       int nv, const T *__restrict__ x,
+                                                       const T *__restrict__ w, size_t L,
+                                                       size_t rpb, int nrb,
+                                                       double *__restrict__ part) {
+    gs_dots2_body<T>(V, stride, nv, x, w, L, rpb, nrb, part, blockIdx.x, blockIdx.y);
+}
+
+// Finish of step k (one block of kFin2Threads threads); see launch_dcgs_finish.
+// The finished part of H is copied to LDS once, so the norm, t = H a and the
+// first pass read no global memory written within the launch; every sum runs
+// in a fixed order, so results are identical run to run.
+constexpr int kFin2Threads = 1024;
+
+// sv[r] = sum_b part[r * nrb + b] for r < rows: each row gets tpr consecutive
+// lanes of one wave (tpr the largest power of two <= 64 with rows tpr <=
+// kFin2Threads); lane j sums b = j, j + tpr, ... in ascending order, then the
+// row's lanes are summed by butterfly.  No thread issues a load it does not
+// use, and all rows are summed at once.
+__device__ __forceinline__ void fin_row_sums(const double *part, int rows, int nrb, double *sv) {
+    const int tid = threadIdx.x;
+    int lg = 6;
+    while (lg > 0 && (rows << lg) > kFin2Threads) --lg;
+    const int tpr = 1 << lg;
+    const int r = tid >> lg, j = tid & (tpr - 1);
+    double s = 0.0;
+    if (r < rows)
+        for (int b = j; b < nrb; b += tpr) s += part[(size_t)r * nrb + b];
+    for (int off = tpr >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (j == 0 && r < rows) sv[r] = s;
+}
+
+struct DcgsFinish {
+    double *S, *H;
+    int k;
+    double *coefA, *coefB;
+    int *flags;
+};
+
+__device__ __forceinline__ void dcgs_finish_body(const double *part, int nrb,
+                                                 const DcgsFinish &f) {
+    constexpr int NW = kFin2Threads / 64;
+    __shared__ double sH[(kMaxM + 1) * LDH];
+    __shared__ double sv[kPartRows];
+    __shared__ double sa[kMaxM + 1], st[kMaxM + 1], se[kMaxM + 1];
+    __shared__ double sw[NW];
+    __shared__ double saa, sab, sbeta;
+    const int k = f.k, nv = k - 1, col = k - 2;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double *H = f.H, *S = f.S;
+    // the scales, rows 0..k-1 and columns 0..k-2 of H (loads unconditional,
+    // indices clamped into range, so a wave's loads are in flight together),
+    // and the row sums of the block partials
+    const double Si = (tid < nv) ? S[tid] : 0.0;
+    {
+        constexpr int QH = (kMaxM + 1 + NW - 1) / NW;
+        const int cc = min(lane, max(col, 0));
+        double hv[QH];
+#pragma unroll
+        for (int q = 0; q < QH; ++q) hv[q] = H[(size_t)min(wave + q * NW, kMaxM) * LDH + cc];
+#pragma unroll
+        for (int q = 0; q < QH; ++q)
+            if (wave + q * NW < k && lane <= col) sH[(wave + q * NW) * LDH + lane] = hv[q];
+    }
+    fin_row_sums(part, 2 * nv + 2, nrb, sv);
+    __syncthreads();
+    // a_i = v_i^T x and b_i = v_i^T w; nv <= kMaxM, so all of them in wave 0
+    double ai = 0.0, bi = 0.0;
+    if (tid < nv) {
+        ai = Si * sv[nv + tid];
+        bi = Si * sv[tid];
+        sa[tid] = ai;
+    }
+    if (wave == 0) {
+        const double aa = wave_sum(ai * ai), ab = wave_sum(ai * bi);
+        if (lane == 0) {
+            saa = aa;
+            sab = ab;
+        }
+    }
+    __syncthreads();
+    const double gam = sv[2 * nv], del = sv[2 * nv + 1];
+    if (k == 1) {
+        // x = u_0 is the finished start vector
+        if (tid == 0) sbeta = 1.0 / S[0];
+        __syncthreads();
+    } else {
+        // second pass of x: ||x - V a||^2 = x^T x - |a|^2 (Pythagoras); the
+        // finished column k-2 is the first pass plus a
+        const double q2 = gam - saa;
+        const double beta = (q2 < 0.0) ? 0.0 : sqrt(q2);  // NaN stays NaN
+        if (tid <= col) sH[tid * LDH + col] += sa[tid];
+        if (tid == 0) sH[(k - 1) * LDH + col] = beta;
+        __syncthreads();
+        // ||H_{0:k, 0:k-1}||_F with the finished column and the new subdiagonal
+        double acc = 0.0;
+        for (int r = wave; r < k; r += NW)
+            for (int c = lane; c <= col; c += 64) {
+                const double h = (r <= c + 1) ? sH[r * LDH + c] : 0.0;
+                acc += h * h;
+            }
+        acc = wave_sum(acc);
+        if (lane == 0) sw[wave] = acc;
+        __syncthreads();
+        if (tid <= col) H[(size_t)tid * LDH + col] = sH[tid * LDH + col];
+        if (tid == 0) {
+            double s = 0.0;
+            for (int q = 0; q < NW; ++q) s += sw[q];
+            const double hf = sqrt(s);
+            if ((!isfinite(beta) || !isfinite(hf)) && f.flags[1] == 0) f.flags[1] = k - 1;
+            const bool brk = beta <= 1e-12 * hf;
+            if (brk) {
+                H[(size_t)(k - 1) * LDH + col] = 0.0;
+                S[k - 1] = 0.0;
+                if (f.flags[0] == 0) f.flags[0] = k - 1;
+            } else {
+                H[(size_t)(k - 1) * LDH + col] = beta;
+                S[k - 1] = 1.0 / beta;
+            }
+            sH[(k - 1) * LDH + col] = brk ? 0.0 : beta;
+            sbeta = brk ? 1.0 : beta;  // after a breakdown the step only has to stay finite
+        }
+        __syncthreads();
+    }
+    const double bet = sbeta;
+    // t = H_{0:k, 0:k-1} a (A V_{k-1} a expressed in the basis V_k): one wave per row
+    for (int r = wave; r < k; r += NW) {
+        double t = 0.0;
+        for (int c = max(r - 1, 0) + lane; c <= col; c += 64) t += sH[r * LDH + c] * sa[c];
+        t = wave_sum(t);
+        if (lane == 0) st[r] = t;
+    }
+    __syncthreads();
+    // first pass of A v_{k-1} = (w - V_k t) / beta; e = t / beta + g
+    if (tid < k) {
+        double g;
+        if (tid < nv)
+            g = (bi - st[tid]) / bet;
+        else
+            g = ((del - sab) / bet - st[tid]) / bet;
+        H[(size_t)tid * LDH + (k - 1)] = g;
+        se[tid] = st[tid] / bet + g;
+    }
+    __syncthreads();
+    const double ek = se[k - 1];
+    if (tid < nv) {
+        f.coefA[tid] = Si * sa[tid];
+        f.coefB[tid] = Si * (se[tid] - sa[tid] * ek / bet);
+    }
+    if (tid == 0) {
+        f.coefB[kScalW] = 1.0 / bet;
+        f.coefB[kScalX] = ek / bet;
+    }
+}
+
+__global__ __launch_bounds__(kFin2Threads) void dcgs_finish_kernel(const double *part, int nrb,
+                                                                   DcgsFinish f) {
+    dcgs_finish_body(part, nrb, f);
+}
+
+// Update sweep of step k: x -= sum_i cA_i u_i (nv > 0) and
+// w <- cB[kScalW] w - cB[kScalX] x_old - sum_i cB_i u_i, reading each u_i once.
+template <typename T>
+__device__ __forceinline__ void dcgs_update_body(const T *__restrict__ V, size_t stride, int nv,
+                                                 const double *cA, const double *cB,
+                                                 T *__restrict__ x, T *__restrict__ w, size_t L,
+                                                 size_t rpb, int rb) {
+    __shared__ double sA[kMaxM], sB[kMaxM], sWX[2];
+    const int tid = threadIdx.x;
+    if (tid < nv) {
+        sA[tid] = cA[tid];
+        sB[tid] = cB[tid];
+    }
+    if (tid == 0) {
+        sWX[0] = cB[kScalW];
+        sWX[1] = cB[kScalX];
+    }
+    __syncthreads();
+    const double cw = sWX[0], cx = sWX[1];
+    const size_t r0 = (size_t)rb * rpb;
+    const size_t r1 = (r0 + rpb < L) ? r0 + rpb : L;
+    constexpr int N = Vec16<T>::N;
+    const size_t nsw = (r1 - r0) / (256 * N);
+    for (size_t k = 0; k < nsw; ++k) {
+        const size_t r = r0 + (k * 256 + tid) * N;
+        double xv[N], wv[N], xn[N], wn[N];
+        ld16(x + r, xv);
+        ld16(w + r, wv);
+#pragma unroll
+        for (int e = 0; e < N; ++e) {
+            xn[e] = xv[e];
+            wn[e] = cw * wv[e] - cx * xv[e];
+        }
+        for (int i = 0; i < nv; ++i) {
+            double vv[N];
+            ld16(V + (size_t)i * stride + r, vv);
+#pragma unroll
+            for (int e = 0; e < N; ++e) {
+                xn[e] -= sA[i] * vv[e];
+                wn[e] -= sB[i] * vv[e];
+            }
+        }
+        if (nv > 0) st16(x + r, xn);
+        st16(w + r, wn);
+    }
+    for (size_t r = r0 + nsw * 256 * N + tid; r < r1; r += 256) {
+        const double xs = (double)x[r];
+        double xn = xs, wn = cw * (double)w[r] - cx * xs;
+        for (int i = 0; i < nv; ++i) {
+            const double u = (double)V[(size_t)i * stride + r];
+            xn -= sA[i] * u;
+            wn -= sB[i] * u;
+        }
+        if (nv > 0) x[r] = (T)xn;
+        w[r] = (T)wn;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void dcgs_update_kernel(const T *__restrict__ V, size_t stride,
+                                                          int nv, const double *cA,
+                                                          const double *cB, T *__restrict__ x,
+                                                          T *__restrict__ w, size_t L,
+                                                          size_t rpb) {
+    dcgs_update_body<T>(V, stride, nv, cA, cB, x, w, L, rpb, blockIdx.x);
 }
 
 template <typename T>
@@ -824,47 +781,29 @@ __global__ __launch_bounds__(256) void combine_kernel(const T *V, size_t stride,
 // independent solves.  Item it owns blocks [bstart[it], bstart[it+1]); an item
 // with no blocks in a launch is skipped.  Each item computes exactly what its
 // own single launch computes (same row partition, same block partials).
-// extra = 1: the dots also take w itself (V_nv is w), giving ||w||^2 in row nv.
-__global__ __launch_bounds__(256) void gs_dots_group(const GsItem *items, const int *bstart,
-                                                     int n, int extra) {
+__global__ __launch_bounds__(256) void gs_dots2_group(const GsItem *items, const int *bstart,
+                                                      int n) {
     const int it = group_item(bstart, n, blockIdx.x);
     const GsItem &g = items[it];
     const int local = blockIdx.x - bstart[it];
-    gs_dots_body<double>(g.V, g.stride, g.nv + extra, g.w, g.L, g.rpb, g.nrb, g.part,
-                         local % g.nrb, local / g.nrb);
+    gs_dots2_body<double>(g.V, g.stride, g.k - 1, g.x, g.w, g.L, g.rpb, g.nrb, g.part,
+                          local % g.nrb, local / g.nrb);
 }
 
-// Finish of the first pass: nrb1 partials per vector from the linear
-// operator's blocks, or (nrb1 = 0) nrb from the separate dot pass.
-__global__ __launch_bounds__(256) void finish_dots_group(const GsItem *items, const int *bstart,
+// One workgroup per item; nrb1 partials per row from the linear operator's
+// blocks, or (nrb1 = 0) nrb from the separate dot pass.
+__global__ __launch_bounds__(kFin2Threads) void dcgs_finish_group(const GsItem *items) {
+    const GsItem &g = items[blockIdx.x];
+    dcgs_finish_body(g.part, g.nrb1 > 0 ? g.nrb1 : g.nrb,
+                     DcgsFinish{g.S, g.H, g.k, g.coefA, g.coefB, g.flags});
+}
+
+__global__ __launch_bounds__(256) void dcgs_update_group(const GsItem *items, const int *bstart,
                                                          int n) {
     const int it = group_item(bstart, n, blockIdx.x);
     const GsItem &g = items[it];
-    const DotFinish f{g.S, g.H, g.col, 0, g.coefA};
-    finish_dots_body(g.part, g.nv, g.nrb1 > 0 ? g.nrb1 : g.nrb, f, blockIdx.x - bstart[it]);
-}
-
-__global__ __launch_bounds__(256) void gs_update_dots_group(const GsItem *items,
-                                                            const int *bstart, int n) {
-    const int it = group_item(bstart, n, blockIdx.x);
-    const GsItem &g = items[it];
-    gs_update_dots_body<double>(g.V, g.stride, g.nv, g.coefA, g.w, g.L, g.rpb, g.nrb, g.part,
-                                blockIdx.x - bstart[it]);
-}
-
-// pass 0: w -= V coefA (first-pass coefficients); pass 1: w -= V coefB.
-__global__ __launch_bounds__(256) void gs_update_group(const GsItem *items, const int *bstart,
-                                                       int n, int pass) {
-    const int it = group_item(bstart, n, blockIdx.x);
-    const GsItem &g = items[it];
-    gs_update_body<double>(g.V, g.stride, g.nv, pass ? g.coefB : g.coefA, g.w, g.L, g.rpb,
-                           blockIdx.x - bstart[it]);
-}
-
-// One workgroup per item.
-__global__ __launch_bounds__(kFin2Threads) void finish_pass2_group(const GsItem *items) {
-    const GsItem &g = items[blockIdx.x];
-    finish_pass2_body(g.part, g.nv, g.nrb, Pass2Finish{g.S, g.H, g.col, g.coefB, g.flags});
+    dcgs_update_body<double>(g.V, g.stride, g.k - 1, g.coefA, g.coefB, g.x, g.w, g.L, g.rpb,
+                             blockIdx.x - bstart[it]);
 }
 
 constexpr size_t kExpmLds = (size_t)4 * NMAX * LDA * sizeof(double);
@@ -897,88 +836,50 @@ RowPartition row_partition(size_t L) {
 }
 
 template <typename T>
-hipError_t launch_gs_dots(const T *V, size_t stride, int nv, const T *w, size_t L,
-                          const RowPartition &rp, double *part, const double *S, double *H,
-                          int col, int accumulate, double *coef_out, hipStream_t s) {
-    if (nv < 1 || nv > kMaxM + 1) return hipErrorInvalidValue;
-    dim3 grid(rp.nrb, (nv + CH - 1) / CH);
-    (void)S, (void)H, (void)col, (void)accumulate, (void)coef_out;
-    return launch_kernel(gs_dots_kernel<T>, grid, dim3(256), 0, s, V, stride, nv, w, L, rp.rpb,
-                         rp.nrb, part);
+hipError_t launch_gs_dots2(const T *V, size_t stride, int nv, const T *x, const T *w, size_t L,
+                           const RowPartition &rp, double *part, hipStream_t s) {
+    if (nv < 0 || nv > kMaxM) return hipErrorInvalidValue;
+    const dim3 grid(rp.nrb, nv > 0 ? (nv + CH - 1) / CH : 1);
+    return launch_kernel(gs_dots2_kernel<T>, grid, dim3(256), 0, s, V, stride, nv, x, w, L,
+                         rp.rpb, rp.nrb, part);
 }
 
-hipError_t launch_gs_finish_dots(const double *part, int nv, const RowPartition &rp,
-                                 const double *S, double *H, int col, int accumulate,
-                                 double *coef_out, hipStream_t s) {
-    return launch_kernel(finish_dots_kernel, dim3((nv + 3) / 4), dim3(256), 0, s, part, nv,
-                         rp.nrb, DotFinish{S, H, col, accumulate, coef_out});
+hipError_t launch_dcgs_finish(const double *part, int nrb, int k, double *S, double *H,
+                              double *coefA, double *coefB, int *flags, hipStream_t s) {
+    if (k < 1 || k > kMaxM + 1 || nrb < 1) return hipErrorInvalidValue;
+    return launch_kernel(dcgs_finish_kernel, dim3(1), dim3(kFin2Threads), 0, s, part, nrb,
+                         DcgsFinish{S, H, k, coefA, coefB, flags});
+}
+
+template <typename T>
+hipError_t launch_dcgs_update(const T *V, size_t stride, int nv, const double *coefA,
+                              const double *coefB, T *x, T *w, size_t L, const RowPartition &rp,
+                              hipStream_t s) {
+    if (nv < 0 || nv > kMaxM) return hipErrorInvalidValue;
+    return launch_kernel(dcgs_update_kernel<T>, dim3(rp.nrb), dim3(256), 0, s, V, stride, nv,
+                         coefA, coefB, x, w, L, rp.rpb);
+}
+
+template <typename T>
+hipError_t launch_gs_norm(const T *z, size_t L, const RowPartition &rp, double *part,
+                          hipStream_t s) {
+    return launch_kernel(gs_norm_kernel<T>, dim3(rp.nrb), dim3(256), 0, s, z, L, rp.rpb, part);
 }
 
 hipError_t launch_gs_finish_norm(const double *part, const RowPartition &rp, double *H, double *S,
-                                 int col, int *flags, double *res, hipStream_t s) {
+                                 int *flags, double *res, hipStream_t s) {
     return launch_kernel(finish_norm_kernel, dim3(1), dim3(256), 0, s, part, rp.nrb,
-                         NormFinish{H, S, col, flags, res});
+                         NormFinish{H, S, flags, res});
 }
 
-template <typename T>
-hipError_t launch_gs_update_dots(const T *V, size_t stride, int nv, const double *coef_in, T *w,
-                                 size_t L, const RowPartition &rp, double *part, const double *S,
-                                 double *H, int col, double *coef_out, hipStream_t s) {
-    if (nv < 1 || nv > kMaxM + 1) return hipErrorInvalidValue;
-    PrevPass prev{coef_in};
-    if (nv <= 32) {
-        return launch_kernel(gs_update_dots_kernel<T>, dim3(rp.nrb), dim3(256), 0, s, V, stride,
-                             nv, prev, w, L, rp.rpb, rp.nrb, part);
-    }
-    hipError_t e = launch_kernel(gs_update_kernel<T>, dim3(rp.nrb), dim3(256), 0, s, V, stride,
-                                 nv, prev, w, L, rp.rpb, rp.nrb);
-    if (e != hipSuccess) return e;
-    // the dots also take w itself (it is V_nv): ||w||^2 in row nv
-    return launch_gs_dots<T>(V, stride, nv + 1, w, L, rp, part, S, H, col, 1, coef_out, s);
-}
-
-template <typename T>
-hipError_t launch_gs_update(const T *V, size_t stride, int nv, const double *coef, T *w, size_t L,
-                            const RowPartition &rp, hipStream_t s) {
-    if (nv < 1 || nv > kMaxM + 1) return hipErrorInvalidValue;
-    PrevPass prev{coef};
-    return launch_kernel(gs_update_kernel<T>, dim3(rp.nrb), dim3(256), 0, s, V, stride, nv, prev,
-                         w, L, rp.rpb, rp.nrb);
-}
-
-hipError_t launch_gs_finish_pass2(const double *part, int nv, const RowPartition &rp, double *S,
-                                  double *H, int col, double *coef_out, int *flags,
-                                  hipStream_t s) {
-    if (nv < 1 || nv > kMaxM) return hipErrorInvalidValue;
-    return launch_kernel(finish_pass2_kernel, dim3(1), dim3(kFin2Threads), 0, s, part, nv, rp.nrb,
-                         Pass2Finish{S, H, col, coef_out, flags});
-}
-
-template <typename T>
-hipError_t launch_gs_update_norm(const T *V, size_t stride, int nv, const double *coef, T *w,
-                                 size_t L, const RowPartition &rp, double *part, double *H,
-                                 double *S, int col, int *flags, double *res, hipStream_t s) {
-    if (nv < 0 || nv > kMaxM + 1) return hipErrorInvalidValue;
-    PrevPass prev{coef};
-    (void)H, (void)S, (void)col, (void)flags, (void)res;
-    return launch_kernel(gs_update_norm_kernel<T>, dim3(rp.nrb), dim3(256), 0, s, V, stride, nv,
-                         prev, w, L, rp.rpb, rp.nrb, part);
-}
-
-#define EXPDG_INST(T)                                                                         \
-    template hipError_t launch_gs_dots<T>(const T *, size_t, int, const T *, size_t,           \
-                                          const RowPartition &, double *, const double *,       \
-                                          double *, int, int, double *, hipStream_t);           \
-    template hipError_t launch_gs_update_dots<T>(const T *, size_t, int, const double *, T *,  \
-                                                 size_t, const RowPartition &, double *,        \
-                                                 const double *, double *, int, double *,       \
-                                                 hipStream_t);                                  \
-    template hipError_t launch_gs_update_norm<T>(const T *, size_t, int, const double *, T *,  \
-                                                 size_t, const RowPartition &, double *,        \
-                                                 double *, double *, int, int *, double *,      \
-                                                 hipStream_t);                                  \
-    template hipError_t launch_gs_update<T>(const T *, size_t, int, const double *, T *, size_t, \
-                                            const RowPartition &, hipStream_t);
+#define EXPDG_INST(T)                                                                          \
+    template hipError_t launch_gs_dots2<T>(const T *, size_t, int, const T *, const T *, size_t, \
+                                           const RowPartition &, double *, hipStream_t);        \
+    template hipError_t launch_dcgs_update<T>(const T *, size_t, int, const double *,           \
+                                              const double *, T *, T *, size_t,                 \
+                                              const RowPartition &, hipStream_t);               \
+    template hipError_t launch_gs_norm<T>(const T *, size_t, const RowPartition &, double *,    \
+                                          hipStream_t);
 EXPDG_INST(double)
 EXPDG_INST(float)
 #undef EXPDG_INST
@@ -1019,12 +920,9 @@ void arnoldi_group_layout(const GsItem *items, int n, int *bstart, int *totals) 
     int t[kGroupLaunches] = {};
     for (int it = 0; it < n; ++it) {
         const GsItem &g = items[it];
-        const int chunks = (g.nv + CH - 1) / CH;
-        const int chunks2 = (g.nv + 1 + CH - 1) / CH;  // with w itself
-        const bool small = g.nv <= 32;
-        const int blocks[kGroupLaunches] = {g.nrb1 > 0 ? 0 : g.nrb * chunks, (g.nv + 3) / 4,
-                                            small ? g.nrb : 0,     small ? 0 : g.nrb,
-                                            small ? 0 : g.nrb * chunks2, g.nrb};
+        const int nv = g.k - 1;
+        const int chunks = nv > 0 ? (nv + CH - 1) / CH : 1;
+        const int blocks[kGroupLaunches] = {g.nrb1 > 0 ? 0 : g.nrb * chunks, g.nrb};
         for (int k = 0; k < kGroupLaunches; ++k) {
             bstart[k * (n + 1) + it] = t[k];
             t[k] += blocks[k];
@@ -1042,29 +940,14 @@ hipError_t launch_arnoldi_group(const GsItem *items, const int *bstart, const in
     const int *b[kGroupLaunches];
     for (int k = 0; k < kGroupLaunches; ++k) b[k] = bstart + (size_t)k * (n + 1);
     hipError_t e;
-    // first pass: h1 = V^T w (partials from the linear operator, or a dot pass)
+    // dot pass of the items whose linear operator does not carry it
     if (totals[0] > 0) {
-        e = launch_kernel(gs_dots_group, dim3(totals[0]), dim3(256), 0, s, items, b[0], n, 0);
+        e = launch_kernel(gs_dots2_group, dim3(totals[0]), dim3(256), 0, s, items, b[0], n);
         if (e != hipSuccess) return e;
     }
-    e = launch_kernel(finish_dots_group, dim3(totals[1]), dim3(256), 0, s, items, b[1], n);
+    e = launch_kernel(dcgs_finish_group, dim3(n), dim3(kFin2Threads), 0, s, items);
     if (e != hipSuccess) return e;
-    // second pass: w -= V h1 ; h2 = V^T w and ||w||^2 (fused for j <= 32)
-    if (totals[2] > 0) {
-        e = launch_kernel(gs_update_dots_group, dim3(totals[2]), dim3(256), 0, s, items, b[2], n);
-        if (e != hipSuccess) return e;
-    }
-    if (totals[3] > 0) {
-        e = launch_kernel(gs_update_group, dim3(totals[3]), dim3(256), 0, s, items, b[3], n, 0);
-        if (e != hipSuccess) return e;
-        e = launch_kernel(gs_dots_group, dim3(totals[4]), dim3(256), 0, s, items, b[4], n, 1);
-        if (e != hipSuccess) return e;
-    }
-    // h2, ||w''|| by Pythagoras, H[j][j-1], S[j], breakdown test
-    e = launch_kernel(finish_pass2_group, dim3(n), dim3(kFin2Threads), 0, s, items);
-    if (e != hipSuccess) return e;
-    // w -= V h2
-    return launch_kernel(gs_update_group, dim3(totals[5]), dim3(256), 0, s, items, b[5], n, 1);
+    return launch_kernel(dcgs_update_group, dim3(totals[1]), dim3(256), 0, s, items, b[1], n);
 }
 
 hipError_t launch_dense_expm(const double *A, int n, double *E, hipStream_t s) {

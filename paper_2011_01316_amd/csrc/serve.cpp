@@ -143,7 +143,7 @@ struct ServeExec {
     };
 
     hipStream_t stream() const;
-    Await iterate(expdg_mesh *m, const OpArgs<double> &a, int j, int naug_nz, const CheckReq *cr,
+    Await iterate(expdg_mesh *m, const OpArgs<double> &a, int k, int naug_nz, const CheckReq *cr,
                   Check *c);
     Await check(expdg_mesh *m, const CheckReq &q, Check *c);
     Await wait_check(expdg_mesh *m, const Check &c);
@@ -246,7 +246,7 @@ namespace {
 
 hipStream_t ServeExec::stream() const { return sv->s; }
 
-ServeExec::Await ServeExec::iterate(expdg_mesh *m, const OpArgs<double> &a, int j, int naug_nz,
+ServeExec::Await ServeExec::iterate(expdg_mesh *m, const OpArgs<double> &a, int k, int naug_nz,
                                     const CheckReq *cr, Check *c) {
     (void)naug_nz;
     IterRec rec;
@@ -257,20 +257,19 @@ ServeExec::Await ServeExec::iterate(expdg_mesh *m, const OpArgs<double> &a, int 
     const KrylovDev &kd = m->kd;
     GsItem &g = rec.g;
     g.V = (const double *)m->V;
+    g.x = (double *)m->V + (size_t)(k - 1) * m->stride;
     g.w = a.out;
     g.stride = m->stride;
     g.L = L;
     g.rpb = rp.rpb;
     g.nrb = rp.nrb;
-    g.nrb1 = (a.nv > 0) ? a.dnb : 0;  // 0: a separate first dot pass
-    g.nv = j;
-    g.col = j - 1;
+    g.nrb1 = a.dots ? a.dnb : 0;  // 0: a separate dot pass
+    g.k = k;
     g.part = kd.part;
     g.S = kd.S;
     g.H = kd.H;
     g.coefA = kd.coefA;
     g.coefB = kd.coefB;
-    g.res = kd.res;
     g.flags = kd.flags;
     sv->iters.push_back(rec);
     if (cr) {
