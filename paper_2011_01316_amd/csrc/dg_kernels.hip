@@ -218,20 +218,32 @@ __device__ __forceinline__ void op_dots2(const OpArgs<T> &a, bool active, unsign
 #pragma unroll
         for (int k = 0; k < 32; ++k) acc[k] = 0.0;
         if (active) {
+            // loads in groups of KG vectors, all issued before their products
+            // (vector index clamped, the extra sums dropped), so a group's
+            // loads are in flight together
+            constexpr int KG = (NV >= 4) ? 4 : 16;
 #pragma unroll
-            for (int k = 0; k < 16; ++k)
-                if (i0 + k < nv) {
-                    const T *Vi = a.basis + (size_t)(i0 + k) * a.bstride;
+            for (int k0 = 0; k0 < 16; k0 += KG) {
+                T u[KG][NV];
+#pragma unroll
+                for (int kk = 0; kk < KG; ++kk) {
+                    const T *Vi = a.basis + (size_t)min(i0 + k0 + kk, nv - 1) * a.bstride;
+#pragma unroll
+                    for (int c = 0; c < NV; ++c) u[kk][c] = ld32(Vi + c * plane, idx);
+                }
+#pragma unroll
+                for (int kk = 0; kk < KG; ++kk) {
                     double sw_ = 0.0, sx_ = 0.0;
 #pragma unroll
                     for (int c = 0; c < NV; ++c) {
-                        const double u = (double)ld32(Vi + c * plane, idx);
-                        sw_ += u * (double)wv[c];
-                        sx_ += u * (double)xv[c];
+                        sw_ += (double)u[kk][c] * (double)wv[c];
+                        sx_ += (double)u[kk][c] * (double)xv[c];
                     }
-                    acc[k] = sw_;
-                    acc[16 + k] = sx_;
+                    const bool in = i0 + k0 + kk < nv;
+                    acc[k0 + kk] = in ? sw_ : 0.0;
+                    acc[16 + k0 + kk] = in ? sx_ : 0.0;
                 }
+            }
         }
         if (tail) {
             for (int t = 0; t < a.naug; ++t) {

@@ -177,17 +177,22 @@ __device__ __forceinline__ void gs_dots2_body(const T *__restrict__ V, size_t st
         double xv[N], wv[N];
         ld16(x + r, xv);
         ld16(w + r, wv);
+        if (nloc > 0) {
+            // unconditional loads (vector index clamped, extra products
+            // dropped), so the chunk's loads are in flight together
+            double vv[CH][N];
 #pragma unroll
-        for (int i = 0; i < CH; ++i)
-            if (i < nloc) {
-                double vv[N];
-                ld16(Vc + (size_t)i * stride + r, vv);
+            for (int i = 0; i < CH; ++i) ld16(Vc + (size_t)min(i, nloc - 1) * stride + r, vv[i]);
+#pragma unroll
+            for (int i = 0; i < CH; ++i) {
+                const bool in = i < nloc;
 #pragma unroll
                 for (int e = 0; e < N; ++e) {
-                    acc[i] += vv[e] * wv[e];
-                    acc[CH + i] += vv[e] * xv[e];
+                    acc[i] += in ? vv[i][e] * wv[e] : 0.0;
+                    acc[CH + i] += in ? vv[i][e] * xv[e] : 0.0;
                 }
             }
+        }
         if (own) {
 #pragma unroll
             for (int e = 0; e < N; ++e) {
@@ -421,13 +426,23 @@ __device__ __forceinline__ void dcgs_update_body(const T *__restrict__ V, size_t
             xn[e] = xv[e];
             wn[e] = cw * wv[e] - cx * xv[e];
         }
-        for (int i = 0; i < nv; ++i) {
-            double vv[N];
-            ld16(V + (size_t)i * stride + r, vv);
+        // batches of UB vectors loaded together (index clamped, coefficient 0
+        // past the end), applied in ascending order
+        constexpr int UB = 8;
+        for (int i0 = 0; i0 < nv; i0 += UB) {
+            double vv[UB][N];
 #pragma unroll
-            for (int e = 0; e < N; ++e) {
-                xn[e] -= sA[i] * vv[e];
-                wn[e] -= sB[i] * vv[e];
+            for (int u = 0; u < UB; ++u) ld16(V + (size_t)min(i0 + u, nv - 1) * stride + r, vv[u]);
+#pragma unroll
+            for (int u = 0; u < UB; ++u) {
+                const bool in = i0 + u < nv;
+                const double ca = in ? sA[min(i0 + u, nv - 1)] : 0.0;
+                const double cb = in ? sB[min(i0 + u, nv - 1)] : 0.0;
+#pragma unroll
+                for (int e = 0; e < N; ++e) {
+                    xn[e] -= ca * vv[u][e];
+                    wn[e] -= cb * vv[u][e];
+                }
             }
         }
         if (nv > 0) st16(x + r, xn);
