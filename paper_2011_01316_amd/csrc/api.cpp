@@ -495,25 +495,36 @@ struct DirectExec {
 
     hipStream_t stream() const { return s; }
 
-    int enqueue_check(expdg_mesh *m, const CheckReq &r, Check *c) {
+    // A check in two parts: mark_check records, on the main stream, the point
+    // after which H and S hold what the check reads; submit_check queues the
+    // small exponential behind that point on the side stream.  Main-stream
+    // work enqueued in between does not wait for the side-stream calls.
+    int mark_check(expdg_mesh *m, const CheckReq &r, Check *c) {
         c->j = r.j;
         c->slot = r.slot;
         HIPTRY(hipEventRecord(m->evH[c->slot], s));
-        HIPTRY(hipStreamWaitEvent(m->side, m->evH[c->slot], 0));
+        return EXPDG_OK;
+    }
+    int submit_check(expdg_mesh *m, const CheckReq &r, const Check &c) {
+        HIPTRY(hipStreamWaitEvent(m->side, m->evH[c.slot], 0));
         const KrylovDev &kd = m->kd;
         ExpmItem it{kd.H,
                     kd.S,
                     kd.res,
                     kd.flags,
-                    m->slots + c->slot * kSlotSize,
-                    m->pin_dev + kPinSlots + c->slot * 8,
+                    m->slots + c.slot * kSlotSize,
+                    m->pin_dev + kPinSlots + c.slot * 8,
                     r.dtau,
                     r.j};
         TRY(prof_begin(m, EXPDG_K_SMALLEXPM));
         HIPTRY(launch_hess_expm(it, m->side));
         TRY(prof_end(m, EXPDG_K_SMALLEXPM, 0.0));
-        HIPTRY(hipEventRecord(m->ev[c->slot], m->side));
+        HIPTRY(hipEventRecord(m->ev[c.slot], m->side));
         return EXPDG_OK;
+    }
+    int enqueue_check(expdg_mesh *m, const CheckReq &r, Check *c) {
+        TRY(mark_check(m, r, c));
+        return submit_check(m, r, *c);
     }
 
     // Arnoldi step k: the operator on x = u_{k-1} (and, in 2D, the dot pass
@@ -542,10 +553,11 @@ struct DirectExec {
         HIPTRY(launch_dcgs_finish(kd.part, nrb, k, kd.S, kd.H, kd.coefA, kd.coefB, kd.flags, s));
         TRY(prof_end(m, EXPDG_K_GS_FINISH, 8.0 * nrb * (2 * nv + 2)));
         // the check needs H and S only: it starts while the update sweep runs
-        if (cr) TRY(enqueue_check(m, *cr, c));
+        if (cr) TRY(mark_check(m, *cr, c));
         TRY(prof_begin(m, EXPDG_K_GS_UPDATE));
         HIPTRY(launch_dcgs_update<T>(V, stride, nv, kd.coefA, kd.coefB, x, w, L, rp, s));
         TRY(prof_end(m, EXPDG_K_GS_UPDATE, (double)(nv + (nv > 0 ? 4 : 3)) * L * eb));
+        if (cr) TRY(submit_check(m, *cr, *c));
         return EXPDG_OK;
     }
 

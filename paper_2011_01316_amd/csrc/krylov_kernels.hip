@@ -250,8 +250,7 @@ constexpr int kFin2Threads = 1024;
 // sv[r] = sum_b part[r * nrb + b] for r < rows: each row gets tpr consecutive
 // lanes of one wave (tpr the largest power of two <= 64 with rows tpr <=
 // kFin2Threads); lane j sums b = j, j + tpr, ... in ascending order, then the
-// row's lanes are summed by butterfly.  No thread issues a load it does not
-// use, and all rows are summed at once.
+// row's lanes are summed by butterfly.  All rows are summed at once.
 __device__ __forceinline__ void fin_row_sums(const double *part, int rows, int nrb, double *sv) {
     const int tid = threadIdx.x;
     int lg = 6;
@@ -259,8 +258,19 @@ __device__ __forceinline__ void fin_row_sums(const double *part, int rows, int n
     const int tpr = 1 << lg;
     const int r = tid >> lg, j = tid & (tpr - 1);
     double s = 0.0;
-    if (r < rows)
-        for (int b = j; b < nrb; b += tpr) s += part[(size_t)r * nrb + b];
+    if (r < rows) {
+        // batches of UB loads in flight together (index clamped, extra
+        // values dropped), added in the same ascending order
+        constexpr int UB = 16;
+        const double *pr = part + (size_t)r * nrb;
+        for (int b0 = j; b0 < nrb; b0 += UB * tpr) {
+            double v[UB];
+#pragma unroll
+            for (int u = 0; u < UB; ++u) v[u] = pr[min(b0 + u * tpr, nrb - 1)];
+#pragma unroll
+            for (int u = 0; u < UB; ++u) s += (b0 + u * tpr < nrb) ? v[u] : 0.0;
+        }
+    }
     for (int off = tpr >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
     if (j == 0 && r < rows) sv[r] = s;
 }
@@ -776,11 +786,19 @@ __global__ __launch_bounds__(256) void combine_kernel(const T *V, size_t stride,
         double acc[N];
 #pragma unroll
         for (int e = 0; e < N; ++e) acc[e] = 0.0;
-        for (int i = 0; i < m; ++i) {
-            double vv[N];
-            ld16(V + (size_t)i * stride + r, vv);
+        // batches of UB basis rows loaded together (index clamped,
+        // coefficient 0 past the end), summed in ascending order
+        constexpr int UB = 8;
+        for (int i0 = 0; i0 < m; i0 += UB) {
+            double vv[UB][N];
 #pragma unroll
-            for (int e = 0; e < N; ++e) acc[e] += sc[i] * vv[e];
+            for (int u = 0; u < UB; ++u) ld16(V + (size_t)min(i0 + u, m - 1) * stride + r, vv[u]);
+#pragma unroll
+            for (int u = 0; u < UB; ++u) {
+                const double c = (i0 + u < m) ? sc[min(i0 + u, m - 1)] : 0.0;
+#pragma unroll
+                for (int e = 0; e < N; ++e) acc[e] += c * vv[u][e];
+            }
         }
         st16(z + r, acc);
     }
