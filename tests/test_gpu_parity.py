@@ -218,6 +218,48 @@ def test_phi_breakdown_tiny_system():
         assert rel(forced, ref) < 1e-12 and rel(adaptive, ref) < 1e-12
 
 
+def test_phi_breakdown_euler_fused_dots():
+    # 1 x 1 mesh, p = 1 Euler: 16 DOF + 2 augmented entries.  The Krylov space
+    # is exhausted before m_max, so the breakdown is detected by the step
+    # finish of the 2D path (dot pass in the linear operator's epilogue).
+    om, gm = euler_pair(1, 1, 1, m_max=30, L=(0.0, 1.0, 0.0, 1.0))
+    with gm:
+        x, y = om.nodes()
+        q = inputs.vortex(x * 10.0, y * 10.0, beta=2.0).reshape(-1)
+        R = om.rhs(q)
+        bs = [None, R, inputs.random_vector(om.n, 7) * 0.1]
+        c, dx = om.max_speed(q)
+        tau = 2.0 * dx / c
+        ref, st, forced, adaptive, gs = run_phi(om, gm, q, tau, bs, m_min=6, m_max=30)
+        dense = oracle.phi_dense(om.assemble_jvp(q), tau, bs)
+        assert st["breakdown"] >= 1 and gs["breakdown"] >= 1
+        assert rel(ref, dense) < 1e-12
+        assert rel(forced, ref) < 1e-12 and rel(adaptive, ref) < 1e-12
+
+
+def test_phi_forced_full_basis():
+    # one substep with the largest basis (m = 64): the step that finishes the
+    # last dimension writes basis slot 65 and Hessenberg column 64, the edges
+    # of the workspace
+    om, gm = euler_pair(4, 4, 3, m_max=64)
+    with gm:
+        x, y = om.nodes()
+        q = inputs.vortex(x, y, beta=3.0).reshape(-1)
+        R = om.rhs(q)
+        c, dx = om.max_speed(q)
+        tau = 3.0 * dx / c
+        bs = [None, R, inputs.random_vector(om.n, 11) * 0.1]
+        sched = [(64, tau, 1)]
+        ref = om.phi_krylov(q, tau, bs, forced=sched)
+        qt = dev(q)
+        bt = [None if b is None else dev(b) for b in bs]
+        w = torch.empty_like(qt)
+        st = B.make_stats()
+        gm.phi_krylov(qt, tau, bt, w, B.make_opts(forced=sched), st)
+        assert B.stats_dict(st)["krylov_iters"] == 65
+        assert rel(host(w), ref) < 1e-12, rel(host(w), ref)
+
+
 def test_phi_zero_inputs():
     om, gm = burgers_pair(8, 2)
     with gm:
