@@ -181,6 +181,17 @@ int expdg_phi_krylov(expdg_mesh *m, const void *qref, double tau, int p,
 int expdg_step(expdg_mesh *m, int scheme, double dt, double *q, double *q_prev, int have_prev,
                const expdg_krylov_opts *o, expdg_krylov_stats *s, void *hip_stream);
 
+/* nsteps >= 1 steps of size dt, the same as nsteps calls of expdg_step (the
+ * first with have_prev as given, every later one with the history the step
+ * before left in q_prev, which must then be non-NULL for EPI3), with bitwise
+ * the same results, but the host waits for the device only once, at the end.
+ * A forced substep schedule in o applies to every step.  The statistics
+ * accumulate over the steps.  On an error the call returns at once with the
+ * state as the failing step left it. */
+int expdg_integrate(expdg_mesh *m, int scheme, double dt, int nsteps, double *q, double *q_prev,
+                    int have_prev, const expdg_krylov_opts *o, expdg_krylov_stats *s,
+                    void *hip_stream);
+
 /* Exponential of a small dense matrix on the device with the same kernel the
  * Krylov controller uses for the projected Hessenberg matrix (diagonal Pade
  * (6,6) with scaling and squaring, Section 2.3).  A and E are row-major

@@ -110,6 +110,9 @@ _SIGS = {
                                    C.POINTER(KrylovStats), C.c_void_p]),
     "expdg_step": (C.c_int, [C.c_void_p, C.c_int, C.c_double, C.c_void_p, C.c_void_p, C.c_int,
                              C.POINTER(KrylovOpts), C.POINTER(KrylovStats), C.c_void_p]),
+    "expdg_integrate": (C.c_int, [C.c_void_p, C.c_int, C.c_double, C.c_int, C.c_void_p,
+                                  C.c_void_p, C.c_int, C.POINTER(KrylovOpts),
+                                  C.POINTER(KrylovStats), C.c_void_p]),
     "expdg_small_expm": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "expdg_profile_enable": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     "expdg_profile_read": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(KernelProfile)]),
@@ -243,6 +246,13 @@ def expdg_step(handle, scheme, dt, q, q_prev, have_prev, opts, stats=None, strea
                             _stream(stream)))
 
 
+def expdg_integrate(handle, scheme, dt, nsteps, q, q_prev, have_prev, opts, stats=None,
+                    stream=None):
+    _check(lib().expdg_integrate(handle, scheme, dt, int(nsteps), _ptr(q), _ptr(q_prev),
+                                 int(have_prev), C.byref(opts),
+                                 C.byref(stats) if stats is not None else None, _stream(stream)))
+
+
 def expdg_small_expm(n, A, E, stream=None):
     _check(lib().expdg_small_expm(n, _ptr(A), _ptr(E), _stream(stream)))
 
@@ -326,6 +336,11 @@ class Mesh:
              stream=None):
         expdg_step(self.handle, scheme, dt, q, q_prev, have_prev, opts or make_opts(), stats,
                    stream)
+
+    def integrate(self, scheme, dt, nsteps, q, q_prev=None, have_prev=False, opts=None,
+                  stats=None, stream=None):
+        expdg_integrate(self.handle, scheme, dt, nsteps, q, q_prev, have_prev,
+                        opts or make_opts(), stats, stream)
 
 
 # ---- solve server -------------------------------------------------------------

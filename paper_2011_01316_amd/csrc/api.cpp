@@ -643,6 +643,29 @@ extern "C" int expdg_step(expdg_mesh *m, int scheme, double dt, double *q, doubl
     return run_now(step_co<float>(x, m, scheme, dt, q, q_prev, have_prev, o, s));
 }
 
+extern "C" int expdg_integrate(expdg_mesh *m, int scheme, double dt, int nsteps, double *q,
+                               double *q_prev, int have_prev, const expdg_krylov_opts *o,
+                               expdg_krylov_stats *s, void *stream) {
+    if (!m || !q) return fail(EXPDG_EINVAL, "NULL argument");
+    if (nsteps < 1) return fail(EXPDG_EINVAL, "nsteps must be >= 1");
+    if (scheme != EXPDG_EPI2 && scheme != EXPDG_EPI3 && scheme != EXPDG_EXPRB32)
+        return fail(EXPDG_EINVAL, "unknown scheme %d", scheme);
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(EXPDG_EINVAL, "dt must be > 0");
+    if (scheme == EXPDG_EPI3 && (have_prev || nsteps > 1) && !q_prev)
+        return fail(EXPDG_EINVAL, "EPI3 over several steps needs q_prev");
+    if (q_prev == q) return fail(EXPDG_EINVAL, "q_prev must not alias q");
+    TRY(check_opts(m, o));
+    DeviceGuard g(m->d.device);
+    hipStream_t st = (hipStream_t)stream;
+    if (m->d.precision == EXPDG_FP64) {
+        DirectExec<double> x{st};
+        return run_now(
+            integrate_co<double>(x, m, scheme, dt, nsteps, q, q_prev, have_prev, o, s));
+    }
+    DirectExec<float> x{st};
+    return run_now(integrate_co<float>(x, m, scheme, dt, nsteps, q, q_prev, have_prev, o, s));
+}
+
 // ---------------------------------------------------------------------------
 
 extern "C" int expdg_small_expm(int n, const double *A, double *E, void *stream) {

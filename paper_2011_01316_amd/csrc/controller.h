@@ -352,7 +352,8 @@ Task<int> phi_co(X &x, expdg_mesh *m, const T *qref, double tau, int p, const T 
 // FP32_BULK.
 template <typename T, typename X>
 Task<int> step_co(X &x, expdg_mesh *m, int scheme, double dt, double *q, double *q_prev,
-                  int have_prev, const expdg_krylov_opts *o, expdg_krylov_stats *st) {
+                  int have_prev, const expdg_krylov_opts *o, expdg_krylov_stats *st,
+                  bool nested = false) {
     hipStream_t s = x.stream();
     const size_t n = m->n;
     constexpr bool bulk = !std::is_same<T, double>::value;
@@ -414,6 +415,20 @@ Task<int> step_co(X &x, expdg_mesh *m, int scheme, double dt, double *q, double 
         CO_AWAIT_TASK((phi_co<T, X>(x, m, qb, dt, 3, b, w2, o, st, &fpos, true, true)));
         if (q_prev) CO_HIPTRY(launch_copy(q, q_prev, n, s));
         CO_HIPTRY(launch_add_mixed<T>(q, m->q2, w2, n, s));
+    }
+    if (!nested) CO_TRY(co_await x.finish(m));
+    co_return EXPDG_OK;
+}
+
+// nsteps steps of step_co; the end of the whole run is the only wait for the
+// device.  Steps after the first have history when q_prev holds it.
+template <typename T, typename X>
+Task<int> integrate_co(X &x, expdg_mesh *m, int scheme, double dt, int nsteps, double *q,
+                       double *q_prev, int have_prev, const expdg_krylov_opts *o,
+                       expdg_krylov_stats *st) {
+    for (int k = 0; k < nsteps; ++k) {
+        const int hp = (k == 0) ? have_prev : (q_prev != nullptr ? 1 : 0);
+        CO_AWAIT_TASK((step_co<T, X>(x, m, scheme, dt, q, q_prev, hp, o, st, true)));
     }
     CO_TRY(co_await x.finish(m));
     co_return EXPDG_OK;

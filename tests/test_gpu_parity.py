@@ -260,6 +260,37 @@ def test_phi_forced_full_basis():
         assert rel(host(w), ref) < 1e-12, rel(host(w), ref)
 
 
+@pytest.mark.parametrize("scheme", [B.EPI2, B.EPI3, B.EXPRB32])
+def test_integrate_equals_steps(scheme):
+    # several steps in one call: bitwise the same as one call per step
+    om, gm = euler_pair(12, 12, 3, m_max=40)
+    with gm:
+        x, y = om.nodes()
+        q0 = dev(inputs.vortex(x, y, beta=4.0).reshape(-1))
+        c, dx = om.max_speed(host(q0))
+        dt = 5.0 * dx / c
+        opts = B.make_opts(1e-10, 8, 40)
+        qa, pa = q0.clone(), torch.empty_like(q0)
+        sa = B.make_stats()
+        for k in range(4):
+            gm.step(scheme, dt, qa, pa, k > 0, opts, sa)
+        qb, pb = q0.clone(), torch.empty_like(q0)
+        sb = B.make_stats()
+        gm.integrate(scheme, dt, 4, qb, pb, False, opts, sb)
+        assert torch.equal(qa, qb) and torch.equal(pa, pb)
+        da, db = B.stats_dict(sa), B.stats_dict(sb)
+        assert da["krylov_iters"] == db["krylov_iters"] and da["log"] == db["log"]
+
+
+def test_integrate_rejects_missing_history():
+    om, gm = euler_pair(4, 4, 2)
+    with gm:
+        q = dev(inputs.vortex(*om.nodes()).reshape(-1))
+        with pytest.raises(B.ExpdgError) as ei:
+            gm.integrate(B.EPI3, 0.01, 2, q)
+        assert ei.value.code == B.EINVAL
+
+
 def test_phi_zero_inputs():
     om, gm = burgers_pair(8, 2)
     with gm:
