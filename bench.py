@@ -77,8 +77,9 @@ def log(msg):
 
 
 class Case:
-    def __init__(self, B, inputs, torch, w, precision):
+    def __init__(self, B, inputs, torch, w, precision, scheme=None):
         self.B, self.torch, self.w = B, torch, w
+        self.scheme = B.EPI3 if scheme is None else scheme
         self.mesh = B.Mesh(B.EULER2D, w["nx"], w["p"], ny=w["ny"], x0=0.0, x1=10.0, y0=0.0,
                            y1=10.0, m_max=w["m_max"], precision=precision)
         self.x, self.y = self.mesh.nodes()
@@ -96,7 +97,8 @@ class Case:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         # the K steps in one library call (the host waits for the device at the end)
-        self.mesh.integrate(B.EPI3, self.dt, steps, self.q, self.qp, self.have, self.opts, st)
+        self.mesh.integrate(self.scheme, self.dt, steps, self.q, self.qp, self.have, self.opts,
+                            st)
         self.have = True
         torch.cuda.synchronize()
         self.nsteps += steps
@@ -154,6 +156,15 @@ def run_gpu(args):
     out["fp64"]["l2_rel_err_vs_exact"], q64 = c.exact_error(inputs, np)
     out["profile"] = c.profile(args.steps)
     c.mesh.close()
+
+    # the fourth-order EXPRB42 on the same workload (two phi evaluations per step)
+    c42 = Case(B, inputs, torch, C2, B.FP64, scheme=B.EXPRB42)
+    c42.run(args.warmup)
+    r42 = c42.run(args.steps)
+    r42["l2_rel_err_vs_exact"], _ = c42.exact_error(inputs, np)
+    log(f"exprb42 timed: {r42['ms_per_step']:.3f} ms/step")
+    out["exprb42"] = r42
+    c42.mesh.close()
 
     if not args.no_fp32:
         c32 = Case(B, inputs, torch, C2, B.FP32_BULK)
@@ -408,6 +419,11 @@ def main():
         "instrumented_ms_per_step": round(g["profile"]["ms_per_step"], 4),
         "l2_rel_err_vs_exact_vortex": f64["l2_rel_err_vs_exact"],
     }
+    e42 = g["exprb42"]
+    line["exprb42"] = dict(value=round(e42["value"], 1), unit=UNIT,
+                           ms_per_step=round(e42["ms_per_step"], 4),
+                           krylov_iters_per_step=e42["krylov_iters_per_step"],
+                           l2_rel_err_vs_exact_vortex=e42["l2_rel_err_vs_exact"])
     if "fp32" in g:
         f32 = g["fp32"]
         line["fp32_bulk"] = dict(value=round(f32["value"], 1), unit=UNIT,

@@ -12,8 +12,8 @@
  *   phi-function combinations sum_k tau^k phi_k(tau L) b_k by Krylov
  *   projection of the augmented matrix (Section 2.3,
  *   eq. linear_combination_of_phifunctions), and
- *   the exponential steppers EPI2 and EXPRB32 (footnotes of Section 5.1) and
- *   Tokman's EPI3 (cited in Section 1).
+ *   the exponential steppers EPI2 and EXPRB32 (footnotes of Section 5.1),
+ *   EXPRB42 (footnote of Section 5.2) and Tokman's EPI3 (cited in Section 1).
  *
  * Every compute step runs in HIP kernels on the device.  All entry points are
  * plain C: pointers and sizes, no C++ or framework types.
@@ -58,7 +58,7 @@ extern "C" {
 
 enum { EXPDG_BURGERS1D = 1, EXPDG_EULER2D = 2 };
 enum { EXPDG_FP64 = 0, EXPDG_FP32_BULK = 1 };
-enum { EXPDG_EPI2 = 2, EXPDG_EPI3 = 3, EXPDG_EXPRB32 = 32 };
+enum { EXPDG_EPI2 = 2, EXPDG_EPI3 = 3, EXPDG_EXPRB32 = 32, EXPDG_EXPRB42 = 42 };
 enum {
     EXPDG_OK = 0,
     EXPDG_EINVAL = -1,     /* invalid argument */
@@ -173,8 +173,8 @@ int expdg_phi_krylov(expdg_mesh *m, const void *qref, double tau, int p,
 
 /* ---- time step (footnotes of Section 5.1; EPI3 after Tokman) ------------ */
 
-/* One step of size dt of scheme EXPDG_EPI2, EXPDG_EPI3 or EXPDG_EXPRB32 on
- * the FP64 device state q (in/out).  EPI3 uses q_prev: when have_prev != 0
+/* One step of size dt of scheme EXPDG_EPI2, EXPDG_EPI3, EXPDG_EXPRB32 or
+ * EXPDG_EXPRB42 on the FP64 device state q (in/out).  EPI3 uses q_prev: when have_prev != 0
  * it holds q^{n-1} on entry; when have_prev == 0 the step is an EPI2 step.
  * If q_prev != NULL it receives q^n on return (for every scheme).  Returns
  * after completion. */

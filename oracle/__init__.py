@@ -28,7 +28,7 @@ SOURCES = ["refelem.cpp", "dg.cpp", "expm.cpp", "krylov.cpp", "steppers.cpp"]
 
 BURGERS1D = 1
 EULER2D = 2
-EPI2, EPI3, EXPRB32 = 2, 3, 32
+EPI2, EPI3, EXPRB32, EXPRB42 = 2, 3, 32, 42
 
 
 def build(verbose: bool = False) -> str:

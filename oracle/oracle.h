@@ -34,7 +34,7 @@ extern "C" {
 #endif
 
 enum { ORC_BURGERS1D = 1, ORC_EULER2D = 2 };
-enum { ORC_EPI2 = 2, ORC_EPI3 = 3, ORC_EXPRB32 = 32 };
+enum { ORC_EPI2 = 2, ORC_EPI3 = 3, ORC_EXPRB32 = 32, ORC_EXPRB42 = 42 };
 
 typedef struct {
     int equation;      /* ORC_BURGERS1D or ORC_EULER2D */

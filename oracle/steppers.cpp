@@ -9,6 +9,13 @@
 //       D = N(q2) - N(q^n) = R(q2) - R^n - L^n (q2 - q^n).
 //     As a phi combination: q^{n+1} = q2 + sum_k dt^k phi_k b_k with
 //     b_3 = 2 D / dt^2 and b_0 = b_1 = b_2 = 0.
+//   EXPRB42 (the fourth-order two-stage scheme, footnote of the comparison of
+//     exponential integrators in Section 5.2):
+//       q2      = q^n + (3/4) dt phi_1((3/4) dt L^n) R^n
+//       q^{n+1} = q^n + dt phi_1(dt L^n) R^n + (32/9) dt phi_3(dt L^n) D,
+//       D = N(q2) - N(q^n) = R(q2) - R^n - L^n (q2 - q^n),
+//     i.e. a combination with tau = 3 dt / 4, b_1 = R^n, then one with
+//     tau = dt, b_1 = R^n, b_3 = (32/9) D / dt^2 (b_0 = b_2 = 0).
 //   EPI3 (Tokman's two-step scheme, cited in Section 1; the paper names it
 //     but does not print it):
 //       q^{n+1} = q^n + dt phi_1(dt L^n) R^n + (2/3) dt phi_2(dt L^n) r,
@@ -30,7 +37,9 @@ extern "C" int orc_step(const orc_mesh *m, int scheme, double dt, double *q, dou
                         int have_prev, const orc_kopts *o, orc_kstats *s) {
     const int ni = orc_ndof(m);
     if (ni < 1 || !q || !(dt > 0.0) || !o) return -1;
-    if (scheme != ORC_EPI2 && scheme != ORC_EPI3 && scheme != ORC_EXPRB32) return -1;
+    if (scheme != ORC_EPI2 && scheme != ORC_EPI3 && scheme != ORC_EXPRB32 &&
+        scheme != ORC_EXPRB42)
+        return -1;
     const size_t n = (size_t)ni;
     std::vector<double> qn(q, q + n), Rn(n), w(n);
     std::function<void(const double *, double *)> Ln = [&](const double *x, double *y) {
@@ -62,6 +71,25 @@ extern "C" int orc_step(const orc_mesh *m, int scheme, double dt, double *q, dou
         rc = orc_phi_krylov_op(n, Ln, dt, 2, b, w.data(), o, s, &fpos);
         if (rc) return rc;
         for (size_t i = 0; i < n; ++i) qnew[i] = qn[i] + w[i];
+    } else if (scheme == ORC_EXPRB42) {
+        const double *b1[2] = {nullptr, Rn.data()};
+        rc = orc_phi_krylov_op(n, Ln, 0.75 * dt, 1, b1, w.data(), o, s, &fpos);
+        if (rc) return rc;
+        std::vector<double> q2(n), R2(n), d(n), Ld(n), b3(n), w2(n);
+        for (size_t i = 0; i < n; ++i) q2[i] = qn[i] + w[i];
+        rc = orc_rhs(m, q2.data(), R2.data());
+        if (rc) return rc;
+        for (size_t i = 0; i < n; ++i) d[i] = q2[i] - qn[i];
+        Ln(d.data(), Ld.data());
+        if (s) {
+            s->rhs_calls += 1;
+            s->jvps += 1;
+        }
+        for (size_t i = 0; i < n; ++i) b3[i] = (32.0 / 9.0) * (R2[i] - Rn[i] - Ld[i]) / (dt * dt);
+        const double *b[4] = {nullptr, Rn.data(), nullptr, b3.data()};
+        rc = orc_phi_krylov_op(n, Ln, dt, 3, b, w2.data(), o, s, &fpos);
+        if (rc) return rc;
+        for (size_t i = 0; i < n; ++i) qnew[i] = qn[i] + w2[i];
     } else {  // EXPRB32
         const double *b1[2] = {nullptr, Rn.data()};
         rc = orc_phi_krylov_op(n, Ln, dt, 1, b1, w.data(), o, s, &fpos);

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libexpdg.so")
 
 BURGERS1D, EULER2D = 1, 2
 FP64, FP32_BULK = 0, 1
-EPI2, EPI3, EXPRB32 = 2, 3, 32
+EPI2, EPI3, EXPRB32, EXPRB42 = 2, 3, 32, 42
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ENONFINITE = 0, -1, -2, -3, -4, -5
 
 

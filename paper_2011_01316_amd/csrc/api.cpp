@@ -626,7 +626,8 @@ extern "C" int expdg_step(expdg_mesh *m, int scheme, double dt, double *q, doubl
                           int have_prev, const expdg_krylov_opts *o, expdg_krylov_stats *s,
                           void *stream) {
     if (!m || !q) return fail(EXPDG_EINVAL, "NULL argument");
-    if (scheme != EXPDG_EPI2 && scheme != EXPDG_EPI3 && scheme != EXPDG_EXPRB32)
+    if (scheme != EXPDG_EPI2 && scheme != EXPDG_EPI3 && scheme != EXPDG_EXPRB32 &&
+        scheme != EXPDG_EXPRB42)
         return fail(EXPDG_EINVAL, "unknown scheme %d", scheme);
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(EXPDG_EINVAL, "dt must be > 0");
     if (scheme == EXPDG_EPI3 && have_prev && !q_prev)
@@ -648,7 +649,8 @@ extern "C" int expdg_integrate(expdg_mesh *m, int scheme, double dt, int nsteps,
                                expdg_krylov_stats *s, void *stream) {
     if (!m || !q) return fail(EXPDG_EINVAL, "NULL argument");
     if (nsteps < 1) return fail(EXPDG_EINVAL, "nsteps must be >= 1");
-    if (scheme != EXPDG_EPI2 && scheme != EXPDG_EPI3 && scheme != EXPDG_EXPRB32)
+    if (scheme != EXPDG_EPI2 && scheme != EXPDG_EPI3 && scheme != EXPDG_EXPRB32 &&
+        scheme != EXPDG_EXPRB42)
         return fail(EXPDG_EINVAL, "unknown scheme %d", scheme);
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(EXPDG_EINVAL, "dt must be > 0");
     if (scheme == EXPDG_EPI3 && (have_prev || nsteps > 1) && !q_prev)

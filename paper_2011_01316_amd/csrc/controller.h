@@ -396,6 +396,27 @@ Task<int> step_co(X &x, expdg_mesh *m, int scheme, double dt, double *q, double 
         const T *b[3] = {nullptr, Rn, d};
         CO_AWAIT_TASK((phi_co<T, X>(x, m, qb, dt, 2, b, w, o, st, &fpos, true, true)));
         CO_HIPTRY(launch_step_update<T>(q, q_prev, w, n, s));
+    } else if (scheme == EXPDG_EXPRB42) {
+        // q2 = q^n + (3/4) dt phi_1((3/4) dt L) R^n; q^{n+1} = q^n + dt phi_1(dt L) R^n
+        // + dt^3 phi_3(dt L) b_3 with b_3 = (32/9) D / dt^2, D = R(q2) - R^n - L (q2 - q^n)
+        const T *b1[2] = {nullptr, Rn};
+        CO_AWAIT_TASK((phi_co<T, X>(x, m, qb, 0.75 * dt, 1, b1, w, o, st, &fpos, true, true)));
+        CO_HIPTRY(launch_add_mixed<T>(m->q2, q, w, n, s));  // q2 = q^n + w1
+        T *q2b = nullptr;
+        CO_HIPTRY(view(m->q2, 2, &q2b));
+        CO_TRY(apply_op<T>(m, false, q2b, nullptr, Rp, s));  // R(q2)
+        CO_HIPTRY((launch_lincomb<T, T>(d, 1.0, q2b, -1.0, qb, 0.0, nullptr, n, s)));
+        CO_TRY(apply_op<T>(m, true, qb, d, Ld, s));
+        if (st) {
+            st->rhs_calls += 1;
+            st->jvps += 1;
+        }
+        const double c = (32.0 / 9.0) / (dt * dt);
+        CO_HIPTRY((launch_lincomb<T, T>(d, c, Rp, -c, Rn, -c, Ld, n, s)));  // b_3 into d
+        const T *b[4] = {nullptr, Rn, nullptr, d};
+        CO_AWAIT_TASK((phi_co<T, X>(x, m, qb, dt, 3, b, w2, o, st, &fpos, true, true)));
+        if (q_prev) CO_HIPTRY(launch_copy(q, q_prev, n, s));
+        CO_HIPTRY(launch_add_to<T>(q, w2, n, s));
     } else {  // EXPRB32
         const T *b1[2] = {nullptr, Rn};
         CO_AWAIT_TASK((phi_co<T, X>(x, m, qb, dt, 1, b1, w, o, st, &fpos, true, true)));

@@ -260,7 +260,7 @@ def test_phi_forced_full_basis():
         assert rel(host(w), ref) < 1e-12, rel(host(w), ref)
 
 
-@pytest.mark.parametrize("scheme", [B.EPI2, B.EPI3, B.EXPRB32])
+@pytest.mark.parametrize("scheme", [B.EPI2, B.EPI3, B.EXPRB32, B.EXPRB42])
 def test_integrate_equals_steps(scheme):
     # several steps in one call: bitwise the same as one call per step
     om, gm = euler_pair(12, 12, 3, m_max=40)
@@ -305,7 +305,7 @@ def test_phi_zero_inputs():
 
 
 # ------------------------------------------------------------------ steps
-@pytest.mark.parametrize("scheme", [B.EPI2, B.EPI3, B.EXPRB32])
+@pytest.mark.parametrize("scheme", [B.EPI2, B.EPI3, B.EXPRB32, B.EXPRB42])
 def test_step_burgers_c1(scheme):
     om, gm = burgers_pair(64, 2, m_max=30)
     with gm:
@@ -325,7 +325,7 @@ def test_step_burgers_c1(scheme):
             assert rel(host(qp), qp_o) < 1e-12, k
 
 
-@pytest.mark.parametrize("scheme", [B.EPI2, B.EPI3, B.EXPRB32])
+@pytest.mark.parametrize("scheme", [B.EPI2, B.EPI3, B.EXPRB32, B.EXPRB42])
 def test_step_vortex_small(scheme):
     # 12 x 12 quads: the beta = 5 vortex on 8 x 8 is under-resolved and the
     # collocation scheme (oracle included) blows up there

@@ -4,7 +4,8 @@
     the span of mass-free vectors on a periodic mesh);
   * observed temporal order against a tiny-step RK4 solution of the same
     semi-discretization: EPI2 -> 2, EPI3 and EXPRB32 -> 3 (paper Section 5.1,
-    Table expo-burgers-tconv-smooth gives orders 2 and 3 for EPI2/EXPRB32);
+    Table expo-burgers-tconv-smooth gives orders 2 and 3 for EPI2/EXPRB32),
+    EXPRB42 -> 4 (the fourth-order scheme of Section 5.2);
   * Burgers with u0 = 0.5 + sin x against the characteristic solution before
     the shock (t_b = 1): spatial order about p + 1;
   * Euler: exact translating isentropic vortex (Section 5.2): spatial order at
@@ -22,7 +23,8 @@ import oracle
 from paper_2011_01316_amd import inputs
 from tests import _textbook as tb
 
-SCHEMES = {"epi2": oracle.EPI2, "epi3": oracle.EPI3, "exprb32": oracle.EXPRB32}
+SCHEMES = {"epi2": oracle.EPI2, "epi3": oracle.EPI3, "exprb32": oracle.EXPRB32,
+           "exprb42": oracle.EXPRB42}
 
 
 def burgers_c1(K=64, p=2):
@@ -70,7 +72,8 @@ def test_mass_conservation(scheme):
 # Jacobian of R by a term proportional to the face jumps of q^n, O(h^{p+1}).
 # That defect adds an O(dt h^{p+1}) error, so the classical orders are pinned on
 # a resolved mesh where it is far below the temporal error.
-@pytest.mark.parametrize("scheme,order", [("epi2", 2.0), ("epi3", 3.0), ("exprb32", 3.0)])
+@pytest.mark.parametrize("scheme,order", [("epi2", 2.0), ("epi3", 3.0), ("exprb32", 3.0),
+                                          ("exprb42", 4.0)])
 def test_temporal_order_burgers(scheme, order):
     m, u, _ = burgers_c1(K=64, p=4)
     T = 0.5
