@@ -29,6 +29,8 @@ SOURCES = ["refelem.cpp", "dg.cpp", "expm.cpp", "krylov.cpp", "steppers.cpp"]
 BURGERS1D = 1
 EULER2D = 2
 EPI2, EPI3, EXPRB32, EXPRB42 = 2, 3, 32, 42
+FLUX_LF, FLUX_EF = 0, 1
+BC_PERIODIC, BC_DIRICHLET = 0, 1
 
 
 def build(verbose: bool = False) -> str:
@@ -47,7 +49,9 @@ def build(verbose: bool = False) -> str:
 class _Mesh(C.Structure):
     _fields_ = [("equation", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("p", C.c_int),
                 ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
-                ("gamma", C.c_double)]
+                ("gamma", C.c_double), ("kappa", C.c_double), ("flux", C.c_int),
+                ("sigma", C.c_double), ("beta", C.c_double), ("bc", C.c_int),
+                ("source", C.POINTER(C.c_double))]
 
 
 class Substep(C.Structure):
@@ -120,6 +124,7 @@ def _declare(L):
     L.orc_mass.argtypes = [mp, dp]
     L.orc_rhs.argtypes = [mp, dp, dp]
     L.orc_jvp.argtypes = [mp, dp, dp, dp]
+    L.orc_gradient.argtypes = [mp, dp, dp]
     L.orc_jvp_complex_step.argtypes = [mp, dp, dp, C.c_double, dp]
     L.orc_assemble_jvp.argtypes = [mp, dp, dp]
     L.orc_max_speed.argtypes = [mp, dp, dp, dp]
@@ -147,19 +152,33 @@ def _check(rc: int, what: str):
 
 
 class Mesh:
-    """Uniform periodic mesh: Burgers 1D (nx intervals) or Euler 2D (nx x ny quads)."""
+    """Uniform mesh: Burgers 1D (nx intervals) or Euler 2D (nx x ny periodic quads).
+
+    Burgers options (Section 3.1): viscosity kappa, nonlinear flux FLUX_LF or
+    FLUX_EF (jump coefficient sigma), diffusion fluxes beta (0 central, 0.5
+    LDG), boundaries BC_PERIODIC or BC_DIRICHLET (u = 0 at both ends), and a
+    nodal source added to the residual.
+    """
 
     def __init__(self, equation: int, nx: int, p: int, ny: int = 1, x0: float = 0.0,
-                 x1: float = 1.0, y0: float = 0.0, y1: float = 1.0, gamma: float = 1.4):
+                 x1: float = 1.0, y0: float = 0.0, y1: float = 1.0, gamma: float = 1.4,
+                 kappa: float = 0.0, flux: int = FLUX_LF, sigma: float = 0.0,
+                 beta: float = 0.0, bc: int = BC_PERIODIC, source=None):
         self.equation, self.nx, self.ny, self.p = equation, nx, ny, p
         self.x0, self.x1, self.y0, self.y1, self.gamma = x0, x1, y0, y1, gamma
-        self._m = _Mesh(equation, nx, ny, p, x0, x1, y0, y1, gamma)
+        self.kappa, self.flux, self.sigma, self.beta, self.bc = kappa, flux, sigma, beta, bc
+        self.source = None if source is None else np.ascontiguousarray(source, dtype=np.float64)
+        sp = _dp(self.source) if self.source is not None else C.POINTER(C.c_double)()
+        self._m = _Mesh(equation, nx, ny, p, x0, x1, y0, y1, gamma, kappa, flux, sigma, beta,
+                        bc, sp)
         self.nvar = 1 if equation == BURGERS1D else 4
         self.Np = (p + 1) if equation == BURGERS1D else (p + 1) ** 2
         self.K = nx * ny
         self.n = lib().orc_ndof(C.byref(self._m))
         if self.n < 0:
             raise ValueError("invalid oracle mesh")
+        if self.source is not None and self.source.size != self.n:
+            raise ValueError("source must have one entry per degree of freedom")
 
     # geometry ------------------------------------------------------------
     def nodes(self):
@@ -191,6 +210,13 @@ class Mesh:
         w = np.zeros(self.n)
         _check(lib().orc_jvp(C.byref(self._m), _dp(qref), _dp(v), _dp(w)), "jvp")
         return w
+
+    def gradient(self, u):
+        """Auxiliary variable q(u) of viscous Burgers (eq. gov-burgers1d-gradu)."""
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        q = np.zeros(self.n)
+        _check(lib().orc_gradient(C.byref(self._m), _dp(u), _dp(q)), "gradient")
+        return q
 
     def jvp_complex_step(self, qref, v, h=1e-30):
         qref = np.ascontiguousarray(qref, dtype=np.float64)

@@ -21,7 +21,30 @@
 //
 // L(q~) v is the same operator with F replaced by F_L(v) = A(q~) v and the
 // dissipation lambda evaluated at q~ (the linear numerical flux (u~ u)* and
-// (A~ q)* of Sections 3.1 and 3.2).  Periodic boundaries everywhere.
+// (A~ q)* of Sections 3.1 and 3.2).
+//
+// Viscous Burgers (Section 3.1, eqs. gov-burgers1d-gradu, BurgerL, BurgerN):
+// the flux is u^2/2 - kappa q with the auxiliary q = u_x, so
+//   R(u) = R_conv(u) + kappa Diff(u) + s,   L(u~) v = L_conv(u~; v) + kappa Diff(v),
+// where Diff is linear (the same in R and L, as the split puts all of the
+// diffusion into L).  In strong form with the LGL lift:
+//   q_i      = (2/h) sum_l D_il u_l + (2/h)(1/w_end) n (u** - u^-)   (end nodes)
+//   Diff_i   = (2/h) sum_l D_il q_l + (2/h)(1/w_end) n (q** - q^-)
+// with, on a face between a left element L and a right element R and the
+// jump [[v]] = v_L - v_R (the paper's jump, a vector along x in 1D):
+//   u** = {{u}} - beta [[u]],   q** = {{q}} + beta [[q]]
+// (beta = 0: the central fluxes of Section 3.1; beta = 1/2: the LDG fluxes of
+// Appendix A, i.e. u** = u_R and q** = q_L).  The nonlinear flux (u^2/2)* is
+// Lax-Friedrichs or the entropy flux
+//   (u^2/2)* . n^- = n^- (u^-^2 + u^- u^+ + u^+^2)/6 + (sigma/h)(u^- - u^+),
+// i.e. (1/3)({{u^2/2}} + {{u}}^2) + (sigma/h)[[u]] of Section 3.1, with h read
+// as the half-width h_e/2 of the element (the Jacobian of the map from
+// [-1, 1]); the linear flux (u~ u)* stays Lax-Friedrichs with
+// lambda = max|u~^+-|.
+//
+// Boundaries: periodic, or (Burgers) zero Dirichlet at both ends following
+// the footnote at the start of Section 6: the exterior state is u^+ = 0 for
+// (u~ u)* and (u^2/2)*, u** = 0 and q** = q^-.
 #include "oracle.h"
 
 #include <cmath>
@@ -39,6 +62,9 @@ using cplx = std::complex<double>;
 struct Geo {
     int eq, nx, ny, p, n1, Np, K, nvar, dim;
     double hx, hy, gamma, x0, y0;
+    double kappa, sigma, beta;
+    int flux, bc;
+    const double *src;
     std::vector<double> xi, w, D;
 };
 
@@ -49,6 +75,12 @@ bool make_geo(const orc_mesh *m, Geo *g) {
     if (m->equation == ORC_BURGERS1D && m->ny != 1) return false;
     if (!(m->x1 > m->x0)) return false;
     if (m->equation == ORC_EULER2D && (!(m->y1 > m->y0) || !(m->gamma > 1.0))) return false;
+    if (!(m->kappa >= 0.0) || !(m->sigma >= 0.0) || !(std::fabs(m->beta) <= 0.5)) return false;
+    if (m->flux != ORC_FLUX_LF && m->flux != ORC_FLUX_EF) return false;
+    if (m->bc != ORC_BC_PERIODIC && m->bc != ORC_BC_DIRICHLET) return false;
+    if (m->equation == ORC_EULER2D &&
+        (m->kappa != 0.0 || m->flux != ORC_FLUX_LF || m->bc != ORC_BC_PERIODIC || m->source))
+        return false;
     g->eq = m->equation;
     g->nx = m->nx;
     g->ny = m->ny;
@@ -63,16 +95,23 @@ bool make_geo(const orc_mesh *m, Geo *g) {
     g->x0 = m->x0;
     g->y0 = m->y0;
     g->gamma = m->gamma;
+    g->kappa = m->kappa;
+    g->sigma = m->sigma;
+    g->beta = m->beta;
+    g->flux = m->flux;
+    g->bc = m->bc;
+    g->src = m->source;
     g->xi.resize(g->n1);
     g->w.resize(g->n1);
     g->D.resize(g->n1 * g->n1);
     return orc_lgl(g->p, g->xi.data(), g->w.data(), g->D.data()) == 0;
 }
 
-// Periodic neighbour of element e across its face in direction dir
-// (0 = x, 1 = y) on side s (-1 = left/bottom, +1 = right/top).
+// Neighbour of element e across its face in direction dir (0 = x, 1 = y) on
+// side s (-1 = left/bottom, +1 = right/top); -1 at a Dirichlet end.
 int neighbour(const Geo &g, int e, int dir, int s) {
     int ex = e % g.nx, ey = e / g.nx;
+    if (g.bc == ORC_BC_DIRICHLET && dir == 0 && (ex + s < 0 || ex + s >= g.nx)) return -1;
     if (dir == 0)
         ex = (ex + s + g.nx) % g.nx;
     else
@@ -157,8 +196,10 @@ double wave_speed(const Geo &g, const double *q, int dir) {
 // out = DG operator applied to the field u with
 //   node_flux(e, n, dir, f): flux at a node (volume and face traces),
 //   lam_ref: real state whose traces give the LF wave speed lambda.
+//   entropy: the nonlinear Burgers face flux is EF instead of LF.
 template <class T, class FluxAt>
-void dg_apply(const Geo &g, const T *u, const double *lam_ref, FluxAt node_flux, T *out) {
+void dg_apply(const Geo &g, const T *u, const double *lam_ref, FluxAt node_flux, T *out,
+              bool entropy = false) {
     const int n1 = g.n1, Np = g.Np, nv = g.nvar;
     const double h[2] = {g.hx, g.hy};
 #pragma omp parallel for schedule(static)
@@ -193,17 +234,27 @@ void dg_apply(const Geo &g, const T *u, const double *lam_ref, FluxAt node_flux,
                         const int nn = (dir == 0) ? node(g, am, jj) : node(g, i, am);
                         T fm[4], fp[4], um[4], up[4];
                         for (int c = 0; c < nv; ++c) fm[c] = F[((size_t)dir * Np + n) * nv + c];
-                        node_flux(en, nn, dir, fp);
                         load(g, u, e, n, um);
-                        load(g, u, en, nn, up);
                         double qm[4], qp[4];
                         load(g, lam_ref, e, n, qm);
-                        load(g, lam_ref, en, nn, qp);
+                        if (en >= 0) {
+                            node_flux(en, nn, dir, fp);
+                            load(g, u, en, nn, up);
+                            load(g, lam_ref, en, nn, qp);
+                        } else {  // Dirichlet end (Burgers): exterior state 0, flux 0
+                            fp[0] = T(0.0);
+                            up[0] = T(0.0);
+                            qp[0] = 0.0;
+                        }
                         const double lam =
                             std::fmax(wave_speed(g, qm, dir), wave_speed(g, qp, dir));
                         const double sn = (double)s;  // n^- . e_dir
                         for (int c = 0; c < nv; ++c) {
                             T fstar_n = 0.5 * sn * (fm[c] + fp[c]) + 0.5 * lam * (um[c] - up[c]);
+                            if (entropy)
+                                fstar_n = sn * (um[0] * um[0] + um[0] * up[0] + up[0] * up[0]) /
+                                              6.0 +
+                                          (2.0 * g.sigma / g.hx) * (um[0] - up[0]);
                             T f_n = sn * fm[c];
                             res[c] -= (2.0 / h[dir]) / g.w[a] * (fstar_n - f_n);
                         }
@@ -215,6 +266,72 @@ void dg_apply(const Geo &g, const T *u, const double *lam_ref, FluxAt node_flux,
     }
 }
 
+// ---- viscous Burgers: auxiliary gradient and diffusion --------------------
+
+// Face values of the element e at its end on side s (-1 left, +1 right):
+// the left and right elements of that face (-1 beyond a Dirichlet end).
+inline void face_sides(const Geo &g, int e, int s, int *eL, int *eR) {
+    const int en = neighbour(g, e, 0, s);
+    *eL = (s < 0) ? en : e;
+    *eR = (s < 0) ? e : en;
+}
+
+// q(u) of eq. gov-burgers1d-gradu (strong form, see the header).
+template <class T>
+void aux_gradient(const Geo &g, const T *u, T *q) {
+    const int n1 = g.n1, p = g.p;
+    const double rh = 2.0 / g.hx;
+#pragma omp parallel for schedule(static)
+    for (int e = 0; e < g.K; ++e) {
+        for (int i = 0; i < n1; ++i) {
+            T acc = T(0.0);
+            for (int l = 0; l < n1; ++l) acc += rh * g.D[i * n1 + l] * u[(size_t)e * n1 + l];
+            for (int s = -1; s <= 1; s += 2) {
+                if ((s == -1 && i != 0) || (s == 1 && i != p)) continue;
+                int eL, eR;
+                face_sides(g, e, s, &eL, &eR);
+                T ustar = T(0.0);  // Dirichlet end: u** = 0
+                if (eL >= 0 && eR >= 0) {
+                    const T uL = u[(size_t)eL * n1 + p], uR = u[(size_t)eR * n1];
+                    ustar = 0.5 * (uL + uR) - g.beta * (uL - uR);
+                }
+                acc += rh / g.w[i] * (double)s * (ustar - u[(size_t)e * n1 + i]);
+            }
+            q[(size_t)e * n1 + i] = acc;
+        }
+    }
+}
+
+// out += kappa Diff(u), the diffusion part of eq. BurgerL (see the header).
+template <class T>
+void add_diffusion(const Geo &g, const T *u, T *out) {
+    if (g.kappa == 0.0) return;
+    const int n1 = g.n1, p = g.p;
+    const double rh = 2.0 / g.hx;
+    std::vector<T> q((size_t)g.K * n1);
+    aux_gradient(g, u, q.data());
+#pragma omp parallel for schedule(static)
+    for (int e = 0; e < g.K; ++e) {
+        for (int i = 0; i < n1; ++i) {
+            T acc = T(0.0);
+            for (int l = 0; l < n1; ++l) acc += rh * g.D[i * n1 + l] * q[(size_t)e * n1 + l];
+            for (int s = -1; s <= 1; s += 2) {
+                if ((s == -1 && i != 0) || (s == 1 && i != p)) continue;
+                int eL, eR;
+                face_sides(g, e, s, &eL, &eR);
+                const T qm = q[(size_t)e * n1 + i];
+                T qstar = qm;  // Dirichlet end: q** = q^-
+                if (eL >= 0 && eR >= 0) {
+                    const T qL = q[(size_t)eL * n1 + p], qR = q[(size_t)eR * n1];
+                    qstar = 0.5 * (qL + qR) + g.beta * (qL - qR);
+                }
+                acc += rh / g.w[i] * (double)s * (qstar - qm);
+            }
+            out[(size_t)e * n1 + i] += g.kappa * acc;
+        }
+    }
+}
+
 template <class T>
 void residual_frozen(const Geo &g, const T *q, const double *lam_ref, T *r) {
     auto fl = [&](int e, int n, int dir, T *f) {
@@ -222,7 +339,8 @@ void residual_frozen(const Geo &g, const T *q, const double *lam_ref, T *r) {
         load(g, q, e, n, qn);
         flux(g, qn, dir, f);
     };
-    dg_apply(g, q, lam_ref, fl, r);
+    dg_apply(g, q, lam_ref, fl, r, g.eq == ORC_BURGERS1D && g.flux == ORC_FLUX_EF);
+    if (g.eq == ORC_BURGERS1D) add_diffusion(g, q, r);
 }
 
 void linear_op(const Geo &g, const double *qt, const double *v, double *w) {
@@ -233,6 +351,7 @@ void linear_op(const Geo &g, const double *qt, const double *v, double *w) {
         lin_flux(g, qn, vn, dir, f);
     };
     dg_apply(g, v, qt, fl, w);
+    if (g.eq == ORC_BURGERS1D) add_diffusion(g, v, w);
 }
 
 }  // namespace
@@ -279,6 +398,17 @@ int orc_rhs(const orc_mesh *m, const double *q, double *r) {
     Geo g;
     if (!make_geo(m, &g) || !q || !r) return -1;
     residual_frozen<double>(g, q, q, r);
+    if (g.src) {
+        const size_t n = (size_t)g.nvar * g.K * g.Np;
+        for (size_t i = 0; i < n; ++i) r[i] += g.src[i];
+    }
+    return 0;
+}
+
+int orc_gradient(const orc_mesh *m, const double *u, double *q) {
+    Geo g;
+    if (!make_geo(m, &g) || g.eq != ORC_BURGERS1D || !u || !q) return -1;
+    aux_gradient<double>(g, u, q);
     return 0;
 }
 

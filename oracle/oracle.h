@@ -17,8 +17,13 @@
  *   - phi-function linear combinations sum_k tau^k phi_k(tau A) b_k
  *     (eq. linear_combination_of_phifunctions) by Krylov projection of the
  *     augmented matrix (Section 2.3), and densely for small systems
- *   - the exponential steppers EPI2, EXPRB32 (footnotes in Section 5.1) and
- *     EPI3 (Tokman's two-step scheme, cited in Section 1)
+ *   - viscous Burgers (Section 3.1, eqs. gov-burgers1d, Burger): auxiliary
+ *     q = u_x with central or LDG (Appendix A) diffusion fluxes, the entropy
+ *     flux (EF) or Lax-Friedrichs for (u^2/2)*, zero Dirichlet ends as in the
+ *     footnote at the start of Section 6, and a nodal source term
+ *   - the exponential steppers EPI2, EXPRB32 (footnotes in Section 5.1),
+ *     EXPRB42 (footnote in Section 5.2) and EPI3 (Tokman's two-step scheme,
+ *     cited in Section 1)
  *
  * Layout of every nodal vector: idx = (c*K + e)*Np + n, c = variable,
  * e = ey*nx + ex, n = j*(p+1) + i with i along x.  Burgers has one variable;
@@ -35,13 +40,24 @@ extern "C" {
 
 enum { ORC_BURGERS1D = 1, ORC_EULER2D = 2 };
 enum { ORC_EPI2 = 2, ORC_EPI3 = 3, ORC_EXPRB32 = 32, ORC_EXPRB42 = 42 };
+enum { ORC_FLUX_LF = 0, ORC_FLUX_EF = 1 };          /* Burgers (u^2/2)* */
+enum { ORC_BC_PERIODIC = 0, ORC_BC_DIRICHLET = 1 };  /* Burgers: u = 0 at x0, x1 */
 
+/* The fields after gamma describe viscous Burgers (Section 3.1); zero-filled
+ * they give the inviscid periodic Lax-Friedrichs problem.  Euler requires
+ * kappa = 0, flux LF, periodic and no source. */
 typedef struct {
     int equation;      /* ORC_BURGERS1D or ORC_EULER2D */
     int nx, ny;        /* elements per direction; ny must be 1 for Burgers */
     int p;             /* polynomial degree, 1..15 */
     double x0, x1, y0, y1;
     double gamma;      /* ratio of specific heats (Euler only) */
+    double kappa;      /* viscosity, >= 0 */
+    int flux;          /* ORC_FLUX_LF or ORC_FLUX_EF for the nonlinear flux */
+    double sigma;      /* EF jump coefficient: the flux adds (sigma/h)[[u]], h = h_e/2 */
+    double beta;       /* diffusion fluxes: 0 central, 1/2 LDG (Appendix A) */
+    int bc;            /* ORC_BC_PERIODIC or ORC_BC_DIRICHLET */
+    const double *source; /* NULL or a nodal source added to R (not to L) */
 } orc_mesh;
 
 /* One accepted Krylov substep: basis size m, substep length dtau, and
@@ -82,6 +98,9 @@ int orc_rhs(const orc_mesh *m, const double *q, double *r);
 /* L(qref) v: DG operator of the linear flux A(qref) v with dissipation
  * frozen at qref. */
 int orc_jvp(const orc_mesh *m, const double *qref, const double *v, double *w);
+/* Auxiliary variable q(u) of the viscous Burgers problem (eq.
+ * gov-burgers1d-gradu); Burgers only. */
+int orc_gradient(const orc_mesh *m, const double *u, double *q);
 /* Complex-step derivative Im R_frozen(qref + i h v) / h with the flux
  * dissipation evaluated at qref (used to pin orc_jvp). */
 int orc_jvp_complex_step(const orc_mesh *m, const double *qref, const double *v,

@@ -12,6 +12,9 @@ Conservative Euler variables are returned stacked as an array of shape
 Workloads (paper, Section 5):
   * Burgers: u0 = 0.5 + sin(x + theta) on [0, 2 pi] (smooth, pre-shock until
     t = 1 for theta = 0).
+  * Viscous Burgers on [0, 1] with u = 0 at both ends (Section 5.1): the
+    time-independent manufactured solution u = sin(x^2) x (x - 1) with its
+    source term, and the smooth initial state sin^3(2 pi x) (1 - x)^{3/2}.
   * Isentropic vortex translating in a uniform mean flow (Section 5.2, after
     Zhou & Wei): velocity perturbation (lambda / 2 pi) e^{alpha (1 - r^2)/2}
     (-y~, x~), temperature T = T_inf - (lambda/2 pi)^2 e^{alpha (1-r^2)} /
@@ -32,6 +35,23 @@ import numpy as np
 def burgers_ic(x: np.ndarray, theta: float = 0.0) -> np.ndarray:
     """u0(x) = 0.5 + sin(x + theta)."""
     return 0.5 + np.sin(np.asarray(x, dtype=np.float64) + theta)
+
+
+def burgers_mms(x: np.ndarray, kappa: float):
+    """Manufactured steady solution u = sin(x^2) x (x - 1) of u_t + (u^2/2)_x =
+    kappa u_xx + s, and its source s = u u_x - kappa u_xx.  Returns (u, s)."""
+    x = np.asarray(x, dtype=np.float64)
+    sn, cs = np.sin(x * x), np.cos(x * x)
+    u = sn * x * (x - 1.0)
+    ux = (2.0 * x - 1.0) * sn + 2.0 * x * x * (x - 1.0) * cs
+    uxx = (2.0 + 4.0 * x ** 3 - 4.0 * x ** 4) * sn + (10.0 * x * x - 6.0 * x) * cs
+    return u, u * ux - kappa * uxx
+
+
+def burgers_smooth(x: np.ndarray) -> np.ndarray:
+    """Smooth viscous Burgers initial state sin^3(2 pi x) (1 - x)^{3/2} on [0, 1]."""
+    x = np.asarray(x, dtype=np.float64)
+    return np.sin(2.0 * math.pi * x) ** 3 * np.clip(1.0 - x, 0.0, None) ** 1.5
 
 
 def primitive_to_conservative(rho, u, v, p, gamma=1.4) -> np.ndarray:

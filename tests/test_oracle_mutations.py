@@ -5,7 +5,8 @@ Each mutation is a one-line edit of the kind a careful reading could miss: a
 flipped dissipation sign, min instead of max in the wave speed, a wrong
 Jacobian entry, a wrong lifting factor, a dropped pressure term, a wrong Pade
 coefficient, a broken augmented shift or scaling, a wrong stepper
-coefficient, a wrong quadrature weight.
+coefficient, a wrong quadrature weight, a wrong entropy-flux coefficient, a
+flipped LDG switch, a wrong Dirichlet trace.
 """
 import os
 import shutil
@@ -17,6 +18,7 @@ from tests import test_oracle_dg as dg
 from tests import test_oracle_phi as phi
 from tests import test_oracle_refelem as refelem
 from tests import test_oracle_steppers as steppers
+from tests import test_oracle_viscous as viscous
 
 MUTATIONS = {
     "dissipation_sign": ("dg.cpp", "0.5 * lam * (um[c] - up[c])", "0.5 * lam * (up[c] - um[c])",
@@ -41,6 +43,14 @@ MUTATIONS = {
                    lambda: steppers.test_temporal_order_burgers("epi3", 3.0)),
     "exprb32_coeff": ("steppers.cpp", "b3[i] = 2.0 * (R2[i]", "b3[i] = 1.0 * (R2[i]",
                       lambda: steppers.test_temporal_order_burgers("exprb32", 3.0)),
+    "ef_coeff": ("dg.cpp", "up[0] * up[0]) /", "up[0] * up[0] * 2.0) /",
+                 lambda: viscous.test_entropy_flux_piecewise_constant(0.0)),
+    "ldg_qstar_sign": ("dg.cpp", "qstar = 0.5 * (qL + qR) + g.beta * (qL - qR);",
+                       "qstar = 0.5 * (qL + qR) - g.beta * (qL - qR);",
+                       lambda: viscous.test_diffusion_energy_identity(0.5, oracle.BC_PERIODIC, 2)),
+    "dirichlet_ustar": ("dg.cpp", "T ustar = T(0.0);  // Dirichlet end: u** = 0",
+                        "T ustar = u[(size_t)e * n1 + i];",
+                        lambda: viscous.test_diffusion_energy_identity(0.0, oracle.BC_DIRICHLET, 2)),
     "lgl_weight": ("refelem.cpp", "w[i] = 2.0 / (p * (p + 1.0) * P * P);",
                    "w[i] = 2.0 / ((p + 1.0) * (p + 1.0) * P * P);",
                    lambda: refelem.test_quadrature_exactness(3)),
