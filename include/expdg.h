@@ -8,7 +8,10 @@
  *   q_t + div F(q) = 0 on a uniform periodic mesh (Section 2.2, eq. pde),
  *   DG semi-discretization dq/dt = R(q) = L q + N(q) with LGL collocation and
  *   Lax-Friedrichs / Rusanov numerical fluxes (Section 2.2,
- *   eq. EXPO-SemiDiscretizedForm_ode; Sections 3.1 and 3.2),
+ *   eq. EXPO-SemiDiscretizedForm_ode; Sections 3.1 and 3.2), and viscous
+ *   Burgers u_t + (u^2/2)_x = kappa u_xx + s (Section 3.1, eqs.
+ *   gov-burgers1d-gradu and Burger) with central or LDG diffusion fluxes
+ *   (Appendix A), the entropy flux, and zero Dirichlet ends,
  *   phi-function combinations sum_k tau^k phi_k(tau L) b_k by Krylov
  *   projection of the augmented matrix (Section 2.3,
  *   eq. linear_combination_of_phifunctions), and
@@ -59,6 +62,8 @@ extern "C" {
 enum { EXPDG_BURGERS1D = 1, EXPDG_EULER2D = 2 };
 enum { EXPDG_FP64 = 0, EXPDG_FP32_BULK = 1 };
 enum { EXPDG_EPI2 = 2, EXPDG_EPI3 = 3, EXPDG_EXPRB32 = 32, EXPDG_EXPRB42 = 42 };
+enum { EXPDG_FLUX_LF = 0, EXPDG_FLUX_EF = 1 };
+enum { EXPDG_BC_PERIODIC = 0, EXPDG_BC_DIRICHLET = 1 };
 enum {
     EXPDG_OK = 0,
     EXPDG_EINVAL = -1,     /* invalid argument */
@@ -68,10 +73,28 @@ enum {
     EXPDG_ENONFINITE = -5  /* non-finite norm, Hessenberg entry or state */
 };
 
-/* Mesh description.  Uniform periodic mesh: nx intervals on [x0, x1]
- * (Burgers, ny = 1) or nx x ny quadrilaterals on [x0, x1] x [y0, y1]
- * (Euler).  p is the LGL degree (1..6).  m_max bounds the Krylov basis
- * (1..64).  gamma is used by Euler only. */
+/* Mesh description.  Uniform mesh: nx intervals on [x0, x1] (Burgers,
+ * ny = 1) or nx x ny periodic quadrilaterals on [x0, x1] x [y0, y1] (Euler).
+ * p is the LGL degree (1..6).  m_max bounds the Krylov basis (1..64).  gamma
+ * is used by Euler only.
+ *
+ * Burgers options (Section 3.1; all zero = inviscid, periodic,
+ * Lax-Friedrichs; Euler requires them zero):
+ *   kappa  viscosity >= 0.  With kappa > 0 the flux is u^2/2 - kappa q with
+ *          the auxiliary q = u_x of eq. gov-burgers1d-gradu, and all of the
+ *          diffusion belongs to the linear operator L (eq. BurgerL);
+ *   flux   EXPDG_FLUX_LF or EXPDG_FLUX_EF: the numerical flux (u^2/2)* of the
+ *          residual; EF is (1/3)({{u^2/2}} + {{u}}^2) + (sigma/h)[[u]] with h
+ *          the half-width h_e/2 of an element.  The linear flux (u~ u)* is
+ *          always Lax-Friedrichs;
+ *   beta   diffusion fluxes u** = {{u}} - beta [[u]], q** = {{q}} + beta [[q]]
+ *          with [[v]] = v_left - v_right: 0 central (Section 3.1), 1/2 LDG
+ *          (Appendix A); |beta| <= 1/2;
+ *   bc     EXPDG_BC_PERIODIC, or EXPDG_BC_DIRICHLET: u = 0 at x0 and x1, taken
+ *          as in the footnote at the start of Section 6 (exterior state 0 in
+ *          the convective fluxes, u** = 0, q** = q^-);
+ *   has_source  nonzero: the mesh holds a source vector s added to R (not to
+ *          L), set by expdg_mesh_set_source (zero until then). */
 typedef struct {
     int equation;   /* EXPDG_BURGERS1D or EXPDG_EULER2D */
     int nx, ny;
@@ -81,6 +104,12 @@ typedef struct {
     double x0, x1, y0, y1;
     double gamma;
     int m_max;
+    double kappa;
+    int flux;
+    double sigma;
+    double beta;
+    int bc;
+    int has_source;
 } expdg_mesh_desc;
 
 typedef struct expdg_mesh expdg_mesh; /* opaque, library-owned */
@@ -138,6 +167,12 @@ size_t expdg_workspace_bytes(const expdg_mesh_desc *desc);
 int expdg_mesh_get_info(const expdg_mesh *m, expdg_mesh_info *info);
 /* Physical node coordinates, host arrays of K*Np doubles (y may be NULL). */
 int expdg_mesh_nodes(const expdg_mesh *m, double *x, double *y);
+/* Copies the source term of a mesh created with has_source: s is a device
+ * array of ndof doubles (the nodal values of the source of Section 5.1's
+ * manufactured solutions), stored in the mesh in its bulk precision.
+ * Asynchronous on hip_stream; s may be reused once the stream has passed the
+ * copy.  EXPDG_EINVAL without has_source or with s == NULL. */
+int expdg_mesh_set_source(expdg_mesh *m, const double *s, void *hip_stream);
 /* The library's LGL reference element: nodes, weights, and the
  * differentiation matrix D[i*(p+1)+j] = l_j'(xi_i); host arrays. */
 int expdg_lgl(int p, double *xi, double *w, double *D);

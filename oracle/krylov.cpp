@@ -256,14 +256,20 @@ int orc_phi_krylov_op(size_t n, const Op &A, double tau, int p, const double *co
         if (st) st->err_est = err;
         if (forced) *fpos += 1;
         if (sub_last) break;
+        const double rem = tau - t_done;
+        if (!(rem > 1e-15 * tau)) {
+            // the accepted substeps already cover [0, tau]: the last one ends
+            // the evaluation, and the log says so (a replay stops there too)
+            if (st && st->log && st->log_len >= 1 && st->log_len <= st->log_cap)
+                st->log[st->log_len - 1].last = 1;
+            break;
+        }
         if (forced) continue;
 
         const double ratio = (err > 0.0) ? tol_abs * dt_sub / tau / err : 0.0;
         double fac = (err > 0.0) ? 0.9 * std::pow(ratio, 1.0 / j_acc) : 5.0;
         fac = std::min(5.0, std::max(1.0, fac));
         const double cand = rnd2(dt_sub * fac);
-        const double rem = tau - t_done;
-        if (!(rem > 1e-15 * tau)) break;
         if (cand >= rem) {
             dtau = rem;
             reaches_end = true;

@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(HERE, "libexpdg.so")
 BURGERS1D, EULER2D = 1, 2
 FP64, FP32_BULK = 0, 1
 EPI2, EPI3, EXPRB32, EXPRB42 = 2, 3, 32, 42
+FLUX_LF, FLUX_EF = 0, 1
+BC_PERIODIC, BC_DIRICHLET = 0, 1
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ENONFINITE = 0, -1, -2, -3, -4, -5
 
 
@@ -31,7 +33,9 @@ class MeshDesc(C.Structure):
     _fields_ = [("equation", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("p", C.c_int),
                 ("precision", C.c_int), ("device", C.c_int), ("x0", C.c_double),
                 ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
-                ("gamma", C.c_double), ("m_max", C.c_int)]
+                ("gamma", C.c_double), ("m_max", C.c_int), ("kappa", C.c_double),
+                ("flux", C.c_int), ("sigma", C.c_double), ("beta", C.c_double),
+                ("bc", C.c_int), ("has_source", C.c_int)]
 
 
 class MeshInfo(C.Structure):
@@ -101,6 +105,7 @@ _SIGS = {
     "expdg_workspace_bytes": (C.c_size_t, [C.POINTER(MeshDesc)]),
     "expdg_mesh_get_info": (C.c_int, [C.c_void_p, C.POINTER(MeshInfo)]),
     "expdg_mesh_nodes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "expdg_mesh_set_source": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "expdg_lgl": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "expdg_rhs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "expdg_jvp": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -191,6 +196,13 @@ def expdg_workspace_bytes(desc: MeshDesc) -> int:
     return lib().expdg_workspace_bytes(C.byref(desc))
 
 
+def expdg_mesh_set_source(handle, s, stream=None):
+    import torch
+    if not (isinstance(s, torch.Tensor) and s.dtype == torch.float64 and s.is_contiguous()):
+        raise ExpdgError(EINVAL, "the source must be a contiguous float64 device tensor")
+    _check(lib().expdg_mesh_set_source(handle, _ptr(s), _stream(stream)))
+
+
 def expdg_rhs(handle, q, r, stream=None):
     _check(lib().expdg_rhs(handle, _ptr(q), _ptr(r), _stream(stream)))
 
@@ -279,9 +291,10 @@ class Mesh:
     """Owns an expdg mesh handle; methods forward to the C entry points."""
 
     def __init__(self, equation, nx, p, ny=1, precision=FP64, device=0, x0=0.0, x1=1.0,
-                 y0=0.0, y1=1.0, gamma=1.4, m_max=64):
+                 y0=0.0, y1=1.0, gamma=1.4, m_max=64, kappa=0.0, flux=FLUX_LF, sigma=0.0,
+                 beta=0.0, bc=BC_PERIODIC, has_source=False):
         self.desc = MeshDesc(equation, nx, ny, p, precision, device, x0, x1, y0, y1, gamma,
-                             m_max)
+                             m_max, kappa, flux, sigma, beta, bc, int(bool(has_source)))
         self.handle = expdg_mesh_create(self.desc)
         info = MeshInfo()
         _check(lib().expdg_mesh_get_info(self.handle, C.byref(info)))
@@ -320,6 +333,10 @@ class Mesh:
         _check(lib().expdg_mesh_nodes(self.handle, x.ctypes.data, y.ctypes.data))
         return x, y
 
+    def set_source(self, s, stream=None):
+        """s: float64 device tensor of ndof entries (copied into the mesh)."""
+        expdg_mesh_set_source(self.handle, s, stream)
+
     def rhs(self, q, r, stream=None):
         expdg_rhs(self.handle, q, r, stream)
 
@@ -346,8 +363,10 @@ class Mesh:
 # ---- solve server -------------------------------------------------------------
 def make_request(equation, nx, p, ny=1, scheme=EPI3, nsteps=20, dt=0.0, cfl=0.0, tol=1e-10,
                  m_min=10, m_max=64, check_every=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0,
-                 gamma=1.4, mesh_m_max=64):
-    return Request(MeshDesc(equation, nx, ny, p, FP64, 0, x0, x1, y0, y1, gamma, mesh_m_max),
+                 gamma=1.4, mesh_m_max=64, kappa=0.0, flux=FLUX_LF, sigma=0.0, beta=0.0,
+                 bc=BC_PERIODIC):
+    return Request(MeshDesc(equation, nx, ny, p, FP64, 0, x0, x1, y0, y1, gamma, mesh_m_max,
+                            kappa, flux, sigma, beta, bc, 0),
                    scheme, nsteps, dt, cfl, tol, m_min, m_max, check_every)
 
 

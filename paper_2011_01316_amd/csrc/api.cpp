@@ -154,6 +154,17 @@ bool desc_ok(const expdg_mesh_desc *d, const char **why) {
     }
     if (d->m_max < 1 || d->m_max > kMaxM) return *why = "m_max must be in 1..64", false;
     if (d->device < 0) return *why = "device must be >= 0", false;
+    if (!(d->kappa >= 0.0) || !std::isfinite(d->kappa)) return *why = "need kappa >= 0", false;
+    if (!(d->sigma >= 0.0) || !std::isfinite(d->sigma)) return *why = "need sigma >= 0", false;
+    if (!(std::fabs(d->beta) <= 0.5)) return *why = "need |beta| <= 1/2", false;
+    if (d->flux != EXPDG_FLUX_LF && d->flux != EXPDG_FLUX_EF)
+        return *why = "flux must be EXPDG_FLUX_LF or EXPDG_FLUX_EF", false;
+    if (d->bc != EXPDG_BC_PERIODIC && d->bc != EXPDG_BC_DIRICHLET)
+        return *why = "bc must be EXPDG_BC_PERIODIC or EXPDG_BC_DIRICHLET", false;
+    if (d->equation == EXPDG_EULER2D &&
+        (d->kappa != 0.0 || d->flux != EXPDG_FLUX_LF || d->sigma != 0.0 || d->beta != 0.0 ||
+         d->bc != EXPDG_BC_PERIODIC || d->has_source))
+        return *why = "Euler takes no Burgers options (kappa, flux, sigma, beta, bc, source)", false;
     return true;
 }
 
@@ -176,6 +187,7 @@ size_t layout(expdg_mesh *m, const expdg_mesh_desc *d, size_t stride, int eb, ch
     if (d->precision == EXPDG_FP32_BULK)
         for (auto &v : m->bq) take(v, vb);
     take(m->q2, stride * 8);
+    if (d->has_source) take(m->src, vb);
     const size_t nlin = lin_elems(d->equation, d->p, d->nx * d->ny);
     if (nlin) take(m->lin, nlin * eb);
     take(m->kd.H, (size_t)(kMaxM + 1) * kLDH * 8);
@@ -395,6 +407,18 @@ extern "C" int expdg_mesh_nodes(const expdg_mesh *m, double *x, double *y) {
                     (m->dim == 2) ? m->d.y0 + ey * m->hy + 0.5 * (m->xi[j] + 1.0) * m->hy : 0.0;
         }
     }
+    return EXPDG_OK;
+}
+
+extern "C" int expdg_mesh_set_source(expdg_mesh *m, const double *src, void *stream) {
+    if (!m || !src) return fail(EXPDG_EINVAL, "NULL argument");
+    if (!m->src) return fail(EXPDG_EINVAL, "the mesh was created without has_source");
+    DeviceGuard g(m->d.device);
+    hipStream_t s = (hipStream_t)stream;
+    if (m->d.precision == EXPDG_FP64)
+        HIPTRY(launch_copy(src, (double *)m->src, m->n, s));
+    else
+        HIPTRY(launch_convert(src, (float *)m->src, m->n, s));
     return EXPDG_OK;
 }
 

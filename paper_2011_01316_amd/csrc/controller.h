@@ -317,14 +317,20 @@ Task<int> phi_co(X &x, expdg_mesh *m, const T *qref, double tau, int p, const T 
         if (st) st->err_est = R.err;
         if (forced) *fpos += 1;
         if (R.sub_last) break;
+        const double rem = tau - R.t_done;
+        if (!(rem > 1e-15 * tau)) {
+            // the accepted substeps already cover [0, tau]: the last one ends
+            // the evaluation, and the log says so (a replay stops there too)
+            if (st && st->log && st->log_len >= 1 && st->log_len <= st->log_cap)
+                st->log[st->log_len - 1].last = 1;
+            break;
+        }
         if (forced) continue;
 
         const double ratio = (R.err > 0.0) ? R.tol_abs * R.dt_sub / tau / R.err : 0.0;
         double fac = (R.err > 0.0) ? 0.9 * std::pow(ratio, 1.0 / R.j_acc) : 5.0;
         fac = std::min(5.0, std::max(1.0, fac));
         const double cand = round2(R.dt_sub * fac);
-        const double rem = tau - R.t_done;
-        if (!(rem > 1e-15 * tau)) break;
         if (cand >= rem) {
             dtau = rem;
             reaches_end = true;

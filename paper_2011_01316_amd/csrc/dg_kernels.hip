@@ -454,16 +454,38 @@ __device__ __forceinline__ void euler_op_body(const OpArgs<T> &a, int tile, bool
 }
 
 // ---- Burgers 1D operator ----------------------------------------------------
-template <int P, typename T, bool JVP>
+// One thread per LGL node, EPB whole elements per block.  Residual of
+// u_t + (u^2/2 - kappa q)_x = s and linear operator of the flux u~ v - kappa q(v)
+// (Section 3.1, eqs. gov-burgers1d-gradu, BurgerL, BurgerN), strong form with
+// the LGL lift 1/w_0 at the end nodes:
+//   convective face flux: Lax-Friedrichs with lambda = max(|u~^-|, |u~^+|), or
+//     (residual, ef) the entropy flux n (u^-^2 + u^- u^+ + u^+^2)/6 +
+//     ef_pen (u^- - u^+);
+//   VISC (kappa > 0): the auxiliary q of the differentiated field z (u for the
+//     residual, v for the linear operator) is formed in LDS for the block's
+//     elements and the two adjacent face nodes of the neighbouring elements:
+//     q = (2/h) D z + (2/h)(1/w_0) n (z** - z^-) at the end nodes, with
+//     z** = {{z}} - beta [[z]] ([[z]] = z_left - z_right); the flux then gets
+//     -kappa q, and the face term kappa (2/h)(1/w_0) n (q** - q^-) with
+//     q** = {{q}} + beta [[q]];
+//   dirichlet: beyond both ends z^+ = 0 for the convective fluxes, z** = 0 and
+//     q** = q^- (no diffusive face term).
+template <int P, typename T, bool JVP, bool VISC>
 __device__ __forceinline__ void burgers_op_body(const OpArgs<T> &a, int tile, bool first) {
     constexpr int N1 = P + 1, EPB = 256 / N1, NT = EPB * N1;
+    // VISC: slots 0 and nact + 1 hold the neighbouring elements (halo)
+    constexpr int NS = VISC ? (EPB + 2) * N1 : 1;
     __shared__ T sF[NT];
+    __shared__ T sZ[NS];
+    __shared__ T sQ[NS];
     const int tid = threadIdx.x;
     const int le = tid / N1;
     const int i = tid - le * N1;
-    const int e = tile * EPB + le;
+    const int e0 = tile * EPB;
+    const int e = e0 + le;
     const bool active = (tid < NT) && (e < a.K);
     const size_t idx = (size_t)e * N1 + i;
+    const bool dir = a.dirichlet != 0;
 
     T sc = T(1);
     if (a.vscale) sc = (T)(*a.vscale);
@@ -478,6 +500,58 @@ __device__ __forceinline__ void burgers_op_body(const OpArgs<T> &a, int tile, bo
         uv = JVP ? a.v[idx] : qv;
         f = JVP ? qv * uv : T(0.5) * qv * qv;
     }
+    const int nact = min(EPB, a.K - e0);  // elements of this block
+    // neighbours of the block: -1 beyond a Dirichlet end
+    int eLh = e0 - 1, eRh = e0 + nact;
+    if (eLh < 0) eLh = dir ? -1 : a.K - 1;
+    if (eRh >= a.K) eRh = dir ? -1 : 0;
+    const T *zsrc = JVP ? a.v : a.q;
+    T qgrad = T(0);
+    if constexpr (VISC) {
+        if (active) sZ[(le + 1) * N1 + i] = uv;
+        if (tid < N1) sZ[tid] = (eLh >= 0) ? zsrc[(size_t)eLh * N1 + tid] : T(0);
+        if (tid >= N1 && tid < 2 * N1)
+            sZ[(nact + 1) * N1 + (tid - N1)] =
+                (eRh >= 0) ? zsrc[(size_t)eRh * N1 + (tid - N1)] : T(0);
+        __syncthreads();
+        const T rl = a.rhx * a.lift;
+        if (active) {
+            const T *z = sZ + (le + 1) * N1;
+            T g = T(0);
+#pragma unroll
+            for (int l = 0; l < N1; ++l) g += a.D[i * N1 + l] * z[l];
+            g *= a.rhx;
+            if (i == 0) {  // face with the left neighbour
+                const bool bnd = dir && e == 0;
+                const T zl = sZ[le * N1 + P], zr = z[0];
+                const T zs = bnd ? T(0) : T(0.5) * (zl + zr) - a.beta * (zl - zr);
+                g -= rl * (zs - zr);
+                if (le == 0 && !bnd) {  // q of the left neighbour at this face
+                    const T *zh = sZ;
+                    T gh = T(0);
+#pragma unroll
+                    for (int l = 0; l < N1; ++l) gh += a.D[P * N1 + l] * zh[l];
+                    sQ[P] = a.rhx * gh + rl * (zs - zl);
+                }
+            }
+            if (i == P) {  // face with the right neighbour
+                const bool bnd = dir && e == a.K - 1;
+                const T zl = z[P], zr = sZ[(le + 2) * N1];
+                const T zs = bnd ? T(0) : T(0.5) * (zl + zr) - a.beta * (zl - zr);
+                g += rl * (zs - zl);
+                if (le == nact - 1 && !bnd) {  // q of the right neighbour at this face
+                    const T *zh = sZ + (nact + 1) * N1;
+                    T gh = T(0);
+#pragma unroll
+                    for (int l = 0; l < N1; ++l) gh += a.D[l] * zh[l];
+                    sQ[(nact + 1) * N1] = a.rhx * gh - rl * (zs - zr);
+                }
+            }
+            qgrad = g;
+            sQ[(le + 1) * N1 + i] = g;
+            f -= a.kappa * g;
+        }
+    }
     if (tid < NT) sF[tid] = f;
     __syncthreads();
 
@@ -490,16 +564,34 @@ __device__ __forceinline__ void burgers_op_body(const OpArgs<T> &a, int tile, bo
     if (active && (i == 0 || i == P)) {
         const int s = (i == P) ? 1 : -1;
         int en = e + s;
+        const bool bnd = dir && (en < 0 || en >= a.K);
         en = en < 0 ? a.K - 1 : (en >= a.K ? 0 : en);
         const size_t nidx = (size_t)en * N1 + (P - i);
-        const T qn = a.q[nidx];
-        const T un = JVP ? a.v[nidx] : qn;
+        const T qn = bnd ? T(0) : a.q[nidx];
+        const T un = JVP ? (bnd ? T(0) : a.v[nidx]) : qn;
         const T fn = JVP ? qn * un : T(0.5) * qn * qn;
-        const T lam = fmax(fabs(qv), fabs(qn));
-        res -= a.rhx * a.lift * (T(0.5) * T(s) * (fn - f) + T(0.5) * lam * (uv - un));
+        const T fc = JVP ? qv * uv : T(0.5) * qv * qv;
+        if (!JVP && a.ef) {
+            const T fs = T(s) * (qv * qv + qv * qn + qn * qn) * T(1.0 / 6.0) +
+                         a.ef_pen * (qv - qn);
+            res -= a.rhx * a.lift * (fs - T(s) * fc);
+        } else {
+            const T lam = fmax(fabs(qv), fabs(qn));
+            res -= a.rhx * a.lift * (T(0.5) * T(s) * (fn - fc) + T(0.5) * lam * (uv - un));
+        }
+        if constexpr (VISC) {
+            if (!bnd) {
+                // q of the two sides of this face, left and right
+                const T qL = (s < 0) ? sQ[le * N1 + P] : qgrad;
+                const T qR = (s < 0) ? qgrad : sQ[(le + 2) * N1];
+                const T qs = T(0.5) * (qL + qR) + a.beta * (qL - qR);
+                res += a.kappa * a.rhx * a.lift * T(s) * (qs - qgrad);
+            }
+        }
     }
     T wv = T(0);
     if (active) {
+        if (!JVP && a.src) res += a.src[idx];
         for (int k = 0; k < a.naug; ++k) {
             const T *b = a.aug[k];
             if (!b) continue;
@@ -517,9 +609,9 @@ __global__ __launch_bounds__(256) void euler_op(OpArgs<T> a) {
     euler_op_body<P, T, JVP>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.x == 0);
 }
 
-template <int P, typename T, bool JVP>
+template <int P, typename T, bool JVP, bool VISC>
 __global__ __launch_bounds__(256) void burgers_op(OpArgs<T> a) {
-    burgers_op_body<P, T, JVP>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.x == 0);
+    burgers_op_body<P, T, JVP, VISC>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.x == 0);
 }
 
 template <int P, typename T, bool JVP>
@@ -530,17 +622,27 @@ __global__ __launch_bounds__(256) void euler_op_group(const OpArgs<T> *items, co
     euler_op_body<P, T, JVP>(items[it], xcd_tile(local, G), local == 0);
 }
 
-template <int P, typename T, bool JVP>
+template <int P, typename T, bool JVP, bool VISC>
 __global__ __launch_bounds__(256) void burgers_op_group(const OpArgs<T> *items, const int *bstart,
                                                         int n) {
     const int it = group_item(bstart, n, blockIdx.x);
     const int local = blockIdx.x - bstart[it], G = bstart[it + 1] - bstart[it];
-    burgers_op_body<P, T, JVP>(items[it], xcd_tile(local, G), local == 0);
+    burgers_op_body<P, T, JVP, VISC>(items[it], xcd_tile(local, G), local == 0);
+}
+
+template <int P, typename T, bool VISC>
+hipError_t launch_burgers_group(bool jvp, const OpArgs<T> *items, const int *bstart, int n,
+                                int total, hipStream_t s) {
+    if (jvp)
+        return launch_kernel(burgers_op_group<P, T, true, VISC>, dim3(total), dim3(256), 0, s,
+                             items, bstart, n);
+    return launch_kernel(burgers_op_group<P, T, false, VISC>, dim3(total), dim3(256), 0, s, items,
+                         bstart, n);
 }
 
 template <int P, typename T>
-hipError_t launch_group_p(int equation, bool jvp, const OpArgs<T> *items, const int *bstart,
-                          int n, int total, hipStream_t s) {
+hipError_t launch_group_p(int equation, bool jvp, bool visc, const OpArgs<T> *items,
+                          const int *bstart, int n, int total, hipStream_t s) {
     if (equation == EXPDG_EULER2D) {
         if (jvp)
             return launch_kernel(euler_op_group<P, T, true>, dim3(total), dim3(256), 0, s, items,
@@ -548,11 +650,8 @@ hipError_t launch_group_p(int equation, bool jvp, const OpArgs<T> *items, const 
         return launch_kernel(euler_op_group<P, T, false>, dim3(total), dim3(256), 0, s, items,
                              bstart, n);
     }
-    if (jvp)
-        return launch_kernel(burgers_op_group<P, T, true>, dim3(total), dim3(256), 0, s, items,
-                             bstart, n);
-    return launch_kernel(burgers_op_group<P, T, false>, dim3(total), dim3(256), 0, s, items,
-                         bstart, n);
+    if (visc) return launch_burgers_group<P, T, true>(jvp, items, bstart, n, total, s);
+    return launch_burgers_group<P, T, false>(jvp, items, bstart, n, total, s);
 }
 
 template <int P, typename T>
@@ -565,8 +664,13 @@ hipError_t launch_p(int equation, bool jvp, const OpArgs<T> &a, hipStream_t s) {
     }
     constexpr int EPB = 256 / (P + 1);
     const int grid = (a.K + EPB - 1) / EPB;
-    if (jvp) return launch_kernel(burgers_op<P, T, true>, dim3(grid), dim3(256), 0, s, a);
-    return launch_kernel(burgers_op<P, T, false>, dim3(grid), dim3(256), 0, s, a);
+    if (a.kappa != T(0)) {
+        if (jvp)
+            return launch_kernel(burgers_op<P, T, true, true>, dim3(grid), dim3(256), 0, s, a);
+        return launch_kernel(burgers_op<P, T, false, true>, dim3(grid), dim3(256), 0, s, a);
+    }
+    if (jvp) return launch_kernel(burgers_op<P, T, true, false>, dim3(grid), dim3(256), 0, s, a);
+    return launch_kernel(burgers_op<P, T, false, false>, dim3(grid), dim3(256), 0, s, a);
 }
 
 template <typename T>
@@ -718,15 +822,17 @@ int dg_blocks(int equation, int p, int K) {
     return (K + epb - 1) / epb;
 }
 
-hipError_t launch_dg_op_group(int equation, int p, bool jvp, const OpArgs<double> *items,
-                              const int *bstart, int n, int total, hipStream_t s) {
+hipError_t launch_dg_op_group(int equation, int p, bool jvp, bool visc,
+                              const OpArgs<double> *items, const int *bstart, int n, int total,
+                              hipStream_t s) {
+    if (visc && equation != EXPDG_BURGERS1D) return hipErrorInvalidValue;
     switch (p) {
-        case 1: return launch_group_p<1, double>(equation, jvp, items, bstart, n, total, s);
-        case 2: return launch_group_p<2, double>(equation, jvp, items, bstart, n, total, s);
-        case 3: return launch_group_p<3, double>(equation, jvp, items, bstart, n, total, s);
-        case 4: return launch_group_p<4, double>(equation, jvp, items, bstart, n, total, s);
-        case 5: return launch_group_p<5, double>(equation, jvp, items, bstart, n, total, s);
-        case 6: return launch_group_p<6, double>(equation, jvp, items, bstart, n, total, s);
+        case 1: return launch_group_p<1, double>(equation, jvp, visc, items, bstart, n, total, s);
+        case 2: return launch_group_p<2, double>(equation, jvp, visc, items, bstart, n, total, s);
+        case 3: return launch_group_p<3, double>(equation, jvp, visc, items, bstart, n, total, s);
+        case 4: return launch_group_p<4, double>(equation, jvp, visc, items, bstart, n, total, s);
+        case 5: return launch_group_p<5, double>(equation, jvp, visc, items, bstart, n, total, s);
+        case 6: return launch_group_p<6, double>(equation, jvp, visc, items, bstart, n, total, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -46,6 +46,16 @@ struct OpArgs {
     T rhx, rhy;        // 2/hx, 2/hy
     T lift;            // 1/w_0 (= 1/w_p)
     T gamma;
+    // Burgers options (Section 3.1): viscosity, entropy flux (residual only)
+    // with jump coefficient sigma / (h/2), diffusion-flux switch beta
+    // (0 central, 1/2 LDG), zero Dirichlet ends, and a source added to the
+    // residual (nullptr = none).
+    T kappa;
+    T ef_pen;          // 2 sigma / hx
+    T beta;
+    int ef;            // nonzero: entropy flux for (u^2/2)*
+    int dirichlet;     // nonzero: u = 0 beyond both ends
+    const T *src;
     T D[(kMaxP + 1) * (kMaxP + 1)];  // D[i*(p+1)+l] = l_l'(xi_i)
 };
 
@@ -86,8 +96,10 @@ size_t lin_elems(int equation, int p, int K);
 int dg_blocks(int equation, int p, int K);
 // Grouped FP64 launch over n meshes of the same equation and degree: item it
 // owns blocks [bstart[it], bstart[it+1]) (device arrays), total = bstart[n].
-hipError_t launch_dg_op_group(int equation, int p, bool jvp, const OpArgs<double> *items,
-                              const int *bstart, int n, int total, hipStream_t s);
+// visc selects the viscous Burgers kernels (every item then has kappa > 0).
+hipError_t launch_dg_op_group(int equation, int p, bool jvp, bool visc,
+                              const OpArgs<double> *items, const int *bstart, int n, int total,
+                              hipStream_t s);
 // Per-block maxima of the wave speed (FP64 state) into part[0..nblk).
 hipError_t launch_max_speed(int equation, const double *q, size_t npts, double gamma,
                             double *part, int nblk, hipStream_t s);

@@ -29,6 +29,7 @@ struct expdg_mesh {
     void *vec[6] = {};           // bulk work vectors (stride each)
     void *bq[3] = {};            // bulk copies of FP64 states (FP32_BULK only)
     double *q2 = nullptr;        // FP64 stage state (EXPRB32)
+    void *src = nullptr;         // source term of the residual (bulk type; has_source only)
     void *lin = nullptr;         // frozen fields of the 2D linear operator (bulk type)
     expdg::KrylovDev kd{};
     double *slots = nullptr;     // kCheckSlots x kSlotSize
@@ -136,6 +137,12 @@ OpArgs<T> op_args(const expdg_mesh *m) {
     a.gamma = (T)m->d.gamma;
     for (int k = 0; k < m->n1 * m->n1; ++k) a.D[k] = (T)m->D[k];
     a.eta = 1.0;
+    a.kappa = (T)m->d.kappa;
+    a.ef_pen = (T)(2.0 * m->d.sigma / m->hx);
+    a.beta = (T)m->d.beta;
+    a.ef = m->d.flux == EXPDG_FLUX_EF;
+    a.dirichlet = m->d.bc == EXPDG_BC_DIRICHLET;
+    a.src = (const T *)m->src;
     return a;
 }
 

@@ -194,6 +194,7 @@ bool request_sizes(const expdg_request *r, size_t *ws, size_t *st, const char **
     d.device = 0;
     if (!desc_ok(&d, why)) return false;
     if (d.precision != EXPDG_FP64) return *why = "served solves are FP64", false;
+    if (d.has_source) return *why = "served solves take no source term", false;
     if (r->scheme != EXPDG_EPI2 && r->scheme != EXPDG_EPI3)
         return *why = "scheme must be EXPDG_EPI2 or EXPDG_EPI3", false;
     if (r->nsteps < 1) return *why = "nsteps must be >= 1", false;
@@ -568,9 +569,10 @@ int launch_batch(expdg_server *sv) {
     size_t used = 0;
     const size_t cap = sv->stage_cap;
     const int n = (int)sv->iters.size();
-    // linear operator: one grouped launch per (equation, degree)
+    // linear operator: one grouped launch per (equation, degree, viscous or not)
     struct Group {
         int eq, p;
+        bool visc;
         std::vector<OpArgs<double>> items;
         std::vector<int> bstart;
         OpArgs<double> *d_items = nullptr;
@@ -579,11 +581,12 @@ int launch_batch(expdg_server *sv) {
     std::vector<Group> groups;
     for (const IterRec &it : sv->iters) {
         const int eq = it.r->mesh.d.equation, p = it.r->mesh.d.p;
+        const bool visc = it.r->mesh.d.kappa != 0.0;
         Group *g = nullptr;
         for (auto &x : groups)
-            if (x.eq == eq && x.p == p) g = &x;
+            if (x.eq == eq && x.p == p && x.visc == visc) g = &x;
         if (!g) {
-            groups.push_back(Group{eq, p, {}, {0}});
+            groups.push_back(Group{eq, p, visc, {}, {0}});
             g = &groups.back();
         }
         g->items.push_back(it.a);
@@ -615,8 +618,8 @@ int launch_batch(expdg_server *sv) {
 
     if (used) HIPTRY(hipMemcpyAsync(b.dev, b.host, used, hipMemcpyHostToDevice, sv->s));
     for (auto &g : groups) {
-        HIPTRY(launch_dg_op_group(g.eq, g.p, true, g.d_items, g.d_bstart, (int)g.items.size(),
-                                  g.bstart.back(), sv->s));
+        HIPTRY(launch_dg_op_group(g.eq, g.p, true, g.visc, g.d_items, g.d_bstart,
+                                  (int)g.items.size(), g.bstart.back(), sv->s));
         sv->st.grouped_launches += 1;
     }
     if (n > 0) {

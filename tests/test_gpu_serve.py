@@ -57,7 +57,8 @@ def standalone(req, q0):
     """The same solve with expdg_step on its own mesh."""
     d = req.mesh
     m = B.Mesh(d.equation, d.nx, d.p, ny=d.ny, x0=d.x0, x1=d.x1, y0=d.y0, y1=d.y1,
-               gamma=d.gamma, m_max=d.m_max)
+               gamma=d.gamma, m_max=d.m_max, kappa=d.kappa, flux=d.flux, sigma=d.sigma,
+               beta=d.beta, bc=d.bc)
     q = torch.tensor(q0, dtype=torch.float64, device="cuda")
     qp = torch.zeros_like(q)
     dt = req.dt if req.dt > 0 else req.cfl * m.dx_min / m.max_speed(q)
@@ -121,6 +122,36 @@ def mixed_cases():
         burgers_case(33, 3, 4.0, nsteps=9),
         euler_case(14, 2, 7.0, 3.0, 4.0, nsteps=2),
     ]
+
+
+def viscous_case(K, p, nsteps=4, scheme=B.EPI3, dt=0.05, **kw):
+    """Viscous Burgers on [0, 1] with zero Dirichlet ends (Section 5.1's smooth state)."""
+    x, _ = lgl_nodes(K, 1, p, 0.0, 1.0, 0, 1, 1)
+    q0 = inputs.burgers_smooth(x)
+    req = B.make_request(B.BURGERS1D, K, p, scheme=scheme, nsteps=nsteps, dt=dt, tol=TOL,
+                         m_min=MMIN, m_max=MMAX, x0=0.0, x1=1.0, kappa=0.03, bc=B.BC_DIRICHLET,
+                         **kw)
+    return req, q0
+
+
+def test_viscous_mix_is_bitwise_each_stepper():
+    # viscous solves (central and LDG diffusion fluxes, LF and entropy flux)
+    # share grouped launches with inviscid Burgers and Euler solves
+    cases = [
+        viscous_case(40, 4),
+        burgers_case(40, 4, 0.5),
+        viscous_case(23, 3, beta=0.5, scheme=B.EPI2),
+        euler_case(10, 4, 5.0, 5.0, 3.0),
+        viscous_case(60, 4, flux=B.FLUX_EF, sigma=3e-4, nsteps=6),
+        viscous_case(17, 2, beta=0.5, flux=B.FLUX_EF, sigma=0.0),
+    ]
+    want = [standalone(r, q0)[0] for r, q0 in cases]
+    with B.Server(hbm_budget=2 << 30, max_active=16) as srv:
+        got = serve_all(srv, cases)
+        srv.sync()
+        assert srv.stats()["arena_used"] == 0
+    for k, w in enumerate(want):
+        np.testing.assert_array_equal(got[k][0], w, err_msg=f"case {k}")
 
 
 def test_mixed_batch_is_bitwise_each_stepper():

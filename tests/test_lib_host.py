@@ -56,7 +56,8 @@ def test_lgl_rejects_bad_degree():
 
 def desc(**kw):
     d = dict(equation=B.EULER2D, nx=64, ny=64, p=4, precision=B.FP64, device=0, x0=0.0,
-             x1=10.0, y0=0.0, y1=10.0, gamma=1.4, m_max=64)
+             x1=10.0, y0=0.0, y1=10.0, gamma=1.4, m_max=64, kappa=0.0, flux=B.FLUX_LF,
+             sigma=0.0, beta=0.0, bc=B.BC_PERIODIC, has_source=0)
     d.update(kw)
     return B.MeshDesc(*[d[f] for f, _ in B.MeshDesc._fields_])
 
@@ -73,6 +74,30 @@ def test_workspace_bytes_and_validation():
         assert B.expdg_workspace_bytes(desc(**bad)) == 0, bad
     h = C.c_void_p()
     assert B.lib().expdg_mesh_create(C.byref(desc(p=9)), C.byref(h)) == B.EINVAL
+
+
+def test_burgers_options_validation():
+    burg = dict(equation=B.BURGERS1D, ny=1, nx=40, p=4, x1=1.0)
+    ok = B.expdg_workspace_bytes(desc(**burg))
+    assert ok > 0
+    visc = dict(burg, kappa=0.03, flux=B.FLUX_EF, sigma=3e-4, beta=0.5, bc=B.BC_DIRICHLET)
+    assert B.expdg_workspace_bytes(desc(**visc)) == ok
+    # the source vector takes one more bulk vector of the workspace
+    assert B.expdg_workspace_bytes(desc(**visc, has_source=1)) > ok
+    for bad in [dict(kappa=-1.0), dict(kappa=float("nan")), dict(sigma=-1e-3), dict(beta=0.75),
+                dict(beta=-0.6), dict(flux=2), dict(bc=2)]:
+        assert B.expdg_workspace_bytes(desc(**dict(burg, **bad))) == 0, bad
+    # Euler takes none of the Burgers options
+    for bad in [dict(kappa=0.1), dict(flux=B.FLUX_EF), dict(sigma=1e-3), dict(beta=0.5),
+                dict(bc=B.BC_DIRICHLET), dict(has_source=1)]:
+        assert B.expdg_workspace_bytes(desc(**bad)) == 0, bad
+
+
+def test_served_requests_take_no_source():
+    req = B.make_request(B.BURGERS1D, 40, 4, dt=1e-2, kappa=0.03, bc=B.BC_DIRICHLET)
+    assert B.expdg_request_bytes(req) > 0
+    req.mesh.has_source = 1
+    assert B.expdg_request_bytes(req) == 0
 
 
 def test_request_bytes_is_workspace_plus_two_states():
