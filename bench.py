@@ -58,17 +58,17 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(symbol):
-    """HBM bytes per launch of a kernel from the committed FETCH_SIZE /
-    WRITE_SIZE summary, or None if that summary was taken on other kernel
-    sources (the kernels changed since the counters were read)."""
+def measured_traffic(symbol, workload="vortex64_p4"):
+    """HBM bytes per launch of a kernel in a workload from the committed
+    FETCH_SIZE / WRITE_SIZE summary, or None if that summary was taken on
+    other kernel sources (the kernels changed since the counters were read)."""
     try:
         d = json.load(open(PMC_FILE))
     except (OSError, ValueError):
         return None
     if d.get("kernel_source_hash") != kernel_source_hash():
         return None
-    k = d.get("kernels", {}).get(symbol)
+    k = d.get("workloads", {}).get(workload, {}).get("kernels", {}).get(symbol)
     return None if k is None else k.get("bytes_per_launch")
 
 
@@ -125,6 +125,93 @@ class Case:
         ex = inputs.vortex(self.x, self.y, t=t, beta=self.w["beta"]).reshape(-1)
         qh = self.q.cpu().numpy()
         return float(np.linalg.norm(qh - ex) / np.linalg.norm(ex)), qh
+
+
+# Viscous Burgers (Section 5.1): the paper's stiff runs on k = 4, N_e = 40 (u0 =
+# sin^3(2 pi x)(1 - x)^{3/2}, kappa = 0.03, zero Dirichlet ends, entropy flux
+# sigma = 3e-4) with EPI2 to t = 1 at Cr_d = 161 (dt = 0.1) and Cr_d = 805
+# (dt = 0.5), and a large mesh of the same problem for throughput.
+VB = dict(K=40, p=4, kappa=0.03, sigma=3e-4, t_end=1.0, dts=(0.1, 0.5), tol=1e-10,
+          name="viscous Burgers, u0 = sin^3(2 pi x)(1-x)^1.5 on [0,1], kappa 0.03, zero "
+               "Dirichlet, LGL p=4, 40 elements, entropy flux sigma 3e-4, EPI2 to t = 1")
+VB_LARGE = dict(K=131072, p=4, kappa=0.03, crd=161.0, steps=10, tol=1e-10,
+                name="viscous Burgers, same problem on 131,072 elements, LGL p=4 (655,360 DOF), "
+                     "Lax-Friedrichs + central diffusion fluxes, EXPRB32 at Cr_d = 161")
+
+
+def run_viscous(args):
+    import torch
+
+    from paper_2011_01316_amd import binding as B
+    from paper_2011_01316_amd import inputs
+
+    out = {}
+    w = VB
+    m = B.Mesh(B.BURGERS1D, w["K"], w["p"], x0=0.0, x1=1.0, kappa=w["kappa"], flux=B.FLUX_EF,
+               sigma=w["sigma"], bc=B.BC_DIRICHLET)
+    x, _ = m.nodes()
+    u0 = torch.tensor(inputs.burgers_smooth(x), dtype=torch.float64, device="cuda:0")
+    opts = B.make_opts(w["tol"], 5, 64)
+    runs = []
+    for dt in w["dts"]:
+        nsteps = int(round(w["t_end"] / dt))
+        times = []
+        for rep in range(6):
+            q = u0.clone()
+            st = B.make_stats()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            m.integrate(B.EPI2, dt, nsteps, q, None, False, opts, st)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        d = B.stats_dict(st)
+        runs.append(dict(dt=dt, cr_d=round(w["kappa"] * dt / m.dx_min ** 2, 1), steps=nsteps,
+                         seconds_to_t1=round(sorted(times[1:])[len(times[1:]) // 2], 6),
+                         krylov_iters=d["krylov_iters"], substeps=d["substeps"]))
+        log(f"viscous Burgers EPI2 dt={dt}: {runs[-1]['seconds_to_t1'] * 1e3:.2f} ms to t = 1")
+    m.close()
+    out["paper_case"] = dict(workload=w["name"], epi2=runs)
+
+    w = VB_LARGE
+    m = B.Mesh(B.BURGERS1D, w["K"], w["p"], x0=0.0, x1=1.0, kappa=w["kappa"],
+               bc=B.BC_DIRICHLET, m_max=64)
+    x, _ = m.nodes()
+    q = torch.tensor(inputs.burgers_smooth(x), dtype=torch.float64, device="cuda:0")
+    dt = w["crd"] * m.dx_min ** 2 / w["kappa"]
+    opts = B.make_opts(w["tol"], 5, 64)
+    m.integrate(B.EXPRB32, dt, 2, q, None, False, opts, B.make_stats())
+    res = {}
+    for prof in (False, True):
+        for c in B.KERNEL_CLASSES:
+            B.expdg_profile_enable(m.handle, c, prof)
+        st = B.make_stats()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m.integrate(B.EXPRB32, dt, w["steps"], q, None, False, opts, st)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        d = B.stats_dict(st)
+        if not prof:
+            res = dict(workload=w["name"], dt=dt, steps=w["steps"],
+                       ms_per_step=round(secs / w["steps"] * 1e3, 4),
+                       value=round(m.n * (d["rhs_calls"] + d["jvps"]) / secs, 1), unit=UNIT,
+                       krylov_iters_per_step=d["krylov_iters"] / w["steps"])
+        else:
+            pr = {B.KERNEL_CLASSES[c]: B.expdg_profile_read(m.handle, c) for c in B.KERNEL_CLASSES}
+            wl = "viscous_burgers_131072_p4"
+            for cls, sym in (("linear_operator", "burgers_op<4, double, true, true>"),
+                             ("residual", "burgers_op<4, double, false, true>"),
+                             ("gs_dots", B.KERNEL_SYMBOLS["gs_dots"]),
+                             ("gs_update", B.KERNEL_SYMBOLS["gs_update"])):
+                res[cls + "_roofline"] = roof(pr[cls], cls, sym, measured_traffic(sym, wl))
+            tot = sum(v["total_ms"] for v in pr.values())
+            res["kernel_time_share"] = {k: round(v["total_ms"] / tot, 4) for k, v in pr.items()}
+    for c in B.KERNEL_CLASSES:
+        B.expdg_profile_enable(m.handle, c, False)
+    log(f"viscous Burgers 131072 x p4: {res['ms_per_step']:.3f} ms/step")
+    m.close()
+    out["large"] = res
+    return out
 
 
 def roof(p, name, symbol, traffic=None):
@@ -360,6 +447,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=200)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-viscous", action="store_true")
+    ap.add_argument("--viscous-only", action="store_true",
+                    help="only the viscous Burgers measurements (one JSON line)")
     ap.add_argument("--serve-requests", type=int, default=SERVED["n_requests"])
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--serve-max-active", type=int, default=256)
@@ -375,6 +465,9 @@ def main():
         return
     if args.serve_only:
         print(json.dumps(run_served(args)), flush=True)
+        return
+    if args.viscous_only:
+        print(json.dumps(run_viscous(args)), flush=True)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -463,6 +556,8 @@ def main():
                                           "euler_op<3, double, true>"),
             gs_update_roofline=roof(pb["gs_update"], "gs_update", B.KERNEL_SYMBOLS["gs_update"]),
             gs_dots_roofline=roof(pb["gs_dots"], "gs_dots", B.KERNEL_SYMBOLS["gs_dots"]))
+    if not args.no_viscous:
+        line["viscous_burgers"] = run_viscous(args)
     if not args.no_serve:
         line["served"] = run_served(args)
     line["cpu_baseline"] = None if args.no_cpu_baseline else run_cpu_baseline(args)

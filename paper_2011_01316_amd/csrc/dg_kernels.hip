@@ -495,10 +495,24 @@ __device__ __forceinline__ void burgers_op_body(const OpArgs<T> &a, int tile, bo
     }
 
     T qv = T(0), uv = T(0), f = T(0);
+    // end nodes: the neighbour's trace across the face (zero beyond a
+    // Dirichlet end), loaded together with the node's own values
+    const bool face = active && (i == 0 || i == P);
+    const int s = (i == P) ? 1 : -1;
+    bool bnd = false;
+    T qn = T(0), un = T(0);
     if (active) {
         qv = a.q[idx];
         uv = JVP ? a.v[idx] : qv;
         f = JVP ? qv * uv : T(0.5) * qv * qv;
+    }
+    if (face) {
+        int en = e + s;
+        bnd = dir && (en < 0 || en >= a.K);
+        en = en < 0 ? a.K - 1 : (en >= a.K ? 0 : en);
+        const size_t nidx = (size_t)en * N1 + (P - i);
+        qn = bnd ? T(0) : a.q[nidx];
+        un = JVP ? (bnd ? T(0) : a.v[nidx]) : qn;
     }
     const int nact = min(EPB, a.K - e0);  // elements of this block
     // neighbours of the block: -1 beyond a Dirichlet end
@@ -561,14 +575,7 @@ __device__ __forceinline__ void burgers_op_body(const OpArgs<T> &a, int tile, bo
 #pragma unroll
         for (int l = 0; l < N1; ++l) res -= a.rhx * a.D[i * N1 + l] * sF[base + l];
     }
-    if (active && (i == 0 || i == P)) {
-        const int s = (i == P) ? 1 : -1;
-        int en = e + s;
-        const bool bnd = dir && (en < 0 || en >= a.K);
-        en = en < 0 ? a.K - 1 : (en >= a.K ? 0 : en);
-        const size_t nidx = (size_t)en * N1 + (P - i);
-        const T qn = bnd ? T(0) : a.q[nidx];
-        const T un = JVP ? (bnd ? T(0) : a.v[nidx]) : qn;
+    if (face) {
         const T fn = JVP ? qn * un : T(0.5) * qn * qn;
         const T fc = JVP ? qv * uv : T(0.5) * qv * qv;
         if (!JVP && a.ef) {
