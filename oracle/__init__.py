@@ -60,7 +60,8 @@ class Substep(C.Structure):
 
 class _KOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("m_min", C.c_int), ("m_max", C.c_int),
-                ("check_every", C.c_int), ("forced", C.POINTER(Substep)), ("n_forced", C.c_int)]
+                ("check_every", C.c_int), ("forced", C.POINTER(Substep)), ("n_forced", C.c_int),
+                ("iop", C.c_int)]
 
 
 class _KStats(C.Structure):
@@ -137,6 +138,7 @@ def _declare(L):
     L.orc_step.argtypes = [mp, C.c_int, C.c_double, dp, dp, C.c_int, C.POINTER(_KOpts),
                            C.POINTER(_KStats)]
     L.orc_rk4.argtypes = [mp, C.c_double, C.c_int, dp]
+    L.orc_arnoldi_dense.argtypes = [C.c_int, dp, dp, C.c_int, C.c_int, dp, dp]
     L.orc_num_threads.restype = C.c_int
     L.orc_set_num_threads.argtypes = [C.c_int]
 
@@ -233,10 +235,10 @@ class Mesh:
         return np.ascontiguousarray(L.T)
 
     def phi_krylov(self, qref, tau, bs, tol=1e-10, m_min=10, m_max=64, check_every=1,
-                   forced=None, stats=False):
+                   forced=None, stats=False, iop=0):
         qref = np.ascontiguousarray(qref, dtype=np.float64)
         out = np.zeros(self.n)
-        opts, st, keep = _kopts(tol, m_min, m_max, check_every, forced)
+        opts, st, keep = _kopts(tol, m_min, m_max, check_every, forced, iop=iop)
         barr, keep2 = _bvec(bs)
         rc = lib().orc_phi_krylov_dg(C.byref(self._m), _dp(qref), tau, len(bs) - 1, barr,
                                      _dp(out), C.byref(opts), C.byref(st))
@@ -244,12 +246,12 @@ class Mesh:
         return (out, _stats(st)) if stats else out
 
     def step(self, scheme, dt, q, q_prev=None, tol=1e-10, m_min=10, m_max=64, check_every=1,
-             forced=None, stats=False):
+             forced=None, stats=False, iop=0):
         """One step; returns (q_new, q_prev_new[, stats]).  Inputs are not modified."""
         q = np.array(q, dtype=np.float64, copy=True)
         have_prev = q_prev is not None
         qp = (np.array(q_prev, dtype=np.float64, copy=True) if have_prev else np.zeros(self.n))
-        opts, st, keep = _kopts(tol, m_min, m_max, check_every, forced)
+        opts, st, keep = _kopts(tol, m_min, m_max, check_every, forced, iop=iop)
         rc = lib().orc_step(C.byref(self._m), scheme, dt, _dp(q), _dp(qp), int(have_prev),
                             C.byref(opts), C.byref(st))
         _check(rc, "step")
@@ -269,14 +271,14 @@ def _bvec(bs):
     return barr, arrs
 
 
-def _kopts(tol, m_min, m_max, check_every, forced, log_cap=4096):
+def _kopts(tol, m_min, m_max, check_every, forced, log_cap=4096, iop=0):
     if forced:
         fa = (Substep * len(forced))(*[Substep(int(m), int(last), float(dt))
                                        for (m, dt, last) in forced])
         fp, nf = fa, len(forced)
     else:
         fa, fp, nf = None, None, 0
-    opts = _KOpts(tol, m_min, m_max, check_every, fp, nf)
+    opts = _KOpts(tol, m_min, m_max, check_every, fp, nf, iop)
     log = (Substep * log_cap)()
     st = _KStats(0, 0, 0, 0, 0, 0, 0, 0.0, log, log_cap, 0)
     return opts, st, (fa, log)
@@ -317,15 +319,26 @@ def phi_dense(A, tau, bs):
 
 
 def phi_krylov_dense(A, tau, bs, tol=1e-10, m_min=10, m_max=64, check_every=1, forced=None,
-                     stats=False):
+                     stats=False, iop=0):
     A = np.ascontiguousarray(A, dtype=np.float64)
     out = np.zeros(A.shape[0])
-    opts, st, keep = _kopts(tol, m_min, m_max, check_every, forced)
+    opts, st, keep = _kopts(tol, m_min, m_max, check_every, forced, iop=iop)
     barr, keep2 = _bvec(bs)
     rc = lib().orc_phi_krylov_dense(A.shape[0], _dp(A), tau, len(bs) - 1, barr, _dp(out),
                                     C.byref(opts), C.byref(st))
     _check(rc, "phi_krylov_dense")
     return (out, _stats(st)) if stats else out
+
+
+def arnoldi_dense(A, b, m, iop=0):
+    """m Arnoldi steps of the phi evaluations' orthogonalization: (V, H), V of
+    shape (m+1, n) (rows are basis vectors), H of shape (m+1, m)."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    n = A.shape[0]
+    V, H = np.zeros((m + 1, n)), np.zeros((m + 1, m))
+    _check(lib().orc_arnoldi_dense(n, _dp(A), _dp(b), m, iop, _dp(V), _dp(H)), "arnoldi")
+    return V, H
 
 
 def num_threads() -> int:

@@ -26,6 +26,13 @@
 //  4. The top n entries of z are the result.
 // A forced schedule (list of (m, dtau, last)) replays given substeps with no
 // error checks.
+//
+// Incomplete orthogonalization (iop = L > 0, the IOP option of KIOPS cited in
+// Section 2.3): each new vector is orthogonalized, with one classical
+// Gram-Schmidt pass, against the L most recent basis vectors only (the one it
+// was computed from included), then normalised by its explicit norm.  H is
+// then banded (h_{i,j} = 0 for i < j + 1 - L) and V is orthonormal only
+// within windows of L consecutive vectors; everything else is unchanged.
 #include "oracle.h"
 
 #include <algorithm>
@@ -85,7 +92,50 @@ int small_expm(const std::vector<double> &H, int ldh, int j, double dtau, std::v
     return orc_expm(nh, X.data(), F.data());
 }
 
+// Orthogonalizes w against the basis vectors V[0..j-1] by classical
+// Gram-Schmidt -- two passes over all of them (iop = 0), or one pass over the
+// last iop of them -- and adds the coefficients to column j-1 of H.
+void orthogonalize(const std::vector<double> &V, size_t na, std::vector<double> &H, int ldh,
+                   int j, int iop, double *w) {
+    const int i_lo = (iop > 0) ? std::max(0, j - iop) : 0;
+    for (int pass = 0; pass < (iop > 0 ? 1 : 2); ++pass) {
+        std::vector<double> h(j, 0.0);
+        for (int i = i_lo; i < j; ++i) h[i] = dot(&V[(size_t)i * na], w, na);
+        for (int i = i_lo; i < j; ++i) {
+            const double *vi = &V[(size_t)i * na];
+            for (size_t r = 0; r < na; ++r) w[r] -= h[i] * vi[r];
+            H[(size_t)i * ldh + (j - 1)] += h[i];
+        }
+    }
+}
+
 }  // namespace
+
+extern "C" int orc_arnoldi_dense(int n, const double *A, const double *b, int m, int iop,
+                                 double *Vout, double *Hout) {
+    if (n < 1 || m < 1 || iop < 0 || !A || !b || !Vout || !Hout) return -1;
+    const size_t na = (size_t)n;
+    std::vector<double> V((size_t)(m + 1) * na, 0.0), H((size_t)(m + 1) * m, 0.0), w(na);
+    const double beta = norm2(b, na);
+    if (!(beta > 0.0)) return -1;
+    for (size_t r = 0; r < na; ++r) V[r] = b[r] / beta;
+    for (int j = 1; j <= m; ++j) {
+        const double *vj = &V[(size_t)(j - 1) * na];
+        for (int r = 0; r < n; ++r) {
+            double acc = 0.0;
+            for (int c = 0; c < n; ++c) acc += A[(size_t)r * n + c] * vj[c];
+            w[r] = acc;
+        }
+        orthogonalize(V, na, H, m, j, iop, w.data());
+        const double hn = norm2(w.data(), na);
+        if (!(hn > 0.0)) return -1;
+        H[(size_t)j * m + (j - 1)] = hn;
+        for (size_t r = 0; r < na; ++r) V[(size_t)j * na + r] = w[r] / hn;
+    }
+    std::copy(V.begin(), V.end(), Vout);
+    std::copy(H.begin(), H.end(), Hout);
+    return 0;
+}
 
 // Shared by the dense and DG entry points and by the steppers.  *fpos is the
 // cursor into the forced schedule (advanced by the substeps replayed).
@@ -93,7 +143,7 @@ int orc_phi_krylov_op(size_t n, const Op &A, double tau, int p, const double *co
                       double *out, const orc_kopts *o, orc_kstats *st, int *fpos) {
     if (!o || !out || p < 0 || p > 8 || !(tau >= 0.0)) return -1;
     if (!(o->tol > 0.0) || o->m_min < 1 || o->m_max < o->m_min || o->m_max > 256 ||
-        o->check_every < 1)
+        o->check_every < 1 || o->iop < 0)
         return -1;
     const bool forced = o->forced && o->n_forced > 0;
     const size_t na = n + (size_t)p;
@@ -175,16 +225,7 @@ int orc_phi_krylov_op(size_t n, const Op &A, double tau, int p, const double *co
                 st->krylov_iters += 1;
                 st->jvps += 1;
             }
-            // classical Gram-Schmidt, two passes
-            for (int pass = 0; pass < 2; ++pass) {
-                std::vector<double> h(j);
-                for (int i = 0; i < j; ++i) h[i] = dot(&V[(size_t)i * na], w.data(), na);
-                for (int i = 0; i < j; ++i) {
-                    const double *vi = &V[(size_t)i * na];
-                    for (size_t r = 0; r < na; ++r) w[r] -= h[i] * vi[r];
-                    H[(size_t)i * ldh + (j - 1)] += h[i];
-                }
-            }
+            orthogonalize(V, na, H, ldh, j, o->iop, w.data());
             const double hn = norm2(w.data(), na);
             if (!std::isfinite(hn)) return -5;
             H[(size_t)j * ldh + (j - 1)] = hn;

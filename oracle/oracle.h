@@ -74,6 +74,8 @@ typedef struct {
     int check_every;   /* check the error every this many iterations */
     const orc_substep *forced; /* if n_forced > 0: replay this schedule */
     int n_forced;
+    int iop;           /* 0: full orthogonalization (two passes); L > 0: one
+                          pass against the L most recent vectors (KIOPS' IOP) */
 } orc_kopts;
 
 typedef struct {
@@ -118,6 +120,11 @@ int orc_expm(int n, const double *A, double *E);
 int orc_phi_dense(int n, const double *A, double tau, int p,
                   const double *const *b, double *out);
 
+/* m Arnoldi steps on a dense A (row-major) from b, with the orthogonalization
+ * of the phi evaluations (iop as in orc_kopts): V (m+1) x n row-major (vector
+ * i at V + i n), H (m+1) x m row-major.  Fails on a breakdown. */
+int orc_arnoldi_dense(int n, const double *A, const double *b, int m, int iop, double *V,
+                      double *H);
 /* Adaptive Krylov phi combination with a dense operator (row-major A). */
 int orc_phi_krylov_dense(int n, const double *A, double tau, int p,
                          const double *const *b, double *out,

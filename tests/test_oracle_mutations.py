@@ -15,6 +15,7 @@ import pytest
 
 import oracle
 from tests import test_oracle_dg as dg
+from tests import test_oracle_iop as iop
 from tests import test_oracle_phi as phi
 from tests import test_oracle_refelem as refelem
 from tests import test_oracle_steppers as steppers
@@ -51,6 +52,8 @@ MUTATIONS = {
     "dirichlet_ustar": ("dg.cpp", "T ustar = T(0.0);  // Dirichlet end: u** = 0",
                         "T ustar = u[(size_t)e * n1 + i];",
                         lambda: viscous.test_diffusion_energy_identity(0.0, oracle.BC_DIRICHLET, 2)),
+    "iop_window": ("krylov.cpp", "std::max(0, j - iop)", "std::max(0, j - iop - 1)",
+                   lambda: iop.test_arnoldi_relation_and_band(2)),
     "lgl_weight": ("refelem.cpp", "w[i] = 2.0 / (p * (p + 1.0) * P * P);",
                    "w[i] = 2.0 / ((p + 1.0) * (p + 1.0) * P * P);",
                    lambda: refelem.test_quadrature_exactness(3)),
