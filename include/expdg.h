@@ -142,6 +142,11 @@ typedef struct {
     int m_min, m_max, check_every;
     const expdg_substep *forced;
     int n_forced;
+    int iop;  /* 0: full orthogonalization (classical Gram-Schmidt applied
+                 twice); L in 1..64: incomplete orthogonalization, each new
+                 vector against the L most recent basis vectors only (one
+                 pass, explicit norm), the IOP option of KIOPS (Section 2.3).
+                 Served solves always use 0. */
 } expdg_krylov_opts;
 
 /* Statistics, accumulated over the call (zero them before the call).  If

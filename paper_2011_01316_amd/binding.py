@@ -50,7 +50,8 @@ class Substep(C.Structure):
 
 class KrylovOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("m_min", C.c_int), ("m_max", C.c_int),
-                ("check_every", C.c_int), ("forced", C.POINTER(Substep)), ("n_forced", C.c_int)]
+                ("check_every", C.c_int), ("forced", C.POINTER(Substep)), ("n_forced", C.c_int),
+                ("iop", C.c_int)]
 
 
 class KrylovStats(C.Structure):
@@ -217,15 +218,16 @@ def expdg_max_speed(handle, q, stream=None) -> float:
     return c.value
 
 
-def make_opts(tol=1e-10, m_min=10, m_max=64, check_every=1, forced=None):
-    """Krylov options; forced is a list of (m, dtau, last)."""
+def make_opts(tol=1e-10, m_min=10, m_max=64, check_every=1, forced=None, iop=0):
+    """Krylov options; forced is a list of (m, dtau, last); iop > 0 selects
+    incomplete orthogonalization against the iop most recent vectors."""
     keep = None
     if forced:
         keep = (Substep * len(forced))(*[Substep(int(m), int(last), float(dt))
                                          for (m, dt, last) in forced])
-        o = KrylovOpts(tol, m_min, m_max, check_every, keep, len(forced))
+        o = KrylovOpts(tol, m_min, m_max, check_every, keep, len(forced), iop)
     else:
-        o = KrylovOpts(tol, m_min, m_max, check_every, None, 0)
+        o = KrylovOpts(tol, m_min, m_max, check_every, None, 0, iop)
     o._keep = keep
     return o
 

@@ -489,6 +489,7 @@ int check_opts(const expdg_mesh *m, const expdg_krylov_opts *o) {
     if (o->m_min < 1 || o->m_max < o->m_min || o->m_max > m->d.m_max)
         return fail(EXPDG_EINVAL, "need 1 <= m_min <= m_max <= mesh m_max (%d)", m->d.m_max);
     if (o->check_every < 1) return fail(EXPDG_EINVAL, "check_every must be >= 1");
+    if (o->iop < 0 || o->iop > kMaxM) return fail(EXPDG_EINVAL, "iop must be in 0..64");
     return EXPDG_OK;
 }
 
@@ -554,13 +555,14 @@ struct DirectExec {
     // Arnoldi step k: the operator on x = u_{k-1} (and, in 2D, the dot pass
     // in its epilogue), the dot pass (1D), the finish, the update sweep.
     int iterate_now(expdg_mesh *m, const OpArgs<T> &a, int k, int naug_nz, const CheckReq *cr,
-                    Check *c) {
+                    Check *c, bool iop) {
         const size_t n = m->n, L = n + (size_t)a.naug, stride = m->stride;
         const RowPartition rp = row_partition(L);
         const KrylovDev &kd = m->kd;
         T *V = (T *)m->V;
         T *x = V + (size_t)(k - 1) * stride, *w = a.out;
-        const int nv = k - 1;
+        const T *basis = a.basis;
+        const int nv = a.nv;  // vectors the dot pass and the update read
         const double eb = (double)sizeof(T);
         const bool fused = a.dots != 0;
         TRY(prof_begin(m, EXPDG_K_LINEAR));
@@ -569,25 +571,33 @@ struct DirectExec {
                      op_bytes(m, true) + (double)(naug_nz + (fused ? nv : 0)) * n * eb));
         if (!fused) {
             TRY(prof_begin(m, EXPDG_K_GS_DOTS));
-            HIPTRY(launch_gs_dots2<T>(V, stride, nv, x, w, L, rp, kd.part, s));
+            HIPTRY(launch_gs_dots2<T>(basis, stride, nv, x, w, L, rp, kd.part, s));
             TRY(prof_end(m, EXPDG_K_GS_DOTS, (double)(nv + 2) * L * eb));
         }
         const int nrb = fused ? a.dnb : rp.nrb;
         TRY(prof_begin(m, EXPDG_K_GS_FINISH));
-        HIPTRY(launch_dcgs_finish(kd.part, nrb, k, kd.S, kd.H, kd.coefA, kd.coefB, kd.flags, s));
+        if (iop)
+            HIPTRY(launch_iop_finish(kd.part, nrb, k, k - 1 - nv, nv, kd.S, kd.H, kd.coefA,
+                                     kd.coefB, kd.flags, s));
+        else
+            HIPTRY(launch_dcgs_finish(kd.part, nrb, k, kd.S, kd.H, kd.coefA, kd.coefB, kd.flags,
+                                      s));
         TRY(prof_end(m, EXPDG_K_GS_FINISH, 8.0 * nrb * (2 * nv + 2)));
         // the check needs H and S only: it starts while the update sweep runs
         if (cr) TRY(mark_check(m, *cr, c));
         TRY(prof_begin(m, EXPDG_K_GS_UPDATE));
-        HIPTRY(launch_dcgs_update<T>(V, stride, nv, kd.coefA, kd.coefB, x, w, L, rp, s));
-        TRY(prof_end(m, EXPDG_K_GS_UPDATE, (double)(nv + (nv > 0 ? 4 : 3)) * L * eb));
+        // incomplete orthogonalization leaves x as it is (only its scale is new)
+        HIPTRY(launch_dcgs_update<T>(basis, stride, nv, kd.coefA, kd.coefB, x, w, L, rp, s,
+                                     !iop));
+        TRY(prof_end(m, EXPDG_K_GS_UPDATE,
+                     (double)(nv + ((nv > 0 && !iop) ? 4 : 3)) * L * eb));
         if (cr) TRY(submit_check(m, *cr, *c));
         return EXPDG_OK;
     }
 
     Ready iterate(expdg_mesh *m, const OpArgs<T> &a, int k, int naug_nz, const CheckReq *cr,
-                  Check *c) {
-        return Ready{iterate_now(m, a, k, naug_nz, cr, c)};
+                  Check *c, bool iop) {
+        return Ready{iterate_now(m, a, k, naug_nz, cr, c, iop)};
     }
     Ready check(expdg_mesh *m, const CheckReq &r, Check *c) { return Ready{enqueue_check(m, r, c)}; }
     Ready wait_check(expdg_mesh *m, const Check &c) { return Ready{sync_event(m->ev[c.slot])}; }

@@ -18,10 +18,11 @@
 //
 // An executor X provides
 //   hipStream_t stream();
-//   awaitable<int> iterate(m, a, k, naug_nz, const CheckReq *chk, Check *c):
-//       the Arnoldi step k (linear operator on u_{k-1}, dot pass, finish,
-//       update sweep; it finishes dimension k - 1) and, if chk, the check of
-//       dimension k - 1 behind it;
+//   awaitable<int> iterate(m, a, k, naug_nz, const CheckReq *chk, Check *c, bool iop):
+//       the Arnoldi step k (linear operator on u_{k-1}, dot pass over the a.nv
+//       vectors from a.basis, finish, update sweep; it finishes dimension
+//       k - 1) and, if chk, the check of dimension k - 1 behind it; iop: the
+//       incomplete orthogonalization's finish and update (window in a.basis);
 //   awaitable<int> check(m, req, Check *c): a check on the current basis;
 //   awaitable<int> wait_check(m, c): the check's header is in the pinned mirror;
 //   int after_check(m, c): the stream waits for the check's coefficients;
@@ -179,6 +180,7 @@ Task<int> phi_co(X &x, expdg_mesh *m, const T *qref, double tau, int p, const T 
     T *V = (T *)m->V;
     KrylovDev &kd = m->kd;
     const bool forced = o->n_forced > 0;
+    const bool iop = o->iop > 0;
     const RowPartition rp = row_partition(L);
     if (st) st->phi_calls += 1;
 
@@ -271,14 +273,18 @@ Task<int> phi_co(X &x, expdg_mesh *m, const T *qref, double tau, int p, const T 
             a.out = w;
             a.vtail = vin + n;
             a.otail = w + n;
-            a.nv = k - 1;
+            // full orthogonalization: the dot pass runs over u_0..u_{k-2};
+            // incomplete (window of L): over the last min(k-1, L-1) of them
+            const int k0 = iop ? std::max(0, k - o->iop) : 0;
+            a.basis = V + (size_t)k0 * stride;
+            a.nv = k - 1 - k0;
             const bool is_check = !forced && D >= 1 &&
                                   (D == o->m_max ||
                                    (D >= o->m_min && (D - o->m_min) % o->check_every == 0));
             CheckReq cr{};
             if (is_check) cr = R.req(D, R.dt_sub);
             Check cur;
-            CO_TRY(co_await x.iterate(m, a, k, naug_nz, is_check ? &cr : nullptr, &cur));
+            CO_TRY(co_await x.iterate(m, a, k, naug_nz, is_check ? &cr : nullptr, &cur, iop));
             if (st) {
                 st->krylov_iters += 1;
                 st->jvps += 1;

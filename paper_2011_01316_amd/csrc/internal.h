@@ -186,12 +186,24 @@ hipError_t launch_gs_dots2(const T *V, size_t stride, int nv, const T *x, const 
 // beta), coefB[kScalW] = 1 / beta, coefB[kScalX] = e_{k-1} / beta.
 hipError_t launch_dcgs_finish(const double *part, int nrb, int k, double *S, double *H,
                               double *coefA, double *coefB, int *flags, hipStream_t s);
-// One sweep of step k: x -= sum_{i<nv} coefA[i] u_i (skipped for nv = 0) and
-// w <- coefB[kScalW] w - coefB[kScalX] x_old - sum_{i<nv} coefB[i] u_i.
+// One sweep of step k: x -= sum_{i<nv} coefA[i] u_i (only if write_x and
+// nv > 0) and w <- coefB[kScalW] w - coefB[kScalX] x_old - sum_{i<nv} coefB[i] u_i.
 template <typename T>
 hipError_t launch_dcgs_update(const T *V, size_t stride, int nv, const double *coefA,
                               const double *coefB, T *x, T *w, size_t L, const RowPartition &rp,
-                              hipStream_t s);
+                              hipStream_t s, bool write_x = true);
+// Incomplete orthogonalization (window of L vectors), finish of step k: x =
+// u_{k-1} (stored unnormalised), w = A x, and the nw = min(k-1, L-1) window
+// vectors u_{k0}, ..., u_{k-2} (k0 = k-1-nw) with block partials in the rows
+// of launch_gs_dots2 (basis = u_{k0}, nv = nw).  k > 1: beta = ||x|| (explicit
+// norm), H[k-1][k-2] = beta, breakdown / non-finite tests as in
+// launch_dcgs_finish, S[k-1] = 1/beta; k = 1: beta = 1/S[0].  Column k-1 of H:
+// h_i = S[k0+i] (u_{k0+i}^T w) / beta on the window, h_{k-1,k-1} = x^T w /
+// beta^2.  The update sweep (write_x = false) then forms u_k = w / beta -
+// sum_i h_i v_{k0+i} - h_{k-1,k-1} x / beta: coefA = 0, coefB[i] = S[k0+i] h_i,
+// coefB[kScalW] = 1/beta, coefB[kScalX] = h_{k-1,k-1} / beta.
+hipError_t launch_iop_finish(const double *part, int nrb, int k, int k0, int nw, double *S,
+                             double *H, double *coefA, double *coefB, int *flags, hipStream_t s);
 // Start vector of a substep: block partials of ||z||^2 (z = V_0) ...
 template <typename T>
 hipError_t launch_gs_norm(const T *z, size_t L, const RowPartition &rp, double *part,

@@ -409,7 +409,7 @@ template <typename T>
 __device__ __forceinline__ void dcgs_update_body(const T *__restrict__ V, size_t stride, int nv,
                                                  const double *cA, const double *cB,
                                                  T *__restrict__ x, T *__restrict__ w, size_t L,
-                                                 size_t rpb, int rb) {
+                                                 size_t rpb, int rb, bool wx) {
     __shared__ double sA[kMaxM], sB[kMaxM], sWX[2];
     const int tid = threadIdx.x;
     if (tid < nv) {
@@ -455,7 +455,7 @@ __device__ __forceinline__ void dcgs_update_body(const T *__restrict__ V, size_t
                 }
             }
         }
-        if (nv > 0) st16(x + r, xn);
+        if (wx) st16(x + r, xn);
         st16(w + r, wn);
     }
     for (size_t r = r0 + nsw * 256 * N + tid; r < r1; r += 256) {
@@ -466,7 +466,7 @@ __device__ __forceinline__ void dcgs_update_body(const T *__restrict__ V, size_t
             xn -= sA[i] * u;
             wn -= sB[i] * u;
         }
-        if (nv > 0) x[r] = (T)xn;
+        if (wx) x[r] = (T)xn;
         w[r] = (T)wn;
     }
 }
@@ -476,8 +476,83 @@ __global__ __launch_bounds__(256) void dcgs_update_kernel(const T *__restrict__ 
                                                           int nv, const double *cA,
                                                           const double *cB, T *__restrict__ x,
                                                           T *__restrict__ w, size_t L,
-                                                          size_t rpb) {
-    dcgs_update_body<T>(V, stride, nv, cA, cB, x, w, L, rpb, blockIdx.x);
+                                                          size_t rpb, int wx) {
+    dcgs_update_body<T>(V, stride, nv, cA, cB, x, w, L, rpb, blockIdx.x, wx != 0);
+}
+
+// Finish of step k with incomplete orthogonalization (window of L vectors):
+// see launch_iop_finish.
+struct IopFinish {
+    double *S, *H;
+    int k, k0, nw;
+    double *coefA, *coefB;
+    int *flags;
+};
+
+__global__ __launch_bounds__(kFin2Threads) void iop_finish_kernel(const double *part, int nrb,
+                                                                  IopFinish f) {
+    constexpr int NW = kFin2Threads / 64;
+    __shared__ double sv[kPartRows];
+    __shared__ double sw[NW];
+    __shared__ double sbeta;
+    const int k = f.k, nw = f.nw, k0 = f.k0, col = k - 2;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double *H = f.H, *S = f.S;
+    fin_row_sums(part, 2 * nw + 2, nrb, sv);
+    __syncthreads();
+    const double gam = sv[2 * nw], del = sv[2 * nw + 1];
+    if (k == 1) {
+        // x = u_0 is the start vector, its norm already known
+        if (tid == 0) sbeta = 1.0 / S[0];
+        __syncthreads();
+    } else {
+        // the explicit norm of the stored u_{k-1} finishes column k-2
+        const double beta = sqrt(gam);
+        double acc = 0.0;
+        for (int r = wave; r < k; r += NW)
+            for (int c = lane; c <= col; c += 64) {
+                const double h = (r == k - 1 && c == col) ? beta
+                                 : (r <= c + 1)           ? H[(size_t)r * LDH + c]
+                                                          : 0.0;
+                acc += h * h;
+            }
+        acc = wave_sum(acc);
+        if (lane == 0) sw[wave] = acc;
+        __syncthreads();
+        if (tid == 0) {
+            double s2 = 0.0;
+            for (int q = 0; q < NW; ++q) s2 += sw[q];
+            const double hf = sqrt(s2);
+            if ((!isfinite(beta) || !isfinite(hf)) && f.flags[1] == 0) f.flags[1] = k - 1;
+            const bool brk = beta <= 1e-12 * hf;
+            if (brk) {
+                H[(size_t)(k - 1) * LDH + col] = 0.0;
+                S[k - 1] = 0.0;
+                if (f.flags[0] == 0) f.flags[0] = k - 1;
+            } else {
+                H[(size_t)(k - 1) * LDH + col] = beta;
+                S[k - 1] = 1.0 / beta;
+            }
+            sbeta = brk ? 1.0 : beta;  // after a breakdown the step only has to stay finite
+        }
+        __syncthreads();
+    }
+    const double bet = sbeta;
+    // column k-1: h_i = v_i^T A v_{k-1} = S_i (u_i^T w) / beta over the window,
+    // and the diagonal x^T w / beta^2; u_k = w / beta - sum_i h_i v_i - h_d x / beta
+    if (tid < nw) {
+        const double Sg = S[k0 + tid];
+        const double h = Sg * sv[tid] / bet;
+        H[(size_t)(k0 + tid) * LDH + (k - 1)] = h;
+        f.coefA[tid] = 0.0;
+        f.coefB[tid] = Sg * h;
+    }
+    if (tid == 0) {
+        const double hd = del / (bet * bet);
+        H[(size_t)(k - 1) * LDH + (k - 1)] = hd;
+        f.coefB[kScalW] = 1.0 / bet;
+        f.coefB[kScalX] = hd / bet;
+    }
 }
 
 template <typename T>
@@ -836,7 +911,7 @@ __global__ __launch_bounds__(256) void dcgs_update_group(const GsItem *items, co
     const int it = group_item(bstart, n, blockIdx.x);
     const GsItem &g = items[it];
     dcgs_update_body<double>(g.V, g.stride, g.k - 1, g.coefA, g.coefB, g.x, g.w, g.L, g.rpb,
-                             blockIdx.x - bstart[it]);
+                             blockIdx.x - bstart[it], g.k > 1);
 }
 
 constexpr size_t kExpmLds = (size_t)4 * NMAX * LDA * sizeof(double);
@@ -887,10 +962,18 @@ hipError_t launch_dcgs_finish(const double *part, int nrb, int k, double *S, dou
 template <typename T>
 hipError_t launch_dcgs_update(const T *V, size_t stride, int nv, const double *coefA,
                               const double *coefB, T *x, T *w, size_t L, const RowPartition &rp,
-                              hipStream_t s) {
+                              hipStream_t s, bool write_x) {
     if (nv < 0 || nv > kMaxM) return hipErrorInvalidValue;
     return launch_kernel(dcgs_update_kernel<T>, dim3(rp.nrb), dim3(256), 0, s, V, stride, nv,
-                         coefA, coefB, x, w, L, rp.rpb);
+                         coefA, coefB, x, w, L, rp.rpb, (write_x && nv > 0) ? 1 : 0);
+}
+
+hipError_t launch_iop_finish(const double *part, int nrb, int k, int k0, int nw, double *S,
+                             double *H, double *coefA, double *coefB, int *flags, hipStream_t s) {
+    if (k < 1 || k > kMaxM + 1 || nrb < 1 || nw < 0 || k0 < 0 || k0 + nw != k - 1)
+        return hipErrorInvalidValue;
+    return launch_kernel(iop_finish_kernel, dim3(1), dim3(kFin2Threads), 0, s, part, nrb,
+                         IopFinish{S, H, k, k0, nw, coefA, coefB, flags});
 }
 
 template <typename T>
@@ -910,7 +993,7 @@ hipError_t launch_gs_finish_norm(const double *part, const RowPartition &rp, dou
                                            const RowPartition &, double *, hipStream_t);        \
     template hipError_t launch_dcgs_update<T>(const T *, size_t, int, const double *,           \
                                               const double *, T *, T *, size_t,                 \
-                                              const RowPartition &, hipStream_t);               \
+                                              const RowPartition &, hipStream_t, bool);         \
     template hipError_t launch_gs_norm<T>(const T *, size_t, const RowPartition &, double *,    \
                                           hipStream_t);
 EXPDG_INST(double)

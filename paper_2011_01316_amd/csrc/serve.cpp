@@ -143,8 +143,10 @@ struct ServeExec {
     };
 
     hipStream_t stream() const;
+    // served solves use full orthogonalization (the server builds their
+    // options with iop = 0), so iop is always false here
     Await iterate(expdg_mesh *m, const OpArgs<double> &a, int k, int naug_nz, const CheckReq *cr,
-                  Check *c);
+                  Check *c, bool iop);
     Await check(expdg_mesh *m, const CheckReq &q, Check *c);
     Await wait_check(expdg_mesh *m, const Check &c);
     int after_check(expdg_mesh *m, const Check &c);
@@ -248,8 +250,9 @@ namespace {
 hipStream_t ServeExec::stream() const { return sv->s; }
 
 ServeExec::Await ServeExec::iterate(expdg_mesh *m, const OpArgs<double> &a, int k, int naug_nz,
-                                    const CheckReq *cr, Check *c) {
+                                    const CheckReq *cr, Check *c, bool iop) {
     (void)naug_nz;
+    (void)iop;
     IterRec rec;
     rec.r = r;
     rec.a = a;
