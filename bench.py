@@ -77,7 +77,7 @@ def log(msg):
 
 
 class Case:
-    def __init__(self, B, inputs, torch, w, precision, scheme=None):
+    def __init__(self, B, inputs, torch, w, precision, scheme=None, iop=0):
         self.B, self.torch, self.w = B, torch, w
         self.scheme = B.EPI3 if scheme is None else scheme
         self.mesh = B.Mesh(B.EULER2D, w["nx"], w["p"], ny=w["ny"], x0=0.0, x1=10.0, y0=0.0,
@@ -87,7 +87,7 @@ class Case:
                               dtype=torch.float64, device="cuda:0")
         self.qp = torch.empty_like(self.q)
         self.dt = w["cr"] * self.mesh.dx_min / self.mesh.max_speed(self.q)
-        self.opts = B.make_opts(w["tol"], w["m_min"], w["m_max"])
+        self.opts = B.make_opts(w["tol"], w["m_min"], w["m_max"], iop=iop)
         self.have = False
         self.nsteps = 0
 
@@ -208,7 +208,22 @@ def run_viscous(args):
             res["kernel_time_share"] = {k: round(v["total_ms"] / tot, 4) for k, v in pr.items()}
     for c in B.KERNEL_CLASSES:
         B.expdg_profile_enable(m.handle, c, False)
-    log(f"viscous Burgers 131072 x p4: {res['ms_per_step']:.3f} ms/step")
+    # the same steps with incomplete orthogonalization (window of 2)
+    q2 = torch.tensor(inputs.burgers_smooth(x), dtype=torch.float64, device="cuda:0")
+    oi = B.make_opts(w["tol"], 5, 64, iop=2)
+    m.integrate(B.EXPRB32, dt, 2, q2, None, False, oi, B.make_stats())
+    st = B.make_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.integrate(B.EXPRB32, dt, w["steps"], q2, None, False, oi, st)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    d = B.stats_dict(st)
+    res["iop2"] = dict(ms_per_step=round(secs / w["steps"] * 1e3, 4),
+                       value=round(m.n * (d["rhs_calls"] + d["jvps"]) / secs, 1),
+                       krylov_iters_per_step=d["krylov_iters"] / w["steps"])
+    log(f"viscous Burgers 131072 x p4: {res['ms_per_step']:.3f} ms/step, "
+        f"iop2 {res['iop2']['ms_per_step']:.3f}")
     m.close()
     out["large"] = res
     return out
@@ -252,6 +267,17 @@ def run_gpu(args):
     log(f"exprb42 timed: {r42['ms_per_step']:.3f} ms/step")
     out["exprb42"] = r42
     c42.mesh.close()
+
+    # incomplete orthogonalization (window of 2, KIOPS' IOP) on the same workload
+    ci = Case(B, inputs, torch, C2, B.FP64, iop=2)
+    ci.run(args.warmup)
+    ri = ci.run(args.steps)
+    ri["l2_rel_err_vs_exact"], qi = ci.exact_error(inputs, np)
+    ri["l2_rel_diff_vs_full"] = float(np.linalg.norm(qi - q64) / np.linalg.norm(q64))
+    ri["profile"] = ci.profile(args.steps)["profile"]
+    log(f"iop2 timed: {ri['ms_per_step']:.3f} ms/step, {ri['krylov_iters_per_step']:.1f} its/step")
+    out["iop2"] = ri
+    ci.mesh.close()
 
     if not args.no_fp32:
         c32 = Case(B, inputs, torch, C2, B.FP32_BULK)
@@ -512,6 +538,18 @@ def main():
         "instrumented_ms_per_step": round(g["profile"]["ms_per_step"], 4),
         "l2_rel_err_vs_exact_vortex": f64["l2_rel_err_vs_exact"],
     }
+    ei = g["iop2"]
+    pi = ei["profile"]
+    line["iop2"] = dict(value=round(ei["value"], 1), unit=UNIT,
+                        ms_per_step=round(ei["ms_per_step"], 4),
+                        step_speedup_vs_full=round(f64["ms_per_step"] / ei["ms_per_step"], 3),
+                        krylov_iters_per_step=ei["krylov_iters_per_step"],
+                        l2_rel_err_vs_exact_vortex=ei["l2_rel_err_vs_exact"],
+                        l2_rel_diff_vs_full_orthogonalization=ei["l2_rel_diff_vs_full"],
+                        kernel_avg_us={k: round(v["total_ms"] * 1e3 / max(1, v["launches"]), 3)
+                                       for k, v in pi.items()},
+                        linear_operator_roofline=roof(pi["linear_operator"], "linear_operator",
+                                                      B.KERNEL_SYMBOLS["linear_operator"]))
     e42 = g["exprb42"]
     line["exprb42"] = dict(value=round(e42["value"], 1), unit=UNIT,
                            ms_per_step=round(e42["ms_per_step"], 4),

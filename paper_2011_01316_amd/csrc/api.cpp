@@ -301,7 +301,8 @@ void release(expdg_mesh *m) {
         if (e) (void)hipEventDestroy(e);
     for (auto &e : m->evH)
         if (e) (void)hipEventDestroy(e);
-    if (m->side) (void)hipStreamDestroy(m->side);
+    for (auto &st : m->side)
+        if (st) (void)hipStreamDestroy(st);
     for (auto &P : m->prof)
         for (auto &e : P.ev) (void)hipEventDestroy(e);
 }
@@ -356,9 +357,12 @@ extern "C" int expdg_mesh_create(const expdg_mesh_desc *d, expdg_mesh **out) {
     for (auto &e : m->evH)
         if (rc == EXPDG_OK && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
             rc = fail(EXPDG_EDEVICE, "hipEventCreate failed");
-    // default-priority side stream for the small exponentials
-    if (rc == EXPDG_OK && hipStreamCreateWithFlags(&m->side, hipStreamNonBlocking) != hipSuccess)
-        rc = fail(EXPDG_EDEVICE, "hipStreamCreate failed");
+    // two default-priority side streams for the small exponentials: checks
+    // alternate between them by slot parity, so two run at once (a slot's
+    // next user queues behind its previous one on the same stream)
+    for (auto &st : m->side)
+        if (rc == EXPDG_OK && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess)
+            rc = fail(EXPDG_EDEVICE, "hipStreamCreate failed");
     if (rc == EXPDG_OK) {
         // zero the whole workspace once (vector padding stays zero)
         if (hipMemset(m->block, 0, m->bytes) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
@@ -509,8 +513,9 @@ void log_sub(expdg_krylov_stats *st, int mm, int last, double dtau) {
 namespace {
 
 // Launches everything at once on stream s; a check's small exponential runs on
-// the mesh's side stream behind the Hessenberg column it needs, overlapping
-// the next Arnoldi step, and is read back one step later.
+// one of the mesh's two side streams behind the Hessenberg column it needs,
+// overlapping the next Arnoldi steps (and the previous check), and is read
+// back one step later.
 template <typename T>
 struct DirectExec {
     // a check is decided one Arnoldi step after the one that launched it (a
@@ -522,7 +527,7 @@ struct DirectExec {
 
     // A check in two parts: mark_check records, on the main stream, the point
     // after which H and S hold what the check reads; submit_check queues the
-    // small exponential behind that point on the side stream.  Main-stream
+    // small exponential behind that point on a side stream.  Main-stream
     // work enqueued in between does not wait for the side-stream calls.
     int mark_check(expdg_mesh *m, const CheckReq &r, Check *c) {
         c->j = r.j;
@@ -531,7 +536,8 @@ struct DirectExec {
         return EXPDG_OK;
     }
     int submit_check(expdg_mesh *m, const CheckReq &r, const Check &c) {
-        HIPTRY(hipStreamWaitEvent(m->side, m->evH[c.slot], 0));
+        hipStream_t side = m->side[c.slot & 1];
+        HIPTRY(hipStreamWaitEvent(side, m->evH[c.slot], 0));
         const KrylovDev &kd = m->kd;
         ExpmItem it{kd.H,
                     kd.S,
@@ -542,9 +548,9 @@ struct DirectExec {
                     r.dtau,
                     r.j};
         TRY(prof_begin(m, EXPDG_K_SMALLEXPM));
-        HIPTRY(launch_hess_expm(it, m->side));
+        HIPTRY(launch_hess_expm(it, side));
         TRY(prof_end(m, EXPDG_K_SMALLEXPM, 0.0));
-        HIPTRY(hipEventRecord(m->ev[c.slot], m->side));
+        HIPTRY(hipEventRecord(m->ev[c.slot], side));
         return EXPDG_OK;
     }
     int enqueue_check(expdg_mesh *m, const CheckReq &r, Check *c) {
@@ -607,8 +613,9 @@ struct DirectExec {
     }
     Ready readback(expdg_mesh *) { return Ready{sync_stream(s)}; }
     Ready finish(expdg_mesh *m) {
-        // no speculative check left running on the side stream
-        int rc = sync_stream(m->side);
+        // no speculative check left running on a side stream
+        int rc = sync_stream(m->side[0]);
+        if (rc == EXPDG_OK) rc = sync_stream(m->side[1]);
         if (rc == EXPDG_OK) rc = sync_stream(s);
         return Ready{rc};
     }

@@ -168,8 +168,9 @@ struct PhiRun {
 // is a zero vector.  *fpos walks a forced substep schedule.  lin_ready: the
 // frozen fields of qref are already in the workspace.  nested: called inside a
 // step, whose own end waits for the device, so this evaluation ends without
-// waiting (a speculative check may still run on the side stream; it only
-// writes its own result slot, and later checks queue behind it).
+// waiting (a speculative check may still run on a side stream; it only
+// writes its own result slot, and a later check that reuses the slot queues
+// behind it on the same side stream).
 template <typename T, typename X>
 Task<int> phi_co(X &x, expdg_mesh *m, const T *qref, double tau, int p, const T *const *b, T *out,
                  const expdg_krylov_opts *o, expdg_krylov_stats *st, int *fpos, bool lin_ready,

@@ -40,7 +40,7 @@ struct expdg_mesh {
     bool owns_pin = false;
     hipEvent_t ev[expdg::kCheckSlots] = {};   // check results ready (side stream)
     hipEvent_t evH[expdg::kCheckSlots] = {};  // Hessenberg column ready (main stream)
-    hipStream_t side = nullptr;              // small exponentials run here
+    hipStream_t side[2] = {};                // small exponentials run here (slot parity)
     size_t bytes = 0;
 
     // live timing of one or more kernel classes
