@@ -269,15 +269,17 @@ def run_gpu(args):
     c42.mesh.close()
 
     # incomplete orthogonalization (window of 2, KIOPS' IOP) on the same workload
-    ci = Case(B, inputs, torch, C2, B.FP64, iop=2)
-    ci.run(args.warmup)
-    ri = ci.run(args.steps)
-    ri["l2_rel_err_vs_exact"], qi = ci.exact_error(inputs, np)
-    ri["l2_rel_diff_vs_full"] = float(np.linalg.norm(qi - q64) / np.linalg.norm(q64))
-    ri["profile"] = ci.profile(args.steps)["profile"]
-    log(f"iop2 timed: {ri['ms_per_step']:.3f} ms/step, {ri['krylov_iters_per_step']:.1f} its/step")
-    out["iop2"] = ri
-    ci.mesh.close()
+    if not args.no_iop:
+        ci = Case(B, inputs, torch, C2, B.FP64, iop=2)
+        ci.run(args.warmup)
+        ri = ci.run(args.steps)
+        ri["l2_rel_err_vs_exact"], qi = ci.exact_error(inputs, np)
+        ri["l2_rel_diff_vs_full"] = float(np.linalg.norm(qi - q64) / np.linalg.norm(q64))
+        ri["profile"] = ci.profile(args.steps)["profile"]
+        log(f"iop2 timed: {ri['ms_per_step']:.3f} ms/step, "
+            f"{ri['krylov_iters_per_step']:.1f} its/step")
+        out["iop2"] = ri
+        ci.mesh.close()
 
     if not args.no_fp32:
         c32 = Case(B, inputs, torch, C2, B.FP32_BULK)
@@ -474,6 +476,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-viscous", action="store_true")
+    ap.add_argument("--no-iop", action="store_true")
     ap.add_argument("--viscous-only", action="store_true",
                     help="only the viscous Burgers measurements (one JSON line)")
     ap.add_argument("--serve-requests", type=int, default=SERVED["n_requests"])
@@ -538,9 +541,9 @@ def main():
         "instrumented_ms_per_step": round(g["profile"]["ms_per_step"], 4),
         "l2_rel_err_vs_exact_vortex": f64["l2_rel_err_vs_exact"],
     }
-    ei = g["iop2"]
-    pi = ei["profile"]
-    line["iop2"] = dict(value=round(ei["value"], 1), unit=UNIT,
+    ei = g.get("iop2")
+    pi = ei["profile"] if ei else None
+    line["iop2"] = None if ei is None else dict(value=round(ei["value"], 1), unit=UNIT,
                         ms_per_step=round(ei["ms_per_step"], 4),
                         step_speedup_vs_full=round(f64["ms_per_step"] / ei["ms_per_step"], 3),
                         krylov_iters_per_step=ei["krylov_iters_per_step"],

@@ -43,8 +43,9 @@ def build(verbose: bool = False) -> str:
         if p.returncode != 0:
             failed.append(src)
             sys.stderr.write("\n".join(lines) + "\n")
-        elif verbose and lines:
-            print("\n".join(lines))
+        elif lines:
+            # warnings are shown on every build
+            sys.stderr.write("\n".join(lines) + "\n")
     if failed:
         raise RuntimeError("hipcc failed for: " + ", ".join(failed))
     tmp = LIB + ".tmp"

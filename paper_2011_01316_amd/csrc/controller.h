@@ -182,6 +182,7 @@ Task<int> phi_co(X &x, expdg_mesh *m, const T *qref, double tau, int p, const T 
     KrylovDev &kd = m->kd;
     const bool forced = o->n_forced > 0;
     const bool iop = o->iop > 0;
+    const int lookahead = X::kLookahead + (iop ? 1 : 0);  // at most kCheckSlots - 2
     const RowPartition rp = row_partition(L);
     if (st) st->phi_calls += 1;
 
@@ -292,10 +293,12 @@ Task<int> phi_co(X &x, expdg_mesh *m, const T *qref, double tau, int p, const T 
             }
             if (forced) continue;
             // decide the checks at least kLookahead steps old (all of them at
-            // the last step): the device works on the newer steps meanwhile
+            // the last step): the device works on the newer steps meanwhile.
+            // The short steps of incomplete orthogonalization take one step
+            // more, so that a check (longer than such a step) is done by then.
             if (is_check) pend[np++] = cur;
             bool done = false;
-            while (np > 0 && (D == m_target || pend[0].j <= D - X::kLookahead)) {
+            while (np > 0 && (D == m_target || pend[0].j <= D - lookahead)) {
                 const Check c = pend[0];
                 for (int q = 1; q < np; ++q) pend[q - 1] = pend[q];
                 --np;

@@ -627,7 +627,8 @@ int launch_batch(expdg_server *sv) {
     }
     if (n > 0) {
         HIPTRY(launch_arnoldi_group(d_gs, d_gb, totals, n, sv->s));
-        sv->st.grouped_launches += (totals[2] > 0 ? 1 : 0) + (totals[3] > 0 ? 2 : 0) + 5;
+        // the separate dot pass (if any item needs it), the finish, the update
+        sv->st.grouped_launches += (totals[0] > 0 ? 1 : 0) + 2;
         sv->st.arnoldi_items += n;
     }
     HIPTRY(hipEventRecord(b.ev_main, sv->s));

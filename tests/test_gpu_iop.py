@@ -180,3 +180,22 @@ def test_iop_rejects_bad_length():
         assert ei.value.code == B.EINVAL
         with pytest.raises(B.ExpdgError):
             gm.phi_krylov(q, 0.1, [q], w, B.make_opts(iop=65))
+
+
+def test_iop_fp32_bulk_step():
+    # FP32 basis and operators with L = 2 against the FP64 run with L = 2: the
+    # same state-level bound as for full orthogonalization in FP32 bulk
+    om = oracle.Mesh(oracle.EULER2D, 32, 4, ny=32, x0=0.0, x1=10.0, y0=0.0, y1=10.0)
+    x, y = om.nodes()
+    q0 = inputs.vortex(x, y).reshape(-1)
+    c, dx = om.max_speed(q0)
+    dt = 5.0 * dx / c
+    out = {}
+    for prec, tol in ((B.FP64, 1e-10), (B.FP32_BULK, 1e-7)):
+        with B.Mesh(B.EULER2D, 32, 4, ny=32, x0=0.0, x1=10.0, y0=0.0, y1=10.0,
+                    precision=prec) as gm:
+            q = dev(q0)
+            qp = torch.empty_like(q)
+            gm.integrate(B.EPI3, dt, 3, q, qp, False, B.make_opts(tol, 10, 64, iop=2))
+            out[prec] = host(q)
+    assert rel(out[B.FP32_BULK], out[B.FP64]) < 1e-6, rel(out[B.FP32_BULK], out[B.FP64])
