@@ -28,6 +28,7 @@ SOURCES = ["refelem.cpp", "dg.cpp", "expm.cpp", "krylov.cpp", "steppers.cpp"]
 
 BURGERS1D = 1
 EULER2D = 2
+EULER3D = 3
 EPI2, EPI3, EXPRB32, EXPRB42 = 2, 3, 32, 42
 FLUX_LF, FLUX_EF = 0, 1
 BC_PERIODIC, BC_DIRICHLET = 0, 1
@@ -51,7 +52,8 @@ class _Mesh(C.Structure):
                 ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
                 ("gamma", C.c_double), ("kappa", C.c_double), ("flux", C.c_int),
                 ("sigma", C.c_double), ("beta", C.c_double), ("bc", C.c_int),
-                ("source", C.POINTER(C.c_double))]
+                ("source", C.POINTER(C.c_double)), ("nz", C.c_int), ("z0", C.c_double),
+                ("z1", C.c_double)]
 
 
 class Substep(C.Structure):
@@ -121,7 +123,7 @@ def _declare(L):
     mp = C.POINTER(_Mesh)
     L.orc_lgl.argtypes = [C.c_int, dp, dp, dp]
     L.orc_ndof.argtypes = [mp]
-    L.orc_nodes.argtypes = [mp, dp, dp]
+    L.orc_nodes.argtypes = [mp, dp, dp, dp]
     L.orc_mass.argtypes = [mp, dp]
     L.orc_rhs.argtypes = [mp, dp, dp]
     L.orc_jvp.argtypes = [mp, dp, dp, dp]
@@ -165,17 +167,21 @@ class Mesh:
     def __init__(self, equation: int, nx: int, p: int, ny: int = 1, x0: float = 0.0,
                  x1: float = 1.0, y0: float = 0.0, y1: float = 1.0, gamma: float = 1.4,
                  kappa: float = 0.0, flux: int = FLUX_LF, sigma: float = 0.0,
-                 beta: float = 0.0, bc: int = BC_PERIODIC, source=None):
-        self.equation, self.nx, self.ny, self.p = equation, nx, ny, p
+                 beta: float = 0.0, bc: int = BC_PERIODIC, source=None, nz: int = 1,
+                 z0: float = 0.0, z1: float = 1.0):
+        self.equation, self.nx, self.ny, self.nz, self.p = equation, nx, ny, nz, p
+        self.z0, self.z1 = z0, z1
         self.x0, self.x1, self.y0, self.y1, self.gamma = x0, x1, y0, y1, gamma
         self.kappa, self.flux, self.sigma, self.beta, self.bc = kappa, flux, sigma, beta, bc
         self.source = None if source is None else np.ascontiguousarray(source, dtype=np.float64)
         sp = _dp(self.source) if self.source is not None else C.POINTER(C.c_double)()
         self._m = _Mesh(equation, nx, ny, p, x0, x1, y0, y1, gamma, kappa, flux, sigma, beta,
-                        bc, sp)
-        self.nvar = 1 if equation == BURGERS1D else 4
-        self.Np = (p + 1) if equation == BURGERS1D else (p + 1) ** 2
-        self.K = nx * ny
+                        bc, sp, nz, z0, z1)
+        dim = {BURGERS1D: 1, EULER2D: 2, EULER3D: 3}.get(equation, 1)
+        self.dim = dim
+        self.nvar = 1 if equation == BURGERS1D else dim + 2
+        self.Np = (p + 1) ** dim
+        self.K = nx * ny * (nz if equation == EULER3D else 1)
         self.n = lib().orc_ndof(C.byref(self._m))
         if self.n < 0:
             raise ValueError("invalid oracle mesh")
@@ -184,10 +190,12 @@ class Mesh:
 
     # geometry ------------------------------------------------------------
     def nodes(self):
+        """(x, y) node coordinates, (x, y, z) for Euler 3D."""
         x = np.zeros(self.K * self.Np)
         y = np.zeros(self.K * self.Np)
-        _check(lib().orc_nodes(C.byref(self._m), _dp(x), _dp(y)), "nodes")
-        return x, y
+        z = np.zeros(self.K * self.Np)
+        _check(lib().orc_nodes(C.byref(self._m), _dp(x), _dp(y), _dp(z)), "nodes")
+        return (x, y, z) if self.dim == 3 else (x, y)
 
     def mass(self):
         w = np.zeros(self.K * self.Np)

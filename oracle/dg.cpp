@@ -3,9 +3,11 @@
 // Equations (paper Section 3):
 //   Burgers, inviscid part:  u_t + (u^2/2)_x = 0, linear flux F_L = u~ u
 //     (Section 3.1 with kappa = 0).
-//   Euler 2D: q = (rho, rho u, rho v, rho E), F = (rho u, rho u (x) u + p I,
-//     rho u H), p = (gamma-1)(rho E - rho |u|^2 / 2) (Section 3.2), linear
-//     flux F_L = A(q~) q with the normal flux Jacobian A(n) printed there.
+//   Euler 2D and 3D: q = (rho, rho u, rho E) with u of 2 or 3 components,
+//     F = (rho u, rho u (x) u + p I, rho u H), p = (gamma-1)(rho E - rho |u|^2/2)
+//     (Section 3.2, written for any dimension), linear flux F_L = A(q~) q with
+//     the normal flux Jacobian A(n) printed there.  The 3D problem is the
+//     extruded one of Section 5.2 (periodic in all directions).
 //
 // Semi-discretization (eq. EXPO-SemiDiscretizedForm_ode): per element,
 //   (q_t, v)_K = -(div F, v)_K - <(F* - F) . n, v>_dK
@@ -60,8 +62,8 @@ namespace {
 using cplx = std::complex<double>;
 
 struct Geo {
-    int eq, nx, ny, p, n1, Np, K, nvar, dim;
-    double hx, hy, gamma, x0, y0;
+    int eq, nx, ny, nz, p, n1, Np, K, nvar, dim;
+    double hx, hy, hz, gamma, x0, y0, z0;
     double kappa, sigma, beta;
     int flux, bc;
     const double *src;
@@ -70,30 +72,38 @@ struct Geo {
 
 bool make_geo(const orc_mesh *m, Geo *g) {
     if (!m) return false;
-    if (m->equation != ORC_BURGERS1D && m->equation != ORC_EULER2D) return false;
+    if (m->equation != ORC_BURGERS1D && m->equation != ORC_EULER2D &&
+        m->equation != ORC_EULER3D)
+        return false;
+    const int nz = (m->nz > 0) ? m->nz : 1;
     if (m->p < 1 || m->p > 15 || m->nx < 1 || m->ny < 1) return false;
     if (m->equation == ORC_BURGERS1D && m->ny != 1) return false;
+    if (m->equation != ORC_EULER3D && nz != 1) return false;
     if (!(m->x1 > m->x0)) return false;
-    if (m->equation == ORC_EULER2D && (!(m->y1 > m->y0) || !(m->gamma > 1.0))) return false;
+    if (m->equation != ORC_BURGERS1D && (!(m->y1 > m->y0) || !(m->gamma > 1.0))) return false;
+    if (m->equation == ORC_EULER3D && !(m->z1 > m->z0)) return false;
     if (!(m->kappa >= 0.0) || !(m->sigma >= 0.0) || !(std::fabs(m->beta) <= 0.5)) return false;
     if (m->flux != ORC_FLUX_LF && m->flux != ORC_FLUX_EF) return false;
     if (m->bc != ORC_BC_PERIODIC && m->bc != ORC_BC_DIRICHLET) return false;
-    if (m->equation == ORC_EULER2D &&
+    if (m->equation != ORC_BURGERS1D &&
         (m->kappa != 0.0 || m->flux != ORC_FLUX_LF || m->bc != ORC_BC_PERIODIC || m->source))
         return false;
     g->eq = m->equation;
     g->nx = m->nx;
     g->ny = m->ny;
+    g->nz = nz;
     g->p = m->p;
     g->n1 = m->p + 1;
-    g->dim = (m->equation == ORC_BURGERS1D) ? 1 : 2;
-    g->Np = (g->dim == 1) ? g->n1 : g->n1 * g->n1;
-    g->K = m->nx * m->ny;
-    g->nvar = (m->equation == ORC_BURGERS1D) ? 1 : 4;
+    g->dim = (m->equation == ORC_BURGERS1D) ? 1 : (m->equation == ORC_EULER2D ? 2 : 3);
+    g->Np = (g->dim == 1) ? g->n1 : (g->dim == 2 ? g->n1 * g->n1 : g->n1 * g->n1 * g->n1);
+    g->K = m->nx * m->ny * nz;
+    g->nvar = (m->equation == ORC_BURGERS1D) ? 1 : g->dim + 2;
     g->hx = (m->x1 - m->x0) / m->nx;
-    g->hy = (g->dim == 2) ? (m->y1 - m->y0) / m->ny : 1.0;
+    g->hy = (g->dim >= 2) ? (m->y1 - m->y0) / m->ny : 1.0;
+    g->hz = (g->dim == 3) ? (m->z1 - m->z0) / nz : 1.0;
     g->x0 = m->x0;
     g->y0 = m->y0;
+    g->z0 = m->z0;
     g->gamma = m->gamma;
     g->kappa = m->kappa;
     g->sigma = m->sigma;
@@ -107,20 +117,25 @@ bool make_geo(const orc_mesh *m, Geo *g) {
     return orc_lgl(g->p, g->xi.data(), g->w.data(), g->D.data()) == 0;
 }
 
-// Neighbour of element e across its face in direction dir (0 = x, 1 = y) on
-// side s (-1 = left/bottom, +1 = right/top); -1 at a Dirichlet end.
+// Neighbour of element e = (ez ny + ey) nx + ex across its face in direction
+// dir (0 = x, 1 = y, 2 = z) on side s (-1 = lower, +1 = upper); -1 at a
+// Dirichlet end.
 int neighbour(const Geo &g, int e, int dir, int s) {
-    int ex = e % g.nx, ey = e / g.nx;
+    int ex = e % g.nx, ey = (e / g.nx) % g.ny, ez = e / (g.nx * g.ny);
     if (g.bc == ORC_BC_DIRICHLET && dir == 0 && (ex + s < 0 || ex + s >= g.nx)) return -1;
     if (dir == 0)
         ex = (ex + s + g.nx) % g.nx;
-    else
+    else if (dir == 1)
         ey = (ey + s + g.ny) % g.ny;
-    return ey * g.nx + ex;
+    else
+        ez = (ez + s + g.nz) % g.nz;
+    return (ez * g.ny + ey) * g.nx + ex;
 }
 
-// Node index of (i, j) and its mirror across a face.
-inline int node(const Geo &g, int i, int j) { return (g.dim == 1) ? i : j * g.n1 + i; }
+// Node index of (i, j, k) (i along x, j along y, k along z).
+inline int node(const Geo &g, int i, int j, int k = 0) {
+    return (g.dim == 1) ? i : (g.dim == 2 ? j * g.n1 + i : (k * g.n1 + j) * g.n1 + i);
+}
 
 template <class T>
 void load(const Geo &g, const T *q, int e, int n, T *out) {
@@ -137,14 +152,17 @@ void flux(const Geo &g, const T *q, int dir, T *f) {
         return;
     }
     const double gm = g.gamma;
+    const int d = g.dim, iE = d + 1;
     T rho = q[0];
-    T u = q[1] / rho, v = q[2] / rho;
-    T p = (gm - 1.0) * (q[3] - 0.5 * (q[1] * u + q[2] * v));
-    T un = (dir == 0) ? u : v;
+    T u[3] = {T(0.0), T(0.0), T(0.0)};
+    for (int a = 0; a < d; ++a) u[a] = q[1 + a] / rho;
+    T mu = q[1] * u[0];
+    for (int a = 1; a < d; ++a) mu += q[1 + a] * u[a];
+    T p = (gm - 1.0) * (q[iE] - 0.5 * mu);
+    T un = u[dir];
     f[0] = rho * un;
-    f[1] = q[1] * un + ((dir == 0) ? p : T(0.0));
-    f[2] = q[2] * un + ((dir == 1) ? p : T(0.0));
-    f[3] = (q[3] + p) * un;
+    for (int a = 0; a < d; ++a) f[1 + a] = q[1 + a] * un + ((dir == a) ? p : T(0.0));
+    f[iE] = (q[iE] + p) * un;
 }
 
 // Linear flux A_dir(qt) v: the paper's normal flux Jacobian with n = e_dir,
@@ -159,36 +177,48 @@ void lin_flux(const Geo &g, const double *qt, const T *v, int dir, T *f) {
         return;
     }
     const double gm = g.gamma, gt = g.gamma - 1.0;
+    const int d = g.dim, iE = d + 1;
     const double rho = qt[0];
-    const double ux = qt[1] / rho, uy = qt[2] / rho;
-    const double p = gt * (qt[3] - 0.5 * rho * (ux * ux + uy * uy));
-    const double H = (qt[3] + p) / rho;
-    const double phi = 0.5 * gt * (ux * ux + uy * uy);
-    const double nx = (dir == 0) ? 1.0 : 0.0, ny = (dir == 1) ? 1.0 : 0.0;
-    const double un = nx * ux + ny * uy;
-    const double u[2] = {ux, uy}, n[2] = {nx, ny};
-    f[0] = nx * v[1] + ny * v[2];
-    for (int a = 0; a < 2; ++a) {
+    double u[3] = {0.0, 0.0, 0.0}, n[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < d; ++a) u[a] = qt[1 + a] / rho;
+    double uu = u[0] * u[0];
+    for (int a = 1; a < d; ++a) uu += u[a] * u[a];
+    const double p = gt * (qt[iE] - 0.5 * rho * uu);
+    const double H = (qt[iE] + p) / rho;
+    const double phi = 0.5 * gt * uu;
+    n[dir] = 1.0;
+    double un = n[0] * u[0];
+    for (int a = 1; a < d; ++a) un += n[a] * u[a];
+    T f0 = n[0] * v[1];
+    for (int a = 1; a < d; ++a) f0 += n[a] * v[1 + a];
+    f[0] = f0;
+    for (int a = 0; a < d; ++a) {
         T acc = (phi * n[a] - u[a] * un) * v[0];
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < d; ++b) {
             double Mab = u[a] * n[b] - gt * n[a] * u[b] + ((a == b) ? un : 0.0);
             acc += Mab * v[1 + b];
         }
-        acc += gt * n[a] * v[3];
+        acc += gt * n[a] * v[iE];
         f[1 + a] = acc;
     }
-    f[3] = (phi - H) * un * v[0] + (H * nx - gt * ux * un) * v[1] +
-           (H * ny - gt * uy * un) * v[2] + gm * un * v[3];
+    T fe = (phi - H) * un * v[0];
+    for (int a = 0; a < d; ++a) fe += (H * n[a] - gt * u[a] * un) * v[1 + a];
+    fe += gm * un * v[iE];
+    f[iE] = fe;
 }
 
 // One-sided wave speed for the Lax-Friedrichs dissipation.
 double wave_speed(const Geo &g, const double *q, int dir) {
     if (g.eq == ORC_BURGERS1D) return std::fabs(q[0]);
+    const int d = g.dim, iE = d + 1;
     const double rho = q[0];
-    const double ux = q[1] / rho, uy = q[2] / rho;
-    const double p = (g.gamma - 1.0) * (q[3] - 0.5 * rho * (ux * ux + uy * uy));
+    double u[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < d; ++k) u[k] = q[1 + k] / rho;
+    double uu = u[0] * u[0];
+    for (int k = 1; k < d; ++k) uu += u[k] * u[k];
+    const double p = (g.gamma - 1.0) * (q[iE] - 0.5 * rho * uu);
     const double a = std::sqrt(g.gamma * p / rho);
-    return std::fabs(dir == 0 ? ux : uy) + a;
+    return std::fabs(u[dir]) + a;
 }
 
 // ---- generic DG operator ------------------------------------------------
@@ -201,23 +231,29 @@ template <class T, class FluxAt>
 void dg_apply(const Geo &g, const T *u, const double *lam_ref, FluxAt node_flux, T *out,
               bool entropy = false) {
     const int n1 = g.n1, Np = g.Np, nv = g.nvar;
-    const double h[2] = {g.hx, g.hy};
+    const double h[3] = {g.hx, g.hy, g.hz};
 #pragma omp parallel for schedule(static)
     for (int e = 0; e < g.K; ++e) {
         // fluxes at all nodes of this element, per direction
         std::vector<T> F((size_t)g.dim * Np * nv);
         for (int dir = 0; dir < g.dim; ++dir)
             for (int n = 0; n < Np; ++n) node_flux(e, n, dir, &F[((size_t)dir * Np + n) * nv]);
-        for (int jj = 0; jj < (g.dim == 2 ? n1 : 1); ++jj) {
+        for (int kk = 0; kk < (g.dim == 3 ? n1 : 1); ++kk)
+        for (int jj = 0; jj < (g.dim >= 2 ? n1 : 1); ++jj) {
             for (int i = 0; i < n1; ++i) {
-                const int n = node(g, i, jj);
-                T res[4];
+                const int n = node(g, i, jj, kk);
+                const int crd[3] = {i, jj, kk};
+                // the node with its coordinate along dir replaced by l
+                auto along = [&](int dir, int l) {
+                    return node(g, dir == 0 ? l : i, dir == 1 ? l : jj, dir == 2 ? l : kk);
+                };
+                T res[5];
                 for (int c = 0; c < nv; ++c) res[c] = T(0.0);
                 // volume: -(2/h_dir) sum_l D_{il} F_dir at the nodes of the line
                 for (int dir = 0; dir < g.dim; ++dir) {
-                    const int a = (dir == 0) ? i : jj;  // coordinate index along dir
+                    const int a = crd[dir];  // coordinate index along dir
                     for (int l = 0; l < n1; ++l) {
-                        const int nl = (dir == 0) ? node(g, l, jj) : node(g, i, l);
+                        const int nl = along(dir, l);
                         const double Dal = g.D[a * n1 + l];
                         for (int c = 0; c < nv; ++c)
                             res[c] -= (2.0 / h[dir]) * Dal * F[((size_t)dir * Np + nl) * nv + c];
@@ -225,17 +261,17 @@ void dg_apply(const Geo &g, const T *u, const double *lam_ref, FluxAt node_flux,
                 }
                 // faces: -(2/h_dir)(1/w_end) (F* . n - F(u^-) . n)
                 for (int dir = 0; dir < g.dim; ++dir) {
-                    const int a = (dir == 0) ? i : jj;
+                    const int a = crd[dir];
                     for (int s = -1; s <= 1; s += 2) {
                         if ((s == -1 && a != 0) || (s == 1 && a != g.p)) continue;
                         const int en = neighbour(g, e, dir, s);
                         // mirror node on the neighbour: coordinate along dir flips end
                         const int am = g.p - a;
-                        const int nn = (dir == 0) ? node(g, am, jj) : node(g, i, am);
-                        T fm[4], fp[4], um[4], up[4];
+                        const int nn = along(dir, am);
+                        T fm[5], fp[5], um[5], up[5];
                         for (int c = 0; c < nv; ++c) fm[c] = F[((size_t)dir * Np + n) * nv + c];
                         load(g, u, e, n, um);
-                        double qm[4], qp[4];
+                        double qm[5], qp[5];
                         load(g, lam_ref, e, n, qm);
                         if (en >= 0) {
                             node_flux(en, nn, dir, fp);
@@ -335,7 +371,7 @@ void add_diffusion(const Geo &g, const T *u, T *out) {
 template <class T>
 void residual_frozen(const Geo &g, const T *q, const double *lam_ref, T *r) {
     auto fl = [&](int e, int n, int dir, T *f) {
-        T qn[4];
+        T qn[5];
         load(g, q, e, n, qn);
         flux(g, qn, dir, f);
     };
@@ -345,7 +381,7 @@ void residual_frozen(const Geo &g, const T *q, const double *lam_ref, T *r) {
 
 void linear_op(const Geo &g, const double *qt, const double *v, double *w) {
     auto fl = [&](int e, int n, int dir, double *f) {
-        double qn[4], vn[4];
+        double qn[5], vn[5];
         load(g, qt, e, n, qn);
         load(g, v, e, n, vn);
         lin_flux(g, qn, vn, dir, f);
@@ -364,18 +400,18 @@ int orc_ndof(const orc_mesh *m) {
     return g.nvar * g.K * g.Np;
 }
 
-int orc_nodes(const orc_mesh *m, double *x, double *y) {
+int orc_nodes(const orc_mesh *m, double *x, double *y, double *z) {
     Geo g;
     if (!make_geo(m, &g) || !x) return -1;
     for (int e = 0; e < g.K; ++e) {
-        const int ex = e % g.nx, ey = e / g.nx;
-        for (int jj = 0; jj < (g.dim == 2 ? g.n1 : 1); ++jj)
+        const int ex = e % g.nx, ey = (e / g.nx) % g.ny, ez = e / (g.nx * g.ny);
+        for (int kk = 0; kk < (g.dim == 3 ? g.n1 : 1); ++kk)
+        for (int jj = 0; jj < (g.dim >= 2 ? g.n1 : 1); ++jj)
             for (int i = 0; i < g.n1; ++i) {
-                const int n = node(g, i, jj);
-                x[(size_t)e * g.Np + n] = g.x0 + ex * g.hx + 0.5 * (g.xi[i] + 1.0) * g.hx;
-                if (y)
-                    y[(size_t)e * g.Np + n] =
-                        (g.dim == 2) ? g.y0 + ey * g.hy + 0.5 * (g.xi[jj] + 1.0) * g.hy : 0.0;
+                const size_t at = (size_t)e * g.Np + node(g, i, jj, kk);
+                x[at] = g.x0 + ex * g.hx + 0.5 * (g.xi[i] + 1.0) * g.hx;
+                if (y) y[at] = (g.dim >= 2) ? g.y0 + ey * g.hy + 0.5 * (g.xi[jj] + 1.0) * g.hy : 0.0;
+                if (z) z[at] = (g.dim == 3) ? g.z0 + ez * g.hz + 0.5 * (g.xi[kk] + 1.0) * g.hz : 0.0;
             }
     }
     return 0;
@@ -385,11 +421,13 @@ int orc_mass(const orc_mesh *m, double *mass) {
     Geo g;
     if (!make_geo(m, &g) || !mass) return -1;
     for (int e = 0; e < g.K; ++e)
-        for (int jj = 0; jj < (g.dim == 2 ? g.n1 : 1); ++jj)
+        for (int kk = 0; kk < (g.dim == 3 ? g.n1 : 1); ++kk)
+        for (int jj = 0; jj < (g.dim >= 2 ? g.n1 : 1); ++jj)
             for (int i = 0; i < g.n1; ++i) {
                 double v = 0.5 * g.hx * g.w[i];
-                if (g.dim == 2) v *= 0.5 * g.hy * g.w[jj];
-                mass[(size_t)e * g.Np + node(g, i, jj)] = v;
+                if (g.dim >= 2) v *= 0.5 * g.hy * g.w[jj];
+                if (g.dim == 3) v *= 0.5 * g.hz * g.w[kk];
+                mass[(size_t)e * g.Np + node(g, i, jj, kk)] = v;
             }
     return 0;
 }
@@ -450,14 +488,15 @@ int orc_max_speed(const orc_mesh *m, const double *q, double *cmax, double *dxmi
     double c = 0.0;
     for (int e = 0; e < g.K; ++e)
         for (int n = 0; n < g.Np; ++n) {
-            double qn[4];
+            double qn[5];
             load(g, q, e, n, qn);
             for (int dir = 0; dir < g.dim; ++dir) c = std::fmax(c, wave_speed(g, qn, dir));
         }
     double dmin = 1e300;
     for (int i = 0; i < g.p; ++i) dmin = std::fmin(dmin, g.xi[i + 1] - g.xi[i]);
     double h = g.hx;
-    if (g.dim == 2) h = std::fmin(g.hx, g.hy);
+    if (g.dim >= 2) h = std::fmin(h, g.hy);
+    if (g.dim == 3) h = std::fmin(h, g.hz);
     if (cmax) *cmax = c;
     if (dxmin) *dxmin = 0.5 * h * dmin;
     return 0;

@@ -26,8 +26,9 @@
  *     cited in Section 1)
  *
  * Layout of every nodal vector: idx = (c*K + e)*Np + n, c = variable,
- * e = ey*nx + ex, n = j*(p+1) + i with i along x.  Burgers has one variable;
- * Euler has (rho, rho u, rho v, rho E).
+ * e = (ez*ny + ey)*nx + ex, n = (k*(p+1) + j)*(p+1) + i with i along x.
+ * Burgers has one variable; Euler 2D (rho, rho u, rho v, rho E); Euler 3D
+ * (rho, rho u, rho v, rho w, rho E).
  *
  * Return codes: 0 on success, negative on invalid input or failure.
  */
@@ -38,7 +39,7 @@
 extern "C" {
 #endif
 
-enum { ORC_BURGERS1D = 1, ORC_EULER2D = 2 };
+enum { ORC_BURGERS1D = 1, ORC_EULER2D = 2, ORC_EULER3D = 3 };
 enum { ORC_EPI2 = 2, ORC_EPI3 = 3, ORC_EXPRB32 = 32, ORC_EXPRB42 = 42 };
 enum { ORC_FLUX_LF = 0, ORC_FLUX_EF = 1 };          /* Burgers (u^2/2)* */
 enum { ORC_BC_PERIODIC = 0, ORC_BC_DIRICHLET = 1 };  /* Burgers: u = 0 at x0, x1 */
@@ -58,6 +59,8 @@ typedef struct {
     double beta;       /* diffusion fluxes: 0 central, 1/2 LDG (Appendix A) */
     int bc;            /* ORC_BC_PERIODIC or ORC_BC_DIRICHLET */
     const double *source; /* NULL or a nodal source added to R (not to L) */
+    int nz;            /* elements along z (Euler 3D; 0 or 1 otherwise) */
+    double z0, z1;
 } orc_mesh;
 
 /* One accepted Krylov substep: basis size m, substep length dtau, and
@@ -90,7 +93,7 @@ typedef struct {
 int orc_lgl(int p, double *xi, double *w, double *D);
 
 int orc_ndof(const orc_mesh *m);
-int orc_nodes(const orc_mesh *m, double *x, double *y);
+int orc_nodes(const orc_mesh *m, double *x, double *y, double *z);
 /* Diagonal mass entries per nodal value (LGL quadrature weight times the
  * element Jacobian), one per node of one variable: K*Np entries. */
 int orc_mass(const orc_mesh *m, double *mass);

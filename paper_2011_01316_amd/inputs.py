@@ -15,7 +15,8 @@ Workloads (paper, Section 5):
   * Viscous Burgers on [0, 1] with u = 0 at both ends (Section 5.1): the
     time-independent manufactured solution u = sin(x^2) x (x - 1) with its
     source term, and the smooth initial state sin^3(2 pi x) (1 - x)^{3/2}.
-  * Isentropic vortex translating in a uniform mean flow (Section 5.2, after
+  * Isentropic vortex translating in a uniform mean flow (Section 5.2; in 3D
+    extruded along z with w = 0; after
     Zhou & Wei): velocity perturbation (lambda / 2 pi) e^{alpha (1 - r^2)/2}
     (-y~, x~), temperature T = T_inf - (lambda/2 pi)^2 e^{alpha (1-r^2)} /
     (2 alpha c_p), c_p = gamma / (gamma - 1), density from the isentropic
@@ -83,6 +84,16 @@ def vortex(x, y, t: float = 0.0, beta: float = 5.0, alpha: float = 2.0, xc: floa
     rho = T ** (1.0 / (gamma - 1.0))
     p = rho * T
     return primitive_to_conservative(rho, u, v, p, gamma)
+
+
+def vortex3d(x, y, z, t: float = 0.0, beta: float = 5.0, xc: float = 5.0, yc: float = 0.0,
+             Lx: float = 10.0, Ly: float = 10.0, **kw) -> np.ndarray:
+    """The vortex extruded along z with zero vertical velocity (Section 5.2's
+    three-dimensional case on (0, 10) x (-5, 5) x (0, 1)): conservative
+    (rho, rho u, rho v, rho w, rho E), shape (5, npts)."""
+    del z  # the state does not depend on z
+    q = vortex(x, y, t=t, beta=beta, xc=xc, yc=yc, Lx=Lx, Ly=Ly, **kw)
+    return np.stack([q[0], q[1], q[2], np.zeros_like(q[0]), q[3]])
 
 
 def shear_layer(x, y, seed: int = 0, a: float = 0.01, sigma: float = 0.04, amp: float = 1e-2,

@@ -15,6 +15,7 @@ import pytest
 
 import oracle
 from tests import test_oracle_dg as dg
+from tests import test_oracle_euler3d as e3
 from tests import test_oracle_iop as iop
 from tests import test_oracle_phi as phi
 from tests import test_oracle_refelem as refelem
@@ -27,12 +28,12 @@ MUTATIONS = {
     "lambda_min": ("dg.cpp", "std::fmax(wave_speed(g, qm, dir), wave_speed(g, qp, dir))",
                    "std::fmin(wave_speed(g, qm, dir), wave_speed(g, qp, dir))",
                    lambda: dg.test_piecewise_constant_rusanov(1)),
-    "jacobian_entry": ("dg.cpp", "acc += gt * n[a] * v[3];", "acc += gm * n[a] * v[3];",
+    "jacobian_entry": ("dg.cpp", "acc += gt * n[a] * v[iE];", "acc += gm * n[a] * v[iE];",
                        lambda: dg.test_jvp_equals_complex_step(2)),
     "lift_factor": ("dg.cpp", "res[c] -= (2.0 / h[dir]) / g.w[a] * (fstar_n - f_n);",
                     "res[c] -= (2.0 / h[dir]) * g.w[a] * (fstar_n - f_n);",
                     lambda: dg.test_piecewise_constant_rusanov(3)),
-    "energy_flux": ("dg.cpp", "f[3] = (q[3] + p) * un;", "f[3] = q[3] * un;",
+    "energy_flux": ("dg.cpp", "f[iE] = (q[iE] + p) * un;", "f[iE] = q[iE] * un;",
                     lambda: steppers.test_vortex_spatial_order(2)),
     "pade_coeff": ("expm.cpp", "(k * (2 * q - k + 1))", "(k * (2 * q - k))",
                    lambda: phi.test_expm_vs_scipy(12, 1.0)),
@@ -52,6 +53,8 @@ MUTATIONS = {
     "dirichlet_ustar": ("dg.cpp", "T ustar = T(0.0);  // Dirichlet end: u** = 0",
                         "T ustar = u[(size_t)e * n1 + i];",
                         lambda: viscous.test_diffusion_energy_identity(0.0, oracle.BC_DIRICHLET, 2)),
+    "normal_speed": ("dg.cpp", "return std::fabs(u[dir]) + a;", "return std::fabs(u[0]) + a;",
+                     lambda: e3.test_axis_permutation(1)),
     "iop_window": ("krylov.cpp", "std::max(0, j - iop)", "std::max(0, j - iop - 1)",
                    lambda: iop.test_arnoldi_relation_and_band(2)),
     "lgl_weight": ("refelem.cpp", "w[i] = 2.0 / (p * (p + 1.0) * P * P);",
