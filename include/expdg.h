@@ -22,10 +22,12 @@
  * plain C: pointers and sizes, no C++ or framework types.
  *
  * Nodal layout of every state vector (device memory):
- *     idx = (c * K + e) * Np + n,   c = variable, e = ey * nx + ex,
- *     n = j * (p + 1) + i  (i along x; 1D: n = i),
- * Burgers: one variable u.  Euler: (rho, rho u, rho v, rho E).
- * Np = p + 1 (1D) or (p + 1)^2 (2D); K = nx * ny; ndof = nvar * K * Np.
+ *     idx = (c * K + e) * Np + n,   c = variable, e = (ez * ny + ey) * nx + ex,
+ *     n = (k * (p + 1) + j) * (p + 1) + i  (i along x, j along y, k along z),
+ * Burgers: one variable u.  Euler 2D: (rho, rho u, rho v, rho E).  Euler 3D:
+ * (rho, rho u, rho v, rho w, rho E) (the system of Section 3.2 with three
+ * velocity components; the extruded problem of Section 5.2).
+ * Np = (p + 1)^dim; K = nx * ny * nz; ndof = nvar * K * Np.
  *
  * Precision: in EXPDG_FP64 every buffer is double.  In EXPDG_FP32_BULK the
  * operator buffers of expdg_rhs / expdg_jvp / expdg_phi_krylov are float and
@@ -59,7 +61,7 @@
 extern "C" {
 #endif
 
-enum { EXPDG_BURGERS1D = 1, EXPDG_EULER2D = 2 };
+enum { EXPDG_BURGERS1D = 1, EXPDG_EULER2D = 2, EXPDG_EULER3D = 3 };
 enum { EXPDG_FP64 = 0, EXPDG_FP32_BULK = 1 };
 enum { EXPDG_EPI2 = 2, EXPDG_EPI3 = 3, EXPDG_EXPRB32 = 32, EXPDG_EXPRB42 = 42 };
 enum { EXPDG_FLUX_LF = 0, EXPDG_FLUX_EF = 1 };
@@ -74,8 +76,9 @@ enum {
 };
 
 /* Mesh description.  Uniform mesh: nx intervals on [x0, x1] (Burgers,
- * ny = 1) or nx x ny periodic quadrilaterals on [x0, x1] x [y0, y1] (Euler).
- * p is the LGL degree (1..6).  m_max bounds the Krylov basis (1..64).  gamma
+ * ny = 1), nx x ny periodic quadrilaterals on [x0, x1] x [y0, y1] (Euler 2D),
+ * or nx x ny x nz periodic hexahedra on [x0, x1] x [y0, y1] x [z0, z1]
+ * (Euler 3D; nz, z0, z1 are read only there).  p is the LGL degree (1..6).  m_max bounds the Krylov basis (1..64).  gamma
  * is used by Euler only.
  *
  * Burgers options (Section 3.1; all zero = inviscid, periodic,
@@ -96,7 +99,7 @@ enum {
  *   has_source  nonzero: the mesh holds a source vector s added to R (not to
  *          L), set by expdg_mesh_set_source (zero until then). */
 typedef struct {
-    int equation;   /* EXPDG_BURGERS1D or EXPDG_EULER2D */
+    int equation;   /* EXPDG_BURGERS1D, EXPDG_EULER2D or EXPDG_EULER3D */
     int nx, ny;
     int p;
     int precision;  /* EXPDG_FP64 or EXPDG_FP32_BULK */
@@ -110,6 +113,8 @@ typedef struct {
     double beta;
     int bc;
     int has_source;
+    int nz;
+    double z0, z1;
 } expdg_mesh_desc;
 
 typedef struct expdg_mesh expdg_mesh; /* opaque, library-owned */
@@ -121,6 +126,7 @@ typedef struct {
     int elem_bytes;    /* 8 (FP64) or 4 (FP32_BULK) for operator buffers */
     double hx, hy;     /* element sizes */
     double dx_min;     /* smallest LGL node spacing in physical units */
+    double hz;         /* element size along z (3D; 1 otherwise) */
 } expdg_mesh_info;
 
 /* One accepted Krylov substep: basis size m, substep length dtau, last != 0
@@ -170,8 +176,9 @@ int expdg_mesh_destroy(expdg_mesh *m);
 /* Device bytes expdg_mesh_create would allocate for desc (0 if invalid). */
 size_t expdg_workspace_bytes(const expdg_mesh_desc *desc);
 int expdg_mesh_get_info(const expdg_mesh *m, expdg_mesh_info *info);
-/* Physical node coordinates, host arrays of K*Np doubles (y may be NULL). */
-int expdg_mesh_nodes(const expdg_mesh *m, double *x, double *y);
+/* Physical node coordinates, host arrays of K*Np doubles (y, z may be NULL;
+ * coordinates a mesh does not have are written as 0). */
+int expdg_mesh_nodes(const expdg_mesh *m, double *x, double *y, double *z);
 /* Copies the source term of a mesh created with has_source: s is a device
  * array of ndof doubles (the nodal values of the source of Section 5.1's
  * manufactured solutions), stored in the mesh in its bulk precision.

@@ -15,7 +15,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libexpdg.so")
 
-BURGERS1D, EULER2D = 1, 2
+BURGERS1D, EULER2D, EULER3D = 1, 2, 3
 FP64, FP32_BULK = 0, 1
 EPI2, EPI3, EXPRB32, EXPRB42 = 2, 3, 32, 42
 FLUX_LF, FLUX_EF = 0, 1
@@ -35,13 +35,14 @@ class MeshDesc(C.Structure):
                 ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
                 ("gamma", C.c_double), ("m_max", C.c_int), ("kappa", C.c_double),
                 ("flux", C.c_int), ("sigma", C.c_double), ("beta", C.c_double),
-                ("bc", C.c_int), ("has_source", C.c_int)]
+                ("bc", C.c_int), ("has_source", C.c_int), ("nz", C.c_int), ("z0", C.c_double),
+                ("z1", C.c_double)]
 
 
 class MeshInfo(C.Structure):
     _fields_ = [("ndof", C.c_size_t), ("nvar", C.c_int), ("K", C.c_int), ("Np", C.c_int),
                 ("elem_bytes", C.c_int), ("hx", C.c_double), ("hy", C.c_double),
-                ("dx_min", C.c_double)]
+                ("dx_min", C.c_double), ("hz", C.c_double)]
 
 
 class Substep(C.Structure):
@@ -105,7 +106,7 @@ _SIGS = {
     "expdg_mesh_destroy": (C.c_int, [C.c_void_p]),
     "expdg_workspace_bytes": (C.c_size_t, [C.POINTER(MeshDesc)]),
     "expdg_mesh_get_info": (C.c_int, [C.c_void_p, C.POINTER(MeshInfo)]),
-    "expdg_mesh_nodes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "expdg_mesh_nodes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "expdg_mesh_set_source": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "expdg_lgl": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "expdg_rhs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -294,14 +295,15 @@ class Mesh:
 
     def __init__(self, equation, nx, p, ny=1, precision=FP64, device=0, x0=0.0, x1=1.0,
                  y0=0.0, y1=1.0, gamma=1.4, m_max=64, kappa=0.0, flux=FLUX_LF, sigma=0.0,
-                 beta=0.0, bc=BC_PERIODIC, has_source=False):
+                 beta=0.0, bc=BC_PERIODIC, has_source=False, nz=1, z0=0.0, z1=1.0):
         self.desc = MeshDesc(equation, nx, ny, p, precision, device, x0, x1, y0, y1, gamma,
-                             m_max, kappa, flux, sigma, beta, bc, int(bool(has_source)))
+                             m_max, kappa, flux, sigma, beta, bc, int(bool(has_source)), nz, z0,
+                             z1)
         self.handle = expdg_mesh_create(self.desc)
         info = MeshInfo()
         _check(lib().expdg_mesh_get_info(self.handle, C.byref(info)))
         self.n, self.nvar, self.K, self.Np = info.ndof, info.nvar, info.K, info.Np
-        self.hx, self.hy, self.dx_min = info.hx, info.hy, info.dx_min
+        self.hx, self.hy, self.hz, self.dx_min = info.hx, info.hy, info.hz, info.dx_min
         self.elem_bytes = info.elem_bytes
         self.p, self.equation, self.precision = p, equation, precision
 
@@ -329,11 +331,13 @@ class Mesh:
         return torch.float64 if self.precision == FP64 else torch.float32
 
     def nodes(self):
+        """(x, y) node coordinates, (x, y, z) for Euler 3D."""
         import numpy as np
         x = np.zeros(self.K * self.Np)
         y = np.zeros(self.K * self.Np)
-        _check(lib().expdg_mesh_nodes(self.handle, x.ctypes.data, y.ctypes.data))
-        return x, y
+        z = np.zeros(self.K * self.Np)
+        _check(lib().expdg_mesh_nodes(self.handle, x.ctypes.data, y.ctypes.data, z.ctypes.data))
+        return (x, y, z) if self.equation == EULER3D else (x, y)
 
     def set_source(self, s, stream=None):
         """s: float64 device tensor of ndof entries (copied into the mesh)."""
@@ -368,7 +372,7 @@ def make_request(equation, nx, p, ny=1, scheme=EPI3, nsteps=20, dt=0.0, cfl=0.0,
                  gamma=1.4, mesh_m_max=64, kappa=0.0, flux=FLUX_LF, sigma=0.0, beta=0.0,
                  bc=BC_PERIODIC):
     return Request(MeshDesc(equation, nx, ny, p, FP64, 0, x0, x1, y0, y1, gamma, mesh_m_max,
-                            kappa, flux, sigma, beta, bc, 0),
+                            kappa, flux, sigma, beta, bc, 0, 1, 0.0, 1.0),
                    scheme, nsteps, dt, cfl, tol, m_min, m_max, check_every)
 
 

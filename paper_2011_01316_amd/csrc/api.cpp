@@ -131,23 +131,34 @@ namespace expdg {
 
 bool desc_ok(const expdg_mesh_desc *d, const char **why) {
     if (!d) return *why = "desc is NULL", false;
-    if (d->equation != EXPDG_BURGERS1D && d->equation != EXPDG_EULER2D)
-        return *why = "equation must be EXPDG_BURGERS1D or EXPDG_EULER2D", false;
+    if (d->equation != EXPDG_BURGERS1D && d->equation != EXPDG_EULER2D &&
+        d->equation != EXPDG_EULER3D)
+        return *why = "equation must be EXPDG_BURGERS1D, EXPDG_EULER2D or EXPDG_EULER3D", false;
+    if (d->equation == EXPDG_EULER3D) {
+        if (d->nz < 1) return *why = "Euler 3D needs nz >= 1", false;
+        if (!(d->z1 > d->z0) || !std::isfinite(d->z0) || !std::isfinite(d->z1))
+            return *why = "need z1 > z0", false;
+    } else if (d->nz > 1) {
+        return *why = "nz > 1 needs EXPDG_EULER3D", false;
+    }
     if (d->p < 1 || d->p > kMaxP) return *why = "p must be in 1..6", false;
     if (d->nx < 1 || d->ny < 1) return *why = "nx and ny must be >= 1", false;
     if (d->equation == EXPDG_BURGERS1D && d->ny != 1) return *why = "Burgers needs ny == 1", false;
-    if ((long long)d->nx * d->ny > (1LL << 26)) return *why = "too many elements", false;
+    const long long nzz = (d->equation == EXPDG_EULER3D) ? d->nz : 1;
+    if ((long long)d->nx * d->ny * nzz > (1LL << 26)) return *why = "too many elements", false;
     {
         // the kernels address one variable plane with 32-bit byte offsets
-        const long long np = (d->equation == EXPDG_BURGERS1D) ? (d->p + 1) : (d->p + 1) * (d->p + 1);
-        if ((long long)d->nx * d->ny * np > (1LL << 29) - 1)
+        const long long n1 = d->p + 1;
+        const long long np = (d->equation == EXPDG_BURGERS1D) ? n1
+                             : (d->equation == EXPDG_EULER2D) ? n1 * n1 : n1 * n1 * n1;
+        if ((long long)d->nx * d->ny * nzz * np > (1LL << 29) - 1)
             return *why = "too many nodes (at most 2^29 - 1 per variable)", false;
     }
     if (d->precision != EXPDG_FP64 && d->precision != EXPDG_FP32_BULK)
         return *why = "precision must be EXPDG_FP64 or EXPDG_FP32_BULK", false;
     if (!(d->x1 > d->x0) || !std::isfinite(d->x0) || !std::isfinite(d->x1))
         return *why = "need x1 > x0", false;
-    if (d->equation == EXPDG_EULER2D) {
+    if (d->equation != EXPDG_BURGERS1D) {
         if (!(d->y1 > d->y0) || !std::isfinite(d->y0) || !std::isfinite(d->y1))
             return *why = "need y1 > y0", false;
         if (!(d->gamma > 1.0) || !std::isfinite(d->gamma)) return *why = "need gamma > 1", false;
@@ -161,7 +172,7 @@ bool desc_ok(const expdg_mesh_desc *d, const char **why) {
         return *why = "flux must be EXPDG_FLUX_LF or EXPDG_FLUX_EF", false;
     if (d->bc != EXPDG_BC_PERIODIC && d->bc != EXPDG_BC_DIRICHLET)
         return *why = "bc must be EXPDG_BC_PERIODIC or EXPDG_BC_DIRICHLET", false;
-    if (d->equation == EXPDG_EULER2D &&
+    if (d->equation != EXPDG_BURGERS1D &&
         (d->kappa != 0.0 || d->flux != EXPDG_FLUX_LF || d->sigma != 0.0 || d->beta != 0.0 ||
          d->bc != EXPDG_BC_PERIODIC || d->has_source))
         return *why = "Euler takes no Burgers options (kappa, flux, sigma, beta, bc, source)", false;
@@ -188,7 +199,9 @@ size_t layout(expdg_mesh *m, const expdg_mesh_desc *d, size_t stride, int eb, ch
         for (auto &v : m->bq) take(v, vb);
     take(m->q2, stride * 8);
     if (d->has_source) take(m->src, vb);
-    const size_t nlin = lin_elems(d->equation, d->p, d->nx * d->ny);
+    // elements of the mesh (nz counts in 3D only)
+    const int K = d->nx * d->ny * (d->equation == EXPDG_EULER3D ? d->nz : 1);
+    const size_t nlin = lin_elems(d->equation, d->p, K);
     if (nlin) take(m->lin, nlin * eb);
     take(m->kd.H, (size_t)(kMaxM + 1) * kLDH * 8);
     take(m->kd.S, (size_t)(kMaxM + 1) * 8);
@@ -196,7 +209,7 @@ size_t layout(expdg_mesh *m, const expdg_mesh_desc *d, size_t stride, int eb, ch
     take(m->kd.coefB, (size_t)(kMaxM + 3) * 8);
     // block partials: row-partitioned passes (<= kRedBlocks) and the dot pass
     // fused into the linear operator (one partial per operator block)
-    const size_t npart = std::max<size_t>(kRedBlocks, dg_blocks(d->equation, d->p, d->nx * d->ny));
+    const size_t npart = std::max<size_t>(kRedBlocks, dg_blocks(d->equation, d->p, K));
     take(m->kd.part, npart * kPartRows * 8);
     take(m->kd.res, 64 * 8);
     take(m->kd.flags, 16);
@@ -211,9 +224,11 @@ size_t layout(expdg_mesh *m, const expdg_mesh_desc *d, size_t stride, int eb, ch
 Sizes sizes_of(const expdg_mesh_desc *d) {
     Sizes s{};
     const int n1 = d->p + 1;
-    const int Np = (d->equation == EXPDG_BURGERS1D) ? n1 : n1 * n1;
-    const int nvar = (d->equation == EXPDG_BURGERS1D) ? 1 : 4;
-    s.n = (size_t)nvar * d->nx * d->ny * Np;
+    const int dim = (d->equation == EXPDG_BURGERS1D) ? 1 : (d->equation == EXPDG_EULER2D ? 2 : 3);
+    const int Np = (dim == 1) ? n1 : (dim == 2 ? n1 * n1 : n1 * n1 * n1);
+    const int nvar = (dim == 1) ? 1 : dim + 2;
+    const size_t K = (size_t)d->nx * d->ny * (dim == 3 ? d->nz : 1);
+    s.n = (size_t)nvar * K * Np;
     s.stride = (s.n + kMaxAug + 63) / 64 * 64;
     s.ebytes = (d->precision == EXPDG_FP64) ? 8 : 4;
     expdg_mesh probe;
@@ -223,22 +238,26 @@ Sizes sizes_of(const expdg_mesh_desc *d) {
 
 void mesh_setup(expdg_mesh *m, const expdg_mesh_desc *d) {
     m->d = *d;
-    m->dim = (d->equation == EXPDG_BURGERS1D) ? 1 : 2;
+    m->dim = (d->equation == EXPDG_BURGERS1D) ? 1 : (d->equation == EXPDG_EULER2D ? 2 : 3);
     m->n1 = d->p + 1;
-    m->Np = (m->dim == 1) ? m->n1 : m->n1 * m->n1;
-    m->K = d->nx * d->ny;
-    m->nvar = (m->dim == 1) ? 1 : 4;
+    m->Np = (m->dim == 1) ? m->n1 : (m->dim == 2 ? m->n1 * m->n1 : m->n1 * m->n1 * m->n1);
+    m->K = d->nx * d->ny * (m->dim == 3 ? d->nz : 1);
+    m->nvar = (m->dim == 1) ? 1 : m->dim + 2;
     const Sizes sz = sizes_of(d);
     m->n = sz.n;
     m->stride = sz.stride;
     m->ebytes = sz.ebytes;
     m->bytes = sz.total;
     m->hx = (d->x1 - d->x0) / d->nx;
-    m->hy = (m->dim == 2) ? (d->y1 - d->y0) / d->ny : 1.0;
+    m->hy = (m->dim >= 2) ? (d->y1 - d->y0) / d->ny : 1.0;
+    m->hz = (m->dim == 3) ? (d->z1 - d->z0) / d->nz : 1.0;
     lgl_tables(d->p, m->xi, m->w, m->D);
     double dmin = 2.0;
     for (int i = 0; i < d->p; ++i) dmin = std::min(dmin, m->xi[i + 1] - m->xi[i]);
-    m->dxmin = 0.5 * ((m->dim == 2) ? std::min(m->hx, m->hy) : m->hx) * dmin;
+    double hmin = m->hx;
+    if (m->dim >= 2) hmin = std::min(hmin, m->hy);
+    if (m->dim == 3) hmin = std::min(hmin, m->hz);
+    m->dxmin = 0.5 * hmin * dmin;
 }
 
 void mesh_carve(expdg_mesh *m, void *block) {
@@ -395,20 +414,24 @@ extern "C" int expdg_mesh_get_info(const expdg_mesh *m, expdg_mesh_info *info) {
     info->elem_bytes = m->ebytes;
     info->hx = m->hx;
     info->hy = m->hy;
+    info->hz = m->hz;
     info->dx_min = m->dxmin;
     return EXPDG_OK;
 }
 
-extern "C" int expdg_mesh_nodes(const expdg_mesh *m, double *x, double *y) {
+extern "C" int expdg_mesh_nodes(const expdg_mesh *m, double *x, double *y, double *z) {
     if (!m || !x) return fail(EXPDG_EINVAL, "NULL argument");
+    const int n1 = m->n1;
     for (int e = 0; e < m->K; ++e) {
-        const int ex = e % m->d.nx, ey = e / m->d.nx;
+        const int ex = e % m->d.nx, ey = (e / m->d.nx) % m->d.ny, ez = e / (m->d.nx * m->d.ny);
         for (int nn = 0; nn < m->Np; ++nn) {
-            const int i = nn % m->n1, j = nn / m->n1;
-            x[(size_t)e * m->Np + nn] = m->d.x0 + ex * m->hx + 0.5 * (m->xi[i] + 1.0) * m->hx;
+            const int i = nn % n1, j = (nn / n1) % n1, k = nn / (n1 * n1);
+            const size_t at = (size_t)e * m->Np + nn;
+            x[at] = m->d.x0 + ex * m->hx + 0.5 * (m->xi[i] + 1.0) * m->hx;
             if (y)
-                y[(size_t)e * m->Np + nn] =
-                    (m->dim == 2) ? m->d.y0 + ey * m->hy + 0.5 * (m->xi[j] + 1.0) * m->hy : 0.0;
+                y[at] = (m->dim >= 2) ? m->d.y0 + ey * m->hy + 0.5 * (m->xi[j] + 1.0) * m->hy : 0.0;
+            if (z)
+                z[at] = (m->dim == 3) ? m->d.z0 + ez * m->hz + 0.5 * (m->xi[k] + 1.0) * m->hz : 0.0;
         }
     }
     return EXPDG_OK;

@@ -224,9 +224,9 @@ Task<int> phi_co(X &x, expdg_mesh *m, const T *qref, double tau, int p, const T 
     a.q = qref;
     a.lin = (const T *)m->lin;
     a.eta = eta;
-    // the dot pass of each Arnoldi step runs inside the 2D linear operator (a
+    // the dot pass of each Arnoldi step runs inside the 2D/3D linear operator (a
     // Burgers tile has too little work to carry it: separate pass there)
-    const bool fuse_dots = m->d.equation == EXPDG_EULER2D;
+    const bool fuse_dots = m->d.equation != EXPDG_BURGERS1D;
     a.basis = V;
     a.bstride = stride;
     a.dpart = kd.part;

@@ -202,12 +202,18 @@ __global__ __launch_bounds__(256) void euler_lin_prepare(const T *q, T *lin, int
 // nodes, u_i^T w and u_i^T x for i < nv (x = the input, w = the output, both as
 // stored), then x^T x and x^T w; tile 0 adds the augmented entries.  Row r of
 // the partials goes to dpart[r * dnb + tile], rows as in launch_gs_dots2.
-template <typename T, int NV>
+template <typename T, int NV, int NW = 4>
 __device__ __forceinline__ void op_dots2(const OpArgs<T> &a, bool active, unsigned idx,
                                          size_t plane, const T *xv, const T *wv, int tile,
                                          bool first) {
-    __shared__ double sw[4][32];
-    __shared__ double s2[4][2];
+    static_assert(NW == 4 || NW == 6, "blocks of 256 or 384 threads");
+    __shared__ double sw[NW][32];
+    __shared__ double s2[NW][2];
+    // fixed-order sum over the block's waves
+    auto wsum = [](double v0, double v1, double v2, double v3, double v4, double v5) {
+        const double s4 = (v0 + v1) + (v2 + v3);
+        return NW == 4 ? s4 : s4 + (v4 + v5);
+    };
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const size_t ntot = NV * plane;
     const int nv = a.nv;
@@ -263,7 +269,9 @@ __device__ __forceinline__ void op_dots2(const OpArgs<T> &a, bool active, unsign
         __syncthreads();
         if (tid < 32 && i0 + (tid & 15) < nv) {
             const int row = (tid < 16) ? i0 + tid : nv + i0 + (tid - 16);
-            a.dpart[(size_t)row * a.dnb + tile] = (sw[0][tid] + sw[1][tid]) + (sw[2][tid] + sw[3][tid]);
+            a.dpart[(size_t)row * a.dnb + tile] =
+                wsum(sw[0][tid], sw[1][tid], sw[2][tid], sw[3][tid], sw[NW > 4 ? 4 : 0][tid],
+                     sw[NW > 5 ? 5 : 0][tid]);
         }
         __syncthreads();
     }
@@ -292,7 +300,8 @@ __device__ __forceinline__ void op_dots2(const OpArgs<T> &a, bool active, unsign
     __syncthreads();
     if (tid < 2)
         a.dpart[(size_t)(2 * nv + tid) * a.dnb + tile] =
-            (s2[0][tid] + s2[1][tid]) + (s2[2][tid] + s2[3][tid]);
+            wsum(s2[0][tid], s2[1][tid], s2[2][tid], s2[3][tid], s2[NW > 4 ? 4 : 0][tid],
+                 s2[NW > 5 ? 5 : 0][tid]);
 }
 
 // ---- Euler 2D operator ------------------------------------------------------
@@ -451,6 +460,291 @@ __device__ __forceinline__ void euler_op_body(const OpArgs<T> &a, int tile, bool
         for (int c = 0; c < 4; ++c) wv[c] = T(0);
     }
     if (JVP && a.dots) op_dots2<T, 4>(a, active, idx, plane, u, wv, tile, first);
+}
+
+// ---- Euler 3D operator ------------------------------------------------------
+// q = (rho, m, n, l, E) with (m, n, l) = rho (u, v, w); the system of
+// Section 3.2 written for three velocity components (the extruded problem of
+// Section 5.2).  Frozen fields of the linear operator: planes u, v, w, H, then
+// the Rusanov speed of every x, y and z face node (N1^2 per element each).
+
+// Physical flux along DIR.
+template <typename T, int DIR>
+__device__ __forceinline__ void euler3_flux_dir(const T *q, T gm1, T *f) {
+    const T ir = T(1) / q[0];
+    const T u = q[1] * ir, v = q[2] * ir, w = q[3] * ir;
+    const T p = gm1 * (q[4] - T(0.5) * (q[1] * u + q[2] * v + q[3] * w));
+    const T un = DIR == 0 ? u : (DIR == 1 ? v : w);
+    f[0] = q[1 + DIR];
+    f[1] = q[1] * un + (DIR == 0 ? p : T(0));
+    f[2] = q[2] * un + (DIR == 1 ? p : T(0));
+    f[3] = q[3] * un + (DIR == 2 ? p : T(0));
+    f[4] = (q[4] + p) * un;
+}
+
+template <typename T, int DIR>
+__device__ __forceinline__ T euler3_speed(const T *q, T gamma) {
+    const T ir = T(1) / q[0];
+    const T u = q[1] * ir, v = q[2] * ir, w = q[3] * ir;
+    const T p = (gamma - T(1)) * (q[4] - T(0.5) * (q[1] * u + q[2] * v + q[3] * w));
+    return fabs(DIR == 0 ? u : (DIR == 1 ? v : w)) + sqrt(gamma * p * ir);
+}
+
+// Directional derivative of the flux along DIR from the frozen fields
+// z = (u, v, w, H): with al = dm - u drho, be = dn - v drho, ga = dl - w drho,
+// dp = (g-1)(dE - u al - v be - w ga - |u|^2/2 drho),
+//   dF_x = (dm, u (dm + al) + dp, u dn + v al, u dl + w al, u (dE + dp) + H al),
+//   dF_y = (dn, u dn + v al, v (dn + be) + dp, v dl + w be, v (dE + dp) + H be),
+//   dF_z = (dl, u dl + w al, v dl + w be, w (dl + ga) + dp, w (dE + dp) + H ga).
+template <typename T, int DIR>
+__device__ __forceinline__ void euler3_jac_lin_dir(const T *z, const T *d, T gm1, T *f) {
+    const T u = z[0], v = z[1], w = z[2], H = z[3];
+    const T al = fma(-u, d[0], d[1]), be = fma(-v, d[0], d[2]), ga = fma(-w, d[0], d[3]);
+    const T k = T(0.5) * fma(u, u, fma(v, v, w * w));
+    const T dp = gm1 * fma(-k, d[0], fma(-w, ga, fma(-v, be, fma(-u, al, d[4]))));
+    const T ep = d[4] + dp;
+    if (DIR == 0) {
+        f[0] = d[1];
+        f[1] = fma(u, d[1] + al, dp);
+        f[2] = fma(u, d[2], v * al);
+        f[3] = fma(u, d[3], w * al);
+        f[4] = fma(u, ep, H * al);
+    } else if (DIR == 1) {
+        f[0] = d[2];
+        f[1] = fma(u, d[2], v * al);
+        f[2] = fma(v, d[2] + be, dp);
+        f[3] = fma(v, d[3], w * be);
+        f[4] = fma(v, ep, H * be);
+    } else {
+        f[0] = d[3];
+        f[1] = fma(u, d[3], w * al);
+        f[2] = fma(v, d[3], w * be);
+        f[3] = fma(w, d[3] + ga, dp);
+        f[4] = fma(w, ep, H * ga);
+    }
+}
+
+template <int P, typename T>
+__global__ __launch_bounds__(256) void euler3_lin_prepare(const T *q, T *lin, int K, int nx,
+                                                          int ny, int nz, T gamma) {
+    constexpr int N1 = P + 1, NP = N1 * N1 * N1, NF = N1 * N1;
+    const size_t plane = (size_t)K * NP;
+    const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= plane) return;
+    const int e = (int)(t / NP), n = (int)(t - (size_t)e * NP);
+    const int i = n % N1, j = (n / N1) % N1, k = n / NF;
+    T qq[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) qq[c] = q[c * plane + t];
+    const T ir = T(1) / qq[0];
+    const T u = qq[1] * ir, v = qq[2] * ir, w = qq[3] * ir;
+    const T p = (gamma - T(1)) * (qq[4] - T(0.5) * (qq[1] * u + qq[2] * v + qq[3] * w));
+    lin[t] = u;
+    lin[plane + t] = v;
+    lin[2 * plane + t] = w;
+    lin[3 * plane + t] = (qq[4] + p) * ir;
+    T *lamx = lin + 4 * plane, *lamy = lamx + (size_t)K * NF, *lamz = lamy + (size_t)K * NF;
+    const int ex = e % nx, ey = (e / nx) % ny, ez = e / (nx * ny);
+    T qn[5];
+    if (i == P) {
+        const int en = (ez * ny + ey) * nx + (ex + 1 == nx ? 0 : ex + 1);
+        const size_t nidx = (size_t)en * NP + (k * N1 + j) * N1;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) qn[c] = q[c * plane + nidx];
+        lamx[(size_t)e * NF + k * N1 + j] =
+            fmax(euler3_speed<T, 0>(qq, gamma), euler3_speed<T, 0>(qn, gamma));
+    }
+    if (j == P) {
+        const int en = (ez * ny + (ey + 1 == ny ? 0 : ey + 1)) * nx + ex;
+        const size_t nidx = (size_t)en * NP + (k * N1) * N1 + i;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) qn[c] = q[c * plane + nidx];
+        lamy[(size_t)e * NF + k * N1 + i] =
+            fmax(euler3_speed<T, 1>(qq, gamma), euler3_speed<T, 1>(qn, gamma));
+    }
+    if (k == P) {
+        const int en = ((ez + 1 == nz ? 0 : ez + 1) * ny + ey) * nx + ex;
+        const size_t nidx = (size_t)en * NP + j * N1 + i;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) qn[c] = q[c * plane + nidx];
+        lamz[(size_t)e * NF + j * N1 + i] =
+            fmax(euler3_speed<T, 2>(qq, gamma), euler3_speed<T, 2>(qn, gamma));
+    }
+}
+
+// Block size of the 3D operator: 256 threads (floor(256/Np) elements) up to
+// p = 5, one element per 384-thread block at p = 6 (343 nodes).
+template <int P>
+struct E3Shape {
+    static constexpr int N1 = P + 1, NP = N1 * N1 * N1;
+    static constexpr int BS = NP > 256 ? 384 : 256;
+    static constexpr int EPB = BS / NP, NT = EPB * NP, NW = BS / 64;
+};
+
+// Face term of the node on the DIR face on side s: the neighbour's trace, its
+// flux and lambda; res -= (2/h)(1/w_0) [ s (F_n - F)/2 + lam (u - u_n)/2 ].
+template <int P, typename T, bool JVP, int DIR>
+__device__ __forceinline__ void euler3_face(const OpArgs<T> &a, const T *const *src,
+                                            const T *const *vin, const T *lamd, int e, int en,
+                                            unsigned nidx, int fidx, int s, T rh, const T *q,
+                                            const T *u, const T *fd, T gm1, T *res) {
+    T qn[5], un[5], fn[5], lam;
+    if (JVP) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) qn[c] = ld32(src[c], nidx);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) un[c] = ld32(vin[c], nidx);
+        euler3_jac_lin_dir<T, DIR>(qn, un, gm1, fn);
+        constexpr int NF = (P + 1) * (P + 1);
+        lam = ld32(lamd, (unsigned)(s > 0 ? e : en) * NF + fidx);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) qn[c] = un[c] = ld32(src[c], nidx);
+        euler3_flux_dir<T, DIR>(qn, gm1, fn);
+        lam = fmax(euler3_speed<T, DIR>(q, a.gamma), euler3_speed<T, DIR>(qn, a.gamma));
+    }
+    const T cf = rh * a.lift;
+    const T ca = cf * T(0.5) * T(s), cb = cf * T(0.5) * lam;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) res[c] = fma(-cb, u[c] - un[c], fma(-ca, fn[c] - fd[c], res[c]));
+}
+
+template <int P, typename T, bool JVP>
+__device__ __forceinline__ void euler3_op_body(const OpArgs<T> &a, int tile, bool first) {
+    using S = E3Shape<P>;
+    constexpr int N1 = S::N1, NP = S::NP, NF = N1 * N1, EPB = S::EPB, NT = S::NT;
+    __shared__ T sF[15][NT];
+    __shared__ T sDx[N1 * N1], sDy[N1 * N1], sDz[N1 * N1];
+    const int tid = threadIdx.x;
+    const int le = tid / NP;
+    const int n = tid - le * NP;
+    const int i = n % N1, j = (n / N1) % N1, k = n / NF;
+    const int e = tile * EPB + le;
+    const bool active = (tid < NT) && (e < a.K);
+    const size_t plane = (size_t)a.K * NP;
+    const unsigned idx = (unsigned)e * NP + n;
+    const T gm1 = a.gamma - T(1);
+    if (tid < N1 * N1) {
+        sDx[tid] = -a.rhx * a.D[tid];
+        sDy[tid] = -a.rhy * a.D[tid];
+        sDz[tid] = -a.rhz * a.D[tid];
+    }
+    const T *src[5], *vin[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        src[c] = (JVP ? a.lin : a.q) + c * plane;  // lin: u, v, w, H planes (the fifth unused)
+        vin[c] = JVP ? a.v + c * plane : src[c];
+    }
+    T sc = T(1);
+    if (a.vscale) sc = (T)(*a.vscale);
+    if (a.naug > 0 && first && tid == 0) {
+        for (int kk = 0; kk < a.naug; ++kk)
+            a.otail[kk] = (kk + 1 < a.naug) ? sc * a.vtail[kk + 1] : T(0);
+    }
+    const int nxy = a.nx * a.ny;
+    const int ex = e % a.nx, ey = (e / a.nx) % a.ny, ez = e / nxy;
+    const T *lamx = a.lin + 4 * plane, *lamy = lamx + (size_t)a.K * NF,
+            *lamz = lamy + (size_t)a.K * NF;
+    T q[5], u[5], fx[5], fy[5], fz[5];
+    if (active) {
+        if (JVP) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) q[c] = ld32(src[c], idx);
+            q[4] = T(0);
+#pragma unroll
+            for (int c = 0; c < 5; ++c) u[c] = ld32(vin[c], idx);
+            euler3_jac_lin_dir<T, 0>(q, u, gm1, fx);
+            euler3_jac_lin_dir<T, 1>(q, u, gm1, fy);
+            euler3_jac_lin_dir<T, 2>(q, u, gm1, fz);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 5; ++c) q[c] = u[c] = ld32(src[c], idx);
+            euler3_flux_dir<T, 0>(q, gm1, fx);
+            euler3_flux_dir<T, 1>(q, gm1, fy);
+            euler3_flux_dir<T, 2>(q, gm1, fz);
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) q[c] = u[c] = fx[c] = fy[c] = fz[c] = T(0);
+    }
+    if (tid < NT) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            sF[c][tid] = fx[c];
+            sF[5 + c][tid] = fy[c];
+            sF[10 + c][tid] = fz[c];
+        }
+    }
+
+    T res[5] = {T(0), T(0), T(0), T(0), T(0)};
+    if (active && (i == 0 || i == P)) {
+        const int s = (i == P) ? 1 : -1;
+        int exn = ex + s;
+        exn = exn < 0 ? a.nx - 1 : (exn >= a.nx ? 0 : exn);
+        const int en = ez * nxy + ey * a.nx + exn;
+        const unsigned nidx = (unsigned)en * NP + (k * N1 + j) * N1 + (P - i);
+        euler3_face<P, T, JVP, 0>(a, src, vin, lamx, e, en, nidx, k * N1 + j, s, a.rhx, q, u, fx,
+                                  gm1, res);
+    }
+    if (active && (j == 0 || j == P)) {
+        const int s = (j == P) ? 1 : -1;
+        int eyn = ey + s;
+        eyn = eyn < 0 ? a.ny - 1 : (eyn >= a.ny ? 0 : eyn);
+        const int en = ez * nxy + eyn * a.nx + ex;
+        const unsigned nidx = (unsigned)en * NP + (k * N1 + (P - j)) * N1 + i;
+        euler3_face<P, T, JVP, 1>(a, src, vin, lamy, e, en, nidx, k * N1 + i, s, a.rhy, q, u, fy,
+                                  gm1, res);
+    }
+    if (active && (k == 0 || k == P)) {
+        const int s = (k == P) ? 1 : -1;
+        int ezn = ez + s;
+        const int nz = a.K / nxy;
+        ezn = ezn < 0 ? nz - 1 : (ezn >= nz ? 0 : ezn);
+        const int en = ezn * nxy + ey * a.nx + ex;
+        const unsigned nidx = (unsigned)en * NP + ((P - k) * N1 + j) * N1 + i;
+        euler3_face<P, T, JVP, 2>(a, src, vin, lamz, e, en, nidx, j * N1 + i, s, a.rhz, q, u, fz,
+                                  gm1, res);
+    }
+    if (active) {
+        for (int kk = 0; kk < a.naug; ++kk) {
+            const T *b = a.aug[kk];
+            if (!b) continue;
+            const T yk = (T)a.eta * a.vtail[kk];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) res[c] = fma(yk, ld32(b + c * plane, idx), res[c]);
+        }
+    }
+    __syncthreads();
+
+    T wv[5];
+    if (active) {
+        const int base = le * NP;
+#pragma unroll
+        for (int l = 0; l < N1; ++l) {
+            const T dx = sDx[i * N1 + l], dy = sDy[j * N1 + l], dz = sDz[k * N1 + l];
+            const int nxl = base + (k * N1 + j) * N1 + l;
+            const int nyl = base + (k * N1 + l) * N1 + i;
+            const int nzl = base + (l * N1 + j) * N1 + i;
+#pragma unroll
+            for (int c = 0; c < 5; ++c)
+                res[c] = fma(dz, sF[10 + c][nzl],
+                             fma(dy, sF[5 + c][nyl], fma(dx, sF[c][nxl], res[c])));
+        }
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            wv[c] = sc * res[c];
+            st32(a.out + c * plane, idx, wv[c]);
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) wv[c] = T(0);
+    }
+    if (JVP && a.dots) op_dots2<T, 5, S::NW>(a, active, idx, plane, u, wv, tile, first);
+}
+
+template <int P, typename T, bool JVP>
+__global__ __launch_bounds__(E3Shape<P>::BS) void euler3_op(OpArgs<T> a) {
+    euler3_op_body<P, T, JVP>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.x == 0);
 }
 
 // ---- Burgers 1D operator ----------------------------------------------------
@@ -650,6 +944,7 @@ hipError_t launch_burgers_group(bool jvp, const OpArgs<T> *items, const int *bst
 template <int P, typename T>
 hipError_t launch_group_p(int equation, bool jvp, bool visc, const OpArgs<T> *items,
                           const int *bstart, int n, int total, hipStream_t s) {
+    if (equation == EXPDG_EULER3D) return hipErrorInvalidValue;  // not served
     if (equation == EXPDG_EULER2D) {
         if (jvp)
             return launch_kernel(euler_op_group<P, T, true>, dim3(total), dim3(256), 0, s, items,
@@ -663,6 +958,12 @@ hipError_t launch_group_p(int equation, bool jvp, bool visc, const OpArgs<T> *it
 
 template <int P, typename T>
 hipError_t launch_p(int equation, bool jvp, const OpArgs<T> &a, hipStream_t s) {
+    if (equation == EXPDG_EULER3D) {
+        using S = E3Shape<P>;
+        const int grid = (a.K + S::EPB - 1) / S::EPB;
+        if (jvp) return launch_kernel(euler3_op<P, T, true>, dim3(grid), dim3(S::BS), 0, s, a);
+        return launch_kernel(euler3_op<P, T, false>, dim3(grid), dim3(S::BS), 0, s, a);
+    }
     if (equation == EXPDG_EULER2D) {
         constexpr int EPB = 256 / ((P + 1) * (P + 1));
         const int grid = (a.K + EPB - 1) / EPB;
@@ -703,6 +1004,12 @@ __global__ __launch_bounds__(256) void max_speed_kernel(int equation, const doub
          r += (size_t)gridDim.x * 256) {
         if (equation == EXPDG_BURGERS1D) {
             mx = fmax(mx, fabs(q[r]));
+        } else if (equation == EXPDG_EULER3D) {
+            const double qq[5] = {q[r], q[npts + r], q[2 * npts + r], q[3 * npts + r],
+                                  q[4 * npts + r]};
+            mx = fmax(mx, fmax(euler3_speed<double, 0>(qq, gamma),
+                               fmax(euler3_speed<double, 1>(qq, gamma),
+                                    euler3_speed<double, 2>(qq, gamma))));
         } else {
             const double qq[4] = {q[r], q[npts + r], q[2 * npts + r], q[3 * npts + r]};
             mx = fmax(mx, fmax(euler_speed<double, 0>(qq, gamma), euler_speed<double, 1>(qq, gamma)));
@@ -800,6 +1107,20 @@ int grid_for(size_t n) {
 template <typename T>
 hipError_t launch_lin_prepare(int equation, int p, const T *q, T *lin, int K, int nx, int ny,
                               double gamma, hipStream_t s) {
+    if (equation == EXPDG_EULER3D) {
+        const size_t npts = (size_t)K * (p + 1) * (p + 1) * (p + 1);
+        const dim3 grid((unsigned)((npts + 255) / 256));
+        const int nz = K / (nx * ny);
+        switch (p) {
+            case 1: return launch_kernel(euler3_lin_prepare<1, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, nz, (T)gamma);
+            case 2: return launch_kernel(euler3_lin_prepare<2, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, nz, (T)gamma);
+            case 3: return launch_kernel(euler3_lin_prepare<3, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, nz, (T)gamma);
+            case 4: return launch_kernel(euler3_lin_prepare<4, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, nz, (T)gamma);
+            case 5: return launch_kernel(euler3_lin_prepare<5, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, nz, (T)gamma);
+            case 6: return launch_kernel(euler3_lin_prepare<6, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, nz, (T)gamma);
+            default: return hipErrorInvalidValue;
+        }
+    }
     if (equation != EXPDG_EULER2D) return hipSuccess;  // Burgers reads the state itself
     const size_t npts = (size_t)K * (p + 1) * (p + 1);
     const dim3 grid((unsigned)((npts + 255) / 256));
@@ -819,13 +1140,21 @@ template hipError_t launch_lin_prepare<float>(int, int, const float *, float *, 
                                               double, hipStream_t);
 
 size_t lin_elems(int equation, int p, int K) {
+    const size_t n1 = (size_t)p + 1;
+    if (equation == EXPDG_EULER3D) return (size_t)K * (4 * n1 * n1 * n1 + 3 * n1 * n1);
     if (equation != EXPDG_EULER2D) return 0;
-    return (size_t)K * (3 * (p + 1) * (p + 1) + 2 * (p + 1));
+    return (size_t)K * (3 * n1 * n1 + 2 * n1);
+}
+
+int dg_block_threads(int equation, int p) {
+    return (equation == EXPDG_EULER3D && (p + 1) * (p + 1) * (p + 1) > 256) ? 384 : 256;
 }
 
 int dg_blocks(int equation, int p, int K) {
-    const int np = (equation == EXPDG_EULER2D) ? (p + 1) * (p + 1) : (p + 1);
-    const int epb = 256 / np;
+    const int n1 = p + 1;
+    const int np = (equation == EXPDG_EULER3D) ? n1 * n1 * n1
+                   : (equation == EXPDG_EULER2D) ? n1 * n1 : n1;
+    const int epb = dg_block_threads(equation, p) / np;
     return (K + epb - 1) / epb;
 }
 

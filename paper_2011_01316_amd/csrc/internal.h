@@ -43,7 +43,7 @@ struct OpArgs {
     double eta;        // scaling of the augmented block
     int naug;          // p
     int K, nx, ny;
-    T rhx, rhy;        // 2/hx, 2/hy
+    T rhx, rhy, rhz;   // 2/hx, 2/hy, 2/hz
     T lift;            // 1/w_0 (= 1/w_p)
     T gamma;
     // Burgers options (Section 3.1): viscosity, entropy flux (residual only)
@@ -94,6 +94,8 @@ hipError_t launch_lin_prepare(int equation, int p, const T *q, T *lin, int K, in
 size_t lin_elems(int equation, int p, int K);
 // Blocks one operator launch uses for K elements.
 int dg_blocks(int equation, int p, int K);
+// Threads per block of the operator launches (256, or 384 for the 3D p = 6 one).
+int dg_block_threads(int equation, int p);
 // Grouped FP64 launch over n meshes of the same equation and degree: item it
 // owns blocks [bstart[it], bstart[it+1]) (device arrays), total = bstart[n].
 // visc selects the viscous Burgers kernels (every item then has kappa > 0).

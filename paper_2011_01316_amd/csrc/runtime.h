@@ -19,7 +19,7 @@ struct expdg_mesh {
     size_t n;       // ndof
     size_t stride;  // elements between Krylov vectors (>= n + kMaxAug)
     int ebytes;     // bytes per bulk element
-    double hx, hy, dxmin;
+    double hx, hy, hz, dxmin;
     double xi[expdg::kMaxP + 1], w[expdg::kMaxP + 1];
     double D[(expdg::kMaxP + 1) * (expdg::kMaxP + 1)];
 
@@ -133,6 +133,7 @@ OpArgs<T> op_args(const expdg_mesh *m) {
     a.ny = m->d.ny;
     a.rhx = (T)(2.0 / m->hx);
     a.rhy = (T)(2.0 / m->hy);
+    a.rhz = (T)(2.0 / m->hz);
     a.lift = (T)(1.0 / m->w[0]);
     a.gamma = (T)m->d.gamma;
     for (int k = 0; k < m->n1 * m->n1; ++k) a.D[k] = (T)m->D[k];

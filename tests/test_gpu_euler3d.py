@@ -1,0 +1,166 @@
+"""Three-dimensional Euler on the GPU (the system of Section 3.2 with three
+velocity components, the extruded vortex of Section 5.2), through the C ABI,
+against the oracle.
+
+Tolerances as in 2D: operators to 1e-12 of the largest output, phi
+combinations and steps on replayed schedules to 1e-12 relative, adaptive runs
+with the oracle's decisions.  Shapes cover every compiled degree, a single
+element (every neighbour is the element itself), ragged last blocks, and the
+one-element-per-384-thread-block layout of p = 6.  At the size of the paper's
+strong-scaling run (80 x 80 x 8 elements, p = 6, 87.8M DOF) the z-independent
+vortex is checked against the 2D operator on the GPU (the w components vanish
+and the others equal the 2D residual node by node).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2011_01316_amd import binding as B
+from paper_2011_01316_amd import inputs
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+DOM = dict(x0=0.0, x1=10.0, y0=-5.0, y1=5.0, z0=0.0, z1=1.0)
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def maxrel(a, b):
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+
+
+def pair(nx, ny, nz, p, m_max=64, precision=B.FP64, dom=DOM):
+    om = oracle.Mesh(oracle.EULER3D, nx, p, ny=ny, nz=nz, **dom)
+    gm = B.Mesh(B.EULER3D, nx, p, ny=ny, nz=nz, m_max=m_max, precision=precision, **dom)
+    return om, gm
+
+
+def random_state(npts, seed):
+    g = np.random.default_rng(seed)
+    rho = 1.0 + 0.2 * g.uniform(-1, 1, npts)
+    vel = [0.3 * g.uniform(-1, 1, npts) for _ in range(3)]
+    p = 1.0 + 0.2 * g.uniform(-1, 1, npts)
+    E = p / 0.4 + 0.5 * rho * sum(v * v for v in vel)
+    return np.concatenate([rho] + [rho * v for v in vel] + [E])
+
+
+SHAPES = [(1, 1, 1, 1), (1, 1, 1, 6), (2, 3, 2, 2), (3, 2, 4, 3), (4, 4, 2, 4), (2, 2, 3, 5),
+          (3, 2, 2, 6), (5, 3, 2, 1)]
+
+
+@pytest.mark.parametrize("nx,ny,nz,p", SHAPES)
+def test_nodes_and_operators(nx, ny, nz, p):
+    om, gm = pair(nx, ny, nz, p)
+    with gm:
+        assert gm.n == om.n
+        gx, gy, gz = gm.nodes()
+        ox, oy, oz = om.nodes()
+        for a, b in ((gx, ox), (gy, oy), (gz, oz)):
+            np.testing.assert_allclose(a, b, atol=1e-14)
+        q = random_state(om.K * om.Np, nx * 100 + ny * 10 + nz + p)
+        v = np.random.default_rng(p).standard_normal(om.n)
+        qt, vt = dev(q), dev(v)
+        r = torch.empty_like(qt)
+        w = torch.empty_like(qt)
+        gm.rhs(qt, r)
+        gm.jvp(qt, vt, w)
+        assert maxrel(host(r), om.rhs(q)) < 1e-12, maxrel(host(r), om.rhs(q))
+        assert maxrel(host(w), om.jvp(q, v)) < 1e-12, maxrel(host(w), om.jvp(q, v))
+
+
+def test_max_speed():
+    om, gm = pair(3, 2, 2, 3)
+    with gm:
+        q = random_state(om.K * om.Np, 3)
+        c, _ = om.max_speed(q)
+        assert abs(gm.max_speed(dev(q)) - c) <= 1e-14 * c
+
+
+@pytest.mark.parametrize("p", [1, 2])
+@pytest.mark.parametrize("iop", [0, 2])
+def test_phi_substeps(p, iop):
+    om, gm = pair(4, 3, 2, 3, m_max=16)
+    with gm:
+        x, y, z = om.nodes()
+        q = inputs.vortex3d(x, y, z, beta=3.0).reshape(-1)
+        R = om.rhs(q)
+        b = [None, R, np.random.default_rng(3).standard_normal(om.n) * 0.1][: p + 1]
+        c, dx = om.max_speed(q)
+        # Courant number 10, m_max 16: 3 to 7 substeps with rejections; as in
+        # the 2D stress case the substeps' exponentials (several squarings
+        # each) compound their rounding, so the bar is 2e-11
+        tau = 10.0 * dx / c
+        ref, st = om.phi_krylov(q, tau, b, tol=1e-10, m_min=4, m_max=16, stats=True, iop=iop)
+        assert st["substeps"] > 1 and st["rejects"] > 0
+        bt = [None if bb is None else dev(bb) for bb in b]
+        qt = dev(q)
+        w = torch.empty_like(qt)
+        gm.phi_krylov(qt, tau, bt, w, B.make_opts(1e-10, 4, 16, forced=st["log"], iop=iop))
+        assert rel(host(w), ref) < 2e-11, rel(host(w), ref)
+        gs = B.make_stats()
+        gm.phi_krylov(qt, tau, bt, w, B.make_opts(1e-10, 4, 16, iop=iop), gs)
+        d = B.stats_dict(gs)
+        assert d["substeps"] == st["substeps"] and d["rejects"] == st["rejects"]
+
+
+@pytest.mark.parametrize("scheme", [B.EPI2, B.EPI3, B.EXPRB32, B.EXPRB42])
+def test_steps_extruded_vortex(scheme):
+    # a vortex of strength 2 on 8 x 8 x 2 elements of degree 3 (a strength-5
+    # core spans less than an element here and the collocation scheme blows up,
+    # oracle included)
+    om, gm = pair(8, 8, 2, 3)
+    with gm:
+        x, y, z = om.nodes()
+        q0 = inputs.vortex3d(x, y, z, beta=2.0).reshape(-1)
+        c, dx = om.max_speed(q0)
+        dt = 5.0 * dx / c
+        kw = dict(tol=1e-10, m_min=10, m_max=64)
+        q_o, qp_o = q0, None
+        q = dev(q0)
+        qp = torch.empty_like(q)
+        for k in range(2):
+            q_o, qp_o, st = om.step(scheme, dt, q_o, qp_o, stats=True, **kw)
+            gm.step(scheme, dt, q, qp, k > 0, B.make_opts(forced=st["log"], **kw))
+            assert rel(host(q), q_o) < 1e-12, (k, rel(host(q), q_o))
+
+
+def test_paper_size_extrusion_matches_2d():
+    # 80 x 80 x 8 elements of degree 6 on (0,10) x (-5,5) x (0,1): the size of
+    # the paper's strong-scaling run (87.8M DOF, 702 MB per vector)
+    nx, nz, p = 80, 8, 6
+    with B.Mesh(B.EULER3D, nx, p, ny=nx, nz=nz, m_max=2, **DOM) as g3:
+        x, y, z = g3.nodes()
+        n1 = p + 1
+        q3 = inputs.vortex3d(x, y, z, beta=5.0).reshape(5, nz, nx * nx, n1, n1, n1)
+        qt = dev(q3.reshape(-1))
+        r3 = torch.empty_like(qt)
+        g3.rhs(qt, r3)
+        r3 = host(r3).reshape(5, nz, nx * nx, n1, n1, n1)
+        del qt
+    with B.Mesh(B.EULER2D, nx, p, ny=nx, x0=0.0, x1=10.0, y0=-5.0, y1=5.0, m_max=2) as g2:
+        q2 = q3[[0, 1, 2, 4], 0, :, 0]  # the bottom layer's z = z_0 plane
+        qt = dev(q2.reshape(-1))
+        r2 = torch.empty_like(qt)
+        g2.rhs(qt, r2)
+        r2 = host(r2).reshape(4, nx * nx, n1, n1)
+    scale = np.max(np.abs(r2))
+    assert np.max(np.abs(r3[3])) <= 1e-12 * scale
+    for c3, c2 in ((0, 0), (1, 1), (2, 2), (4, 3)):
+        for ez in (0, nz - 1):
+            for k in (0, p):
+                d = np.max(np.abs(r3[c3, ez, :, k] - r2[c2]))
+                assert d <= 1e-12 * scale, (c3, ez, k, d / scale)

@@ -57,7 +57,7 @@ def test_lgl_rejects_bad_degree():
 def desc(**kw):
     d = dict(equation=B.EULER2D, nx=64, ny=64, p=4, precision=B.FP64, device=0, x0=0.0,
              x1=10.0, y0=0.0, y1=10.0, gamma=1.4, m_max=64, kappa=0.0, flux=B.FLUX_LF,
-             sigma=0.0, beta=0.0, bc=B.BC_PERIODIC, has_source=0)
+             sigma=0.0, beta=0.0, bc=B.BC_PERIODIC, has_source=0, nz=1, z0=0.0, z1=1.0)
     d.update(kw)
     return B.MeshDesc(*[d[f] for f, _ in B.MeshDesc._fields_])
 
@@ -69,7 +69,7 @@ def test_workspace_bytes_and_validation():
     assert B.expdg_workspace_bytes(desc(m_max=32)) < ok
     assert B.expdg_workspace_bytes(desc(precision=B.FP32_BULK)) < ok
     for bad in [dict(p=0), dict(p=7), dict(nx=0), dict(m_max=0), dict(m_max=65),
-                dict(equation=3), dict(precision=2), dict(x1=-1.0), dict(gamma=1.0),
+                dict(equation=4), dict(precision=2), dict(x1=-1.0), dict(gamma=1.0),
                 dict(equation=B.BURGERS1D, ny=2)]:
         assert B.expdg_workspace_bytes(desc(**bad)) == 0, bad
     h = C.c_void_p()
@@ -91,6 +91,28 @@ def test_burgers_options_validation():
     for bad in [dict(kappa=0.1), dict(flux=B.FLUX_EF), dict(sigma=1e-3), dict(beta=0.5),
                 dict(bc=B.BC_DIRICHLET), dict(has_source=1)]:
         assert B.expdg_workspace_bytes(desc(**bad)) == 0, bad
+
+
+def test_euler3d_validation():
+    e3 = dict(equation=B.EULER3D, nx=8, ny=8, nz=4, p=3, x1=10.0, y0=-5.0, y1=5.0, z1=1.0)
+    ok = B.expdg_workspace_bytes(desc(**e3))
+    ndof = 5 * 8 * 8 * 4 * 64
+    assert ok > 65 * ndof * 8
+    for bad in [dict(nz=0), dict(z1=0.0), dict(kappa=0.1), dict(bc=B.BC_DIRICHLET), dict(p=7)]:
+        assert B.expdg_workspace_bytes(desc(**dict(e3, **bad))) == 0, bad
+    # the workspace (Krylov block, frozen fields of the linear operator, block
+    # partials) scales with all nz layers of elements
+    w4 = B.expdg_workspace_bytes(desc(**dict(e3, nz=16)))
+    w8 = B.expdg_workspace_bytes(desc(**dict(e3, nz=32)))
+    assert w8 > 1.95 * w4
+    # nz > 1 only in 3D
+    assert B.expdg_workspace_bytes(desc(nz=2)) == 0
+    # served solves are 1D or 2D
+    req = B.make_request(B.EULER2D, 8, 3, ny=8, nsteps=2, dt=1e-2, x1=10.0, y1=10.0)
+    assert B.expdg_request_bytes(req) > 0
+    req.mesh.equation = B.EULER3D
+    req.mesh.nz = 2
+    assert B.expdg_request_bytes(req) == 0
 
 
 def test_served_requests_take_no_source():
