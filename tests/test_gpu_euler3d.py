@@ -164,3 +164,41 @@ def test_paper_size_extrusion_matches_2d():
             for k in (0, p):
                 d = np.max(np.abs(r3[c3, ez, :, k] - r2[c2]))
                 assert d <= 1e-12 * scale, (c3, ez, k, d / scale)
+
+
+def test_fp32_bulk_operators_and_step():
+    # FP32 bulk on float-rounded inputs: every entry within c u32 S as in 2D
+    # (S = (2/h)(max_i sum_l |D_il| + 1/w_0) max |F|, c = 4 (p + 11) plus the
+    # third direction's terms: c = 6 (p + 11)); one EPI2 step within 1e-6 of
+    # the FP64 one at the state level
+    nx, ny, nz, p = 4, 4, 2, 3
+    om = oracle.Mesh(oracle.EULER3D, nx, p, ny=ny, nz=nz, **DOM)
+    x, y, z = om.nodes()
+    q = inputs.vortex3d(x, y, z, beta=2.0).reshape(-1).astype(np.float32)
+    v = (q * (1.0 + 0.1 * np.random.default_rng(4).standard_normal(q.size))).astype(np.float32)
+    with B.Mesh(B.EULER3D, nx, p, ny=ny, nz=nz, precision=B.FP32_BULK, **DOM) as gm:
+        qt = torch.tensor(q, device=DEV)
+        vt = torch.tensor(v, device=DEV)
+        r = torch.empty_like(qt)
+        w = torch.empty_like(qt)
+        gm.rhs(qt, r)
+        gm.jvp(qt, vt, w)
+        qd, vd = q.astype(np.float64), v.astype(np.float64)
+        ro, wo = om.rhs(qd), om.jvp(qd, vd)
+        xi, wq, D = oracle.lgl(p)
+        h = min(10.0 / nx, 10.0 / ny, 1.0 / nz)
+        st = (2.0 / h) * (np.abs(D).sum(axis=1).max() + 1.0 / wq[0])
+        fmax = 4.0 * max(np.abs(qd).max(), 1.0) ** 2
+        bound = 6 * (p + 11) * 2.0 ** -24 * st * fmax
+        assert np.max(np.abs(host(r).astype(np.float64) - ro)) <= bound
+        assert np.max(np.abs(host(w).astype(np.float64) - wo)) <= bound * 4.0
+    q0 = inputs.vortex3d(x, y, z, beta=2.0).reshape(-1)
+    c, dx = om.max_speed(q0)
+    dt = 5.0 * dx / c
+    out = {}
+    for prec, tol in ((B.FP64, 1e-10), (B.FP32_BULK, 1e-7)):
+        with B.Mesh(B.EULER3D, nx, p, ny=ny, nz=nz, precision=prec, **DOM) as gm:
+            qq = dev(q0)
+            gm.step(B.EPI2, dt, qq, None, False, B.make_opts(tol, 10, 64))
+            out[prec] = host(qq)
+    assert rel(out[B.FP32_BULK], out[B.FP64]) < 1e-6
