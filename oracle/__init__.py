@@ -53,7 +53,8 @@ class _Mesh(C.Structure):
                 ("gamma", C.c_double), ("kappa", C.c_double), ("flux", C.c_int),
                 ("sigma", C.c_double), ("beta", C.c_double), ("bc", C.c_int),
                 ("source", C.POINTER(C.c_double)), ("nz", C.c_int), ("z0", C.c_double),
-                ("z1", C.c_double)]
+                ("z1", C.c_double), ("ev_ce", C.c_double), ("ev_cmax", C.c_double),
+                ("nu", C.POINTER(C.c_double))]
 
 
 class Substep(C.Structure):
@@ -128,6 +129,8 @@ def _declare(L):
     L.orc_rhs.argtypes = [mp, dp, dp]
     L.orc_jvp.argtypes = [mp, dp, dp, dp]
     L.orc_gradient.argtypes = [mp, dp, dp]
+    L.orc_ev_diffusion.argtypes = [mp, dp, dp]
+    L.orc_entropy_viscosity.argtypes = [mp, dp, dp, C.c_double, dp]
     L.orc_jvp_complex_step.argtypes = [mp, dp, dp, C.c_double, dp]
     L.orc_assemble_jvp.argtypes = [mp, dp, dp]
     L.orc_max_speed.argtypes = [mp, dp, dp, dp]
@@ -168,15 +171,19 @@ class Mesh:
                  x1: float = 1.0, y0: float = 0.0, y1: float = 1.0, gamma: float = 1.4,
                  kappa: float = 0.0, flux: int = FLUX_LF, sigma: float = 0.0,
                  beta: float = 0.0, bc: int = BC_PERIODIC, source=None, nz: int = 1,
-                 z0: float = 0.0, z1: float = 1.0):
+                 z0: float = 0.0, z1: float = 1.0, ev_ce: float = 0.0, ev_cmax: float = 0.0,
+                 nu=None):
         self.equation, self.nx, self.ny, self.nz, self.p = equation, nx, ny, nz, p
         self.z0, self.z1 = z0, z1
         self.x0, self.x1, self.y0, self.y1, self.gamma = x0, x1, y0, y1, gamma
         self.kappa, self.flux, self.sigma, self.beta, self.bc = kappa, flux, sigma, beta, bc
         self.source = None if source is None else np.ascontiguousarray(source, dtype=np.float64)
         sp = _dp(self.source) if self.source is not None else C.POINTER(C.c_double)()
+        self.ev_ce, self.ev_cmax = ev_ce, ev_cmax
+        self.nu = None if nu is None else np.ascontiguousarray(nu, dtype=np.float64)
+        nup = _dp(self.nu) if self.nu is not None else C.POINTER(C.c_double)()
         self._m = _Mesh(equation, nx, ny, p, x0, x1, y0, y1, gamma, kappa, flux, sigma, beta,
-                        bc, sp, nz, z0, z1)
+                        bc, sp, nz, z0, z1, ev_ce, ev_cmax, nup)
         dim = {BURGERS1D: 1, EULER2D: 2, EULER3D: 3}.get(equation, 1)
         self.dim = dim
         self.nvar = 1 if equation == BURGERS1D else dim + 2
@@ -220,6 +227,22 @@ class Mesh:
         w = np.zeros(self.n)
         _check(lib().orc_jvp(C.byref(self._m), _dp(qref), _dp(v), _dp(w)), "jvp")
         return w
+
+    def entropy_viscosity(self, q, q_prev, dt):
+        """Nodal entropy viscosity (K*Np values) of q after q_prev, step dt."""
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        q_prev = np.ascontiguousarray(q_prev, dtype=np.float64)
+        nu = np.zeros(self.K * self.Np)
+        _check(lib().orc_entropy_viscosity(C.byref(self._m), _dp(q), _dp(q_prev), dt, _dp(nu)),
+               "entropy viscosity")
+        return nu
+
+    def ev_diffusion(self, v):
+        """div(nu grad v) with the mesh's nodal viscosity."""
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        out = np.zeros(self.n)
+        _check(lib().orc_ev_diffusion(C.byref(self._m), _dp(v), _dp(out)), "ev diffusion")
+        return out
 
     def gradient(self, u):
         """Auxiliary variable q(u) of viscous Burgers (eq. gov-burgers1d-gradu)."""

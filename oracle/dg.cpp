@@ -67,6 +67,8 @@ struct Geo {
     double kappa, sigma, beta;
     int flux, bc;
     const double *src;
+    double ev_ce, ev_cmax;
+    const double *nu;
     std::vector<double> xi, w, D;
 };
 
@@ -88,6 +90,8 @@ bool make_geo(const orc_mesh *m, Geo *g) {
     if (m->equation != ORC_BURGERS1D &&
         (m->kappa != 0.0 || m->flux != ORC_FLUX_LF || m->bc != ORC_BC_PERIODIC || m->source))
         return false;
+    if (!(m->ev_ce >= 0.0) || !(m->ev_cmax >= 0.0)) return false;
+    if (m->equation != ORC_EULER2D && (m->ev_ce > 0.0 || m->nu)) return false;
     g->eq = m->equation;
     g->nx = m->nx;
     g->ny = m->ny;
@@ -111,6 +115,9 @@ bool make_geo(const orc_mesh *m, Geo *g) {
     g->flux = m->flux;
     g->bc = m->bc;
     g->src = m->source;
+    g->ev_ce = m->ev_ce;
+    g->ev_cmax = m->ev_cmax;
+    g->nu = m->nu;
     g->xi.resize(g->n1);
     g->w.resize(g->n1);
     g->D.resize(g->n1 * g->n1);
@@ -368,6 +375,70 @@ void add_diffusion(const Geo &g, const T *u, T *out) {
     }
 }
 
+// ---- entropy viscosity (Euler 2D) ------------------------------------------
+//
+// The linear diffusion div(nu grad v) of each conserved variable with the
+// nodal viscosity nu (Section 3.2, "Artificial viscosity": F^EV = nu grad q,
+// treated like the Burgers diffusion with central fluxes): per direction d
+//   g_d = (2/h_d) D_d v + (2/h_d)(1/w_end) n_d ({{v}} - v^-)          (faces along d)
+//   out += (2/h_d) D_d (nu g_d) + (2/h_d)(1/w_end) n_d ({{nu g_d}} - (nu g_d)^-).
+template <class T>
+void ev_diffusion(const Geo &g, const T *v, T *out) {
+    if (!g.nu) return;
+    const int n1 = g.n1, Np = g.Np, p = g.p;
+    const double h[2] = {g.hx, g.hy};
+    const size_t plane = (size_t)g.K * Np;
+    std::vector<T> G(2 * plane);
+    auto along = [&](int i, int j, int d, int l) { return d == 0 ? j * n1 + l : l * n1 + i; };
+    for (int c = 0; c < 4; ++c) {
+        const T *vc = v + c * plane;
+#pragma omp parallel for schedule(static)
+        for (int e = 0; e < g.K; ++e)
+            for (int j = 0; j < n1; ++j)
+                for (int i = 0; i < n1; ++i) {
+                    const int n = j * n1 + i, crd[2] = {i, j};
+                    for (int d = 0; d < 2; ++d) {
+                        const int a = crd[d];
+                        T acc = T(0.0);
+                        for (int l = 0; l < n1; ++l)
+                            acc += (2.0 / h[d]) * g.D[a * n1 + l] * vc[(size_t)e * Np + along(i, j, d, l)];
+                        for (int s = -1; s <= 1; s += 2) {
+                            if ((s == -1 && a != 0) || (s == 1 && a != p)) continue;
+                            const int en = neighbour(g, e, d, s);
+                            const int nn = along(i, j, d, p - a);
+                            const T vm = vc[(size_t)e * Np + n], vp = vc[(size_t)en * Np + nn];
+                            acc += (2.0 / h[d]) / g.w[a] * (double)s * (0.5 * (vm + vp) - vm);
+                        }
+                        G[d * plane + (size_t)e * Np + n] = acc;
+                    }
+                }
+#pragma omp parallel for schedule(static)
+        for (int e = 0; e < g.K; ++e)
+            for (int j = 0; j < n1; ++j)
+                for (int i = 0; i < n1; ++i) {
+                    const int n = j * n1 + i, crd[2] = {i, j};
+                    T acc = T(0.0);
+                    for (int d = 0; d < 2; ++d) {
+                        const int a = crd[d];
+                        for (int l = 0; l < n1; ++l) {
+                            const size_t at = (size_t)e * Np + along(i, j, d, l);
+                            acc += (2.0 / h[d]) * g.D[a * n1 + l] * (g.nu[at] * G[d * plane + at]);
+                        }
+                        for (int s = -1; s <= 1; s += 2) {
+                            if ((s == -1 && a != 0) || (s == 1 && a != p)) continue;
+                            const int en = neighbour(g, e, d, s);
+                            const size_t am = (size_t)e * Np + n;
+                            const size_t ap = (size_t)en * Np + along(i, j, d, p - a);
+                            const T fm = g.nu[am] * G[d * plane + am];
+                            const T fp = g.nu[ap] * G[d * plane + ap];
+                            acc += (2.0 / h[d]) / g.w[a] * (double)s * (0.5 * (fm + fp) - fm);
+                        }
+                    }
+                    out[c * plane + (size_t)e * Np + n] += acc;
+                }
+    }
+}
+
 template <class T>
 void residual_frozen(const Geo &g, const T *q, const double *lam_ref, T *r) {
     auto fl = [&](int e, int n, int dir, T *f) {
@@ -377,6 +448,7 @@ void residual_frozen(const Geo &g, const T *q, const double *lam_ref, T *r) {
     };
     dg_apply(g, q, lam_ref, fl, r, g.eq == ORC_BURGERS1D && g.flux == ORC_FLUX_EF);
     if (g.eq == ORC_BURGERS1D) add_diffusion(g, q, r);
+    if (g.eq == ORC_EULER2D) ev_diffusion(g, q, r);
 }
 
 void linear_op(const Geo &g, const double *qt, const double *v, double *w) {
@@ -388,6 +460,7 @@ void linear_op(const Geo &g, const double *qt, const double *v, double *w) {
     };
     dg_apply(g, v, qt, fl, w);
     if (g.eq == ORC_BURGERS1D) add_diffusion(g, v, w);
+    if (g.eq == ORC_EULER2D) ev_diffusion(g, v, w);
 }
 
 }  // namespace
@@ -439,6 +512,107 @@ int orc_rhs(const orc_mesh *m, const double *q, double *r) {
     if (g.src) {
         const size_t n = (size_t)g.nvar * g.K * g.Np;
         for (size_t i = 0; i < n; ++i) r[i] += g.src[i];
+    }
+    return 0;
+}
+
+int orc_ev_diffusion(const orc_mesh *m, const double *v, double *out) {
+    Geo g;
+    if (!make_geo(m, &g) || g.eq != ORC_EULER2D || !v || !out) return -1;
+    const size_t n = (size_t)g.nvar * g.K * g.Np;
+    for (size_t i = 0; i < n; ++i) out[i] = 0.0;
+    ev_diffusion<double>(g, v, out);
+    return 0;
+}
+
+// Entropy viscosity (Section 3.2, "Artificial viscosity", with the entropy
+// residual of its footnote): with S = rho/(g-1) log(p/rho^g) and the entropy
+// flux u S,
+//   Res = (S(q) - S(q_prev))/dt + (div(u S)(q) + div(u S)(q_prev))/2
+// at the nodes (element-local derivative); per element, with h = 2r/k (r the
+// radius of the element's circumscribed circle, k = p) = sqrt(hx^2+hy^2)/p,
+//   nu_E = c_E h^2 max(max|Res|, max|[[u S . n]]| / h),
+//   nu_max = c_max h max(|u . e_d| + a),  nu_e = min(nu_max, nu_E);
+// the vertex values average the four elements around each vertex, and nu at
+// a node is their bilinear interpolant on its element.
+int orc_entropy_viscosity(const orc_mesh *m, const double *q, const double *q_prev, double dt,
+                          double *nu) {
+    Geo g;
+    if (!make_geo(m, &g) || g.eq != ORC_EULER2D || !q || !q_prev || !nu || !(dt > 0.0))
+        return -1;
+    const int n1 = g.n1, Np = g.Np, p = g.p;
+    const size_t plane = (size_t)g.K * Np;
+    const double gm = g.gamma, h[2] = {g.hx, g.hy};
+    // S and the entropy flux at every node of q and q_prev
+    std::vector<double> S(2 * plane), F(4 * plane);  // F[(st*2 + d) * plane + i]
+    for (int st = 0; st < 2; ++st) {
+        const double *qq = st == 0 ? q : q_prev;
+        for (size_t i = 0; i < plane; ++i) {
+            const double rho = qq[i], u = qq[plane + i] / rho, v = qq[2 * plane + i] / rho;
+            const double pr = (gm - 1.0) * (qq[3 * plane + i] - 0.5 * rho * (u * u + v * v));
+            const double Sv = rho / (gm - 1.0) * std::log(pr / std::pow(rho, gm));
+            S[st * plane + i] = Sv;
+            F[(st * 2 + 0) * plane + i] = u * Sv;
+            F[(st * 2 + 1) * plane + i] = v * Sv;
+        }
+    }
+    const double he = std::sqrt(g.hx * g.hx + g.hy * g.hy) / p;
+    std::vector<double> nue(g.K);
+    for (int e = 0; e < g.K; ++e) {
+        double rmax = 0.0, jmax = 0.0, lam = 0.0;
+        for (int j = 0; j < n1; ++j)
+            for (int i = 0; i < n1; ++i) {
+                const int n = j * n1 + i, crd[2] = {i, j};
+                const size_t at = (size_t)e * Np + n;
+                double div[2] = {0.0, 0.0};
+                for (int st = 0; st < 2; ++st)
+                    for (int d = 0; d < 2; ++d)
+                        for (int l = 0; l < n1; ++l) {
+                            const int nl = d == 0 ? j * n1 + l : l * n1 + i;
+                            div[st] += (2.0 / h[d]) * g.D[crd[d] * n1 + l] *
+                                       F[(st * 2 + d) * plane + (size_t)e * Np + nl];
+                        }
+                const double res = (S[at] - S[plane + at]) / dt + 0.5 * (div[0] + div[1]);
+                rmax = std::fmax(rmax, std::fabs(res));
+                double qn[4];
+                load(g, q, e, n, qn);
+                for (int d = 0; d < 2; ++d) {
+                    lam = std::fmax(lam, wave_speed(g, qn, d));
+                    const int a = crd[d];
+                    for (int s = -1; s <= 1; s += 2) {
+                        if ((s == -1 && a != 0) || (s == 1 && a != p)) continue;
+                        const int en = neighbour(g, e, d, s);
+                        const int nn = d == 0 ? j * n1 + (p - a) : (p - a) * n1 + i;
+                        const double jump =
+                            F[d * plane + at] - F[d * plane + (size_t)en * Np + nn];
+                        jmax = std::fmax(jmax, std::fabs(jump));
+                    }
+                }
+            }
+        const double nu_e = g.ev_ce * he * he * std::fmax(rmax, jmax / he);
+        const double nu_max = g.ev_cmax * he * lam;
+        nue[e] = std::fmin(nu_max, nu_e);
+    }
+    // vertex (vx, vy) is the lower-left corner of element (vx, vy)
+    std::vector<double> vert(g.K);
+    for (int vy = 0; vy < g.ny; ++vy)
+        for (int vx = 0; vx < g.nx; ++vx) {
+            const int xm = (vx + g.nx - 1) % g.nx, ym = (vy + g.ny - 1) % g.ny;
+            vert[vy * g.nx + vx] = 0.25 * ((nue[vy * g.nx + vx] + nue[vy * g.nx + xm]) +
+                                           (nue[ym * g.nx + vx] + nue[ym * g.nx + xm]));
+        }
+    for (int e = 0; e < g.K; ++e) {
+        const int ex = e % g.nx, ey = e / g.nx;
+        const int xp = (ex + 1) % g.nx, yp = (ey + 1) % g.ny;
+        const double v00 = vert[ey * g.nx + ex], v10 = vert[ey * g.nx + xp];
+        const double v01 = vert[yp * g.nx + ex], v11 = vert[yp * g.nx + xp];
+        for (int j = 0; j < n1; ++j)
+            for (int i = 0; i < n1; ++i) {
+                const double r = 0.5 * (g.xi[i] + 1.0), t = 0.5 * (g.xi[j] + 1.0);
+                nu[(size_t)e * Np + j * n1 + i] =
+                    (1.0 - r) * (1.0 - t) * v00 + r * (1.0 - t) * v10 + (1.0 - r) * t * v01 +
+                    r * t * v11;
+            }
     }
     return 0;
 }

@@ -21,6 +21,9 @@
  *     q = u_x with central or LDG (Appendix A) diffusion fluxes, the entropy
  *     flux (EF) or Lax-Friedrichs for (u^2/2)*, zero Dirichlet ends as in the
  *     footnote at the start of Section 6, and a nodal source term
+ *   - entropy viscosity for 2D Euler (Section 3.2, "Artificial viscosity"):
+ *     entropy residual, element viscosity, vertex-averaged bilinear
+ *     smoothing, and the linear diffusion div(nu grad q) with central fluxes
  *   - the exponential steppers EPI2, EXPRB32 (footnotes in Section 5.1),
  *     EXPRB42 (footnote in Section 5.2) and EPI3 (Tokman's two-step scheme,
  *     cited in Section 1)
@@ -61,6 +64,13 @@ typedef struct {
     const double *source; /* NULL or a nodal source added to R (not to L) */
     int nz;            /* elements along z (Euler 3D; 0 or 1 otherwise) */
     double z0, z1;
+    /* Entropy viscosity (Euler 2D, Section 3.2 "Artificial viscosity"):
+     * ev_ce > 0 enables it; the steppers then compute the nodal viscosity of
+     * each step from q^n and q^{n-1} (orc_entropy_viscosity) and add the
+     * linear diffusion div(nu grad q) to R and L; outside a step, nu (NULL =
+     * none) is the nodal viscosity the operators use. */
+    double ev_ce, ev_cmax;
+    const double *nu;
 } orc_mesh;
 
 /* One accepted Krylov substep: basis size m, substep length dtau, and
@@ -106,6 +116,15 @@ int orc_jvp(const orc_mesh *m, const double *qref, const double *v, double *w);
 /* Auxiliary variable q(u) of the viscous Burgers problem (eq.
  * gov-burgers1d-gradu); Burgers only. */
 int orc_gradient(const orc_mesh *m, const double *u, double *q);
+/* Nodal entropy viscosity of q (with q_prev the previous step's state and dt
+ * the step; Euler 2D): the entropy residual, the element viscosity
+ * min(nu_max, nu_E) and its vertex-averaged bilinear reconstruction.  K*Np
+ * values, one per node of one variable. */
+int orc_entropy_viscosity(const orc_mesh *m, const double *q, const double *q_prev, double dt,
+                          double *nu);
+/* The diffusion operator div(nu grad v) alone (central fluxes), with the
+ * mesh's nodal nu (Euler 2D). */
+int orc_ev_diffusion(const orc_mesh *m, const double *v, double *out);
 /* Complex-step derivative Im R_frozen(qref + i h v) / h with the flux
  * dissipation evaluated at qref (used to pin orc_jvp). */
 int orc_jvp_complex_step(const orc_mesh *m, const double *qref, const double *v,

@@ -23,6 +23,8 @@
 //     i.e. one combination with b_1 = R^n and b_2 = (2/3) r / dt.  The first
 //     step, which has no q^{n-1}, is an EPI2 step.
 //   RK4: the classical four-stage Runge-Kutta method (test reference only).
+// With entropy viscosity (Euler 2D) each step first computes its nodal
+// viscosity from q^n and q^{n-1} and keeps it for all its operators.
 #include "oracle.h"
 
 #include <cmath>
@@ -41,6 +43,18 @@ extern "C" int orc_step(const orc_mesh *m, int scheme, double dt, double *q, dou
         scheme != ORC_EXPRB42)
         return -1;
     const size_t n = (size_t)ni;
+    // entropy viscosity: this step's nodal viscosity from q^n and q^{n-1}
+    // (q^n itself on a first step); every operator of the step uses it
+    orc_mesh mev = *m;
+    std::vector<double> nuv;
+    if (m->ev_ce > 0.0) {
+        nuv.resize(n / 4);
+        const int rc0 = orc_entropy_viscosity(m, q, (q_prev && have_prev) ? q_prev : q, dt,
+                                              nuv.data());
+        if (rc0) return rc0;
+        mev.nu = nuv.data();
+        m = &mev;
+    }
     std::vector<double> qn(q, q + n), Rn(n), w(n);
     std::function<void(const double *, double *)> Ln = [&](const double *x, double *y) {
         orc_jvp(m, qn.data(), x, y);

@@ -16,6 +16,7 @@ import pytest
 import oracle
 from tests import test_oracle_dg as dg
 from tests import test_oracle_euler3d as e3
+from tests import test_oracle_ev as ev
 from tests import test_oracle_iop as iop
 from tests import test_oracle_phi as phi
 from tests import test_oracle_refelem as refelem
@@ -55,6 +56,8 @@ MUTATIONS = {
                         lambda: viscous.test_diffusion_energy_identity(0.0, oracle.BC_DIRICHLET, 2)),
     "normal_speed": ("dg.cpp", "return std::fabs(u[dir]) + a;", "return std::fabs(u[0]) + a;",
                      lambda: e3.test_axis_permutation(1)),
+    "ev_face_flux": ("dg.cpp", "(0.5 * (fm + fp) - fm)", "(0.5 * (fm - fp) - fm)",
+                     lambda: ev.test_diffusion_symmetric_negative(3)),
     "iop_window": ("krylov.cpp", "std::max(0, j - iop)", "std::max(0, j - iop - 1)",
                    lambda: iop.test_arnoldi_relation_and_band(2)),
     "lgl_weight": ("refelem.cpp", "w[i] = 2.0 / (p * (p + 1.0) * P * P);",
