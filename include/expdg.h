@@ -97,7 +97,17 @@ enum {
  *          as in the footnote at the start of Section 6 (exterior state 0 in
  *          the convective fluxes, u** = 0, q** = q^-);
  *   has_source  nonzero: the mesh holds a source vector s added to R (not to
- *          L), set by expdg_mesh_set_source (zero until then). */
+ *          L), set by expdg_mesh_set_source (zero until then).
+ *
+ * Entropy viscosity (Euler 2D only; Section 3.2, "Artificial viscosity"):
+ *   ev_ce, ev_cmax  the constants c_E and c_max (both >= 0; the paper takes 1
+ *          and 0.1).  With ev_ce > 0 the mesh holds a nodal viscosity nu
+ *          (bulk precision, zero at creation) and both operators gain the
+ *          linear diffusion div(nu grad v) of each conserved variable, with
+ *          central fluxes: F^EV = nu grad q in R, nu grad v in L.  Every step
+ *          (expdg_step, expdg_integrate) first sets nu from q^n and q^{n-1}
+ *          (q^n again when it has no history) as expdg_entropy_viscosity does;
+ *          expdg_rhs, expdg_jvp and expdg_phi_krylov use nu as it stands. */
 typedef struct {
     int equation;   /* EXPDG_BURGERS1D, EXPDG_EULER2D or EXPDG_EULER3D */
     int nx, ny;
@@ -115,6 +125,7 @@ typedef struct {
     int has_source;
     int nz;
     double z0, z1;
+    double ev_ce, ev_cmax;
 } expdg_mesh_desc;
 
 typedef struct expdg_mesh expdg_mesh; /* opaque, library-owned */
@@ -185,6 +196,25 @@ int expdg_mesh_nodes(const expdg_mesh *m, double *x, double *y, double *z);
  * Asynchronous on hip_stream; s may be reused once the stream has passed the
  * copy.  EXPDG_EINVAL without has_source or with s == NULL. */
 int expdg_mesh_set_source(expdg_mesh *m, const double *s, void *hip_stream);
+/* Entropy viscosity of the state q after q_prev, one step dt apart (Section
+ * 3.2, "Artificial viscosity", with the entropy residual of its footnote):
+ * S = rho/(gamma-1) log(p / rho^gamma), Res = (S(q) - S(q_prev))/dt +
+ * (div(u S)(q) + div(u S)(q_prev))/2 from each element's own derivative;
+ * per element, with h = sqrt(hx^2 + hy^2)/p (twice the circumradius over the
+ * degree), nu_E = c_E h^2 max(max |Res|, max |[[u S . n]]| / h) over its nodes
+ * and faces, nu_max = c_max h max(|u . e_d| + a), nu_e = min(nu_max, nu_E);
+ * each vertex averages its four elements and nu at a node is the bilinear
+ * interpolant of its element's vertex values.  q, q_prev: device arrays of
+ * ndof doubles (conserved variables, rho > 0, p > 0); the result becomes the
+ * mesh's nu and, if nu != NULL, is also written to nu (device, K*Np doubles,
+ * one per node).  Asynchronous on hip_stream.  EXPDG_EINVAL unless the mesh
+ * was created with ev_ce > 0, for dt <= 0 or NULL q / q_prev. */
+int expdg_entropy_viscosity(expdg_mesh *m, const double *q, const double *q_prev, double dt,
+                            double *nu, void *hip_stream);
+/* Sets the mesh's nodal viscosity to nu (device, K*Np doubles; stored in the
+ * bulk precision), for operators outside a step.  Asynchronous on
+ * hip_stream.  EXPDG_EINVAL unless the mesh was created with ev_ce > 0. */
+int expdg_mesh_set_viscosity(expdg_mesh *m, const double *nu, void *hip_stream);
 /* The library's LGL reference element: nodes, weights, and the
  * differentiation matrix D[i*(p+1)+j] = l_j'(xi_i); host arrays. */
 int expdg_lgl(int p, double *xi, double *w, double *D);

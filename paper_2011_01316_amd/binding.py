@@ -36,7 +36,7 @@ class MeshDesc(C.Structure):
                 ("gamma", C.c_double), ("m_max", C.c_int), ("kappa", C.c_double),
                 ("flux", C.c_int), ("sigma", C.c_double), ("beta", C.c_double),
                 ("bc", C.c_int), ("has_source", C.c_int), ("nz", C.c_int), ("z0", C.c_double),
-                ("z1", C.c_double)]
+                ("z1", C.c_double), ("ev_ce", C.c_double), ("ev_cmax", C.c_double)]
 
 
 class MeshInfo(C.Structure):
@@ -108,6 +108,9 @@ _SIGS = {
     "expdg_mesh_get_info": (C.c_int, [C.c_void_p, C.POINTER(MeshInfo)]),
     "expdg_mesh_nodes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "expdg_mesh_set_source": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "expdg_mesh_set_viscosity": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "expdg_entropy_viscosity": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                                          C.c_void_p, C.c_void_p]),
     "expdg_lgl": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "expdg_rhs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "expdg_jvp": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -205,6 +208,23 @@ def expdg_mesh_set_source(handle, s, stream=None):
     _check(lib().expdg_mesh_set_source(handle, _ptr(s), _stream(stream)))
 
 
+def _f64_dev(x, what):
+    import torch
+    if not (isinstance(x, torch.Tensor) and x.dtype == torch.float64 and x.is_contiguous()):
+        raise ExpdgError(EINVAL, what + " must be a contiguous float64 device tensor")
+    return _ptr(x)
+
+
+def expdg_mesh_set_viscosity(handle, nu, stream=None):
+    _check(lib().expdg_mesh_set_viscosity(handle, _f64_dev(nu, "nu"), _stream(stream)))
+
+
+def expdg_entropy_viscosity(handle, q, q_prev, dt, nu=None, stream=None):
+    _check(lib().expdg_entropy_viscosity(handle, _f64_dev(q, "q"), _f64_dev(q_prev, "q_prev"),
+                                         float(dt), None if nu is None else _f64_dev(nu, "nu"),
+                                         _stream(stream)))
+
+
 def expdg_rhs(handle, q, r, stream=None):
     _check(lib().expdg_rhs(handle, _ptr(q), _ptr(r), _stream(stream)))
 
@@ -295,10 +315,11 @@ class Mesh:
 
     def __init__(self, equation, nx, p, ny=1, precision=FP64, device=0, x0=0.0, x1=1.0,
                  y0=0.0, y1=1.0, gamma=1.4, m_max=64, kappa=0.0, flux=FLUX_LF, sigma=0.0,
-                 beta=0.0, bc=BC_PERIODIC, has_source=False, nz=1, z0=0.0, z1=1.0):
+                 beta=0.0, bc=BC_PERIODIC, has_source=False, nz=1, z0=0.0, z1=1.0, ev_ce=0.0,
+                 ev_cmax=0.0):
         self.desc = MeshDesc(equation, nx, ny, p, precision, device, x0, x1, y0, y1, gamma,
                              m_max, kappa, flux, sigma, beta, bc, int(bool(has_source)), nz, z0,
-                             z1)
+                             z1, ev_ce, ev_cmax)
         self.handle = expdg_mesh_create(self.desc)
         info = MeshInfo()
         _check(lib().expdg_mesh_get_info(self.handle, C.byref(info)))
@@ -342,6 +363,15 @@ class Mesh:
     def set_source(self, s, stream=None):
         """s: float64 device tensor of ndof entries (copied into the mesh)."""
         expdg_mesh_set_source(self.handle, s, stream)
+
+    def set_viscosity(self, nu, stream=None):
+        """nu: float64 device tensor of K*Np nodal viscosities (copied into the mesh)."""
+        expdg_mesh_set_viscosity(self.handle, nu, stream)
+
+    def entropy_viscosity(self, q, q_prev, dt, nu=None, stream=None):
+        """Sets the mesh's viscosity from q after q_prev (float64 device tensors);
+        also writes it to nu (float64, K*Np) when given."""
+        expdg_entropy_viscosity(self.handle, q, q_prev, dt, nu, stream)
 
     def rhs(self, q, r, stream=None):
         expdg_rhs(self.handle, q, r, stream)

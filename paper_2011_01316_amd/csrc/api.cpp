@@ -176,6 +176,11 @@ bool desc_ok(const expdg_mesh_desc *d, const char **why) {
         (d->kappa != 0.0 || d->flux != EXPDG_FLUX_LF || d->sigma != 0.0 || d->beta != 0.0 ||
          d->bc != EXPDG_BC_PERIODIC || d->has_source))
         return *why = "Euler takes no Burgers options (kappa, flux, sigma, beta, bc, source)", false;
+    if (!(d->ev_ce >= 0.0) || !std::isfinite(d->ev_ce) || !(d->ev_cmax >= 0.0) ||
+        !std::isfinite(d->ev_cmax))
+        return *why = "need ev_ce >= 0 and ev_cmax >= 0", false;
+    if (d->ev_ce > 0.0 && d->equation != EXPDG_EULER2D)
+        return *why = "entropy viscosity needs EXPDG_EULER2D", false;
     return true;
 }
 
@@ -203,6 +208,12 @@ size_t layout(expdg_mesh *m, const expdg_mesh_desc *d, size_t stride, int eb, ch
     const int K = d->nx * d->ny * (d->equation == EXPDG_EULER3D ? d->nz : 1);
     const size_t nlin = lin_elems(d->equation, d->p, K);
     if (nlin) take(m->lin, nlin * eb);
+    if (d->ev_ce > 0.0) {
+        const size_t pts = (size_t)K * (d->p + 1) * (d->p + 1);
+        take(m->nu, pts * eb);
+        take(m->evg, 8 * pts * eb);
+        take(m->nue, (size_t)K * 8);
+    }
     take(m->kd.H, (size_t)(kMaxM + 1) * kLDH * 8);
     take(m->kd.S, (size_t)(kMaxM + 1) * 8);
     take(m->kd.coefA, (size_t)(kMaxM + 1) * 8);
@@ -449,6 +460,37 @@ extern "C" int expdg_mesh_set_source(expdg_mesh *m, const double *src, void *str
     return EXPDG_OK;
 }
 
+extern "C" int expdg_mesh_set_viscosity(expdg_mesh *m, const double *nu, void *stream) {
+    if (!m || !nu) return fail(EXPDG_EINVAL, "NULL argument");
+    if (!m->nu) return fail(EXPDG_EINVAL, "the mesh was created without entropy viscosity");
+    DeviceGuard g(m->d.device);
+    hipStream_t s = (hipStream_t)stream;
+    const size_t pts = (size_t)m->K * m->Np;
+    if (m->d.precision == EXPDG_FP64)
+        HIPTRY(launch_copy(nu, (double *)m->nu, pts, s));
+    else
+        HIPTRY(launch_convert(nu, (float *)m->nu, pts, s));
+    return EXPDG_OK;
+}
+
+extern "C" int expdg_entropy_viscosity(expdg_mesh *m, const double *q, const double *q_prev,
+                                       double dt, double *nu, void *stream) {
+    if (!m || !q || !q_prev) return fail(EXPDG_EINVAL, "NULL argument");
+    if (!m->nu) return fail(EXPDG_EINVAL, "the mesh was created without entropy viscosity");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(EXPDG_EINVAL, "dt must be > 0");
+    DeviceGuard g(m->d.device);
+    hipStream_t s = (hipStream_t)stream;
+    const size_t pts = (size_t)m->K * m->Np;
+    if (m->d.precision == EXPDG_FP64) {
+        HIPTRY(entropy_viscosity<double>(m, q, q_prev, dt, s));
+        if (nu) HIPTRY(launch_copy((const double *)m->nu, nu, pts, s));
+    } else {
+        HIPTRY(entropy_viscosity<float>(m, q, q_prev, dt, s));
+        if (nu) HIPTRY(launch_convert((const float *)m->nu, nu, pts, s));
+    }
+    return EXPDG_OK;
+}
+
 extern "C" int expdg_lgl(int p, double *xi, double *w, double *D) {
     if (!xi || !w || !D) return fail(EXPDG_EINVAL, "NULL argument");
     if (p < 1 || p > kMaxP) return fail(EXPDG_EINVAL, "p must be in 1..6");
@@ -594,6 +636,7 @@ struct DirectExec {
         const int nv = a.nv;  // vectors the dot pass and the update read
         const double eb = (double)sizeof(T);
         const bool fused = a.dots != 0;
+        if (a.nu) HIPTRY(launch_ev_grad<T>(a, m->d.p, a.v, (T *)m->evg, s));
         TRY(prof_begin(m, EXPDG_K_LINEAR));
         HIPTRY(launch_dg_op(m->d.equation, m->d.p, true, a, s));
         TRY(prof_end(m, EXPDG_K_LINEAR,

@@ -364,6 +364,16 @@ __device__ __forceinline__ void euler_op_body(const OpArgs<T> &a, int tile, bool
 #pragma unroll
         for (int c = 0; c < 4; ++c) q[c] = u[c] = fx[c] = fy[c] = T(0);
     }
+    // entropy viscosity: the flux gets -nu grad(differentiated field)
+    const bool ev = a.nu != nullptr;
+    if (ev && active) {
+        const T nuv = ld32(a.nu, idx);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            fx[c] -= nuv * ld32(a.evg + c * plane, idx);
+            fy[c] -= nuv * ld32(a.evg + (4 + c) * plane, idx);
+        }
+    }
     if (tid < NT) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
@@ -393,6 +403,11 @@ __device__ __forceinline__ void euler_op_body(const OpArgs<T> &a, int tile, bool
             euler_flux_dir<T, 0>(qn, gm1, fn);
             lam = fmax(euler_speed<T, 0>(q, a.gamma), euler_speed<T, 0>(qn, a.gamma));
         }
+        if (ev) {
+            const T nun = ld32(a.nu, nidx);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) fn[c] -= nun * ld32(a.evg + c * plane, nidx);
+        }
         // res -= (2/h)(1/w_0) [ s (F_n - F)/2 + lam (u - u_n)/2 ]
         const T cf = a.rhx * a.lift;
         const T ca = cf * T(0.5) * T(s), cb = cf * T(0.5) * lam;
@@ -418,6 +433,11 @@ __device__ __forceinline__ void euler_op_body(const OpArgs<T> &a, int tile, bool
             for (int c = 0; c < 4; ++c) qn[c] = un[c] = ld32(src[c], nidx);
             euler_flux_dir<T, 1>(qn, gm1, fn);
             lam = fmax(euler_speed<T, 1>(q, a.gamma), euler_speed<T, 1>(qn, a.gamma));
+        }
+        if (ev) {
+            const T nun = ld32(a.nu, nidx);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) fn[c] -= nun * ld32(a.evg + (4 + c) * plane, nidx);
         }
         const T cf = a.rhy * a.lift;
         const T ca = cf * T(0.5) * T(s), cb = cf * T(0.5) * lam;
@@ -460,6 +480,194 @@ __device__ __forceinline__ void euler_op_body(const OpArgs<T> &a, int tile, bool
         for (int c = 0; c < 4; ++c) wv[c] = T(0);
     }
     if (JVP && a.dots) op_dots2<T, 4>(a, active, idx, plane, u, wv, tile, first);
+}
+
+// ---- entropy viscosity (2D Euler) ---------------------------------------------
+// Section 3.2, "Artificial viscosity": S = rho/(g-1) log(p / rho^g), entropy
+// flux u S; Res = (S(q) - S(q_prev))/dt + (div(uS)(q) + div(uS)(q_prev))/2 at
+// the nodes (element-local derivative); per element nu_E = c_E h^2 max(max|Res|,
+// max|[[uS . n]]| / h), nu_max = c_max h max(|u . e_d| + a), nu_e = min of the
+// two (h = sqrt(hx^2 + hy^2)/p); the nodal nu is the bilinear interpolant of
+// the vertex averages of nu_e.
+
+__device__ __forceinline__ void ev_entropy(const double *q, double gamma, double *S, double *fx,
+                                           double *fy) {
+    const double rho = q[0], u = q[1] / rho, v = q[2] / rho;
+    const double pr = (gamma - 1.0) * (q[3] - 0.5 * rho * (u * u + v * v));
+    *S = rho / (gamma - 1.0) * log(pr / pow(rho, gamma));
+    *fx = u * *S;
+    *fy = v * *S;
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void ev_element_kernel(EvParams ep, const double *q,
+                                                         const double *qp, double *nue) {
+    constexpr int N1 = P + 1, NP = N1 * N1, EPB = 256 / NP, NT = EPB * NP;
+    __shared__ double sF[4][NT];   // uS_x(q), uS_y(q), uS_x(q_prev), uS_y(q_prev)
+    __shared__ double sR[3][NT];   // |Res|, face jumps, wave speed
+    const int tid = threadIdx.x;
+    const int le = tid / NP, n = tid - le * NP;
+    const int i = n % N1, j = n / N1;
+    const int e = blockIdx.x * EPB + le;
+    const bool active = (tid < NT) && (e < ep.K);
+    const size_t plane = (size_t)ep.K * NP;
+    const size_t idx = (size_t)e * NP + n;
+    double qq[4], qo[4], S = 0.0, So = 0.0, fx = 0.0, fy = 0.0, fxo = 0.0, fyo = 0.0;
+    if (active) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            qq[c] = q[c * plane + idx];
+            qo[c] = qp[c * plane + idx];
+        }
+        ev_entropy(qq, ep.gamma, &S, &fx, &fy);
+        ev_entropy(qo, ep.gamma, &So, &fxo, &fyo);
+    }
+    if (tid < NT) {
+        sF[0][tid] = fx;
+        sF[1][tid] = fy;
+        sF[2][tid] = fxo;
+        sF[3][tid] = fyo;
+    }
+    __syncthreads();
+    double ares = 0.0, jmax = 0.0, lam = 0.0;
+    if (active) {
+        const int base = le * NP;
+        double div[2] = {0.0, 0.0};
+#pragma unroll
+        for (int st = 0; st < 2; ++st) {
+#pragma unroll
+            for (int l = 0; l < N1; ++l)
+                div[st] += ep.rhx * ep.D[i * N1 + l] * sF[2 * st][base + j * N1 + l];
+#pragma unroll
+            for (int l = 0; l < N1; ++l)
+                div[st] += ep.rhy * ep.D[j * N1 + l] * sF[2 * st + 1][base + l * N1 + i];
+        }
+        ares = fabs((S - So) / ep.dt + 0.5 * (div[0] + div[1]));
+        const double u = qq[1] / qq[0], v = qq[2] / qq[0];
+        const double pr = (ep.gamma - 1.0) * (qq[3] - 0.5 * qq[0] * (u * u + v * v));
+        const double a = sqrt(ep.gamma * pr / qq[0]);
+        lam = fmax(fabs(u) + a, fabs(v) + a);
+        const int ex = e % ep.nx, ey = e / ep.nx;
+        if (i == 0 || i == P) {
+            const int s = (i == P) ? 1 : -1;
+            const int exn = (ex + s + ep.nx) % ep.nx;
+            const size_t nidx = (size_t)(ey * ep.nx + exn) * NP + j * N1 + (P - i);
+            double qn[4], Sn, fxn, fyn;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) qn[c] = q[c * plane + nidx];
+            ev_entropy(qn, ep.gamma, &Sn, &fxn, &fyn);
+            jmax = fmax(jmax, fabs(fx - fxn));
+        }
+        if (j == 0 || j == P) {
+            const int s = (j == P) ? 1 : -1;
+            const int eyn = (ey + s + ep.ny) % ep.ny;
+            const size_t nidx = (size_t)(eyn * ep.nx + ex) * NP + (P - j) * N1 + i;
+            double qn[4], Sn, fxn, fyn;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) qn[c] = q[c * plane + nidx];
+            ev_entropy(qn, ep.gamma, &Sn, &fxn, &fyn);
+            jmax = fmax(jmax, fabs(fy - fyn));
+        }
+    }
+    if (tid < NT) {
+        sR[0][tid] = ares;
+        sR[1][tid] = jmax;
+        sR[2][tid] = lam;
+    }
+    __syncthreads();
+    if (active && n == 0) {
+        const int base = le * NP;
+        double rm = 0.0, jm = 0.0, lm = 0.0;
+        for (int k = 0; k < NP; ++k) {
+            rm = fmax(rm, sR[0][base + k]);
+            jm = fmax(jm, sR[1][base + k]);
+            lm = fmax(lm, sR[2][base + k]);
+        }
+        const double nu_e = ep.ce * ep.he * ep.he * fmax(rm, jm / ep.he);
+        const double nu_max = ep.cmax * ep.he * lm;
+        nue[e] = fmin(nu_max, nu_e);
+    }
+}
+
+template <int P, typename T>
+__global__ __launch_bounds__(256) void ev_smooth_kernel(EvParams ep, const double *nue, T *nu) {
+    constexpr int N1 = P + 1, NP = N1 * N1;
+    const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (size_t)ep.K * NP) return;
+    const int e = (int)(t / NP), n = (int)(t - (size_t)e * NP);
+    const int i = n % N1, j = n / N1;
+    const int nx = ep.nx, ny = ep.ny;
+    const int ex = e % nx, ey = e / nx;
+    // vertex (vx, vy) is the lower-left corner of element (vx, vy)
+    auto vert = [&](int vx, int vy) {
+        const int xm = (vx + nx - 1) % nx, ym = (vy + ny - 1) % ny;
+        return 0.25 * ((nue[vy * nx + vx] + nue[vy * nx + xm]) +
+                       (nue[ym * nx + vx] + nue[ym * nx + xm]));
+    };
+    const int xp = (ex + 1) % nx, yp = (ey + 1) % ny;
+    const double v00 = vert(ex, ey), v10 = vert(xp, ey), v01 = vert(ex, yp), v11 = vert(xp, yp);
+    const double r = 0.5 * (ep.xi[i] + 1.0), s = 0.5 * (ep.xi[j] + 1.0);
+    nu[t] = (T)((1.0 - r) * (1.0 - s) * v00 + r * (1.0 - s) * v10 + (1.0 - r) * s * v01 +
+                r * s * v11);
+}
+
+// Gradient of each of the four planes of v with central lifts:
+// g_d = (2/h_d) D_d v + (2/h_d)(1/w_0) n_d ({{v}} - v^-) on the faces along d.
+template <int P, typename T>
+__global__ __launch_bounds__(256) void ev_grad_kernel(OpArgs<T> a, const T *v, T *evg) {
+    constexpr int N1 = P + 1, NP = N1 * N1, EPB = 256 / NP, NT = EPB * NP;
+    __shared__ T sV[4][NT];
+    const int tid = threadIdx.x;
+    const int le = tid / NP, n = tid - le * NP;
+    const int i = n % N1, j = n / N1;
+    const int e = xcd_tile(blockIdx.x, gridDim.x) * EPB + le;
+    const bool active = (tid < NT) && (e < a.K);
+    const size_t plane = (size_t)a.K * NP;
+    const unsigned idx = (unsigned)e * NP + n;
+    T vv[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) vv[c] = active ? ld32(v + c * plane, idx) : T(0);
+    if (tid < NT) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sV[c][tid] = vv[c];
+    }
+    __syncthreads();
+    if (!active) return;
+    const int base = le * NP;
+    T gx[4] = {T(0), T(0), T(0), T(0)}, gy[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int l = 0; l < N1; ++l) {
+        const T dx = a.rhx * a.D[i * N1 + l], dy = a.rhy * a.D[j * N1 + l];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            gx[c] += dx * sV[c][base + j * N1 + l];
+            gy[c] += dy * sV[c][base + l * N1 + i];
+        }
+    }
+    const int ex = e % a.nx, ey = e / a.nx;
+    if (i == 0 || i == P) {
+        const int s = (i == P) ? 1 : -1;
+        const int exn = (ex + s + a.nx) % a.nx;
+        const unsigned nidx = (unsigned)(ey * a.nx + exn) * NP + j * N1 + (P - i);
+        const T cf = a.rhx * a.lift * T(s);
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            gx[c] += cf * (T(0.5) * (vv[c] + ld32(v + c * plane, nidx)) - vv[c]);
+    }
+    if (j == 0 || j == P) {
+        const int s = (j == P) ? 1 : -1;
+        const int eyn = (ey + s + a.ny) % a.ny;
+        const unsigned nidx = (unsigned)(eyn * a.nx + ex) * NP + (P - j) * N1 + i;
+        const T cf = a.rhy * a.lift * T(s);
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            gy[c] += cf * (T(0.5) * (vv[c] + ld32(v + c * plane, nidx)) - vv[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        st32(evg + c * plane, idx, gx[c]);
+        st32(evg + (4 + c) * plane, idx, gy[c]);
+    }
 }
 
 // ---- Euler 3D operator ------------------------------------------------------
@@ -1103,6 +1311,57 @@ int grid_for(size_t n) {
 }
 
 }  // namespace
+
+template <typename T>
+hipError_t launch_entropy_viscosity(const EvParams &ep, const double *q, const double *q_prev,
+                                    double *nue, T *nu, hipStream_t s) {
+    const int p = ep.p, np = (p + 1) * (p + 1), epb = 256 / np;
+    const dim3 g1((unsigned)((ep.K + epb - 1) / epb));
+    const size_t npts = (size_t)ep.K * np;
+    const dim3 g2((unsigned)((npts + 255) / 256));
+    hipError_t err = hipSuccess;
+    switch (p) {
+#define EXPDG_EV(PP)                                                                          \
+    case PP:                                                                                  \
+        err = launch_kernel(ev_element_kernel<PP>, g1, dim3(256), 0, s, ep, q, q_prev, nue);  \
+        if (err != hipSuccess) return err;                                                    \
+        return launch_kernel(ev_smooth_kernel<PP, T>, g2, dim3(256), 0, s, ep, (const double *)nue, \
+                             nu);
+        EXPDG_EV(1)
+        EXPDG_EV(2)
+        EXPDG_EV(3)
+        EXPDG_EV(4)
+        EXPDG_EV(5)
+        EXPDG_EV(6)
+#undef EXPDG_EV
+        default: return hipErrorInvalidValue;
+    }
+}
+template hipError_t launch_entropy_viscosity<double>(const EvParams &, const double *,
+                                                     const double *, double *, double *,
+                                                     hipStream_t);
+template hipError_t launch_entropy_viscosity<float>(const EvParams &, const double *,
+                                                    const double *, double *, float *,
+                                                    hipStream_t);
+
+template <typename T>
+hipError_t launch_ev_grad(const OpArgs<T> &a, int p, const T *v, T *evg, hipStream_t s) {
+    const int np = (p + 1) * (p + 1), epb = 256 / np;
+    const dim3 grid((unsigned)((a.K + epb - 1) / epb));
+    switch (p) {
+        case 1: return launch_kernel(ev_grad_kernel<1, T>, grid, dim3(256), 0, s, a, v, evg);
+        case 2: return launch_kernel(ev_grad_kernel<2, T>, grid, dim3(256), 0, s, a, v, evg);
+        case 3: return launch_kernel(ev_grad_kernel<3, T>, grid, dim3(256), 0, s, a, v, evg);
+        case 4: return launch_kernel(ev_grad_kernel<4, T>, grid, dim3(256), 0, s, a, v, evg);
+        case 5: return launch_kernel(ev_grad_kernel<5, T>, grid, dim3(256), 0, s, a, v, evg);
+        case 6: return launch_kernel(ev_grad_kernel<6, T>, grid, dim3(256), 0, s, a, v, evg);
+        default: return hipErrorInvalidValue;
+    }
+}
+template hipError_t launch_ev_grad<double>(const OpArgs<double> &, int, const double *, double *,
+                                           hipStream_t);
+template hipError_t launch_ev_grad<float>(const OpArgs<float> &, int, const float *, float *,
+                                          hipStream_t);
 
 template <typename T>
 hipError_t launch_lin_prepare(int equation, int p, const T *q, T *lin, int K, int nx, int ny,

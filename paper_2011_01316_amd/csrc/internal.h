@@ -56,6 +56,10 @@ struct OpArgs {
     int ef;            // nonzero: entropy flux for (u^2/2)*
     int dirichlet;     // nonzero: u = 0 beyond both ends
     const T *src;
+    // Entropy viscosity (2D Euler): nodal viscosity nu and the gradient of the
+    // differentiated field (x planes then y planes), or nullptr
+    const T *nu;
+    const T *evg;
     T D[(kMaxP + 1) * (kMaxP + 1)];  // D[i*(p+1)+l] = l_l'(xi_i)
 };
 
@@ -102,6 +106,21 @@ int dg_block_threads(int equation, int p);
 hipError_t launch_dg_op_group(int equation, int p, bool jvp, bool visc,
                               const OpArgs<double> *items, const int *bstart, int n, int total,
                               hipStream_t s);
+// Entropy viscosity (2D Euler): the element viscosity of q after q_prev (FP64
+// states, step dt) into nue[K], then its vertex-averaged bilinear
+// reconstruction at the nodes into nu (bulk type).
+struct EvParams {
+    int K, nx, ny, p;
+    double rhx, rhy, lift, gamma, dt, ce, cmax, he;
+    double xi[kMaxP + 1];                // LGL nodes (bilinear reconstruction)
+    double D[(kMaxP + 1) * (kMaxP + 1)];  // D[i*(p+1)+l] = l_l'(xi_i)
+};
+template <typename T>
+hipError_t launch_entropy_viscosity(const EvParams &ep, const double *q, const double *q_prev,
+                                    double *nue, T *nu, hipStream_t s);
+// Gradient of the four planes of v (central lift) into evg: x planes, then y.
+template <typename T>
+hipError_t launch_ev_grad(const OpArgs<T> &a, int p, const T *v, T *evg, hipStream_t s);
 // Per-block maxima of the wave speed (FP64 state) into part[0..nblk).
 hipError_t launch_max_speed(int equation, const double *q, size_t npts, double gamma,
                             double *part, int nblk, hipStream_t s);

@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstddef>
 #include <vector>
 
@@ -31,6 +32,9 @@ struct expdg_mesh {
     double *q2 = nullptr;        // FP64 stage state (EXPRB32)
     void *src = nullptr;         // source term of the residual (bulk type; has_source only)
     void *lin = nullptr;         // frozen fields of the 2D linear operator (bulk type)
+    void *nu = nullptr;          // entropy viscosity at the nodes (bulk type; ev_ce > 0 only)
+    void *evg = nullptr;         // gradient of an operator's input (8 planes, bulk type)
+    double *nue = nullptr;       // element viscosities (K)
     expdg::KrylovDev kd{};
     double *slots = nullptr;     // kCheckSlots x kSlotSize
     double *dnorm = nullptr;     // 8
@@ -144,7 +148,36 @@ OpArgs<T> op_args(const expdg_mesh *m) {
     a.ef = m->d.flux == EXPDG_FLUX_EF;
     a.dirichlet = m->d.bc == EXPDG_BC_DIRICHLET;
     a.src = (const T *)m->src;
+    a.nu = (const T *)m->nu;
+    a.evg = (const T *)m->evg;
     return a;
+}
+
+// Entropy viscosity parameters of the mesh for a step dt.
+inline EvParams ev_params(const expdg_mesh *m, double dt) {
+    EvParams ep{};
+    ep.K = m->K;
+    ep.nx = m->d.nx;
+    ep.ny = m->d.ny;
+    ep.p = m->d.p;
+    ep.rhx = 2.0 / m->hx;
+    ep.rhy = 2.0 / m->hy;
+    ep.lift = 1.0 / m->w[0];
+    ep.gamma = m->d.gamma;
+    ep.dt = dt;
+    ep.ce = m->d.ev_ce;
+    ep.cmax = m->d.ev_cmax;
+    ep.he = std::sqrt(m->hx * m->hx + m->hy * m->hy) / m->d.p;
+    for (int k = 0; k < m->n1; ++k) ep.xi[k] = m->xi[k];
+    for (int k = 0; k < m->n1 * m->n1; ++k) ep.D[k] = m->D[k];
+    return ep;
+}
+
+// The mesh's nodal viscosity from the FP64 states q and q_prev (ev_ce > 0).
+template <typename T>
+hipError_t entropy_viscosity(expdg_mesh *m, const double *q, const double *q_prev, double dt,
+                             hipStream_t s) {
+    return launch_entropy_viscosity<T>(ev_params(m, dt), q, q_prev, m->nue, (T *)m->nu, s);
 }
 
 // Frozen fields of the linear operator at the reference state q (into m->lin).
@@ -174,6 +207,8 @@ int apply_op(expdg_mesh *m, bool jvp, const T *q, const T *v, T *out, hipStream_
     a.v = v;
     a.out = out;
     a.lin = (const T *)m->lin;
+    // the diffusion of the entropy viscosity needs the gradient of the input
+    if (a.nu) HIPTRY(launch_ev_grad<T>(a, m->d.p, jvp ? v : q, (T *)m->evg, s));
     const int cls = jvp ? EXPDG_K_LINEAR : EXPDG_K_RESIDUAL;
     TRY(prof_begin(m, cls));
     HIPTRY(launch_dg_op(m->d.equation, m->d.p, jvp, a, s));

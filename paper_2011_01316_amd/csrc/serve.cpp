@@ -198,6 +198,7 @@ bool request_sizes(const expdg_request *r, size_t *ws, size_t *st, const char **
     if (d.precision != EXPDG_FP64) return *why = "served solves are FP64", false;
     if (d.has_source) return *why = "served solves take no source term", false;
     if (d.equation == EXPDG_EULER3D) return *why = "served solves are 1D or 2D", false;
+    if (d.ev_ce > 0.0) return *why = "served solves take no entropy viscosity", false;
     if (r->scheme != EXPDG_EPI2 && r->scheme != EXPDG_EPI3)
         return *why = "scheme must be EXPDG_EPI2 or EXPDG_EPI3", false;
     if (r->nsteps < 1) return *why = "nsteps must be >= 1", false;

@@ -57,7 +57,8 @@ def test_lgl_rejects_bad_degree():
 def desc(**kw):
     d = dict(equation=B.EULER2D, nx=64, ny=64, p=4, precision=B.FP64, device=0, x0=0.0,
              x1=10.0, y0=0.0, y1=10.0, gamma=1.4, m_max=64, kappa=0.0, flux=B.FLUX_LF,
-             sigma=0.0, beta=0.0, bc=B.BC_PERIODIC, has_source=0, nz=1, z0=0.0, z1=1.0)
+             sigma=0.0, beta=0.0, bc=B.BC_PERIODIC, has_source=0, nz=1, z0=0.0, z1=1.0,
+             ev_ce=0.0, ev_cmax=0.0)
     d.update(kw)
     return B.MeshDesc(*[d[f] for f, _ in B.MeshDesc._fields_])
 
@@ -112,6 +113,28 @@ def test_euler3d_validation():
     assert B.expdg_request_bytes(req) > 0
     req.mesh.equation = B.EULER3D
     req.mesh.nz = 2
+    assert B.expdg_request_bytes(req) == 0
+
+
+def test_entropy_viscosity_validation():
+    # Euler 2D only, constants >= 0; the workspace gains the nodal viscosity,
+    # the eight gradient planes and one element viscosity per element
+    base = B.expdg_workspace_bytes(desc())
+    ev = B.expdg_workspace_bytes(desc(ev_ce=1.0, ev_cmax=0.1))
+    pts, K = 64 * 64 * 25, 64 * 64
+    assert ev - base >= 9 * pts * 8 + K * 8
+    assert ev - base <= 9 * pts * 8 + K * 8 + 3 * 256
+    evf = B.expdg_workspace_bytes(desc(ev_ce=1.0, ev_cmax=0.1, precision=B.FP32_BULK))
+    basef = B.expdg_workspace_bytes(desc(precision=B.FP32_BULK))
+    assert evf - basef >= 9 * pts * 4 + K * 8
+    assert B.expdg_workspace_bytes(desc(ev_ce=0.0, ev_cmax=0.1)) == base
+    for bad in [dict(ev_ce=-1.0), dict(ev_cmax=-0.1), dict(ev_ce=float("nan")),
+                dict(equation=B.BURGERS1D, ny=1, ev_ce=1.0),
+                dict(equation=B.EULER3D, nz=2, ev_ce=1.0)]:
+        assert B.expdg_workspace_bytes(desc(**bad)) == 0, bad
+    # served solves take no entropy viscosity
+    req = B.make_request(B.EULER2D, 8, 3, ny=8, nsteps=2, dt=1e-2, x1=10.0, y1=10.0)
+    req.mesh.ev_ce = 1.0
     assert B.expdg_request_bytes(req) == 0
 
 
