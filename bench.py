@@ -299,6 +299,142 @@ def run_euler3d(args):
     return out
 
 
+# Entropy viscosity (Section 3.2, "Artificial viscosity"): the paper's
+# Kelvin-Helmholtz run of Section 5.3 (N_e = 722 = 38 x 19 elements of degree 6
+# on (-5, 5) x (0, 5), c_E = 1, c_max = 0.1, EPI2 to t = 100 at dt = 0.5 and
+# 0.04), taken periodic in y (the uniform stream is the same at both walls),
+# and the 512 x 512, p = 4 shear layer with and without the viscosity.
+KH = dict(nx=38, ny=19, p=6, ce=1.0, cmax=0.1, t_end=100.0, dts=(0.5, 0.04), tol=1e-10,
+          m_min=10, m_max=64,
+          name="Kelvin-Helmholtz, (-5,5)x(0,5) periodic, 38x19 quads (N_e = 722), LGL p=6 "
+               "(141,512 DOF), entropy viscosity c_E = 1, c_max = 0.1, EPI2 to t = 100, FP64")
+KH_PAPER_SECONDS = {"rk4_dt0.005": 8729.0, "epi2_dt0.04": 3505.0, "epi2_dt0.5": 2656.0}
+SL = dict(nx=512, ny=512, p=4, cr=5.0, steps=20, tol=1e-7, m_min=10, m_max=64, ce=1.0, cmax=0.1,
+          name="shear layer, periodic [0,1]^2, 512x512 quads, LGL p=4 (26,214,400 DOF), density "
+               "2:1, seeded 1e-2 perturbation, EPI3 FP32-bulk at Courant 5, tol 1e-7")
+
+
+def run_ev(args):
+    import numpy as np
+    import torch
+
+    from paper_2011_01316_amd import binding as B
+    from paper_2011_01316_amd import inputs
+
+    out = {}
+    w = KH
+    m = B.Mesh(B.EULER2D, w["nx"], w["p"], ny=w["ny"], x0=-5.0, x1=5.0, y0=0.0, y1=5.0,
+               m_max=w["m_max"], ev_ce=w["ce"], ev_cmax=w["cmax"])
+    x, y = m.nodes()
+    q0 = torch.tensor(inputs.kelvin_helmholtz(x, y).reshape(-1), dtype=torch.float64,
+                      device="cuda:0")
+    _, wq, _ = B.expdg_lgl(w["p"])
+    wn = np.outer(wq, wq).reshape(-1) * (m.hx * m.hy / 4.0)
+    mass = np.tile(wn, m.K)
+    npts = m.K * m.Np
+    m0 = [float(mass @ q0.cpu().numpy()[c * npts:(c + 1) * npts]) for c in range(4)]
+    runs = {}
+    for dt in w["dts"]:
+        nsteps = int(round(w["t_end"] / dt))
+        q = q0.clone()
+        qp = torch.empty_like(q)
+        st = B.make_stats()
+        opts = B.make_opts(w["tol"], w["m_min"], w["m_max"])
+        # chunks of `chunk` steps, so that a run that loses positivity is
+        # reported with the time it reached (one library call per chunk)
+        chunk = nsteps if dt < 0.1 else 2
+        done, failed = 0, None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while done < nsteps and failed is None:
+            k = min(chunk, nsteps - done)
+            try:
+                m.integrate(B.EPI2, dt, k, q, qp, done > 0, opts, st)
+                done += k
+            except B.ExpdgError as e:
+                failed = str(e)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        d = B.stats_dict(st)
+        key = f"epi2_dt{dt:g}"
+        r = dict(dt=dt, steps=nsteps, steps_done=done, t_reached=round(done * dt, 3),
+                 seconds=round(secs, 3), ms_per_step=round(secs / max(1, done) * 1e3, 4),
+                 krylov_iters=d["krylov_iters"], substeps=d["substeps"], rejects=d["rejects"],
+                 courant=round(dt * m.max_speed(q0) / m.dx_min, 2))
+        if failed is None:
+            qh = q.cpu().numpy()
+            rho = qh[:npts]
+            vel2 = (qh[npts:2 * npts] ** 2 + qh[2 * npts:3 * npts] ** 2) / rho
+            pr = 0.4 * (qh[3 * npts:] - 0.5 * vel2)
+            nu = torch.empty(npts, dtype=torch.float64, device="cuda:0")
+            m.entropy_viscosity(q, qp, dt, nu)
+            r.update(seconds_to_t100=round(secs, 3),
+                     vs_paper=round(KH_PAPER_SECONDS[key] / secs, 1),
+                     min_density=float(rho.min()), min_pressure=float(pr.min()),
+                     max_nu_final=float(nu.max().item()),
+                     mass_drift=max(abs(float(mass @ qh[c * npts:(c + 1) * npts]) - m0[c]) /
+                                    max(1.0, abs(m0[c])) for c in range(4)))
+            log(f"KH EPI2 dt={dt}: {secs:.3f} s to t = 100 ({nsteps} steps, "
+                f"{d['krylov_iters']} Krylov iterations)")
+        else:
+            r["diverged"] = failed
+            log(f"KH EPI2 dt={dt}: diverged after t = {done * dt:g} ({failed})")
+        runs[key] = r
+    out["kelvin_helmholtz"] = dict(workload=w["name"], ndof=m.n, runs=runs,
+                                   paper_seconds=KH_PAPER_SECONDS)
+    m.close()
+
+    # the 512 x 512 shear layer: EPI3 steps with and without the viscosity,
+    # then one instrumented pass of the same steps
+    w = SL
+    res = {}
+    for ev in (False, True):
+        kw = dict(ev_ce=w["ce"], ev_cmax=w["cmax"]) if ev else {}
+        m = B.Mesh(B.EULER2D, w["nx"], w["p"], ny=w["ny"], m_max=w["m_max"],
+                   precision=B.FP32_BULK, **kw)
+        x, y = m.nodes()
+        q = torch.tensor(inputs.shear_layer(x, y, seed=0).reshape(-1), dtype=torch.float64,
+                         device="cuda:0")
+        del x, y
+        qp = torch.empty_like(q)
+        dt = w["cr"] * m.dx_min / m.max_speed(q)
+        opts = B.make_opts(w["tol"], w["m_min"], w["m_max"])
+        m.integrate(B.EPI3, dt, 2, q, qp, False, opts, B.make_stats())
+        st = B.make_stats()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m.integrate(B.EPI3, dt, w["steps"], q, qp, True, opts, st)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        d = B.stats_dict(st)
+        r = dict(ms_per_step=round(secs / w["steps"] * 1e3, 3),
+                 value=round(m.n * (d["rhs_calls"] + d["jvps"]) / secs, 1), unit=UNIT,
+                 krylov_iters_per_step=d["krylov_iters"] / w["steps"],
+                 finite=bool(torch.isfinite(q).all().item()))
+        if ev:
+            for c in B.KERNEL_CLASSES:
+                B.expdg_profile_enable(m.handle, c, True)
+            m.integrate(B.EPI3, dt, 2, q, qp, True, opts, B.make_stats())
+            pr = {B.KERNEL_CLASSES[c]: B.expdg_profile_read(m.handle, c) for c in B.KERNEL_CLASSES}
+            for c in B.KERNEL_CLASSES:
+                B.expdg_profile_enable(m.handle, c, False)
+            r["linear_operator_roofline"] = roof(pr["linear_operator"], "linear_operator",
+                                                 "euler_op<4, float, true>")
+            r["ev_grad_roofline"] = roof(pr["ev_grad"], "ev_grad", "ev_grad_kernel<4, float>")
+            r["ev_visc_roofline"] = roof(pr["ev_visc"], "ev_visc",
+                                         "ev_element_kernel<4> / ev_smooth_kernel<4, float>")
+            tot = sum(v["total_ms"] for v in pr.values())
+            r["kernel_time_share"] = {k: round(v["total_ms"] / tot, 4) for k, v in pr.items()}
+        res["with_ev" if ev else "without_ev"] = r
+        log(f"shear layer 512^2 p=4 ev={ev}: {r['ms_per_step']:.3f} ms/step")
+        m.close()
+        del q, qp
+    res["ev_step_cost_ratio"] = round(res["with_ev"]["ms_per_step"] /
+                                      res["without_ev"]["ms_per_step"], 3)
+    out["shear_layer_512_p4"] = dict(workload=w["name"], steps=w["steps"], **res)
+    return out
+
+
 def roof(p, name, symbol, traffic=None):
     if not p or not p["launches"] or p["total_ms"] <= 0:
         return None
@@ -557,6 +693,9 @@ def main():
     ap.add_argument("--serve-max-active", type=int, default=256)
     ap.add_argument("--serve-seq", type=int, default=40,
                     help="first requests also run one after another for comparison")
+    ap.add_argument("--no-ev", action="store_true")
+    ap.add_argument("--ev-only", action="store_true",
+                    help="only run the entropy-viscosity workloads and print their figures")
     ap.add_argument("--serve-only", action="store_true",
                     help="only run the served workload and print its figures")
     ap.add_argument("--copy-probe", action="store_true",
@@ -573,6 +712,9 @@ def main():
         return
     if args.euler3d_only:
         print(json.dumps(run_euler3d(args)), flush=True)
+        return
+    if args.ev_only:
+        print(json.dumps(run_ev(args)), flush=True)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -677,6 +819,8 @@ def main():
         line["viscous_burgers"] = run_viscous(args)
     if not args.no_euler3d:
         line["euler3d_paper_strong_scaling"] = run_euler3d(args)
+    if not args.no_ev:
+        line["entropy_viscosity"] = run_ev(args)
     if not args.no_serve:
         line["served"] = run_served(args)
     line["cpu_baseline"] = None if args.no_cpu_baseline else run_cpu_baseline(args)

@@ -482,10 +482,10 @@ extern "C" int expdg_entropy_viscosity(expdg_mesh *m, const double *q, const dou
     hipStream_t s = (hipStream_t)stream;
     const size_t pts = (size_t)m->K * m->Np;
     if (m->d.precision == EXPDG_FP64) {
-        HIPTRY(entropy_viscosity<double>(m, q, q_prev, dt, s));
+        TRY(entropy_viscosity<double>(m, q, q_prev, dt, s));
         if (nu) HIPTRY(launch_copy((const double *)m->nu, nu, pts, s));
     } else {
-        HIPTRY(entropy_viscosity<float>(m, q, q_prev, dt, s));
+        TRY(entropy_viscosity<float>(m, q, q_prev, dt, s));
         if (nu) HIPTRY(launch_convert((const float *)m->nu, nu, pts, s));
     }
     return EXPDG_OK;
@@ -636,7 +636,7 @@ struct DirectExec {
         const int nv = a.nv;  // vectors the dot pass and the update read
         const double eb = (double)sizeof(T);
         const bool fused = a.dots != 0;
-        if (a.nu) HIPTRY(launch_ev_grad<T>(a, m->d.p, a.v, (T *)m->evg, s));
+        if (a.nu) TRY(ev_gradient<T>(m, a, a.v, s));
         TRY(prof_begin(m, EXPDG_K_LINEAR));
         HIPTRY(launch_dg_op(m->d.equation, m->d.p, true, a, s));
         TRY(prof_end(m, EXPDG_K_LINEAR,

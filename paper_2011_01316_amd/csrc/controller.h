@@ -388,7 +388,7 @@ Task<int> step_co(X &x, expdg_mesh *m, int scheme, double dt, double *q, double 
     int fpos = 0;
     // entropy viscosity of the step from q^n and q^{n-1} (q^n without history)
     if (m->nu)
-        CO_HIPTRY(entropy_viscosity<T>(m, q, (q_prev && have_prev) ? q_prev : q, dt, s));
+        CO_TRY(entropy_viscosity<T>(m, q, (q_prev && have_prev) ? q_prev : q, dt, s));
     T *qb = nullptr;
     CO_HIPTRY(view(q, 0, &qb));
     // every linear operator of the step is frozen at q^n

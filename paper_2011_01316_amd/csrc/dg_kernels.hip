@@ -1312,37 +1312,39 @@ int grid_for(size_t n) {
 
 }  // namespace
 
-template <typename T>
-hipError_t launch_entropy_viscosity(const EvParams &ep, const double *q, const double *q_prev,
-                                    double *nue, T *nu, hipStream_t s) {
-    const int p = ep.p, np = (p + 1) * (p + 1), epb = 256 / np;
-    const dim3 g1((unsigned)((ep.K + epb - 1) / epb));
-    const size_t npts = (size_t)ep.K * np;
-    const dim3 g2((unsigned)((npts + 255) / 256));
-    hipError_t err = hipSuccess;
-    switch (p) {
-#define EXPDG_EV(PP)                                                                          \
-    case PP:                                                                                  \
-        err = launch_kernel(ev_element_kernel<PP>, g1, dim3(256), 0, s, ep, q, q_prev, nue);  \
-        if (err != hipSuccess) return err;                                                    \
-        return launch_kernel(ev_smooth_kernel<PP, T>, g2, dim3(256), 0, s, ep, (const double *)nue, \
-                             nu);
-        EXPDG_EV(1)
-        EXPDG_EV(2)
-        EXPDG_EV(3)
-        EXPDG_EV(4)
-        EXPDG_EV(5)
-        EXPDG_EV(6)
-#undef EXPDG_EV
+hipError_t launch_ev_element(const EvParams &ep, const double *q, const double *q_prev,
+                             double *nue, hipStream_t s) {
+    const int np = (ep.p + 1) * (ep.p + 1), epb = 256 / np;
+    const dim3 grid((unsigned)((ep.K + epb - 1) / epb));
+    switch (ep.p) {
+        case 1: return launch_kernel(ev_element_kernel<1>, grid, dim3(256), 0, s, ep, q, q_prev, nue);
+        case 2: return launch_kernel(ev_element_kernel<2>, grid, dim3(256), 0, s, ep, q, q_prev, nue);
+        case 3: return launch_kernel(ev_element_kernel<3>, grid, dim3(256), 0, s, ep, q, q_prev, nue);
+        case 4: return launch_kernel(ev_element_kernel<4>, grid, dim3(256), 0, s, ep, q, q_prev, nue);
+        case 5: return launch_kernel(ev_element_kernel<5>, grid, dim3(256), 0, s, ep, q, q_prev, nue);
+        case 6: return launch_kernel(ev_element_kernel<6>, grid, dim3(256), 0, s, ep, q, q_prev, nue);
         default: return hipErrorInvalidValue;
     }
 }
-template hipError_t launch_entropy_viscosity<double>(const EvParams &, const double *,
-                                                     const double *, double *, double *,
-                                                     hipStream_t);
-template hipError_t launch_entropy_viscosity<float>(const EvParams &, const double *,
-                                                    const double *, double *, float *,
-                                                    hipStream_t);
+
+template <typename T>
+hipError_t launch_ev_smooth(const EvParams &ep, const double *nue, T *nu, hipStream_t s) {
+    const size_t npts = (size_t)ep.K * (ep.p + 1) * (ep.p + 1);
+    const dim3 grid((unsigned)((npts + 255) / 256));
+    switch (ep.p) {
+        case 1: return launch_kernel(ev_smooth_kernel<1, T>, grid, dim3(256), 0, s, ep, nue, nu);
+        case 2: return launch_kernel(ev_smooth_kernel<2, T>, grid, dim3(256), 0, s, ep, nue, nu);
+        case 3: return launch_kernel(ev_smooth_kernel<3, T>, grid, dim3(256), 0, s, ep, nue, nu);
+        case 4: return launch_kernel(ev_smooth_kernel<4, T>, grid, dim3(256), 0, s, ep, nue, nu);
+        case 5: return launch_kernel(ev_smooth_kernel<5, T>, grid, dim3(256), 0, s, ep, nue, nu);
+        case 6: return launch_kernel(ev_smooth_kernel<6, T>, grid, dim3(256), 0, s, ep, nue, nu);
+        default: return hipErrorInvalidValue;
+    }
+}
+template hipError_t launch_ev_smooth<double>(const EvParams &, const double *, double *,
+                                             hipStream_t);
+template hipError_t launch_ev_smooth<float>(const EvParams &, const double *, float *,
+                                            hipStream_t);
 
 template <typename T>
 hipError_t launch_ev_grad(const OpArgs<T> &a, int p, const T *v, T *evg, hipStream_t s) {

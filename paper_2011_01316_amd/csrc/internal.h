@@ -115,9 +115,10 @@ struct EvParams {
     double xi[kMaxP + 1];                // LGL nodes (bilinear reconstruction)
     double D[(kMaxP + 1) * (kMaxP + 1)];  // D[i*(p+1)+l] = l_l'(xi_i)
 };
+hipError_t launch_ev_element(const EvParams &ep, const double *q, const double *q_prev,
+                             double *nue, hipStream_t s);
 template <typename T>
-hipError_t launch_entropy_viscosity(const EvParams &ep, const double *q, const double *q_prev,
-                                    double *nue, T *nu, hipStream_t s);
+hipError_t launch_ev_smooth(const EvParams &ep, const double *nue, T *nu, hipStream_t s);
 // Gradient of the four planes of v (central lift) into evg: x planes, then y.
 template <typename T>
 hipError_t launch_ev_grad(const OpArgs<T> &a, int p, const T *v, T *evg, hipStream_t s);

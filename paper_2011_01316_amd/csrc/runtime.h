@@ -125,9 +125,7 @@ void mesh_setup(expdg_mesh *m, const expdg_mesh_desc *d);
 // Points every device buffer into block (sizes_of(d).total bytes, 256-aligned).
 void mesh_carve(expdg_mesh *m, void *block);
 
-// Live timing of kernel class c around the next launch.
-int prof_begin(expdg_mesh *m, int c);
-int prof_end(expdg_mesh *m, int c, double bytes);
+// Live timing of kernel class c around the next launch (declared above).
 
 template <typename T>
 OpArgs<T> op_args(const expdg_mesh *m) {
@@ -173,11 +171,24 @@ inline EvParams ev_params(const expdg_mesh *m, double dt) {
     return ep;
 }
 
+int prof_begin(expdg_mesh *m, int c);
+int prof_end(expdg_mesh *m, int c, double bytes);
+
 // The mesh's nodal viscosity from the FP64 states q and q_prev (ev_ce > 0).
+// Algorithmic bytes: both states and the element viscosities (element
+// kernel); the element viscosities and the nodal output (reconstruction).
 template <typename T>
-hipError_t entropy_viscosity(expdg_mesh *m, const double *q, const double *q_prev, double dt,
-                             hipStream_t s) {
-    return launch_entropy_viscosity<T>(ev_params(m, dt), q, q_prev, m->nue, (T *)m->nu, s);
+int entropy_viscosity(expdg_mesh *m, const double *q, const double *q_prev, double dt,
+                      hipStream_t s) {
+    const EvParams ep = ev_params(m, dt);
+    const double pts = (double)m->K * m->Np;
+    TRY(prof_begin(m, EXPDG_K_EV_VISC));
+    HIPTRY(launch_ev_element(ep, q, q_prev, m->nue, s));
+    TRY(prof_end(m, EXPDG_K_EV_VISC, 2.0 * m->n * 8.0 + m->K * 8.0));
+    TRY(prof_begin(m, EXPDG_K_EV_VISC));
+    HIPTRY(launch_ev_smooth<T>(ep, m->nue, (T *)m->nu, s));
+    TRY(prof_end(m, EXPDG_K_EV_VISC, m->K * 8.0 + pts * sizeof(T)));
+    return EXPDG_OK;
 }
 
 // Frozen fields of the linear operator at the reference state q (into m->lin).
@@ -193,9 +204,21 @@ hipError_t prepare_lin(expdg_mesh *m, const T *q, hipStream_t s) {
 // (linear operator).  Augmented blocks and fused dots are added by the caller.
 inline double op_bytes(const expdg_mesh *m, bool jvp) {
     const double n = (double)m->n, eb = (double)m->ebytes;
-    if (!jvp) return 2.0 * n * eb;
+    // entropy viscosity: the nodal viscosity and the eight gradient planes
+    const double ev = m->nu ? 9.0 * m->K * m->Np * eb : 0.0;
+    if (!jvp) return 2.0 * n * eb + ev;
     const double lin = (double)lin_elems(m->d.equation, m->d.p, m->K);
-    return (lin > 0.0 ? 2.0 * n + lin : 3.0 * n) * eb;
+    return (lin > 0.0 ? 2.0 * n + lin : 3.0 * n) * eb + ev;
+}
+
+// Gradient of an operator's input for the entropy viscosity: four planes
+// read, eight written.
+template <typename T>
+int ev_gradient(expdg_mesh *m, const OpArgs<T> &a, const T *v, hipStream_t s) {
+    TRY(prof_begin(m, EXPDG_K_EV_GRAD));
+    HIPTRY(launch_ev_grad<T>(a, m->d.p, v, (T *)m->evg, s));
+    TRY(prof_end(m, EXPDG_K_EV_GRAD, 12.0 * m->K * m->Np * sizeof(T)));
+    return EXPDG_OK;
 }
 
 // Residual (jvp = false) or linear operator of the mesh on stream s; the
@@ -208,7 +231,7 @@ int apply_op(expdg_mesh *m, bool jvp, const T *q, const T *v, T *out, hipStream_
     a.out = out;
     a.lin = (const T *)m->lin;
     // the diffusion of the entropy viscosity needs the gradient of the input
-    if (a.nu) HIPTRY(launch_ev_grad<T>(a, m->d.p, jvp ? v : q, (T *)m->evg, s));
+    if (a.nu) TRY(ev_gradient<T>(m, a, jvp ? v : q, s));
     const int cls = jvp ? EXPDG_K_LINEAR : EXPDG_K_RESIDUAL;
     TRY(prof_begin(m, cls));
     HIPTRY(launch_dg_op(m->d.equation, m->d.p, jvp, a, s));

@@ -124,6 +124,25 @@ def shear_layer(x, y, seed: int = 0, a: float = 0.01, sigma: float = 0.04, amp: 
     return primitive_to_conservative(rho, u, v, p, gamma)
 
 
+def kelvin_helmholtz(x, y, a: float = 0.05, amp: float = 0.01, sigma: float = 0.2,
+                     s1: float = 2.0, s2: float = 3.0, gamma: float = 1.4) -> np.ndarray:
+    """The Kelvin-Helmholtz initial state of Section 5.3 on (-5, 5) x (0, 5).
+
+    rho = 1 + (tanh((y-s1)/a) - tanh((y-s2)/a))/2, u = 0.1 + tanh((y-s1)/a) -
+    tanh((y-s2)/a) - 1, v = amp sin(2 pi x)(e^{-(y-s1)^2/sigma^2} +
+    e^{-(y-s2)^2/sigma^2}), p = 1/gamma.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    t = np.tanh((y - s1) / a) - np.tanh((y - s2) / a)
+    rho = 1.0 + 0.5 * t
+    u = 0.1 + t - 1.0
+    env = np.exp(-((y - s1) ** 2) / sigma ** 2) + np.exp(-((y - s2) ** 2) / sigma ** 2)
+    v = amp * np.sin(2.0 * math.pi * x) * env
+    p = np.full_like(x, 1.0 / gamma)
+    return primitive_to_conservative(rho, u, v, p, gamma)
+
+
 def random_euler_state(npts: int, seed: int, gamma: float = 1.4, spread: float = 0.2) -> np.ndarray:
     """Pointwise random admissible Euler state (positive density and pressure)."""
     rng = np.random.default_rng(seed)
