@@ -315,13 +315,20 @@ SL = dict(nx=512, ny=512, p=4, cr=5.0, steps=20, tol=1e-7, m_min=10, m_max=64, c
 
 
 def run_ev(args):
+    out = {}
+    if not args.no_kh:
+        out["kelvin_helmholtz"] = run_kh(args)
+    out["shear_layer_512_p4"] = run_shear_ev(args)
+    return out
+
+
+def run_kh(args):
     import numpy as np
     import torch
 
     from paper_2011_01316_amd import binding as B
     from paper_2011_01316_amd import inputs
 
-    out = {}
     w = KH
     m = B.Mesh(B.EULER2D, w["nx"], w["p"], ny=w["ny"], x0=-5.0, x1=5.0, y0=0.0, y1=5.0,
                m_max=w["m_max"], ev_ce=w["ce"], ev_cmax=w["cmax"])
@@ -334,12 +341,14 @@ def run_ev(args):
     npts = m.K * m.Np
     m0 = [float(mass @ q0.cpu().numpy()[c * npts:(c + 1) * npts]) for c in range(4)]
     runs = {}
-    for dt in w["dts"]:
+    # both of the paper's steps, and the smaller one again with incomplete
+    # orthogonalization (L = 2)
+    for dt, iop in [(dt, 0) for dt in w["dts"]] + [(min(w["dts"]), 2)]:
         nsteps = int(round(w["t_end"] / dt))
         q = q0.clone()
         qp = torch.empty_like(q)
         st = B.make_stats()
-        opts = B.make_opts(w["tol"], w["m_min"], w["m_max"])
+        opts = B.make_opts(w["tol"], w["m_min"], w["m_max"], iop=iop)
         # chunks of `chunk` steps, so that a run that loses positivity is
         # reported with the time it reached (one library call per chunk)
         chunk = nsteps if dt < 0.1 else 2
@@ -356,8 +365,9 @@ def run_ev(args):
         torch.cuda.synchronize()
         secs = time.perf_counter() - t0
         d = B.stats_dict(st)
-        key = f"epi2_dt{dt:g}"
-        r = dict(dt=dt, steps=nsteps, steps_done=done, t_reached=round(done * dt, 3),
+        paper_key = f"epi2_dt{dt:g}"
+        key = paper_key + ("_iop2" if iop else "")
+        r = dict(dt=dt, iop=iop, steps=nsteps, steps_done=done, t_reached=round(done * dt, 3),
                  seconds=round(secs, 3), ms_per_step=round(secs / max(1, done) * 1e3, 4),
                  krylov_iters=d["krylov_iters"], substeps=d["substeps"], rejects=d["rejects"],
                  courant=round(dt * m.max_speed(q0) / m.dx_min, 2))
@@ -369,23 +379,29 @@ def run_ev(args):
             nu = torch.empty(npts, dtype=torch.float64, device="cuda:0")
             m.entropy_viscosity(q, qp, dt, nu)
             r.update(seconds_to_t100=round(secs, 3),
-                     vs_paper=round(KH_PAPER_SECONDS[key] / secs, 1),
+                     vs_paper=round(KH_PAPER_SECONDS[paper_key] / secs, 1),
                      min_density=float(rho.min()), min_pressure=float(pr.min()),
                      max_nu_final=float(nu.max().item()),
                      mass_drift=max(abs(float(mass @ qh[c * npts:(c + 1) * npts]) - m0[c]) /
                                     max(1.0, abs(m0[c])) for c in range(4)))
-            log(f"KH EPI2 dt={dt}: {secs:.3f} s to t = 100 ({nsteps} steps, "
+            log(f"KH EPI2 dt={dt} iop={iop}: {secs:.3f} s to t = 100 ({nsteps} steps, "
                 f"{d['krylov_iters']} Krylov iterations)")
         else:
             r["diverged"] = failed
             log(f"KH EPI2 dt={dt}: diverged after t = {done * dt:g} ({failed})")
         runs[key] = r
-    out["kelvin_helmholtz"] = dict(workload=w["name"], ndof=m.n, runs=runs,
-                                   paper_seconds=KH_PAPER_SECONDS)
     m.close()
+    return dict(workload=w["name"], ndof=m.n, runs=runs, paper_seconds=KH_PAPER_SECONDS)
 
-    # the 512 x 512 shear layer: EPI3 steps with and without the viscosity,
-    # then one instrumented pass of the same steps
+
+def run_shear_ev(args):
+    """The 512 x 512 shear layer: EPI3 steps with and without the viscosity,
+    then two instrumented steps with it."""
+    import torch
+
+    from paper_2011_01316_amd import binding as B
+    from paper_2011_01316_amd import inputs
+
     w = SL
     res = {}
     for ev in (False, True):
@@ -418,9 +434,10 @@ def run_ev(args):
             pr = {B.KERNEL_CLASSES[c]: B.expdg_profile_read(m.handle, c) for c in B.KERNEL_CLASSES}
             for c in B.KERNEL_CLASSES:
                 B.expdg_profile_enable(m.handle, c, False)
-            r["linear_operator_roofline"] = roof(pr["linear_operator"], "linear_operator",
-                                                 "euler_op<4, float, true>")
-            r["ev_grad_roofline"] = roof(pr["ev_grad"], "ev_grad", "ev_grad_kernel<4, float>")
+            wl = "shear512_p4_ev"
+            r["linear_operator_roofline"] = roof(
+                pr["linear_operator"], "linear_operator", "euler_op<4, float, true, true>",
+                measured_traffic("euler_op<4, float, true, true>", wl))
             r["ev_visc_roofline"] = roof(pr["ev_visc"], "ev_visc",
                                          "ev_element_kernel<4> / ev_smooth_kernel<4, float>")
             tot = sum(v["total_ms"] for v in pr.values())
@@ -431,8 +448,7 @@ def run_ev(args):
         del q, qp
     res["ev_step_cost_ratio"] = round(res["with_ev"]["ms_per_step"] /
                                       res["without_ev"]["ms_per_step"], 3)
-    out["shear_layer_512_p4"] = dict(workload=w["name"], steps=w["steps"], **res)
-    return out
+    return dict(workload=w["name"], steps=w["steps"], **res)
 
 
 def roof(p, name, symbol, traffic=None):
@@ -694,6 +710,8 @@ def main():
     ap.add_argument("--serve-seq", type=int, default=40,
                     help="first requests also run one after another for comparison")
     ap.add_argument("--no-ev", action="store_true")
+    ap.add_argument("--no-kh", action="store_true",
+                    help="entropy viscosity: skip the Kelvin-Helmholtz runs")
     ap.add_argument("--ev-only", action="store_true",
                     help="only run the entropy-viscosity workloads and print their figures")
     ap.add_argument("--serve-only", action="store_true",
@@ -812,7 +830,7 @@ def main():
             fp32_speedup=round(b32["value"] / b64["value"], 3),
             fp32_tol1e_7_step_speedup=round(b64["ms_per_step"] / b7["ms_per_step"], 3),
             linear_operator_roofline=roof(pb["linear_operator"], "linear_operator",
-                                          "euler_op<3, double, true>"),
+                                          "euler_op<3, double, true, false>"),
             gs_update_roofline=roof(pb["gs_update"], "gs_update", B.KERNEL_SYMBOLS["gs_update"]),
             gs_dots_roofline=roof(pb["gs_dots"], "gs_dots", B.KERNEL_SYMBOLS["gs_dots"]))
     if not args.no_viscous:

@@ -290,10 +290,9 @@ enum {
                                    first pass of the new one */
     EXPDG_K_GS_NORM = 6,        /* norm of a substep's start vector */
     EXPDG_K_GS_FINISH = 7,      /* fixed-order sums of the block partials (step finish) */
-    EXPDG_K_EV_GRAD = 8,        /* entropy viscosity: gradient of an operator's input */
-    EXPDG_K_EV_VISC = 9,        /* entropy viscosity: element viscosity and its nodal
+    EXPDG_K_EV_VISC = 8,        /* entropy viscosity: element viscosity and its nodal
                                    reconstruction (two launches per evaluation) */
-    EXPDG_K_NCLASSES = 10
+    EXPDG_K_NCLASSES = 9
 };
 
 /* Accumulated timing of one kernel class: launches, summed event-measured

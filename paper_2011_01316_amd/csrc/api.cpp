@@ -211,7 +211,6 @@ size_t layout(expdg_mesh *m, const expdg_mesh_desc *d, size_t stride, int eb, ch
     if (d->ev_ce > 0.0) {
         const size_t pts = (size_t)K * (d->p + 1) * (d->p + 1);
         take(m->nu, pts * eb);
-        take(m->evg, 8 * pts * eb);
         take(m->nue, (size_t)K * 8);
     }
     take(m->kd.H, (size_t)(kMaxM + 1) * kLDH * 8);
@@ -636,7 +635,6 @@ struct DirectExec {
         const int nv = a.nv;  // vectors the dot pass and the update read
         const double eb = (double)sizeof(T);
         const bool fused = a.dots != 0;
-        if (a.nu) TRY(ev_gradient<T>(m, a, a.v, s));
         TRY(prof_begin(m, EXPDG_K_LINEAR));
         HIPTRY(launch_dg_op(m->d.equation, m->d.p, true, a, s));
         TRY(prof_end(m, EXPDG_K_LINEAR,

@@ -311,7 +311,7 @@ __device__ __forceinline__ void op_dots2(const OpArgs<T> &a, bool active, unsign
 // residual the state itself.  Face and augmented terms need no LDS and are
 // added before the barrier; -(2/h) D is staged in LDS for the derivative.
 // Node offsets are 32-bit within one variable plane.
-template <int P, typename T, bool JVP>
+template <int P, typename T, bool JVP, bool EV = false>
 __device__ __forceinline__ void euler_op_body(const OpArgs<T> &a, int tile, bool first) {
     constexpr int N1 = P + 1, NP = N1 * N1, EPB = 256 / NP, NT = EPB * NP;
     __shared__ T sF[8][NT];
@@ -364,85 +364,196 @@ __device__ __forceinline__ void euler_op_body(const OpArgs<T> &a, int tile, bool
 #pragma unroll
         for (int c = 0; c < 4; ++c) q[c] = u[c] = fx[c] = fy[c] = T(0);
     }
-    // entropy viscosity: the flux gets -nu grad(differentiated field)
-    const bool ev = a.nu != nullptr;
-    if (ev && active) {
-        const T nuv = ld32(a.nu, idx);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            fx[c] -= nuv * ld32(a.evg + c * plane, idx);
-            fy[c] -= nuv * ld32(a.evg + (4 + c) * plane, idx);
-        }
-    }
-    if (tid < NT) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            sF[c][tid] = fx[c];
-            sF[4 + c][tid] = fy[c];
-        }
-    }
-
     T res[4] = {T(0), T(0), T(0), T(0)};
-    if (active && (i == 0 || i == P)) {
-        const int s = (i == P) ? 1 : -1;
-        int exn = ex + s;
-        exn = exn < 0 ? a.nx - 1 : (exn >= a.nx ? 0 : exn);
-        const int en = ey * a.nx + exn;
-        const unsigned nidx = (unsigned)en * NP + j * N1 + (P - i);
-        T qn[4], un[4], fn[4], lam;
-        if (JVP) {
+    if constexpr (EV) {
+        // Entropy viscosity: the flux becomes F - nu g, g the central gradient
+        // of the differentiated field v (u here), g_d = (2/h_d) D_d v +
+        // (2/h_d)(1/w_0) n_d ({{v}} - v^-) on the faces along d.  g at the
+        // node comes from the element's v staged in LDS; g at the neighbour's
+        // matching face node from that neighbour's row of nodes along the
+        // normal and the shared face's mean.
+        __shared__ T sV[4][NT];
+        if (tid < NT) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) qn[c] = ld32(src[c], nidx);
-#pragma unroll
-            for (int c = 0; c < 4; ++c) un[c] = ld32(vin[c], nidx);
-            euler_jac_lin_dir<T, 0>(qn, un, gm1, fn);
-            lam = ld32(lamx, (unsigned)(s > 0 ? e : en) * N1 + j);
-        } else {
-#pragma unroll
-            for (int c = 0; c < 4; ++c) qn[c] = un[c] = ld32(src[c], nidx);
-            euler_flux_dir<T, 0>(qn, gm1, fn);
-            lam = fmax(euler_speed<T, 0>(q, a.gamma), euler_speed<T, 0>(qn, a.gamma));
+            for (int c = 0; c < 4; ++c) sV[c][tid] = u[c];
         }
-        if (ev) {
-            const T nun = ld32(a.nu, nidx);
+        const bool onx = active && (i == 0 || i == P), ony = active && (j == 0 || j == P);
+        const int sx = (i == P) ? 1 : -1, sy = (j == P) ? 1 : -1;
+        int exn = ex + sx, eyn = ey + sy;
+        exn = exn < 0 ? a.nx - 1 : (exn >= a.nx ? 0 : exn);
+        eyn = eyn < 0 ? a.ny - 1 : (eyn >= a.ny ? 0 : eyn);
+        const int enx = ey * a.nx + exn, eny = eyn * a.nx + ex;
+        const unsigned nix = (unsigned)enx * NP + j * N1 + (P - i);
+        const unsigned niy = (unsigned)eny * NP + (P - j) * N1 + i;
+        T unx[4], fnx[4], uny[4], fny[4], lx = T(0), ly = T(0);
+        if (onx) {
+            T qn[4];
+            if (JVP) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) fn[c] -= nun * ld32(a.evg + c * plane, nidx);
+                for (int c = 0; c < 3; ++c) qn[c] = ld32(src[c], nix);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) unx[c] = ld32(vin[c], nix);
+                euler_jac_lin_dir<T, 0>(qn, unx, gm1, fnx);
+                lx = ld32(lamx, (unsigned)(sx > 0 ? e : enx) * N1 + j);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) qn[c] = unx[c] = ld32(src[c], nix);
+                euler_flux_dir<T, 0>(qn, gm1, fnx);
+                lx = fmax(euler_speed<T, 0>(q, a.gamma), euler_speed<T, 0>(qn, a.gamma));
+            }
+        }
+        if (ony) {
+            T qn[4];
+            if (JVP) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) qn[c] = ld32(src[c], niy);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) uny[c] = ld32(vin[c], niy);
+                euler_jac_lin_dir<T, 1>(qn, uny, gm1, fny);
+                ly = ld32(lamy, (unsigned)(sy > 0 ? e : eny) * N1 + i);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) qn[c] = uny[c] = ld32(src[c], niy);
+                euler_flux_dir<T, 1>(qn, gm1, fny);
+                ly = fmax(euler_speed<T, 1>(q, a.gamma), euler_speed<T, 1>(qn, a.gamma));
+            }
+        }
+        __syncthreads();
+        if (active) {
+            const int base = le * NP;
+            const T nuv = ld32(a.nu, idx);
+            T gx[4] = {T(0), T(0), T(0), T(0)}, gy[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+            for (int l = 0; l < N1; ++l) {
+                const T dx = sDx[i * N1 + l], dy = sDy[j * N1 + l];  // -(2/h) D
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    gx[c] = fma(-dx, sV[c][base + j * N1 + l], gx[c]);
+                    gy[c] = fma(-dy, sV[c][base + l * N1 + i], gy[c]);
+                }
+            }
+            if (onx) {
+                const T cf = a.rhx * a.lift * T(sx);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) gx[c] += cf * (T(0.5) * (u[c] + unx[c]) - u[c]);
+                // the neighbour's node: index P - i along x, outward normal -sx
+                const T nun = ld32(a.nu, nix);
+                const unsigned row = (unsigned)enx * NP + j * N1;
+                const int an = P - i;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    T g = T(0);
+#pragma unroll
+                    for (int l = 0; l < N1; ++l) g = fma(-sDx[an * N1 + l], ld32(vin[c], row + l), g);
+                    g -= cf * (T(0.5) * (unx[c] + u[c]) - unx[c]);
+                    fnx[c] -= nun * g;
+                }
+            }
+            if (ony) {
+                const T cf = a.rhy * a.lift * T(sy);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) gy[c] += cf * (T(0.5) * (u[c] + uny[c]) - u[c]);
+                const T nun = ld32(a.nu, niy);
+                const unsigned col = (unsigned)eny * NP + i;
+                const int an = P - j;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    T g = T(0);
+#pragma unroll
+                    for (int l = 0; l < N1; ++l)
+                        g = fma(-sDy[an * N1 + l], ld32(vin[c], col + l * N1), g);
+                    g -= cf * (T(0.5) * (uny[c] + u[c]) - uny[c]);
+                    fny[c] -= nun * g;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                fx[c] -= nuv * gx[c];
+                fy[c] -= nuv * gy[c];
+            }
+        }
+        if (tid < NT) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                sF[c][tid] = fx[c];
+                sF[4 + c][tid] = fy[c];
+            }
         }
         // res -= (2/h)(1/w_0) [ s (F_n - F)/2 + lam (u - u_n)/2 ]
-        const T cf = a.rhx * a.lift;
-        const T ca = cf * T(0.5) * T(s), cb = cf * T(0.5) * lam;
+        if (onx) {
+            const T cf = a.rhx * a.lift;
+            const T ca = cf * T(0.5) * T(sx), cb = cf * T(0.5) * lx;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) res[c] = fma(-cb, u[c] - un[c], fma(-ca, fn[c] - fx[c], res[c]));
-    }
-    if (active && (j == 0 || j == P)) {
-        const int s = (j == P) ? 1 : -1;
-        int eyn = ey + s;
-        eyn = eyn < 0 ? a.ny - 1 : (eyn >= a.ny ? 0 : eyn);
-        const int en = eyn * a.nx + ex;
-        const unsigned nidx = (unsigned)en * NP + (P - j) * N1 + i;
-        T qn[4], un[4], fn[4], lam;
-        if (JVP) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) qn[c] = ld32(src[c], nidx);
-#pragma unroll
-            for (int c = 0; c < 4; ++c) un[c] = ld32(vin[c], nidx);
-            euler_jac_lin_dir<T, 1>(qn, un, gm1, fn);
-            lam = ld32(lamy, (unsigned)(s > 0 ? e : en) * N1 + i);
-        } else {
-#pragma unroll
-            for (int c = 0; c < 4; ++c) qn[c] = un[c] = ld32(src[c], nidx);
-            euler_flux_dir<T, 1>(qn, gm1, fn);
-            lam = fmax(euler_speed<T, 1>(q, a.gamma), euler_speed<T, 1>(qn, a.gamma));
+            for (int c = 0; c < 4; ++c)
+                res[c] = fma(-cb, u[c] - unx[c], fma(-ca, fnx[c] - fx[c], res[c]));
         }
-        if (ev) {
-            const T nun = ld32(a.nu, nidx);
+        if (ony) {
+            const T cf = a.rhy * a.lift;
+            const T ca = cf * T(0.5) * T(sy), cb = cf * T(0.5) * ly;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) fn[c] -= nun * ld32(a.evg + (4 + c) * plane, nidx);
+            for (int c = 0; c < 4; ++c)
+                res[c] = fma(-cb, u[c] - uny[c], fma(-ca, fny[c] - fy[c], res[c]));
         }
-        const T cf = a.rhy * a.lift;
-        const T ca = cf * T(0.5) * T(s), cb = cf * T(0.5) * lam;
+    } else {
+        if (tid < NT) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) res[c] = fma(-cb, u[c] - un[c], fma(-ca, fn[c] - fy[c], res[c]));
+            for (int c = 0; c < 4; ++c) {
+                sF[c][tid] = fx[c];
+                sF[4 + c][tid] = fy[c];
+            }
+        }
+
+        if (active && (i == 0 || i == P)) {
+            const int s = (i == P) ? 1 : -1;
+            int exn = ex + s;
+            exn = exn < 0 ? a.nx - 1 : (exn >= a.nx ? 0 : exn);
+            const int en = ey * a.nx + exn;
+            const unsigned nidx = (unsigned)en * NP + j * N1 + (P - i);
+            T qn[4], un[4], fn[4], lam;
+            if (JVP) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) qn[c] = ld32(src[c], nidx);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) un[c] = ld32(vin[c], nidx);
+                euler_jac_lin_dir<T, 0>(qn, un, gm1, fn);
+                lam = ld32(lamx, (unsigned)(s > 0 ? e : en) * N1 + j);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) qn[c] = un[c] = ld32(src[c], nidx);
+                euler_flux_dir<T, 0>(qn, gm1, fn);
+                lam = fmax(euler_speed<T, 0>(q, a.gamma), euler_speed<T, 0>(qn, a.gamma));
+            }
+            // res -= (2/h)(1/w_0) [ s (F_n - F)/2 + lam (u - u_n)/2 ]
+            const T cf = a.rhx * a.lift;
+            const T ca = cf * T(0.5) * T(s), cb = cf * T(0.5) * lam;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) res[c] = fma(-cb, u[c] - un[c], fma(-ca, fn[c] - fx[c], res[c]));
+        }
+        if (active && (j == 0 || j == P)) {
+            const int s = (j == P) ? 1 : -1;
+            int eyn = ey + s;
+            eyn = eyn < 0 ? a.ny - 1 : (eyn >= a.ny ? 0 : eyn);
+            const int en = eyn * a.nx + ex;
+            const unsigned nidx = (unsigned)en * NP + (P - j) * N1 + i;
+            T qn[4], un[4], fn[4], lam;
+            if (JVP) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) qn[c] = ld32(src[c], nidx);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) un[c] = ld32(vin[c], nidx);
+                euler_jac_lin_dir<T, 1>(qn, un, gm1, fn);
+                lam = ld32(lamy, (unsigned)(s > 0 ? e : en) * N1 + i);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) qn[c] = un[c] = ld32(src[c], nidx);
+                euler_flux_dir<T, 1>(qn, gm1, fn);
+                lam = fmax(euler_speed<T, 1>(q, a.gamma), euler_speed<T, 1>(qn, a.gamma));
+            }
+            const T cf = a.rhy * a.lift;
+            const T ca = cf * T(0.5) * T(s), cb = cf * T(0.5) * lam;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) res[c] = fma(-cb, u[c] - un[c], fma(-ca, fn[c] - fy[c], res[c]));
+        }
     }
     // augmented block: + eta sum_k y_k b_{p+1-k}
     if (active) {
@@ -609,65 +720,6 @@ __global__ __launch_bounds__(256) void ev_smooth_kernel(EvParams ep, const doubl
     const double r = 0.5 * (ep.xi[i] + 1.0), s = 0.5 * (ep.xi[j] + 1.0);
     nu[t] = (T)((1.0 - r) * (1.0 - s) * v00 + r * (1.0 - s) * v10 + (1.0 - r) * s * v01 +
                 r * s * v11);
-}
-
-// Gradient of each of the four planes of v with central lifts:
-// g_d = (2/h_d) D_d v + (2/h_d)(1/w_0) n_d ({{v}} - v^-) on the faces along d.
-template <int P, typename T>
-__global__ __launch_bounds__(256) void ev_grad_kernel(OpArgs<T> a, const T *v, T *evg) {
-    constexpr int N1 = P + 1, NP = N1 * N1, EPB = 256 / NP, NT = EPB * NP;
-    __shared__ T sV[4][NT];
-    const int tid = threadIdx.x;
-    const int le = tid / NP, n = tid - le * NP;
-    const int i = n % N1, j = n / N1;
-    const int e = xcd_tile(blockIdx.x, gridDim.x) * EPB + le;
-    const bool active = (tid < NT) && (e < a.K);
-    const size_t plane = (size_t)a.K * NP;
-    const unsigned idx = (unsigned)e * NP + n;
-    T vv[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) vv[c] = active ? ld32(v + c * plane, idx) : T(0);
-    if (tid < NT) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) sV[c][tid] = vv[c];
-    }
-    __syncthreads();
-    if (!active) return;
-    const int base = le * NP;
-    T gx[4] = {T(0), T(0), T(0), T(0)}, gy[4] = {T(0), T(0), T(0), T(0)};
-#pragma unroll
-    for (int l = 0; l < N1; ++l) {
-        const T dx = a.rhx * a.D[i * N1 + l], dy = a.rhy * a.D[j * N1 + l];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            gx[c] += dx * sV[c][base + j * N1 + l];
-            gy[c] += dy * sV[c][base + l * N1 + i];
-        }
-    }
-    const int ex = e % a.nx, ey = e / a.nx;
-    if (i == 0 || i == P) {
-        const int s = (i == P) ? 1 : -1;
-        const int exn = (ex + s + a.nx) % a.nx;
-        const unsigned nidx = (unsigned)(ey * a.nx + exn) * NP + j * N1 + (P - i);
-        const T cf = a.rhx * a.lift * T(s);
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-            gx[c] += cf * (T(0.5) * (vv[c] + ld32(v + c * plane, nidx)) - vv[c]);
-    }
-    if (j == 0 || j == P) {
-        const int s = (j == P) ? 1 : -1;
-        const int eyn = (ey + s + a.ny) % a.ny;
-        const unsigned nidx = (unsigned)(eyn * a.nx + ex) * NP + (P - j) * N1 + i;
-        const T cf = a.rhy * a.lift * T(s);
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-            gy[c] += cf * (T(0.5) * (vv[c] + ld32(v + c * plane, nidx)) - vv[c]);
-    }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        st32(evg + c * plane, idx, gx[c]);
-        st32(evg + (4 + c) * plane, idx, gy[c]);
-    }
 }
 
 // ---- Euler 3D operator ------------------------------------------------------
@@ -1113,9 +1165,9 @@ __device__ __forceinline__ void burgers_op_body(const OpArgs<T> &a, int tile, bo
         op_dots2<T, 1>(a, active, (unsigned)idx, (size_t)a.K * N1, &uv, &wv, tile, first);
 }
 
-template <int P, typename T, bool JVP>
+template <int P, typename T, bool JVP, bool EV>
 __global__ __launch_bounds__(256) void euler_op(OpArgs<T> a) {
-    euler_op_body<P, T, JVP>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.x == 0);
+    euler_op_body<P, T, JVP, EV>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.x == 0);
 }
 
 template <int P, typename T, bool JVP, bool VISC>
@@ -1175,8 +1227,13 @@ hipError_t launch_p(int equation, bool jvp, const OpArgs<T> &a, hipStream_t s) {
     if (equation == EXPDG_EULER2D) {
         constexpr int EPB = 256 / ((P + 1) * (P + 1));
         const int grid = (a.K + EPB - 1) / EPB;
-        if (jvp) return launch_kernel(euler_op<P, T, true>, dim3(grid), dim3(256), 0, s, a);
-        return launch_kernel(euler_op<P, T, false>, dim3(grid), dim3(256), 0, s, a);
+        if (a.nu) {
+            if (jvp)
+                return launch_kernel(euler_op<P, T, true, true>, dim3(grid), dim3(256), 0, s, a);
+            return launch_kernel(euler_op<P, T, false, true>, dim3(grid), dim3(256), 0, s, a);
+        }
+        if (jvp) return launch_kernel(euler_op<P, T, true, false>, dim3(grid), dim3(256), 0, s, a);
+        return launch_kernel(euler_op<P, T, false, false>, dim3(grid), dim3(256), 0, s, a);
     }
     constexpr int EPB = 256 / (P + 1);
     const int grid = (a.K + EPB - 1) / EPB;
@@ -1345,25 +1402,6 @@ template hipError_t launch_ev_smooth<double>(const EvParams &, const double *, d
                                              hipStream_t);
 template hipError_t launch_ev_smooth<float>(const EvParams &, const double *, float *,
                                             hipStream_t);
-
-template <typename T>
-hipError_t launch_ev_grad(const OpArgs<T> &a, int p, const T *v, T *evg, hipStream_t s) {
-    const int np = (p + 1) * (p + 1), epb = 256 / np;
-    const dim3 grid((unsigned)((a.K + epb - 1) / epb));
-    switch (p) {
-        case 1: return launch_kernel(ev_grad_kernel<1, T>, grid, dim3(256), 0, s, a, v, evg);
-        case 2: return launch_kernel(ev_grad_kernel<2, T>, grid, dim3(256), 0, s, a, v, evg);
-        case 3: return launch_kernel(ev_grad_kernel<3, T>, grid, dim3(256), 0, s, a, v, evg);
-        case 4: return launch_kernel(ev_grad_kernel<4, T>, grid, dim3(256), 0, s, a, v, evg);
-        case 5: return launch_kernel(ev_grad_kernel<5, T>, grid, dim3(256), 0, s, a, v, evg);
-        case 6: return launch_kernel(ev_grad_kernel<6, T>, grid, dim3(256), 0, s, a, v, evg);
-        default: return hipErrorInvalidValue;
-    }
-}
-template hipError_t launch_ev_grad<double>(const OpArgs<double> &, int, const double *, double *,
-                                           hipStream_t);
-template hipError_t launch_ev_grad<float>(const OpArgs<float> &, int, const float *, float *,
-                                          hipStream_t);
 
 template <typename T>
 hipError_t launch_lin_prepare(int equation, int p, const T *q, T *lin, int K, int nx, int ny,

@@ -56,10 +56,8 @@ struct OpArgs {
     int ef;            // nonzero: entropy flux for (u^2/2)*
     int dirichlet;     // nonzero: u = 0 beyond both ends
     const T *src;
-    // Entropy viscosity (2D Euler): nodal viscosity nu and the gradient of the
-    // differentiated field (x planes then y planes), or nullptr
+    // Entropy viscosity (2D Euler): nodal viscosity nu, or nullptr
     const T *nu;
-    const T *evg;
     T D[(kMaxP + 1) * (kMaxP + 1)];  // D[i*(p+1)+l] = l_l'(xi_i)
 };
 
@@ -119,9 +117,6 @@ hipError_t launch_ev_element(const EvParams &ep, const double *q, const double *
                              double *nue, hipStream_t s);
 template <typename T>
 hipError_t launch_ev_smooth(const EvParams &ep, const double *nue, T *nu, hipStream_t s);
-// Gradient of the four planes of v (central lift) into evg: x planes, then y.
-template <typename T>
-hipError_t launch_ev_grad(const OpArgs<T> &a, int p, const T *v, T *evg, hipStream_t s);
 // Per-block maxima of the wave speed (FP64 state) into part[0..nblk).
 hipError_t launch_max_speed(int equation, const double *q, size_t npts, double gamma,
                             double *part, int nblk, hipStream_t s);

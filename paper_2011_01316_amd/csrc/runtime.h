@@ -33,7 +33,6 @@ struct expdg_mesh {
     void *src = nullptr;         // source term of the residual (bulk type; has_source only)
     void *lin = nullptr;         // frozen fields of the 2D linear operator (bulk type)
     void *nu = nullptr;          // entropy viscosity at the nodes (bulk type; ev_ce > 0 only)
-    void *evg = nullptr;         // gradient of an operator's input (8 planes, bulk type)
     double *nue = nullptr;       // element viscosities (K)
     expdg::KrylovDev kd{};
     double *slots = nullptr;     // kCheckSlots x kSlotSize
@@ -147,7 +146,6 @@ OpArgs<T> op_args(const expdg_mesh *m) {
     a.dirichlet = m->d.bc == EXPDG_BC_DIRICHLET;
     a.src = (const T *)m->src;
     a.nu = (const T *)m->nu;
-    a.evg = (const T *)m->evg;
     return a;
 }
 
@@ -204,22 +202,13 @@ hipError_t prepare_lin(expdg_mesh *m, const T *q, hipStream_t s) {
 // (linear operator).  Augmented blocks and fused dots are added by the caller.
 inline double op_bytes(const expdg_mesh *m, bool jvp) {
     const double n = (double)m->n, eb = (double)m->ebytes;
-    // entropy viscosity: the nodal viscosity and the eight gradient planes
-    const double ev = m->nu ? 9.0 * m->K * m->Np * eb : 0.0;
+    // entropy viscosity: the nodal viscosity
+    const double ev = m->nu ? (double)m->K * m->Np * eb : 0.0;
     if (!jvp) return 2.0 * n * eb + ev;
     const double lin = (double)lin_elems(m->d.equation, m->d.p, m->K);
     return (lin > 0.0 ? 2.0 * n + lin : 3.0 * n) * eb + ev;
 }
 
-// Gradient of an operator's input for the entropy viscosity: four planes
-// read, eight written.
-template <typename T>
-int ev_gradient(expdg_mesh *m, const OpArgs<T> &a, const T *v, hipStream_t s) {
-    TRY(prof_begin(m, EXPDG_K_EV_GRAD));
-    HIPTRY(launch_ev_grad<T>(a, m->d.p, v, (T *)m->evg, s));
-    TRY(prof_end(m, EXPDG_K_EV_GRAD, 12.0 * m->K * m->Np * sizeof(T)));
-    return EXPDG_OK;
-}
 
 // Residual (jvp = false) or linear operator of the mesh on stream s; the
 // linear operator needs the frozen fields of q prepared (prepare_lin).
@@ -230,8 +219,6 @@ int apply_op(expdg_mesh *m, bool jvp, const T *q, const T *v, T *out, hipStream_
     a.v = v;
     a.out = out;
     a.lin = (const T *)m->lin;
-    // the diffusion of the entropy viscosity needs the gradient of the input
-    if (a.nu) TRY(ev_gradient<T>(m, a, jvp ? v : q, s));
     const int cls = jvp ? EXPDG_K_LINEAR : EXPDG_K_RESIDUAL;
     TRY(prof_begin(m, cls));
     HIPTRY(launch_dg_op(m->d.equation, m->d.p, jvp, a, s));

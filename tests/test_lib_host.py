@@ -117,16 +117,16 @@ def test_euler3d_validation():
 
 
 def test_entropy_viscosity_validation():
-    # Euler 2D only, constants >= 0; the workspace gains the nodal viscosity,
-    # the eight gradient planes and one element viscosity per element
+    # Euler 2D only, constants >= 0; the workspace gains the nodal viscosity
+    # and one element viscosity per element
     base = B.expdg_workspace_bytes(desc())
     ev = B.expdg_workspace_bytes(desc(ev_ce=1.0, ev_cmax=0.1))
     pts, K = 64 * 64 * 25, 64 * 64
-    assert ev - base >= 9 * pts * 8 + K * 8
-    assert ev - base <= 9 * pts * 8 + K * 8 + 3 * 256
+    assert ev - base >= pts * 8 + K * 8
+    assert ev - base <= pts * 8 + K * 8 + 2 * 256
     evf = B.expdg_workspace_bytes(desc(ev_ce=1.0, ev_cmax=0.1, precision=B.FP32_BULK))
     basef = B.expdg_workspace_bytes(desc(precision=B.FP32_BULK))
-    assert evf - basef >= 9 * pts * 4 + K * 8
+    assert evf - basef >= pts * 4 + K * 8
     assert B.expdg_workspace_bytes(desc(ev_ce=0.0, ev_cmax=0.1)) == base
     for bad in [dict(ev_ce=-1.0), dict(ev_cmax=-0.1), dict(ev_ce=float("nan")),
                 dict(equation=B.BURGERS1D, ny=1, ev_ce=1.0),
