@@ -33,6 +33,11 @@ Checks:
       exact, and the Krylov combination of up to m vectors multiplies that.
       Hence |mass of the increment| <= 2048 u dt S area, with u the unit
       roundoff of the bulk type (2^-53 or 2^-24).
+  * Entropy viscosity on the shear layer at 512 x 512, p = 4 (the size its
+    measurement runs at): the nodal viscosity and both operators with it
+    against the oracle within bounds of the same kind (stated with the
+    tests), and one FP32-bulk EPI3 step with the viscosity against the FP64
+    one.
 """
 import math
 
@@ -185,3 +190,116 @@ def test_fp32_bulk_step_full_size(case):
     m32, _ = discrete_mass(om, w32, p)
     assert abs(m64) <= 2048 * 2.0 ** -53 * dt * S * area, (m64, dt * S * area)
     assert abs(m32) <= 2048 * U32 * dt * S * area, (m32, dt * S * area)
+
+
+# ---- entropy viscosity at the size of its measurement (512 x 512, p = 4) ----
+# The viscosity: Res at a node sums the two entropy time terms and the 2(p+1)
+# terms of the two element-local divergences, each at most
+# T = 2 max|S| / dt + (2/h) max_i sum_l |D_il| max|uS| in size, so its error is
+# at most c u T; a face jump |[[uS . n]]| is off by at most 2 u max|uS|; the
+# element viscosity scales these by c_E h_e^2 (at most h_e^2 T c_E when the cap
+# is not taken, at most the cap's own rounding otherwise) and the smoothing
+# only averages.  Hence |nu_gpu - nu_oracle| <= c u c_E h_e^2 (T + max|uS|/h_e)
+# + c u max(nu), c = 4 (p + 11).
+# The operators with a viscosity nu: the viscous terms are a second stencil
+# applied to nu g, g itself a stencil of v: each entry within
+# c u (S + 2 S_v) with S_v = (2/h)^2 (max_i sum_l |D_il| + 1/w_0)^2 max(nu) max|v|.
+
+def entropy_fields(q, npts):
+    r, m, nn, E = q.reshape(4, npts)
+    u, v = m / r, nn / r
+    pr = (GAMMA - 1.0) * (E - 0.5 * (m * u + nn * v))
+    S = r / (GAMMA - 1.0) * np.log(pr / r ** GAMMA)
+    return S, np.abs(u * S).max() + np.abs(v * S).max()
+
+
+def ev_setup(precision=B.FP64):
+    n, p = 512, 4
+    om = oracle.Mesh(oracle.EULER2D, n, p, ny=n, ev_ce=1.0, ev_cmax=0.1)
+    gm = B.Mesh(B.EULER2D, n, p, ny=n, precision=precision, ev_ce=1.0, ev_cmax=0.1)
+    x, y = om.nodes()
+    q = inputs.shear_layer(x, y, seed=0).reshape(-1)
+    qp = q * (1.0 + 1e-3 * np.random.default_rng(5).standard_normal(q.size))
+    return om, gm, q, qp
+
+
+def test_entropy_viscosity_full_size():
+    om, gm, q, qp = ev_setup()
+    p, dt = 4, 0.02
+    with gm:
+        nu = torch.empty(gm.K * gm.Np, dtype=torch.float64, device=DEV)
+        gm.entropy_viscosity(torch.tensor(q, device=DEV), torch.tensor(qp, device=DEV), dt, nu)
+        got = nu.cpu().numpy()
+    want = om.entropy_viscosity(q, qp, dt)
+    npts = q.size // 4
+    S, us = entropy_fields(q, npts)
+    Sp, usp = entropy_fields(qp, npts)
+    xi, w, D = oracle.lgl(p)
+    h = 1.0 / 512
+    he = math.sqrt(2.0) * h / p
+    T = 2 * max(np.abs(S).max(), np.abs(Sp).max()) / dt + \
+        (2.0 / h) * np.abs(D).sum(axis=1).max() * max(us, usp)
+    c = 4 * (p + 11)
+    u = 2.0 ** -53
+    bound = c * u * (he * he * (T + max(us, usp) / he) + want.max())
+    err = np.max(np.abs(got - want))
+    assert want.max() > 0 and err <= bound, (err, bound, want.max())
+
+
+def test_operators_with_viscosity_full_size():
+    om0, gm, q, qp = ev_setup()
+    p = 4
+    nu = om0.entropy_viscosity(q, qp, 0.02)
+    om = oracle.Mesh(oracle.EULER2D, 512, p, ny=512, ev_ce=1.0, ev_cmax=0.1, nu=nu)
+    with gm:
+        gm.set_viscosity(torch.tensor(nu, device=DEV))
+        v = q * (1.0 + 0.1 * np.random.default_rng(6).standard_normal(q.size))
+        qt = torch.tensor(q, device=DEV)
+        vt = torch.tensor(v, device=DEV)
+        r = torch.empty_like(qt)
+        w = torch.empty_like(qt)
+        gm.rhs(qt, r)
+        gm.jvp(qt, vt, w)
+        torch.cuda.synchronize()
+        rg, wg = r.cpu().numpy(), w.cpu().numpy()
+    ro, wo = om.rhs(q), om.jvp(q, v)
+    bound_r, bound_w = operator_bounds(om, p, q, v, 2.0 ** -53)
+    xi, wq, D = oracle.lgl(p)
+    k2 = ((2.0 * 512) * (np.abs(D).sum(axis=1).max() + 1.0 / wq[0])) ** 2
+    c = 4 * (p + 11)
+    sv_r = 2 * c * 2.0 ** -53 * k2 * nu.max() * np.abs(q).max()
+    sv_w = 2 * c * 2.0 ** -53 * k2 * nu.max() * np.abs(v).max()
+    er, ew = np.max(np.abs(rg - ro)), np.max(np.abs(wg - wo))
+    assert er <= bound_r + sv_r, (er, bound_r, sv_r)
+    assert ew <= bound_w + sv_w, (ew, bound_w, sv_w)
+    # the viscosity is active at this size
+    assert np.max(np.abs(wo - om0.jvp(q, v))) > 1e3 * (bound_w + sv_w)
+
+
+def test_fp32_bulk_step_with_viscosity_full_size():
+    # one EPI3 step (first step: EPI2 form) as the bench times it, FP32 bulk at
+    # tol 1e-7 against FP64 at tol 1e-10, both recomputing the viscosity from
+    # the state: state-level l2 difference <= 1e-6, discrete mass of both
+    # increments as in the inviscid check (the diffusion conserves mass)
+    p = 4
+    om, g64, q, _ = ev_setup()
+    with g64:
+        q0 = torch.tensor(q, device=DEV)
+        dt = 5.0 * g64.dx_min / g64.max_speed(q0)
+        q64 = q0.clone()
+        qp = torch.empty_like(q0)
+        g64.step(B.EPI3, dt, q64, qp, False, B.make_opts(1e-10, 10, 64, 1))
+        w64 = (q64 - q0).cpu().numpy()
+    g32 = B.Mesh(B.EULER2D, 512, p, ny=512, precision=B.FP32_BULK, ev_ce=1.0, ev_cmax=0.1)
+    with g32:
+        q32 = q0.clone()
+        g32.step(B.EPI3, dt, q32, qp, False, B.make_opts(1e-7, 10, 64, 1))
+        w32 = (q32 - q0).cpu().numpy()
+    state_diff = np.linalg.norm(w32 - w64) / np.linalg.norm(q + w64)
+    assert state_diff <= 1e-6, state_diff
+    fx, fy = flux_np(q, q.size // 4)
+    S = stencil_bound(om, p, max(np.abs(fx).max(), np.abs(fy).max()))
+    m64, _ = discrete_mass(om, w64, p)
+    m32, _ = discrete_mass(om, w32, p)
+    assert abs(m64) <= 2048 * 2.0 ** -53 * dt * S, (m64, dt * S)
+    assert abs(m32) <= 2048 * U32 * dt * S, (m32, dt * S)
