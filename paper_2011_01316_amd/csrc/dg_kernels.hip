@@ -202,11 +202,15 @@ __global__ __launch_bounds__(256) void euler_lin_prepare(const T *q, T *lin, int
 // nodes, u_i^T w and u_i^T x for i < nv (x = the input, w = the output, both as
 // stored), then x^T x and x^T w; tile 0 adds the augmented entries.  Row r of
 // the partials goes to dpart[r * dnb + tile], rows as in launch_gs_dots2.
-template <typename T, int NV, int NW = 4>
+// CH basis vectors per chunk (2 CH FP64 accumulators per thread): the 2D and
+// 3D operators take 8, which keeps the 3D operator at four waves per SIMD
+// instead of three and the FP32-bulk 2D operator at five instead of four.
+template <typename T, int NV, int NW = 4, int CH = 16>
 __device__ __forceinline__ void op_dots2(const OpArgs<T> &a, bool active, unsigned idx,
                                          size_t plane, const T *xv, const T *wv, int tile,
                                          bool first) {
     static_assert(NW == 4 || NW == 6, "blocks of 256 or 384 threads");
+    static_assert(CH == 16 || CH == 8, "chunks of 16 or 8 vectors");
     __shared__ double sw[NW][32];
     __shared__ double s2[NW][2];
     // fixed-order sum over the block's waves
@@ -219,17 +223,17 @@ __device__ __forceinline__ void op_dots2(const OpArgs<T> &a, bool active, unsign
     const int nv = a.nv;
     const bool tail = first && tid == 0 && a.naug > 0;
     const T sc = a.vscale ? (T)(*a.vscale) : T(1);
-    for (int i0 = 0; i0 < nv; i0 += 16) {
-        double acc[32];
+    for (int i0 = 0; i0 < nv; i0 += CH) {
+        double acc[2 * CH];
 #pragma unroll
-        for (int k = 0; k < 32; ++k) acc[k] = 0.0;
+        for (int k = 0; k < 2 * CH; ++k) acc[k] = 0.0;
         if (active) {
             // loads in groups of KG vectors, all issued before their products
             // (vector index clamped, the extra sums dropped), so a group's
             // loads are in flight together
-            constexpr int KG = (NV >= 4) ? 4 : 16;
+            constexpr int KG = (NV >= 4) ? 4 : CH;
 #pragma unroll
-            for (int k0 = 0; k0 < 16; k0 += KG) {
+            for (int k0 = 0; k0 < CH; k0 += KG) {
                 T u[KG][NV];
 #pragma unroll
                 for (int kk = 0; kk < KG; ++kk) {
@@ -247,7 +251,7 @@ __device__ __forceinline__ void op_dots2(const OpArgs<T> &a, bool active, unsign
                     }
                     const bool in = i0 + k0 + kk < nv;
                     acc[k0 + kk] = in ? sw_ : 0.0;
-                    acc[16 + k0 + kk] = in ? sx_ : 0.0;
+                    acc[CH + k0 + kk] = in ? sx_ : 0.0;
                 }
             }
         }
@@ -256,19 +260,24 @@ __device__ __forceinline__ void op_dots2(const OpArgs<T> &a, bool active, unsign
                 const T wt = (t + 1 < a.naug) ? sc * a.vtail[t + 1] : T(0);
                 const T xt = a.vtail[t];
 #pragma unroll
-                for (int k = 0; k < 16; ++k)
+                for (int k = 0; k < CH; ++k)
                     if (i0 + k < nv) {
                         const double u = (double)a.basis[(size_t)(i0 + k) * a.bstride + ntot + t];
                         acc[k] += u * (double)wt;
-                        acc[16 + k] += u * (double)xt;
+                        acc[CH + k] += u * (double)xt;
                     }
             }
         }
-        const double v = transpose_reduce32(acc);
-        if ((lane & 1) == 0) sw[wave][lane >> 1] = v;
+        if constexpr (CH == 16) {
+            const double v = transpose_reduce32(acc);
+            if ((lane & 1) == 0) sw[wave][lane >> 1] = v;
+        } else {
+            const double v = transpose_reduce16(acc);
+            if ((lane & 3) == 0) sw[wave][lane >> 2] = v;
+        }
         __syncthreads();
-        if (tid < 32 && i0 + (tid & 15) < nv) {
-            const int row = (tid < 16) ? i0 + tid : nv + i0 + (tid - 16);
+        if (tid < 2 * CH && i0 + (tid % CH) < nv) {
+            const int row = (tid < CH) ? i0 + tid : nv + i0 + (tid - CH);
             a.dpart[(size_t)row * a.dnb + tile] =
                 wsum(sw[0][tid], sw[1][tid], sw[2][tid], sw[3][tid], sw[NW > 4 ? 4 : 0][tid],
                      sw[NW > 5 ? 5 : 0][tid]);
@@ -590,7 +599,7 @@ __device__ __forceinline__ void euler_op_body(const OpArgs<T> &a, int tile, bool
 #pragma unroll
         for (int c = 0; c < 4; ++c) wv[c] = T(0);
     }
-    if (JVP && a.dots) op_dots2<T, 4>(a, active, idx, plane, u, wv, tile, first);
+    if (JVP && a.dots) op_dots2<T, 4, 4, 8>(a, active, idx, plane, u, wv, tile, first);
 }
 
 // ---- entropy viscosity (2D Euler) ---------------------------------------------
@@ -999,7 +1008,7 @@ __device__ __forceinline__ void euler3_op_body(const OpArgs<T> &a, int tile, boo
 #pragma unroll
         for (int c = 0; c < 5; ++c) wv[c] = T(0);
     }
-    if (JVP && a.dots) op_dots2<T, 5, S::NW>(a, active, idx, plane, u, wv, tile, first);
+    if (JVP && a.dots) op_dots2<T, 5, S::NW, 8>(a, active, idx, plane, u, wv, tile, first);
 }
 
 template <int P, typename T, bool JVP>

@@ -13,6 +13,7 @@ viscosity"), through the C ABI, against the oracle.
     1e-12 relative, and the adaptive run taking the oracle's decisions;
   * two steps of each scheme on the shear layer, the viscosity recomputed in
     each step from q^n and q^{n-1}, to 1e-12 relative at the state level;
+    several steps in one call bitwise equal to one call per step;
   * FP32 bulk: one EPI2 step within 1e-6 of the FP64 oracle.
 """
 import numpy as np
@@ -143,6 +144,28 @@ def test_steps_shear_layer(scheme):
         gm.entropy_viscosity(q, qp, dt, nu)
         want = om.entropy_viscosity(q_o, qp_o, dt)
         assert np.max(want) > 0 and maxrel(host(nu), want) < 1e-10
+
+
+@pytest.mark.parametrize("scheme", [B.EPI2, B.EPI3, B.EXPRB42])
+def test_integrate_equals_steps_with_viscosity(scheme):
+    # several steps in one call: bitwise the same as one call per step, each
+    # step's viscosity from its own q^n and q^{n-1}
+    nx, ny, p = 8, 8, 3
+    with B.Mesh(B.EULER2D, nx, p, ny=ny, ev_ce=1.0, ev_cmax=0.1, **DOM) as gm:
+        x, y = gm.nodes()
+        q0 = dev(inputs.shear_layer(x, y, seed=4).reshape(-1))
+        dt = 5.0 * gm.dx_min / gm.max_speed(q0)
+        opts = B.make_opts(1e-10, 10, 64)
+        qa, pa = q0.clone(), torch.empty_like(q0)
+        sa = B.make_stats()
+        for k in range(3):
+            gm.step(scheme, dt, qa, pa, k > 0, opts, sa)
+        qb, pb = q0.clone(), torch.empty_like(q0)
+        sb = B.make_stats()
+        gm.integrate(scheme, dt, 3, qb, pb, False, opts, sb)
+        assert torch.equal(qa, qb) and torch.equal(pa, pb)
+        da, db = B.stats_dict(sa), B.stats_dict(sb)
+        assert da["krylov_iters"] == db["krylov_iters"] and da["log"] == db["log"]
 
 
 def test_fp32_bulk_step():
