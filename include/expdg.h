@@ -253,8 +253,10 @@ int expdg_phi_krylov(expdg_mesh *m, const void *qref, double tau, int p,
 /* One step of size dt of scheme EXPDG_EPI2, EXPDG_EPI3, EXPDG_EXPRB32 or
  * EXPDG_EXPRB42 on the FP64 device state q (in/out).  EPI3 uses q_prev: when have_prev != 0
  * it holds q^{n-1} on entry; when have_prev == 0 the step is an EPI2 step.
- * If q_prev != NULL it receives q^n on return (for every scheme).  Returns
- * after completion. */
+ * With entropy viscosity (ev_ce > 0) every scheme uses it too: the step's
+ * viscosity comes from q and, when q_prev != NULL and have_prev != 0, from
+ * q_prev as q^{n-1} (otherwise from q alone).  If q_prev != NULL it receives
+ * q^n on return (for every scheme).  Returns after completion. */
 int expdg_step(expdg_mesh *m, int scheme, double dt, double *q, double *q_prev, int have_prev,
                const expdg_krylov_opts *o, expdg_krylov_stats *s, void *hip_stream);
 
