@@ -14,7 +14,9 @@ viscosity"), through the C ABI, against the oracle.
   * two steps of each scheme on the shear layer, the viscosity recomputed in
     each step from q^n and q^{n-1}, to 1e-12 relative at the state level;
     several steps in one call bitwise equal to one call per step;
-  * FP32 bulk: one EPI2 step within 1e-6 of the FP64 oracle.
+  * FP32 bulk: one EPI2 step within 1e-6 of the FP64 oracle;
+  * c_max = 0: the viscosity vanishes exactly and steps equal the inviscid
+    ones to 1e-12.
 """
 import numpy as np
 import pytest
@@ -55,7 +57,8 @@ def states(m, seed):
     return q, qp
 
 
-SHAPES = [(1, 1, 1), (1, 1, 6), (4, 3, 2), (3, 5, 3), (6, 4, 4), (5, 3, 5), (3, 4, 6), (7, 2, 1)]
+SHAPES = [(1, 1, 1), (1, 1, 6), (4, 3, 2), (3, 5, 3), (6, 4, 4), (5, 3, 5), (3, 4, 6), (7, 2, 1),
+          (5, 1, 3), (1, 4, 4)]
 
 
 @pytest.mark.parametrize("nx,ny,p", SHAPES)
@@ -181,6 +184,29 @@ def test_fp32_bulk_step():
         q = dev(q0)
         gm.step(B.EPI2, dt, q, None, False, B.make_opts(1e-7, 10, 64))
         assert rel(host(q), ref) < 1e-6, rel(host(q), ref)
+
+
+def test_zero_cap_equals_inviscid():
+    # c_max = 0: nu = min(nu_max, nu_E) = 0 everywhere (exactly), and steps
+    # equal the inviscid ones to rounding: the viscous kernel subtracts nu g =
+    # 0 exactly, but the compiler contracts products into the surrounding
+    # sums differently in the two kernels, so the last bits may differ
+    nx, ny, p = 6, 5, 3
+    with B.Mesh(B.EULER2D, nx, p, ny=ny, ev_ce=1.0, ev_cmax=0.0, **DOM) as ge, \
+            B.Mesh(B.EULER2D, nx, p, ny=ny, **DOM) as g0:
+        x, y = g0.nodes()
+        q0 = dev(inputs.shear_layer(x, y, seed=6).reshape(-1))
+        nu = torch.empty(ge.K * ge.Np, dtype=torch.float64, device=DEV)
+        ge.entropy_viscosity(q0, q0 * 1.001, 0.01, nu)
+        assert torch.count_nonzero(nu).item() == 0
+        dt = 5.0 * g0.dx_min / g0.max_speed(q0)
+        opts = B.make_opts(1e-10, 10, 64)
+        qa, qb = q0.clone(), q0.clone()
+        pa, pb = torch.empty_like(q0), torch.empty_like(q0)
+        for k in range(2):
+            ge.step(B.EPI3, dt, qa, pa, k > 0, opts)
+            g0.step(B.EPI3, dt, qb, pb, k > 0, opts)
+        assert rel(host(qa), host(qb)) < 1e-12, rel(host(qa), host(qb))
 
 
 def test_rejections():
