@@ -550,7 +550,7 @@ SERVED = dict(n_requests=2000, rate=200.0, seed=0, steps=20, tol=1e-10, m_min=10
                    "16..128, p 2..4, Courant 5), 20 EPI3 steps each, FP64, tol 1e-10")
 
 
-def run_served(args):
+def run_served(args, iop=0, compare=True):
     import numpy as np
     import torch
 
@@ -561,7 +561,7 @@ def run_served(args):
     t = time.time()
     mix = inputs.served_mix(n_requests=args.serve_requests, rate=w["rate"], seed=w["seed"],
                             steps=w["steps"])
-    items = serving.prepare(mix, tol=w["tol"], m_min=w["m_min"], m_max=w["m_max"])
+    items = serving.prepare(mix, tol=w["tol"], m_min=w["m_min"], m_max=w["m_max"], iop=iop)
     log(f"served: {len(items)} requests prepared in {time.time() - t:.1f}s")
     torch.zeros(1, device="cuda")
     srv = B.Server(hbm_budget=int(args.serve_budget_gib * (1 << 30)),
@@ -577,7 +577,7 @@ def run_served(args):
     srv.sync()
     st = srv.stats()
     srv.close()
-    log(f"served: {res['completed']} solves, {res['solves_per_s']:.1f}/s, "
+    log(f"served (iop {iop}): {res['completed']} solves, {res['solves_per_s']:.1f}/s, "
         f"p50 {res['latency_p50_s']:.2f}s p99 {res['latency_p99_s']:.2f}s")
     out = dict(
         workload=w["name"], requests=res["requests"], completed=res["completed"],
@@ -597,7 +597,7 @@ def run_served(args):
 
     # the first requests one after another through expdg_step
     K = min(args.serve_seq, len(items))
-    if K < 1:
+    if K < 1 or not compare:
         return out
     t = time.time()
     work = 0.0
@@ -841,6 +841,12 @@ def main():
         line["entropy_viscosity"] = run_ev(args)
     if not args.no_serve:
         line["served"] = run_served(args)
+        if not args.no_iop:
+            # the same mix with incomplete orthogonalization (L = 2) in every solve
+            si = run_served(args, iop=2, compare=False)
+            line["served"]["iop2"] = {k: si[k] for k in (
+                "completed", "solves_per_s", "latency_p50_s", "latency_p99_s",
+                "dof_stage_updates_per_s", "arnoldi_steps_per_tick")}
     line["cpu_baseline"] = None if args.no_cpu_baseline else run_cpu_baseline(args)
     print(json.dumps(line), flush=True)
 

@@ -163,7 +163,7 @@ typedef struct {
                  twice); L in 1..64: incomplete orthogonalization, each new
                  vector against the L most recent basis vectors only (one
                  pass, explicit norm), the IOP option of KIOPS (Section 2.3).
-                 Served solves always use 0. */
+                 Served solves take it from their request. */
 } expdg_krylov_opts;
 
 /* Statistics, accumulated over the call (zero them before the call).  If
@@ -346,6 +346,8 @@ typedef struct {
     double cfl;           /* used when dt <= 0 (must then be > 0) */
     double tol;           /* Krylov options as in expdg_krylov_opts (no forced schedule) */
     int m_min, m_max, check_every;
+    int iop;              /* 0: full orthogonalization; L in 1..64: incomplete (as in
+                             expdg_krylov_opts.iop) */
 } expdg_request;
 
 enum {

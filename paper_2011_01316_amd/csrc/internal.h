@@ -258,6 +258,8 @@ struct GsItem {
     double *x, *w;
     size_t stride, L, rpb;
     int nrb, k;
+    int k0, nv;          // the vectors u_k0 .. u_{k0+nv-1} the step orthogonalizes against
+    int iop;             // nonzero: incomplete orthogonalization (one pass, explicit norm)
     int nrb1;            // partials per row written by the linear operator (its blocks),
                          // or 0: a separate dot pass
     double *part, *S, *H, *coefA, *coefB;

@@ -489,8 +489,7 @@ struct IopFinish {
     int *flags;
 };
 
-__global__ __launch_bounds__(kFin2Threads) void iop_finish_kernel(const double *part, int nrb,
-                                                                  IopFinish f) {
+__device__ __forceinline__ void iop_finish_body(const double *part, int nrb, const IopFinish &f) {
     constexpr int NW = kFin2Threads / 64;
     __shared__ double sv[kPartRows];
     __shared__ double sw[NW];
@@ -553,6 +552,11 @@ __global__ __launch_bounds__(kFin2Threads) void iop_finish_kernel(const double *
         f.coefB[kScalW] = 1.0 / bet;
         f.coefB[kScalX] = hd / bet;
     }
+}
+
+__global__ __launch_bounds__(kFin2Threads) void iop_finish_kernel(const double *part, int nrb,
+                                                                  IopFinish f) {
+    iop_finish_body(part, nrb, f);
 }
 
 template <typename T>
@@ -894,24 +898,29 @@ __global__ __launch_bounds__(256) void gs_dots2_group(const GsItem *items, const
     const int it = group_item(bstart, n, blockIdx.x);
     const GsItem &g = items[it];
     const int local = blockIdx.x - bstart[it];
-    gs_dots2_body<double>(g.V, g.stride, g.k - 1, g.x, g.w, g.L, g.rpb, g.nrb, g.part,
-                          local % g.nrb, local / g.nrb);
+    gs_dots2_body<double>(g.V + (size_t)g.k0 * g.stride, g.stride, g.nv, g.x, g.w, g.L, g.rpb,
+                          g.nrb, g.part, local % g.nrb, local / g.nrb);
 }
 
 // One workgroup per item; nrb1 partials per row from the linear operator's
 // blocks, or (nrb1 = 0) nrb from the separate dot pass.
 __global__ __launch_bounds__(kFin2Threads) void dcgs_finish_group(const GsItem *items) {
     const GsItem &g = items[blockIdx.x];
-    dcgs_finish_body(g.part, g.nrb1 > 0 ? g.nrb1 : g.nrb,
-                     DcgsFinish{g.S, g.H, g.k, g.coefA, g.coefB, g.flags});
+    const int nrb = g.nrb1 > 0 ? g.nrb1 : g.nrb;
+    if (g.iop)
+        iop_finish_body(g.part, nrb,
+                        IopFinish{g.S, g.H, g.k, g.k0, g.nv, g.coefA, g.coefB, g.flags});
+    else
+        dcgs_finish_body(g.part, nrb, DcgsFinish{g.S, g.H, g.k, g.coefA, g.coefB, g.flags});
 }
 
 __global__ __launch_bounds__(256) void dcgs_update_group(const GsItem *items, const int *bstart,
                                                          int n) {
     const int it = group_item(bstart, n, blockIdx.x);
     const GsItem &g = items[it];
-    dcgs_update_body<double>(g.V, g.stride, g.k - 1, g.coefA, g.coefB, g.x, g.w, g.L, g.rpb,
-                             blockIdx.x - bstart[it], g.k > 1);
+    // incomplete orthogonalization leaves x as it is (only its scale is new)
+    dcgs_update_body<double>(g.V + (size_t)g.k0 * g.stride, g.stride, g.nv, g.coefA, g.coefB,
+                             g.x, g.w, g.L, g.rpb, blockIdx.x - bstart[it], g.k > 1 && !g.iop);
 }
 
 constexpr size_t kExpmLds = (size_t)4 * NMAX * LDA * sizeof(double);
@@ -1036,7 +1045,7 @@ void arnoldi_group_layout(const GsItem *items, int n, int *bstart, int *totals) 
     int t[kGroupLaunches] = {};
     for (int it = 0; it < n; ++it) {
         const GsItem &g = items[it];
-        const int nv = g.k - 1;
+        const int nv = g.nv;
         const int chunks = nv > 0 ? (nv + CH - 1) / CH : 1;
         const int blocks[kGroupLaunches] = {g.nrb1 > 0 ? 0 : g.nrb * chunks, g.nrb};
         for (int k = 0; k < kGroupLaunches; ++k) {

@@ -143,8 +143,6 @@ struct ServeExec {
     };
 
     hipStream_t stream() const;
-    // served solves use full orthogonalization (the server builds their
-    // options with iop = 0), so iop is always false here
     Await iterate(expdg_mesh *m, const OpArgs<double> &a, int k, int naug_nz, const CheckReq *cr,
                   Check *c, bool iop);
     Await check(expdg_mesh *m, const CheckReq &q, Check *c);
@@ -209,6 +207,7 @@ bool request_sizes(const expdg_request *r, size_t *ws, size_t *st, const char **
     if (r->m_min < 1 || r->m_max < r->m_min || r->m_max > d.m_max)
         return *why = "need 1 <= m_min <= m_max <= mesh.m_max", false;
     if (r->check_every < 1) return *why = "check_every must be >= 1", false;
+    if (r->iop < 0 || r->iop > kMaxM) return *why = "iop must be in 0..64", false;
     const Sizes sz = sizes_of(&d);
     *ws = Arena::round(sz.total);
     *st = Arena::round(sz.stride * 8) * 2;
@@ -254,7 +253,6 @@ hipStream_t ServeExec::stream() const { return sv->s; }
 ServeExec::Await ServeExec::iterate(expdg_mesh *m, const OpArgs<double> &a, int k, int naug_nz,
                                     const CheckReq *cr, Check *c, bool iop) {
     (void)naug_nz;
-    (void)iop;
     IterRec rec;
     rec.r = r;
     rec.a = a;
@@ -271,6 +269,9 @@ ServeExec::Await ServeExec::iterate(expdg_mesh *m, const OpArgs<double> &a, int 
     g.nrb = rp.nrb;
     g.nrb1 = a.dots ? a.dnb : 0;  // 0: a separate dot pass
     g.k = k;
+    g.nv = a.nv;
+    g.k0 = k - 1 - a.nv;
+    g.iop = iop ? 1 : 0;
     g.part = kd.part;
     g.S = kd.S;
     g.H = kd.H;
@@ -487,7 +488,7 @@ int admit(expdg_server *sv) {
         // asynchronously)
         HIPTRY(hipMemcpyAsync(r->q, r->q0.data(), r->mesh.n * 8, hipMemcpyHostToDevice, sv->s));
         r->opts = expdg_krylov_opts{r->rq.tol, r->rq.m_min, r->rq.m_max, r->rq.check_every,
-                                    nullptr, 0};
+                                    nullptr, 0, r->rq.iop};
         r->state = EXPDG_REQ_ACTIVE;
         r->t_admit = sv->now();
         r->x.sv = sv;

@@ -42,8 +42,9 @@ def node_coords(nx, ny, p, x0, x1, y0, y1, dim):
     return x.ravel(), y.ravel()
 
 
-def prepare(mix, tol=1e-10, m_min=10, m_max=64, check_every=1):
-    """Server requests and initial states for a request mix.
+def prepare(mix, tol=1e-10, m_min=10, m_max=64, check_every=1, iop=0):
+    """Server requests and initial states for a request mix (iop: the
+    orthogonalization window of every request, 0 = full).
 
     Returns a list of dicts: arrival (s), req (binding.Request), q0 (host
     float64), ndof, equation name, size and degree.
@@ -57,14 +58,15 @@ def prepare(mix, tol=1e-10, m_min=10, m_max=64, check_every=1):
             req = B.make_request(B.BURGERS1D, r["nx"], p, scheme=B.EPI3, nsteps=r["steps"],
                                  dt=r["dt"], tol=tol, m_min=m_min, m_max=m_max,
                                  check_every=check_every, x0=BURGERS_DOMAIN[0],
-                                 x1=BURGERS_DOMAIN[1])
+                                 x1=BURGERS_DOMAIN[1], iop=iop)
         else:
             x, y = node_coords(r["nx"], r["ny"], p, *EULER_DOMAIN, 2)
             q0 = inputs.vortex(x, y, beta=r["beta"], xc=r["xc"], yc=r["yc"]).ravel()
             req = B.make_request(B.EULER2D, r["nx"], p, ny=r["ny"], scheme=B.EPI3,
                                  nsteps=r["steps"], dt=0.0, cfl=r["cr"], tol=tol, m_min=m_min,
                                  m_max=m_max, check_every=check_every, x0=EULER_DOMAIN[0],
-                                 x1=EULER_DOMAIN[1], y0=EULER_DOMAIN[2], y1=EULER_DOMAIN[3])
+                                 x1=EULER_DOMAIN[1], y0=EULER_DOMAIN[2], y1=EULER_DOMAIN[3],
+                                 iop=iop)
         items.append(dict(arrival=r["arrival"], req=req, q0=np.ascontiguousarray(q0),
                           ndof=int(q0.size), equation=r["equation"], nx=r["nx"], p=p))
     return items

@@ -3,8 +3,9 @@
 A served solve runs the same controller and kernel bodies as expdg_step, so
 its final state must be bit-identical to the stand-alone step loop on its own
 mesh with the same options -- alone in the server, among other solves of
-other equations, sizes and degrees, under a small HBM budget that forces
-queueing, and next to solves that are cancelled.  One served solve is also
+other equations, sizes and degrees, with full or incomplete
+orthogonalization, under a small HBM budget that forces queueing, and next to
+solves that are cancelled.  One served solve is also
 compared with the oracle directly (FP64 tolerance as for expdg_step).
 """
 import math
@@ -62,7 +63,7 @@ def standalone(req, q0):
     q = torch.tensor(q0, dtype=torch.float64, device="cuda")
     qp = torch.zeros_like(q)
     dt = req.dt if req.dt > 0 else req.cfl * m.dx_min / m.max_speed(q)
-    o = B.make_opts(req.tol, req.m_min, req.m_max, req.check_every)
+    o = B.make_opts(req.tol, req.m_min, req.m_max, req.check_every, iop=req.iop)
     for k in range(req.nsteps):
         m.step(req.scheme, dt, q, qp if req.scheme == B.EPI3 else None, k > 0, o)
     torch.cuda.synchronize()
@@ -167,6 +168,28 @@ def test_mixed_batch_is_bitwise_each_stepper():
         assert st["check_items"] >= st["batched_checks"]
     for k, w in enumerate(want):
         np.testing.assert_array_equal(got[k][0], w, err_msg=f"case {k}")
+
+
+@pytest.mark.parametrize("window", [1, 2, 5])
+def test_incomplete_orthogonalization_is_bitwise_each_stepper(window):
+    # served solves with incomplete orthogonalization (a window of the most
+    # recent basis vectors) next to solves with full orthogonalization, in
+    # the same grouped launches
+    cases = mixed_cases() + viscous_cases_small()
+    for k, (r, _) in enumerate(cases):
+        r.iop = window if k % 3 != 2 else 0
+    want = [standalone(r, q0)[0] for r, q0 in cases]
+    with B.Server(hbm_budget=4 << 30, max_active=64) as srv:
+        got = serve_all(srv, cases)
+        srv.sync()
+        st = srv.stats()
+        assert st["arena_used"] == 0 and st["arnoldi_items"] > st["ticks"]
+    for k, w in enumerate(want):
+        np.testing.assert_array_equal(got[k][0], w, err_msg=f"case {k}")
+
+
+def viscous_cases_small():
+    return [viscous_case(40, 4), viscous_case(23, 3, beta=0.5, scheme=B.EPI2)]
 
 
 def test_small_budget_queues_and_stays_exact():

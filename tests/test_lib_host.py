@@ -138,6 +138,14 @@ def test_entropy_viscosity_validation():
     assert B.expdg_request_bytes(req) == 0
 
 
+def test_served_request_orthogonalization_window():
+    req = B.make_request(B.EULER2D, 8, 3, ny=8, nsteps=2, dt=1e-2, x1=10.0, y1=10.0, iop=2)
+    assert B.expdg_request_bytes(req) > 0
+    for bad in (-1, 65):
+        req.iop = bad
+        assert B.expdg_request_bytes(req) == 0, bad
+
+
 def test_served_requests_take_no_source():
     req = B.make_request(B.BURGERS1D, 40, 4, dt=1e-2, kappa=0.03, bc=B.BC_DIRICHLET)
     assert B.expdg_request_bytes(req) > 0
