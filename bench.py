@@ -323,6 +323,8 @@ def run_ev(args):
 
 
 def run_kh(args):
+    import math
+
     import numpy as np
     import torch
 
@@ -341,9 +343,8 @@ def run_kh(args):
     npts = m.K * m.Np
     m0 = [float(mass @ q0.cpu().numpy()[c * npts:(c + 1) * npts]) for c in range(4)]
     runs = {}
-    # both of the paper's steps, and the smaller one again with incomplete
-    # orthogonalization (L = 2)
-    for dt, iop in [(dt, 0) for dt in w["dts"]] + [(min(w["dts"]), 2)]:
+
+    def run_one(m, dt, iop, tag=""):
         nsteps = int(round(w["t_end"] / dt))
         q = q0.clone()
         qp = torch.empty_like(q)
@@ -366,7 +367,7 @@ def run_kh(args):
         secs = time.perf_counter() - t0
         d = B.stats_dict(st)
         paper_key = f"epi2_dt{dt:g}"
-        key = paper_key + ("_iop2" if iop else "")
+        key = paper_key + ("_iop2" if iop else "") + tag
         r = dict(dt=dt, iop=iop, steps=nsteps, steps_done=done, t_reached=round(done * dt, 3),
                  seconds=round(secs, 3), ms_per_step=round(secs / max(1, done) * 1e3, 4),
                  krylov_iters=d["krylov_iters"], substeps=d["substeps"], rejects=d["rejects"],
@@ -384,12 +385,24 @@ def run_kh(args):
                      max_nu_final=float(nu.max().item()),
                      mass_drift=max(abs(float(mass @ qh[c * npts:(c + 1) * npts]) - m0[c]) /
                                     max(1.0, abs(m0[c])) for c in range(4)))
-            log(f"KH EPI2 dt={dt} iop={iop}: {secs:.3f} s to t = 100 ({nsteps} steps, "
+            log(f"KH EPI2 dt={dt} iop={iop}{tag}: {secs:.3f} s to t = 100 ({nsteps} steps, "
                 f"{d['krylov_iters']} Krylov iterations)")
         else:
             r["diverged"] = failed
-            log(f"KH EPI2 dt={dt}: diverged after t = {done * dt:g} ({failed})")
+            log(f"KH EPI2 dt={dt}{tag}: diverged after t = {done * dt:g} ({failed})")
         runs[key] = r
+
+    # both of the paper's steps, and the smaller one again with incomplete
+    # orthogonalization (L = 2)
+    for dt, iop in [(dt, 0) for dt in w["dts"]] + [(min(w["dts"]), 2)]:
+        run_one(m, dt, iop)
+    # sensitivity of the larger step to the amount of viscosity: the same run
+    # with the cap constant c_max raised by sqrt(2)
+    ms = B.Mesh(B.EULER2D, w["nx"], w["p"], ny=w["ny"], x0=-5.0, x1=5.0, y0=0.0, y1=5.0,
+                m_max=w["m_max"], ev_ce=w["ce"], ev_cmax=w["cmax"] * math.sqrt(2.0))
+    run_one(ms, max(w["dts"]), 0, "_cmax_x1.414")
+    runs[f"epi2_dt{max(w['dts']):g}_cmax_x1.414"]["note"] = "c_max = 0.1 sqrt(2) (not the paper's)"
+    ms.close()
     m.close()
     return dict(workload=w["name"], ndof=m.n, runs=runs, paper_seconds=KH_PAPER_SECONDS)
 
