@@ -291,10 +291,11 @@ def run_euler3d(args):
     pr = {B.KERNEL_CLASSES[c]: B.expdg_profile_read(m.handle, c) for c in B.KERNEL_CLASSES}
     for c in B.KERNEL_CLASSES:
         B.expdg_profile_enable(m.handle, c, False)
-    out["linear_operator_roofline"] = roof(pr["linear_operator"], "linear_operator",
-                                           "euler3_op<6, double, true>")
-    out["residual_roofline"] = roof(pr["residual"], "residual", "euler3_op<6, double, false>")
-    out["gs_update_roofline"] = roof(pr["gs_update"], "gs_update", B.KERNEL_SYMBOLS["gs_update"])
+    wl = "euler3d_80x80x8_p6"
+    for cls, sym in (("linear_operator", "euler3_op<6, double, true>"),
+                     ("residual", "euler3_op<6, double, false>"),
+                     ("gs_update", B.KERNEL_SYMBOLS["gs_update"])):
+        out[cls + "_roofline"] = roof(pr[cls], cls, sym, measured_traffic(sym, wl))
     m.close()
     return out
 
