@@ -843,9 +843,12 @@ def main():
                                    l2_rel_diff_vs_fp64=b7["l2_rel_diff_vs_fp64"]),
             fp32_speedup=round(b32["value"] / b64["value"], 3),
             fp32_tol1e_7_step_speedup=round(b64["ms_per_step"] / b7["ms_per_step"], 3),
-            linear_operator_roofline=roof(pb["linear_operator"], "linear_operator",
-                                          "euler_op<3, double, true, false>"),
-            gs_update_roofline=roof(pb["gs_update"], "gs_update", B.KERNEL_SYMBOLS["gs_update"]),
+            linear_operator_roofline=roof(
+                pb["linear_operator"], "linear_operator", "euler_op<3, double, true, false>",
+                measured_traffic("euler_op<3, double, true, false>", "vortex256_p3")),
+            gs_update_roofline=roof(pb["gs_update"], "gs_update", B.KERNEL_SYMBOLS["gs_update"],
+                                    measured_traffic(B.KERNEL_SYMBOLS["gs_update"],
+                                                     "vortex256_p3")),
             gs_dots_roofline=roof(pb["gs_dots"], "gs_dots", B.KERNEL_SYMBOLS["gs_dots"]))
     if not args.no_viscous:
         line["viscous_burgers"] = run_viscous(args)
