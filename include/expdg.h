@@ -294,7 +294,9 @@ enum {
     EXPDG_K_GS_FINISH = 7,      /* fixed-order sums of the block partials (step finish) */
     EXPDG_K_EV_VISC = 8,        /* entropy viscosity: element viscosity and its nodal
                                    reconstruction (two launches per evaluation) */
-    EXPDG_K_NCLASSES = 9
+    EXPDG_K_GS_FOLD = 9,        /* fold of long partial rows before the finish (operators of
+                                   more than 1024 blocks) */
+    EXPDG_K_NCLASSES = 10
 };
 
 /* Accumulated timing of one kernel class: launches, summed event-measured

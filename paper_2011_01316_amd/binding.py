@@ -92,9 +92,11 @@ REQ_QUEUED, REQ_ACTIVE, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
 K_RESIDUAL, K_LINEAR, K_GS_DOTS, K_SMALLEXPM, K_COMBINE = 0, 1, 2, 3, 4
 K_GS_UPDATE, K_GS_NORM, K_GS_FINISH = 5, 6, 7
 K_EV_VISC = 8
+K_GS_FOLD = 9
 KERNEL_CLASSES = {K_RESIDUAL: "residual", K_LINEAR: "linear_operator", K_GS_DOTS: "gs_dots",
                   K_SMALLEXPM: "small_expm", K_COMBINE: "combine", K_GS_UPDATE: "gs_update",
-                  K_GS_NORM: "gs_norm", K_GS_FINISH: "gs_finish", K_EV_VISC: "ev_visc"}
+                  K_GS_NORM: "gs_norm", K_GS_FINISH: "gs_finish", K_EV_VISC: "ev_visc",
+                  K_GS_FOLD: "gs_fold"}
 # kernel symbol of each class, as rocprofv3 names it
 KERNEL_SYMBOLS = {"residual": "euler_op<4, double, false, false>",
                   "linear_operator": "euler_op<4, double, true, false>",
@@ -102,7 +104,8 @@ KERNEL_SYMBOLS = {"residual": "euler_op<4, double, false, false>",
                   "combine": "combine_kernel<double>", "gs_update": "dcgs_update_kernel<double>",
                   "gs_norm": "gs_norm_kernel<double>",
                   "gs_finish": "dcgs_finish_kernel / finish_norm_kernel",
-                  "ev_visc": "ev_element_kernel<4> / ev_smooth_kernel<4, double>"}
+                  "ev_visc": "ev_element_kernel<4> / ev_smooth_kernel<4, double>",
+                  "gs_fold": "fold_kernel"}
 
 # name -> (restype, argtypes)
 _SIGS = {

@@ -221,6 +221,7 @@ size_t layout(expdg_mesh *m, const expdg_mesh_desc *d, size_t stride, int eb, ch
     // fused into the linear operator (one partial per operator block)
     const size_t npart = std::max<size_t>(kRedBlocks, dg_blocks(d->equation, d->p, K));
     take(m->kd.part, npart * kPartRows * 8);
+    take(m->kd.fold, (size_t)std::max(1, fold_chunks((int)npart)) * kPartRows * 8);
     take(m->kd.res, 64 * 8);
     take(m->kd.flags, 16);
     take(m->slots, (size_t)kCheckSlots * kSlotSize * 8);
@@ -644,15 +645,24 @@ struct DirectExec {
             HIPTRY(launch_gs_dots2<T>(basis, stride, nv, x, w, L, rp, kd.part, s));
             TRY(prof_end(m, EXPDG_K_GS_DOTS, (double)(nv + 2) * L * eb));
         }
-        const int nrb = fused ? a.dnb : rp.nrb;
+        int nrb = fused ? a.dnb : rp.nrb;
+        const double *part = kd.part;
+        const int rows = 2 * nv + 2;
+        if (fold_chunks(nrb) > 0) {
+            // long partial rows (one per block of a large operator launch)
+            TRY(prof_begin(m, EXPDG_K_GS_FOLD));
+            HIPTRY(launch_fold(kd.part, nrb, rows, kd.fold, s));
+            TRY(prof_end(m, EXPDG_K_GS_FOLD, 8.0 * rows * (nrb + fold_chunks(nrb))));
+            part = kd.fold;
+            nrb = fold_chunks(nrb);
+        }
         TRY(prof_begin(m, EXPDG_K_GS_FINISH));
         if (iop)
-            HIPTRY(launch_iop_finish(kd.part, nrb, k, k - 1 - nv, nv, kd.S, kd.H, kd.coefA,
-                                     kd.coefB, kd.flags, s));
+            HIPTRY(launch_iop_finish(part, nrb, k, k - 1 - nv, nv, kd.S, kd.H, kd.coefA, kd.coefB,
+                                     kd.flags, s));
         else
-            HIPTRY(launch_dcgs_finish(kd.part, nrb, k, kd.S, kd.H, kd.coefA, kd.coefB, kd.flags,
-                                      s));
-        TRY(prof_end(m, EXPDG_K_GS_FINISH, 8.0 * nrb * (2 * nv + 2)));
+            HIPTRY(launch_dcgs_finish(part, nrb, k, kd.S, kd.H, kd.coefA, kd.coefB, kd.flags, s));
+        TRY(prof_end(m, EXPDG_K_GS_FINISH, 8.0 * nrb * rows));
         // the check needs H and S only: it starts while the update sweep runs
         if (cr) TRY(mark_check(m, *cr, c));
         TRY(prof_begin(m, EXPDG_K_GS_UPDATE));

@@ -173,6 +173,7 @@ struct KrylovDev {
     double *coefA;   // kMaxM+1: x -= sum_i coefA[i] u_i
     double *coefB;   // kMaxM+3: w <- coefB[kScalW] w - coefB[kScalX] x - sum_i coefB[i] u_i
     double *part;    // partials: kPartRows rows of max(kRedBlocks, operator blocks)
+    double *fold;    // folded partials: kPartRows rows of fold_chunks(operator blocks)
     double *res;     // res[0] = beta
     int *flags;      // [0] first breakdown dimension (0 = none), [1] first non-finite one
 };
@@ -209,6 +210,17 @@ template <typename T>
 hipError_t launch_dcgs_update(const T *V, size_t stride, int nv, const double *coefA,
                               const double *coefB, T *x, T *w, size_t L, const RowPartition &rp,
                               hipStream_t s, bool write_x = true);
+// Partial rows longer than kFoldAbove (the dot pass fused into the operator
+// of a large mesh writes one partial per operator block) are first folded by a
+// many-block launch: out[r * nc + c] = the fixed-order sum of chunk c
+// (kFoldChunk consecutive partials) of row r, nc = fold_chunks(nrb); the
+// finish then sums nc values per row instead of nrb.
+constexpr int kFoldAbove = 1024;
+constexpr int kFoldChunk = 1024;
+inline int fold_chunks(int nrb) {
+    return nrb > kFoldAbove ? (nrb + kFoldChunk - 1) / kFoldChunk : 0;
+}
+hipError_t launch_fold(const double *part, int nrb, int rows, double *out, hipStream_t s);
 // Incomplete orthogonalization (window of L vectors), finish of step k: x =
 // u_{k-1} (stored unnormalised), w = A x, and the nw = min(k-1, L-1) window
 // vectors u_{k0}, ..., u_{k-2} (k0 = k-1-nw) with block partials in the rows
@@ -262,13 +274,14 @@ struct GsItem {
     int iop;             // nonzero: incomplete orthogonalization (one pass, explicit norm)
     int nrb1;            // partials per row written by the linear operator (its blocks),
                          // or 0: a separate dot pass
-    double *part, *S, *H, *coefA, *coefB;
+    int nfold;           // fold_chunks(nrb1): > 0 when the partials are folded first
+    double *part, *fold, *S, *H, *coefA, *coefB;
     int *flags;
 };
 // Block ranges of a grouped Arnoldi step: the dot pass (items whose linear
-// operator does not carry it) and the update sweep.  (The finish runs one
-// block per item.)
-constexpr int kGroupLaunches = 2;
+// operator does not carry it), the fold of long partial rows (items with
+// nfold > 0) and the update sweep.  (The finish runs one block per item.)
+constexpr int kGroupLaunches = 3;
 // Host: block ranges bstart[k*(n+1) + it] of launch k and the totals.
 void arnoldi_group_layout(const GsItem *items, int n, int *bstart, int *totals);
 // Device copies of items and bstart; totals from arnoldi_group_layout.

@@ -275,6 +275,34 @@ __device__ __forceinline__ void fin_row_sums(const double *part, int rows, int n
     if (j == 0 && r < rows) sv[r] = s;
 }
 
+// Fold of long partial rows (see kFoldAbove): block (c, r) of 256 threads
+// sums chunk c of row r; thread t adds its four partials c kFoldChunk + t +
+// 256 u in ascending u, then the wave butterfly, then the four wave sums as
+// (w0 + w1) + (w2 + w3).  The order is fixed, so results repeat bitwise.
+__device__ __forceinline__ void fold_body(const double *part, int nrb, double *out, int nc,
+                                          int r, int c) {
+    static_assert(kFoldChunk == 4 * 256, "four partials per thread");
+    __shared__ double sw[4];
+    const int tid = threadIdx.x;
+    const double *pr = part + (size_t)r * nrb;
+    const int b0 = c * kFoldChunk + tid;
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = pr[min(b0 + u * 256, nrb - 1)];
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s += (b0 + u * 256 < nrb) ? v[u] : 0.0;
+    s = wave_sum(s);
+    if ((tid & 63) == 0) sw[tid >> 6] = s;
+    __syncthreads();
+    if (tid == 0) out[(size_t)r * nc + c] = (sw[0] + sw[1]) + (sw[2] + sw[3]);
+}
+
+__global__ __launch_bounds__(256) void fold_kernel(const double *part, int nrb, double *out,
+                                                   int nc) {
+    fold_body(part, nrb, out, nc, blockIdx.y, blockIdx.x);
+}
+
 struct DcgsFinish {
     double *S, *H;
     int k;
@@ -902,16 +930,26 @@ __global__ __launch_bounds__(256) void gs_dots2_group(const GsItem *items, const
                           g.nrb, g.part, local % g.nrb, local / g.nrb);
 }
 
+// Fold of the items with nfold > 0: item it owns (2 nv + 2) nfold blocks,
+// block (r, c) of the item folding chunk c of row r as fold_kernel does.
+__global__ __launch_bounds__(256) void fold_group(const GsItem *items, const int *bstart, int n) {
+    const int it = group_item(bstart, n, blockIdx.x);
+    const GsItem &g = items[it];
+    const int local = blockIdx.x - bstart[it];
+    fold_body(g.part, g.nrb1, g.fold, g.nfold, local / g.nfold, local % g.nfold);
+}
+
 // One workgroup per item; nrb1 partials per row from the linear operator's
-// blocks, or (nrb1 = 0) nrb from the separate dot pass.
+// blocks (nfold per row once folded), or (nrb1 = 0) nrb from the separate dot
+// pass.
 __global__ __launch_bounds__(kFin2Threads) void dcgs_finish_group(const GsItem *items) {
     const GsItem &g = items[blockIdx.x];
-    const int nrb = g.nrb1 > 0 ? g.nrb1 : g.nrb;
+    const int nrb = g.nfold > 0 ? g.nfold : (g.nrb1 > 0 ? g.nrb1 : g.nrb);
+    const double *part = g.nfold > 0 ? g.fold : g.part;
     if (g.iop)
-        iop_finish_body(g.part, nrb,
-                        IopFinish{g.S, g.H, g.k, g.k0, g.nv, g.coefA, g.coefB, g.flags});
+        iop_finish_body(part, nrb, IopFinish{g.S, g.H, g.k, g.k0, g.nv, g.coefA, g.coefB, g.flags});
     else
-        dcgs_finish_body(g.part, nrb, DcgsFinish{g.S, g.H, g.k, g.coefA, g.coefB, g.flags});
+        dcgs_finish_body(part, nrb, DcgsFinish{g.S, g.H, g.k, g.coefA, g.coefB, g.flags});
 }
 
 __global__ __launch_bounds__(256) void dcgs_update_group(const GsItem *items, const int *bstart,
@@ -959,6 +997,12 @@ hipError_t launch_gs_dots2(const T *V, size_t stride, int nv, const T *x, const 
     const dim3 grid(rp.nrb, nv > 0 ? (nv + CH - 1) / CH : 1);
     return launch_kernel(gs_dots2_kernel<T>, grid, dim3(256), 0, s, V, stride, nv, x, w, L,
                          rp.rpb, rp.nrb, part);
+}
+
+hipError_t launch_fold(const double *part, int nrb, int rows, double *out, hipStream_t s) {
+    const int nc = fold_chunks(nrb);
+    if (nc < 1 || rows < 1 || rows > kPartRows) return hipErrorInvalidValue;
+    return launch_kernel(fold_kernel, dim3(nc, rows), dim3(256), 0, s, part, nrb, out, nc);
 }
 
 hipError_t launch_dcgs_finish(const double *part, int nrb, int k, double *S, double *H,
@@ -1047,7 +1091,8 @@ void arnoldi_group_layout(const GsItem *items, int n, int *bstart, int *totals) 
         const GsItem &g = items[it];
         const int nv = g.nv;
         const int chunks = nv > 0 ? (nv + CH - 1) / CH : 1;
-        const int blocks[kGroupLaunches] = {g.nrb1 > 0 ? 0 : g.nrb * chunks, g.nrb};
+        const int blocks[kGroupLaunches] = {g.nrb1 > 0 ? 0 : g.nrb * chunks,
+                                            g.nfold > 0 ? (2 * nv + 2) * g.nfold : 0, g.nrb};
         for (int k = 0; k < kGroupLaunches; ++k) {
             bstart[k * (n + 1) + it] = t[k];
             t[k] += blocks[k];
@@ -1070,9 +1115,14 @@ hipError_t launch_arnoldi_group(const GsItem *items, const int *bstart, const in
         e = launch_kernel(gs_dots2_group, dim3(totals[0]), dim3(256), 0, s, items, b[0], n);
         if (e != hipSuccess) return e;
     }
+    // fold of the long partial rows of large meshes
+    if (totals[1] > 0) {
+        e = launch_kernel(fold_group, dim3(totals[1]), dim3(256), 0, s, items, b[1], n);
+        if (e != hipSuccess) return e;
+    }
     e = launch_kernel(dcgs_finish_group, dim3(n), dim3(kFin2Threads), 0, s, items);
     if (e != hipSuccess) return e;
-    return launch_kernel(dcgs_update_group, dim3(totals[1]), dim3(256), 0, s, items, b[1], n);
+    return launch_kernel(dcgs_update_group, dim3(totals[2]), dim3(256), 0, s, items, b[2], n);
 }
 
 hipError_t launch_dense_expm(const double *A, int n, double *E, hipStream_t s) {

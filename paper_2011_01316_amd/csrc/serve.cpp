@@ -268,6 +268,8 @@ ServeExec::Await ServeExec::iterate(expdg_mesh *m, const OpArgs<double> &a, int 
     g.rpb = rp.rpb;
     g.nrb = rp.nrb;
     g.nrb1 = a.dots ? a.dnb : 0;  // 0: a separate dot pass
+    g.nfold = fold_chunks(g.nrb1);
+    g.fold = kd.fold;
     g.k = k;
     g.nv = a.nv;
     g.k0 = k - 1 - a.nv;

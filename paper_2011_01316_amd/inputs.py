@@ -159,6 +159,22 @@ def random_vector(n: int, seed: int, scale: float = 1.0) -> np.ndarray:
     return scale * rng.uniform(-1.0, 1.0, n)
 
 
+def bloch_mode_plus_noise(K: int, p: int, wavenumber: int, eps: float, seed: int) -> np.ndarray:
+    """A 1D nodal vector (K elements of p+1 nodes) of the form
+    Re(exp(2 pi i k e / K) phi_i) with random complex phi, scaled to unit
+    length, plus eps times a random unit vector.  On a periodic mesh with a
+    constant reference state every element applies the same operator, so the
+    first part spans an invariant subspace of dimension 2(p+1) of the linear
+    operator (a nearly invariant one for small eps)."""
+    rng = np.random.default_rng(seed)
+    phi = rng.standard_normal(p + 1) + 1j * rng.standard_normal(p + 1)
+    e = np.arange(K)
+    base = (np.exp(2j * math.pi * wavenumber * e / K)[:, None] * phi[None, :]).real.reshape(-1)
+    base /= np.linalg.norm(base)
+    r = rng.standard_normal(K * (p + 1))
+    return base + eps * r / np.linalg.norm(r)
+
+
 def served_mix(n_requests: int = 2000, rate: float = 200.0, seed: int = 0,
                burgers_k=(32, 4096), burgers_p=(1, 4), euler_n=(16, 128), euler_p=(2, 4),
                steps: int = 20):

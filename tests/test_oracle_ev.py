@@ -170,3 +170,87 @@ def test_steps_with_viscosity_conserve_mass():
     for _ in range(3):
         q2, qp2 = m2.step(oracle.EPI2, dt, q2, qp2, tol=1e-10, m_min=10, m_max=64)
     assert np.linalg.norm(q - q2) > 1e-8 * np.linalg.norm(q)
+
+
+# ---- nu_E against the paper's definitions written out with numpy -------------
+from tests import _textbook as T  # noqa: E402
+
+BOX = (0.0, 2.0, 0.0, 1.0)  # hx != hy: h = sqrt(hx^2 + hy^2)/p is neither hx/p nor hy/p
+
+
+def node_xy(nx, ny, p, box):
+    """Node coordinates in the library's layout from the textbook LGL nodes."""
+    xi = T.lgl_textbook(p)[0]
+    x0, x1, y0, y1 = box
+    hx, hy = (x1 - x0) / nx, (y1 - y0) / ny
+    ex = np.arange(nx)[None, :, None, None]
+    ey = np.arange(ny)[:, None, None, None]
+    X = x0 + hx * (ex + 0.5 * (xi[None, None, None, :] + 1.0)) + 0.0 * ey
+    Y = y0 + hy * (ey + 0.5 * (xi[None, None, :, None] + 1.0)) + 0.0 * ex
+    return np.broadcast_to(X, (ny, nx, p + 1, p + 1)).reshape(-1), \
+        np.broadcast_to(Y, (ny, nx, p + 1, p + 1)).reshape(-1)
+
+
+def conservative(rho, u, v, pr):
+    return np.concatenate([rho, rho * u, rho * v, pr / (GAMMA - 1.0) + 0.5 * rho * (u * u + v * v)])
+
+
+def test_nu_E_polynomial_entropy_closed_form():
+    """rho = 1, constant velocity (u0, v0), p = exp(s) with s quadratic: S =
+    s/(gamma-1) and u S are polynomials of degree 2 <= p, so the nodal
+    divergence is exact and Res has a closed form.  The periodic seams make
+    [[u S . n]] nonzero on the boundary elements (the jump branch of the max)
+    and zero inside (the residual branch)."""
+    nx, ny, p, dt = 6, 4, 3, 0.1
+    u0, v0, gm1 = 0.3, -0.2, GAMMA - 1.0
+    x, y = node_xy(nx, ny, p, BOX)
+    s = 0.1 + 0.2 * x + 0.3 * y * y
+    s_prev = s - dt * 0.01 * (1.0 + x)
+    one = np.ones_like(x)
+    q = conservative(one, u0 * one, v0 * one, np.exp(s))
+    qp = conservative(one, u0 * one, v0 * one, np.exp(s_prev))
+    res_exact = (0.01 * (1.0 + x) + 0.5 * (u0 * (0.2 + 0.2 - 0.01 * dt) + 2.0 * v0 * 0.6 * y)) / gm1
+    nu_tb, parts = T.entropy_viscosity_2d(q, qp, dt, nx, ny, p, BOX, 1.0, 1e9, parts=True)
+    assert np.max(np.abs(parts["res"].reshape(-1) - res_exact)) <= 1e-12 * np.max(np.abs(res_exact))
+    # both branches of max(|Res|, |[[uS.n]]|/h) are taken
+    jump_wins = parts["jmax"] / parts["h"] > parts["rmax"]
+    assert jump_wins[0, 0] and not jump_wins[1, 2] and 0 < jump_wins.sum() < nx * ny
+    m = mesh(nx, ny, p, x0=BOX[0], x1=BOX[1], y0=BOX[2], y1=BOX[3], ev_ce=1.0, ev_cmax=1e9)
+    ox, oy = m.nodes()
+    assert np.max(np.abs(ox - x)) <= 1e-14 and np.max(np.abs(oy - y)) <= 1e-14
+    nu = m.entropy_viscosity(q, qp, dt)
+    assert np.max(np.abs(nu - nu_tb)) <= 1e-12 * np.max(nu_tb), np.max(np.abs(nu - nu_tb))
+
+
+@pytest.mark.parametrize("ce,cmax", [(0.05, 1e9), (0.5, 0.1)])
+def test_nu_E_smooth_state_with_element_jumps(ce, cmax):
+    """A smooth non-isentropic state with a per-element pressure offset
+    (nonzero face jumps everywhere), the previous state shifted in phase:
+    the oracle's viscosity against the definitions written out with numpy,
+    with nu_E alone (c_max large) and with c_E = 0.5, c_max = 0.1 (the min
+    takes both branches; so does the max inside nu_E)."""
+    nx, ny, p, dt = 5, 4, 4, 0.05
+    x, y = node_xy(nx, ny, p, BOX)
+    g = np.random.default_rng(11)
+    off = np.repeat(g.uniform(-1.0, 1.0, nx * ny), (p + 1) ** 2)
+
+    def state(ph):
+        rho = 1.0 + 0.2 * np.sin(math.pi * (x + ph)) * np.cos(2 * math.pi * y)
+        u = 0.3 + 0.1 * np.cos(2 * math.pi * (y - ph))
+        v = 0.1 * np.sin(math.pi * x)
+        pr = 1.0 + 0.1 * np.cos(math.pi * x + 2 * math.pi * (y + ph)) + 0.3 * off
+        return conservative(rho, u, v, pr)
+
+    q, qp = state(0.0), state(0.05)
+    nu_tb, parts = T.entropy_viscosity_2d(q, qp, dt, nx, ny, p, BOX, ce, cmax, parts=True)
+    m = mesh(nx, ny, p, x0=BOX[0], x1=BOX[1], y0=BOX[2], y1=BOX[3], ev_ce=ce, ev_cmax=cmax)
+    nu = m.entropy_viscosity(q, qp, dt)
+    assert np.max(np.abs(nu - nu_tb)) <= 1e-12 * np.max(nu_tb), np.max(np.abs(nu - nu_tb))
+    nu_E = ce * parts["h"] ** 2 * np.maximum(parts["rmax"], parts["jmax"] / parts["h"])
+    jump_wins = parts["jmax"] / parts["h"] > parts["rmax"]
+    assert 0 < jump_wins.sum() < nx * ny, jump_wins.sum()
+    if cmax > 1.0:
+        assert np.all(nu_E < cmax * parts["h"] * parts["lam"])
+    else:
+        capped = cmax * parts["h"] * parts["lam"] < nu_E
+        assert 0 < capped.sum() < nx * ny, capped.sum()

@@ -6,7 +6,9 @@ flipped dissipation sign, min instead of max in the wave speed, a wrong
 Jacobian entry, a wrong lifting factor, a dropped pressure term, a wrong Pade
 coefficient, a broken augmented shift or scaling, a wrong stepper
 coefficient, a wrong quadrature weight, a wrong entropy-flux coefficient, a
-flipped LDG switch, a wrong Dirichlet trace.
+flipped LDG switch, a wrong Dirichlet trace, and in the entropy viscosity a
+dropped half on the mean divergence, h instead of h^2, a missing 1/h on the
+face jump and a wrong element size.
 """
 import os
 import shutil
@@ -58,6 +60,17 @@ MUTATIONS = {
                      lambda: e3.test_axis_permutation(1)),
     "ev_face_flux": ("dg.cpp", "(0.5 * (fm + fp) - fm)", "(0.5 * (fm - fp) - fm)",
                      lambda: ev.test_diffusion_symmetric_negative(3)),
+    "ev_half_divergence": ("dg.cpp", "0.5 * (div[0] + div[1])", "(div[0] + div[1])",
+                           lambda: ev.test_nu_E_polynomial_entropy_closed_form()),
+    "ev_h_squared": ("dg.cpp", "g.ev_ce * he * he * std::fmax(rmax, jmax / he)",
+                     "g.ev_ce * he * std::fmax(rmax, jmax / he)",
+                     lambda: ev.test_nu_E_smooth_state_with_element_jumps(0.05, 1e9)),
+    "ev_jump_over_h": ("dg.cpp", "g.ev_ce * he * he * std::fmax(rmax, jmax / he)",
+                       "g.ev_ce * he * he * std::fmax(rmax, jmax)",
+                       lambda: ev.test_nu_E_polynomial_entropy_closed_form()),
+    "ev_h_circumradius": ("dg.cpp", "std::sqrt(g.hx * g.hx + g.hy * g.hy) / p",
+                          "std::fmax(g.hx, g.hy) / p",
+                          lambda: ev.test_nu_E_smooth_state_with_element_jumps(0.05, 1e9)),
     "iop_window": ("krylov.cpp", "std::max(0, j - iop)", "std::max(0, j - iop - 1)",
                    lambda: iop.test_arnoldi_relation_and_band(2)),
     "lgl_weight": ("refelem.cpp", "w[i] = 2.0 / (p * (p + 1.0) * P * P);",
