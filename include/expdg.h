@@ -232,6 +232,26 @@ int expdg_rhs(expdg_mesh *m, const void *q, void *r, void *hip_stream);
  * ndof bulk-type elements; v and w must not alias. */
 int expdg_jvp(expdg_mesh *m, const void *qref, const void *v, void *w, void *hip_stream);
 
+/* Allocation-free linear operator, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): w = L(qref) v exactly as expdg_jvp computes it on a mesh
+ * created from *desc (bitwise the same result), without a mesh handle.  The
+ * frozen fields of the Euler operators (velocities, enthalpy and face wave
+ * speeds of qref) are kept in a static device array of
+ * EXPDG_NOALLOC_SCRATCH_MIB MiB that every GPU the library runs on holds until
+ * the process ends; meshes whose frozen fields need more are rejected with
+ * EXPDG_EINVAL (in FP64 about 0.85 * ndof * 8 bytes at p = 4: up to roughly
+ * 9.8 million DOF).  The description is validated as for expdg_mesh_create
+ * (m_max is not used); entropy viscosity (ev_ce > 0) needs a mesh and is
+ * rejected.  The call allocates nothing: no hipMalloc, no hipFree, no events
+ * or streams.  Asynchronous on hip_stream.  All calls on one GPU share its
+ * scratch array, so calls that overlap on one GPU (other streams, other host
+ * threads) race; the array keeps the last call's contents, and nothing in it
+ * needs to start at zero (each call writes the fields before reading them). */
+enum { EXPDG_NOALLOC_SCRATCH_MIB = 64 };
+int expdg_jvp_noalloc(const expdg_mesh_desc *desc, const void *qref, const void *v, void *w,
+                      void *hip_stream);
+
 /* Largest wave speed max(|u|) or max(|u.n| + a) over the nodes of q
  * (device, FP64 state) into *cmax (host); synchronous.  Used for the CFL
  * time step dt = Cr dx_min / c (Courant number of Section 5). */

@@ -121,6 +121,8 @@ _SIGS = {
     "expdg_lgl": (C.c_int, [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "expdg_rhs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "expdg_jvp": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "expdg_jvp_noalloc": (C.c_int, [C.POINTER(MeshDesc), C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_void_p]),
     "expdg_max_speed": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.c_void_p]),
     "expdg_phi_krylov": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_int,
                                    C.POINTER(C.c_void_p), C.c_void_p, C.POINTER(KrylovOpts),
@@ -238,6 +240,10 @@ def expdg_rhs(handle, q, r, stream=None):
 
 def expdg_jvp(handle, qref, v, w, stream=None):
     _check(lib().expdg_jvp(handle, _ptr(qref), _ptr(v), _ptr(w), _stream(stream)))
+
+
+def expdg_jvp_noalloc(desc: MeshDesc, qref, v, w, stream=None):
+    _check(lib().expdg_jvp_noalloc(C.byref(desc), _ptr(qref), _ptr(v), _ptr(w), _stream(stream)))
 
 
 def expdg_max_speed(handle, q, stream=None) -> float:

@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -101,7 +102,7 @@ int lgl_tables(int p, double *xi, double *w, double *D) {
         }
         xi[i] = x;
     }
-    std::vector<double> Pv(n1);
+    double Pv[kMaxP + 1];
     for (int i = 0; i <= p; ++i) {
         double P, dP, Pm, dPm;
         legendre_pd(p, xi[i], &P, &dP, &Pm, &dPm);
@@ -537,6 +538,77 @@ extern "C" int expdg_max_speed(expdg_mesh *m, const double *q, double *cmax, voi
     if (!std::isfinite(c)) return fail(EXPDG_ENONFINITE, "non-finite wave speed");
     *cmax = c;
     return EXPDG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free linear operator.  The only device memory the linear operator
+// needs beyond its inputs and output is the frozen-field buffer of the 2D and
+// 3D Euler operators; expdg_jvp_noalloc keeps it in a file-scope device array
+// (one copy per GPU, resident until the process ends) instead of a mesh
+// workspace, so it needs no mesh handle and allocates nothing.
+
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)EXPDG_NOALLOC_SCRATCH_MIB << 20;
+constexpr int kScratchDevices = 64;
+
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kScratchDevices] = {};
+
+// Device address of the current device's copy of scratch, looked up once per
+// device (with that device current) and kept.  The array's host-side name is
+// only a stand-in: kernels get this address.
+int scratch_address(int device, void **out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(EXPDG_EDEVICE, "hipGetSymbolAddress(scratch) on device %d failed: %s",
+                        device, hipGetErrorString(e));
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return EXPDG_OK;
+}
+
+}  // namespace
+
+extern "C" int expdg_jvp_noalloc(const expdg_mesh_desc *d, const void *qref, const void *v,
+                                 void *w, void *stream) {
+    const char *why = "";
+    if (!desc_ok(d, &why)) return fail(EXPDG_EINVAL, "invalid mesh description: %s", why);
+    if (d->ev_ce > 0.0)
+        return fail(EXPDG_EINVAL, "entropy viscosity needs a mesh (it holds nu): use expdg_jvp");
+    if (!qref || !v || !w) return fail(EXPDG_EINVAL, "NULL argument");
+    if (v == w || qref == w) return fail(EXPDG_EINVAL, "output must not alias an input");
+    if (d->device >= kScratchDevices) return fail(EXPDG_EINVAL, "device %d out of range", d->device);
+    expdg_mesh m;  // host-side description only: no device block, events or streams
+    mesh_setup(&m, d);
+    const size_t need = lin_elems(d->equation, d->p, m.K) * (size_t)m.ebytes;
+    if (need > kScratchBytes)
+        return fail(EXPDG_EINVAL,
+                    "the frozen fields of this mesh take %zu bytes, more than the %zu bytes of "
+                    "static scratch of expdg_jvp_noalloc",
+                    need, kScratchBytes);
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+        return fail(EXPDG_EDEVICE, "no HIP device available");
+    if (d->device >= ndev) return fail(EXPDG_EINVAL, "device %d out of range", d->device);
+    DeviceGuard g(d->device);
+    if (!g.ok) return fail(EXPDG_EDEVICE, "hipSetDevice(%d) failed", d->device);
+    void *scr = nullptr;
+    TRY(scratch_address(d->device, &scr));
+    m.lin = need ? scr : nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    if (d->precision == EXPDG_FP64) {
+        HIPTRY(prepare_lin<double>(&m, (const double *)qref, s));
+        return apply_op<double>(&m, true, (const double *)qref, (const double *)v, (double *)w, s);
+    }
+    HIPTRY(prepare_lin<float>(&m, (const float *)qref, s));
+    return apply_op<float>(&m, true, (const float *)qref, (const float *)v, (float *)w, s);
 }
 
 // ---------------------------------------------------------------------------
