@@ -77,7 +77,7 @@ def log(msg):
 
 
 class Case:
-    def __init__(self, B, inputs, torch, w, precision, scheme=None, iop=0):
+    def __init__(self, B, inputs, torch, w, precision, scheme=None, iop=0, adapt=0):
         self.B, self.torch, self.w = B, torch, w
         self.scheme = B.EPI3 if scheme is None else scheme
         self.mesh = B.Mesh(B.EULER2D, w["nx"], w["p"], ny=w["ny"], x0=0.0, x1=10.0, y0=0.0,
@@ -87,7 +87,7 @@ class Case:
                               dtype=torch.float64, device="cuda:0")
         self.qp = torch.empty_like(self.q)
         self.dt = w["cr"] * self.mesh.dx_min / self.mesh.max_speed(self.q)
-        self.opts = B.make_opts(w["tol"], w["m_min"], w["m_max"], iop=iop)
+        self.opts = B.make_opts(w["tol"], w["m_min"], w["m_max"], iop=iop, adapt=adapt)
         self.have = False
         self.nsteps = 0
 
@@ -208,20 +208,36 @@ def run_viscous(args):
             res["kernel_time_share"] = {k: round(v["total_ms"] / tot, 4) for k, v in pr.items()}
     for c in B.KERNEL_CLASSES:
         B.expdg_profile_enable(m.handle, c, False)
-    # the same steps with incomplete orthogonalization (window of 2)
-    q2 = torch.tensor(inputs.burgers_smooth(x), dtype=torch.float64, device="cuda:0")
-    oi = B.make_opts(w["tol"], 5, 64, iop=2)
-    m.integrate(B.EXPRB32, dt, 2, q2, None, False, oi, B.make_stats())
-    st = B.make_stats()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    m.integrate(B.EXPRB32, dt, w["steps"], q2, None, False, oi, st)
-    torch.cuda.synchronize()
-    secs = time.perf_counter() - t0
-    d = B.stats_dict(st)
-    res["iop2"] = dict(ms_per_step=round(secs / w["steps"] * 1e3, 4),
-                       value=round(m.n * (d["rhs_calls"] + d["jvps"]) / secs, 1),
-                       krylov_iters_per_step=d["krylov_iters"] / w["steps"])
+    # the same steps with incomplete orthogonalization (window of 2) and with
+    # the cost-based adaptivity (errors checked at the target sizes only)
+    for key, oi in (("iop2", B.make_opts(w["tol"], 5, 64, iop=2)),
+                    ("adapt", B.make_opts(w["tol"], 5, 64, adapt=1)),
+                    ("iop2_adapt", B.make_opts(w["tol"], 5, 64, iop=2, adapt=1))):
+        q2 = torch.tensor(inputs.burgers_smooth(x), dtype=torch.float64, device="cuda:0")
+        m.integrate(B.EXPRB32, dt, 2, q2, None, False, oi, B.make_stats())
+        for prof in (False, True):
+            for c in B.KERNEL_CLASSES:
+                B.expdg_profile_enable(m.handle, c, prof)
+            st = B.make_stats()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            m.integrate(B.EXPRB32, dt, w["steps"], q2, None, False, oi, st)
+            torch.cuda.synchronize()
+            secs = time.perf_counter() - t0
+            d = B.stats_dict(st)
+            if not prof:
+                res[key] = dict(ms_per_step=round(secs / w["steps"] * 1e3, 4),
+                                value=round(m.n * (d["rhs_calls"] + d["jvps"]) / secs, 1),
+                                krylov_iters_per_step=d["krylov_iters"] / w["steps"],
+                                checks_per_step=d["checks"] / w["steps"])
+            else:
+                pr = {B.KERNEL_CLASSES[c]: B.expdg_profile_read(m.handle, c)
+                      for c in B.KERNEL_CLASSES}
+                tot = sum(v["total_ms"] for v in pr.values())
+                res[key]["kernel_time_share"] = {k: round(v["total_ms"] / tot, 4)
+                                                 for k, v in pr.items()}
+        for c in B.KERNEL_CLASSES:
+            B.expdg_profile_enable(m.handle, c, False)
     log(f"viscous Burgers 131072 x p4: {res['ms_per_step']:.3f} ms/step, "
         f"iop2 {res['iop2']['ms_per_step']:.3f}")
     m.close()
@@ -259,21 +275,21 @@ def run_euler3d(args):
     q0 = torch.tensor(q0h, dtype=torch.float64, device="cuda:0")
     out["ndof"] = m.n
     out["courant"] = round(w["dt"] * m.max_speed(q0) / m.dx_min, 2)
-    for iop in (0, 2):
+    for iop, adapt in ((0, 0), (2, 0), (0, 1), (2, 1)):
         q = q0.clone()
         st = B.make_stats()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         m.integrate(B.EPI2, w["dt"], w["steps"], q, None, False,
-                    B.make_opts(w["tol"], w["m_min"], w["m_max"], iop=iop), st)
+                    B.make_opts(w["tol"], w["m_min"], w["m_max"], iop=iop, adapt=adapt), st)
         torch.cuda.synchronize()
         secs = time.perf_counter() - t0
         d = B.stats_dict(st)
         ex = inputs.vortex3d(*m.nodes(), t=w["dt"] * w["steps"], beta=0.05).reshape(-1)
         err = float(np.linalg.norm(q.cpu().numpy() - ex) / np.linalg.norm(ex))
-        key = "full_orthogonalization" if iop == 0 else "iop2"
+        key = ("full_orthogonalization" if iop == 0 else "iop2") + ("_adapt" if adapt else "")
         out[key] = dict(seconds_to_t1=round(secs, 4), krylov_iters=d["krylov_iters"],
-                        substeps=d["substeps"],
+                        substeps=d["substeps"], checks=d["checks"],
                         value=round(m.n * (d["rhs_calls"] + d["jvps"]) / secs, 1), unit=UNIT,
                         l2_rel_err_vs_exact=err,
                         vs_paper_4096_cores=round(E3_PAPER_SECONDS[4096] / secs, 2),
@@ -296,19 +312,23 @@ def run_euler3d(args):
                      ("residual", "euler3_op<6, double, false>"),
                      ("gs_update", B.KERNEL_SYMBOLS["gs_update"])):
         out[cls + "_roofline"] = roof(pr[cls], cls, sym, measured_traffic(sym, wl))
+    out["kernel_avg_us"] = {k: round(v["total_ms"] * 1e3 / max(1, v["launches"]), 3)
+                            for k, v in pr.items()}
     m.close()
     return out
 
 
 # Entropy viscosity (Section 3.2, "Artificial viscosity"): the paper's
 # Kelvin-Helmholtz run of Section 5.3 (N_e = 722 = 38 x 19 elements of degree 6
-# on (-5, 5) x (0, 5), c_E = 1, c_max = 0.1, EPI2 to t = 100 at dt = 0.5 and
-# 0.04), taken periodic in y (the uniform stream is the same at both walls),
-# and the 512 x 512, p = 4 shear layer with and without the viscosity.
+# on (-5, 5) x (0, 5), periodic in x with no-slip walls at y = 0 and 5,
+# c_E = 1, c_max = 0.1, EPI2 to t = 100 at dt = 0.5 and 0.04; quadrilaterals
+# where the paper's footnote on h speaks of triangles), and the 512 x 512,
+# p = 4 shear layer with and without the viscosity.
 KH = dict(nx=38, ny=19, p=6, ce=1.0, cmax=0.1, t_end=100.0, dts=(0.5, 0.04), tol=1e-10,
           m_min=10, m_max=64,
-          name="Kelvin-Helmholtz, (-5,5)x(0,5) periodic, 38x19 quads (N_e = 722), LGL p=6 "
-               "(141,512 DOF), entropy viscosity c_E = 1, c_max = 0.1, EPI2 to t = 100, FP64")
+          name="Kelvin-Helmholtz, (-5,5)x(0,5) periodic in x, no-slip walls at y = 0 and 5, "
+               "38x19 quads (N_e = 722), LGL p=6 (141,512 DOF), entropy viscosity c_E = 1, "
+               "c_max = 0.1, EPI2 to t = 100, FP64")
 KH_PAPER_SECONDS = {"rk4_dt0.005": 8729.0, "epi2_dt0.04": 3505.0, "epi2_dt0.5": 2656.0}
 SL = dict(nx=512, ny=512, p=4, cr=5.0, steps=20, tol=1e-7, m_min=10, m_max=64, ce=1.0, cmax=0.1,
           name="shear layer, periodic [0,1]^2, 512x512 quads, LGL p=4 (26,214,400 DOF), density "
@@ -334,7 +354,7 @@ def run_kh(args):
 
     w = KH
     m = B.Mesh(B.EULER2D, w["nx"], w["p"], ny=w["ny"], x0=-5.0, x1=5.0, y0=0.0, y1=5.0,
-               m_max=w["m_max"], ev_ce=w["ce"], ev_cmax=w["cmax"])
+               m_max=w["m_max"], ev_ce=w["ce"], ev_cmax=w["cmax"], bc=B.BC_WALL_Y)
     x, y = m.nodes()
     q0 = torch.tensor(inputs.kelvin_helmholtz(x, y).reshape(-1), dtype=torch.float64,
                       device="cuda:0")
@@ -384,8 +404,8 @@ def run_kh(args):
                      vs_paper=round(KH_PAPER_SECONDS[paper_key] / secs, 1),
                      min_density=float(rho.min()), min_pressure=float(pr.min()),
                      max_nu_final=float(nu.max().item()),
-                     mass_drift=max(abs(float(mass @ qh[c * npts:(c + 1) * npts]) - m0[c]) /
-                                    max(1.0, abs(m0[c])) for c in range(4)))
+                     mass_energy_drift=max(abs(float(mass @ qh[c * npts:(c + 1) * npts]) -
+                                               m0[c]) / max(1.0, abs(m0[c])) for c in (0, 3)))
             log(f"KH EPI2 dt={dt} iop={iop}{tag}: {secs:.3f} s to t = 100 ({nsteps} steps, "
                 f"{d['krylov_iters']} Krylov iterations)")
         else:
@@ -400,7 +420,8 @@ def run_kh(args):
     # sensitivity of the larger step to the amount of viscosity: the same run
     # with the cap constant c_max raised by sqrt(2)
     ms = B.Mesh(B.EULER2D, w["nx"], w["p"], ny=w["ny"], x0=-5.0, x1=5.0, y0=0.0, y1=5.0,
-                m_max=w["m_max"], ev_ce=w["ce"], ev_cmax=w["cmax"] * math.sqrt(2.0))
+                m_max=w["m_max"], ev_ce=w["ce"], ev_cmax=w["cmax"] * math.sqrt(2.0),
+                bc=B.BC_WALL_Y)
     run_one(ms, max(w["dts"]), 0, "_cmax_x1.414")
     runs[f"epi2_dt{max(w['dts']):g}_cmax_x1.414"]["note"] = "c_max = 0.1 sqrt(2) (not the paper's)"
     ms.close()
@@ -456,6 +477,8 @@ def run_shear_ev(args):
                                          "ev_element_kernel<4> / ev_smooth_kernel<4, float>")
             tot = sum(v["total_ms"] for v in pr.values())
             r["kernel_time_share"] = {k: round(v["total_ms"] / tot, 4) for k, v in pr.items()}
+            r["kernel_avg_us"] = {k: round(v["total_ms"] * 1e3 / max(1, v["launches"]), 3)
+                                  for k, v in pr.items()}
         res["with_ev" if ev else "without_ev"] = r
         log(f"shear layer 512^2 p=4 ev={ev}: {r['ms_per_step']:.3f} ms/step")
         m.close()
@@ -518,39 +541,55 @@ def run_gpu(args):
         ci.mesh.close()
 
     if not args.no_fp32:
-        c32 = Case(B, inputs, torch, C2, B.FP32_BULK)
-        c32.run(args.warmup)
-        r32 = c32.run(args.steps)
-        log(f"fp32-bulk timed: {r32['ms_per_step']:.3f} ms/step")
-        q32 = c32.q.cpu().numpy()
-        r32["l2_rel_diff_vs_fp64"] = float(np.linalg.norm(q32 - q64) / np.linalg.norm(q64))
-        out["fp32"] = r32
-        c32.mesh.close()
-
-        # the FP32 basis resolves about 1e-7: the same run at that tolerance
-        c32b = Case(B, inputs, torch, dict(C2, tol=1e-7), B.FP32_BULK)
-        c32b.run(args.warmup)
-        r32b = c32b.run(args.steps)
-        q32b = c32b.q.cpu().numpy()
-        r32b["l2_rel_diff_vs_fp64"] = float(np.linalg.norm(q32b - q64) / np.linalg.norm(q64))
-        out["fp32_tol7"] = r32b
-        c32b.mesh.close()
+        # precision mode at equal tolerance: FP32 bulk against FP64, both at the
+        # tolerance of the workload (1e-10) and at 1e-7 (what an FP32 basis can
+        # resolve); each final state is kept for the comparison with the oracle
+        prec = {}
+        for name, pr, tol in (("fp64_tol1e-10", B.FP64, 1e-10), ("fp32_tol1e-10", B.FP32_BULK, 1e-10),
+                              ("fp64_tol1e-7", B.FP64, 1e-7), ("fp32_tol1e-7", B.FP32_BULK, 1e-7),
+                              ("fp64_tol1e-6", B.FP64, 1e-6), ("fp32_tol1e-6", B.FP32_BULK, 1e-6),
+                              ("fp64_tol1e-10_adapt", B.FP64, 1e-10),
+                              ("fp32_tol1e-10_adapt", B.FP32_BULK, 1e-10),
+                              ("fp64_tol1e-7_adapt", B.FP64, 1e-7),
+                              ("fp32_tol1e-7_adapt", B.FP32_BULK, 1e-7)):
+            kavg = None
+            if name == "fp64_tol1e-10":
+                rp, qp_ = r, q64
+            else:
+                cp = Case(B, inputs, torch, dict(C2, tol=tol), pr,
+                          adapt=1 if name.endswith("_adapt") else 0)
+                cp.run(args.warmup)
+                rp = cp.run(args.steps)
+                qp_ = cp.q.cpu().numpy()
+                if name == "fp32_tol1e-7":
+                    pf = cp.profile(args.steps)["profile"]
+                    kavg = {k: round(v["total_ms"] * 1e3 / max(1, v["launches"]), 3)
+                            for k, v in pf.items() if v["launches"]}
+                cp.mesh.close()
+            prec[name] = dict(ms_per_step=round(rp["ms_per_step"], 4), value=round(rp["value"], 1),
+                              krylov_iters_per_step=rp["krylov_iters_per_step"], state=qp_)
+            if kavg:
+                prec[name]["kernel_avg_us"] = kavg
+            log(f"precision 64x64 p=4 {name}: {rp['ms_per_step']:.3f} ms/step, "
+                f"{rp['krylov_iters_per_step']:.1f} its/step")
+        out["precision_c2"] = dict(steps_from_start=args.warmup + args.steps, runs=prec)
 
     if not args.no_large:
         big = {}
-        for prec, name, tol in ((B.FP64, "fp64", 1e-10), (B.FP32_BULK, "fp32_bulk", 1e-10),
-                                (B.FP32_BULK, "fp32_bulk_tol1e-7", 1e-7)):
+        for prec, name, tol in ((B.FP64, "fp64_tol1e-10", 1e-10),
+                                (B.FP32_BULK, "fp32_tol1e-10", 1e-10),
+                                (B.FP64, "fp64_tol1e-7", 1e-7),
+                                (B.FP32_BULK, "fp32_tol1e-7", 1e-7),
+                                (B.FP64, "fp64_tol1e-6", 1e-6),
+                                (B.FP32_BULK, "fp32_tol1e-6", 1e-6)):
             cb = Case(B, inputs, torch, dict(C3, tol=tol), prec)
             cb.run(1)
             rb = cb.run(args.large_steps)
             err, qb = cb.exact_error(inputs, np)
             rb["l2_rel_err_vs_exact"] = err
-            if prec == B.FP64:
+            rb["state"] = qb
+            if name == "fp64_tol1e-10":
                 rb["profile"] = cb.profile(args.large_steps)["profile"]
-                q_ref = qb
-            else:
-                rb["l2_rel_diff_vs_fp64"] = float(np.linalg.norm(qb - q_ref) /
-                                                  np.linalg.norm(q_ref))
             log(f"256^2 p=3 {name}: {rb['ms_per_step']:.3f} ms/step")
             big[name] = rb
             cb.mesh.close()
@@ -564,7 +603,7 @@ SERVED = dict(n_requests=2000, rate=200.0, seed=0, steps=20, tol=1e-10, m_min=10
                    "16..128, p 2..4, Courant 5), 20 EPI3 steps each, FP64, tol 1e-10")
 
 
-def run_served(args, iop=0, compare=True):
+def run_served(args, iop=0, compare=True, rate=None, n_requests=None):
     import numpy as np
     import torch
 
@@ -572,8 +611,10 @@ def run_served(args, iop=0, compare=True):
     from paper_2011_01316_amd import inputs, serving
 
     w = SERVED
+    rate = w["rate"] if rate is None else rate
+    n_requests = args.serve_requests if n_requests is None else n_requests
     t = time.time()
-    mix = inputs.served_mix(n_requests=args.serve_requests, rate=w["rate"], seed=w["seed"],
+    mix = inputs.served_mix(n_requests=n_requests, rate=rate, seed=w["seed"],
                             steps=w["steps"])
     items = serving.prepare(mix, tol=w["tol"], m_min=w["m_min"], m_max=w["m_max"], iop=iop)
     log(f"served: {len(items)} requests prepared in {time.time() - t:.1f}s")
@@ -651,11 +692,21 @@ def run_served(args, iop=0, compare=True):
     return out
 
 
-def run_cpu_baseline(args):
-    import oracle
-    from paper_2011_01316_amd import inputs
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    w = C2
+
+def oracle_run(oracle, inputs, w, nsteps, timed_from=1):
+    """The oracle on the vortex workload w from its initial state: nsteps steps
+    (an EPI2 start, then EPI3), the steps from timed_from on timed.  Returns
+    (final state, seconds, operator applications timed, mesh, state after the
+    first step)."""
     om = oracle.Mesh(oracle.EULER2D, w["nx"], w["p"], ny=w["ny"], x0=0.0, x1=10.0, y0=0.0,
                      y1=10.0)
     x, y = om.nodes()
@@ -663,18 +714,117 @@ def run_cpu_baseline(args):
     c, dx = om.max_speed(q)
     dt = w["cr"] * dx / c
     kw = dict(tol=w["tol"], m_min=w["m_min"], m_max=w["m_max"])
-    q, qp = om.step(oracle.EPI3, dt, q, None, **kw)  # EPI2 start, untimed
-    apps, nsteps = 0, 0
-    t0 = time.perf_counter()
-    while nsteps < args.cpu_steps and time.perf_counter() - t0 < args.cpu_budget:
+    qp, apps, secs, first = None, 0, 0.0, None
+    for k in range(nsteps):
+        t0 = time.perf_counter()
         q, qp, st = om.step(oracle.EPI3, dt, q, qp, stats=True, **kw)
-        apps += st["rhs_calls"] + st["jvps"]
-        nsteps += 1
-    secs = time.perf_counter() - t0
-    return dict(value=round(om.n * apps / secs, 1), unit=UNIT, cores=oracle.num_threads(),
-                kind="oracle",
-                sample=f"{nsteps} EPI3 steps of the 64x64 p=4 vortex (409,600 DOF) after an "
-                       f"untimed EPI2 start, {secs:.1f} s wall")
+        if k >= timed_from:
+            secs += time.perf_counter() - t0
+            apps += st["rhs_calls"] + st["jvps"]
+        if k == 0:
+            first = (q.copy(), qp.copy())
+    return q, secs, apps, om, first, dt
+
+
+def run_cpu_baseline(args, g, states):
+    """The oracle on the host cores: the 64x64 p=4 vortex for as many steps as
+    the GPU runs took from the initial state (EPI2 start untimed), the
+    256x256 p=3 vortex for its steps, and two 64x64 steps on one core.  The
+    final states are kept in states for the precision comparison."""
+    import oracle
+    from paper_2011_01316_amd import inputs
+
+    n2 = args.warmup + args.steps
+    q2, secs, apps, om, first, dt = oracle_run(oracle, inputs, C2, n2)
+    states["c2"] = q2
+    res = dict(value=round(om.n * apps / secs, 1), unit=UNIT, cores=oracle.num_threads(),
+               kind="oracle", cpu_model=cpu_model(), host_cpus=os.cpu_count(),
+               sample=f"{n2 - 1} EPI3 steps of the 64x64 p=4 vortex (409,600 DOF) after an "
+                      f"untimed EPI2 start, {secs:.1f} s wall")
+    log(f"oracle 64x64 p=4: {res['value']:.3g} DOF-stage updates/s on {res['cores']} threads")
+    # one core: two EPI3 steps from the state after the first step
+    nt = oracle.num_threads()
+    oracle.set_num_threads(1)
+    try:
+        q, qp = first
+        kw = dict(tol=C2["tol"], m_min=C2["m_min"], m_max=C2["m_max"])
+        t0 = time.perf_counter()
+        a1 = 0
+        for _ in range(2):
+            q, qp, st = om.step(oracle.EPI3, dt, q, qp, stats=True, **kw)
+            a1 += st["rhs_calls"] + st["jvps"]
+        s1 = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(nt)
+    res["one_core"] = dict(value=round(om.n * a1 / s1, 1), unit=UNIT, cores=1,
+                           sample=f"2 EPI3 steps of the 64x64 p=4 vortex, {s1:.1f} s wall")
+    log(f"oracle 64x64 p=4 on one core: {res['one_core']['value']:.3g}")
+    if "large" in g:
+        n3 = 1 + args.large_steps
+        q3, s3, a3, om3, _, _ = oracle_run(oracle, inputs, C3, n3)
+        states["c3"] = q3
+        res["vortex_256x256_p3"] = dict(
+            value=round(om3.n * a3 / s3, 1), unit=UNIT, cores=oracle.num_threads(),
+            sample=f"{n3 - 1} EPI3 steps of the 256x256 p=3 vortex (4,194,304 DOF) after an "
+                   f"untimed EPI2 start, {s3:.1f} s wall")
+        log(f"oracle 256x256 p=3: {res['vortex_256x256_p3']['value']:.3g}")
+    return res
+
+
+def precision_report(args, g, states):
+    """FP32 bulk against FP64 at equal tolerance: ms/step of each (ratio > 1:
+    FP32 bulk is faster) and the relative l2 difference of each final state
+    from the FP64 oracle's after the same steps from the same initial state."""
+    import numpy as np
+
+    def block(runs, ref, steps, workload):
+        out = dict(workload=workload, steps_from_start=steps, runs={})
+        for name, r in runs.items():
+            d = {k: v for k, v in r.items() if k in ("ms_per_step", "krylov_iters_per_step",
+                                                     "l2_rel_err_vs_exact", "kernel_avg_us")}
+            if "value" in r:
+                d["value"] = round(r["value"], 1)
+            if ref is not None:
+                d["l2_rel_err_vs_oracle"] = float(np.linalg.norm(r["state"] - ref) /
+                                                  np.linalg.norm(ref))
+            out["runs"][name] = d
+        out["step_time_ratio_fp64_over_fp32"] = {
+            tol: round(runs["fp64_" + tol]["ms_per_step"] / runs["fp32_" + tol]["ms_per_step"], 3)
+            for tol in ("tol1e-10", "tol1e-7", "tol1e-6", "tol1e-10_adapt", "tol1e-7_adapt")
+            if "fp64_" + tol in runs and "fp32_" + tol in runs}
+        if ref is None:
+            out["oracle"] = "not run (--no-cpu-baseline)"
+        return out
+
+    rep = {}
+    if "precision_c2" in g:
+        pc = g["precision_c2"]
+        rep["vortex_64x64_p4"] = block(pc["runs"], states.get("c2"), pc["steps_from_start"],
+                                       C2["name"])
+    if "large" in g:
+        rep["vortex_256x256_p3"] = block(g["large"], states.get("c3"), 1 + args.large_steps,
+                                         C3["name"])
+    rep["note"] = ("tol1e-10 is the workload's tolerance; an FP32 basis resolves about 1e-7, "
+                   "so FP32 bulk at 1e-10 takes more Krylov iterations for no accuracy; the "
+                   "equal-tolerance 1e-7 pair is the precision mode's own gain")
+    return rep
+
+
+def fp32_probe():
+    """An EPI2 and an EPI3 step of the 256x256 p=3 vortex in FP32 bulk at tol
+    1e-7 (the run the VALU / MFMA counters of the FP32 linear operator are
+    read on)."""
+    import torch
+
+    from paper_2011_01316_amd import binding as B
+    from paper_2011_01316_amd import inputs
+
+    c = Case(B, inputs, torch, dict(C3, tol=1e-7), B.FP32_BULK)
+    r = c.run(2)
+    c.mesh.close()
+    return dict(workload=C3["name"] + ", FP32 bulk, tol 1e-7", steps=2,
+                ms_per_step=round(r["ms_per_step"], 3),
+                krylov_iters_per_step=r["krylov_iters_per_step"])
 
 
 def copy_probe(nbytes=1 << 30, reps=20):
@@ -732,7 +882,13 @@ def main():
                     help="only run the served workload and print its figures")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only time a plain 1 GiB device copy and print it")
+    ap.add_argument("--fp32-probe", action="store_true",
+                    help="only two FP32-bulk steps of the 256x256 p=3 vortex (tol 1e-7), for "
+                         "instruction counters of its linear operator")
     args = ap.parse_args()
+    if args.fp32_probe:
+        print(json.dumps(fp32_probe()), flush=True)
+        return
     if args.copy_probe:
         print(json.dumps(copy_probe()), flush=True)
         return
@@ -808,48 +964,21 @@ def main():
                            ms_per_step=round(e42["ms_per_step"], 4),
                            krylov_iters_per_step=e42["krylov_iters_per_step"],
                            l2_rel_err_vs_exact_vortex=e42["l2_rel_err_vs_exact"])
-    if "fp32" in g:
-        f32 = g["fp32"]
-        line["fp32_bulk"] = dict(value=round(f32["value"], 1), unit=UNIT,
-                                 ms_per_step=round(f32["ms_per_step"], 4),
-                                 speedup_vs_fp64=round(f32["value"] / f64["value"], 3),
-                                 l2_rel_diff_vs_fp64=f32["l2_rel_diff_vs_fp64"],
-                                 krylov_iters_per_step=f32["krylov_iters_per_step"])
-    if "fp32_tol7" in g:
-        f7 = g["fp32_tol7"]
-        line["fp32_bulk_tol1e-7"] = dict(value=round(f7["value"], 1), unit=UNIT,
-                                         ms_per_step=round(f7["ms_per_step"], 4),
-                                         speedup_vs_fp64_steps=round(f64["ms_per_step"] /
-                                                                     f7["ms_per_step"], 3),
-                                         l2_rel_diff_vs_fp64=f7["l2_rel_diff_vs_fp64"],
-                                         krylov_iters_per_step=f7["krylov_iters_per_step"])
     if "large" in g:
-        b64, b32 = g["large"]["fp64"], g["large"]["fp32_bulk"]
-        b7 = g["large"]["fp32_bulk_tol1e-7"]
-        pb = b64["profile"]
+        pb = g["large"]["fp64_tol1e-10"]["profile"]
         line["large_256x256_p3"] = dict(
             workload=C3["name"], steps=args.large_steps,
-            fp64=dict(value=round(b64["value"], 1), ms_per_step=round(b64["ms_per_step"], 3),
-                      krylov_iters_per_step=b64["krylov_iters_per_step"],
-                      l2_rel_err_vs_exact=b64["l2_rel_err_vs_exact"]),
-            fp32_bulk=dict(value=round(b32["value"], 1), ms_per_step=round(b32["ms_per_step"], 3),
-                           krylov_iters_per_step=b32["krylov_iters_per_step"],
-                           l2_rel_err_vs_exact=b32["l2_rel_err_vs_exact"],
-                           l2_rel_diff_vs_fp64=b32["l2_rel_diff_vs_fp64"]),
-            fp32_bulk_tol1e_7=dict(value=round(b7["value"], 1),
-                                   ms_per_step=round(b7["ms_per_step"], 3),
-                                   krylov_iters_per_step=b7["krylov_iters_per_step"],
-                                   l2_rel_err_vs_exact=b7["l2_rel_err_vs_exact"],
-                                   l2_rel_diff_vs_fp64=b7["l2_rel_diff_vs_fp64"]),
-            fp32_speedup=round(b32["value"] / b64["value"], 3),
-            fp32_tol1e_7_step_speedup=round(b64["ms_per_step"] / b7["ms_per_step"], 3),
             linear_operator_roofline=roof(
                 pb["linear_operator"], "linear_operator", "euler_op<3, double, true, false>",
                 measured_traffic("euler_op<3, double, true, false>", "vortex256_p3")),
+            residual_roofline=roof(
+                pb["residual"], "residual", "euler_op<3, double, false, false>",
+                measured_traffic("euler_op<3, double, false, false>", "vortex256_p3")),
             gs_update_roofline=roof(pb["gs_update"], "gs_update", B.KERNEL_SYMBOLS["gs_update"],
                                     measured_traffic(B.KERNEL_SYMBOLS["gs_update"],
                                                      "vortex256_p3")),
-            gs_dots_roofline=roof(pb["gs_dots"], "gs_dots", B.KERNEL_SYMBOLS["gs_dots"]))
+            kernel_avg_us={k: round(v["total_ms"] * 1e3 / max(1, v["launches"]), 3)
+                           for k, v in pb.items()})
     if not args.no_viscous:
         line["viscous_burgers"] = run_viscous(args)
     if not args.no_euler3d:
@@ -864,7 +993,22 @@ def main():
             line["served"]["iop2"] = {k: si[k] for k in (
                 "completed", "solves_per_s", "latency_p50_s", "latency_p99_s",
                 "dof_stage_updates_per_s", "arnoldi_steps_per_tick")}
-    line["cpu_baseline"] = None if args.no_cpu_baseline else run_cpu_baseline(args)
+        # offered rates the server keeps up with (the same mix, fewer requests):
+        # latency is then service time plus a short admission wait
+        sus = {}
+        for rate, iop in ((100.0, 0), (160.0, 2)):
+            r = run_served(args, iop=iop, compare=False, rate=rate,
+                           n_requests=min(args.serve_requests, 1000))
+            sus[f"rate{rate:g}_iop{iop}"] = {k: r[k] for k in (
+                "requests", "completed", "solves_per_s", "latency_p50_s", "latency_p99_s",
+                "admission_wait_p50_s", "admission_wait_p99_s", "makespan_s",
+                "dof_stage_updates_per_s")}
+            sus[f"rate{rate:g}_iop{iop}"]["offered_rate"] = rate
+        line["served"]["sustained"] = sus
+    oracle_states = {}
+    line["cpu_baseline"] = None if args.no_cpu_baseline else run_cpu_baseline(args, g,
+                                                                            oracle_states)
+    line["precision_mode"] = precision_report(args, g, oracle_states)
     print(json.dumps(line), flush=True)
 
 

@@ -64,8 +64,8 @@ extern "C" {
 enum { EXPDG_BURGERS1D = 1, EXPDG_EULER2D = 2, EXPDG_EULER3D = 3 };
 enum { EXPDG_FP64 = 0, EXPDG_FP32_BULK = 1 };
 enum { EXPDG_EPI2 = 2, EXPDG_EPI3 = 3, EXPDG_EXPRB32 = 32, EXPDG_EXPRB42 = 42 };
-enum { EXPDG_FLUX_LF = 0, EXPDG_FLUX_EF = 1 };
-enum { EXPDG_BC_PERIODIC = 0, EXPDG_BC_DIRICHLET = 1 };
+enum { EXPDG_FLUX_LF = 0, EXPDG_FLUX_EF = 1, EXPDG_FLUX_EF_LOCAL = 2 };
+enum { EXPDG_BC_PERIODIC = 0, EXPDG_BC_DIRICHLET = 1, EXPDG_BC_WALL_Y = 2 };
 enum {
     EXPDG_OK = 0,
     EXPDG_EINVAL = -1,     /* invalid argument */
@@ -82,14 +82,16 @@ enum {
  * is used by Euler only.
  *
  * Burgers options (Section 3.1; all zero = inviscid, periodic,
- * Lax-Friedrichs; Euler requires them zero):
+ * Lax-Friedrichs; Euler requires them zero, except bc below):
  *   kappa  viscosity >= 0.  With kappa > 0 the flux is u^2/2 - kappa q with
  *          the auxiliary q = u_x of eq. gov-burgers1d-gradu, and all of the
  *          diffusion belongs to the linear operator L (eq. BurgerL);
- *   flux   EXPDG_FLUX_LF or EXPDG_FLUX_EF: the numerical flux (u^2/2)* of the
- *          residual; EF is (1/3)({{u^2/2}} + {{u}}^2) + (sigma/h)[[u]] with h
- *          the half-width h_e/2 of an element.  The linear flux (u~ u)* is
- *          always Lax-Friedrichs;
+ *   flux   EXPDG_FLUX_LF, EXPDG_FLUX_EF or EXPDG_FLUX_EF_LOCAL: the
+ *          numerical flux (u^2/2)* of the residual; EF is (1/3)({{u^2/2}} +
+ *          {{u}}^2) + (sigma/h)[[u]] with h the half-width h_e/2 of an
+ *          element; EF_LOCAL takes sigma = kappa/100 + h max|u^+-| at each
+ *          face (the steep-gradient example of Section 5.1; sigma is then
+ *          not read).  The linear flux (u~ u)* is always Lax-Friedrichs;
  *   beta   diffusion fluxes u** = {{u}} - beta [[u]], q** = {{q}} + beta [[q]]
  *          with [[v]] = v_left - v_right: 0 central (Section 3.1), 1/2 LDG
  *          (Appendix A); |beta| <= 1/2;
@@ -98,6 +100,15 @@ enum {
  *          the convective fluxes, u** = 0, q** = q^-);
  *   has_source  nonzero: the mesh holds a source vector s added to R (not to
  *          L), set by expdg_mesh_set_source (zero until then).
+ *
+ * Euler 2D boundaries (bc): EXPDG_BC_PERIODIC, or EXPDG_BC_WALL_Y: periodic in
+ * x, no-slip walls at y0 and y1 (the Kelvin-Helmholtz problem of Section 5.3).
+ * At a wall face node the exterior state is the mirror M q = (rho, -rho u,
+ * -rho v, rho E) in the Rusanov flux of R, and M v at the mirrored reference
+ * state in L; with entropy viscosity the gradient takes (v + M v)/2 on the
+ * wall and the diffusive flux through it is the interior one for the momenta
+ * and zero for density and energy; the face jump of u S . n is 2 |v S| and a
+ * wall vertex averages its two elements.
  *
  * Entropy viscosity (Euler 2D only; Section 3.2, "Artificial viscosity"):
  *   ev_ce, ev_cmax  the constants c_E and c_max (both >= 0; the paper takes 1
@@ -164,6 +175,25 @@ typedef struct {
                  vector against the L most recent basis vectors only (one
                  pass, explicit norm), the IOP option of KIOPS (Section 2.3).
                  Served solves take it from their request. */
+    int adapt;  /* 0: the fixed controller above.  1: cost-based choice of the
+                   Krylov size and the substep (after KIOPS, Section 2.3): the
+                   error is checked only at the target size m of a substep, as
+                   omega = err tau / (tol nu dtau) (accepted when <= 1); after
+                   each check, keeping m with dtau scaled by
+                   clamp((0.8/omega)^(1/q), 0.2, 5) (0.9 at most after a
+                   rejection) and keeping dtau (capped to R) with m moved by
+                   ln(omega'/0.8)/ln(kappa), omega' = omega (min(dtau, R) /
+                   dtau)^q (within [m_min, min(m_max, 4m/3)]) are priced at
+                   ceil(R/dtau') substeps of m'^2 + 9m' state-vector passes
+                   each (m'(2L + 7) with a window of L), R the interval left,
+                   and the cheaper one is taken (omega rounded up to a power of
+                   10^(1/4), q and kappa to two significant digits).  q (the order of omega in
+                   dtau) starts at m and
+                   kappa (the gain of one more vector) at 2, and both are
+                   re-estimated from two checks of the same substep.  A
+                   rejection either re-checks the same basis with the shorter
+                   substep or extends the Arnoldi process. */
+    int m_init; /* adapt = 1: first target size (0: m_min) */
 } expdg_krylov_opts;
 
 /* Statistics, accumulated over the call (zero them before the call).  If
@@ -174,6 +204,8 @@ typedef struct {
     double err_est;
     expdg_substep *log;
     int log_cap, log_len;
+    int checks;  /* small exponentials evaluated (error checks) */
+    int m_next;  /* adapt = 1: the Krylov size chosen for a next substep */
 } expdg_krylov_stats;
 
 /* ---- mesh -------------------------------------------------------------- */
@@ -370,6 +402,7 @@ typedef struct {
     int m_min, m_max, check_every;
     int iop;              /* 0: full orthogonalization; L in 1..64: incomplete (as in
                              expdg_krylov_opts.iop) */
+    int adapt;            /* 0 or 1, as in expdg_krylov_opts.adapt */
 } expdg_request;
 
 enum {

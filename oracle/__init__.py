@@ -30,8 +30,8 @@ BURGERS1D = 1
 EULER2D = 2
 EULER3D = 3
 EPI2, EPI3, EXPRB32, EXPRB42 = 2, 3, 32, 42
-FLUX_LF, FLUX_EF = 0, 1
-BC_PERIODIC, BC_DIRICHLET = 0, 1
+FLUX_LF, FLUX_EF, FLUX_EF_LOCAL = 0, 1, 2
+BC_PERIODIC, BC_DIRICHLET, BC_WALL_Y = 0, 1, 2
 
 
 def build(verbose: bool = False) -> str:
@@ -64,14 +64,15 @@ class Substep(C.Structure):
 class _KOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("m_min", C.c_int), ("m_max", C.c_int),
                 ("check_every", C.c_int), ("forced", C.POINTER(Substep)), ("n_forced", C.c_int),
-                ("iop", C.c_int)]
+                ("iop", C.c_int), ("adapt", C.c_int), ("m_init", C.c_int)]
 
 
 class _KStats(C.Structure):
     _fields_ = [("substeps", C.c_int), ("rejects", C.c_int), ("krylov_iters", C.c_int),
                 ("jvps", C.c_int), ("breakdown", C.c_int), ("phi_calls", C.c_int),
                 ("rhs_calls", C.c_int), ("err_est", C.c_double),
-                ("log", C.POINTER(Substep)), ("log_cap", C.c_int), ("log_len", C.c_int)]
+                ("log", C.POINTER(Substep)), ("log_cap", C.c_int), ("log_len", C.c_int),
+                ("checks", C.c_int), ("m_next", C.c_int)]
 
 
 _lib = None
@@ -266,10 +267,11 @@ class Mesh:
         return np.ascontiguousarray(L.T)
 
     def phi_krylov(self, qref, tau, bs, tol=1e-10, m_min=10, m_max=64, check_every=1,
-                   forced=None, stats=False, iop=0):
+                   forced=None, stats=False, iop=0, adapt=0, m_init=0):
         qref = np.ascontiguousarray(qref, dtype=np.float64)
         out = np.zeros(self.n)
-        opts, st, keep = _kopts(tol, m_min, m_max, check_every, forced, iop=iop)
+        opts, st, keep = _kopts(tol, m_min, m_max, check_every, forced, iop=iop, adapt=adapt,
+                                m_init=m_init)
         barr, keep2 = _bvec(bs)
         rc = lib().orc_phi_krylov_dg(C.byref(self._m), _dp(qref), tau, len(bs) - 1, barr,
                                      _dp(out), C.byref(opts), C.byref(st))
@@ -277,12 +279,13 @@ class Mesh:
         return (out, _stats(st)) if stats else out
 
     def step(self, scheme, dt, q, q_prev=None, tol=1e-10, m_min=10, m_max=64, check_every=1,
-             forced=None, stats=False, iop=0):
+             forced=None, stats=False, iop=0, adapt=0, m_init=0):
         """One step; returns (q_new, q_prev_new[, stats]).  Inputs are not modified."""
         q = np.array(q, dtype=np.float64, copy=True)
         have_prev = q_prev is not None
         qp = (np.array(q_prev, dtype=np.float64, copy=True) if have_prev else np.zeros(self.n))
-        opts, st, keep = _kopts(tol, m_min, m_max, check_every, forced, iop=iop)
+        opts, st, keep = _kopts(tol, m_min, m_max, check_every, forced, iop=iop, adapt=adapt,
+                                m_init=m_init)
         rc = lib().orc_step(C.byref(self._m), scheme, dt, _dp(q), _dp(qp), int(have_prev),
                             C.byref(opts), C.byref(st))
         _check(rc, "step")
@@ -302,16 +305,16 @@ def _bvec(bs):
     return barr, arrs
 
 
-def _kopts(tol, m_min, m_max, check_every, forced, log_cap=4096, iop=0):
+def _kopts(tol, m_min, m_max, check_every, forced, log_cap=4096, iop=0, adapt=0, m_init=0):
     if forced:
         fa = (Substep * len(forced))(*[Substep(int(m), int(last), float(dt))
                                        for (m, dt, last) in forced])
         fp, nf = fa, len(forced)
     else:
         fa, fp, nf = None, None, 0
-    opts = _KOpts(tol, m_min, m_max, check_every, fp, nf, iop)
+    opts = _KOpts(tol, m_min, m_max, check_every, fp, nf, iop, adapt, m_init)
     log = (Substep * log_cap)()
-    st = _KStats(0, 0, 0, 0, 0, 0, 0, 0.0, log, log_cap, 0)
+    st = _KStats(0, 0, 0, 0, 0, 0, 0, 0.0, log, log_cap, 0, 0, 0)
     return opts, st, (fa, log)
 
 
@@ -322,6 +325,7 @@ def _stats(st):
         "jvps": st.jvps, "breakdown": st.breakdown, "phi_calls": st.phi_calls,
         "rhs_calls": st.rhs_calls, "err_est": st.err_est,
         "log": [(st.log[i].m, st.log[i].dtau, st.log[i].last) for i in range(n)],
+        "checks": st.checks, "m_next": st.m_next,
     }
 
 
@@ -350,10 +354,11 @@ def phi_dense(A, tau, bs):
 
 
 def phi_krylov_dense(A, tau, bs, tol=1e-10, m_min=10, m_max=64, check_every=1, forced=None,
-                     stats=False, iop=0):
+                     stats=False, iop=0, adapt=0, m_init=0):
     A = np.ascontiguousarray(A, dtype=np.float64)
     out = np.zeros(A.shape[0])
-    opts, st, keep = _kopts(tol, m_min, m_max, check_every, forced, iop=iop)
+    opts, st, keep = _kopts(tol, m_min, m_max, check_every, forced, iop=iop, adapt=adapt,
+                                m_init=m_init)
     barr, keep2 = _bvec(bs)
     rc = lib().orc_phi_krylov_dense(A.shape[0], _dp(A), tau, len(bs) - 1, barr, _dp(out),
                                     C.byref(opts), C.byref(st))

@@ -42,11 +42,25 @@
 // i.e. (1/3)({{u^2/2}} + {{u}}^2) + (sigma/h)[[u]] of Section 3.1, with h read
 // as the half-width h_e/2 of the element (the Jacobian of the map from
 // [-1, 1]); the linear flux (u~ u)* stays Lax-Friedrichs with
-// lambda = max|u~^+-|.
+// lambda = max|u~^+-|.  For the steep-gradient example of Section 5.1 the
+// penalty is set per face, sigma = kappa/100 + h max|u^+-| with the same h,
+// so sigma/h = kappa/(100 h) + max|u^+-|.
 //
 // Boundaries: periodic, or (Burgers) zero Dirichlet at both ends following
 // the footnote at the start of Section 6: the exterior state is u^+ = 0 for
 // (u~ u)* and (u^2/2)*, u** = 0 and q** = q^-.
+//
+// Euler 2D with no-slip walls at y0 and y1 (Section 5.3, periodic in x): at a
+// wall face node the exterior state is the mirror q^+ = M q^-, M = diag(1, -1,
+// -1, 1) (both momentum components reversed, so the mean velocity on the wall
+// is zero), in the Rusanov flux of R; the linear flux takes v^+ = M v^- at the
+// mirrored reference state M q~^- (lambda is the same on both sides).  The
+// entropy-viscosity diffusion mirrors too: the gradient takes
+// v** = (v^- + M v^-)/2 (zero momentum on the wall, density and energy
+// unchanged), and the normal diffusive flux of the mirror is -M (nu g)^-, so
+// (nu g)** = (I - M)(nu g)^-/2: the interior value for the momenta (as the
+// Dirichlet end above) and zero for density and energy (no diffusive flux
+// through the wall).
 #include "oracle.h"
 
 #include <cmath>
@@ -85,11 +99,15 @@ bool make_geo(const orc_mesh *m, Geo *g) {
     if (m->equation != ORC_BURGERS1D && (!(m->y1 > m->y0) || !(m->gamma > 1.0))) return false;
     if (m->equation == ORC_EULER3D && !(m->z1 > m->z0)) return false;
     if (!(m->kappa >= 0.0) || !(m->sigma >= 0.0) || !(std::fabs(m->beta) <= 0.5)) return false;
-    if (m->flux != ORC_FLUX_LF && m->flux != ORC_FLUX_EF) return false;
-    if (m->bc != ORC_BC_PERIODIC && m->bc != ORC_BC_DIRICHLET) return false;
-    if (m->equation != ORC_BURGERS1D &&
-        (m->kappa != 0.0 || m->flux != ORC_FLUX_LF || m->bc != ORC_BC_PERIODIC || m->source))
+    if (m->flux != ORC_FLUX_LF && m->flux != ORC_FLUX_EF && m->flux != ORC_FLUX_EF_LOCAL)
         return false;
+    if (m->bc != ORC_BC_PERIODIC && m->bc != ORC_BC_DIRICHLET && m->bc != ORC_BC_WALL_Y)
+        return false;
+    if (m->equation == ORC_BURGERS1D && m->bc == ORC_BC_WALL_Y) return false;
+    if (m->equation != ORC_BURGERS1D &&
+        (m->kappa != 0.0 || m->flux != ORC_FLUX_LF || m->bc == ORC_BC_DIRICHLET || m->source))
+        return false;
+    if (m->equation == ORC_EULER3D && m->bc != ORC_BC_PERIODIC) return false;
     if (!(m->ev_ce >= 0.0) || !(m->ev_cmax >= 0.0)) return false;
     if (m->equation != ORC_EULER2D && (m->ev_ce > 0.0 || m->nu)) return false;
     g->eq = m->equation;
@@ -126,10 +144,11 @@ bool make_geo(const orc_mesh *m, Geo *g) {
 
 // Neighbour of element e = (ez ny + ey) nx + ex across its face in direction
 // dir (0 = x, 1 = y, 2 = z) on side s (-1 = lower, +1 = upper); -1 at a
-// Dirichlet end.
+// Dirichlet end or a wall.
 int neighbour(const Geo &g, int e, int dir, int s) {
     int ex = e % g.nx, ey = (e / g.nx) % g.ny, ez = e / (g.nx * g.ny);
     if (g.bc == ORC_BC_DIRICHLET && dir == 0 && (ex + s < 0 || ex + s >= g.nx)) return -1;
+    if (g.bc == ORC_BC_WALL_Y && dir == 1 && (ey + s < 0 || ey + s >= g.ny)) return -1;
     if (dir == 0)
         ex = (ex + s + g.nx) % g.nx;
     else if (dir == 1)
@@ -147,6 +166,15 @@ inline int node(const Geo &g, int i, int j, int k = 0) {
 template <class T>
 void load(const Geo &g, const T *q, int e, int n, T *out) {
     for (int c = 0; c < g.nvar; ++c) out[c] = q[((size_t)c * g.K + e) * g.Np + n];
+}
+
+// The wall mirror M q: both momentum components reversed (Euler 2D).
+template <class T>
+void mirror(const T *q, T *out) {
+    out[0] = q[0];
+    out[1] = -q[1];
+    out[2] = -q[2];
+    out[3] = q[3];
 }
 
 // ---- physics -------------------------------------------------------------
@@ -234,9 +262,10 @@ double wave_speed(const Geo &g, const double *q, int dir) {
 //   node_flux(e, n, dir, f): flux at a node (volume and face traces),
 //   lam_ref: real state whose traces give the LF wave speed lambda.
 //   entropy: the nonlinear Burgers face flux is EF instead of LF.
-template <class T, class FluxAt>
-void dg_apply(const Geo &g, const T *u, const double *lam_ref, FluxAt node_flux, T *out,
-              bool entropy = false) {
+// wall_flux(e, n, dir, fp, up): exterior flux and field at a wall face node.
+template <class T, class FluxAt, class WallAt>
+void dg_apply(const Geo &g, const T *u, const double *lam_ref, FluxAt node_flux, WallAt wall_flux,
+              T *out, bool entropy = false) {
     const int n1 = g.n1, Np = g.Np, nv = g.nvar;
     const double h[3] = {g.hx, g.hy, g.hz};
 #pragma omp parallel for schedule(static)
@@ -284,6 +313,9 @@ void dg_apply(const Geo &g, const T *u, const double *lam_ref, FluxAt node_flux,
                             node_flux(en, nn, dir, fp);
                             load(g, u, en, nn, up);
                             load(g, lam_ref, en, nn, qp);
+                        } else if (g.bc == ORC_BC_WALL_Y) {  // wall: the mirror state
+                            wall_flux(e, n, dir, fp, up);
+                            mirror(qm, qp);
                         } else {  // Dirichlet end (Burgers): exterior state 0, flux 0
                             fp[0] = T(0.0);
                             up[0] = T(0.0);
@@ -294,10 +326,17 @@ void dg_apply(const Geo &g, const T *u, const double *lam_ref, FluxAt node_flux,
                         const double sn = (double)s;  // n^- . e_dir
                         for (int c = 0; c < nv; ++c) {
                             T fstar_n = 0.5 * sn * (fm[c] + fp[c]) + 0.5 * lam * (um[c] - up[c]);
-                            if (entropy)
+                            if (entropy) {
+                                // sigma / h with h the half-width; the face-dependent
+                                // sigma = kappa/100 + h max|u^+-| gives
+                                // sigma / h = kappa / (100 h) + max|u^+-| (lam here)
+                                const double pen = (g.flux == ORC_FLUX_EF_LOCAL)
+                                                       ? 2.0 * g.kappa / (100.0 * g.hx) + lam
+                                                       : 2.0 * g.sigma / g.hx;
                                 fstar_n = sn * (um[0] * um[0] + um[0] * up[0] + up[0] * up[0]) /
                                               6.0 +
-                                          (2.0 * g.sigma / g.hx) * (um[0] - up[0]);
+                                          pen * (um[0] - up[0]);
+                            }
                             T f_n = sn * fm[c];
                             res[c] -= (2.0 / h[dir]) / g.w[a] * (fstar_n - f_n);
                         }
@@ -406,7 +445,10 @@ void ev_diffusion(const Geo &g, const T *v, T *out) {
                             if ((s == -1 && a != 0) || (s == 1 && a != p)) continue;
                             const int en = neighbour(g, e, d, s);
                             const int nn = along(i, j, d, p - a);
-                            const T vm = vc[(size_t)e * Np + n], vp = vc[(size_t)en * Np + nn];
+                            const T vm = vc[(size_t)e * Np + n];
+                            // wall: the mirror's component (momentum reversed)
+                            const T vp = en >= 0 ? vc[(size_t)en * Np + nn]
+                                                 : ((c == 1 || c == 2) ? -vm : vm);
                             acc += (2.0 / h[d]) / g.w[a] * (double)s * (0.5 * (vm + vp) - vm);
                         }
                         G[d * plane + (size_t)e * Np + n] = acc;
@@ -427,6 +469,16 @@ void ev_diffusion(const Geo &g, const T *v, T *out) {
                         for (int s = -1; s <= 1; s += 2) {
                             if ((s == -1 && a != 0) || (s == 1 && a != p)) continue;
                             const int en = neighbour(g, e, d, s);
+                            if (en < 0) {
+                                // wall: (nu g)** = 0 for density and energy, (nu g)^- for
+                                // the momenta (no face term)
+                                if (c == 0 || c == 3) {
+                                    const size_t am = (size_t)e * Np + n;
+                                    const T fm = g.nu[am] * G[d * plane + am];
+                                    acc += (2.0 / h[d]) / g.w[a] * (double)s * (0.0 - fm);
+                                }
+                                continue;
+                            }
                             const size_t am = (size_t)e * Np + n;
                             const size_t ap = (size_t)en * Np + along(i, j, d, p - a);
                             const T fm = g.nu[am] * G[d * plane + am];
@@ -446,7 +498,13 @@ void residual_frozen(const Geo &g, const T *q, const double *lam_ref, T *r) {
         load(g, q, e, n, qn);
         flux(g, qn, dir, f);
     };
-    dg_apply(g, q, lam_ref, fl, r, g.eq == ORC_BURGERS1D && g.flux == ORC_FLUX_EF);
+    auto wall = [&](int e, int n, int dir, T *f, T *up) {
+        T qn[5];
+        load(g, q, e, n, qn);
+        mirror(qn, up);
+        flux(g, up, dir, f);
+    };
+    dg_apply(g, q, lam_ref, fl, wall, r, g.eq == ORC_BURGERS1D && g.flux != ORC_FLUX_LF);
     if (g.eq == ORC_BURGERS1D) add_diffusion(g, q, r);
     if (g.eq == ORC_EULER2D) ev_diffusion(g, q, r);
 }
@@ -458,7 +516,15 @@ void linear_op(const Geo &g, const double *qt, const double *v, double *w) {
         load(g, v, e, n, vn);
         lin_flux(g, qn, vn, dir, f);
     };
-    dg_apply(g, v, qt, fl, w);
+    auto wall = [&](int e, int n, int dir, double *f, double *up) {
+        double qn[5], qm[5], vn[5];
+        load(g, qt, e, n, qn);
+        load(g, v, e, n, vn);
+        mirror(qn, qm);
+        mirror(vn, up);
+        lin_flux(g, qm, up, dir, f);
+    };
+    dg_apply(g, v, qt, fl, wall, w);
     if (g.eq == ORC_BURGERS1D) add_diffusion(g, v, w);
     if (g.eq == ORC_EULER2D) ev_diffusion(g, v, w);
 }
@@ -583,8 +649,10 @@ int orc_entropy_viscosity(const orc_mesh *m, const double *q, const double *q_pr
                         if ((s == -1 && a != 0) || (s == 1 && a != p)) continue;
                         const int en = neighbour(g, e, d, s);
                         const int nn = d == 0 ? j * n1 + (p - a) : (p - a) * n1 + i;
-                        const double jump =
-                            F[d * plane + at] - F[d * plane + (size_t)en * Np + nn];
+                        // a wall's mirror state carries -v S: the jump is 2 v S
+                        const double fp = en >= 0 ? F[d * plane + (size_t)en * Np + nn]
+                                                  : -F[d * plane + at];
+                        const double jump = F[d * plane + at] - fp;
                         jmax = std::fmax(jmax, std::fabs(jump));
                     }
                 }
@@ -593,17 +661,28 @@ int orc_entropy_viscosity(const orc_mesh *m, const double *q, const double *q_pr
         const double nu_max = g.ev_cmax * he * lam;
         nue[e] = std::fmin(nu_max, nu_e);
     }
-    // vertex (vx, vy) is the lower-left corner of element (vx, vy)
-    std::vector<double> vert(g.K);
-    for (int vy = 0; vy < g.ny; ++vy)
+    // vertex (vx, vy) is the lower-left corner of element (vx, vy); with walls
+    // there is one more row of vertices (y1), and a wall vertex averages the
+    // two elements it belongs to
+    const bool walls = g.bc == ORC_BC_WALL_Y;
+    const int nvy = walls ? g.ny + 1 : g.ny;
+    std::vector<double> vert((size_t)nvy * g.nx);
+    for (int vy = 0; vy < nvy; ++vy)
         for (int vx = 0; vx < g.nx; ++vx) {
-            const int xm = (vx + g.nx - 1) % g.nx, ym = (vy + g.ny - 1) % g.ny;
-            vert[vy * g.nx + vx] = 0.25 * ((nue[vy * g.nx + vx] + nue[vy * g.nx + xm]) +
-                                           (nue[ym * g.nx + vx] + nue[ym * g.nx + xm]));
+            const int xm = (vx + g.nx - 1) % g.nx;
+            if (walls && (vy == 0 || vy == g.ny)) {
+                const int ey = vy == 0 ? 0 : g.ny - 1;
+                vert[(size_t)vy * g.nx + vx] =
+                    0.5 * (nue[ey * g.nx + vx] + nue[ey * g.nx + xm]);
+                continue;
+            }
+            const int ym = (vy + g.ny - 1) % g.ny;
+            vert[(size_t)vy * g.nx + vx] = 0.25 * ((nue[vy * g.nx + vx] + nue[vy * g.nx + xm]) +
+                                                   (nue[ym * g.nx + vx] + nue[ym * g.nx + xm]));
         }
     for (int e = 0; e < g.K; ++e) {
         const int ex = e % g.nx, ey = e / g.nx;
-        const int xp = (ex + 1) % g.nx, yp = (ey + 1) % g.ny;
+        const int xp = (ex + 1) % g.nx, yp = walls ? ey + 1 : (ey + 1) % g.ny;
         const double v00 = vert[ey * g.nx + ex], v10 = vert[ey * g.nx + xp];
         const double v01 = vert[yp * g.nx + ex], v11 = vert[yp * g.nx + xp];
         for (int j = 0; j < n1; ++j)

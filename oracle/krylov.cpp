@@ -27,6 +27,32 @@
 // A forced schedule (list of (m, dtau, last)) replays given substeps with no
 // error checks.
 //
+// Cost-based adaptivity (adapt = 1, after KIOPS, which the paper cites for its
+// phi evaluations in Section 2.3; the paper gives no parameters, so these are
+// the written rules both the oracle and the GPU library follow).  The error is
+// checked only at the target size m of the substep, as
+//    omega = err tau / (tol_abs dtau)       (accept when omega <= 1),
+// and after every check two candidates for going on are priced:
+//    A: keep m, dtau_A = RND2(dtau clamp((0.8/omega)^(1/q), 0.2, 5)),
+//    B: keep dtau (capped to R), m_B = ceil(m + ln(omega_B/0.8)/ln kappa)
+//       clamped to [m_min, min(m_max, ceil(4m/3))], omega_B =
+//       omega (min(dtau, R)/dtau)^q,
+// each at ceil(R/dtau') substeps of cost C(m') = m'^2 + 9m' (full
+// orthogonalization; m'(2L + 7) with a window of L), R the interval still to
+// cover; the cheaper one is taken (A on a tie).  omega and omega_B are rounded up
+// to a power of 10^(1/4), q and kappa to two significant digits (RND2), before
+// they are used, so both implementations take the same decisions (a tiny error
+// estimate has few correct digits).  q, the order of omega in dtau,
+// is m (the Expokit estimate) until two checks of one substep share m and
+// differ in dtau, then max(1, ln(omega/omega')/ln(dtau/dtau')); kappa, the factor one more
+// Krylov vector gains, is 2 until two checks share dtau and differ in m, then
+// max(1.1, (omega'/omega)^(1/(m - m'))).  A rejected check retries with A on
+// the same basis (dtau_A then at most RND2(0.9 dtau)) or extends the same
+// Arnoldi process to m_B; at m_max only A is possible.  An accepted substep
+// hands the chosen candidate to the next one (dtau capped to what remains).
+// The first substep starts at m = m_init (m_min if 0) and dtau = tau; a happy
+// breakdown is exact and takes the whole remaining interval as above.
+//
 // Incomplete orthogonalization (iop = L > 0, the IOP option of KIOPS cited in
 // Section 2.3): each new vector is orthogonalized, with one classical
 // Gram-Schmidt pass, against the L most recent basis vectors only (the one it
@@ -63,6 +89,13 @@ double dot(const double *a, const double *b, size_t n) {
 }
 
 double norm2(const double *a, size_t n) { return std::sqrt(dot(a, a, n)); }
+
+// Rounds up to a power of 10^(1/4) (quarter decades): error ratios are used
+// on this grid, which is coarse next to the accuracy of a tiny error estimate.
+double q4(double x) {
+    if (!(x > 0.0)) return x;
+    return std::pow(10.0, std::ceil(4.0 * std::log10(x)) / 4.0);
+}
 
 double rnd2(double x) {
     if (!(x > 0.0)) return x;
@@ -107,6 +140,45 @@ void orthogonalize(const std::vector<double> &V, size_t na, std::vector<double> 
             H[(size_t)i * ldh + (j - 1)] += h[i];
         }
     }
+}
+
+// Cost of one substep of Krylov size m (in state-vector passes): the operator
+// and the two Gram-Schmidt sweeps of each Arnoldi step, m^2 + 9m with full
+// orthogonalization, m (2L + 7) with a window of L.
+double substep_cost(int m, int iop) {
+    return iop > 0 ? (double)m * (2.0 * iop + 7.0) : (double)m * m + 9.0 * m;
+}
+
+// The two candidates after a check at (m, dtau) with error ratio omega: A
+// keeps m and takes dtau_a, B keeps dtau and takes m_b; *take_a when A is the
+// cheaper way to cover rem.  rejected: dtau_a < dtau is enforced.
+struct CostChoice {
+    double dtau_a;
+    int m_b;
+    bool take_a;
+};
+CostChoice cost_choice(int m, double dtau, double omega, double q, double kappa, double rem,
+                       bool rejected, const orc_kopts *o) {
+    const double gam = 0.8;
+    const double om = std::max(omega, 1e-300);
+    CostChoice c;
+    double fa = std::pow(gam / om, 1.0 / q);
+    fa = std::min(rejected ? 0.9 : 5.0, std::max(0.2, fa));
+    c.dtau_a = rnd2(dtau * fa);
+    // B takes min(dtau, rem): its error ratio scales by (that / dtau)^q
+    const double dtb = (rem > 0.0) ? std::min(dtau, rem) : dtau;
+    const double om_b = q4(std::max(om * std::pow(dtb / dtau, q), 1e-300));
+    const int hi = std::min(o->m_max, (4 * m + 2) / 3);
+    const double mb = std::ceil(m + std::log(om_b / gam) / std::log(kappa));
+    c.m_b = (int)std::min((double)hi, std::max((double)o->m_min, mb));
+    if (!(rem > 0.0)) {
+        c.take_a = true;  // nothing left to cover
+        return c;
+    }
+    const double ca = std::ceil(rem / std::min(c.dtau_a, rem)) * substep_cost(m, o->iop);
+    const double cb = std::ceil(rem / dtb) * substep_cost(c.m_b, o->iop);
+    c.take_a = ca <= cb || (rejected && c.m_b <= m);
+    return c;
 }
 
 }  // namespace
@@ -194,6 +266,140 @@ int orc_phi_krylov_op(size_t n, const Op &A, double tau, int p, const double *co
     const int ldh = mmax;
     std::vector<double> V((size_t)(mmax + 1) * na), H((size_t)(mmax + 1) * mmax), w(na), F;
 
+    auto expm_at = [&](int j, double dt) {
+        if (st) st->checks += 1;
+        return small_expm(H, ldh, j, dt, F);
+    };
+
+    // one Arnoldi step: v_{j} from v_{j-1} (1-based j); 1 on a happy breakdown
+    auto arnoldi_step = [&](int j) -> int {
+        const double *vj = &V[(size_t)(j - 1) * na];
+        aug(vj, w.data());
+        if (st) {
+            st->krylov_iters += 1;
+            st->jvps += 1;
+        }
+        orthogonalize(V, na, H, ldh, j, o->iop, w.data());
+        const double hn = norm2(w.data(), na);
+        if (!std::isfinite(hn)) return -5;
+        H[(size_t)j * ldh + (j - 1)] = hn;
+        double hf = 0.0;
+        for (int r = 0; r <= j; ++r)
+            for (int c = 0; c < j; ++c) hf += H[(size_t)r * ldh + c] * H[(size_t)r * ldh + c];
+        hf = std::sqrt(hf);
+        if (hn <= 1e-12 * hf) {
+            H[(size_t)j * ldh + (j - 1)] = 0.0;
+            if (st) st->breakdown += 1;
+            return 1;
+        }
+        for (size_t r = 0; r < na; ++r) V[(size_t)j * na + r] = w[r] / hn;
+        return 0;
+    };
+
+    // z <- beta V_j F_{1:j,1}
+    auto combine = [&](int j_acc, double beta) {
+        const int nh = j_acc + 1;
+        std::fill(z.begin(), z.end(), 0.0);
+        for (int i = 0; i < j_acc; ++i) {
+            const double c = beta * F[(size_t)i * nh + 0];
+            const double *vi = &V[(size_t)i * na];
+            for (size_t r = 0; r < na; ++r) z[r] += c * vi[r];
+        }
+    };
+
+    if (o->adapt == 1 && !forced) {
+        // cost-based choice of the Krylov size and the substep
+        int m = std::min(o->m_max, std::max(o->m_min, o->m_init > 0 ? o->m_init : o->m_min));
+        double t_done = 0.0, dtau = tau;
+        while (true) {
+            const double rem0 = tau - t_done;
+            bool last = !(dtau < rem0);
+            if (last) dtau = rem0;
+            const double beta = norm2(z.data(), na);
+            if (!std::isfinite(beta)) return -5;
+            if (beta == 0.0) {
+                for (size_t i = 0; i < n; ++i) out[i] = 0.0;
+                return 0;
+            }
+            for (size_t i = 0; i < na; ++i) V[i] = z[i] / beta;
+            std::fill(H.begin(), H.end(), 0.0);
+            int j = 0, j_acc = 0;
+            double err = 0.0;
+            double q = m, kappa = 2.0;
+            double om_p = 0.0, dt_p = 0.0;
+            int m_p = -1;
+            CostChoice next{};
+            while (true) {
+                bool brk = false;
+                while (j < m) {
+                    const int rc = arnoldi_step(j + 1);
+                    if (rc < 0) return rc;
+                    ++j;
+                    if (rc == 1) {
+                        brk = true;
+                        break;
+                    }
+                }
+                if (brk) {
+                    // happy breakdown: exact, the whole remaining interval
+                    dtau = rem0;
+                    last = true;
+                    if (expm_at(j, dtau)) return -5;
+                    err = 0.0;
+                    j_acc = j;
+                    next = CostChoice{dtau, m, true};
+                    break;
+                }
+                if (expm_at(m, dtau)) return -5;
+                err = beta * std::fabs(F[(size_t)m * (m + 1) + 0]);
+                if (!std::isfinite(err)) return -5;
+                // omega rounded up to a quarter decade, q and kappa to two
+                // significant digits, so that decisions do not turn on the
+                // last bits of err
+                const double om = q4(err * tau / (tol_abs * dtau));
+                if (m_p == m && dt_p != dtau && om_p > 0.0 && om > 0.0)
+                    q = rnd2(std::max(1.0, std::log(om / om_p) / std::log(dtau / dt_p)));
+                if (m_p >= 0 && m_p != m && dt_p == dtau && om > 0.0 && om_p > 0.0)
+                    kappa = rnd2(std::max(1.1, std::pow(om_p / om, 1.0 / (m - m_p))));
+                const bool ok = om <= 1.0;
+                const double rem = ok ? rem0 - dtau : rem0;
+                next = cost_choice(m, dtau, om, q, kappa, rem, !ok, o);
+                if (ok) {
+                    j_acc = m;
+                    break;
+                }
+                if (st) st->rejects += 1;
+                om_p = om;
+                dt_p = dtau;
+                m_p = m;
+                if (next.take_a) {
+                    dtau = next.dtau_a;  // same basis, shorter substep
+                    last = false;
+                    if (!(dtau > 1e-12 * tau)) return -4;
+                } else {
+                    m = next.m_b;  // extend the Arnoldi process
+                }
+            }
+            combine(j_acc, beta);
+            t_done += dtau;
+            log_substep(st, j_acc, last ? 1 : 0, dtau);
+            if (st) st->err_est = err;
+            const double rem = tau - t_done;
+            if (last || !(rem > 1e-15 * tau)) {
+                if (!last && st && st->log && st->log_len >= 1 && st->log_len <= st->log_cap)
+                    st->log[st->log_len - 1].last = 1;
+                if (st) st->m_next = next.take_a ? m : next.m_b;
+                break;
+            }
+            if (next.take_a)
+                dtau = next.dtau_a;
+            else
+                m = next.m_b;
+        }
+        for (size_t i = 0; i < n; ++i) out[i] = z[i];
+        return 0;
+    }
+
     double t_done = 0.0, dtau = tau;
     bool reaches_end = true;  // the current dtau covers the rest of [0, tau]
     while (true) {
@@ -243,7 +449,7 @@ int orc_phi_krylov_op(size_t n, const Op &A, double tau, int p, const double *co
 
             if (forced) {
                 if (brk || j == m_target) {
-                    if (small_expm(H, ldh, j, dt_sub, F)) return -5;
+                    if (expm_at(j, dt_sub)) return -5;
                     j_acc = j;
                     break;
                 }
@@ -255,12 +461,12 @@ int orc_phi_krylov_op(size_t n, const Op &A, double tau, int p, const double *co
             if (brk) {
                 dt_sub = tau - t_done;
                 sub_last = true;
-                if (small_expm(H, ldh, j, dt_sub, F)) return -5;
+                if (expm_at(j, dt_sub)) return -5;
                 err = 0.0;
                 j_acc = j;
                 break;
             }
-            if (small_expm(H, ldh, j, dt_sub, F)) return -5;
+            if (expm_at(j, dt_sub)) return -5;
             err = beta * std::fabs(F[(size_t)j * (j + 1) + 0]);
             if (err <= tol_abs * dt_sub / tau) {
                 j_acc = j;
@@ -275,7 +481,7 @@ int orc_phi_krylov_op(size_t n, const Op &A, double tau, int p, const double *co
                     sub_last = false;
                     if (st) st->rejects += 1;
                     if (!(dt_sub > 1e-12 * tau)) return -4;
-                    if (small_expm(H, ldh, j, dt_sub, F)) return -5;
+                    if (expm_at(j, dt_sub)) return -5;
                     err = beta * std::fabs(F[(size_t)j * (j + 1) + 0]);
                 }
                 j_acc = j;

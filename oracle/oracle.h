@@ -44,8 +44,13 @@ extern "C" {
 
 enum { ORC_BURGERS1D = 1, ORC_EULER2D = 2, ORC_EULER3D = 3 };
 enum { ORC_EPI2 = 2, ORC_EPI3 = 3, ORC_EXPRB32 = 32, ORC_EXPRB42 = 42 };
-enum { ORC_FLUX_LF = 0, ORC_FLUX_EF = 1 };          /* Burgers (u^2/2)* */
-enum { ORC_BC_PERIODIC = 0, ORC_BC_DIRICHLET = 1 };  /* Burgers: u = 0 at x0, x1 */
+/* Burgers (u^2/2)*: Lax-Friedrichs, the entropy flux with the constant
+ * sigma, or the entropy flux with sigma = kappa/100 + h max|u^+-| at each face
+ * (the steep-gradient example of Section 5.1). */
+enum { ORC_FLUX_LF = 0, ORC_FLUX_EF = 1, ORC_FLUX_EF_LOCAL = 2 };
+/* ORC_BC_DIRICHLET: Burgers, u = 0 at x0, x1.  ORC_BC_WALL_Y: Euler 2D,
+ * no-slip walls at y0 and y1 (periodic in x), as in Section 5.3. */
+enum { ORC_BC_PERIODIC = 0, ORC_BC_DIRICHLET = 1, ORC_BC_WALL_Y = 2 };
 
 /* The fields after gamma describe viscous Burgers (Section 3.1); zero-filled
  * they give the inviscid periodic Lax-Friedrichs problem.  Euler requires
@@ -57,10 +62,10 @@ typedef struct {
     double x0, x1, y0, y1;
     double gamma;      /* ratio of specific heats (Euler only) */
     double kappa;      /* viscosity, >= 0 */
-    int flux;          /* ORC_FLUX_LF or ORC_FLUX_EF for the nonlinear flux */
+    int flux;          /* ORC_FLUX_LF, ORC_FLUX_EF or ORC_FLUX_EF_LOCAL */
     double sigma;      /* EF jump coefficient: the flux adds (sigma/h)[[u]], h = h_e/2 */
     double beta;       /* diffusion fluxes: 0 central, 1/2 LDG (Appendix A) */
-    int bc;            /* ORC_BC_PERIODIC or ORC_BC_DIRICHLET */
+    int bc;            /* ORC_BC_PERIODIC, ORC_BC_DIRICHLET or ORC_BC_WALL_Y */
     const double *source; /* NULL or a nodal source added to R (not to L) */
     int nz;            /* elements along z (Euler 3D; 0 or 1 otherwise) */
     double z0, z1;
@@ -89,6 +94,9 @@ typedef struct {
     int n_forced;
     int iop;           /* 0: full orthogonalization (two passes); L > 0: one
                           pass against the L most recent vectors (KIOPS' IOP) */
+    int adapt;         /* 0: the fixed controller; 1: the cost-based choice of
+                          the Krylov size and the substep (after KIOPS) */
+    int m_init;        /* adapt = 1: first target size (0: m_min) */
 } orc_kopts;
 
 typedef struct {
@@ -96,6 +104,8 @@ typedef struct {
     double err_est;
     orc_substep *log;  /* optional: accepted substeps are appended here */
     int log_cap, log_len;
+    int checks;        /* small exponentials evaluated */
+    int m_next;        /* adapt = 1: the size chosen for a next substep */
 } orc_kstats;
 
 /* LGL nodes xi (ascending), weights w, differentiation matrix

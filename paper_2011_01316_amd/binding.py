@@ -18,8 +18,8 @@ LIB_PATH = os.path.join(HERE, "libexpdg.so")
 BURGERS1D, EULER2D, EULER3D = 1, 2, 3
 FP64, FP32_BULK = 0, 1
 EPI2, EPI3, EXPRB32, EXPRB42 = 2, 3, 32, 42
-FLUX_LF, FLUX_EF = 0, 1
-BC_PERIODIC, BC_DIRICHLET = 0, 1
+FLUX_LF, FLUX_EF, FLUX_EF_LOCAL = 0, 1, 2
+BC_PERIODIC, BC_DIRICHLET, BC_WALL_Y = 0, 1, 2
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ENONFINITE = 0, -1, -2, -3, -4, -5
 
 
@@ -52,14 +52,15 @@ class Substep(C.Structure):
 class KrylovOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("m_min", C.c_int), ("m_max", C.c_int),
                 ("check_every", C.c_int), ("forced", C.POINTER(Substep)), ("n_forced", C.c_int),
-                ("iop", C.c_int)]
+                ("iop", C.c_int), ("adapt", C.c_int), ("m_init", C.c_int)]
 
 
 class KrylovStats(C.Structure):
     _fields_ = [("substeps", C.c_int), ("rejects", C.c_int), ("krylov_iters", C.c_int),
                 ("jvps", C.c_int), ("breakdown", C.c_int), ("phi_calls", C.c_int),
                 ("rhs_calls", C.c_int), ("err_est", C.c_double),
-                ("log", C.POINTER(Substep)), ("log_cap", C.c_int), ("log_len", C.c_int)]
+                ("log", C.POINTER(Substep)), ("log_cap", C.c_int), ("log_len", C.c_int),
+                ("checks", C.c_int), ("m_next", C.c_int)]
 
 
 class KernelProfile(C.Structure):
@@ -70,7 +71,7 @@ class Request(C.Structure):
     _fields_ = [("mesh", MeshDesc), ("scheme", C.c_int), ("nsteps", C.c_int),
                 ("dt", C.c_double), ("cfl", C.c_double), ("tol", C.c_double),
                 ("m_min", C.c_int), ("m_max", C.c_int), ("check_every", C.c_int),
-                ("iop", C.c_int)]
+                ("iop", C.c_int), ("adapt", C.c_int)]
 
 
 class RequestInfo(C.Structure):
@@ -252,23 +253,25 @@ def expdg_max_speed(handle, q, stream=None) -> float:
     return c.value
 
 
-def make_opts(tol=1e-10, m_min=10, m_max=64, check_every=1, forced=None, iop=0):
+def make_opts(tol=1e-10, m_min=10, m_max=64, check_every=1, forced=None, iop=0, adapt=0,
+              m_init=0):
     """Krylov options; forced is a list of (m, dtau, last); iop > 0 selects
-    incomplete orthogonalization against the iop most recent vectors."""
+    incomplete orthogonalization against the iop most recent vectors; adapt = 1
+    the cost-based choice of the Krylov size and the substep."""
     keep = None
     if forced:
         keep = (Substep * len(forced))(*[Substep(int(m), int(last), float(dt))
                                          for (m, dt, last) in forced])
-        o = KrylovOpts(tol, m_min, m_max, check_every, keep, len(forced), iop)
+        o = KrylovOpts(tol, m_min, m_max, check_every, keep, len(forced), iop, adapt, m_init)
     else:
-        o = KrylovOpts(tol, m_min, m_max, check_every, None, 0, iop)
+        o = KrylovOpts(tol, m_min, m_max, check_every, None, 0, iop, adapt, m_init)
     o._keep = keep
     return o
 
 
 def make_stats(log_cap=4096):
     log = (Substep * log_cap)()
-    s = KrylovStats(0, 0, 0, 0, 0, 0, 0, 0.0, log, log_cap, 0)
+    s = KrylovStats(0, 0, 0, 0, 0, 0, 0, 0.0, log, log_cap, 0, 0, 0)
     s._keep = log
     return s
 
@@ -278,7 +281,8 @@ def stats_dict(s: KrylovStats):
     return {"substeps": s.substeps, "rejects": s.rejects, "krylov_iters": s.krylov_iters,
             "jvps": s.jvps, "breakdown": s.breakdown, "phi_calls": s.phi_calls,
             "rhs_calls": s.rhs_calls, "err_est": s.err_est,
-            "log": [(s.log[i].m, s.log[i].dtau, s.log[i].last) for i in range(n)]}
+            "log": [(s.log[i].m, s.log[i].dtau, s.log[i].last) for i in range(n)],
+            "checks": s.checks, "m_next": s.m_next}
 
 
 def expdg_phi_krylov(handle, qref, tau, bs, w, opts, stats=None, stream=None):
@@ -413,10 +417,10 @@ class Mesh:
 def make_request(equation, nx, p, ny=1, scheme=EPI3, nsteps=20, dt=0.0, cfl=0.0, tol=1e-10,
                  m_min=10, m_max=64, check_every=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0,
                  gamma=1.4, mesh_m_max=64, kappa=0.0, flux=FLUX_LF, sigma=0.0, beta=0.0,
-                 bc=BC_PERIODIC, iop=0):
+                 bc=BC_PERIODIC, iop=0, adapt=0):
     return Request(MeshDesc(equation, nx, ny, p, FP64, 0, x0, x1, y0, y1, gamma, mesh_m_max,
                             kappa, flux, sigma, beta, bc, 0, 1, 0.0, 1.0),
-                   scheme, nsteps, dt, cfl, tol, m_min, m_max, check_every, iop)
+                   scheme, nsteps, dt, cfl, tol, m_min, m_max, check_every, iop, adapt)
 
 
 def expdg_request_bytes(req: Request) -> int:

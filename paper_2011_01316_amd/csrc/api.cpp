@@ -169,14 +169,17 @@ bool desc_ok(const expdg_mesh_desc *d, const char **why) {
     if (!(d->kappa >= 0.0) || !std::isfinite(d->kappa)) return *why = "need kappa >= 0", false;
     if (!(d->sigma >= 0.0) || !std::isfinite(d->sigma)) return *why = "need sigma >= 0", false;
     if (!(std::fabs(d->beta) <= 0.5)) return *why = "need |beta| <= 1/2", false;
-    if (d->flux != EXPDG_FLUX_LF && d->flux != EXPDG_FLUX_EF)
-        return *why = "flux must be EXPDG_FLUX_LF or EXPDG_FLUX_EF", false;
-    if (d->bc != EXPDG_BC_PERIODIC && d->bc != EXPDG_BC_DIRICHLET)
-        return *why = "bc must be EXPDG_BC_PERIODIC or EXPDG_BC_DIRICHLET", false;
+    if (d->flux != EXPDG_FLUX_LF && d->flux != EXPDG_FLUX_EF && d->flux != EXPDG_FLUX_EF_LOCAL)
+        return *why = "flux must be EXPDG_FLUX_LF, EXPDG_FLUX_EF or EXPDG_FLUX_EF_LOCAL", false;
+    if (d->bc != EXPDG_BC_PERIODIC && d->bc != EXPDG_BC_DIRICHLET && d->bc != EXPDG_BC_WALL_Y)
+        return *why = "bc must be EXPDG_BC_PERIODIC, EXPDG_BC_DIRICHLET or EXPDG_BC_WALL_Y", false;
+    if (d->bc == EXPDG_BC_WALL_Y && d->equation != EXPDG_EULER2D)
+        return *why = "EXPDG_BC_WALL_Y needs EXPDG_EULER2D", false;
     if (d->equation != EXPDG_BURGERS1D &&
         (d->kappa != 0.0 || d->flux != EXPDG_FLUX_LF || d->sigma != 0.0 || d->beta != 0.0 ||
-         d->bc != EXPDG_BC_PERIODIC || d->has_source))
-        return *why = "Euler takes no Burgers options (kappa, flux, sigma, beta, bc, source)", false;
+         d->bc == EXPDG_BC_DIRICHLET || d->has_source))
+        return *why = "Euler takes no Burgers options (kappa, flux, sigma, beta, Dirichlet, source)",
+               false;
     if (!(d->ev_ce >= 0.0) || !std::isfinite(d->ev_ce) || !(d->ev_cmax >= 0.0) ||
         !std::isfinite(d->ev_cmax))
         return *why = "need ev_ce >= 0 and ev_cmax >= 0", false;
@@ -631,6 +634,9 @@ int check_opts(const expdg_mesh *m, const expdg_krylov_opts *o) {
         return fail(EXPDG_EINVAL, "need 1 <= m_min <= m_max <= mesh m_max (%d)", m->d.m_max);
     if (o->check_every < 1) return fail(EXPDG_EINVAL, "check_every must be >= 1");
     if (o->iop < 0 || o->iop > kMaxM) return fail(EXPDG_EINVAL, "iop must be in 0..64");
+    if (o->adapt != 0 && o->adapt != 1) return fail(EXPDG_EINVAL, "adapt must be 0 or 1");
+    if (o->m_init < 0 || o->m_init > o->m_max)
+        return fail(EXPDG_EINVAL, "m_init must be in 0..m_max");
     return EXPDG_OK;
 }
 

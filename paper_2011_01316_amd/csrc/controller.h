@@ -93,7 +93,10 @@ struct PhiRun {
     PhiRun(X &x_, expdg_mesh *m_, const expdg_krylov_opts *o_, expdg_krylov_stats *st_)
         : x(x_), m(m_), o(o_), st(st_) {}
 
-    CheckReq req(int j, double dtau) { return CheckReq{j, dtau, (nchecks++) % kCheckSlots}; }
+    CheckReq req(int j, double dtau) {
+        if (st) st->checks += 1;
+        return CheckReq{j, dtau, (nchecks++) % kCheckSlots};
+    }
 
     // Decision on check c: accept (possibly after shrinking the substep on the
     // same basis at m_max), take a happy breakdown, or go on (done = false).
@@ -154,6 +157,53 @@ struct PhiRun {
         co_return EXPDG_OK;
     }
 };
+
+// Error ratios of the cost-based adaptivity are used rounded up to a power of
+// 10^(1/4) (a tiny error estimate has few correct digits; the oracle rounds
+// the same way).
+inline double quarter_decade(double x) {
+    if (!(x > 0.0)) return x;
+    return std::pow(10.0, std::ceil(4.0 * std::log10(x)) / 4.0);
+}
+
+// Cost-based adaptivity (expdg_krylov_opts.adapt = 1): state-vector passes of
+// one substep of Krylov size m (the operator and the two Gram-Schmidt sweeps
+// of each Arnoldi step).
+inline double adapt_substep_cost(int m, int iop) {
+    return iop > 0 ? (double)m * (2.0 * iop + 7.0) : (double)m * m + 9.0 * m;
+}
+
+// The two ways to go on after a check at size m and substep dtau with error
+// ratio omega (q, kappa: the current order estimates; rem: the interval still
+// to cover): A keeps m and takes dtau_a, B keeps dtau and takes m_b.
+struct AdaptChoice {
+    double dtau_a;
+    int m_b;
+    bool take_a;
+};
+inline AdaptChoice adapt_choice(int m, double dtau, double omega, double q, double kappa,
+                                double rem, bool rejected, const expdg_krylov_opts *o) {
+    constexpr double kSafety = 0.8;
+    const double om = std::max(omega, 1e-300);
+    AdaptChoice c;
+    const double f = std::min(rejected ? 0.9 : 5.0,
+                              std::max(0.2, std::pow(kSafety / om, 1.0 / q)));
+    c.dtau_a = round2(dtau * f);
+    // B takes min(dtau, rem): its error ratio scales by (that / dtau)^q
+    const double dtb = (rem > 0.0) ? std::min(dtau, rem) : dtau;
+    const double om_b = quarter_decade(std::max(om * std::pow(dtb / dtau, q), 1e-300));
+    const int hi = std::min(o->m_max, (4 * m + 2) / 3);
+    const double mb = std::ceil(m + std::log(om_b / kSafety) / std::log(kappa));
+    c.m_b = (int)std::min((double)hi, std::max((double)o->m_min, mb));
+    if (!(rem > 0.0)) {
+        c.take_a = true;
+        return c;
+    }
+    const double cost_a = std::ceil(rem / std::min(c.dtau_a, rem)) * adapt_substep_cost(m, o->iop);
+    const double cost_b = std::ceil(rem / dtb) * adapt_substep_cost(c.m_b, o->iop);
+    c.take_a = cost_a <= cost_b || (rejected && c.m_b <= m);
+    return c;
+}
 
 // Awaits a sub-task, reporting a frame allocation failure as ENOMEM.
 #define CO_AWAIT_TASK(task_expr)                                                   \
@@ -240,6 +290,138 @@ Task<int> phi_co(X &x, expdg_mesh *m, const T *qref, double tau, int p, const T 
         naug_nz += bx[p + 1 - k] ? 1 : 0;
     }
     const double eb = (double)sizeof(T);
+
+    if (o->adapt == 1 && !forced) {
+        // cost-based choice of the Krylov size and the substep: the error is
+        // checked at the target size mt only; a rejection re-checks the same
+        // basis with a shorter substep or extends the Arnoldi process
+        int mt = std::min(o->m_max, std::max(o->m_min, o->m_init > 0 ? o->m_init : o->m_min));
+        double dtau = tau;
+        while (true) {
+            const double rem0 = tau - R.t_done;
+            R.sub_last = !(dtau < rem0);
+            R.dt_sub = R.sub_last ? rem0 : dtau;
+            CO_TRY(prof_begin(m, EXPDG_K_GS_NORM));
+            CO_HIPTRY(launch_gs_norm<T>(V, L, rp, kd.part, s));
+            CO_TRY(prof_end(m, EXPDG_K_GS_NORM, (double)L * eb));
+            CO_TRY(prof_begin(m, EXPDG_K_GS_FINISH));
+            CO_HIPTRY(launch_gs_finish_norm(kd.part, rp, kd.H, kd.S, kd.flags, kd.res, s));
+            CO_TRY(prof_end(m, EXPDG_K_GS_FINISH, 8.0 * rp.nrb));
+            int k = 0;  // Arnoldi steps of this substep (step k finishes dimension k - 1)
+            double q = mt, kappa = 2.0, om_p = 0.0, dt_p = 0.0;
+            int m_p = -1;
+            AdaptChoice next{};
+            Check pend;
+            bool have_pend = false;
+            R.j_acc = 0;
+            while (true) {
+                while (k < mt + 1) {
+                    ++k;
+                    const int D = k - 1;
+                    a.v = V + (size_t)(k - 1) * stride;
+                    a.out = V + (size_t)k * stride;
+                    a.vtail = a.v + n;
+                    a.otail = a.out + n;
+                    const int k0 = iop ? std::max(0, k - o->iop) : 0;
+                    a.basis = V + (size_t)k0 * stride;
+                    a.nv = k - 1 - k0;
+                    const bool is_check = D == mt;
+                    CheckReq cr{};
+                    if (is_check) cr = R.req(D, R.dt_sub);
+                    Check cur;
+                    CO_TRY(co_await x.iterate(m, a, k, naug_nz, is_check ? &cr : nullptr, &cur,
+                                              iop));
+                    if (st) {
+                        st->krylov_iters += 1;
+                        st->jvps += 1;
+                    }
+                    if (is_check) {
+                        pend = cur;
+                        have_pend = true;
+                    }
+                }
+                if (!have_pend) {
+                    // the basis already reaches mt (after a shorter substep): check it
+                    CO_TRY(co_await x.check(m, R.req(mt, R.dt_sub), &pend));
+                }
+                have_pend = false;
+                CO_TRY(co_await x.wait_check(m, pend));
+                const CheckResult r = read_check(m, pend);
+                if (r.nonfinite) co_return fail(EXPDG_ENONFINITE, "non-finite Krylov norm");
+                if (r.brk > 0) {
+                    // happy breakdown: exact, the whole remaining interval
+                    R.dt_sub = rem0;
+                    R.sub_last = true;
+                    Check bc;
+                    CO_TRY(co_await x.check(m, R.req(r.brk, R.dt_sub), &bc));
+                    CO_TRY(co_await x.wait_check(m, bc));
+                    const CheckResult br = read_check(m, bc);
+                    if (br.singular) co_return fail(EXPDG_ENONFINITE, "singular Pade denominator");
+                    if (st) st->breakdown += 1;
+                    R.err = 0.0;
+                    R.j_acc = r.brk;
+                    R.acc = bc;
+                    next = AdaptChoice{R.dt_sub, mt, true};
+                    break;
+                }
+                if (r.singular) co_return fail(EXPDG_ENONFINITE, "singular Pade denominator");
+                if (!std::isfinite(r.err)) co_return fail(EXPDG_ENONFINITE, "non-finite error estimate");
+                // omega rounded up to a quarter decade, q and kappa to two
+                // significant digits (the oracle does the same), so decisions
+                // do not turn on the last bits of err
+                const double om = quarter_decade(r.err * tau / (R.tol_abs * R.dt_sub));
+                if (m_p == mt && dt_p != R.dt_sub && om_p > 0.0 && om > 0.0)
+                    q = round2(std::max(1.0, std::log(om / om_p) / std::log(R.dt_sub / dt_p)));
+                if (m_p >= 0 && m_p != mt && dt_p == R.dt_sub && om > 0.0 && om_p > 0.0)
+                    kappa = round2(std::max(1.1, std::pow(om_p / om, 1.0 / (mt - m_p))));
+                const bool ok = om <= 1.0;
+                next = adapt_choice(mt, R.dt_sub, om, q, kappa, ok ? rem0 - R.dt_sub : rem0, !ok,
+                                    o);
+                if (ok) {
+                    R.err = r.err;
+                    R.j_acc = mt;
+                    R.acc = pend;
+                    break;
+                }
+                if (st) st->rejects += 1;
+                om_p = om;
+                dt_p = R.dt_sub;
+                m_p = mt;
+                if (next.take_a) {
+                    R.dt_sub = next.dtau_a;  // same basis, shorter substep
+                    R.sub_last = false;
+                    if (!(R.dt_sub > 1e-12 * tau))
+                        co_return fail(EXPDG_ENOCONV, "Krylov substep below its floor");
+                } else {
+                    mt = next.m_b;  // extend the Arnoldi process
+                }
+            }
+            CO_TRY(x.after_check(m, R.acc));
+            CO_TRY(prof_begin(m, EXPDG_K_COMBINE));
+            CO_HIPTRY(launch_combine<T>(V, stride, R.j_acc,
+                                        m->slots + R.acc.slot * kSlotSize + kSlotCoef, V, L, s));
+            CO_TRY(prof_end(m, EXPDG_K_COMBINE, (double)(R.j_acc + 1) * L * eb));
+            R.t_done += R.dt_sub;
+            log_sub(st, R.j_acc, R.sub_last ? 1 : 0, R.dt_sub);
+            if (st) st->err_est = R.err;
+            const double rem = tau - R.t_done;
+            if (R.sub_last || !(rem > 1e-15 * tau)) {
+                if (!R.sub_last && st && st->log && st->log_len >= 1 && st->log_len <= st->log_cap)
+                    st->log[st->log_len - 1].last = 1;
+                if (st) st->m_next = next.take_a ? mt : next.m_b;
+                break;
+            }
+            if (next.take_a)
+                dtau = next.dtau_a;
+            else {
+                mt = next.m_b;
+                dtau = R.dt_sub;
+            }
+        }
+        CO_HIPTRY(launch_copy(V, out, n, s));
+        if (!nested) CO_TRY(co_await x.finish(m));
+        co_return EXPDG_OK;
+    }
 
     double dtau = tau;
     bool reaches_end = true;

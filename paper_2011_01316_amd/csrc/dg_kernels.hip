@@ -142,6 +142,22 @@ __device__ __forceinline__ void euler_jac_lin_dir(const T *w, const T *d, T gm1,
     for (int c = 0; c < 4; ++c) f[c] = DIR == 0 ? fx[c] : fy[c];
 }
 
+// Wall mirror of a state or direction (both momenta reversed).
+template <typename T>
+__device__ __forceinline__ void wall_mirror(const T *q, T *out) {
+    out[0] = q[0];
+    out[1] = -q[1];
+    out[2] = -q[2];
+    out[3] = q[3];
+}
+
+// |v| + a at a wall from the frozen fields (u, v, H) of the reference state:
+// a^2 = (g-1)(H - |u|^2/2) = gamma p / rho (the mirror has the same speed).
+template <typename T>
+__device__ __forceinline__ T wall_speed_lin(const T *z, T gm1) {
+    return fabs(z[1]) + sqrt(gm1 * (z[2] - T(0.5) * (z[0] * z[0] + z[1] * z[1])));
+}
+
 // Load of base[off] through a 32-bit byte offset from a block-uniform base
 // (one addressing instruction instead of 64-bit index arithmetic); callers
 // keep every plane below 2^32 bytes.
@@ -411,9 +427,25 @@ __device__ __forceinline__ void euler_op_body(const OpArgs<T> &a, int tile, bool
                 lx = fmax(euler_speed<T, 0>(q, a.gamma), euler_speed<T, 0>(qn, a.gamma));
             }
         }
+        const bool wy = ony && a.ywall && ((sy < 0 && ey == 0) || (sy > 0 && ey == a.ny - 1));
         if (ony) {
             T qn[4];
-            if (JVP) {
+            if (wy) {
+                // no-slip wall: the mirror state
+                if (JVP) {
+                    qn[0] = -q[0];
+                    qn[1] = -q[1];
+                    qn[2] = q[2];
+                    wall_mirror(u, uny);
+                    euler_jac_lin_dir<T, 1>(qn, uny, gm1, fny);
+                    ly = wall_speed_lin(q, gm1);
+                } else {
+                    wall_mirror(q, qn);
+                    wall_mirror(q, uny);
+                    euler_flux_dir<T, 1>(qn, gm1, fny);
+                    ly = euler_speed<T, 1>(q, a.gamma);
+                }
+            } else if (JVP) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) qn[c] = ld32(src[c], niy);
 #pragma unroll
@@ -458,7 +490,18 @@ __device__ __forceinline__ void euler_op_body(const OpArgs<T> &a, int tile, bool
                     fnx[c] -= nun * g;
                 }
             }
-            if (ony) {
+            if (wy) {
+                // wall: v** = (v + M v)/2; the mirror's diffusive flux is
+                // -M (nu g), so the face flux is the interior one for the
+                // momenta and zero for density and energy
+                const T cf = a.rhy * a.lift * T(sy);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) gy[c] += cf * (T(0.5) * (u[c] + uny[c]) - u[c]);
+                fny[0] += nuv * gy[0];
+                fny[1] -= nuv * gy[1];
+                fny[2] -= nuv * gy[2];
+                fny[3] += nuv * gy[3];
+            } else if (ony) {
                 const T cf = a.rhy * a.lift * T(sy);
 #pragma unroll
                 for (int c = 0; c < 4; ++c) gy[c] += cf * (T(0.5) * (u[c] + uny[c]) - u[c]);
@@ -544,8 +587,24 @@ __device__ __forceinline__ void euler_op_body(const OpArgs<T> &a, int tile, bool
             eyn = eyn < 0 ? a.ny - 1 : (eyn >= a.ny ? 0 : eyn);
             const int en = eyn * a.nx + ex;
             const unsigned nidx = (unsigned)en * NP + (P - j) * N1 + i;
+            const bool wall = a.ywall && ((s < 0 && ey == 0) || (s > 0 && ey == a.ny - 1));
             T qn[4], un[4], fn[4], lam;
-            if (JVP) {
+            if (wall) {
+                // no-slip wall: the mirror state
+                if (JVP) {
+                    qn[0] = -q[0];
+                    qn[1] = -q[1];
+                    qn[2] = q[2];
+                    wall_mirror(u, un);
+                    euler_jac_lin_dir<T, 1>(qn, un, gm1, fn);
+                    lam = wall_speed_lin(q, gm1);
+                } else {
+                    wall_mirror(q, qn);
+                    wall_mirror(q, un);
+                    euler_flux_dir<T, 1>(qn, gm1, fn);
+                    lam = euler_speed<T, 1>(q, a.gamma);
+                }
+            } else if (JVP) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) qn[c] = ld32(src[c], nidx);
 #pragma unroll
@@ -680,13 +739,18 @@ __global__ __launch_bounds__(256) void ev_element_kernel(EvParams ep, const doub
         }
         if (j == 0 || j == P) {
             const int s = (j == P) ? 1 : -1;
-            const int eyn = (ey + s + ep.ny) % ep.ny;
-            const size_t nidx = (size_t)(eyn * ep.nx + ex) * NP + (P - j) * N1 + i;
-            double qn[4], Sn, fxn, fyn;
+            if (ep.ywall && ((s < 0 && ey == 0) || (s > 0 && ey == ep.ny - 1))) {
+                // wall: the mirror carries -v S
+                jmax = fmax(jmax, fabs(fy - (-fy)));
+            } else {
+                const int eyn = (ey + s + ep.ny) % ep.ny;
+                const size_t nidx = (size_t)(eyn * ep.nx + ex) * NP + (P - j) * N1 + i;
+                double qn[4], Sn, fxn, fyn;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) qn[c] = q[c * plane + nidx];
-            ev_entropy(qn, ep.gamma, &Sn, &fxn, &fyn);
-            jmax = fmax(jmax, fabs(fy - fyn));
+                for (int c = 0; c < 4; ++c) qn[c] = q[c * plane + nidx];
+                ev_entropy(qn, ep.gamma, &Sn, &fxn, &fyn);
+                jmax = fmax(jmax, fabs(fy - fyn));
+            }
         }
     }
     if (tid < NT) {
@@ -718,13 +782,20 @@ __global__ __launch_bounds__(256) void ev_smooth_kernel(EvParams ep, const doubl
     const int i = n % N1, j = n / N1;
     const int nx = ep.nx, ny = ep.ny;
     const int ex = e % nx, ey = e / nx;
-    // vertex (vx, vy) is the lower-left corner of element (vx, vy)
+    // vertex (vx, vy) is the lower-left corner of element (vx, vy); with walls
+    // the vertices on y0 and y1 average the two elements they belong to
+    const bool walls = ep.ywall != 0;
     auto vert = [&](int vx, int vy) {
-        const int xm = (vx + nx - 1) % nx, ym = (vy + ny - 1) % ny;
+        const int xm = (vx + nx - 1) % nx;
+        if (walls && (vy == 0 || vy == ny)) {
+            const int ew = vy == 0 ? 0 : ny - 1;
+            return 0.5 * (nue[ew * nx + vx] + nue[ew * nx + xm]);
+        }
+        const int ym = (vy + ny - 1) % ny;
         return 0.25 * ((nue[vy * nx + vx] + nue[vy * nx + xm]) +
                        (nue[ym * nx + vx] + nue[ym * nx + xm]));
     };
-    const int xp = (ex + 1) % nx, yp = (ey + 1) % ny;
+    const int xp = (ex + 1) % nx, yp = walls ? ey + 1 : (ey + 1) % ny;
     const double v00 = vert(ex, ey), v10 = vert(xp, ey), v01 = vert(ex, yp), v11 = vert(xp, yp);
     const double r = 0.5 * (ep.xi[i] + 1.0), s = 0.5 * (ep.xi[j] + 1.0);
     nu[t] = (T)((1.0 - r) * (1.0 - s) * v00 + r * (1.0 - s) * v10 + (1.0 - r) * s * v01 +
@@ -1023,7 +1094,8 @@ __global__ __launch_bounds__(E3Shape<P>::BS) void euler3_op(OpArgs<T> a) {
 // the LGL lift 1/w_0 at the end nodes:
 //   convective face flux: Lax-Friedrichs with lambda = max(|u~^-|, |u~^+|), or
 //     (residual, ef) the entropy flux n (u^-^2 + u^- u^+ + u^+^2)/6 +
-//     ef_pen (u^- - u^+);
+//     pen (u^- - u^+), pen = ef_pen, or ef_pen + max(|u^-|, |u^+|) with
+//     ef_local (the face-dependent penalty of Section 5.1's steep gradient);
 //   VISC (kappa > 0): the auxiliary q of the differentiated field z (u for the
 //     residual, v for the linear operator) is formed in LDS for the block's
 //     elements and the two adjacent face nodes of the neighbouring elements:
@@ -1142,8 +1214,8 @@ __device__ __forceinline__ void burgers_op_body(const OpArgs<T> &a, int tile, bo
         const T fn = JVP ? qn * un : T(0.5) * qn * qn;
         const T fc = JVP ? qv * uv : T(0.5) * qv * qv;
         if (!JVP && a.ef) {
-            const T fs = T(s) * (qv * qv + qv * qn + qn * qn) * T(1.0 / 6.0) +
-                         a.ef_pen * (qv - qn);
+            const T pen = a.ef_local ? a.ef_pen + fmax(fabs(qv), fabs(qn)) : a.ef_pen;
+            const T fs = T(s) * (qv * qv + qv * qn + qn * qn) * T(1.0 / 6.0) + pen * (qv - qn);
             res -= a.rhx * a.lift * (fs - T(s) * fc);
         } else {
             const T lam = fmax(fabs(qv), fabs(qn));

@@ -54,10 +54,14 @@ struct OpArgs {
     T ef_pen;          // 2 sigma / hx
     T beta;
     int ef;            // nonzero: entropy flux for (u^2/2)*
+    int ef_local;      // nonzero: the penalty is ef_pen + max|u^+-| at each face
     int dirichlet;     // nonzero: u = 0 beyond both ends
     const T *src;
     // Entropy viscosity (2D Euler): nodal viscosity nu, or nullptr
     const T *nu;
+    // Euler 2D: nonzero for no-slip walls at y0 and y1 (exterior state at a
+    // wall face node: the mirror, both momenta reversed)
+    int ywall;
     T D[(kMaxP + 1) * (kMaxP + 1)];  // D[i*(p+1)+l] = l_l'(xi_i)
 };
 
@@ -109,6 +113,7 @@ hipError_t launch_dg_op_group(int equation, int p, bool jvp, bool visc,
 // reconstruction at the nodes into nu (bulk type).
 struct EvParams {
     int K, nx, ny, p;
+    int ywall;  // no-slip walls at y0 and y1
     double rhx, rhy, lift, gamma, dt, ce, cmax, he;
     double xi[kMaxP + 1];                // LGL nodes (bilinear reconstruction)
     double D[(kMaxP + 1) * (kMaxP + 1)];  // D[i*(p+1)+l] = l_l'(xi_i)

@@ -140,12 +140,16 @@ OpArgs<T> op_args(const expdg_mesh *m) {
     for (int k = 0; k < m->n1 * m->n1; ++k) a.D[k] = (T)m->D[k];
     a.eta = 1.0;
     a.kappa = (T)m->d.kappa;
-    a.ef_pen = (T)(2.0 * m->d.sigma / m->hx);
+    // entropy flux penalty sigma / (h/2): constant, or kappa/100 + (h/2) max|u^+-|
+    // per face (the kernel adds max|u^+-| to 2 kappa / (100 h))
+    a.ef_local = m->d.flux == EXPDG_FLUX_EF_LOCAL;
+    a.ef_pen = (T)(a.ef_local ? 2.0 * m->d.kappa / (100.0 * m->hx) : 2.0 * m->d.sigma / m->hx);
     a.beta = (T)m->d.beta;
-    a.ef = m->d.flux == EXPDG_FLUX_EF;
+    a.ef = m->d.flux != EXPDG_FLUX_LF;
     a.dirichlet = m->d.bc == EXPDG_BC_DIRICHLET;
     a.src = (const T *)m->src;
     a.nu = (const T *)m->nu;
+    a.ywall = m->d.equation == EXPDG_EULER2D && m->d.bc == EXPDG_BC_WALL_Y;
     return a;
 }
 
@@ -156,6 +160,7 @@ inline EvParams ev_params(const expdg_mesh *m, double dt) {
     ep.nx = m->d.nx;
     ep.ny = m->d.ny;
     ep.p = m->d.p;
+    ep.ywall = m->d.bc == EXPDG_BC_WALL_Y;
     ep.rhx = 2.0 / m->hx;
     ep.rhy = 2.0 / m->hy;
     ep.lift = 1.0 / m->w[0];

@@ -208,6 +208,7 @@ bool request_sizes(const expdg_request *r, size_t *ws, size_t *st, const char **
         return *why = "need 1 <= m_min <= m_max <= mesh.m_max", false;
     if (r->check_every < 1) return *why = "check_every must be >= 1", false;
     if (r->iop < 0 || r->iop > kMaxM) return *why = "iop must be in 0..64", false;
+    if (r->adapt != 0 && r->adapt != 1) return *why = "adapt must be 0 or 1", false;
     const Sizes sz = sizes_of(&d);
     *ws = Arena::round(sz.total);
     *st = Arena::round(sz.stride * 8) * 2;
@@ -490,7 +491,7 @@ int admit(expdg_server *sv) {
         // asynchronously)
         HIPTRY(hipMemcpyAsync(r->q, r->q0.data(), r->mesh.n * 8, hipMemcpyHostToDevice, sv->s));
         r->opts = expdg_krylov_opts{r->rq.tol, r->rq.m_min, r->rq.m_max, r->rq.check_every,
-                                    nullptr, 0, r->rq.iop};
+                                    nullptr, 0, r->rq.iop, r->rq.adapt, 0};
         r->state = EXPDG_REQ_ACTIVE;
         r->t_admit = sv->now();
         r->x.sv = sv;

@@ -65,7 +65,8 @@ def lgl_textbook(p):
     return xi, w, Vx @ np.linalg.inv(V)
 
 
-def entropy_viscosity_2d(q, q_prev, dt, nx, ny, p, box, ce, cmax, gamma=1.4, parts=False):
+def entropy_viscosity_2d(q, q_prev, dt, nx, ny, p, box, ce, cmax, gamma=1.4, parts=False,
+                         walls=False):
     """Entropy viscosity of Section 3.2 ("Artificial viscosity" and its
     footnotes) on a periodic nx x ny mesh of box = (x0, x1, y0, y1), written
     out from the definitions with numpy:
@@ -79,6 +80,9 @@ def entropy_viscosity_2d(q, q_prev, dt, nx, ny, p, box, ce, cmax, gamma=1.4, par
       nu_max = c_max h max(|f'(q)|) = c_max h max over its nodes of |u.e_d| + a;
       Smooth: vertex averages of min(nu_max, nu_E), then the bilinear
       interpolant on each element.
+    With walls (no-slip at y0 and y1, periodic in x): the face beyond a wall
+    carries the mirror state (v reversed), so its jump is 2 |v S|, and a wall
+    vertex averages the two elements it belongs to.
     Returns the nodal viscosity in the library's layout (and, with parts, the
     per-element maxima rmax, jmax, the wave speed and h)."""
     x0, x1, y0, y1 = box
@@ -108,19 +112,29 @@ def entropy_viscosity_2d(q, q_prev, dt, nx, ny, p, box, ce, cmax, gamma=1.4, par
     # x faces: the right face of element ex against the left face of ex+1
     jx = np.abs(F1[:, :, :, p] - np.roll(F1, -1, axis=1)[:, :, :, 0]).max(axis=2)
     jy = np.abs(G1[:, :, p, :] - np.roll(G1, -1, axis=0)[:, :, 0, :]).max(axis=2)
-    jmax = np.maximum(np.maximum(jx, np.roll(jx, 1, axis=1)),
-                      np.maximum(jy, np.roll(jy, 1, axis=0)))
+    jy_below = np.roll(jy, 1, axis=0)
+    if walls:
+        jy[-1] = np.abs(2.0 * G1[-1, :, p, :]).max(axis=1)     # top wall
+        jy_below[0] = np.abs(2.0 * G1[0, :, 0, :]).max(axis=1)  # bottom wall
+    jmax = np.maximum(np.maximum(jx, np.roll(jx, 1, axis=1)), np.maximum(jy, jy_below))
     nu_E = ce * h * h * np.maximum(rmax, jmax / h)
     nu_max = cmax * h * lam.max(axis=(2, 3))
     nue = np.minimum(nu_max, nu_E)
     # vertex (vy, vx): lower-left corner of element (vy, vx)
-    vert = 0.25 * (nue + np.roll(nue, 1, axis=1) + np.roll(nue, 1, axis=0) +
-                   np.roll(np.roll(nue, 1, axis=0), 1, axis=1))
+    row = 0.5 * (nue + np.roll(nue, 1, axis=1))  # the two elements left/right of a vertex
+    if walls:
+        vert = np.empty((ny + 1, nx))
+        vert[1:ny] = 0.5 * (row[1:] + row[:-1])
+        vert[0], vert[ny] = row[0], row[ny - 1]
+        up = vert[1:]
+    else:
+        vert = 0.5 * (row + np.roll(row, 1, axis=0))
+        up = np.roll(vert, -1, axis=0)
     r = 0.5 * (xi + 1.0)
-    v00 = vert[:, :, None, None]
-    v10 = np.roll(vert, -1, axis=1)[:, :, None, None]
-    v01 = np.roll(vert, -1, axis=0)[:, :, None, None]
-    v11 = np.roll(np.roll(vert, -1, axis=0), -1, axis=1)[:, :, None, None]
+    v00 = vert[:ny, :, None, None]
+    v10 = np.roll(vert[:ny], -1, axis=1)[:, :, None, None]
+    v01 = up[:, :, None, None]
+    v11 = np.roll(up, -1, axis=1)[:, :, None, None]
     R, T = r[None, None, None, :], r[None, None, :, None]  # [j, i]: x weight r_i, y weight r_j
     nu = ((1 - R) * (1 - T) * v00 + R * (1 - T) * v10 + (1 - R) * T * v01 + R * T * v11)
     nu = nu.reshape(-1)

@@ -63,7 +63,8 @@ def standalone(req, q0):
     q = torch.tensor(q0, dtype=torch.float64, device="cuda")
     qp = torch.zeros_like(q)
     dt = req.dt if req.dt > 0 else req.cfl * m.dx_min / m.max_speed(q)
-    o = B.make_opts(req.tol, req.m_min, req.m_max, req.check_every, iop=req.iop)
+    o = B.make_opts(req.tol, req.m_min, req.m_max, req.check_every, iop=req.iop,
+                    adapt=req.adapt)
     for k in range(req.nsteps):
         m.step(req.scheme, dt, q, qp if req.scheme == B.EPI3 else None, k > 0, o)
     torch.cuda.synchronize()

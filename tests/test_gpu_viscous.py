@@ -52,6 +52,10 @@ OPTS = {
     "ef_ldg_per": dict(kappa=0.2, flux=1, sigma=0.01, beta=0.5),
     "lf_ldgm_per": dict(kappa=0.2, beta=-0.5),
     "ef_inviscid_dir": dict(flux=1, sigma=1e-3, bc=1),
+    # the face-dependent penalty sigma = kappa/100 + h max|u^+-| (Section 5.1,
+    # steep gradient)
+    "eflocal_central_dir": dict(kappa=0.002, flux=2, bc=1),
+    "eflocal_ldg_per": dict(kappa=0.05, flux=2, beta=0.5),
 }
 
 
@@ -202,3 +206,28 @@ def test_temporal_table_on_gpu():
                          B.make_opts(1e-12, 5, 64))
             err = math.sqrt(float(np.sum(M * (host(q) - ref) ** 2)))
             assert abs(err / err_p - 1.0) <= 5e-3, (name, dt, err, err_p)
+
+
+def test_shock_temporal_table_on_gpu():
+    """Table expo-burgers-tconv-shock (Section 5.1, steep gradient: kappa =
+    0.002, k = 4, N_e = 160, LF and the entropy flux with the face-dependent
+    penalty) through expdg_integrate: the GPU's EPI2 and EXPRB32 errors at
+    t = 1 against the reference of the paper's discretization (k = 10,
+    N_e = 160; tests/golden, written by the oracle) within 0.5 % of the
+    printed ones (EXPRB32 at dt = 0.02 within 10 %, as for the oracle)."""
+    from tests.test_oracle_shock import _error, _read, _reference
+    ref = _reference()
+    for r in _read("burgers_viscous_shock_tconv.txt"):
+        flux = B.FLUX_LF if r[0] == "LF" else B.FLUX_EF_LOCAL
+        dt = float(r[1])
+        print(f"shock table: flux {r[0]} dt {dt}", flush=True)
+        with B.Mesh(B.BURGERS1D, 160, 4, x0=0.0, x1=1.0, kappa=0.002, bc=B.BC_DIRICHLET,
+                    flux=flux) as gm:
+            x = gm.nodes()[0]
+            for col, scheme in ((3, B.EPI2), (4, B.EXPRB32)):
+                q = dev(np.sin(2.0 * math.pi * x))
+                gm.integrate(scheme, dt, int(round(1.0 / dt)), q, None, False,
+                             B.make_opts(1e-10, 5, 64))
+                e = _error(host(q), 4, 160, ref)
+                tolr = 0.10 if (scheme == B.EXPRB32 and dt == 0.02) else 0.005
+                assert abs(e / float(r[col]) - 1.0) <= tolr, (r[0], dt, scheme, e, r[col])

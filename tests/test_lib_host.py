@@ -86,12 +86,19 @@ def test_burgers_options_validation():
     # the source vector takes one more bulk vector of the workspace
     assert B.expdg_workspace_bytes(desc(**visc, has_source=1)) > ok
     for bad in [dict(kappa=-1.0), dict(kappa=float("nan")), dict(sigma=-1e-3), dict(beta=0.75),
-                dict(beta=-0.6), dict(flux=2), dict(bc=2)]:
+                dict(beta=-0.6), dict(flux=3), dict(bc=2), dict(bc=3)]:
         assert B.expdg_workspace_bytes(desc(**dict(burg, **bad))) == 0, bad
+    # the face-dependent entropy-flux penalty is a Burgers flux
+    assert B.expdg_workspace_bytes(desc(**dict(burg, flux=B.FLUX_EF_LOCAL))) == ok
     # Euler takes none of the Burgers options
-    for bad in [dict(kappa=0.1), dict(flux=B.FLUX_EF), dict(sigma=1e-3), dict(beta=0.5),
-                dict(bc=B.BC_DIRICHLET), dict(has_source=1)]:
+    for bad in [dict(kappa=0.1), dict(flux=B.FLUX_EF), dict(flux=B.FLUX_EF_LOCAL),
+                dict(sigma=1e-3), dict(beta=0.5), dict(bc=B.BC_DIRICHLET), dict(has_source=1)]:
         assert B.expdg_workspace_bytes(desc(**bad)) == 0, bad
+    # no-slip walls: Euler 2D only
+    assert B.expdg_workspace_bytes(desc(bc=B.BC_WALL_Y)) > 0
+    e3w = dict(equation=B.EULER3D, nx=4, ny=4, nz=2, p=2, x1=1.0, y1=1.0, z1=1.0,
+               bc=B.BC_WALL_Y)
+    assert B.expdg_workspace_bytes(desc(**e3w)) == 0
 
 
 def test_euler3d_validation():

@@ -8,7 +8,9 @@ coefficient, a broken augmented shift or scaling, a wrong stepper
 coefficient, a wrong quadrature weight, a wrong entropy-flux coefficient, a
 flipped LDG switch, a wrong Dirichlet trace, and in the entropy viscosity a
 dropped half on the mean divergence, h instead of h^2, a missing 1/h on the
-face jump and a wrong element size.
+face jump and a wrong element size, and a loose acceptance in the cost-based
+Krylov adaptivity, a slip mirror or a diffusive flux through a wall, and half
+the face-dependent entropy-flux penalty.
 """
 import os
 import shutil
@@ -16,14 +18,17 @@ import shutil
 import pytest
 
 import oracle
+from tests import test_oracle_adapt as ad
 from tests import test_oracle_dg as dg
 from tests import test_oracle_euler3d as e3
 from tests import test_oracle_ev as ev
 from tests import test_oracle_iop as iop
 from tests import test_oracle_phi as phi
 from tests import test_oracle_refelem as refelem
+from tests import test_oracle_shock as sh
 from tests import test_oracle_steppers as steppers
 from tests import test_oracle_viscous as viscous
+from tests import test_oracle_walls as wl
 
 MUTATIONS = {
     "dissipation_sign": ("dg.cpp", "0.5 * lam * (um[c] - up[c])", "0.5 * lam * (up[c] - um[c])",
@@ -71,6 +76,15 @@ MUTATIONS = {
     "ev_h_circumradius": ("dg.cpp", "std::sqrt(g.hx * g.hx + g.hy * g.hy) / p",
                           "std::fmax(g.hx, g.hy) / p",
                           lambda: ev.test_nu_E_smooth_state_with_element_jumps(0.05, 1e9)),
+    "adapt_acceptance": ("krylov.cpp", "const bool ok = om <= 1.0;", "const bool ok = om <= 1e4;",
+                         lambda: ad.test_adapt_accuracy_and_checks("burgers", 30.0, 2, 0)),
+    "wall_slip_mirror": ("dg.cpp", "    out[1] = -q[1];", "    out[1] = q[1];",
+                         lambda: wl.test_constant_state_wall_flux_is_textbook_rusanov()),
+    "wall_diffusive_flux": ("dg.cpp", "(double)s * (0.0 - fm);", "(double)s * (fm - fm);",
+                            lambda: wl.test_diffusion_with_walls_symmetric_negative(3)),
+    "ef_local_penalty": ("dg.cpp", "2.0 * g.kappa / (100.0 * g.hx) + lam",
+                         "2.0 * g.kappa / (100.0 * g.hx) + 0.5 * lam",
+                         lambda: sh.test_local_penalty_piecewise_constant(0.0)),
     "iop_window": ("krylov.cpp", "std::max(0, j - iop)", "std::max(0, j - iop - 1)",
                    lambda: iop.test_arnoldi_relation_and_band(2)),
     "lgl_weight": ("refelem.cpp", "w[i] = 2.0 / (p * (p + 1.0) * P * P);",
