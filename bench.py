@@ -429,6 +429,62 @@ def run_kh(args):
     return dict(workload=w["name"], ndof=m.n, runs=runs, paper_seconds=KH_PAPER_SECONDS)
 
 
+C5 = dict(nx=512, ny=512, p=4, cr=5.0, steps=100, tol=1e-7, m_min=10, m_max=64,
+          name="shear layer, periodic [0,1]^2, 512x512 quads, LGL p=4 (26,214,400 DOF), density "
+               "2:1, seeded 1e-2 velocity perturbation, EPI3 at Courant 5, 100 steps, tol 1e-7")
+
+
+def run_c5(args):
+    """The shear layer as configured: 100 EPI3 steps in FP32 bulk (FP64
+    Arnoldi), and the same 100 steps in FP64 for the difference; finiteness,
+    mass and energy drift."""
+    import numpy as np
+    import torch
+
+    from paper_2011_01316_amd import binding as B
+    from paper_2011_01316_amd import inputs
+
+    w = C5
+    out = dict(workload=w["name"], steps=w["steps"])
+    states = {}
+    for name, prec in (("fp32_bulk", B.FP32_BULK), ("fp64", B.FP64)):
+        m = B.Mesh(B.EULER2D, w["nx"], w["p"], ny=w["ny"], m_max=w["m_max"], precision=prec)
+        x, y = m.nodes()
+        q0h = inputs.shear_layer(x, y, seed=0).reshape(-1)
+        del x, y
+        _, wq, _ = B.expdg_lgl(w["p"])
+        wn = np.tile(np.outer(wq, wq).reshape(-1) * (m.hx * m.hy / 4.0), m.K)
+        npts = m.K * m.Np
+        q = torch.tensor(q0h, dtype=torch.float64, device="cuda:0")
+        qp = torch.empty_like(q)
+        dt = w["cr"] * m.dx_min / m.max_speed(q)
+        st = B.make_stats()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m.integrate(B.EPI3, dt, w["steps"], q, qp, False,
+                    B.make_opts(w["tol"], w["m_min"], w["m_max"]), st)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        d = B.stats_dict(st)
+        qh = q.cpu().numpy()
+        drift = max(abs(float(wn @ (qh[c * npts:(c + 1) * npts] - q0h[c * npts:(c + 1) * npts]))) /
+                    abs(float(wn @ q0h[c * npts:(c + 1) * npts])) for c in (0, 3))
+        out[name] = dict(ms_per_step=round(secs / w["steps"] * 1e3, 3), dt=dt,
+                         value=round(m.n * (d["rhs_calls"] + d["jvps"]) / secs, 1), unit=UNIT,
+                         krylov_iters_per_step=d["krylov_iters"] / w["steps"],
+                         finite=bool(np.all(np.isfinite(qh))), mass_energy_drift=drift,
+                         min_density=float(qh[:npts].min()))
+        states[name] = qh
+        log(f"512^2 p=4 shear layer, 100 EPI3 steps, {name}: {out[name]['ms_per_step']} ms/step")
+        m.close()
+        del q, qp
+    a, b = states["fp32_bulk"], states["fp64"]
+    out["fp32_l2_rel_diff_vs_fp64"] = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    out["step_time_ratio_fp64_over_fp32"] = round(out["fp64"]["ms_per_step"] /
+                                                  out["fp32_bulk"]["ms_per_step"], 3)
+    return out
+
+
 def run_shear_ev(args):
     """The 512 x 512 shear layer: EPI3 steps with and without the viscosity,
     then two instrumented steps with it."""
@@ -985,6 +1041,7 @@ def main():
         line["euler3d_paper_strong_scaling"] = run_euler3d(args)
     if not args.no_ev:
         line["entropy_viscosity"] = run_ev(args)
+        line["shear_layer_512x512_p4_100_steps"] = run_c5(args)
     if not args.no_serve:
         line["served"] = run_served(args)
         if not args.no_iop:

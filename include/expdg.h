@@ -393,7 +393,11 @@ typedef struct expdg_server expdg_server; /* opaque, library-owned */
 
 typedef struct {
     expdg_mesh_desc mesh; /* precision must be EXPDG_FP64; device is ignored
-                             (the server's device is used) */
+                             (the server's device is used); no source term,
+                             not 3D; entropy viscosity (ev_ce > 0) and walls as
+                             for expdg_step, the viscosity of each step from
+                             q^n and q^{n-1} (q^n on the first) for EPI2 and
+                             EPI3 alike */
     int scheme;           /* EXPDG_EPI2 or EXPDG_EPI3 (first step EPI2) */
     int nsteps;           /* >= 1 */
     double dt;            /* > 0: the step; <= 0: cfl * dx_min / max wave speed of q0 */

@@ -417,9 +417,9 @@ class Mesh:
 def make_request(equation, nx, p, ny=1, scheme=EPI3, nsteps=20, dt=0.0, cfl=0.0, tol=1e-10,
                  m_min=10, m_max=64, check_every=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0,
                  gamma=1.4, mesh_m_max=64, kappa=0.0, flux=FLUX_LF, sigma=0.0, beta=0.0,
-                 bc=BC_PERIODIC, iop=0, adapt=0):
+                 bc=BC_PERIODIC, iop=0, adapt=0, ev_ce=0.0, ev_cmax=0.0):
     return Request(MeshDesc(equation, nx, ny, p, FP64, 0, x0, x1, y0, y1, gamma, mesh_m_max,
-                            kappa, flux, sigma, beta, bc, 0, 1, 0.0, 1.0),
+                            kappa, flux, sigma, beta, bc, 0, 1, 0.0, 1.0, ev_ce, ev_cmax),
                    scheme, nsteps, dt, cfl, tol, m_min, m_max, check_every, iop, adapt)
 
 

@@ -32,10 +32,33 @@ __device__ __forceinline__ int xcd_tile(int b, int G) {
 }
 
 // ---- Euler physics --------------------------------------------------------
+// Reciprocal and square root of the flux and wave-speed evaluations: the
+// hardware approximation refined by Newton steps (within an ulp or two of the
+// rounded result).  The IEEE-exact FP64 division and square root expand to
+// sequences several times longer, and the residual, which evaluates the full
+// flux and the Rusanov speeds at every face node, is bound by them.
+__device__ __forceinline__ double recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ float recip(float x) {
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+__device__ __forceinline__ double root(double y) {
+    const double r = __builtin_amdgcn_rsq(y);  // about 1/sqrt(y)
+    const double h = 0.5 * r;
+    double s = y * r;
+    s = fma(h, fma(-s, s, y), s);
+    return fma(h, fma(-s, s, y), s);
+}
+__device__ __forceinline__ float root(float y) { return sqrtf(y); }
+
 // Physical fluxes F_x, F_y of q = (rho, m, n, E), m = rho u, n = rho v.
 template <typename T>
 __device__ __forceinline__ void euler_flux(const T *q, T gm1, T *fx, T *fy) {
-    const T ir = T(1) / q[0];
+    const T ir = recip(q[0]);
     const T u = q[1] * ir, v = q[2] * ir;
     const T p = gm1 * (q[3] - T(0.5) * (q[1] * u + q[2] * v));
     fx[0] = q[1];
@@ -53,7 +76,7 @@ __device__ __forceinline__ void euler_flux(const T *q, T gm1, T *fx, T *fy) {
 // the flux Jacobian of Section 3.2 applied to d.
 template <typename T>
 __device__ __forceinline__ void euler_jac(const T *q, const T *d, T gm1, T *fx, T *fy) {
-    const T ir = T(1) / q[0];
+    const T ir = recip(q[0]);
     const T u = q[1] * ir, v = q[2] * ir;
     const T p = gm1 * (q[3] - T(0.5) * (q[1] * u + q[2] * v));
     const T H = (q[3] + p) * ir;
@@ -71,7 +94,7 @@ __device__ __forceinline__ void euler_jac(const T *q, const T *d, T gm1, T *fx, 
 // One direction only (for the neighbour trace).
 template <typename T, int DIR>
 __device__ __forceinline__ void euler_flux_dir(const T *q, T gm1, T *f) {
-    const T ir = T(1) / q[0];
+    const T ir = recip(q[0]);
     const T u = q[1] * ir, v = q[2] * ir;
     const T p = gm1 * (q[3] - T(0.5) * (q[1] * u + q[2] * v));
     const T un = DIR == 0 ? u : v;
@@ -83,7 +106,7 @@ __device__ __forceinline__ void euler_flux_dir(const T *q, T gm1, T *f) {
 
 template <typename T, int DIR>
 __device__ __forceinline__ void euler_jac_dir(const T *q, const T *d, T gm1, T *f) {
-    const T ir = T(1) / q[0];
+    const T ir = recip(q[0]);
     const T u = q[1] * ir, v = q[2] * ir;
     const T p = gm1 * (q[3] - T(0.5) * (q[1] * u + q[2] * v));
     const T H = (q[3] + p) * ir;
@@ -104,10 +127,10 @@ __device__ __forceinline__ void euler_jac_dir(const T *q, const T *d, T gm1, T *
 // |u . e_dir| + a, a = sqrt(gamma p / rho).
 template <typename T, int DIR>
 __device__ __forceinline__ T euler_speed(const T *q, T gamma) {
-    const T ir = T(1) / q[0];
+    const T ir = recip(q[0]);
     const T u = q[1] * ir, v = q[2] * ir;
     const T p = (gamma - T(1)) * (q[3] - T(0.5) * (q[1] * u + q[2] * v));
-    return fabs(DIR == 0 ? u : v) + sqrt(gamma * p * ir);
+    return fabs(DIR == 0 ? u : v) + root(gamma * p * ir);
 }
 
 // The same directional derivatives from the frozen fields w = (u, v, H) of
@@ -155,7 +178,7 @@ __device__ __forceinline__ void wall_mirror(const T *q, T *out) {
 // a^2 = (g-1)(H - |u|^2/2) = gamma p / rho (the mirror has the same speed).
 template <typename T>
 __device__ __forceinline__ T wall_speed_lin(const T *z, T gm1) {
-    return fabs(z[1]) + sqrt(gm1 * (z[2] - T(0.5) * (z[0] * z[0] + z[1] * z[1])));
+    return fabs(z[1]) + root(gm1 * (z[2] - T(0.5) * (z[0] * z[0] + z[1] * z[1])));
 }
 
 // Load of base[off] through a 32-bit byte offset from a block-uniform base
@@ -188,7 +211,7 @@ __global__ __launch_bounds__(256) void euler_lin_prepare(const T *q, T *lin, int
     T qq[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) qq[c] = q[c * plane + t];
-    const T ir = T(1) / qq[0];
+    const T ir = recip(qq[0]);
     const T u = qq[1] * ir, v = qq[2] * ir;
     const T p = (gamma - T(1)) * (qq[3] - T(0.5) * (qq[1] * u + qq[2] * v));
     lin[t] = u;
@@ -811,7 +834,7 @@ __global__ __launch_bounds__(256) void ev_smooth_kernel(EvParams ep, const doubl
 // Physical flux along DIR.
 template <typename T, int DIR>
 __device__ __forceinline__ void euler3_flux_dir(const T *q, T gm1, T *f) {
-    const T ir = T(1) / q[0];
+    const T ir = recip(q[0]);
     const T u = q[1] * ir, v = q[2] * ir, w = q[3] * ir;
     const T p = gm1 * (q[4] - T(0.5) * (q[1] * u + q[2] * v + q[3] * w));
     const T un = DIR == 0 ? u : (DIR == 1 ? v : w);
@@ -824,10 +847,10 @@ __device__ __forceinline__ void euler3_flux_dir(const T *q, T gm1, T *f) {
 
 template <typename T, int DIR>
 __device__ __forceinline__ T euler3_speed(const T *q, T gamma) {
-    const T ir = T(1) / q[0];
+    const T ir = recip(q[0]);
     const T u = q[1] * ir, v = q[2] * ir, w = q[3] * ir;
     const T p = (gamma - T(1)) * (q[4] - T(0.5) * (q[1] * u + q[2] * v + q[3] * w));
-    return fabs(DIR == 0 ? u : (DIR == 1 ? v : w)) + sqrt(gamma * p * ir);
+    return fabs(DIR == 0 ? u : (DIR == 1 ? v : w)) + root(gamma * p * ir);
 }
 
 // Directional derivative of the flux along DIR from the frozen fields
@@ -876,7 +899,7 @@ __global__ __launch_bounds__(256) void euler3_lin_prepare(const T *q, T *lin, in
     T qq[5];
 #pragma unroll
     for (int c = 0; c < 5; ++c) qq[c] = q[c * plane + t];
-    const T ir = T(1) / qq[0];
+    const T ir = recip(qq[0]);
     const T u = qq[1] * ir, v = qq[2] * ir, w = qq[3] * ir;
     const T p = (gamma - T(1)) * (qq[4] - T(0.5) * (qq[1] * u + qq[2] * v + qq[3] * w));
     lin[t] = u;
@@ -1256,12 +1279,12 @@ __global__ __launch_bounds__(256) void burgers_op(OpArgs<T> a) {
     burgers_op_body<P, T, JVP, VISC>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.x == 0);
 }
 
-template <int P, typename T, bool JVP>
+template <int P, typename T, bool JVP, bool EV>
 __global__ __launch_bounds__(256) void euler_op_group(const OpArgs<T> *items, const int *bstart,
                                                       int n) {
     const int it = group_item(bstart, n, blockIdx.x);
     const int local = blockIdx.x - bstart[it], G = bstart[it + 1] - bstart[it];
-    euler_op_body<P, T, JVP>(items[it], xcd_tile(local, G), local == 0);
+    euler_op_body<P, T, JVP, EV>(items[it], xcd_tile(local, G), local == 0);
 }
 
 template <int P, typename T, bool JVP, bool VISC>
@@ -1287,11 +1310,19 @@ hipError_t launch_group_p(int equation, bool jvp, bool visc, const OpArgs<T> *it
                           const int *bstart, int n, int total, hipStream_t s) {
     if (equation == EXPDG_EULER3D) return hipErrorInvalidValue;  // not served
     if (equation == EXPDG_EULER2D) {
+        // visc: the items carry an entropy viscosity
+        if (visc) {
+            if (jvp)
+                return launch_kernel(euler_op_group<P, T, true, true>, dim3(total), dim3(256), 0,
+                                     s, items, bstart, n);
+            return launch_kernel(euler_op_group<P, T, false, true>, dim3(total), dim3(256), 0, s,
+                                 items, bstart, n);
+        }
         if (jvp)
-            return launch_kernel(euler_op_group<P, T, true>, dim3(total), dim3(256), 0, s, items,
-                                 bstart, n);
-        return launch_kernel(euler_op_group<P, T, false>, dim3(total), dim3(256), 0, s, items,
-                             bstart, n);
+            return launch_kernel(euler_op_group<P, T, true, false>, dim3(total), dim3(256), 0, s,
+                                 items, bstart, n);
+        return launch_kernel(euler_op_group<P, T, false, false>, dim3(total), dim3(256), 0, s,
+                             items, bstart, n);
     }
     if (visc) return launch_burgers_group<P, T, true>(jvp, items, bstart, n, total, s);
     return launch_burgers_group<P, T, false>(jvp, items, bstart, n, total, s);
@@ -1541,7 +1572,7 @@ int dg_blocks(int equation, int p, int K) {
 hipError_t launch_dg_op_group(int equation, int p, bool jvp, bool visc,
                               const OpArgs<double> *items, const int *bstart, int n, int total,
                               hipStream_t s) {
-    if (visc && equation != EXPDG_BURGERS1D) return hipErrorInvalidValue;
+    if (visc && equation == EXPDG_EULER3D) return hipErrorInvalidValue;
     switch (p) {
         case 1: return launch_group_p<1, double>(equation, jvp, visc, items, bstart, n, total, s);
         case 2: return launch_group_p<2, double>(equation, jvp, visc, items, bstart, n, total, s);

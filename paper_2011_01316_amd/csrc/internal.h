@@ -104,7 +104,8 @@ int dg_blocks(int equation, int p, int K);
 int dg_block_threads(int equation, int p);
 // Grouped FP64 launch over n meshes of the same equation and degree: item it
 // owns blocks [bstart[it], bstart[it+1]) (device arrays), total = bstart[n].
-// visc selects the viscous Burgers kernels (every item then has kappa > 0).
+// visc selects the viscous Burgers kernels (every item then has kappa > 0), or
+// for Euler 2D the kernels with entropy viscosity (every item has nu).
 hipError_t launch_dg_op_group(int equation, int p, bool jvp, bool visc,
                               const OpArgs<double> *items, const int *bstart, int n, int total,
                               hipStream_t s);

@@ -196,7 +196,6 @@ bool request_sizes(const expdg_request *r, size_t *ws, size_t *st, const char **
     if (d.precision != EXPDG_FP64) return *why = "served solves are FP64", false;
     if (d.has_source) return *why = "served solves take no source term", false;
     if (d.equation == EXPDG_EULER3D) return *why = "served solves are 1D or 2D", false;
-    if (d.ev_ce > 0.0) return *why = "served solves take no entropy viscosity", false;
     if (r->scheme != EXPDG_EPI2 && r->scheme != EXPDG_EPI3)
         return *why = "scheme must be EXPDG_EPI2 or EXPDG_EPI3", false;
     if (r->nsteps < 1) return *why = "nsteps must be >= 1", false;
@@ -358,7 +357,8 @@ Task<int> serve_co(ServeExec &x, Req *r) {
     } else {
         r->dt = r->rq.dt;
     }
-    double *qp = (r->rq.scheme == EXPDG_EPI3) ? r->qp : nullptr;
+    // the history: EPI3, and the entropy viscosity's q^{n-1}
+    double *qp = (r->rq.scheme == EXPDG_EPI3 || m->d.ev_ce > 0.0) ? r->qp : nullptr;
     for (int k = 0; k < r->rq.nsteps; ++k) {
         CO_AWAIT_TASK((step_co<double, ServeExec>(x, m, r->rq.scheme, r->dt, r->q, qp, k > 0,
                                                   &r->opts, &r->stats)));
@@ -590,7 +590,8 @@ int launch_batch(expdg_server *sv) {
     std::vector<Group> groups;
     for (const IterRec &it : sv->iters) {
         const int eq = it.r->mesh.d.equation, p = it.r->mesh.d.p;
-        const bool visc = it.r->mesh.d.kappa != 0.0;
+        // viscous Burgers, or Euler 2D with entropy viscosity
+        const bool visc = it.r->mesh.d.kappa != 0.0 || it.r->mesh.d.ev_ce > 0.0;
         Group *g = nullptr;
         for (auto &x : groups)
             if (x.eq == eq && x.p == p && x.visc == visc) g = &x;

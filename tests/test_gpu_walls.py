@@ -115,3 +115,32 @@ def test_kh_steps_with_walls(scheme):
         for c_ in (0, 3):
             a, b = M @ q0[c_ * npts:(c_ + 1) * npts], M @ qh[c_ * npts:(c_ + 1) * npts]
             assert abs(a - b) <= 1e-12 * abs(a), c_
+
+
+def test_served_viscosity_and_walls_bitwise():
+    """Served solves with entropy viscosity and walls (grouped launches of the
+    viscous operator, mixed with inviscid and periodic solves) are bitwise
+    equal to expdg_step on their own meshes (history passed for EPI2 too, so
+    each step's viscosity sees q^{n-1})."""
+    from tests.test_gpu_serve import burgers_case, euler_case, serve_all
+    print("served viscosity and walls", flush=True)
+    kh = []
+    for (nx, ny, p, scheme, bc) in [(8, 4, 3, B.EPI2, B.BC_WALL_Y), (6, 6, 2, B.EPI3, B.BC_WALL_Y),
+                                    (8, 4, 3, B.EPI3, B.BC_PERIODIC)]:
+        r = B.make_request(B.EULER2D, nx, p, ny=ny, scheme=scheme, nsteps=3, cfl=4.0, tol=1e-10,
+                           m_min=10, m_max=64, bc=bc, ev_ce=1.0, ev_cmax=0.1, **DOM)
+        m = B.Mesh(B.EULER2D, nx, p, ny=ny, bc=bc, ev_ce=1.0, ev_cmax=0.1, **DOM)
+        q0 = kh_state(m)
+        kh.append((r, q0, m))
+    plain = [burgers_case(40, 2, 0.3), euler_case(10, 3, 4.0, 6.0, 3.0)]
+    cases = [(r, q0) for (r, q0, _) in kh] + plain
+    with B.Server(hbm_budget=1 << 30, max_active=8) as srv:
+        got = serve_all(srv, cases)
+    for k, (r, q0, m) in enumerate(kh):
+        with m:
+            q = dev(q0)
+            qp = torch.empty_like(q)
+            dt = r.cfl * m.dx_min / m.max_speed(q)
+            for s in range(r.nsteps):
+                m.step(r.scheme, dt, q, qp, s > 0, B.make_opts(1e-10, 10, 64))
+            np.testing.assert_array_equal(host(q), got[k][0])

@@ -139,10 +139,14 @@ def test_entropy_viscosity_validation():
                 dict(equation=B.BURGERS1D, ny=1, ev_ce=1.0),
                 dict(equation=B.EULER3D, nz=2, ev_ce=1.0)]:
         assert B.expdg_workspace_bytes(desc(**bad)) == 0, bad
-    # served solves take no entropy viscosity
+    # served solves take the entropy viscosity (the workspace holds nu), not in 3D
     req = B.make_request(B.EULER2D, 8, 3, ny=8, nsteps=2, dt=1e-2, x1=10.0, y1=10.0)
-    req.mesh.ev_ce = 1.0
-    assert B.expdg_request_bytes(req) == 0
+    plain = B.expdg_request_bytes(req)
+    req.mesh.ev_ce, req.mesh.ev_cmax = 1.0, 0.1
+    assert B.expdg_request_bytes(req) > plain > 0
+    req3 = B.make_request(B.EULER3D, 4, 2, ny=4, nsteps=2, dt=1e-2, x1=1.0, y1=1.0)
+    req3.mesh.nz, req3.mesh.z1 = 2, 1.0
+    assert B.expdg_request_bytes(req3) == 0
 
 
 def test_served_request_orthogonalization_window():
