@@ -204,8 +204,7 @@ size_t layout(expdg_mesh *m, const expdg_mesh_desc *d, size_t stride, int eb, ch
     // m_max + 2 vectors: the step that finishes dimension m_max also writes the next one
     take(m->V, (size_t)(d->m_max + 2) * vb);
     for (auto &v : m->vec) take(v, vb);
-    if (d->precision == EXPDG_FP32_BULK)
-        for (auto &v : m->bq) take(v, vb);
+    if (d->precision == EXPDG_FP32_BULK) take(m->bq, vb);
     take(m->q2, stride * 8);
     if (d->has_source) take(m->src, vb);
     // elements of the mesh (nz counts in 3D only)

@@ -546,8 +546,12 @@ Task<int> phi_co(X &x, expdg_mesh *m, const T *qref, double tau, int p, const T 
 
 // One step of EPI2, EPI3 (Tokman's three-stage form; the first step, without
 // history, is EPI2) or EXPRB32 (the schemes of Section 5.1), on the FP64 state
-// q (and its history q_prev for EPI3).  The operator views are bulk copies in
-// FP32_BULK.
+// q (and its history q_prev for EPI3).  In FP32_BULK the residuals, the frozen
+// fields and the stage differences are formed from the FP64 states (rounding
+// the state first would put its rounding noise into every residual, and the
+// Krylov process would spend iterations resolving it); only the Krylov
+// vectors, the b vectors and the linear operator's reference state (Burgers)
+// are FP32.
 template <typename T, typename X>
 Task<int> step_co(X &x, expdg_mesh *m, int scheme, double dt, double *q, double *q_prev,
                   int have_prev, const expdg_krylov_opts *o, expdg_krylov_stats *st,
@@ -557,25 +561,32 @@ Task<int> step_co(X &x, expdg_mesh *m, int scheme, double dt, double *q, double 
     constexpr bool bulk = !std::is_same<T, double>::value;
     T *Rn = (T *)m->vec[0], *Rp = (T *)m->vec[1], *d = (T *)m->vec[2], *Ld = (T *)m->vec[3],
       *w = (T *)m->vec[4], *w2 = (T *)m->vec[5];
-    // operator views of the FP64 states
-    auto view = [&](double *src, int k, T **dst) -> hipError_t {
+    // operator view of the FP64 state q^n
+    auto view = [&](double *src, T **dst) -> hipError_t {
         if constexpr (!bulk) {
             *dst = (T *)src;
             return hipSuccess;
         } else {
-            *dst = (T *)m->bq[k];
+            *dst = (T *)m->bq;
             return launch_convert(src, (float *)*dst, n, s);
         }
+    };
+    T *qb = nullptr;
+    // residual of an FP64 state (FP32 storage: read in FP64, stored in FP32)
+    auto residual = [&](const double *state, T *out) -> int {
+        if constexpr (bulk)
+            return apply_op<T>(m, false, qb, nullptr, out, s, state);
+        else
+            return apply_op<T>(m, false, (const T *)state, nullptr, out, s);
     };
     int fpos = 0;
     // entropy viscosity of the step from q^n and q^{n-1} (q^n without history)
     if (m->nu)
         CO_TRY(entropy_viscosity<T>(m, q, (q_prev && have_prev) ? q_prev : q, dt, s));
-    T *qb = nullptr;
-    CO_HIPTRY(view(q, 0, &qb));
+    CO_HIPTRY(view(q, &qb));
     // every linear operator of the step is frozen at q^n
-    CO_HIPTRY(prepare_lin<T>(m, qb, s));
-    CO_TRY(apply_op<T>(m, false, qb, nullptr, Rn, s));
+    CO_HIPTRY(prepare_lin<T>(m, (const double *)q, s));
+    CO_TRY(residual(q, Rn));
     if (st) st->rhs_calls += 1;
 
     if (scheme == EXPDG_EPI2 || (scheme == EXPDG_EPI3 && !(q_prev && have_prev))) {
@@ -583,10 +594,8 @@ Task<int> step_co(X &x, expdg_mesh *m, int scheme, double dt, double *q, double 
         CO_AWAIT_TASK((phi_co<T, X>(x, m, qb, dt, 1, b, w, o, st, &fpos, true, true)));
         CO_HIPTRY(launch_step_update<T>(q, q_prev, w, n, s));
     } else if (scheme == EXPDG_EPI3) {
-        T *qpb = nullptr;
-        CO_HIPTRY(view(q_prev, 1, &qpb));
-        CO_TRY(apply_op<T>(m, false, qpb, nullptr, Rp, s));
-        CO_HIPTRY((launch_lincomb<T, T>(d, 1.0, qpb, -1.0, qb, 0.0, nullptr, n, s)));
+        CO_TRY(residual(q_prev, Rp));
+        CO_HIPTRY((launch_lincomb<T, double>(d, 1.0, q_prev, -1.0, q, 0.0, nullptr, n, s)));
         CO_TRY(apply_op<T>(m, true, qb, d, Ld, s));
         if (st) {
             st->rhs_calls += 1;
@@ -603,10 +612,8 @@ Task<int> step_co(X &x, expdg_mesh *m, int scheme, double dt, double *q, double 
         const T *b1[2] = {nullptr, Rn};
         CO_AWAIT_TASK((phi_co<T, X>(x, m, qb, 0.75 * dt, 1, b1, w, o, st, &fpos, true, true)));
         CO_HIPTRY(launch_add_mixed<T>(m->q2, q, w, n, s));  // q2 = q^n + w1
-        T *q2b = nullptr;
-        CO_HIPTRY(view(m->q2, 2, &q2b));
-        CO_TRY(apply_op<T>(m, false, q2b, nullptr, Rp, s));  // R(q2)
-        CO_HIPTRY((launch_lincomb<T, T>(d, 1.0, q2b, -1.0, qb, 0.0, nullptr, n, s)));
+        CO_TRY(residual(m->q2, Rp));                       // R(q2)
+        CO_HIPTRY((launch_lincomb<T, double>(d, 1.0, m->q2, -1.0, q, 0.0, nullptr, n, s)));
         CO_TRY(apply_op<T>(m, true, qb, d, Ld, s));
         if (st) {
             st->rhs_calls += 1;
@@ -622,10 +629,8 @@ Task<int> step_co(X &x, expdg_mesh *m, int scheme, double dt, double *q, double 
         const T *b1[2] = {nullptr, Rn};
         CO_AWAIT_TASK((phi_co<T, X>(x, m, qb, dt, 1, b1, w, o, st, &fpos, true, true)));
         CO_HIPTRY(launch_add_mixed<T>(m->q2, q, w, n, s));  // q2 = q^n + w1
-        T *q2b = nullptr;
-        CO_HIPTRY(view(m->q2, 2, &q2b));
-        CO_TRY(apply_op<T>(m, false, q2b, nullptr, Rp, s));  // R(q2)
-        CO_HIPTRY((launch_lincomb<T, T>(d, 1.0, q2b, -1.0, qb, 0.0, nullptr, n, s)));
+        CO_TRY(residual(m->q2, Rp));                       // R(q2)
+        CO_HIPTRY((launch_lincomb<T, double>(d, 1.0, m->q2, -1.0, q, 0.0, nullptr, n, s)));
         CO_TRY(apply_op<T>(m, true, qb, d, Ld, s));
         if (st) {
             st->rhs_calls += 1;

@@ -17,6 +17,8 @@
 // memory; the block -> tile map gives each XCD a contiguous range of
 // elements so y-neighbours (nx elements away) are usually resident in that
 // XCD's L2.
+#include <type_traits>
+
 #include "internal.h"
 #include "reduce.h"
 
@@ -32,6 +34,12 @@ __device__ __forceinline__ int xcd_tile(int b, int G) {
 }
 
 // ---- Euler physics --------------------------------------------------------
+// The operators compute in FP64 for both storage types: the FP32-bulk mode
+// loads FP32 vectors, computes in FP64 and rounds only what it stores, so the
+// linear operator stays linear up to the storage rounding of its output.
+// (With FP32 arithmetic the rounding inside the flux evaluations made the
+// Krylov process take 20-35% more iterations than FP64 at the same tolerance;
+// FP32 storage alone does not.)
 // Reciprocal and square root of the flux and wave-speed evaluations: the
 // hardware approximation refined by Newton steps (within an ulp or two of the
 // rounded result).  The IEEE-exact FP64 division and square root expand to
@@ -42,10 +50,6 @@ __device__ __forceinline__ double recip(double x) {
     r = fma(r, fma(-x, r, 1.0), r);
     return fma(r, fma(-x, r, 1.0), r);
 }
-__device__ __forceinline__ float recip(float x) {
-    const float r = __builtin_amdgcn_rcpf(x);
-    return fmaf(r, fmaf(-x, r, 1.0f), r);
-}
 __device__ __forceinline__ double root(double y) {
     const double r = __builtin_amdgcn_rsq(y);  // about 1/sqrt(y)
     const double h = 0.5 * r;
@@ -53,7 +57,6 @@ __device__ __forceinline__ double root(double y) {
     s = fma(h, fma(-s, s, y), s);
     return fma(h, fma(-s, s, y), s);
 }
-__device__ __forceinline__ float root(float y) { return sqrtf(y); }
 
 // Physical fluxes F_x, F_y of q = (rho, m, n, E), m = rho u, n = rho v.
 template <typename T>
@@ -199,9 +202,10 @@ __device__ __forceinline__ void st32(T *base, unsigned off, T v) {
 // once per reference state): planes u, v, H, then the Rusanov speed of every
 // x face, lamx[e (p+1) + j] = max(|u|+a) over the face between element e and
 // its x+ neighbour at node row j, and of every y face, lamy[e (p+1) + i].
-template <int P, typename T>
-__global__ __launch_bounds__(256) void euler_lin_prepare(const T *q, T *lin, int K, int nx, int ny,
-                                                         T gamma) {
+template <int P, typename Q, typename S>
+__global__ __launch_bounds__(256) void euler_lin_prepare(const Q *q, S *lin, int K, int nx, int ny,
+                                                         double gamma) {
+    using T = double;  // arithmetic; S is the storage type
     constexpr int N1 = P + 1, NP = N1 * N1;
     const size_t plane = (size_t)K * NP;
     const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
@@ -214,10 +218,10 @@ __global__ __launch_bounds__(256) void euler_lin_prepare(const T *q, T *lin, int
     const T ir = recip(qq[0]);
     const T u = qq[1] * ir, v = qq[2] * ir;
     const T p = (gamma - T(1)) * (qq[3] - T(0.5) * (qq[1] * u + qq[2] * v));
-    lin[t] = u;
-    lin[plane + t] = v;
-    lin[2 * plane + t] = (qq[3] + p) * ir;
-    T *lamx = lin + 3 * plane, *lamy = lamx + (size_t)K * N1;
+    lin[t] = (S)u;
+    lin[plane + t] = (S)v;
+    lin[2 * plane + t] = (S)((qq[3] + p) * ir);
+    S *lamx = lin + 3 * plane, *lamy = lamx + (size_t)K * N1;
     const int ex = e % nx, ey = e / nx;
     if (i == P) {
         const int en = ey * nx + (ex + 1 == nx ? 0 : ex + 1);
@@ -225,7 +229,7 @@ __global__ __launch_bounds__(256) void euler_lin_prepare(const T *q, T *lin, int
         T qn[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) qn[c] = q[c * plane + nidx];
-        lamx[(size_t)e * N1 + j] = fmax(euler_speed<T, 0>(qq, gamma), euler_speed<T, 0>(qn, gamma));
+        lamx[(size_t)e * N1 + j] = (S)fmax(euler_speed<T, 0>(qq, gamma), euler_speed<T, 0>(qn, gamma));
     }
     if (j == P) {
         const int en = (ey + 1 == ny ? 0 : ey + 1) * nx + ex;
@@ -233,7 +237,7 @@ __global__ __launch_bounds__(256) void euler_lin_prepare(const T *q, T *lin, int
         T qn[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) qn[c] = q[c * plane + nidx];
-        lamy[(size_t)e * N1 + i] = fmax(euler_speed<T, 1>(qq, gamma), euler_speed<T, 1>(qn, gamma));
+        lamy[(size_t)e * N1 + i] = (S)fmax(euler_speed<T, 1>(qq, gamma), euler_speed<T, 1>(qn, gamma));
     }
 }
 
@@ -246,8 +250,8 @@ __global__ __launch_bounds__(256) void euler_lin_prepare(const T *q, T *lin, int
 // instead of three and the FP32-bulk 2D operator at five instead of four.
 template <typename T, int NV, int NW = 4, int CH = 16>
 __device__ __forceinline__ void op_dots2(const OpArgs<T> &a, bool active, unsigned idx,
-                                         size_t plane, const T *xv, const T *wv, int tile,
-                                         bool first) {
+                                         size_t plane, const double *xv, const double *wv,
+                                         int tile, bool first) {
     static_assert(NW == 4 || NW == 6, "blocks of 256 or 384 threads");
     static_assert(CH == 16 || CH == 8, "chunks of 16 or 8 vectors");
     __shared__ double sw[NW][32];
@@ -261,7 +265,7 @@ __device__ __forceinline__ void op_dots2(const OpArgs<T> &a, bool active, unsign
     const size_t ntot = NV * plane;
     const int nv = a.nv;
     const bool tail = first && tid == 0 && a.naug > 0;
-    const T sc = a.vscale ? (T)(*a.vscale) : T(1);
+    const double sc = a.vscale ? *a.vscale : 1.0;
     for (int i0 = 0; i0 < nv; i0 += CH) {
         double acc[2 * CH];
 #pragma unroll
@@ -296,7 +300,7 @@ __device__ __forceinline__ void op_dots2(const OpArgs<T> &a, bool active, unsign
         }
         if (tail) {
             for (int t = 0; t < a.naug; ++t) {
-                const T wt = (t + 1 < a.naug) ? sc * a.vtail[t + 1] : T(0);
+                const T wt = (t + 1 < a.naug) ? (T)(sc * (double)a.vtail[t + 1]) : T(0);
                 const T xt = a.vtail[t];
 #pragma unroll
                 for (int k = 0; k < CH; ++k)
@@ -333,7 +337,7 @@ __device__ __forceinline__ void op_dots2(const OpArgs<T> &a, bool active, unsign
     }
     if (tail) {
         for (int t = 0; t < a.naug; ++t) {
-            const T wt = (t + 1 < a.naug) ? sc * a.vtail[t + 1] : T(0);
+            const T wt = (t + 1 < a.naug) ? (T)(sc * (double)a.vtail[t + 1]) : T(0);
             const T xt = a.vtail[t];
             xx += (double)xt * (double)xt;
             xw += (double)xt * (double)wt;
@@ -359,8 +363,10 @@ __device__ __forceinline__ void op_dots2(const OpArgs<T> &a, bool active, unsign
 // residual the state itself.  Face and augmented terms need no LDS and are
 // added before the barrier; -(2/h) D is staged in LDS for the derivative.
 // Node offsets are 32-bit within one variable plane.
-template <int P, typename T, bool JVP, bool EV = false>
-__device__ __forceinline__ void euler_op_body(const OpArgs<T> &a, int tile, bool first) {
+template <int P, typename S, bool JVP, bool EV = false, typename Q = S>
+__device__ __forceinline__ void euler_op_body(const OpArgs<S> &a, int tile, bool first) {
+    using T = double;  // arithmetic; S is the storage type
+    static_assert(!JVP || std::is_same<Q, S>::value, "the linear operator reads stored vectors");
     constexpr int N1 = P + 1, NP = N1 * N1, EPB = 256 / NP, NT = EPB * NP;
     __shared__ T sF[8][NT];
     __shared__ T sDx[N1 * N1], sDy[N1 * N1];
@@ -377,12 +383,15 @@ __device__ __forceinline__ void euler_op_body(const OpArgs<T> &a, int tile, bool
         sDx[tid] = -a.rhx * a.D[tid];
         sDy[tid] = -a.rhy * a.D[tid];
     }
-    // block-uniform plane pointers
-    const T *src[4], *vin[4];
+    // block-uniform plane pointers; the residual reads the state as stored,
+    // or its FP64 copy (Q = double with FP32 storage)
+    const Q *qin = (const Q *)(std::is_same<Q, S>::value ? (const void *)a.q : (const void *)a.q64);
+    const Q *src[4], *vin[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        src[c] = (JVP ? a.lin : a.q) + c * plane;  // lin: u, v, H planes (the fourth unused)
-        vin[c] = JVP ? a.v + c * plane : src[c];
+        // lin: u, v, H planes (the fourth unused)
+        src[c] = (JVP ? (const Q *)(const void *)a.lin : qin) + c * plane;
+        vin[c] = JVP ? (const Q *)(const void *)a.v + c * plane : src[c];
     }
 
     T sc = T(1);
@@ -390,11 +399,11 @@ __device__ __forceinline__ void euler_op_body(const OpArgs<T> &a, int tile, bool
     // augmented entries of the output: (y_2, ..., y_p, 0), scaled
     if (a.naug > 0 && first && tid == 0) {
         for (int k = 0; k < a.naug; ++k)
-            a.otail[k] = (k + 1 < a.naug) ? sc * a.vtail[k + 1] : T(0);
+            a.otail[k] = (k + 1 < a.naug) ? (S)(sc * (T)a.vtail[k + 1]) : S(0);
     }
 
     const int ex = e % a.nx, ey = e / a.nx;
-    const T *lamx = a.lin + 3 * plane, *lamy = lamx + (size_t)a.K * N1;
+    const S *lamx = a.lin + 3 * plane, *lamy = lamx + (size_t)a.K * N1;
     T q[4], u[4], fx[4], fy[4];
     if (active) {
         if (JVP) {
@@ -649,7 +658,7 @@ __device__ __forceinline__ void euler_op_body(const OpArgs<T> &a, int tile, bool
     // augmented block: + eta sum_k y_k b_{p+1-k}
     if (active) {
         for (int k = 0; k < a.naug; ++k) {
-            const T *b = a.aug[k];
+            const S *b = a.aug[k];
             if (!b) continue;
             const T yk = (T)a.eta * a.vtail[k];
 #pragma unroll
@@ -669,19 +678,21 @@ __device__ __forceinline__ void euler_op_body(const OpArgs<T> &a, int tile, bool
             for (int c = 0; c < 4; ++c)
                 res[c] = fma(dy, sF[4 + c][base + l * N1 + i], fma(dx, sF[c][base + j * N1 + l], res[c]));
         }
-        T *out[4];
+        S *out[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) out[c] = a.out + c * plane;
+        // the dot pass sees the output as stored
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            wv[c] = sc * res[c];
-            st32(out[c], idx, wv[c]);
+            const S ws = (S)(sc * res[c]);
+            wv[c] = (T)ws;
+            st32(out[c], idx, ws);
         }
     } else {
 #pragma unroll
         for (int c = 0; c < 4; ++c) wv[c] = T(0);
     }
-    if (JVP && a.dots) op_dots2<T, 4, 4, 8>(a, active, idx, plane, u, wv, tile, first);
+    if (JVP && a.dots) op_dots2<S, 4, 4, 8>(a, active, idx, plane, u, wv, tile, first);
 }
 
 // ---- entropy viscosity (2D Euler) ---------------------------------------------
@@ -887,9 +898,10 @@ __device__ __forceinline__ void euler3_jac_lin_dir(const T *z, const T *d, T gm1
     }
 }
 
-template <int P, typename T>
-__global__ __launch_bounds__(256) void euler3_lin_prepare(const T *q, T *lin, int K, int nx,
-                                                          int ny, int nz, T gamma) {
+template <int P, typename Q, typename St>
+__global__ __launch_bounds__(256) void euler3_lin_prepare(const Q *q, St *lin, int K, int nx,
+                                                          int ny, int nz, double gamma) {
+    using T = double;  // arithmetic; St is the storage type
     constexpr int N1 = P + 1, NP = N1 * N1 * N1, NF = N1 * N1;
     const size_t plane = (size_t)K * NP;
     const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
@@ -902,11 +914,11 @@ __global__ __launch_bounds__(256) void euler3_lin_prepare(const T *q, T *lin, in
     const T ir = recip(qq[0]);
     const T u = qq[1] * ir, v = qq[2] * ir, w = qq[3] * ir;
     const T p = (gamma - T(1)) * (qq[4] - T(0.5) * (qq[1] * u + qq[2] * v + qq[3] * w));
-    lin[t] = u;
-    lin[plane + t] = v;
-    lin[2 * plane + t] = w;
-    lin[3 * plane + t] = (qq[4] + p) * ir;
-    T *lamx = lin + 4 * plane, *lamy = lamx + (size_t)K * NF, *lamz = lamy + (size_t)K * NF;
+    lin[t] = (St)u;
+    lin[plane + t] = (St)v;
+    lin[2 * plane + t] = (St)w;
+    lin[3 * plane + t] = (St)((qq[4] + p) * ir);
+    St *lamx = lin + 4 * plane, *lamy = lamx + (size_t)K * NF, *lamz = lamy + (size_t)K * NF;
     const int ex = e % nx, ey = (e / nx) % ny, ez = e / (nx * ny);
     T qn[5];
     if (i == P) {
@@ -914,24 +926,21 @@ __global__ __launch_bounds__(256) void euler3_lin_prepare(const T *q, T *lin, in
         const size_t nidx = (size_t)en * NP + (k * N1 + j) * N1;
 #pragma unroll
         for (int c = 0; c < 5; ++c) qn[c] = q[c * plane + nidx];
-        lamx[(size_t)e * NF + k * N1 + j] =
-            fmax(euler3_speed<T, 0>(qq, gamma), euler3_speed<T, 0>(qn, gamma));
+        lamx[(size_t)e * NF + k * N1 + j] = (St)fmax(euler3_speed<T, 0>(qq, gamma), euler3_speed<T, 0>(qn, gamma));
     }
     if (j == P) {
         const int en = (ez * ny + (ey + 1 == ny ? 0 : ey + 1)) * nx + ex;
         const size_t nidx = (size_t)en * NP + (k * N1) * N1 + i;
 #pragma unroll
         for (int c = 0; c < 5; ++c) qn[c] = q[c * plane + nidx];
-        lamy[(size_t)e * NF + k * N1 + i] =
-            fmax(euler3_speed<T, 1>(qq, gamma), euler3_speed<T, 1>(qn, gamma));
+        lamy[(size_t)e * NF + k * N1 + i] = (St)fmax(euler3_speed<T, 1>(qq, gamma), euler3_speed<T, 1>(qn, gamma));
     }
     if (k == P) {
         const int en = ((ez + 1 == nz ? 0 : ez + 1) * ny + ey) * nx + ex;
         const size_t nidx = (size_t)en * NP + j * N1 + i;
 #pragma unroll
         for (int c = 0; c < 5; ++c) qn[c] = q[c * plane + nidx];
-        lamz[(size_t)e * NF + j * N1 + i] =
-            fmax(euler3_speed<T, 2>(qq, gamma), euler3_speed<T, 2>(qn, gamma));
+        lamz[(size_t)e * NF + j * N1 + i] = (St)fmax(euler3_speed<T, 2>(qq, gamma), euler3_speed<T, 2>(qn, gamma));
     }
 }
 
@@ -946,11 +955,13 @@ struct E3Shape {
 
 // Face term of the node on the DIR face on side s: the neighbour's trace, its
 // flux and lambda; res -= (2/h)(1/w_0) [ s (F_n - F)/2 + lam (u - u_n)/2 ].
-template <int P, typename T, bool JVP, int DIR>
-__device__ __forceinline__ void euler3_face(const OpArgs<T> &a, const T *const *src,
-                                            const T *const *vin, const T *lamd, int e, int en,
-                                            unsigned nidx, int fidx, int s, T rh, const T *q,
-                                            const T *u, const T *fd, T gm1, T *res) {
+template <int P, typename St, bool JVP, int DIR, typename Q>
+__device__ __forceinline__ void euler3_face(const OpArgs<St> &a, const Q *const *src,
+                                            const Q *const *vin, const St *lamd, int e, int en,
+                                            unsigned nidx, int fidx, int s, double rh,
+                                            const double *q, const double *u, const double *fd,
+                                            double gm1, double *res) {
+    using T = double;
     T qn[5], un[5], fn[5], lam;
     if (JVP) {
 #pragma unroll
@@ -972,8 +983,10 @@ __device__ __forceinline__ void euler3_face(const OpArgs<T> &a, const T *const *
     for (int c = 0; c < 5; ++c) res[c] = fma(-cb, u[c] - un[c], fma(-ca, fn[c] - fd[c], res[c]));
 }
 
-template <int P, typename T, bool JVP>
-__device__ __forceinline__ void euler3_op_body(const OpArgs<T> &a, int tile, bool first) {
+template <int P, typename St, bool JVP, typename Q = St>
+__device__ __forceinline__ void euler3_op_body(const OpArgs<St> &a, int tile, bool first) {
+    using T = double;  // arithmetic; St is the storage type
+    static_assert(!JVP || std::is_same<Q, St>::value, "the linear operator reads stored vectors");
     using S = E3Shape<P>;
     constexpr int N1 = S::N1, NP = S::NP, NF = N1 * N1, EPB = S::EPB, NT = S::NT;
     __shared__ T sF[15][NT];
@@ -992,22 +1005,26 @@ __device__ __forceinline__ void euler3_op_body(const OpArgs<T> &a, int tile, boo
         sDy[tid] = -a.rhy * a.D[tid];
         sDz[tid] = -a.rhz * a.D[tid];
     }
-    const T *src[5], *vin[5];
+    // the residual reads the state as stored, or its FP64 copy (Q = double)
+    const Q *qin =
+        (const Q *)(std::is_same<Q, St>::value ? (const void *)a.q : (const void *)a.q64);
+    const Q *src[5], *vin[5];
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-        src[c] = (JVP ? a.lin : a.q) + c * plane;  // lin: u, v, w, H planes (the fifth unused)
-        vin[c] = JVP ? a.v + c * plane : src[c];
+        // lin: u, v, w, H planes (the fifth unused)
+        src[c] = (JVP ? (const Q *)(const void *)a.lin : qin) + c * plane;
+        vin[c] = JVP ? (const Q *)(const void *)a.v + c * plane : src[c];
     }
     T sc = T(1);
     if (a.vscale) sc = (T)(*a.vscale);
     if (a.naug > 0 && first && tid == 0) {
         for (int kk = 0; kk < a.naug; ++kk)
-            a.otail[kk] = (kk + 1 < a.naug) ? sc * a.vtail[kk + 1] : T(0);
+            a.otail[kk] = (kk + 1 < a.naug) ? (St)(sc * (T)a.vtail[kk + 1]) : St(0);
     }
     const int nxy = a.nx * a.ny;
     const int ex = e % a.nx, ey = (e / a.nx) % a.ny, ez = e / nxy;
-    const T *lamx = a.lin + 4 * plane, *lamy = lamx + (size_t)a.K * NF,
-            *lamz = lamy + (size_t)a.K * NF;
+    const St *lamx = a.lin + 4 * plane, *lamy = lamx + (size_t)a.K * NF,
+             *lamz = lamy + (size_t)a.K * NF;
     T q[5], u[5], fx[5], fy[5], fz[5];
     if (active) {
         if (JVP) {
@@ -1046,7 +1063,7 @@ __device__ __forceinline__ void euler3_op_body(const OpArgs<T> &a, int tile, boo
         exn = exn < 0 ? a.nx - 1 : (exn >= a.nx ? 0 : exn);
         const int en = ez * nxy + ey * a.nx + exn;
         const unsigned nidx = (unsigned)en * NP + (k * N1 + j) * N1 + (P - i);
-        euler3_face<P, T, JVP, 0>(a, src, vin, lamx, e, en, nidx, k * N1 + j, s, a.rhx, q, u, fx,
+        euler3_face<P, St, JVP, 0, Q>(a, src, vin, lamx, e, en, nidx, k * N1 + j, s, a.rhx, q, u, fx,
                                   gm1, res);
     }
     if (active && (j == 0 || j == P)) {
@@ -1055,7 +1072,7 @@ __device__ __forceinline__ void euler3_op_body(const OpArgs<T> &a, int tile, boo
         eyn = eyn < 0 ? a.ny - 1 : (eyn >= a.ny ? 0 : eyn);
         const int en = ez * nxy + eyn * a.nx + ex;
         const unsigned nidx = (unsigned)en * NP + (k * N1 + (P - j)) * N1 + i;
-        euler3_face<P, T, JVP, 1>(a, src, vin, lamy, e, en, nidx, k * N1 + i, s, a.rhy, q, u, fy,
+        euler3_face<P, St, JVP, 1, Q>(a, src, vin, lamy, e, en, nidx, k * N1 + i, s, a.rhy, q, u, fy,
                                   gm1, res);
     }
     if (active && (k == 0 || k == P)) {
@@ -1065,12 +1082,12 @@ __device__ __forceinline__ void euler3_op_body(const OpArgs<T> &a, int tile, boo
         ezn = ezn < 0 ? nz - 1 : (ezn >= nz ? 0 : ezn);
         const int en = ezn * nxy + ey * a.nx + ex;
         const unsigned nidx = (unsigned)en * NP + ((P - k) * N1 + j) * N1 + i;
-        euler3_face<P, T, JVP, 2>(a, src, vin, lamz, e, en, nidx, j * N1 + i, s, a.rhz, q, u, fz,
+        euler3_face<P, St, JVP, 2, Q>(a, src, vin, lamz, e, en, nidx, j * N1 + i, s, a.rhz, q, u, fz,
                                   gm1, res);
     }
     if (active) {
         for (int kk = 0; kk < a.naug; ++kk) {
-            const T *b = a.aug[kk];
+            const St *b = a.aug[kk];
             if (!b) continue;
             const T yk = (T)a.eta * a.vtail[kk];
 #pragma unroll
@@ -1093,21 +1110,23 @@ __device__ __forceinline__ void euler3_op_body(const OpArgs<T> &a, int tile, boo
                 res[c] = fma(dz, sF[10 + c][nzl],
                              fma(dy, sF[5 + c][nyl], fma(dx, sF[c][nxl], res[c])));
         }
+        // the dot pass sees the output as stored
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
-            wv[c] = sc * res[c];
-            st32(a.out + c * plane, idx, wv[c]);
+            const St ws = (St)(sc * res[c]);
+            wv[c] = (T)ws;
+            st32(a.out + c * plane, idx, ws);
         }
     } else {
 #pragma unroll
         for (int c = 0; c < 5; ++c) wv[c] = T(0);
     }
-    if (JVP && a.dots) op_dots2<T, 5, S::NW, 8>(a, active, idx, plane, u, wv, tile, first);
+    if (JVP && a.dots) op_dots2<St, 5, S::NW, 8>(a, active, idx, plane, u, wv, tile, first);
 }
 
-template <int P, typename T, bool JVP>
+template <int P, typename T, bool JVP, typename Q = T>
 __global__ __launch_bounds__(E3Shape<P>::BS) void euler3_op(OpArgs<T> a) {
-    euler3_op_body<P, T, JVP>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.x == 0);
+    euler3_op_body<P, T, JVP, Q>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.x == 0);
 }
 
 // ---- Burgers 1D operator ----------------------------------------------------
@@ -1128,8 +1147,13 @@ __global__ __launch_bounds__(E3Shape<P>::BS) void euler3_op(OpArgs<T> a) {
 //     q** = {{q}} + beta [[q]];
 //   dirichlet: beyond both ends z^+ = 0 for the convective fluxes, z** = 0 and
 //     q** = q^- (no diffusive face term).
-template <int P, typename T, bool JVP, bool VISC>
-__device__ __forceinline__ void burgers_op_body(const OpArgs<T> &a, int tile, bool first) {
+template <int P, typename S, bool JVP, bool VISC, typename Q = S>
+__device__ __forceinline__ void burgers_op_body(const OpArgs<S> &a, int tile, bool first) {
+    using T = double;  // arithmetic; S is the storage type
+    static_assert(!JVP || std::is_same<Q, S>::value, "the linear operator reads stored vectors");
+    // the state as stored, or (residual, Q = double) its FP64 copy
+    const Q *qs = (const Q *)(std::is_same<Q, S>::value ? (const void *)a.q : (const void *)a.q64);
+    const Q *vs = (const Q *)(const void *)a.v;
     constexpr int N1 = P + 1, EPB = 256 / N1, NT = EPB * N1;
     // VISC: slots 0 and nact + 1 hold the neighbouring elements (halo)
     constexpr int NS = VISC ? (EPB + 2) * N1 : 1;
@@ -1149,7 +1173,7 @@ __device__ __forceinline__ void burgers_op_body(const OpArgs<T> &a, int tile, bo
     if (a.vscale) sc = (T)(*a.vscale);
     if (a.naug > 0 && first && tid == 0) {
         for (int k = 0; k < a.naug; ++k)
-            a.otail[k] = (k + 1 < a.naug) ? sc * a.vtail[k + 1] : T(0);
+            a.otail[k] = (k + 1 < a.naug) ? (S)(sc * (T)a.vtail[k + 1]) : S(0);
     }
 
     T qv = T(0), uv = T(0), f = T(0);
@@ -1160,8 +1184,8 @@ __device__ __forceinline__ void burgers_op_body(const OpArgs<T> &a, int tile, bo
     bool bnd = false;
     T qn = T(0), un = T(0);
     if (active) {
-        qv = a.q[idx];
-        uv = JVP ? a.v[idx] : qv;
+        qv = qs[idx];
+        uv = JVP ? vs[idx] : qv;
         f = JVP ? qv * uv : T(0.5) * qv * qv;
     }
     if (face) {
@@ -1169,15 +1193,15 @@ __device__ __forceinline__ void burgers_op_body(const OpArgs<T> &a, int tile, bo
         bnd = dir && (en < 0 || en >= a.K);
         en = en < 0 ? a.K - 1 : (en >= a.K ? 0 : en);
         const size_t nidx = (size_t)en * N1 + (P - i);
-        qn = bnd ? T(0) : a.q[nidx];
-        un = JVP ? (bnd ? T(0) : a.v[nidx]) : qn;
+        qn = bnd ? T(0) : qs[nidx];
+        un = JVP ? (bnd ? T(0) : vs[nidx]) : qn;
     }
     const int nact = min(EPB, a.K - e0);  // elements of this block
     // neighbours of the block: -1 beyond a Dirichlet end
     int eLh = e0 - 1, eRh = e0 + nact;
     if (eLh < 0) eLh = dir ? -1 : a.K - 1;
     if (eRh >= a.K) eRh = dir ? -1 : 0;
-    const T *zsrc = JVP ? a.v : a.q;
+    const Q *zsrc = JVP ? vs : qs;
     T qgrad = T(0);
     if constexpr (VISC) {
         if (active) sZ[(le + 1) * N1 + i] = uv;
@@ -1258,25 +1282,27 @@ __device__ __forceinline__ void burgers_op_body(const OpArgs<T> &a, int tile, bo
     if (active) {
         if (!JVP && a.src) res += a.src[idx];
         for (int k = 0; k < a.naug; ++k) {
-            const T *b = a.aug[k];
+            const S *b = a.aug[k];
             if (!b) continue;
-            res += (T)a.eta * a.vtail[k] * b[idx];
+            res += (T)a.eta * (T)a.vtail[k] * (T)b[idx];
         }
-        wv = sc * res;
-        a.out[idx] = wv;
+        // the dot pass sees the output as stored
+        const S ws = (S)(sc * res);
+        wv = (T)ws;
+        a.out[idx] = ws;
     }
     if (JVP && a.dots)
-        op_dots2<T, 1>(a, active, (unsigned)idx, (size_t)a.K * N1, &uv, &wv, tile, first);
+        op_dots2<S, 1>(a, active, (unsigned)idx, (size_t)a.K * N1, &uv, &wv, tile, first);
 }
 
-template <int P, typename T, bool JVP, bool EV>
+template <int P, typename T, bool JVP, bool EV, typename Q = T>
 __global__ __launch_bounds__(256) void euler_op(OpArgs<T> a) {
-    euler_op_body<P, T, JVP, EV>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.x == 0);
+    euler_op_body<P, T, JVP, EV, Q>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.x == 0);
 }
 
-template <int P, typename T, bool JVP, bool VISC>
+template <int P, typename T, bool JVP, bool VISC, typename Q = T>
 __global__ __launch_bounds__(256) void burgers_op(OpArgs<T> a) {
-    burgers_op_body<P, T, JVP, VISC>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.x == 0);
+    burgers_op_body<P, T, JVP, VISC, Q>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.x == 0);
 }
 
 template <int P, typename T, bool JVP, bool EV>
@@ -1330,10 +1356,14 @@ hipError_t launch_group_p(int equation, bool jvp, bool visc, const OpArgs<T> *it
 
 template <int P, typename T>
 hipError_t launch_p(int equation, bool jvp, const OpArgs<T> &a, hipStream_t s) {
+    // FP32 storage: the residual of an FP64 state (a.q64) reads it directly
+    const bool r64 = !jvp && !std::is_same<T, double>::value && a.q64 != nullptr;
     if (equation == EXPDG_EULER3D) {
         using S = E3Shape<P>;
         const int grid = (a.K + S::EPB - 1) / S::EPB;
         if (jvp) return launch_kernel(euler3_op<P, T, true>, dim3(grid), dim3(S::BS), 0, s, a);
+        if (r64)
+            return launch_kernel(euler3_op<P, T, false, double>, dim3(grid), dim3(S::BS), 0, s, a);
         return launch_kernel(euler3_op<P, T, false>, dim3(grid), dim3(S::BS), 0, s, a);
     }
     if (equation == EXPDG_EULER2D) {
@@ -1342,19 +1372,31 @@ hipError_t launch_p(int equation, bool jvp, const OpArgs<T> &a, hipStream_t s) {
         if (a.nu) {
             if (jvp)
                 return launch_kernel(euler_op<P, T, true, true>, dim3(grid), dim3(256), 0, s, a);
+            if (r64)
+                return launch_kernel(euler_op<P, T, false, true, double>, dim3(grid), dim3(256),
+                                     0, s, a);
             return launch_kernel(euler_op<P, T, false, true>, dim3(grid), dim3(256), 0, s, a);
         }
         if (jvp) return launch_kernel(euler_op<P, T, true, false>, dim3(grid), dim3(256), 0, s, a);
+        if (r64)
+            return launch_kernel(euler_op<P, T, false, false, double>, dim3(grid), dim3(256), 0,
+                                 s, a);
         return launch_kernel(euler_op<P, T, false, false>, dim3(grid), dim3(256), 0, s, a);
     }
     constexpr int EPB = 256 / (P + 1);
     const int grid = (a.K + EPB - 1) / EPB;
-    if (a.kappa != T(0)) {
+    if (a.kappa != 0.0) {
         if (jvp)
             return launch_kernel(burgers_op<P, T, true, true>, dim3(grid), dim3(256), 0, s, a);
+        if (r64)
+            return launch_kernel(burgers_op<P, T, false, true, double>, dim3(grid), dim3(256), 0,
+                                 s, a);
         return launch_kernel(burgers_op<P, T, false, true>, dim3(grid), dim3(256), 0, s, a);
     }
     if (jvp) return launch_kernel(burgers_op<P, T, true, false>, dim3(grid), dim3(256), 0, s, a);
+    if (r64)
+        return launch_kernel(burgers_op<P, T, false, false, double>, dim3(grid), dim3(256), 0, s,
+                             a);
     return launch_kernel(burgers_op<P, T, false, false>, dim3(grid), dim3(256), 0, s, a);
 }
 
@@ -1515,20 +1557,20 @@ template hipError_t launch_ev_smooth<double>(const EvParams &, const double *, d
 template hipError_t launch_ev_smooth<float>(const EvParams &, const double *, float *,
                                             hipStream_t);
 
-template <typename T>
-hipError_t launch_lin_prepare(int equation, int p, const T *q, T *lin, int K, int nx, int ny,
+template <typename Q, typename T>
+hipError_t launch_lin_prepare(int equation, int p, const Q *q, T *lin, int K, int nx, int ny,
                               double gamma, hipStream_t s) {
     if (equation == EXPDG_EULER3D) {
         const size_t npts = (size_t)K * (p + 1) * (p + 1) * (p + 1);
         const dim3 grid((unsigned)((npts + 255) / 256));
         const int nz = K / (nx * ny);
         switch (p) {
-            case 1: return launch_kernel(euler3_lin_prepare<1, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, nz, (T)gamma);
-            case 2: return launch_kernel(euler3_lin_prepare<2, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, nz, (T)gamma);
-            case 3: return launch_kernel(euler3_lin_prepare<3, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, nz, (T)gamma);
-            case 4: return launch_kernel(euler3_lin_prepare<4, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, nz, (T)gamma);
-            case 5: return launch_kernel(euler3_lin_prepare<5, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, nz, (T)gamma);
-            case 6: return launch_kernel(euler3_lin_prepare<6, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, nz, (T)gamma);
+            case 1: return launch_kernel(euler3_lin_prepare<1, Q, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, nz, gamma);
+            case 2: return launch_kernel(euler3_lin_prepare<2, Q, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, nz, gamma);
+            case 3: return launch_kernel(euler3_lin_prepare<3, Q, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, nz, gamma);
+            case 4: return launch_kernel(euler3_lin_prepare<4, Q, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, nz, gamma);
+            case 5: return launch_kernel(euler3_lin_prepare<5, Q, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, nz, gamma);
+            case 6: return launch_kernel(euler3_lin_prepare<6, Q, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, nz, gamma);
             default: return hipErrorInvalidValue;
         }
     }
@@ -1536,19 +1578,21 @@ hipError_t launch_lin_prepare(int equation, int p, const T *q, T *lin, int K, in
     const size_t npts = (size_t)K * (p + 1) * (p + 1);
     const dim3 grid((unsigned)((npts + 255) / 256));
     switch (p) {
-        case 1: return launch_kernel(euler_lin_prepare<1, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, (T)gamma);
-        case 2: return launch_kernel(euler_lin_prepare<2, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, (T)gamma);
-        case 3: return launch_kernel(euler_lin_prepare<3, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, (T)gamma);
-        case 4: return launch_kernel(euler_lin_prepare<4, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, (T)gamma);
-        case 5: return launch_kernel(euler_lin_prepare<5, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, (T)gamma);
-        case 6: return launch_kernel(euler_lin_prepare<6, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, (T)gamma);
+        case 1: return launch_kernel(euler_lin_prepare<1, Q, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, gamma);
+        case 2: return launch_kernel(euler_lin_prepare<2, Q, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, gamma);
+        case 3: return launch_kernel(euler_lin_prepare<3, Q, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, gamma);
+        case 4: return launch_kernel(euler_lin_prepare<4, Q, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, gamma);
+        case 5: return launch_kernel(euler_lin_prepare<5, Q, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, gamma);
+        case 6: return launch_kernel(euler_lin_prepare<6, Q, T>, grid, dim3(256), 0, s, q, lin, K, nx, ny, gamma);
         default: return hipErrorInvalidValue;
     }
 }
-template hipError_t launch_lin_prepare<double>(int, int, const double *, double *, int, int, int,
-                                               double, hipStream_t);
-template hipError_t launch_lin_prepare<float>(int, int, const float *, float *, int, int, int,
-                                              double, hipStream_t);
+template hipError_t launch_lin_prepare<double, double>(int, int, const double *, double *, int,
+                                                       int, int, double, hipStream_t);
+template hipError_t launch_lin_prepare<float, float>(int, int, const float *, float *, int, int,
+                                                     int, double, hipStream_t);
+template hipError_t launch_lin_prepare<double, float>(int, int, const double *, float *, int, int,
+                                                      int, double, hipStream_t);
 
 size_t lin_elems(int equation, int p, int K) {
     const size_t n1 = (size_t)p + 1;

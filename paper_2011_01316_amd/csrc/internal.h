@@ -23,6 +23,10 @@ constexpr int kRedThreads = 256;
 template <typename T>
 struct OpArgs {
     const T *q;        // state (residual) or reference state (linear operator)
+    // FP32-bulk residual: the state in FP64, read instead of q when set (the
+    // residual of the FP32-rounded state carries that rounding's
+    // high-frequency noise, which the Krylov process would have to resolve)
+    const double *q64;
     const T *v;        // direction of the linear operator (nullptr for the residual)
     T *out;
     const T *aug[kMaxAug];  // aug[k-1] multiplies y_k: b_{p+1-k} (nullptr = zero)
@@ -43,16 +47,18 @@ struct OpArgs {
     double eta;        // scaling of the augmented block
     int naug;          // p
     int K, nx, ny;
-    T rhx, rhy, rhz;   // 2/hx, 2/hy, 2/hz
-    T lift;            // 1/w_0 (= 1/w_p)
-    T gamma;
+    // geometry and physics constants: FP64 for both storage types (the
+    // operators compute in FP64 and store in T)
+    double rhx, rhy, rhz;   // 2/hx, 2/hy, 2/hz
+    double lift;            // 1/w_0 (= 1/w_p)
+    double gamma;
     // Burgers options (Section 3.1): viscosity, entropy flux (residual only)
     // with jump coefficient sigma / (h/2), diffusion-flux switch beta
     // (0 central, 1/2 LDG), zero Dirichlet ends, and a source added to the
     // residual (nullptr = none).
-    T kappa;
-    T ef_pen;          // 2 sigma / hx
-    T beta;
+    double kappa;
+    double ef_pen;     // 2 sigma / hx
+    double beta;
     int ef;            // nonzero: entropy flux for (u^2/2)*
     int ef_local;      // nonzero: the penalty is ef_pen + max|u^+-| at each face
     int dirichlet;     // nonzero: u = 0 beyond both ends
@@ -62,7 +68,7 @@ struct OpArgs {
     // Euler 2D: nonzero for no-slip walls at y0 and y1 (exterior state at a
     // wall face node: the mirror, both momenta reversed)
     int ywall;
-    T D[(kMaxP + 1) * (kMaxP + 1)];  // D[i*(p+1)+l] = l_l'(xi_i)
+    double D[(kMaxP + 1) * (kMaxP + 1)];  // D[i*(p+1)+l] = l_l'(xi_i)
 };
 
 // Start/stop events that the next kernel launch of this host thread records as
@@ -94,8 +100,10 @@ hipError_t launch_dg_op(int equation, int p, bool jvp, const OpArgs<float> &a, h
 // Frozen fields of the 2D linear operator at the reference state q (planes u,
 // v, H, then the Rusanov speed of every x face and every y face; lin_elems
 // elements).  Burgers needs none (no-op, lin_elems = 0).
-template <typename T>
-hipError_t launch_lin_prepare(int equation, int p, const T *q, T *lin, int K, int nx, int ny,
+// The state may be FP64 for FP32 fields (an FP32-bulk step prepares them from
+// its FP64 state).
+template <typename Q, typename T>
+hipError_t launch_lin_prepare(int equation, int p, const Q *q, T *lin, int K, int nx, int ny,
                               double gamma, hipStream_t s);
 size_t lin_elems(int equation, int p, int K);
 // Blocks one operator launch uses for K elements.

@@ -28,7 +28,7 @@ struct expdg_mesh {
     bool owns_block = false;
     void *V = nullptr;           // (m_max+1) x stride bulk
     void *vec[6] = {};           // bulk work vectors (stride each)
-    void *bq[3] = {};            // bulk copies of FP64 states (FP32_BULK only)
+    void *bq = nullptr;          // bulk copy of the FP64 state q^n (FP32_BULK only)
     double *q2 = nullptr;        // FP64 stage state (EXPRB32)
     void *src = nullptr;         // source term of the residual (bulk type; has_source only)
     void *lin = nullptr;         // frozen fields of the 2D linear operator (bulk type)
@@ -132,19 +132,19 @@ OpArgs<T> op_args(const expdg_mesh *m) {
     a.K = m->K;
     a.nx = m->d.nx;
     a.ny = m->d.ny;
-    a.rhx = (T)(2.0 / m->hx);
-    a.rhy = (T)(2.0 / m->hy);
-    a.rhz = (T)(2.0 / m->hz);
-    a.lift = (T)(1.0 / m->w[0]);
-    a.gamma = (T)m->d.gamma;
-    for (int k = 0; k < m->n1 * m->n1; ++k) a.D[k] = (T)m->D[k];
+    a.rhx = 2.0 / m->hx;
+    a.rhy = 2.0 / m->hy;
+    a.rhz = 2.0 / m->hz;
+    a.lift = 1.0 / m->w[0];
+    a.gamma = m->d.gamma;
+    for (int k = 0; k < m->n1 * m->n1; ++k) a.D[k] = m->D[k];
     a.eta = 1.0;
-    a.kappa = (T)m->d.kappa;
+    a.kappa = m->d.kappa;
     // entropy flux penalty sigma / (h/2): constant, or kappa/100 + (h/2) max|u^+-|
     // per face (the kernel adds max|u^+-| to 2 kappa / (100 h))
     a.ef_local = m->d.flux == EXPDG_FLUX_EF_LOCAL;
-    a.ef_pen = (T)(a.ef_local ? 2.0 * m->d.kappa / (100.0 * m->hx) : 2.0 * m->d.sigma / m->hx);
-    a.beta = (T)m->d.beta;
+    a.ef_pen = a.ef_local ? 2.0 * m->d.kappa / (100.0 * m->hx) : 2.0 * m->d.sigma / m->hx;
+    a.beta = m->d.beta;
     a.ef = m->d.flux != EXPDG_FLUX_LF;
     a.dirichlet = m->d.bc == EXPDG_BC_DIRICHLET;
     a.src = (const T *)m->src;
@@ -194,11 +194,12 @@ int entropy_viscosity(expdg_mesh *m, const double *q, const double *q_prev, doub
     return EXPDG_OK;
 }
 
-// Frozen fields of the linear operator at the reference state q (into m->lin).
-template <typename T>
-hipError_t prepare_lin(expdg_mesh *m, const T *q, hipStream_t s) {
-    return launch_lin_prepare<T>(m->d.equation, m->d.p, q, (T *)m->lin, m->K, m->d.nx, m->d.ny,
-                                 m->d.gamma, s);
+// Frozen fields of the linear operator at the reference state q (into m->lin);
+// q may be the FP64 state of an FP32-bulk mesh.
+template <typename T, typename Q>
+hipError_t prepare_lin(expdg_mesh *m, const Q *q, hipStream_t s) {
+    return launch_lin_prepare<Q, T>(m->d.equation, m->d.p, q, (T *)m->lin, m->K, m->d.nx,
+                                    m->d.ny, m->d.gamma, s);
 }
 
 // Algorithmic bytes of one residual (jvp = false) or linear-operator
@@ -216,11 +217,14 @@ inline double op_bytes(const expdg_mesh *m, bool jvp) {
 
 
 // Residual (jvp = false) or linear operator of the mesh on stream s; the
-// linear operator needs the frozen fields of q prepared (prepare_lin).
+// linear operator needs the frozen fields of q prepared (prepare_lin).  q64
+// (FP32 storage, residual only): the state in FP64, read instead of q.
 template <typename T>
-int apply_op(expdg_mesh *m, bool jvp, const T *q, const T *v, T *out, hipStream_t s) {
+int apply_op(expdg_mesh *m, bool jvp, const T *q, const T *v, T *out, hipStream_t s,
+             const double *q64 = nullptr) {
     OpArgs<T> a = op_args<T>(m);
     a.q = q;
+    a.q64 = q64;
     a.v = v;
     a.out = out;
     a.lin = (const T *)m->lin;

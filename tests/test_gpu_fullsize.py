@@ -150,6 +150,11 @@ def test_operators_full_size_fp32_bulk(case):
         ew = np.max(np.abs(w.cpu().numpy().astype(np.float64) - wo))
         assert er <= bound_r, (er, bound_r)
         assert ew <= bound_w, (ew, bound_w)
+        # FP32 storage, FP64 arithmetic: the stored residual is the FP64 value
+        # rounded once to FP32 (the FP64 arithmetic's own c u64 S on top)
+        r64 = r.cpu().numpy().astype(np.float64)
+        tight = U32 * np.abs(ro) + operator_bounds(om, p, qd, vd, 2.0 ** -53)[0]
+        assert np.all(np.abs(r64 - ro) <= tight), np.max(np.abs(r64 - ro) - tight)
 
 
 def discrete_mass(om, q, p):
