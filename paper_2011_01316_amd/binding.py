@@ -99,8 +99,10 @@ KERNEL_CLASSES = {K_RESIDUAL: "residual", K_LINEAR: "linear_operator", K_GS_DOTS
                   K_GS_NORM: "gs_norm", K_GS_FINISH: "gs_finish", K_EV_VISC: "ev_visc",
                   K_GS_FOLD: "gs_fold"}
 # kernel symbol of each class, as rocprofv3 names it
+# kernels of the 64x64 p=4 vortex (410 operator blocks: the linear operator
+# runs as 512-thread blocks there; larger grids launch euler_op<p, T, true, false>)
 KERNEL_SYMBOLS = {"residual": "euler_op<4, double, false, false>",
-                  "linear_operator": "euler_op<4, double, true, false>",
+                  "linear_operator": "euler_op_halves<4, double>",
                   "gs_dots": "gs_dots2_kernel<double>", "small_expm": "hess_expm_kernel",
                   "combine": "combine_kernel<double>", "gs_update": "dcgs_update_kernel<double>",
                   "gs_norm": "gs_norm_kernel<double>",

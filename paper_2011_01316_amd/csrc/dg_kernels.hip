@@ -248,29 +248,39 @@ __global__ __launch_bounds__(256) void euler_lin_prepare(const Q *q, S *lin, int
 // CH basis vectors per chunk (2 CH FP64 accumulators per thread): the 2D and
 // 3D operators take 8, which keeps the 3D operator at four waves per SIMD
 // instead of three and the FP32-bulk 2D operator at five instead of four.
-template <typename T, int NV, int NW = 4, int CH = 16>
+template <typename T, int NV, int NW = 4, int CH = 16, int HV = 1>
 __device__ __forceinline__ void op_dots2(const OpArgs<T> &a, bool active, unsigned idx,
                                          size_t plane, const double *xv, const double *wv,
                                          int tile, bool first) {
     static_assert(NW == 4 || NW == 6, "blocks of 256 or 384 threads");
     static_assert(CH == 16 || CH == 8, "chunks of 16 or 8 vectors");
-    __shared__ double sw[NW][32];
+    static_assert(HV == 1 || (HV == 2 && NW == 4), "two halves of 256 threads");
+    // HV = 2: the block is two halves of NW waves over the same nodes (thread
+    // t and t + 256 hold node t); half h takes chunks h, h + 2, ...  A row's
+    // partial is still one half's NW waves in the same order, so the result
+    // equals that of one half taking every chunk.
+    __shared__ double sw[HV][NW][32];
     __shared__ double s2[NW][2];
     // fixed-order sum over the block's waves
     auto wsum = [](double v0, double v1, double v2, double v3, double v4, double v5) {
         const double s4 = (v0 + v1) + (v2 + v3);
         return NW == 4 ? s4 : s4 + (v4 + v5);
     };
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int h = HV == 2 ? (int)(threadIdx.x >> 8) : 0;
+    const int tid = HV == 2 ? (int)(threadIdx.x & 255) : (int)threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
     const size_t ntot = NV * plane;
     const int nv = a.nv;
     const bool tail = first && tid == 0 && a.naug > 0;
     const double sc = a.vscale ? *a.vscale : 1.0;
-    for (int i0 = 0; i0 < nv; i0 += CH) {
+    const int nch = (nv + CH - 1) / CH, iters = (nch + HV - 1) / HV;
+    for (int it = 0; it < iters; ++it) {
+        const int i0 = (it * HV + h) * CH;
+        const bool run = i0 < nv;  // this half has a chunk in this round
         double acc[2 * CH];
 #pragma unroll
         for (int k = 0; k < 2 * CH; ++k) acc[k] = 0.0;
-        if (active) {
+        if (active && run) {
             // loads in groups of KG vectors, all issued before their products
             // (vector index clamped, the extra sums dropped), so a group's
             // loads are in flight together
@@ -298,7 +308,7 @@ __device__ __forceinline__ void op_dots2(const OpArgs<T> &a, bool active, unsign
                 }
             }
         }
-        if (tail) {
+        if (tail && run) {
             for (int t = 0; t < a.naug; ++t) {
                 const T wt = (t + 1 < a.naug) ? (T)(sc * (double)a.vtail[t + 1]) : T(0);
                 const T xt = a.vtail[t];
@@ -313,20 +323,21 @@ __device__ __forceinline__ void op_dots2(const OpArgs<T> &a, bool active, unsign
         }
         if constexpr (CH == 16) {
             const double v = transpose_reduce32(acc);
-            if ((lane & 1) == 0) sw[wave][lane >> 1] = v;
+            if ((lane & 1) == 0) sw[h][wave][lane >> 1] = v;
         } else {
             const double v = transpose_reduce16(acc);
-            if ((lane & 3) == 0) sw[wave][lane >> 2] = v;
+            if ((lane & 3) == 0) sw[h][wave][lane >> 2] = v;
         }
         __syncthreads();
-        if (tid < 2 * CH && i0 + (tid % CH) < nv) {
+        if (run && tid < 2 * CH && i0 + (tid % CH) < nv) {
             const int row = (tid < CH) ? i0 + tid : nv + i0 + (tid - CH);
             a.dpart[(size_t)row * a.dnb + tile] =
-                wsum(sw[0][tid], sw[1][tid], sw[2][tid], sw[3][tid], sw[NW > 4 ? 4 : 0][tid],
-                     sw[NW > 5 ? 5 : 0][tid]);
+                wsum(sw[h][0][tid], sw[h][1][tid], sw[h][2][tid], sw[h][3][tid],
+                     sw[h][NW > 4 ? 4 : 0][tid], sw[h][NW > 5 ? 5 : 0][tid]);
         }
         __syncthreads();
     }
+    // x^T x and x^T w: the first half (both halves hold the same sums)
     double xx = 0.0, xw = 0.0;
     if (active) {
 #pragma unroll
@@ -345,12 +356,12 @@ __device__ __forceinline__ void op_dots2(const OpArgs<T> &a, bool active, unsign
     }
     xx = wave_sum(xx);
     xw = wave_sum(xw);
-    if (lane == 0) {
+    if (lane == 0 && h == 0) {
         s2[wave][0] = xx;
         s2[wave][1] = xw;
     }
     __syncthreads();
-    if (tid < 2)
+    if (h == 0 && tid < 2)
         a.dpart[(size_t)(2 * nv + tid) * a.dnb + tile] =
             wsum(s2[0][tid], s2[1][tid], s2[2][tid], s2[3][tid], s2[NW > 4 ? 4 : 0][tid],
                  s2[NW > 5 ? 5 : 0][tid]);
@@ -363,23 +374,27 @@ __device__ __forceinline__ void op_dots2(const OpArgs<T> &a, bool active, unsign
 // residual the state itself.  Face and augmented terms need no LDS and are
 // added before the barrier; -(2/h) D is staged in LDS for the derivative.
 // Node offsets are 32-bit within one variable plane.
-template <int P, typename S, bool JVP, bool EV = false, typename Q = S>
+template <int P, typename S, bool JVP, bool EV = false, typename Q = S, int HV = 1>
 __device__ __forceinline__ void euler_op_body(const OpArgs<S> &a, int tile, bool first) {
     using T = double;  // arithmetic; S is the storage type
     static_assert(!JVP || std::is_same<Q, S>::value, "the linear operator reads stored vectors");
     constexpr int N1 = P + 1, NP = N1 * N1, EPB = 256 / NP, NT = EPB * NP;
     __shared__ T sF[8][NT];
     __shared__ T sDx[N1 * N1], sDy[N1 * N1];
-    const int tid = threadIdx.x;
+    static_assert(HV == 1 || (JVP && !EV), "two halves: the linear operator's dot pass");
+    // HV = 2: 512 threads, the second half joins for the dot pass only
+    const bool lead = HV == 1 || threadIdx.x < 256;
+    const int tid = HV == 2 ? (int)(threadIdx.x & 255) : (int)threadIdx.x;
     const int le = tid / NP;
     const int n = tid - le * NP;
     const int i = n % N1, j = n / N1;
     const int e = tile * EPB + le;
-    const bool active = (tid < NT) && (e < a.K);
+    const bool node = (tid < NT) && (e < a.K);
+    const bool active = lead && node;
     const size_t plane = (size_t)a.K * NP;
     const unsigned idx = (unsigned)e * NP + n;
     const T gm1 = a.gamma - T(1);
-    if (tid < N1 * N1) {
+    if (lead && tid < N1 * N1) {
         sDx[tid] = -a.rhx * a.D[tid];
         sDy[tid] = -a.rhy * a.D[tid];
     }
@@ -397,7 +412,7 @@ __device__ __forceinline__ void euler_op_body(const OpArgs<S> &a, int tile, bool
     T sc = T(1);
     if (a.vscale) sc = (T)(*a.vscale);
     // augmented entries of the output: (y_2, ..., y_p, 0), scaled
-    if (a.naug > 0 && first && tid == 0) {
+    if (a.naug > 0 && first && lead && tid == 0) {
         for (int k = 0; k < a.naug; ++k)
             a.otail[k] = (k + 1 < a.naug) ? (S)(sc * (T)a.vtail[k + 1]) : S(0);
     }
@@ -430,7 +445,7 @@ __device__ __forceinline__ void euler_op_body(const OpArgs<S> &a, int tile, bool
         // matching face node from that neighbour's row of nodes along the
         // normal and the shared face's mean.
         __shared__ T sV[4][NT];
-        if (tid < NT) {
+        if (lead && tid < NT) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) sV[c][tid] = u[c];
         }
@@ -556,7 +571,7 @@ __device__ __forceinline__ void euler_op_body(const OpArgs<S> &a, int tile, bool
                 fy[c] -= nuv * gy[c];
             }
         }
-        if (tid < NT) {
+        if (lead && tid < NT) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 sF[c][tid] = fx[c];
@@ -579,7 +594,7 @@ __device__ __forceinline__ void euler_op_body(const OpArgs<S> &a, int tile, bool
                 res[c] = fma(-cb, u[c] - uny[c], fma(-ca, fny[c] - fy[c], res[c]));
         }
     } else {
-        if (tid < NT) {
+        if (lead && tid < NT) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 sF[c][tid] = fx[c];
@@ -692,7 +707,28 @@ __device__ __forceinline__ void euler_op_body(const OpArgs<S> &a, int tile, bool
 #pragma unroll
         for (int c = 0; c < 4; ++c) wv[c] = T(0);
     }
-    if (JVP && a.dots) op_dots2<S, 4, 4, 8>(a, active, idx, plane, u, wv, tile, first);
+    if constexpr (HV == 2) {
+        // the second half takes the node's input and output from the first
+        __shared__ double sXW[8][256];
+        if (lead) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                sXW[c][tid] = u[c];
+                sXW[4 + c][tid] = wv[c];
+            }
+        }
+        __syncthreads();
+        if (!lead) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                u[c] = sXW[c][tid];
+                wv[c] = sXW[4 + c][tid];
+            }
+        }
+        op_dots2<S, 4, 4, 8, 2>(a, node, idx, plane, u, wv, tile, first);
+    } else if (JVP && a.dots) {
+        op_dots2<S, 4, 4, 8>(a, active, idx, plane, u, wv, tile, first);
+    }
 }
 
 // ---- entropy viscosity (2D Euler) ---------------------------------------------
@@ -1124,9 +1160,15 @@ __device__ __forceinline__ void euler3_op_body(const OpArgs<St> &a, int tile, bo
     if (JVP && a.dots) op_dots2<St, 5, S::NW, 8>(a, active, idx, plane, u, wv, tile, first);
 }
 
-template <int P, typename T, bool JVP, typename Q = T>
+template <int P, typename T, bool JVP>
 __global__ __launch_bounds__(E3Shape<P>::BS) void euler3_op(OpArgs<T> a) {
-    euler3_op_body<P, T, JVP, Q>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.x == 0);
+    euler3_op_body<P, T, JVP>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.x == 0);
+}
+
+// Residual of the FP64 state a.q64 with T storage (FP32-bulk steps).
+template <int P, typename T>
+__global__ __launch_bounds__(E3Shape<P>::BS) void euler3_op_r64(OpArgs<T> a) {
+    euler3_op_body<P, T, false, double>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.x == 0);
 }
 
 // ---- Burgers 1D operator ----------------------------------------------------
@@ -1295,14 +1337,35 @@ __device__ __forceinline__ void burgers_op_body(const OpArgs<S> &a, int tile, bo
         op_dots2<S, 1>(a, active, (unsigned)idx, (size_t)a.K * N1, &uv, &wv, tile, first);
 }
 
-template <int P, typename T, bool JVP, bool EV, typename Q = T>
+template <int P, typename T, bool JVP, bool EV>
 __global__ __launch_bounds__(256) void euler_op(OpArgs<T> a) {
-    euler_op_body<P, T, JVP, EV, Q>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.x == 0);
+    euler_op_body<P, T, JVP, EV>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.x == 0);
 }
 
-template <int P, typename T, bool JVP, bool VISC, typename Q = T>
+// Residual of the FP64 state a.q64 with T storage (FP32-bulk steps).
+template <int P, typename T, bool EV>
+__global__ __launch_bounds__(256) void euler_op_r64(OpArgs<T> a) {
+    euler_op_body<P, T, false, EV, double>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.x == 0);
+}
+
+// The linear operator with its dot pass over 512 threads: the second half
+// takes half of the basis chunks (grids of a few blocks per CU, where one
+// block's chain of chunks sets the launch time).
+template <int P, typename T>
+__global__ __launch_bounds__(512) void euler_op_halves(OpArgs<T> a) {
+    euler_op_body<P, T, true, false, T, 2>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.x == 0);
+}
+
+template <int P, typename T, bool JVP, bool VISC>
 __global__ __launch_bounds__(256) void burgers_op(OpArgs<T> a) {
-    burgers_op_body<P, T, JVP, VISC, Q>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.x == 0);
+    burgers_op_body<P, T, JVP, VISC>(a, xcd_tile(blockIdx.x, gridDim.x), blockIdx.x == 0);
+}
+
+// Residual of the FP64 state a.q64 with T storage (FP32-bulk steps).
+template <int P, typename T, bool VISC>
+__global__ __launch_bounds__(256) void burgers_op_r64(OpArgs<T> a) {
+    burgers_op_body<P, T, false, VISC, double>(a, xcd_tile(blockIdx.x, gridDim.x),
+                                               blockIdx.x == 0);
 }
 
 template <int P, typename T, bool JVP, bool EV>
@@ -1356,14 +1419,32 @@ hipError_t launch_group_p(int equation, bool jvp, bool visc, const OpArgs<T> *it
 
 template <int P, typename T>
 hipError_t launch_p(int equation, bool jvp, const OpArgs<T> &a, hipStream_t s) {
-    // FP32 storage: the residual of an FP64 state (a.q64) reads it directly
-    const bool r64 = !jvp && !std::is_same<T, double>::value && a.q64 != nullptr;
+    if constexpr (!std::is_same<T, double>::value) {
+        // FP32 storage: the residual of an FP64 state (a.q64) reads it directly
+        if (!jvp && a.q64) {
+            if (equation == EXPDG_EULER3D) {
+                using S = E3Shape<P>;
+                const int grid = (a.K + S::EPB - 1) / S::EPB;
+                return launch_kernel(euler3_op_r64<P, T>, dim3(grid), dim3(S::BS), 0, s, a);
+            }
+            if (equation == EXPDG_EULER2D) {
+                constexpr int EPB = 256 / ((P + 1) * (P + 1));
+                const int grid = (a.K + EPB - 1) / EPB;
+                if (a.nu)
+                    return launch_kernel(euler_op_r64<P, T, true>, dim3(grid), dim3(256), 0, s, a);
+                return launch_kernel(euler_op_r64<P, T, false>, dim3(grid), dim3(256), 0, s, a);
+            }
+            constexpr int EPB = 256 / (P + 1);
+            const int grid = (a.K + EPB - 1) / EPB;
+            if (a.kappa != 0.0)
+                return launch_kernel(burgers_op_r64<P, T, true>, dim3(grid), dim3(256), 0, s, a);
+            return launch_kernel(burgers_op_r64<P, T, false>, dim3(grid), dim3(256), 0, s, a);
+        }
+    }
     if (equation == EXPDG_EULER3D) {
         using S = E3Shape<P>;
         const int grid = (a.K + S::EPB - 1) / S::EPB;
         if (jvp) return launch_kernel(euler3_op<P, T, true>, dim3(grid), dim3(S::BS), 0, s, a);
-        if (r64)
-            return launch_kernel(euler3_op<P, T, false, double>, dim3(grid), dim3(S::BS), 0, s, a);
         return launch_kernel(euler3_op<P, T, false>, dim3(grid), dim3(S::BS), 0, s, a);
     }
     if (equation == EXPDG_EULER2D) {
@@ -1372,15 +1453,11 @@ hipError_t launch_p(int equation, bool jvp, const OpArgs<T> &a, hipStream_t s) {
         if (a.nu) {
             if (jvp)
                 return launch_kernel(euler_op<P, T, true, true>, dim3(grid), dim3(256), 0, s, a);
-            if (r64)
-                return launch_kernel(euler_op<P, T, false, true, double>, dim3(grid), dim3(256),
-                                     0, s, a);
             return launch_kernel(euler_op<P, T, false, true>, dim3(grid), dim3(256), 0, s, a);
         }
+        if (jvp && a.dots && grid <= kHalvesBlocks)
+            return launch_kernel(euler_op_halves<P, T>, dim3(grid), dim3(512), 0, s, a);
         if (jvp) return launch_kernel(euler_op<P, T, true, false>, dim3(grid), dim3(256), 0, s, a);
-        if (r64)
-            return launch_kernel(euler_op<P, T, false, false, double>, dim3(grid), dim3(256), 0,
-                                 s, a);
         return launch_kernel(euler_op<P, T, false, false>, dim3(grid), dim3(256), 0, s, a);
     }
     constexpr int EPB = 256 / (P + 1);
@@ -1388,15 +1465,9 @@ hipError_t launch_p(int equation, bool jvp, const OpArgs<T> &a, hipStream_t s) {
     if (a.kappa != 0.0) {
         if (jvp)
             return launch_kernel(burgers_op<P, T, true, true>, dim3(grid), dim3(256), 0, s, a);
-        if (r64)
-            return launch_kernel(burgers_op<P, T, false, true, double>, dim3(grid), dim3(256), 0,
-                                 s, a);
         return launch_kernel(burgers_op<P, T, false, true>, dim3(grid), dim3(256), 0, s, a);
     }
     if (jvp) return launch_kernel(burgers_op<P, T, true, false>, dim3(grid), dim3(256), 0, s, a);
-    if (r64)
-        return launch_kernel(burgers_op<P, T, false, false, double>, dim3(grid), dim3(256), 0, s,
-                             a);
     return launch_kernel(burgers_op<P, T, false, false>, dim3(grid), dim3(256), 0, s, a);
 }
 

@@ -235,6 +235,16 @@ inline int fold_chunks(int nrb) {
     return nrb > kFoldAbove ? (nrb + kFoldChunk - 1) / kFoldChunk : 0;
 }
 hipError_t launch_fold(const double *part, int nrb, int rows, double *out, hipStream_t s);
+// The 2D Euler linear operator with its dot pass runs as 512-thread blocks
+// (two halves splitting the basis chunks, same partials bit for bit) up to
+// this many blocks: two blocks per CU or fewer leave one or two waves per
+// SIMD, and a block's sequence of chunks sets the time (measured: 9-14 %
+// faster at 231-410 blocks, 7-13 % slower from 640 up, where the idle
+// second half costs occupancy).
+#ifndef EXPDG_HALVES_BLOCKS
+#define EXPDG_HALVES_BLOCKS 512
+#endif
+constexpr int kHalvesBlocks = EXPDG_HALVES_BLOCKS;
 // Incomplete orthogonalization (window of L vectors), finish of step k: x =
 // u_{k-1} (stored unnormalised), w = A x, and the nw = min(k-1, L-1) window
 // vectors u_{k0}, ..., u_{k-2} (k0 = k-1-nw) with block partials in the rows
