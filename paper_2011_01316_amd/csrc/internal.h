@@ -17,6 +17,15 @@ constexpr int kMaxP = 6;       // largest LGL degree compiled
 constexpr int kMaxM = 64;      // largest Krylov basis (Hessenberg exponential in LDS)
 constexpr int kMaxAug = 3;     // largest number of phi terms beyond phi_0
 constexpr int kRedBlocks = 1024;  // blocks of the row-partitioned reduction kernels
+#ifndef EXPDG_UPDATE_SPLIT
+#define EXPDG_UPDATE_SPLIT 8
+#endif
+// Blocks of the update sweep per block of the reductions' row partition: the
+// sweep writes no partials, and eight times the blocks keep more loads in
+// flight (measured: 256x256 p = 3 109 -> 100 us, 512x512 p = 4 FP32 bulk
+// 374 -> 350 us, 128x128 p = 4 34.7 -> 32.1 us; unchanged where the
+// partition is already one 1024-row sweep per block).
+constexpr int kUpdateSplit = EXPDG_UPDATE_SPLIT;
 constexpr int kRedThreads = 256;
 
 // Arguments of the fused DG operator kernels (residual or linear operator).

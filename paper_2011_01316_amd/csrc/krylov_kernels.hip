@@ -1017,8 +1017,13 @@ hipError_t launch_dcgs_update(const T *V, size_t stride, int nv, const double *c
                               const double *coefB, T *x, T *w, size_t L, const RowPartition &rp,
                               hipStream_t s, bool write_x) {
     if (nv < 0 || nv > kMaxM) return hipErrorInvalidValue;
-    return launch_kernel(dcgs_update_kernel<T>, dim3(rp.nrb), dim3(256), 0, s, V, stride, nv,
-                         coefA, coefB, x, w, L, rp.rpb, (write_x && nv > 0) ? 1 : 0);
+    // the sweep has no partials: it may take more blocks than the reductions'
+    // partition (whole 1024-row sweeps per block, the same rows in the scalar
+    // tail, so the result does not depend on the split)
+    const size_t rpb = std::max<size_t>(1024, (rp.rpb / kUpdateSplit + 1023) / 1024 * 1024);
+    const unsigned nb = (unsigned)((L + rpb - 1) / rpb);
+    return launch_kernel(dcgs_update_kernel<T>, dim3(nb), dim3(256), 0, s, V, stride, nv,
+                         coefA, coefB, x, w, L, rpb, (write_x && nv > 0) ? 1 : 0);
 }
 
 hipError_t launch_iop_finish(const double *part, int nrb, int k, int k0, int nw, double *S,
