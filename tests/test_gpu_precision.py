@@ -80,3 +80,54 @@ def test_fp32_bulk_steps_against_oracle(scheme):
     # vectors costs about 1e-7 of each
     assert err <= 2e-9, err
     assert rel(got, q0) > 1e-4  # the steps moved the state
+
+
+@pytest.mark.parametrize("scheme", [B.EPI2, B.EPI3, B.EXPRB32])
+def test_fp32_bulk_viscous_burgers_steps_against_oracle(scheme):
+    # the FP64-state residual of the viscous Burgers operator (zero Dirichlet
+    # ends, entropy flux) at a diffusive Courant number of a few hundred
+    print(f"fp32 bulk viscous Burgers steps: scheme {scheme}", flush=True)
+    K, p, kappa, nsteps = 20, 4, 0.03, 3
+    kw = dict(kappa=kappa, flux=1, sigma=3e-4, bc=1)
+    om = oracle.Mesh(oracle.BURGERS1D, K, p, x0=0.0, x1=1.0, **kw)
+    x, _ = om.nodes()
+    u0 = np.sin(2 * np.pi * x) ** 3 * (1.0 - x) ** 1.5
+    dt = 0.02
+    oq, oqp = u0, None
+    for _ in range(nsteps):
+        oq, oqp = om.step(scheme, dt, oq, oqp, tol=1e-10, m_min=10, m_max=64)
+    with B.Mesh(B.BURGERS1D, K, p, x0=0.0, x1=1.0, m_max=64, precision=B.FP32_BULK,
+                **kw) as gm:
+        q = torch.tensor(u0, dtype=torch.float64, device=DEV)
+        qp = torch.empty_like(q)
+        gm.integrate(scheme, dt, nsteps, q, qp, False, B.make_opts(1e-10, 10, 64),
+                     B.make_stats())
+        torch.cuda.synchronize()
+        got = q.cpu().numpy()
+    err = rel(got, oq)
+    assert err <= 5e-8, err
+    assert rel(got, u0) > 1e-2
+
+
+def test_fp32_bulk_euler3d_steps_against_oracle():
+    print("fp32 bulk 3D Euler steps against the oracle", flush=True)
+    nx, ny, nz, p, nsteps = 4, 4, 2, 3, 2
+    dom = dict(x0=0.0, x1=10.0, y0=-5.0, y1=5.0, z0=0.0, z1=1.0)
+    om = oracle.Mesh(oracle.EULER3D, nx, p, ny=ny, nz=nz, **dom)
+    x, y, z = om.nodes()
+    q0 = inputs.vortex3d(x, y, z, beta=2.0).reshape(-1)
+    c, dx = om.max_speed(q0)
+    dt = 5.0 * dx / c
+    oq, oqp = q0, None
+    for _ in range(nsteps):
+        oq, oqp = om.step(B.EPI3, dt, oq, oqp, tol=1e-10, m_min=10, m_max=64)
+    with B.Mesh(B.EULER3D, nx, p, ny=ny, nz=nz, m_max=64, precision=B.FP32_BULK, **dom) as gm:
+        q = torch.tensor(q0, dtype=torch.float64, device=DEV)
+        qp = torch.empty_like(q)
+        gm.integrate(B.EPI3, dt, nsteps, q, qp, False, B.make_opts(1e-10, 10, 64),
+                     B.make_stats())
+        torch.cuda.synchronize()
+        got = q.cpu().numpy()
+    err = rel(got, oq)
+    assert err <= 2e-9, err
+    assert rel(got, q0) > 1e-4
