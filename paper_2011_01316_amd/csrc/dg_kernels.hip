@@ -1031,8 +1031,17 @@ __device__ __forceinline__ void euler3_op_body(const OpArgs<St> &a, int tile, bo
     const int le = tid / NP;
     const int n = tid - le * NP;
     const int i = n % N1, j = (n / N1) % N1, k = n / NF;
-    const int e = tile * EPB + le;
-    const bool active = (tid < NT) && (e < a.K);
+    // the linear operator's tiles run through the elements column by column (z
+    // fastest): an element's z neighbours are the tiles next to it and its x
+    // neighbours nz tiles away, so their face traces are read while they are
+    // still in the XCD's L2 (measured on the 80x80x8 p = 6 run: the operator
+    // 5.07 -> 4.98 ms and the update sweep after it 4.43 -> 4.21 ms, which
+    // reads what the operator just wrote).  The residual keeps the plain
+    // order (the column order made it read 1.45x its bytes instead of 1.26x).
+    const int nxy = a.nx * a.ny, nz = a.K / nxy;
+    const int el = tile * EPB + le;
+    const int e = JVP ? (el % nz) * nxy + el / nz : el;
+    const bool active = (tid < NT) && (el < a.K);
     const size_t plane = (size_t)a.K * NP;
     const unsigned idx = (unsigned)e * NP + n;
     const T gm1 = a.gamma - T(1);
@@ -1057,7 +1066,6 @@ __device__ __forceinline__ void euler3_op_body(const OpArgs<St> &a, int tile, bo
         for (int kk = 0; kk < a.naug; ++kk)
             a.otail[kk] = (kk + 1 < a.naug) ? (St)(sc * (T)a.vtail[kk + 1]) : St(0);
     }
-    const int nxy = a.nx * a.ny;
     const int ex = e % a.nx, ey = (e / a.nx) % a.ny, ez = e / nxy;
     const St *lamx = a.lin + 4 * plane, *lamy = lamx + (size_t)a.K * NF,
              *lamz = lamy + (size_t)a.K * NF;
@@ -1114,7 +1122,6 @@ __device__ __forceinline__ void euler3_op_body(const OpArgs<St> &a, int tile, bo
     if (active && (k == 0 || k == P)) {
         const int s = (k == P) ? 1 : -1;
         int ezn = ez + s;
-        const int nz = a.K / nxy;
         ezn = ezn < 0 ? nz - 1 : (ezn >= nz ? 0 : ezn);
         const int en = ezn * nxy + ey * a.nx + ex;
         const unsigned nidx = (unsigned)en * NP + ((P - k) * N1 + j) * N1 + i;
