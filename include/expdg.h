@@ -33,7 +33,12 @@
  * operator buffers of expdg_rhs / expdg_jvp / expdg_phi_krylov are float and
  * the Krylov basis is stored in float, while inner products, norms, the
  * Hessenberg matrix, its exponential and the controller stay in double, and
- * expdg_step keeps its state q in double.
+ * expdg_step keeps its state q in double.  The operators compute in double in
+ * both modes and round only what they store; expdg_step / expdg_integrate
+ * form every residual, the frozen fields of the linear operator and the stage
+ * differences from the double states (a float copy of the state would put
+ * its rounding into each residual as high-frequency noise), so FP32_BULK
+ * steps take the FP64 Krylov iteration counts at the same tolerance.
  *
  * Ownership: the caller owns every state, input and output buffer; the mesh
  * owns its geometry tables and the Krylov workspace, allocated once by
