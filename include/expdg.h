@@ -453,8 +453,11 @@ int expdg_server_destroy(expdg_server *s);
  * EINVAL if it is invalid or can never fit the budget; *id identifies it. */
 int expdg_server_submit(expdg_server *s, const expdg_request *r, const double *q0, long long *id);
 /* Admits what fits, advances every ready solve and launches the tick's grouped
- * work.  block != 0: if no solve is ready, first wait until one is.  Returns
- * the number of solves that finished in this call in *finished (may be NULL). */
+ * work.  block != 0: while fewer than 90 % of the running solves are ready and
+ * earlier ticks are still on the device, first wait for the oldest of them
+ * (so a tick carries most solves instead of running thin batches ahead of the
+ * device), and if no solve is ready, wait until one is.  Returns the number of
+ * solves that finished in this call in *finished (may be NULL). */
 int expdg_server_tick(expdg_server *s, int block, int *finished);
 /* Ids of solves finished (DONE or FAILED) since the last call, at most cap;
  * returns the count written (or a negative status). */

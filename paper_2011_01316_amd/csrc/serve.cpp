@@ -110,6 +110,14 @@ struct CheckRec {
 };
 
 constexpr int kRing = 16;  // ticks in flight (staging buffers and events)
+// A blocking tick waits for earlier ticks while fewer than this share of the
+// running solves is ready.  Without it the host ran many ticks ahead of the
+// device, each carrying the ~12 % of solves whose results were back; on the
+// 2000-request mix at 200/s (max_active 256) waiting for 90 % took the solves
+// per tick from 30 to 91 Arnoldi steps and the throughput from 123 to 141
+// solves/s (p50 3.36 -> 2.48 s, p99 7.9 -> 6.0 s; 75 % and 100 % measured
+// 140/s).
+constexpr int kGatherPercent = 90;
 
 struct Batch {
     long long tick = -1;
@@ -817,9 +825,26 @@ extern "C" int expdg_server_tick(expdg_server *sv, int block, int *finished) {
     }
     sv->tick = t;
     if (block) {
-        bool any = false;
-        for (Req *r : sv->active) any = any || ready(sv, r);
-        if (!any) {
+        auto count_ready = [&] {
+            int k = 0;
+            for (Req *r : sv->active) k += ready(sv, r) ? 1 : 0;
+            return k;
+        };
+        int nready = count_ready();
+        // Few solves ready while earlier ticks are still on the device: wait
+        // for the oldest of them, so this tick carries the solves it releases
+        // instead of launching a thin batch far ahead of the device.
+        while ((long long)nready * 100 < (long long)kGatherPercent * (long long)sv->active.size() &&
+               sv->done_tick < t - 1) {
+            const Batch &ob = sv->ring[(sv->done_tick + 1) % kRing];
+            if (ob.tick != sv->done_tick + 1) break;
+            if (hipEventSynchronize(ob.ev_main) != hipSuccess ||
+                hipEventSynchronize(ob.ev_side) != hipSuccess)
+                return device_error(fail(EXPDG_EDEVICE, "batch wait failed"));
+            advance(sv);
+            nready = count_ready();
+        }
+        if (nready == 0) {
             rc = wait_any(sv);
             if (rc != EXPDG_OK) return device_error(rc);
         }
