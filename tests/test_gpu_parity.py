@@ -8,7 +8,7 @@ Tolerances (FP64 path):
   * small exponential: normwise 1e-13 (Pade(6,6) with identical scaling s;
     rounding grows with the s squarings).
   * phi combinations and steps on a replayed (forced) schedule: relative l2
-    <= 1e-12 (the benchmark spec's target for the FP64 path).
+    <= 1e-12 (the target for the FP64 path).
   * adaptive runs: identical substep decisions where the error estimate is not
     within rounding of a threshold, and the result within 10 tol nu of the
     oracle's.
