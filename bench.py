@@ -884,6 +884,44 @@ def fp32_probe():
                 krylov_iters_per_step=r["krylov_iters_per_step"])
 
 
+def euler3d_op_probe(reps=4):
+    """The residual and the linear operator (without a dot pass) of the 3D
+    run's mesh and state, applied a few times each (the run the instruction
+    and wait counters of the 3D operators are read on); per-launch averages
+    from the library's kernel timing (the linear operator's call also prepares
+    its frozen fields, which that timing leaves out)."""
+    import torch
+
+    from paper_2011_01316_amd import binding as B
+    from paper_2011_01316_amd import inputs
+
+    w = E3
+    m = B.Mesh(B.EULER3D, w["nx"], w["p"], ny=w["ny"], nz=w["nz"], x0=0.0, x1=10.0, y0=-5.0,
+               y1=5.0, z0=0.0, z1=1.0, m_max=8)
+    x, y, z = m.nodes()
+    q = torch.tensor(inputs.vortex3d(x, y, z, beta=0.05).reshape(-1), dtype=torch.float64,
+                     device="cuda:0")
+    del x, y, z
+    r = torch.empty_like(q)
+    v = torch.empty_like(q)
+    out = dict(workload=w["name"] + ": residual and linear operator alone", reps=reps)
+    m.rhs(q, r)
+    m.jvp(q, r, v)
+    torch.cuda.synchronize()
+    for name, call in (("residual", lambda: m.rhs(q, r)), ("linear_operator", lambda: m.jvp(q, r, v))):
+        c = {v: k for k, v in B.KERNEL_CLASSES.items()}[name]
+        B.expdg_profile_enable(m.handle, c, True)
+        for _ in range(reps):
+            call()
+        torch.cuda.synchronize()
+        pr = B.expdg_profile_read(m.handle, c)
+        B.expdg_profile_enable(m.handle, c, False)
+        out[name + "_us"] = round(pr["total_ms"] * 1e3 / pr["launches"], 1)
+        out[name + "_gbs_algorithmic"] = round(pr["bytes"] / (pr["total_ms"] * 1e-3) / 1e9, 1)
+    m.close()
+    return out
+
+
 def copy_probe(nbytes=1 << 30, reps=20):
     """Plain device-to-device copy of a known size: measured copy bandwidth and
     the reference dispatch for scaling the FETCH_SIZE / WRITE_SIZE counters."""
@@ -942,7 +980,13 @@ def main():
     ap.add_argument("--fp32-probe", action="store_true",
                     help="only two FP32-bulk steps of the 256x256 p=3 vortex (tol 1e-7), for "
                          "instruction counters of its linear operator")
+    ap.add_argument("--euler3d-op-probe", action="store_true",
+                    help="only the 3D run's residual and linear operator, a few times each, for "
+                         "instruction and wait counters")
     args = ap.parse_args()
+    if args.euler3d_op_probe:
+        print(json.dumps(euler3d_op_probe()), flush=True)
+        return
     if args.fp32_probe:
         print(json.dumps(fp32_probe()), flush=True)
         return
