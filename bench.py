@@ -922,6 +922,47 @@ def euler3d_op_probe(reps=4):
     return out
 
 
+def size_sweep(p, sizes=(32, 48, 64, 96, 128, 192, 256, 384, 512)):
+    """The vortex of the 64x64 workload (EPI3, Courant 5, tol 1e-10, FP64) on
+    n x n meshes of degree p: two steps, then two more with live kernel timing
+    of the linear operator (with the step's dot pass), the update sweep, the
+    finish and the residual; one JSON line per mesh with each class's average
+    launch time, algorithmic bytes and their fraction of 8 TB/s."""
+    import torch
+
+    from paper_2011_01316_amd import binding as B
+    from paper_2011_01316_amd import inputs
+
+    for n in sizes:
+        m = B.Mesh(B.EULER2D, n, p, ny=n, x0=0.0, x1=10.0, y0=0.0, y1=10.0, m_max=64)
+        x, y = m.nodes()
+        q = torch.tensor(inputs.vortex(x, y, beta=5.0).reshape(-1), dtype=torch.float64,
+                         device="cuda:0")
+        del x, y
+        qp = torch.empty_like(q)
+        dt = 5.0 * m.dx_min / m.max_speed(q)
+        opts = B.make_opts(1e-10, 10, 64)
+        m.integrate(B.EPI3, dt, 2, q, qp, False, opts, B.make_stats())
+        for c in B.KERNEL_CLASSES:
+            B.expdg_profile_enable(m.handle, c, True)
+        st = B.make_stats()
+        m.integrate(B.EPI3, dt, 2, q, qp, True, opts, st)
+        torch.cuda.synchronize()
+        pr = {B.KERNEL_CLASSES[c]: B.expdg_profile_read(m.handle, c) for c in B.KERNEL_CLASSES}
+        m.close()
+        row = dict(n=n, p=p, ndof=n * n * (p + 1) ** 2 * 4,
+                   krylov_iters=B.stats_dict(st)["krylov_iters"])
+        for k in ("linear_operator", "gs_update", "gs_finish", "gs_fold", "residual"):
+            v = pr[k]
+            if v["launches"]:
+                row[k] = dict(us=round(v["total_ms"] * 1e3 / v["launches"], 2),
+                              mb=round(v["bytes"] / v["launches"] / 1e6, 2),
+                              frac=round(v["bytes"] / (v["total_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 3))
+        print(json.dumps(row), flush=True)
+        del q, qp
+        torch.cuda.empty_cache()
+
+
 def copy_probe(nbytes=1 << 30, reps=20):
     """Plain device-to-device copy of a known size: measured copy bandwidth and
     the reference dispatch for scaling the FETCH_SIZE / WRITE_SIZE counters."""
@@ -980,10 +1021,16 @@ def main():
     ap.add_argument("--fp32-probe", action="store_true",
                     help="only two FP32-bulk steps of the 256x256 p=3 vortex (tol 1e-7), for "
                          "instruction counters of its linear operator")
+    ap.add_argument("--size-sweep", type=int, default=0, metavar="P",
+                    help="only the 64x64 workload's vortex on n x n meshes of degree P, "
+                         "n = 32..512: per-kernel times and roofline fractions, one line each")
     ap.add_argument("--euler3d-op-probe", action="store_true",
                     help="only the 3D run's residual and linear operator, a few times each, for "
                          "instruction and wait counters")
     args = ap.parse_args()
+    if args.size_sweep:
+        size_sweep(args.size_sweep)
+        return
     if args.euler3d_op_probe:
         print(json.dumps(euler3d_op_probe()), flush=True)
         return
