@@ -744,8 +744,12 @@ struct DirectExec {
         if (cr) TRY(mark_check(m, *cr, c));
         TRY(prof_begin(m, EXPDG_K_GS_UPDATE));
         // incomplete orthogonalization leaves x as it is (only its scale is new)
+        // with the dot pass in the operator's epilogue, the sweep runs against
+        // the operator's order (kUpdateLanesPerPlane); after the separate 1D
+        // dot pass, which walks the rows upwards, one lane walked downwards
+        const int lanes = fused ? kUpdateLanesPerPlane * m->nvar : 1;
         HIPTRY(launch_dcgs_update<T>(basis, stride, nv, kd.coefA, kd.coefB, x, w, L, rp, s,
-                                     !iop));
+                                     !iop, lanes));
         TRY(prof_end(m, EXPDG_K_GS_UPDATE,
                      (double)(nv + ((nv > 0 && !iop) ? 4 : 3)) * L * eb));
         if (cr) TRY(submit_check(m, *cr, *c));

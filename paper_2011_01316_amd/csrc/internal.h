@@ -26,6 +26,19 @@ constexpr int kRedBlocks = 1024;  // blocks of the row-partitioned reduction ker
 // 374 -> 350 us, 128x128 p = 4 34.7 -> 32.1 us; unchanged where the
 // partition is already one 1024-row sweep per block).
 constexpr int kUpdateSplit = EXPDG_UPDATE_SPLIT;
+// Lanes of the update sweep per variable plane when the dot pass runs in the
+// operator's epilogue.  The operator's blocks give XCD x (of 8) the x-th
+// eighth of the elements and walk it upwards in every plane, so when it ends
+// the most recently read rows of the basis are the top of each of these
+// eighths; the update walks each eighth of each plane downwards, starting on
+// rows still in the 256 MB last-level cache and ending on the bottoms, where
+// the next operator starts.  Results do not depend on the order.  Measured,
+// same box, bitwise-equal results: 256x256 p = 3 6.52 -> 6.29 ms/step (FP64)
+// and 4.19 -> 3.96 (FP32 bulk), 192x192 p = 4 4.77 -> 4.65; unchanged at
+// 64x64 and 128x128 p = 4, on 512x512 p = 4 (FP32 bulk) and in the 3D run,
+// whose basis vectors (702 MB) leave nothing to reuse; there a lane per z layer
+// and XCD, the 3D operator's own order, measured the same.
+constexpr int kUpdateLanesPerPlane = 8;
 constexpr int kRedThreads = 256;
 
 // Arguments of the fused DG operator kernels (residual or linear operator).
@@ -229,10 +242,12 @@ hipError_t launch_dcgs_finish(const double *part, int nrb, int k, double *S, dou
                               double *coefA, double *coefB, int *flags, hipStream_t s);
 // One sweep of step k: x -= sum_{i<nv} coefA[i] u_i (only if write_x and
 // nv > 0) and w <- coefB[kScalW] w - coefB[kScalX] x_old - sum_{i<nv} coefB[i] u_i.
+// The rows are cut into `lanes` equal contiguous lanes (whole 1024-row
+// multiples), each walked from its end to its start; see kUpdateLanesPerPlane.
 template <typename T>
 hipError_t launch_dcgs_update(const T *V, size_t stride, int nv, const double *coefA,
                               const double *coefB, T *x, T *w, size_t L, const RowPartition &rp,
-                              hipStream_t s, bool write_x = true);
+                              hipStream_t s, bool write_x = true, int lanes = 1);
 // Partial rows longer than kFoldAbove (the dot pass fused into the operator
 // of a large mesh writes one partial per operator block) are first folded by a
 // many-block launch: out[r * nc + c] = the fixed-order sum of chunk c

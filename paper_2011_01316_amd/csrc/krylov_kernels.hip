@@ -499,13 +499,23 @@ __device__ __forceinline__ void dcgs_update_body(const T *__restrict__ V, size_t
     }
 }
 
+// Block b takes lane b % nl (rows [l lane_len, min((l+1) lane_len, L))) and
+// in it the chunk of rpb rows that is (b / nl)-th from the lane's end; lane_len
+// and rpb are multiples of 1024, so every chunk starts on a whole sweep.
 template <typename T>
 __global__ __launch_bounds__(256) void dcgs_update_kernel(const T *__restrict__ V, size_t stride,
                                                           int nv, const double *cA,
                                                           const double *cB, T *__restrict__ x,
                                                           T *__restrict__ w, size_t L,
-                                                          size_t rpb, int wx) {
-    dcgs_update_body<T>(V, stride, nv, cA, cB, x, w, L, rpb, blockIdx.x, wx != 0);
+                                                          size_t rpb, int nl, size_t lane_len,
+                                                          int wx) {
+    const int l = (int)(blockIdx.x % (unsigned)nl), back = (int)(blockIdx.x / (unsigned)nl);
+    const size_t s0 = (size_t)l * lane_len;
+    if (s0 >= L) return;
+    const size_t len = (s0 + lane_len < L) ? lane_len : L - s0;
+    const int chunk = (int)((len + rpb - 1) / rpb) - 1 - back;
+    if (chunk < 0) return;
+    dcgs_update_body<T>(V + s0, stride, nv, cA, cB, x + s0, w + s0, len, rpb, chunk, wx != 0);
 }
 
 // Finish of step k with incomplete orthogonalization (window of L vectors):
@@ -1015,15 +1025,17 @@ hipError_t launch_dcgs_finish(const double *part, int nrb, int k, double *S, dou
 template <typename T>
 hipError_t launch_dcgs_update(const T *V, size_t stride, int nv, const double *coefA,
                               const double *coefB, T *x, T *w, size_t L, const RowPartition &rp,
-                              hipStream_t s, bool write_x) {
-    if (nv < 0 || nv > kMaxM) return hipErrorInvalidValue;
+                              hipStream_t s, bool write_x, int lanes) {
+    if (nv < 0 || nv > kMaxM || lanes < 1 || L < 1) return hipErrorInvalidValue;
     // the sweep has no partials: it may take more blocks than the reductions'
     // partition (whole 1024-row sweeps per block, the same rows in the scalar
-    // tail, so the result does not depend on the split)
+    // tail, so the result does not depend on the split or on the order)
     const size_t rpb = std::max<size_t>(1024, (rp.rpb / kUpdateSplit + 1023) / 1024 * 1024);
-    const unsigned nb = (unsigned)((L + rpb - 1) / rpb);
+    const size_t lane_len = ((L + lanes - 1) / lanes + 1023) / 1024 * 1024;
+    const unsigned nb = (unsigned)(((lane_len + rpb - 1) / rpb) * lanes);
     return launch_kernel(dcgs_update_kernel<T>, dim3(nb), dim3(256), 0, s, V, stride, nv,
-                         coefA, coefB, x, w, L, rpb, (write_x && nv > 0) ? 1 : 0);
+                         coefA, coefB, x, w, L, rpb, lanes, lane_len,
+                         (write_x && nv > 0) ? 1 : 0);
 }
 
 hipError_t launch_iop_finish(const double *part, int nrb, int k, int k0, int nw, double *S,
@@ -1051,7 +1063,7 @@ hipError_t launch_gs_finish_norm(const double *part, const RowPartition &rp, dou
                                            const RowPartition &, double *, hipStream_t);        \
     template hipError_t launch_dcgs_update<T>(const T *, size_t, int, const double *,           \
                                               const double *, T *, T *, size_t,                 \
-                                              const RowPartition &, hipStream_t, bool);         \
+                                              const RowPartition &, hipStream_t, bool, int);    \
     template hipError_t launch_gs_norm<T>(const T *, size_t, const RowPartition &, double *,    \
                                           hipStream_t);
 EXPDG_INST(double)
