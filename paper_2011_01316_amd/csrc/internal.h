@@ -33,11 +33,12 @@ constexpr int kUpdateSplit = EXPDG_UPDATE_SPLIT;
 // eighths; the update walks each eighth of each plane downwards, starting on
 // rows still in the 256 MB last-level cache and ending on the bottoms, where
 // the next operator starts.  Results do not depend on the order.  Measured,
-// same box, bitwise-equal results: 256x256 p = 3 6.52 -> 6.29 ms/step (FP64)
-// and 4.19 -> 3.96 (FP32 bulk), 192x192 p = 4 4.77 -> 4.65; unchanged at
-// 64x64 and 128x128 p = 4, on 512x512 p = 4 (FP32 bulk) and in the 3D run,
-// whose basis vectors (702 MB) leave nothing to reuse; there a lane per z layer
-// and XCD, the 3D operator's own order, measured the same.
+// same box, bitwise-equal results: 256x256 p = 3 6.62 -> 6.26 ms/step (FP64)
+// and 4.24 -> 4.00 (FP32 bulk); operator + update per Arnoldi step 192x192
+// p = 4 175 -> 170 us, 128x128 p = 4 72.2 -> 71.5, 64x64 p = 3 23.0 -> 22.8;
+// 512x512 p = 4 1235 -> 1245 us in FP64 (the update 3 % slower: a basis
+// vector is 210 MB, there is nothing to reuse) and 13.01 -> 12.96 ms/step in
+// FP32 bulk; the 3D run (702 MB vectors) unchanged.
 constexpr int kUpdateLanesPerPlane = 8;
 constexpr int kRedThreads = 256;
 
@@ -242,8 +243,9 @@ hipError_t launch_dcgs_finish(const double *part, int nrb, int k, double *S, dou
                               double *coefA, double *coefB, int *flags, hipStream_t s);
 // One sweep of step k: x -= sum_{i<nv} coefA[i] u_i (only if write_x and
 // nv > 0) and w <- coefB[kScalW] w - coefB[kScalX] x_old - sum_{i<nv} coefB[i] u_i.
-// The rows are cut into `lanes` equal contiguous lanes (whole 1024-row
-// multiples), each walked from its end to its start; see kUpdateLanesPerPlane.
+// The rows are cut into `lanes` contiguous lanes of nearly equal length (at
+// most L / 1024 of them, each starting on a multiple of 1024 rows), each walked
+// from its end to its start; see kUpdateLanesPerPlane.
 template <typename T>
 hipError_t launch_dcgs_update(const T *V, size_t stride, int nv, const double *coefA,
                               const double *coefB, T *x, T *w, size_t L, const RowPartition &rp,

@@ -436,8 +436,8 @@ __global__ __launch_bounds__(kFin2Threads) void dcgs_finish_kernel(const double 
 template <typename T>
 __device__ __forceinline__ void dcgs_update_body(const T *__restrict__ V, size_t stride, int nv,
                                                  const double *cA, const double *cB,
-                                                 T *__restrict__ x, T *__restrict__ w, size_t L,
-                                                 size_t rpb, int rb, bool wx) {
+                                                 T *__restrict__ x, T *__restrict__ w, size_t r0,
+                                                 size_t r1, bool wx) {
     __shared__ double sA[kMaxM], sB[kMaxM], sWX[2];
     const int tid = threadIdx.x;
     if (tid < nv) {
@@ -450,8 +450,6 @@ __device__ __forceinline__ void dcgs_update_body(const T *__restrict__ V, size_t
     }
     __syncthreads();
     const double cw = sWX[0], cx = sWX[1];
-    const size_t r0 = (size_t)rb * rpb;
-    const size_t r1 = (r0 + rpb < L) ? r0 + rpb : L;
     constexpr int N = Vec16<T>::N;
     const size_t nsw = (r1 - r0) / (256 * N);
     for (size_t k = 0; k < nsw; ++k) {
@@ -499,23 +497,29 @@ __device__ __forceinline__ void dcgs_update_body(const T *__restrict__ V, size_t
     }
 }
 
-// Block b takes lane b % nl (rows [l lane_len, min((l+1) lane_len, L))) and
-// in it the chunk of rpb rows that is (b / nl)-th from the lane's end; lane_len
-// and rpb are multiples of 1024, so every chunk starts on a whole sweep.
+// Lane l of nl over L rows starts at row (l L / nl) rounded down to a multiple
+// of 1024; the last lane ends at L.
+__device__ __host__ __forceinline__ size_t lane_start(int l, int nl, size_t L) {
+    return l >= nl ? L : ((size_t)l * L / (size_t)nl) / 1024 * 1024;
+}
+
+// Block b takes lane l = b % nl and in it the chunk that is (b / nl)-th from
+// the lane's end: chunks of rpb rows, the lane's last chunk taking the rest
+// of the lane.  Lane starts and rpb are multiples of 1024, so every chunk
+// starts on a whole sweep.
 template <typename T>
 __global__ __launch_bounds__(256) void dcgs_update_kernel(const T *__restrict__ V, size_t stride,
                                                           int nv, const double *cA,
                                                           const double *cB, T *__restrict__ x,
                                                           T *__restrict__ w, size_t L,
-                                                          size_t rpb, int nl, size_t lane_len,
-                                                          int wx) {
+                                                          size_t rpb, int nl, int wx) {
     const int l = (int)(blockIdx.x % (unsigned)nl), back = (int)(blockIdx.x / (unsigned)nl);
-    const size_t s0 = (size_t)l * lane_len;
-    if (s0 >= L) return;
-    const size_t len = (s0 + lane_len < L) ? lane_len : L - s0;
-    const int chunk = (int)((len + rpb - 1) / rpb) - 1 - back;
-    if (chunk < 0) return;
-    dcgs_update_body<T>(V + s0, stride, nv, cA, cB, x + s0, w + s0, len, rpb, chunk, wx != 0);
+    const size_t s0 = lane_start(l, nl, L), len = lane_start(l + 1, nl, L) - s0;
+    const size_t nch = (len / rpb > 0) ? len / rpb : 1;
+    if ((size_t)back >= nch) return;
+    const size_t j = nch - 1 - (size_t)back;
+    const size_t r0 = s0 + j * rpb, r1 = (j == nch - 1) ? s0 + len : r0 + rpb;
+    dcgs_update_body<T>(V, stride, nv, cA, cB, x, w, r0, r1, wx != 0);
 }
 
 // Finish of step k with incomplete orthogonalization (window of L vectors):
@@ -967,8 +971,10 @@ __global__ __launch_bounds__(256) void dcgs_update_group(const GsItem *items, co
     const int it = group_item(bstart, n, blockIdx.x);
     const GsItem &g = items[it];
     // incomplete orthogonalization leaves x as it is (only its scale is new)
+    const size_t r0 = (size_t)(blockIdx.x - bstart[it]) * g.rpb;
+    const size_t r1 = (r0 + g.rpb < g.L) ? r0 + g.rpb : g.L;
     dcgs_update_body<double>(g.V + (size_t)g.k0 * g.stride, g.stride, g.nv, g.coefA, g.coefB,
-                             g.x, g.w, g.L, g.rpb, blockIdx.x - bstart[it], g.k > 1 && !g.iop);
+                             g.x, g.w, r0, r1, g.k > 1 && !g.iop);
 }
 
 constexpr size_t kExpmLds = (size_t)4 * NMAX * LDA * sizeof(double);
@@ -1031,11 +1037,15 @@ hipError_t launch_dcgs_update(const T *V, size_t stride, int nv, const double *c
     // partition (whole 1024-row sweeps per block, the same rows in the scalar
     // tail, so the result does not depend on the split or on the order)
     const size_t rpb = std::max<size_t>(1024, (rp.rpb / kUpdateSplit + 1023) / 1024 * 1024);
-    const size_t lane_len = ((L + lanes - 1) / lanes + 1023) / 1024 * 1024;
-    const unsigned nb = (unsigned)(((lane_len + rpb - 1) / rpb) * lanes);
+    // lanes of at least 1024 rows (lane_start); the grid has as many chunks
+    // per lane as the longest lane
+    const int nl = (int)std::max<size_t>(1, std::min<size_t>((size_t)lanes, L / 1024));
+    size_t nch = 1;
+    for (int l = 0; l < nl; ++l)
+        nch = std::max(nch, (lane_start(l + 1, nl, L) - lane_start(l, nl, L)) / rpb);
+    const unsigned nb = (unsigned)(nch * nl);
     return launch_kernel(dcgs_update_kernel<T>, dim3(nb), dim3(256), 0, s, V, stride, nv,
-                         coefA, coefB, x, w, L, rpb, lanes, lane_len,
-                         (write_x && nv > 0) ? 1 : 0);
+                         coefA, coefB, x, w, L, rpb, nl, (write_x && nv > 0) ? 1 : 0);
 }
 
 hipError_t launch_iop_finish(const double *part, int nrb, int k, int k0, int nw, double *S,
