@@ -31,8 +31,10 @@ constexpr int kUpdateSplit = EXPDG_UPDATE_SPLIT;
 // eighth of the elements and walk it upwards in every plane, so when it ends
 // the most recently read rows of the basis are the top of each of these
 // eighths; the update walks each eighth of each plane downwards, starting on
-// rows still in the 256 MB last-level cache and ending on the bottoms, where
-// the next operator starts.  Results do not depend on the order.  Measured,
+// the rows read last (the likeliest to be still in the 256 MB last-level
+// cache) and ending on the bottoms, where the next operator starts.  Results
+// do not depend on the order.  (The counters at the L2's memory side count
+// last-level cache hits too and read the same bytes either way.)  Measured,
 // same box, bitwise-equal results: 256x256 p = 3 6.62 -> 6.26 ms/step (FP64)
 // and 4.24 -> 4.00 (FP32 bulk); operator + update per Arnoldi step 192x192
 // p = 4 175 -> 170 us, 128x128 p = 4 72.2 -> 71.5, 64x64 p = 3 23.0 -> 22.8;
