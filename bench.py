@@ -903,13 +903,15 @@ def euler3d_op_probe(reps=4):
                      device="cuda:0")
     del x, y, z
     r = torch.empty_like(q)
-    v = torch.empty_like(q)
+    lv = torch.empty_like(q)
     out = dict(workload=w["name"] + ": residual and linear operator alone", reps=reps)
     m.rhs(q, r)
-    m.jvp(q, r, v)
+    m.jvp(q, r, lv)
     torch.cuda.synchronize()
-    for name, call in (("residual", lambda: m.rhs(q, r)), ("linear_operator", lambda: m.jvp(q, r, v))):
-        c = {v: k for k, v in B.KERNEL_CLASSES.items()}[name]
+    class_id = {name: c for c, name in B.KERNEL_CLASSES.items()}
+    for name, call in (("residual", lambda: m.rhs(q, r)),
+                       ("linear_operator", lambda: m.jvp(q, r, lv))):
+        c = class_id[name]
         B.expdg_profile_enable(m.handle, c, True)
         for _ in range(reps):
             call()
