@@ -171,6 +171,20 @@ def test_mixed_batch_is_bitwise_each_stepper():
         np.testing.assert_array_equal(got[k][0], w, err_msg=f"case {k}")
 
 
+def test_meshes_of_many_sweep_blocks_are_bitwise_each_stepper():
+    # more than 32 x 1024 rows, one of them not a multiple of 1024: the
+    # stepper's update sweep cuts its rows into lanes walked from their ends
+    # (starts rounded to 1024 rows), the server's walks its row partition
+    # upwards; every row must come out the same
+    cases = [euler_case(48, 3, 4.0, 6.0, 3.0, nsteps=2),
+             euler_case(41, 4, 5.5, 4.5, 2.0, nsteps=2, scheme=B.EPI2)]
+    want = [standalone(r, q0)[0] for r, q0 in cases]
+    with B.Server(hbm_budget=4 << 30, max_active=8) as srv:
+        got = serve_all(srv, cases)
+    for k, w in enumerate(want):
+        np.testing.assert_array_equal(got[k][0], w, err_msg=f"case {k}")
+
+
 @pytest.mark.parametrize("window", [1, 2, 5])
 def test_incomplete_orthogonalization_is_bitwise_each_stepper(window):
     # served solves with incomplete orthogonalization (a window of the most
