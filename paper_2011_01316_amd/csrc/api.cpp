@@ -745,8 +745,11 @@ struct DirectExec {
         TRY(prof_begin(m, EXPDG_K_GS_UPDATE));
         // incomplete orthogonalization leaves x as it is (only its scale is new)
         // with the dot pass in the operator's epilogue, the sweep runs against
-        // the operator's order (kUpdateLanesPerPlane); after the separate 1D
-        // dot pass, which walks the rows upwards, one lane walked downwards
+        // the operator's order (kUpdateLanesPerPlane; the 3D operator walks
+        // its columns through every z layer, which eight lanes per plane only
+        // approximate, and its vectors are too large for the cache to matter);
+        // after the separate 1D dot pass, which walks the rows upwards, one
+        // lane walked downwards
         const int lanes = fused ? kUpdateLanesPerPlane * m->nvar : 1;
         HIPTRY(launch_dcgs_update<T>(basis, stride, nv, kd.coefA, kd.coefB, x, w, L, rp, s,
                                      !iop, lanes));
